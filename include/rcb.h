@@ -1,0 +1,175 @@
+/*
+ * rcb.h -- C ABI of the MI355X recursive coordinate bisection (RCB) tree:
+ * neighbour search and self-gravity for N particles, after Gafton & Rosswog,
+ * "A fast recursive coordinate bisection tree for neighbour search and
+ * gravity", MNRAS 2011 (arXiv:1108.0028).
+ *
+ * Problem (Sec. 1-2): given positions, masses and smoothing lengths of N
+ * particles, an average leaf population N_ll and an opening angle theta
+ * (G = 1), return each particle's neighbours inside its kernel support 2h and
+ * its gravitational acceleration: a kernel-softened direct sum over nearby
+ * cells plus a quadrupole far field Taylor-expanded about each leaf's centre
+ * of mass.
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers (HIP global memory of the
+ *    current device) unless a comment says "host". Arrays are plain
+ *    structure-of-arrays, one element per particle, in the caller's particle
+ *    order; every per-particle output is also in the caller's order.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    All work is enqueued on it; inputs must stay valid and outputs must not
+ *    be read until the stream has passed the call. Only
+ *    rcb_neighbours_count() synchronises the stream (it returns a host total).
+ *  - Inputs stay owned by the caller. rcb_build() copies what it needs, so
+ *    the tree never aliases caller memory after the call returns.
+ *  - Calls return rcb_status; nothing throws across the ABI. Argument errors
+ *    are detected on the host before any launch. A failed call leaves its
+ *    outputs unspecified; rcb_last_error() describes the last failure on
+ *    the calling thread.
+ *  - A tree may be used by one stream at a time; calls on one tree must not
+ *    overlap.
+ */
+#ifndef RCB_H
+#define RCB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rcb_tree rcb_tree;
+
+typedef enum {
+    RCB_OK = 0,
+    RCB_EINVAL = 1,     /* invalid argument (null pointer, n < 1, n_ll < 1, theta < 0 or not finite, ...) */
+    RCB_ENOMEM = 2,     /* device memory allocation failed */
+    RCB_EHIP = 3,       /* HIP runtime error */
+    RCB_ECAPACITY = 4,  /* caller buffer smaller than the result */
+    RCB_ESTATE = 5,     /* call out of order for this tree */
+    RCB_EINPUT = 6      /* validate = 1 found a non-finite coordinate, m <= 0 or h <= 0 */
+} rcb_status;
+
+typedef enum {
+    RCB_FP64 = 0,       /* all interaction arithmetic in FP64 */
+    RCB_MIXED = 1       /* FP32 leaf-relative interactions; FP64 moments and Taylor shift */
+} rcb_precision;
+
+typedef struct {
+    int32_t n_ll;       /* average particles per lowest-level cell, Sec. 3.2.1 (paper: 12) */
+    int32_t precision;  /* rcb_precision */
+    double theta;       /* opening angle of the geometric MAC, Sec. 2.4.1 (paper default 0.7) */
+    int32_t validate;   /* 1: check inputs on the device first (one extra pass) */
+    int32_t reserved;   /* must be 0 */
+} rcb_params;
+
+/* Paper defaults: n_ll = 12, theta = 0.7, FP64, validate = 0. */
+void rcb_params_default(rcb_params *p);
+
+/*
+ * Build the tree top-down (Sec. 2.1): the root cell is the particles'
+ * bounding box; each cell is split perpendicular to its longest side through
+ * its centre of mass, particles with coordinate < plane going to the lower
+ * child 2n (stable), the rest to 2n+1, until level k = min{k : n <= n_ll 2^k}.
+ * Every node gets its mass, centre of mass (canonical pairwise sums over its
+ * particles in ascending input index), traceless quadrupole (Eq. 1 at the
+ * leaves, Eq. 2 upwards), h_node_int and, for leaves, h_node (Sec. 2.3.1).
+ *  x, y, z, m, h: n FP64 values each (device). h > 0, m > 0.
+ *  n >= 1 and n <= 2^31 - 1.  p: host pointer.  *out: new tree (host).
+ * The interaction lists are made by the first call that needs them.
+ */
+rcb_status rcb_build(const double *x, const double *y, const double *z, const double *m,
+                     const double *h, int64_t n, const rcb_params *p, void *stream,
+                     rcb_tree **out);
+
+/*
+ * Neighbour search, step 1 (Sec. 2.3): for every particle a the number of
+ * particles b != a with |r_a - r_b| < 2 h_a, found among the cells that the
+ * reachability test of Sec. 2.3.1 keeps.
+ *  offsets: device int64[n + 1], receives the exclusive prefix sum of the
+ *           counts (offsets[0] = 0, offsets[n] = total).
+ *  total:   host int64, receives offsets[n]. This call synchronises `stream`.
+ */
+rcb_status rcb_neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, void *stream);
+
+/*
+ * Neighbour search, step 2: writes the neighbour ids (caller indices) of
+ * particle a to ids[offsets[a] .. offsets[a+1]) -- the one-dimensional list
+ * of Sec. 2.3.2. Within a list, neighbours appear in tree order (candidate
+ * cells by ascending label, then the cell's particle order).
+ *  offsets:  the array filled by rcb_neighbours_count() for this tree.
+ *  ids:      device int32[capacity]; capacity >= total, else RCB_ECAPACITY.
+ */
+rcb_status rcb_neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids,
+                               int64_t capacity, void *stream);
+
+/*
+ * Gravitational accelerations (Sec. 2.4), G = 1:
+ *   a_a = -sum over particles b of near cells of m_b S(r_ab, h_ab) e_ab   (Eq. for f_ng)
+ *         + f_A + J_A d_a + 1/2 d_a^T H_A d_a                             (Eq. 6)
+ * with h_ab = (h_a + h_b)/2, d_a = r_a - COM_A, and f_A, J_A, H_A the field,
+ * Jacobian and Hessian at COM_A of the quadrupole expansions (Eq. 5) of the
+ * cells accepted by the MAC H_B / R_AB < theta (reachable cells are never
+ * accepted). ax, ay, az: n values, FP64 for RCB_FP64, FP32 for RCB_MIXED.
+ */
+rcb_status rcb_gravity(rcb_tree *t, void *ax, void *ay, void *az, void *stream);
+
+/*
+ * Vector-Jacobian product of rcb_gravity with the tree held fixed (same
+ * topology, particle-to-leaf map and interaction lists; masses, centres of
+ * mass and quadrupoles vary with the inputs): for L = sum_a g_a . a_a,
+ * writes dL/dx, dL/dy, dL/dz and dL/dm. h gets no gradient. Near-field pairs
+ * are recomputed, not stored. g*: n values, d*: n values, FP64 for RCB_FP64
+ * and FP32 for RCB_MIXED. Valid after rcb_build() (gravity need not have run).
+ */
+rcb_status rcb_gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *gz,
+                           void *dx, void *dy, void *dz, void *dm, void *stream);
+
+typedef struct {
+    int64_t n;            /* particles */
+    int32_t k;            /* leaf level; leaves are labels 2^k .. 2^(k+1)-1 */
+    int32_t precision;
+    int64_t n_labels;     /* 2^(k+1); label 0 unused */
+    int64_t near_total;   /* interaction-list sizes, -1 until the walk has run */
+    int64_t far_total;
+    double theta;
+} rcb_tree_info;
+
+rcb_status rcb_get_info(const rcb_tree *t, rcb_tree_info *info /* host */);
+
+/* Fields of rcb_tree_export(): the tree's own arrays, for inspection and tests. */
+typedef enum {
+    RCB_FIELD_PERM = 0,      /* int32[n]        tree position -> caller index */
+    RCB_FIELD_FIRST = 1,     /* int32[n_labels] first tree position of each node */
+    RCB_FIELD_COUNT = 2,     /* int32[n_labels] particles in each node */
+    RCB_FIELD_LO = 3,        /* f64[3 n_labels] cell lower corner, (x,y,z) per label */
+    RCB_FIELD_HI = 4,        /* f64[3 n_labels] cell upper corner */
+    RCB_FIELD_COM = 5,       /* f64[3 n_labels] centre of mass */
+    RCB_FIELD_MASS = 6,      /* f64[n_labels] */
+    RCB_FIELD_QUAD = 7,      /* f64[6 n_labels] Q_xx Q_xy Q_xz Q_yy Q_yz Q_zz */
+    RCB_FIELD_HINT = 8,      /* f64[n_labels] h_node_int (-1 for empty nodes) */
+    RCB_FIELD_HNODE = 9,     /* f64[n_labels] h_node of leaves (-1 elsewhere) */
+    RCB_FIELD_NEAR_OFF = 10, /* int64[2^k + 1] per-leaf offsets into NEAR (needs the walk) */
+    RCB_FIELD_FAR_OFF = 11,  /* int64[2^k + 1] per-leaf offsets into FAR */
+    RCB_FIELD_NEAR = 12,     /* int32[near_total] leaf label | candidate << 31, ascending labels */
+    RCB_FIELD_FAR = 13       /* int32[far_total] accepted node labels, unordered */
+} rcb_field;
+
+/*
+ * Copy one of the tree's arrays into caller device memory `dst` of `bytes`
+ * bytes (RCB_ECAPACITY if smaller than the field). List fields run the walk
+ * first if it has not run yet.
+ */
+rcb_status rcb_tree_export(rcb_tree *t, int32_t field, void *dst, size_t bytes, void *stream);
+
+/* Free the tree and its device memory (waits for its last stream). */
+void rcb_destroy(rcb_tree *t);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *rcb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RCB_H */

@@ -1,0 +1,775 @@
+// k_build.hip -- top-down RCB build on the device, one pass per level
+// (Sec. 2.1: "Strategy", "Load balancing", "Particle sorting", "Node
+// labelling", "Multipole moments").
+//
+// Each level l = 0 .. k-1 splits every node through its centre of mass,
+// perpendicular to the longest side of its box, with a stable partition
+// (coordinate < plane -> child 2n). Node sums are canonical pairwise sums
+// over the node's particles in their order at split time, which is ascending
+// input index because every partition is stable and starts from input
+// order. The pairwise tree is aligned at the node's first particle and padded
+// with +0.0 to a power of two; a final "+ 0.0" maps -0.0 to +0.0, so any
+// wider padding gives the same bits.
+//
+// Work split: a node of <= 512 particles is handled by one wave end to end
+// (sums, split, partition) from registers. Larger nodes register in a list;
+// their 512-particle chunks are reduced by one wave each, a wave per node
+// combines the chunk sums, and the partition runs as count / scan / scatter
+// over the same chunks. Kernels are HBM-bound: each level reads 32 B and
+// writes 36 B per particle.
+#include "rcb_internal.h"
+
+namespace rcb {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// ---------------------------------------------------------------------------
+// bounds, validation, initial copy
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_bounds_partial(const double *__restrict__ x,
+                                                           const double *__restrict__ y,
+                                                           const double *__restrict__ z, int64_t n,
+                                                           double *__restrict__ part) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        double v[3] = {x[i], y[i], z[i]};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fmin(lo[d], v[d]);
+            hi[d] = fmax(hi[d], v[d]);
+        }
+    }
+    __shared__ double red[6][kWavesPerBlock];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double a = lo[d], b = hi[d];
+        for (int o = 1; o < kWave; o <<= 1) {
+            a = fmin(a, __shfl_xor(a, o, kWave));
+            b = fmax(b, __shfl_xor(b, o, kWave));
+        }
+        if (lane_id() == 0) {
+            red[d][threadIdx.x / kWave] = a;
+            red[3 + d][threadIdx.x / kWave] = b;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double r = red[threadIdx.x][0];
+        for (int w = 1; w < kWavesPerBlock; ++w)
+            r = threadIdx.x < 3 ? fmin(r, red[threadIdx.x][w]) : fmax(r, red[threadIdx.x][w]);
+        part[6 * blockIdx.x + threadIdx.x] = r;
+    }
+}
+
+__global__ void k_bounds_final(const double *__restrict__ part, int nb, double *__restrict__ nlo,
+                               double *__restrict__ nhi) {
+    int d = threadIdx.x;
+    if (d >= 6) return;
+    double r = part[d];
+    for (int b = 1; b < nb; ++b) r = d < 3 ? fmin(r, part[6 * b + d]) : fmax(r, part[6 * b + d]);
+    if (d < 3) nlo[3 + d] = r;   // label 1
+    else nhi[3 + d - 3] = r;
+}
+
+__global__ void k_validate(const double *__restrict__ x, const double *__restrict__ y,
+                           const double *__restrict__ z, const double *__restrict__ m,
+                           const double *__restrict__ h, int64_t n, int32_t *__restrict__ flag) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        bool bad = !isfinite(x[i]) || !isfinite(y[i]) || !isfinite(z[i]) || !(m[i] > 0.0) ||
+                   !(h[i] > 0.0) || !isfinite(m[i]) || !isfinite(h[i]);
+        if (bad) atomicOr(flag, 1);
+    }
+}
+
+__global__ void k_init(const double *__restrict__ x, const double *__restrict__ y,
+                       const double *__restrict__ z, const double *__restrict__ m, int64_t n,
+                       double *__restrict__ ox, double *__restrict__ oy, double *__restrict__ oz,
+                       double *__restrict__ om, int32_t *__restrict__ oid) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        ox[i] = x[i];
+        oy[i] = y[i];
+        oz[i] = z[i];
+        om[i] = m[i];
+        oid[i] = (int32_t)i;
+    }
+}
+
+__global__ void k_set_root(int32_t *nfirst, int32_t *ncount, int32_t n) {
+    nfirst[1] = 0;
+    ncount[1] = n;
+}
+
+__global__ void k_gather_h(const double *__restrict__ h, const int32_t *__restrict__ id, int64_t n,
+                           double *__restrict__ oh) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        oh[i] = h[id[i]];
+}
+
+// ---------------------------------------------------------------------------
+// chunk sums. Payload A: m, m x, m y, m z and max |r - g|^2 (g = box centre).
+// Payload B (leaves): the six Eq. 1 components about the leaf centre of mass
+// and max(|r - g| + 2h). Lane l holds the 8 consecutive elements
+// [base + 8l, base + 8l + 8); pairs, quads and octets are summed in the lane,
+// the remaining 6 levels of the 512-wide tree across lanes.
+// ---------------------------------------------------------------------------
+template <int P>
+struct Pay;
+template <>
+struct Pay<0> {
+    static constexpr int NS = 4;
+};
+template <>
+struct Pay<1> {
+    static constexpr int NS = 6;
+};
+
+struct PartIn {
+    const double *x, *y, *z, *m, *h;
+};
+
+template <int P>
+__device__ __forceinline__ void chunk_sums(const PartIn &in, int64_t base, int64_t end,
+                                           const double g[3], const double c[3],
+                                           double (&sums)[Pay<P>::NS], double &mx) {
+    constexpr int NS = Pay<P>::NS;
+    double v[8][NS];
+    double ml = -1.0;
+    const int64_t p0 = base + 8 * (int64_t)lane_id();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int64_t i = p0 + t;
+        if (i < end) {
+            const double xi = in.x[i], yi = in.y[i], zi = in.z[i], mi = in.m[i];
+            if constexpr (P == 0) {
+                v[t][0] = mi;
+                v[t][1] = mi * xi;
+                v[t][2] = mi * yi;
+                v[t][3] = mi * zi;
+                ml = fmax(ml, dist2(xi, yi, zi, g[0], g[1], g[2]));
+            } else {
+                const double d0 = xi - c[0], d1 = yi - c[1], d2 = zi - c[2];
+                const double r2 = (d0 * d0 + d1 * d1) + d2 * d2;
+                const double m3 = 3.0 * mi;
+                const double mr2 = mi * r2;
+                v[t][0] = (m3 * d0) * d0 - mr2;
+                v[t][1] = (m3 * d0) * d1;
+                v[t][2] = (m3 * d0) * d2;
+                v[t][3] = (m3 * d1) * d1 - mr2;
+                v[t][4] = (m3 * d1) * d2;
+                v[t][5] = (m3 * d2) * d2 - mr2;
+                const double rg = sqrt(dist2(xi, yi, zi, g[0], g[1], g[2]));
+                ml = fmax(ml, rg + 2.0 * in.h[i]);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) v[t][s] = 0.0;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const double a = (v[0][s] + v[1][s]) + (v[2][s] + v[3][s]);
+        const double b = (v[4][s] + v[5][s]) + (v[6][s] + v[7][s]);
+        sums[s] = wave_sum(a + b);
+    }
+    mx = wave_max(ml);
+}
+
+struct NodeOut {
+    int32_t *nfirst, *ncount;
+    double *nlo, *nhi, *ncom, *nM, *nhint, *nhnode, *nQ;
+    int32_t *naxis;
+    double *nplane;
+};
+
+__device__ __forceinline__ void box_centre(const NodeOut &o, int64_t lab, double g[3]) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[d] = 0.5 * (o.nlo[3 * lab + d] + o.nhi[3 * lab + d]);
+}
+
+// Payload-A result of a non-empty node: mass, centre of mass, h_node_int,
+// and for an internal node the split axis/plane and the children's boxes.
+__device__ void finish_a(const NodeOut &o, int64_t lab, bool leaf, const double s[4], double mx) {
+    const double M = s[0] + 0.0;
+    double com[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) com[d] = (s[1 + d] + 0.0) / M;
+    if (lane_id() == 0) {
+        o.nM[lab] = M;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) o.ncom[3 * lab + d] = com[d];
+        o.nhint[lab] = sqrt(mx);
+        o.nhnode[lab] = -1.0;
+    }
+    if (leaf) return;
+    double lo[3], hi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = o.nlo[3 * lab + d];
+        hi[d] = o.nhi[3 * lab + d];
+    }
+    int ax = 0;
+    double best = hi[0] - lo[0];
+    if (hi[1] - lo[1] > best) {
+        best = hi[1] - lo[1];
+        ax = 1;
+    }
+    if (hi[2] - lo[2] > best) ax = 2;
+    const double plane = ax == 0 ? com[0] : (ax == 1 ? com[1] : com[2]);
+    if (lane_id() == 0) {
+        o.naxis[lab] = ax;
+        o.nplane[lab] = plane;
+    }
+    const int l = lane_id();
+    if (l < 6) {   // children boxes: lanes 0-2 lower corners, 3-5 upper corners
+        const int d = l % 3;
+        const bool upper = l >= 3;
+        const double v = upper ? hi[d] : lo[d];
+        const int64_t L = 2 * lab, R = 2 * lab + 1;
+        double *dL = upper ? o.nhi : o.nlo;
+        dL[3 * L + d] = (upper && d == ax) ? plane : v;
+        dL[3 * R + d] = (!upper && d == ax) ? plane : v;
+    }
+}
+
+__device__ void finish_b(const NodeOut &o, int64_t lab, const double s[6], double mx) {
+    const int l = lane_id();
+    if (l < 6) o.nQ[6 * lab + l] = (l == 0 ? s[0] : l == 1 ? s[1] : l == 2 ? s[2] : l == 3 ? s[3] : l == 4 ? s[4] : s[5]) + 0.0;
+    if (l == 0) o.nhnode[lab] = mx;
+}
+
+__device__ void finish_empty(const NodeOut &o, int64_t lab, bool leaf, int32_t first) {
+    const int l = lane_id();
+    double g[3];
+    box_centre(o, lab, g);
+    if (l == 0) {
+        o.nM[lab] = 0.0;
+        o.ncom[3 * lab] = g[0];
+        o.ncom[3 * lab + 1] = g[1];
+        o.ncom[3 * lab + 2] = g[2];
+        o.nhint[lab] = -1.0;
+        o.nhnode[lab] = -1.0;
+        if (leaf) {
+            for (int q = 0; q < 6; ++q) o.nQ[6 * lab + q] = 0.0;
+        } else {
+            o.naxis[lab] = -1;
+            o.nfirst[2 * lab] = first;
+            o.ncount[2 * lab] = 0;
+            o.nfirst[2 * lab + 1] = first;
+            o.ncount[2 * lab + 1] = 0;
+        }
+    }
+    if (!leaf && l < 6) {
+        const int d = l % 3;
+        double *dst = l >= 3 ? o.nhi : o.nlo;
+        const double v = dst[3 * lab + d];
+        dst[3 * (2 * lab) + d] = v;
+        dst[3 * (2 * lab + 1) + d] = v;
+    }
+}
+
+struct PartOut {
+    double *x, *y, *z, *m;
+    int32_t *id;
+};
+
+// Stable partition of the elements [base, end) held 8-per-lane; `lb` is the
+// number of left elements before base within the node, `rb` the right ones.
+__device__ __forceinline__ void scatter_chunk(const PartIn &in, const int32_t *__restrict__ id,
+                                              const PartOut &out, int64_t base, int64_t end,
+                                              int ax, double plane, int64_t node_first,
+                                              int64_t nleft_total, int64_t lb, int64_t rb) {
+    const int64_t p0 = base + 8 * (int64_t)lane_id();
+    const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
+    bool left[8];
+    int nl = 0, nv = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int64_t i = p0 + t;
+        const bool valid = i < end;
+        left[t] = valid && (xa[i] < plane);
+        nl += left[t];
+        nv += valid;
+    }
+    const int el = wave_excl_scan(nl);
+    const int ev = wave_excl_scan(nv);
+    int rl = lb + el, rr = rb + (ev - el);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int64_t i = p0 + t;
+        if (i < end) {
+            const int64_t dst = left[t] ? node_first + (rl++) : node_first + nleft_total + (rr++);
+            out.x[dst] = in.x[i];
+            out.y[dst] = in.y[i];
+            out.z[dst] = in.z[i];
+            out.m[dst] = in.m[i];
+            out.id[dst] = id[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one wave per node of the level: nodes of <= 512 particles are done here,
+// larger ones are put on the big-node list.
+// ---------------------------------------------------------------------------
+struct BigCtl {
+    int32_t *ctl;         // [0] big nodes, [1] items
+    int32_t *big_node, *big_base, *item_big;
+};
+
+__global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level, PartIn in,
+                                                        const int32_t *__restrict__ id,
+                                                        PartOut out, NodeOut o, BigCtl bc) {
+    const int64_t w = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t nodes = (int64_t)1 << lvl;
+    if (w >= nodes) return;
+    const int64_t lab = nodes + w;
+    const int32_t s = o.nfirst[lab];
+    const int32_t c = o.ncount[lab];
+    const bool leaf = leaf_level != 0;
+    if (c > kChunk) {
+        int bi = 0, base = 0;
+        const int nch = (c + kChunk - 1) / kChunk;
+        if (lane_id() == 0) {
+            bi = atomicAdd(&bc.ctl[0], 1);
+            base = atomicAdd(&bc.ctl[1], nch);
+            bc.big_node[bi] = (int32_t)lab;
+            bc.big_base[bi] = base;
+        }
+        bi = __shfl(bi, 0, kWave);
+        base = __shfl(base, 0, kWave);
+        for (int j = lane_id(); j < nch; j += kWave) bc.item_big[base + j] = bi;
+        return;
+    }
+    if (c == 0) {
+        finish_empty(o, lab, leaf, s);
+        return;
+    }
+    double g[3];
+    box_centre(o, lab, g);
+    double sa[4], mx;
+    chunk_sums<0>(in, s, (int64_t)s + c, g, g, sa, mx);
+    finish_a(o, lab, leaf, sa, mx);
+    if (leaf) {
+        double com[3];
+        const double M = sa[0] + 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) com[d] = (sa[1 + d] + 0.0) / M;
+        double sb[6], hn;
+        chunk_sums<1>(in, s, (int64_t)s + c, g, com, sb, hn);
+        finish_b(o, lab, sb, hn);
+        return;
+    }
+    // split: axis and plane as finish_a computed them (recomputed in-wave)
+    double lo[3], hi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = o.nlo[3 * lab + d];
+        hi[d] = o.nhi[3 * lab + d];
+    }
+    int ax = 0;
+    double best = hi[0] - lo[0];
+    if (hi[1] - lo[1] > best) {
+        best = hi[1] - lo[1];
+        ax = 1;
+    }
+    if (hi[2] - lo[2] > best) ax = 2;
+    const double plane = (sa[1 + ax] + 0.0) / (sa[0] + 0.0);
+    // count the left side first (needed for the right side's base)
+    const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
+    int nl = 0;
+    const int64_t p0 = (int64_t)s + 8 * (int64_t)lane_id();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int64_t i = p0 + t;
+        nl += (i < (int64_t)s + c) && (xa[i] < plane);
+    }
+    const int nleft = wave_sum_i(nl);
+    scatter_chunk(in, id, out, s, (int64_t)s + c, ax, plane, s, nleft, 0, 0);
+    if (lane_id() == 0) {
+        o.nfirst[2 * lab] = s;
+        o.ncount[2 * lab] = nleft;
+        o.nfirst[2 * lab + 1] = s + nleft;
+        o.ncount[2 * lab + 1] = c - nleft;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// big nodes
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_chunk_reduce(PartIn in, NodeOut o, BigCtl bc,
+                                                         double *__restrict__ part) {
+    const int64_t w = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (w >= bc.ctl[1]) return;
+    const int bi = bc.item_big[w];
+    const int64_t lab = bc.big_node[bi];
+    const int64_t j = w - bc.big_base[bi];
+    const int64_t s = o.nfirst[lab], c = o.ncount[lab];
+    const int64_t base = s + j * kChunk;
+    const int64_t end = min(base + kChunk, s + c);
+    double g[3], com[3] = {0.0, 0.0, 0.0};
+    box_centre(o, lab, g);
+    if constexpr (P == 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) com[d] = o.ncom[3 * lab + d];
+    }
+    constexpr int NS = Pay<P>::NS;
+    double sums[NS], mx;
+    chunk_sums<P>(in, base, end, g, com, sums, mx);
+    const int l = lane_id();
+    if (l < NS) {
+        double v = sums[0];
+#pragma unroll
+        for (int q = 1; q < NS; ++q)
+            if (l == q) v = sums[q];
+        part[8 * w + l] = v;
+    }
+    if (l == 7) part[8 * w + 7] = mx;
+}
+
+// Canonical combination of a big node's chunk sums: groups of 64 chunks are
+// summed across lanes, then the group sums enter a binary-counter stack
+// (LDS) that merges equal-size neighbours left + right; the group count is
+// padded with zero groups to a power of two.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_big_finalize(int leaf_level, NodeOut o, BigCtl bc,
+                                                         const double *__restrict__ part) {
+    constexpr int NS = Pay<P>::NS;
+    __shared__ double stk[kWavesPerBlock][32][NS];
+    const int wv = threadIdx.x / kWave;
+    const int64_t bi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (bi >= bc.ctl[0]) return;
+    const int64_t lab = bc.big_node[bi];
+    const int64_t base = bc.big_base[bi];
+    const int64_t c = o.ncount[lab];
+    const int64_t nch = (c + kChunk - 1) / kChunk;
+    const int64_t ngroups = (nch + kWave - 1) / kWave;
+    int64_t gp = 1;
+    while (gp < ngroups) gp <<= 1;
+    double mx = -1.0;
+    for (int64_t gi = 0; gi < gp; ++gi) {
+        const int64_t j = gi * kWave + lane_id();
+        double v[NS];
+        const bool ok = j < nch;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) v[q] = ok ? part[8 * (base + j) + q] : 0.0;
+        if (ok) mx = fmax(mx, part[8 * (base + j) + 7]);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) v[q] = wave_sum(v[q]);
+        int L = 0;
+        while ((gi >> L) & 1) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) v[q] = stk[wv][L][q] + v[q];
+            ++L;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane_id() == 0) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) stk[wv][L][q] = v[q];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    int top = 0;
+    while ((1ll << top) < gp) ++top;
+    double s[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) s[q] = stk[wv][top][q];
+    mx = wave_max(mx);
+    if constexpr (P == 0) {
+        finish_a(o, lab, leaf_level != 0, s, mx);
+    } else {
+        finish_b(o, lab, s, mx);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_part_count(PartIn in, NodeOut o, BigCtl bc,
+                                                       int32_t *__restrict__ part_left) {
+    const int64_t w = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (w >= bc.ctl[1]) return;
+    const int bi = bc.item_big[w];
+    const int64_t lab = bc.big_node[bi];
+    const int64_t j = w - bc.big_base[bi];
+    const int64_t s = o.nfirst[lab], c = o.ncount[lab];
+    const int64_t base = s + j * kChunk;
+    const int64_t end = min(base + kChunk, s + c);
+    const int ax = o.naxis[lab];
+    const double plane = o.nplane[lab];
+    const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
+    int nl = 0;
+    const int64_t p0 = base + 8 * (int64_t)lane_id();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int64_t i = p0 + t;
+        nl += (i < end) && (xa[i] < plane);
+    }
+    nl = wave_sum_i(nl);
+    if (lane_id() == 0) part_left[w] = nl;
+}
+
+__global__ __launch_bounds__(kBlock) void k_part_scan(NodeOut o, BigCtl bc,
+                                                      int32_t *__restrict__ part_left) {
+    const int64_t bi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (bi >= bc.ctl[0]) return;
+    const int64_t lab = bc.big_node[bi];
+    const int64_t base = bc.big_base[bi];
+    const int64_t s = o.nfirst[lab], c = o.ncount[lab];
+    const int64_t nch = (c + kChunk - 1) / kChunk;
+    int64_t run = 0;
+    for (int64_t g0 = 0; g0 < nch; g0 += kWave) {
+        const int64_t j = g0 + lane_id();
+        const int v = j < nch ? part_left[base + j] : 0;
+        const int e = wave_excl_scan(v);
+        if (j < nch) part_left[base + j] = (int32_t)(run + e);
+        run += wave_sum_i(v);
+    }
+    if (lane_id() == 0) {
+        o.nfirst[2 * lab] = (int32_t)s;
+        o.ncount[2 * lab] = (int32_t)run;
+        o.nfirst[2 * lab + 1] = (int32_t)(s + run);
+        o.ncount[2 * lab + 1] = (int32_t)(c - run);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_part_scatter(PartIn in, const int32_t *__restrict__ id,
+                                                         PartOut out, NodeOut o, BigCtl bc,
+                                                         const int32_t *__restrict__ part_left) {
+    const int64_t w = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (w >= bc.ctl[1]) return;
+    const int bi = bc.item_big[w];
+    const int64_t lab = bc.big_node[bi];
+    const int64_t j = w - bc.big_base[bi];
+    const int64_t s = o.nfirst[lab], c = o.ncount[lab];
+    const int64_t base = s + j * kChunk;
+    const int64_t end = min(base + kChunk, s + c);
+    const int64_t lb = part_left[w];
+    const int64_t rb = j * kChunk - lb;
+    const int64_t nleft = o.ncount[2 * lab];
+    scatter_chunk(in, id, out, base, end, o.naxis[lab], o.nplane[lab], s, nleft, lb, rb);
+}
+
+// Eq. 2: parent quadrupole from the non-empty children, shifted by the
+// offset between the centres of mass.
+__global__ void k_upward(int lvl, NodeOut o) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nodes = (int64_t)1 << lvl;
+    if (i >= nodes) return;
+    const int64_t lab = nodes + i;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (o.ncount[lab] > 0) {
+        const double pc[3] = {o.ncom[3 * lab], o.ncom[3 * lab + 1], o.ncom[3 * lab + 2]};
+        for (int ch = 0; ch < 2; ++ch) {
+            const int64_t C = 2 * lab + ch;
+            if (o.ncount[C] == 0) continue;
+            const double dx[3] = {o.ncom[3 * C] - pc[0], o.ncom[3 * C + 1] - pc[1],
+                                  o.ncom[3 * C + 2] - pc[2]};
+            const double r2 = (dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2];
+            const double MC = o.nM[C];
+            const double m3 = 3.0 * MC;
+            const double mr2 = MC * r2;
+            acc[0] += (o.nQ[6 * C + 0] + (m3 * dx[0]) * dx[0]) - mr2;
+            acc[1] += o.nQ[6 * C + 1] + (m3 * dx[0]) * dx[1];
+            acc[2] += o.nQ[6 * C + 2] + (m3 * dx[0]) * dx[2];
+            acc[3] += (o.nQ[6 * C + 3] + (m3 * dx[1]) * dx[1]) - mr2;
+            acc[4] += o.nQ[6 * C + 4] + (m3 * dx[1]) * dx[2];
+            acc[5] += (o.nQ[6 * C + 5] + (m3 * dx[2]) * dx[2]) - mr2;
+        }
+    }
+    for (int q = 0; q < 6; ++q) o.nQ[6 * lab + q] = acc[q];
+}
+
+// walk records: {box centre, h_node_int (-1 if empty)}, {centre of mass, H_B}
+__global__ void k_records(int64_t nlab, NodeOut o, double4 *__restrict__ rec) {
+    const int64_t lab = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (lab < 1 || lab >= nlab) return;
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = o.nlo[3 * lab + d];
+        hi[d] = o.nhi[3 * lab + d];
+    }
+    double hb = hi[0] - lo[0];
+    if (hi[1] - lo[1] > hb) hb = hi[1] - lo[1];
+    if (hi[2] - lo[2] > hb) hb = hi[2] - lo[2];
+    const bool empty = o.ncount[lab] == 0;
+    rec[2 * lab] = make_double4(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2]),
+                                empty ? -1.0 : o.nhint[lab]);
+    rec[2 * lab + 1] = make_double4(o.ncom[3 * lab], o.ncom[3 * lab + 1], o.ncom[3 * lab + 2], hb);
+}
+
+// mixed form: FP32 offsets from the leaf centre of mass, FP32 m and h
+__global__ void k_mixed_prep(int64_t nleaf, const int32_t *__restrict__ nfirst,
+                             const int32_t *__restrict__ ncount, const double *__restrict__ ncom,
+                             const double *__restrict__ px, const double *__restrict__ py,
+                             const double *__restrict__ pz, const double *__restrict__ pm,
+                             const double *__restrict__ ph, float *__restrict__ fdx,
+                             float *__restrict__ fdy, float *__restrict__ fdz,
+                             float *__restrict__ fm, float *__restrict__ fh) {
+    const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    if (w >= nleaf) return;
+    const int64_t lab = nleaf + w;
+    const int64_t s = nfirst[lab], c = ncount[lab];
+    const double cx = ncom[3 * lab], cy = ncom[3 * lab + 1], cz = ncom[3 * lab + 2];
+    for (int64_t i = s + lane_id(); i < s + c; i += kWave) {
+        fdx[i] = (float)(px[i] - cx);
+        fdy[i] = (float)(py[i] - cy);
+        fdz[i] = (float)(pz[i] - cz);
+        fm[i] = (float)pm[i];
+        fh[i] = (float)ph[i];
+    }
+}
+
+inline unsigned blocks_for_waves(int64_t waves) {
+    return (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+}
+
+}  // namespace
+
+rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const double *z,
+                      const double *m, const double *h, hipStream_t s) {
+    const int64_t n = t->n;
+    std::vector<void *> tmp;   // build scratch, freed at the end
+    auto A = [&](size_t bytes, std::vector<void *> &owner) { return dalloc(t, bytes, s, owner); };
+
+    // tree-owned arrays
+    t->nfirst = (int32_t *)A(sizeof(int32_t) * t->nlab, t->allocs);
+    t->ncount = (int32_t *)A(sizeof(int32_t) * t->nlab, t->allocs);
+    t->nlo = (double *)A(sizeof(double) * 3 * t->nlab, t->allocs);
+    t->nhi = (double *)A(sizeof(double) * 3 * t->nlab, t->allocs);
+    t->ncom = (double *)A(sizeof(double) * 3 * t->nlab, t->allocs);
+    t->nM = (double *)A(sizeof(double) * t->nlab, t->allocs);
+    t->nQ = (double *)A(sizeof(double) * 6 * t->nlab, t->allocs);
+    t->nhint = (double *)A(sizeof(double) * t->nlab, t->allocs);
+    t->nhnode = (double *)A(sizeof(double) * t->nlab, t->allocs);
+    t->wrec = (double4 *)A(sizeof(double4) * 2 * t->nlab, t->allocs);
+    t->ph = (double *)A(sizeof(double) * n, t->allocs);
+    t->dflag = (int32_t *)A(sizeof(int32_t) * 4, t->allocs);
+    BuildScratch b{};
+    for (int i = 0; i < 2; ++i) {
+        b.x[i] = (double *)A(sizeof(double) * n, tmp);
+        b.y[i] = (double *)A(sizeof(double) * n, tmp);
+        b.z[i] = (double *)A(sizeof(double) * n, tmp);
+        b.m[i] = (double *)A(sizeof(double) * n, tmp);
+        b.id[i] = (int32_t *)A(sizeof(int32_t) * n, tmp);
+    }
+    b.max_big = std::min<int64_t>(t->nleaf, n / (kChunk + 1) + 1);
+    b.max_items = n / kChunk + b.max_big + 1;
+    b.ctl = (int32_t *)A(sizeof(int32_t) * 4, tmp);
+    b.big_node = (int32_t *)A(sizeof(int32_t) * b.max_big, tmp);
+    b.big_base = (int32_t *)A(sizeof(int32_t) * b.max_big, tmp);
+    b.item_big = (int32_t *)A(sizeof(int32_t) * b.max_items, tmp);
+    b.part = (double *)A(sizeof(double) * 8 * b.max_items, tmp);
+    b.part_left = (int32_t *)A(sizeof(int32_t) * b.max_items, tmp);
+    b.naxis = (int32_t *)A(sizeof(int32_t) * t->nlab, tmp);
+    b.nplane = (double *)A(sizeof(double) * t->nlab, tmp);
+    const int nbp = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
+    b.bounds = (double *)A(sizeof(double) * 6 * nbp, tmp);
+    for (void *p : t->allocs)
+        if (!p) return RCB_ENOMEM;
+    for (void *p : tmp)
+        if (!p) return RCB_ENOMEM;
+
+    RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 4, s));
+    if (t->p.validate) {
+        k_validate<<<nbp, kBlock, 0, s>>>(x, y, z, m, h, n, t->dflag);
+        RCB_LAUNCH_CHECK("k_validate");
+        int32_t flag = 0;
+        RCB_HIP(hipMemcpyAsync(&flag, t->dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        RCB_HIP(hipStreamSynchronize(s));
+        if (flag) {
+            set_error("rcb_build: input has a non-finite coordinate, m <= 0 or h <= 0");
+            for (void *p : tmp) hipFreeAsync(p, s);
+            return RCB_EINPUT;
+        }
+    }
+    const unsigned gN = (unsigned)std::min<int64_t>(4096, (n + kBlock - 1) / kBlock);
+    k_init<<<gN, kBlock, 0, s>>>(x, y, z, m, n, b.x[0], b.y[0], b.z[0], b.m[0], b.id[0]);
+    RCB_LAUNCH_CHECK("k_init");
+    k_bounds_partial<<<nbp, kBlock, 0, s>>>(x, y, z, n, b.bounds);
+    RCB_LAUNCH_CHECK("k_bounds_partial");
+    k_bounds_final<<<1, 64, 0, s>>>(b.bounds, nbp, t->nlo, t->nhi);
+    RCB_LAUNCH_CHECK("k_bounds_final");
+    k_set_root<<<1, 1, 0, s>>>(t->nfirst, t->ncount, (int32_t)n);
+    RCB_LAUNCH_CHECK("k_set_root");
+    NodeOut o{t->nfirst, t->ncount, t->nlo, t->nhi, t->ncom, t->nM, t->nhint, t->nhnode, t->nQ,
+              b.naxis, b.nplane};
+    BigCtl bc{b.ctl, b.big_node, b.big_base, b.item_big};
+    int cur = 0;
+    const int64_t item_waves = b.max_items;
+    const int64_t big_waves = b.max_big;
+    for (int lvl = 0; lvl <= t->k; ++lvl) {
+        const bool leaf = lvl == t->k;
+        if (leaf) {
+            k_gather_h<<<gN, kBlock, 0, s>>>(h, b.id[cur], n, t->ph);
+            RCB_LAUNCH_CHECK("k_gather_h");
+        }
+        PartIn in{b.x[cur], b.y[cur], b.z[cur], b.m[cur], t->ph};
+        PartOut out{b.x[cur ^ 1], b.y[cur ^ 1], b.z[cur ^ 1], b.m[cur ^ 1], b.id[cur ^ 1]};
+        RCB_HIP(hipMemsetAsync(b.ctl, 0, sizeof(int32_t) * 4, s));
+        const int64_t nodes = (int64_t)1 << lvl;
+        k_level_small<<<blocks_for_waves(nodes), kBlock, 0, s>>>(lvl, leaf, in, b.id[cur], out, o, bc);
+        RCB_LAUNCH_CHECK("k_level_small");
+        const int64_t bw = std::min<int64_t>(big_waves, nodes);
+        k_chunk_reduce<0><<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part);
+        RCB_LAUNCH_CHECK("k_chunk_reduce<0>");
+        k_big_finalize<0><<<blocks_for_waves(bw), kBlock, 0, s>>>(leaf, o, bc, b.part);
+        RCB_LAUNCH_CHECK("k_big_finalize<0>");
+        if (leaf) {
+            k_chunk_reduce<1><<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part);
+            RCB_LAUNCH_CHECK("k_chunk_reduce<1>");
+            k_big_finalize<1><<<blocks_for_waves(bw), kBlock, 0, s>>>(leaf, o, bc, b.part);
+            RCB_LAUNCH_CHECK("k_big_finalize<1>");
+        } else {
+            k_part_count<<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part_left);
+            RCB_LAUNCH_CHECK("k_part_count");
+            k_part_scan<<<blocks_for_waves(bw), kBlock, 0, s>>>(o, bc, b.part_left);
+            RCB_LAUNCH_CHECK("k_part_scan");
+            k_part_scatter<<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, b.id[cur], out, o, bc,
+                                                                           b.part_left);
+            RCB_LAUNCH_CHECK("k_part_scatter");
+            cur ^= 1;
+        }
+    }
+    for (int lvl = t->k - 1; lvl >= 0; --lvl) {
+        const int64_t nodes = (int64_t)1 << lvl;
+        k_upward<<<(unsigned)((nodes + 255) / 256), 256, 0, s>>>(lvl, o);
+        RCB_LAUNCH_CHECK("k_upward");
+    }
+    k_records<<<(unsigned)((t->nlab + 255) / 256), 256, 0, s>>>(t->nlab, o, t->wrec);
+    RCB_LAUNCH_CHECK("k_records");
+
+    // keep the final particle buffers; release the other half of the ping-pong
+    t->px = b.x[cur];
+    t->py = b.y[cur];
+    t->pz = b.z[cur];
+    t->pm = b.m[cur];
+    t->pid = b.id[cur];
+    for (void *p : {(void *)b.x[cur], (void *)b.y[cur], (void *)b.z[cur], (void *)b.m[cur],
+                    (void *)b.id[cur]}) {
+        t->allocs.push_back(p);
+        for (auto &q : tmp)
+            if (q == p) q = nullptr;
+    }
+    if (t->p.precision == RCB_MIXED) {
+        t->fdx = (float *)A(sizeof(float) * n, t->allocs);
+        t->fdy = (float *)A(sizeof(float) * n, t->allocs);
+        t->fdz = (float *)A(sizeof(float) * n, t->allocs);
+        t->fm = (float *)A(sizeof(float) * n, t->allocs);
+        t->fh = (float *)A(sizeof(float) * n, t->allocs);
+        if (!t->fdx || !t->fdy || !t->fdz || !t->fm || !t->fh) return RCB_ENOMEM;
+        k_mixed_prep<<<blocks_for_waves(t->nleaf), kBlock, 0, s>>>(
+            t->nleaf, t->nfirst, t->ncount, t->ncom, t->px, t->py, t->pz, t->pm, t->ph, t->fdx,
+            t->fdy, t->fdz, t->fm, t->fh);
+        RCB_LAUNCH_CHECK("k_mixed_prep");
+    }
+    for (void *p : tmp)
+        if (p) RCB_HIP(hipFreeAsync(p, s));
+    return RCB_OK;
+}
+
+}  // namespace rcb

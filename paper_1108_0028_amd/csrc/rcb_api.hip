@@ -1,0 +1,240 @@
+// rcb_api.hip -- the C ABI declared in include/rcb.h: argument checks on the
+// host, tree lifetime, stream-ordered device memory.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "rcb_internal.h"
+
+namespace rcb {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+rcb_status hip_fail(hipError_t e, const char *what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? RCB_ENOMEM : RCB_EHIP;
+}
+
+// Stream-ordered allocation from the device's default pool, which keeps
+// freed memory for reuse (release threshold raised once per device).
+void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owner) {
+    static bool pool_set[64] = {false};
+    if (t->device >= 0 && t->device < 64 && !pool_set[t->device]) {
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, t->device) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+        pool_set[t->device] = true;
+    }
+    void *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess) {
+        set_error(std::string("hipMallocAsync(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    owner.push_back(p);
+    return p;
+}
+
+static void free_all(rcb_tree *t) {
+    for (void *p : t->list_allocs)
+        if (p) (void)hipFreeAsync(p, t->stream);
+    for (void *p : t->allocs)
+        if (p) (void)hipFreeAsync(p, t->stream);
+    t->list_allocs.clear();
+    t->allocs.clear();
+    (void)hipStreamSynchronize(t->stream);
+}
+
+}  // namespace rcb
+
+using namespace rcb;
+
+extern "C" {
+
+void rcb_params_default(rcb_params *p) {
+    if (!p) return;
+    p->n_ll = 12;
+    p->precision = RCB_FP64;
+    p->theta = 0.7;
+    p->validate = 0;
+    p->reserved = 0;
+}
+
+const char *rcb_last_error(void) { return g_last_error.c_str(); }
+
+rcb_status rcb_build(const double *x, const double *y, const double *z, const double *m,
+                     const double *h, int64_t n, const rcb_params *p, void *stream,
+                     rcb_tree **out) {
+    g_last_error.clear();
+    if (!out) {
+        set_error("rcb_build: out is NULL");
+        return RCB_EINVAL;
+    }
+    *out = nullptr;
+    if (!x || !y || !z || !m || !h || !p) {
+        set_error("rcb_build: NULL input pointer or params");
+        return RCB_EINVAL;
+    }
+    if (n < 1 || n > 0x7fffffffLL) {
+        set_error("rcb_build: n must be in [1, 2^31 - 1]");
+        return RCB_EINVAL;
+    }
+    if (p->n_ll < 1) {
+        set_error("rcb_build: n_ll must be >= 1");
+        return RCB_EINVAL;
+    }
+    if (!(p->theta >= 0.0) || !std::isfinite(p->theta)) {
+        set_error("rcb_build: theta must be finite and >= 0");
+        return RCB_EINVAL;
+    }
+    if (p->precision != RCB_FP64 && p->precision != RCB_MIXED) {
+        set_error("rcb_build: unknown precision");
+        return RCB_EINVAL;
+    }
+    if (p->reserved != 0) {
+        set_error("rcb_build: reserved field must be 0");
+        return RCB_EINVAL;
+    }
+    int k = 0;
+    while ((int64_t)p->n_ll * ((int64_t)1 << k) < n) ++k;
+    if (k > 29) {
+        set_error("rcb_build: tree deeper than 29 levels (n / n_ll too large)");
+        return RCB_EINVAL;
+    }
+    rcb_tree *t = new rcb_tree();
+    t->n = n;
+    t->k = k;
+    t->nleaf = (int64_t)1 << k;
+    t->nlab = (int64_t)2 << k;
+    t->p = *p;
+    t->stream = (hipStream_t)stream;
+    if (hipGetDevice(&t->device) != hipSuccess) t->device = 0;
+    rcb_status st = build_tree(t, x, y, z, m, h, t->stream);
+    if (st != RCB_OK) {
+        std::string msg = g_last_error;
+        free_all(t);
+        delete t;
+        g_last_error = msg;
+        return st;
+    }
+    *out = t;
+    return RCB_OK;
+}
+
+rcb_status rcb_neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, void *stream) {
+    g_last_error.clear();
+    if (!t || !offsets || !total) {
+        set_error("rcb_neighbours_count: NULL argument");
+        return RCB_EINVAL;
+    }
+    t->stream = (hipStream_t)stream;
+    return neighbours_count(t, offsets, total, t->stream);
+}
+
+rcb_status rcb_neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, int64_t capacity,
+                               void *stream) {
+    g_last_error.clear();
+    if (!t || !offsets || (!ids && capacity > 0)) {
+        set_error("rcb_neighbours_fill: NULL argument");
+        return RCB_EINVAL;
+    }
+    if (capacity < 0) {
+        set_error("rcb_neighbours_fill: negative capacity");
+        return RCB_EINVAL;
+    }
+    t->stream = (hipStream_t)stream;
+    return neighbours_fill(t, offsets, ids, capacity, t->stream);
+}
+
+rcb_status rcb_gravity(rcb_tree *t, void *ax, void *ay, void *az, void *stream) {
+    g_last_error.clear();
+    if (!t || !ax || !ay || !az) {
+        set_error("rcb_gravity: NULL argument");
+        return RCB_EINVAL;
+    }
+    t->stream = (hipStream_t)stream;
+    return gravity(t, ax, ay, az, t->stream);
+}
+
+rcb_status rcb_gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *gz, void *dx,
+                           void *dy, void *dz, void *dm, void *stream) {
+    g_last_error.clear();
+    if (!t || !gx || !gy || !gz || !dx || !dy || !dz || !dm) {
+        set_error("rcb_gravity_vjp: NULL argument");
+        return RCB_EINVAL;
+    }
+    t->stream = (hipStream_t)stream;
+    return gravity_vjp(t, gx, gy, gz, dx, dy, dz, dm, t->stream);
+}
+
+rcb_status rcb_get_info(const rcb_tree *t, rcb_tree_info *info) {
+    if (!t || !info) {
+        set_error("rcb_get_info: NULL argument");
+        return RCB_EINVAL;
+    }
+    info->n = t->n;
+    info->k = t->k;
+    info->precision = t->p.precision;
+    info->n_labels = t->nlab;
+    info->near_total = t->walked ? t->near_total : -1;
+    info->far_total = t->walked ? t->far_total : -1;
+    info->theta = t->p.theta;
+    return RCB_OK;
+}
+
+rcb_status rcb_tree_export(rcb_tree *t, int32_t field, void *dst, size_t bytes, void *stream) {
+    g_last_error.clear();
+    if (!t || !dst) {
+        set_error("rcb_tree_export: NULL argument");
+        return RCB_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    t->stream = s;
+    if (field >= RCB_FIELD_NEAR_OFF) {
+        rcb_status st = ensure_walk(t, s);
+        if (st != RCB_OK) return st;
+    }
+    const void *src = nullptr;
+    size_t need = 0;
+    const size_t L = (size_t)t->nlab;
+    switch (field) {
+        case RCB_FIELD_PERM: src = t->pid; need = sizeof(int32_t) * (size_t)t->n; break;
+        case RCB_FIELD_FIRST: src = t->nfirst; need = sizeof(int32_t) * L; break;
+        case RCB_FIELD_COUNT: src = t->ncount; need = sizeof(int32_t) * L; break;
+        case RCB_FIELD_LO: src = t->nlo; need = sizeof(double) * 3 * L; break;
+        case RCB_FIELD_HI: src = t->nhi; need = sizeof(double) * 3 * L; break;
+        case RCB_FIELD_COM: src = t->ncom; need = sizeof(double) * 3 * L; break;
+        case RCB_FIELD_MASS: src = t->nM; need = sizeof(double) * L; break;
+        case RCB_FIELD_QUAD: src = t->nQ; need = sizeof(double) * 6 * L; break;
+        case RCB_FIELD_HINT: src = t->nhint; need = sizeof(double) * L; break;
+        case RCB_FIELD_HNODE: src = t->nhnode; need = sizeof(double) * L; break;
+        case RCB_FIELD_NEAR_OFF: src = t->near_off; need = sizeof(int64_t) * ((size_t)t->nleaf + 1); break;
+        case RCB_FIELD_FAR_OFF: src = t->far_off; need = sizeof(int64_t) * ((size_t)t->nleaf + 1); break;
+        case RCB_FIELD_NEAR: src = t->near_list; need = sizeof(int32_t) * (size_t)t->near_total; break;
+        case RCB_FIELD_FAR: src = t->far_list; need = sizeof(int32_t) * (size_t)t->far_total; break;
+        default:
+            set_error("rcb_tree_export: unknown field");
+            return RCB_EINVAL;
+    }
+    if (bytes < need) {
+        set_error("rcb_tree_export: buffer of " + std::to_string(bytes) + " bytes < " +
+                  std::to_string(need));
+        return RCB_ECAPACITY;
+    }
+    if (need) RCB_HIP(hipMemcpyAsync(dst, src, need, hipMemcpyDeviceToDevice, s));
+    return RCB_OK;
+}
+
+void rcb_destroy(rcb_tree *t) {
+    if (!t) return;
+    free_all(t);
+    delete t;
+}
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+// rcb_internal.h -- private declarations of the MI355X RCB-tree library.
+//
+// Layout in HBM (all arrays owned by the tree, allocated stream-ordered):
+//   particles, tree order (a node's particles are contiguous, Sec. 2.1
+//   "Particle sorting"): px py pz pm ph (FP64), pid (int32 caller index);
+//   mixed form adds fdx fdy fdz (FP32 offset from the leaf centre of mass),
+//   fm fh (FP32).
+//   nodes, indexed by label (root 1, children 2n and 2n+1, Sec. 2.1 "Node
+//   labelling"): nfirst ncount (int32), nlo nhi ncom (3 FP64 per label),
+//   nM nhint nhnode (FP64), nQ (6 FP64 per label), nplane + naxis (split).
+//   walk records: two double4 per label {g.xyz, h_int} {com.xyz, H_B};
+//   an empty node has h_int = -1.
+//   interaction lists: per leaf CSR, near entries = label | candidate << 31.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "rcb.h"
+
+namespace rcb {
+
+constexpr int kWave = 64;
+constexpr int kChunk = 512;          // elements per wave item of the big-node passes
+constexpr int kStackCap = 2048;      // LIFO walk stack entries per wave (LDS)
+constexpr double kReachPad = 1.0 + 0x1p-32;
+
+struct BuildScratch {
+    // ping-pong particle buffers
+    double *x[2], *y[2], *z[2], *m[2];
+    int32_t *id[2];
+    // big-node machinery
+    int32_t *ctl;          // [0] big-node count, [1] item count, [2] error flag
+    int32_t *big_node;     // big-node list (labels)
+    int32_t *big_base;     // first item of each big node
+    int32_t *item_big;     // item -> big-node index
+    double *part;          // item partial sums, 8 doubles per item
+    int32_t *part_left;    // item left-flag counts, then exclusive offsets
+    int32_t *naxis;        // split axis per label
+    double *nplane;        // split coordinate per label
+    double *bounds;        // per-block min/max partials (6 per block)
+    int64_t max_items;
+    int64_t max_big;
+};
+
+}  // namespace rcb
+
+struct rcb_tree {
+    int64_t n = 0;
+    int k = 0;
+    int64_t nleaf = 0;
+    int64_t nlab = 0;
+    rcb_params p{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    double *px = nullptr, *py = nullptr, *pz = nullptr, *pm = nullptr, *ph = nullptr;
+    int32_t *pid = nullptr;
+    float *fdx = nullptr, *fdy = nullptr, *fdz = nullptr, *fm = nullptr, *fh = nullptr;
+
+    int32_t *nfirst = nullptr, *ncount = nullptr;
+    double *nlo = nullptr, *nhi = nullptr, *ncom = nullptr, *nM = nullptr, *nQ = nullptr;
+    double *nhint = nullptr, *nhnode = nullptr;
+    double4 *wrec = nullptr;
+
+    bool walked = false;
+    int64_t near_total = -1, far_total = -1;
+    int64_t *near_off = nullptr, *far_off = nullptr;
+    int32_t *near_list = nullptr, *far_list = nullptr;
+    int32_t *dflag = nullptr;          // device error flags (walk overflow etc.)
+
+    std::vector<void *> allocs;        // everything to free on destroy
+    std::vector<void *> list_allocs;
+};
+
+namespace rcb {
+
+void set_error(const std::string &msg);
+rcb_status hip_fail(hipError_t e, const char *what);
+void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owner);
+
+// build (k_build.hip)
+rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const double *z,
+                      const double *m, const double *h, hipStream_t s);
+// device exclusive scan of int64 counts in place-free form: out[0..n] (k_scan.hip)
+rcb_status scan_i64(rcb_tree *t, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+// walk (k_walk.hip)
+rcb_status ensure_walk(rcb_tree *t, hipStream_t s);
+// neighbours (k_neigh.hip)
+rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipStream_t s);
+rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, int64_t cap,
+                           hipStream_t s);
+// gravity (k_grav.hip)
+rcb_status gravity(rcb_tree *t, void *ax, void *ay, void *az, hipStream_t s);
+// vjp (k_vjp.hip)
+rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *gz, void *dx,
+                       void *dy, void *dz, void *dm, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// device helpers shared by the kernels of this library
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Canonical sum of the 64 lane values: adjacent lanes first, then pairs of
+// pairs (xor butterfly; both partners of a pair get the same, commutative sum).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+__device__ __forceinline__ float wave_sumf(float v) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+// exclusive prefix sum over lanes
+__device__ __forceinline__ int wave_excl_scan(int v) {
+    int x = v;
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int y = __shfl_up(x, o, kWave);
+        if (l >= o) x += y;
+    }
+    return x - v;
+}
+__device__ __forceinline__ int64_t wave_excl_scan64(int64_t v) {
+    int64_t x = v;
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int64_t y = __shfl_up(x, o, kWave);
+        if (l >= o) x += y;
+    }
+    return x - v;
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int rank_below(uint64_t mask) {
+    const int l = lane_id();
+    uint64_t below = l ? (mask & ((~0ull) >> (64 - l))) : 0ull;
+    return __popcll(below);
+}
+__device__ __forceinline__ double dist2(double ax, double ay, double az, double bx, double by,
+                                        double bz) {
+    double dx = ax - bx, dy = ay - by, dz = az - bz;
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+}  // namespace rcb
+
+#define RCB_HIP(expr)                                         \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return rcb::hip_fail(_e, #expr); \
+    } while (0)
+
+#define RCB_LAUNCH_CHECK(name)                                   \
+    do {                                                         \
+        hipError_t _e = hipGetLastError();                       \
+        if (_e != hipSuccess) return rcb::hip_fail(_e, name);    \
+    } while (0)

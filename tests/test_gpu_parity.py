@@ -1,0 +1,165 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bars: tree (ranges, permutation, boxes, masses, centres of mass, radii,
+quadrupoles) and interaction lists bit-identical; neighbour CSR identical;
+accelerations within 1e-5 (FP64 form) and 2e-4 (mixed form) of the oracle on
+the same tree, measured as max_i |da_i| / max(|a_i|, 1e-3 rms|a|).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from oracle import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-5, "mixed": 2e-4}
+
+SMALL = [(1, 12, "uniform"), (5, 12, "uniform"), (13, 12, "uniform"), (300, 4, "clustered"),
+         (1001, 8, "plummer"), (777, 3, "uniform"), (12305, 6, "clustered"), (40000, 12, "plummer")]
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _gpu_tree(c, n_ll, theta, precision="fp64"):
+    torch = _torch()
+    from paper_1108_0028_amd import Tree
+    dev = torch.device("cuda:0")
+    cv = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    return Tree(cv(c.x), cv(c.y), cv(c.z), cv(c.m), cv(c.h), n_ll=n_ll, theta=theta,
+                precision=precision)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _bits(a):
+    return np.ascontiguousarray(a, dtype=np.float64).view(np.int64)
+
+
+def compare_trees(gt, ot):
+    topo, nd = ot.topology(), ot.nodes()
+    L = ot.nlab
+    assert gt.info()["k"] == ot.k
+    np.testing.assert_array_equal(_np(gt.export("perm")), topo["perm"])
+    np.testing.assert_array_equal(_np(gt.export("first"))[1:], topo["first"][1:])
+    np.testing.assert_array_equal(_np(gt.export("count"))[1:], topo["count"][1:])
+    for f, key, w in (("lo", "lo", 3), ("hi", "hi", 3), ("com", "com", 3), ("mass", "M", 1),
+                      ("hint", "hint", 1), ("hnode", "hnode", 1), ("quad", "Q", 6)):
+        g = _np(gt.export(f)).reshape(L, w) if w > 1 else _np(gt.export(f))
+        o = nd[key]
+        bad = np.nonzero(_bits(g[1:]).reshape(L - 1, -1) != _bits(o[1:]).reshape(L - 1, -1))[0]
+        assert bad.size == 0, f"{f}: {bad.size} labels differ, first {bad[:5] + 1}: gpu {g[1:][bad[:3]]} oracle {o[1:][bad[:3]]}"
+
+
+def compare_lists(gt, ot, leaves=None):
+    noff = _np(gt.export("near_off"))
+    foff = _np(gt.export("far_off"))
+    near = _np(gt.export("near")).view(np.uint32)
+    far = _np(gt.export("far"))
+    ot.cache_sizes()
+    nleaf = ot.n_leaves
+    idx = range(nleaf) if leaves is None else [l - nleaf for l in leaves]
+    for i in idx:
+        on, of = ot.leaf_lists(nleaf + i)
+        gn = near[noff[i]:noff[i + 1]]
+        gf = far[foff[i]:foff[i + 1]]
+        np.testing.assert_array_equal(gn, on, err_msg=f"near list of leaf {nleaf + i}")
+        np.testing.assert_array_equal(np.sort(gf), np.sort(of), err_msg=f"far list of leaf {nleaf + i}")
+
+
+def gate(a_gpu, a_ref):
+    da = np.linalg.norm(a_gpu - a_ref, axis=1)
+    na = np.linalg.norm(a_ref, axis=1)
+    rms = np.sqrt(np.mean(na * na))
+    return float(np.max(da / np.maximum(na, 1e-3 * rms)))
+
+
+@pytest.mark.parametrize("n,nll,kind", SMALL)
+def test_tree_and_lists_bit_identical(n, nll, kind):
+    c = W.small_random(n, 1000 + n, kind)
+    _say("tree", n, nll, kind)
+    gt = _gpu_tree(c, nll, 0.6)
+    ot = O.OracleTree(*c.arrays(), n_ll=nll)
+    compare_trees(gt, ot)
+    ot.walk(0.6)
+    compare_lists(gt, ot)
+
+
+def test_degenerate_coincident_particles():
+    c = W.small_random(700, 3, "uniform")
+    c.x[:] = 0.25
+    c.y[:] = -0.5
+    c.z[:] = 0.125
+    _say("coincident", c.n)
+    gt = _gpu_tree(c, 4, 0.7)
+    ot = O.OracleTree(*c.arrays(), n_ll=4)
+    compare_trees(gt, ot)
+    ot.walk(0.7)
+    compare_lists(gt, ot)
+    off, ids = gt.neighbours()
+    ooff, oids, _ = ot.neighbours()
+    np.testing.assert_array_equal(_np(off), ooff)
+    np.testing.assert_array_equal(_np(ids), oids)
+
+
+@pytest.mark.parametrize("n,nll,kind", SMALL)
+def test_neighbours_identical(n, nll, kind):
+    c = W.small_random(n, 2000 + n, kind, h_scale=1.5)
+    _say("neighbours", n, nll, kind)
+    gt = _gpu_tree(c, nll, 0.5)
+    off, ids = gt.neighbours()
+    ot = O.OracleTree(*c.arrays(), n_ll=nll)
+    ot.walk(0.5)
+    ooff, oids, valid = ot.neighbours()
+    np.testing.assert_array_equal(_np(off), ooff)
+    np.testing.assert_array_equal(_np(ids), oids)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,nll,kind", SMALL)
+def test_gravity_matches_oracle(n, nll, kind, precision):
+    c = W.small_random(n, 3000 + n, kind)
+    for theta in (0.0, 0.5, 0.8):
+        _say("gravity", precision, n, nll, kind, theta)
+        gt = _gpu_tree(c, nll, theta, precision)
+        a = np.stack([_np(v).astype(np.float64) for v in gt.gravity()], 1)
+        ot = O.OracleTree(*c.arrays(), n_ll=nll)
+        ot.walk(theta)
+        ref = np.stack(ot.gravity(), 1)
+        g = gate(a, ref)
+        assert g <= TOL[precision], (precision, theta, g)
+        if precision == "fp64":
+            assert g <= 1e-11, (theta, g)   # only summation order differs
+
+
+def test_uniform_sphere_config():
+    c = W.uniform_sphere()
+    _say("uniform sphere 4096")
+    gt = _gpu_tree(c, 8, 0.5)
+    ot = O.OracleTree(*c.arrays(), n_ll=8)
+    compare_trees(gt, ot)
+    ot.walk(0.5)
+    compare_lists(gt, ot)
+    off, ids = gt.neighbours()
+    assert np.all(np.diff(_np(off)) == 50)
+    ooff, oids, _ = ot.neighbours()
+    np.testing.assert_array_equal(_np(ids), oids)
+    ref = np.stack(ot.gravity(), 1)
+    for prec in ("fp64", "mixed"):
+        g = _gpu_tree(c, 8, 0.5, prec)
+        a = np.stack([_np(v).astype(np.float64) for v in g.gravity()], 1)
+        assert gate(a, ref) <= TOL[prec]
