@@ -16,15 +16,8 @@
 // their leaf's centre of mass; per (A, B) the FP64 offset com_A - com_B is
 // rounded to FP32 once; P2P, accumulation and L2P in FP32; M2L in FP64.
 //
-// Closed forms used for one source (x = R, r = |R|, q = Q x, s = x.Q.x,
-// D_n = (-1)^n (2n-1)!! / r^(2n+1)):
-//   f_i   = a1 x_i + c0 q_i
-//   J_il  = b2 x_i x_l + a1 d_il + c1 (q_i x_l + q_l x_i) + c0 Q_il
-//   H_ilm = e3 x_i x_l x_m + b2 (d_il x_m + d_im x_l + d_lm x_i)
-//           + c2 (q_i x_l x_m + q_l x_i x_m + q_m x_i x_l)
-//           + c1 (Q_lm x_i + Q_im x_l + Q_il x_m + q_i d_lm + q_l d_im + q_m d_il)
-//   a1 = M D1 + s D3/6, b2 = M D2 + s D4/6, e3 = M D3 + s D5/6,
-//   c0 = D2/3, c1 = D3/3, c2 = D4/3   (traceless Q).
+// The far-field closed forms are in far_math.h.
+#include "far_math.h"
 #include "rcb_internal.h"
 
 namespace rcb {
@@ -33,73 +26,9 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
 
-// unique-component index maps
-__host__ __device__ constexpr int jidx(int i, int l) {
-    const int a = i < l ? i : l, b = i < l ? l : i;
-    return a == 0 ? b : (a == 1 ? 2 + b : 5);
-}
-__host__ __device__ constexpr int hidx(int i, int l, int m) {
-    // sort (i, l, m)
-    int a = i, b = l, c = m, t = 0;
-    if (a > b) { t = a; a = b; b = t; }
-    if (b > c) { t = b; b = c; c = t; }
-    if (a > b) { t = a; a = b; b = t; }
-    // (0,0,0)=0 (0,0,1)=1 (0,0,2)=2 (0,1,1)=3 (0,1,2)=4 (0,2,2)=5 (1,1,1)=6 (1,1,2)=7 (1,2,2)=8 (2,2,2)=9
-    return a == 0 ? (b == 0 ? c : (b == 1 ? 2 + c : 5)) : (a == 1 ? (b == 1 ? 5 + c : 8) : 9);
-}
-
-__device__ __forceinline__ void m2l_accumulate(double x, double y, double z, double M,
-                                               const double qq[6], double (&c)[19]) {
-    const double r2 = (x * x + y * y) + z * z;
-    const double rinv = 1.0 / sqrt(r2);
-    const double rinv2 = rinv * rinv;
-    const double D1 = -rinv * rinv2;
-    const double D2 = -3.0 * D1 * rinv2;
-    const double D3 = -5.0 * D2 * rinv2;
-    const double D4 = -7.0 * D3 * rinv2;
-    const double D5 = -9.0 * D4 * rinv2;
-    const double X[3] = {x, y, z};
-    const double Qm[3][3] = {{qq[0], qq[1], qq[2]}, {qq[1], qq[3], qq[4]}, {qq[2], qq[4], qq[5]}};
-    double qv[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) qv[i] = Qm[i][0] * x + Qm[i][1] * y + Qm[i][2] * z;
-    const double s = qv[0] * x + qv[1] * y + qv[2] * z;
-    constexpr double sixth = 1.0 / 6.0, third = 1.0 / 3.0;
-    const double a1 = M * D1 + sixth * D3 * s;
-    const double b2 = M * D2 + sixth * D4 * s;
-    const double e3 = M * D3 + sixth * D5 * s;
-    const double c0 = third * D2, c1 = third * D3, c2 = third * D4;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) c[i] += a1 * X[i] + c0 * qv[i];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int l = i; l < 3; ++l) {
-            double v = b2 * X[i] * X[l] + c1 * (qv[i] * X[l] + qv[l] * X[i]) + c0 * Qm[i][l];
-            if (i == l) v += a1;
-            c[3 + jidx(i, l)] += v;
-        }
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int l = i; l < 3; ++l)
-#pragma unroll
-            for (int m = l; m < 3; ++m) {
-                double v = e3 * X[i] * X[l] * X[m];
-                double dd = 0.0;
-                if (i == l) dd += X[m];
-                if (i == m) dd += X[l];
-                if (l == m) dd += X[i];
-                v += b2 * dd;
-                v += c2 * (qv[i] * X[l] * X[m] + qv[l] * X[i] * X[m] + qv[m] * X[i] * X[l]);
-                double w = Qm[l][m] * X[i] + Qm[i][m] * X[l] + Qm[i][l] * X[m];
-                if (l == m) w += qv[i];
-                if (i == m) w += qv[l];
-                if (i == l) w += qv[m];
-                v += c1 * w;
-                c[9 + hidx(i, l, m)] += v;
-            }
-}
+using rcbfar::hidx;
+using rcbfar::jidx;
+using rcbfar::m2l_accumulate;
 
 // F = S(q)/r of the cubic-spline softening; FP64
 __device__ __forceinline__ double soft_F(double r2, double hab) {

@@ -1,14 +1,339 @@
-// k_vjp.hip -- vector-Jacobian product of the accelerations (placeholder
-// until the backward kernels land).
+// k_vjp.hip -- vector-Jacobian product of the accelerations with the tree
+// held fixed (topology, particle-to-leaf map and interaction lists frozen;
+// M, COM and Q of every node are functions of the inputs). For
+// L = sum_a g_a . a_a it returns dL/dx, dL/dy, dL/dz, dL/dm.
+//
+// Near field (Sec. 2.4.3), pair (a, b), v = r_a - r_b:
+//   K = F I + (dF/dr / r) v v^T;  dr_a -= m_b K g_a;  dr_b += m_b K g_a;
+//   dm_b -= F (v . g_a).
+// Pairs are recomputed from the lists, not stored. The source-side terms
+// are summed over the wave's sinks and added with FP64 atomics.
+// Far field (Sec. 2.4.2, Eq. 6): per sink leaf the cotangent moments G0, G1,
+// G2 (far_math.h), then
+//   dr_a += J g_a + H[g_a, d_a]                       (d_a = r_a - com_A)
+//   com_A receives cot = sum_B d(G2:H/2)/dR  ->  dr_a += m_a/M_A cot,
+//                                              dm_a += cot . d_a / M_A
+//   node B receives dM, -dPsi/dR, dQ (FP64 atomics).
+// Push: every node's adjoint reaches its particles b through
+//   M = sum m, COM = sum m r / M, Q = sum m (3 d d^T - |d|^2 I), d = r - COM:
+//   dr_b += aR m_b / M + m_b (6 aQ d - 2 tr(aQ) d)
+//   dm_b += aM + aR . d / M + 3 d.aQ.d - |d|^2 tr(aQ)
+// (dQ/dCOM = 0 because sum m d = 0).
+#include "far_math.h"
 #include "rcb_internal.h"
 
 namespace rcb {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / kWave;
+constexpr int kAdj = 10;   // M, R(3), Q(6)
+
+using rcbfar::hidx;
+using rcbfar::jidx;
+
+template <typename T>
+__device__ __forceinline__ void soft_FdF(T r2, T hab, T &F, T &dFr) {
+    const T rinv = r2 > (T)0 ? (T)1 / sqrt(r2) : (T)0;
+    const T r = r2 * rinv;
+    const T hinv = (T)1 / hab;
+    const T q = r * hinv;
+    const T h2 = hinv * hinv;
+    const T h3 = h2 * hinv;
+    const T h4 = h2 * h2;
+    const T h5 = h4 * hinv;
+    const T r3 = rinv * rinv * rinv;
+    const T r5 = r3 * rinv * rinv;
+    const T Fin = h3 * ((T)(4.0 / 3.0) + q * q * ((T)(-6.0 / 5.0) + (T)0.5 * q));
+    const T dFin = h5 * ((T)(-12.0 / 5.0) + (T)1.5 * q);
+    const T Fmid = h3 * ((T)(8.0 / 3.0) + q * ((T)-3.0 + q * ((T)(6.0 / 5.0) - q * (T)(1.0 / 6.0)))) -
+                   r3 * (T)(1.0 / 15.0);
+    const T dFmid = h5 * ((T)(12.0 / 5.0) - (T)0.5 * q) - (T)3.0 * h4 * rinv + (T)0.2 * r5;
+    const bool in = q < (T)1, mid = q < (T)2;
+    F = in ? Fin : (mid ? Fmid : r3);
+    dFr = in ? dFin : (mid ? dFmid : (T)-3.0 * r5);
+}
+
+struct VjpArgs {
+    int64_t nleaf;
+    const int32_t *nfirst, *ncount;
+    const double *ncom, *nM, *nQ;
+    const int64_t *near_off, *far_off;
+    const int32_t *near_list, *far_list;
+    const double *px, *py, *pz, *pm, *ph;
+    const float *fdx, *fdy, *fdz, *fm, *fh;
+    const int32_t *pid;
+    const void *gx, *gy, *gz;
+    double *sink;   // 4 n, tree order: dx dy dz dm
+    double *src;    // 4 n, tree order, atomics
+    double *adj;    // kAdj per label, atomics
+    int64_t n;
+};
+
+template <bool MIXED>
+__device__ __forceinline__ double load_g(const void *p, int32_t i) {
+    if constexpr (MIXED) return (double)((const float *)p)[i];
+    else return ((const double *)p)[i];
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_vjp_leaf(VjpArgs a) {
+    const int64_t li = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (li >= a.nleaf) return;
+    const int lane = lane_id();
+    const int64_t A = a.nleaf + li;
+    const int32_t sA = a.nfirst[A], nA = a.ncount[A];
+    if (nA == 0) return;
+    const double cA[3] = {a.ncom[3 * A], a.ncom[3 * A + 1], a.ncom[3 * A + 2]};
+    const double MA = a.nM[A];
+
+    // cotangent moments of the sink leaf
+    rcbfar::SinkMoments G;
+    {
+        double m[30];
+#pragma unroll
+        for (int q = 0; q < 30; ++q) m[q] = 0.0;
+        for (int i = lane; i < nA; i += kWave) {
+            const int64_t p = (int64_t)sA + i;
+            const int32_t o = a.pid[p];
+            const double g[3] = {load_g<MIXED>(a.gx, o), load_g<MIXED>(a.gy, o), load_g<MIXED>(a.gz, o)};
+            const double d[3] = {a.px[p] - cA[0], a.py[p] - cA[1], a.pz[p] - cA[2]};
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                m[u] += g[u];
+#pragma unroll
+                for (int l = 0; l < 3; ++l) m[3 + 3 * u + l] += g[u] * d[l];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    const int l = k < 3 ? 0 : (k < 5 ? 1 : 2);
+                    const int mm = k < 3 ? k : (k < 5 ? k - 2 : 2);
+                    m[12 + 6 * u + k] += g[u] * d[l] * d[mm];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 30; ++q) m[q] = wave_sum(m[q]);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) G.G0[q] = m[q];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) G.G1[q] = m[3 + q];
+#pragma unroll
+        for (int q = 0; q < 18; ++q) G.G2[q] = m[12 + q];
+        rcbfar::sink_traces(G);
+    }
+
+    // far field: forward coefficients, the sink-centre term, node adjoints
+    double c[19];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) c[q] = 0.0;
+    double cot[3] = {0.0, 0.0, 0.0};
+    const int64_t f0 = a.far_off[li], f1 = a.far_off[li + 1];
+    for (int64_t e = f0 + lane; e < f1; e += kWave) {
+        const int64_t B = a.far_list[e];
+        double qq[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) qq[q] = a.nQ[6 * B + q];
+        const double R[3] = {cA[0] - a.ncom[3 * B], cA[1] - a.ncom[3 * B + 1], cA[2] - a.ncom[3 * B + 2]};
+        const double MB = a.nM[B];
+        rcbfar::m2l_accumulate(R[0], R[1], R[2], MB, qq, c);
+        double rho[3], ct[3], aM, aQ[6];
+        rcbfar::far_pair_adjoint(R[0], R[1], R[2], MB, qq, G, rho, ct, aM, aQ);
+        double *ad = a.adj + kAdj * B;
+        atomicAdd(ad + 0, aM);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            atomicAdd(ad + 1 + u, -rho[u]);
+            cot[u] += ct[u];
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) atomicAdd(ad + 4 + k, aQ[k]);
+    }
+#pragma unroll
+    for (int q = 0; q < 19; ++q) c[q] = wave_sum(c[q]);
+#pragma unroll
+    for (int u = 0; u < 3; ++u) cot[u] = wave_sum(cot[u]);
+
+    // near field
+    int S = 1;
+    while (S < nA && S < kWave) S <<= 1;
+    const int J = kWave / S;
+    const int sslot = lane / J;
+    const int slice = lane % J;
+    const int64_t l0 = a.near_off[li], l1 = a.near_off[li + 1];
+    for (int g0 = 0; g0 < nA; g0 += kWave) {
+        const int si = g0 + sslot;
+        const bool has_sink = si < nA;
+        const int64_t pa = (int64_t)sA + (has_sink ? si : 0);
+        const int32_t oa = a.pid[pa];
+        double ga[3] = {0.0, 0.0, 0.0};
+        if (has_sink) {
+            ga[0] = load_g<MIXED>(a.gx, oa);
+            ga[1] = load_g<MIXED>(a.gy, oa);
+            ga[2] = load_g<MIXED>(a.gz, oa);
+        }
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t e = l0; e < l1; ++e) {
+            const int64_t B = (uint32_t)a.near_list[e] & 0x7fffffffu;
+            const int32_t fB = a.nfirst[B], cB = a.ncount[B];
+            float off[3] = {0.f, 0.f, 0.f};
+            if constexpr (MIXED) {
+                off[0] = (float)(cA[0] - a.ncom[3 * B]);
+                off[1] = (float)(cA[1] - a.ncom[3 * B + 1]);
+                off[2] = (float)(cA[2] - a.ncom[3 * B + 2]);
+            }
+            for (int32_t t0 = 0; t0 < cB; t0 += J) {
+                const int32_t ob = t0 + slice;
+                const bool valid = ob < cB;
+                const int64_t pb = (int64_t)fB + (valid ? ob : 0);
+                double s[4];   // source-side contributions of this pair
+                if constexpr (!MIXED) {
+                    const double v[3] = {a.px[pa] - a.px[pb], a.py[pa] - a.py[pb], a.pz[pa] - a.pz[pb]};
+                    const double r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+                    double F, dFr;
+                    soft_FdF<double>(r2, 0.5 * (a.ph[pa] + a.ph[pb]), F, dFr);
+                    const double vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
+                    const double mb = valid ? a.pm[pb] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        const double Kg = mb * (F * ga[u] + dFr * v[u] * vg);
+                        acc[u] -= Kg;
+                        s[u] = Kg;
+                    }
+                    s[3] = valid ? -F * vg : 0.0;
+                } else {
+                    const float v[3] = {(a.fdx[pa] + off[0]) - a.fdx[pb], (a.fdy[pa] + off[1]) - a.fdy[pb],
+                                        (a.fdz[pa] + off[2]) - a.fdz[pb]};
+                    const float r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+                    float F, dFr;
+                    soft_FdF<float>(r2, 0.5f * (a.fh[pa] + a.fh[pb]), F, dFr);
+                    const float gf[3] = {(float)ga[0], (float)ga[1], (float)ga[2]};
+                    const float vg = v[0] * gf[0] + v[1] * gf[1] + v[2] * gf[2];
+                    const float mb = valid ? a.fm[pb] : 0.0f;
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        const float Kg = mb * (F * gf[u] + dFr * v[u] * vg);
+                        acc[u] -= (double)Kg;
+                        s[u] = (double)Kg;
+                    }
+                    s[3] = valid ? (double)(-F * vg) : 0.0;
+                }
+                // sum the contributions of the wave's sinks to source pb
+                for (int o = J; o < kWave; o <<= 1) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) s[u] += __shfl_xor(s[u], o, kWave);
+                }
+                if (sslot == 0 && valid) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) atomicAdd(a.src + u * a.n + pb, s[u]);
+                }
+            }
+        }
+        for (int o = 1; o < J; o <<= 1) {
+#pragma unroll
+            for (int u = 0; u < 3; ++u) acc[u] += __shfl_xor(acc[u], o, kWave);
+        }
+        if (has_sink && slice == 0) {
+            const double d[3] = {a.px[pa] - cA[0], a.py[pa] - cA[1], a.pz[pa] - cA[2]};
+            const double ma = a.pm[pa];
+            double out[3];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                double v = acc[l] + ma / MA * cot[l];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    v += ga[i] * c[3 + jidx(i, l)];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) v += ga[i] * c[9 + hidx(i, l, m)] * d[m];
+                }
+                out[l] = v;
+            }
+            a.sink[pa] = out[0];
+            a.sink[a.n + pa] = out[1];
+            a.sink[2 * a.n + pa] = out[2];
+            a.sink[3 * a.n + pa] = (cot[0] * d[0] + cot[1] * d[1] + cot[2] * d[2]) / MA;
+        }
+    }
+}
+
+// node adjoints -> particles along each particle's ancestor chain; then the
+// three parts are summed and written in caller order.
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_vjp_push(VjpArgs a, int k, void *dx, void *dy, void *dz,
+                                                     void *dm) {
+    const int64_t li = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (li >= a.nleaf) return;
+    const int64_t A = a.nleaf + li;
+    const int32_t sA = a.nfirst[A], nA = a.ncount[A];
+    for (int i = lane_id(); i < nA; i += kWave) {
+        const int64_t p = (int64_t)sA + i;
+        const double r[3] = {a.px[p], a.py[p], a.pz[p]};
+        const double mb = a.pm[p];
+        double dr[3] = {a.sink[p] + a.src[p], a.sink[a.n + p] + a.src[a.n + p],
+                        a.sink[2 * a.n + p] + a.src[2 * a.n + p]};
+        double dmb = a.sink[3 * a.n + p] + a.src[3 * a.n + p];
+        for (int64_t B = A; B >= 1; B >>= 1) {
+            const double *ad = a.adj + kAdj * B;
+            const double aM = ad[0];
+            const double aR[3] = {ad[1], ad[2], ad[3]};
+            const double Q[3][3] = {{ad[4], ad[5], ad[6]}, {ad[5], ad[7], ad[8]}, {ad[6], ad[8], ad[9]}};
+            const double MB = a.nM[B];
+            const double d[3] = {r[0] - a.ncom[3 * B], r[1] - a.ncom[3 * B + 1], r[2] - a.ncom[3 * B + 2]};
+            const double trQ = Q[0][0] + Q[1][1] + Q[2][2];
+            const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+            double Qd[3];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) Qd[l] = Q[l][0] * d[0] + Q[l][1] * d[1] + Q[l][2] * d[2];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) dr[l] += aR[l] * mb / MB + mb * (6.0 * Qd[l] - 2.0 * trQ * d[l]);
+            dmb += aM + (aR[0] * d[0] + aR[1] * d[1] + aR[2] * d[2]) / MB +
+                   3.0 * (d[0] * Qd[0] + d[1] * Qd[1] + d[2] * Qd[2]) - d2 * trQ;
+        }
+        const int32_t o = a.pid[p];
+        if constexpr (MIXED) {
+            ((float *)dx)[o] = (float)dr[0];
+            ((float *)dy)[o] = (float)dr[1];
+            ((float *)dz)[o] = (float)dr[2];
+            ((float *)dm)[o] = (float)dmb;
+        } else {
+            ((double *)dx)[o] = dr[0];
+            ((double *)dy)[o] = dr[1];
+            ((double *)dz)[o] = dr[2];
+            ((double *)dm)[o] = dmb;
+        }
+    }
+    (void)k;
+}
+
+}  // namespace
 
 rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *gz, void *dx,
                        void *dy, void *dz, void *dm, hipStream_t s) {
-    (void)t; (void)gx; (void)gy; (void)gz; (void)dx; (void)dy; (void)dz; (void)dm; (void)s;
-    set_error("rcb_gravity_vjp: not implemented");
-    return RCB_ESTATE;
+    rcb_status st = ensure_walk(t, s);
+    if (st != RCB_OK) return st;
+    std::vector<void *> tmp;
+    const int64_t n = t->n;
+    double *sink = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
+    double *src = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
+    double *adj = (double *)dalloc(t, sizeof(double) * kAdj * t->nlab, s, tmp);
+    if (!sink || !src || !adj) return RCB_ENOMEM;
+    RCB_HIP(hipMemsetAsync(src, 0, sizeof(double) * 4 * n, s));
+    RCB_HIP(hipMemsetAsync(adj, 0, sizeof(double) * kAdj * t->nlab, s));
+    VjpArgs a{t->nleaf, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ, t->near_off, t->far_off,
+              t->near_list, t->far_list, t->px, t->py, t->pz, t->pm, t->ph, t->fdx, t->fdy, t->fdz,
+              t->fm, t->fh, t->pid, gx, gy, gz, sink, src, adj, n};
+    const unsigned grid = (unsigned)((t->nleaf + kWaves - 1) / kWaves);
+    if (t->p.precision == RCB_MIXED) {
+        k_vjp_leaf<true><<<grid, kBlock, 0, s>>>(a);
+        RCB_LAUNCH_CHECK("k_vjp_leaf");
+        k_vjp_push<true><<<grid, kBlock, 0, s>>>(a, t->k, dx, dy, dz, dm);
+    } else {
+        k_vjp_leaf<false><<<grid, kBlock, 0, s>>>(a);
+        RCB_LAUNCH_CHECK("k_vjp_leaf");
+        k_vjp_push<false><<<grid, kBlock, 0, s>>>(a, t->k, dx, dy, dz, dm);
+    }
+    RCB_LAUNCH_CHECK("k_vjp_push");
+    for (void *p : tmp) RCB_HIP(hipFreeAsync(p, s));
+    return RCB_OK;
 }
 
 }  // namespace rcb

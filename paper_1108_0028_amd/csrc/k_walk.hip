@@ -130,16 +130,18 @@ __global__ __launch_bounds__(kBlock) void k_walk(const double4 *__restrict__ rec
         if (lane == 0) {
             near_cnt[li] = nn;
             far_cnt[li] = nf;
+            if (nn > kStackCap) atomicAdd(&flag[1], 1);
         }
         return;
     }
 }
 
 // Sort each leaf's near list by label (bitonic network in LDS, one wave per
-// leaf); lists longer than the LDS tile raise flag bit 2.
+// leaf). Lists longer than the LDS tile are queued for k_sort_long.
 __global__ __launch_bounds__(kBlock) void k_sort_near(int64_t nleaf, const int64_t *__restrict__ near_off,
                                                       int32_t *__restrict__ near_list,
-                                                      int32_t *__restrict__ flag) {
+                                                      int32_t *__restrict__ flag,
+                                                      int32_t *__restrict__ long_q) {
     __shared__ int32_t buf_all[kWaves][kStackCap];
     int32_t *buf = buf_all[threadIdx.x / kWave];
     const int64_t li = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_near(int64_t nleaf, const int64
     const int64_t nn = near_off[li + 1] - nbase;
     if (nn <= 1) return;
     if (nn > kStackCap) {
-        if (lane == 0) atomicOr(flag, 2);
+        if (lane == 0) long_q[atomicAdd(&flag[2], 1)] = (int32_t)li;
         return;
     }
     int P = 1;
@@ -176,6 +178,37 @@ __global__ __launch_bounds__(kBlock) void k_sort_near(int64_t nleaf, const int64
     for (int i = lane; i < nn; i += kWave) near_list[nbase + i] = buf[i];
 }
 
+// Sort of the queued long near lists, one block each, in global memory:
+// bitonic network in its all-ascending form (the first merge step of each
+// stage compares i with i ^ (size - 1)), so the virtual +inf padding past the
+// list end never moves and pairs reaching past the end are simply skipped.
+__global__ __launch_bounds__(1024) void k_sort_long(const int32_t *__restrict__ long_q,
+                                                    const int64_t *__restrict__ near_off,
+                                                    int32_t *__restrict__ near_list) {
+    const int64_t li = long_q[blockIdx.x];
+    int32_t *v = near_list + near_off[li];
+    const int64_t nn = near_off[li + 1] - near_off[li];
+    int64_t P = 1;
+    while (P < nn) P <<= 1;
+    for (int64_t size = 2; size <= P; size <<= 1) {
+        for (int64_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int64_t q = threadIdx.x; q < (P >> 1); q += blockDim.x) {
+                const int64_t i = 2 * stride * (q / stride) + (q % stride);
+                const int64_t j = stride == (size >> 1) ? (i ^ (size - 1)) : i + stride;
+                if (j < nn) {
+                    const int32_t a = v[i], c = v[j];
+                    if (((uint32_t)a & kLabelMask) > ((uint32_t)c & kLabelMask)) {
+                        v[i] = c;
+                        v[j] = a;
+                    }
+                }
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
+    }
+}
+
 }  // namespace
 
 rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
@@ -189,7 +222,7 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     if (!ncnt || !fcnt || !t->near_off || !t->far_off) return RCB_ENOMEM;
     const double theta2 = t->p.theta * t->p.theta;
     const unsigned grid = (unsigned)((L + kWaves - 1) / kWaves);
-    RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t), s));
+    RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 4, s));
     k_walk<false><<<grid, kBlock, 0, s>>>(t->wrec, t->nhnode, t->k, L, theta2, ncnt, fcnt, nullptr,
                                           nullptr, nullptr, nullptr, t->dflag);
     RCB_LAUNCH_CHECK("k_walk<count>");
@@ -198,12 +231,13 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     st = scan_i64(t, fcnt, t->far_off, L, s);
     if (st != RCB_OK) return st;
     int64_t tot[2] = {0, 0};
-    int32_t flag = 0;
+    int32_t flags[4] = {0, 0, 0, 0};
     RCB_HIP(hipMemcpyAsync(&tot[0], t->near_off + L, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RCB_HIP(hipMemcpyAsync(&tot[1], t->far_off + L, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RCB_HIP(hipMemcpyAsync(&flag, t->dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
     RCB_HIP(hipStreamSynchronize(s));
-    if (flag) {
+    const int32_t nlong = flags[1];
+    if (flags[0]) {
         set_error("walk: LIFO stack overflow (tree deeper than the stack supports)");
         return RCB_ECAPACITY;
     }
@@ -213,13 +247,16 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     k_walk<true><<<grid, kBlock, 0, s>>>(t->wrec, t->nhnode, t->k, L, theta2, nullptr, nullptr,
                                          t->near_off, t->far_off, t->near_list, t->far_list, t->dflag);
     RCB_LAUNCH_CHECK("k_walk<fill>");
-    k_sort_near<<<grid, kBlock, 0, s>>>(L, t->near_off, t->near_list, t->dflag);
+    int32_t *long_q = nullptr;
+    if (nlong > 0) {
+        long_q = (int32_t *)dalloc(t, sizeof(int32_t) * nlong, s, tmp);
+        if (!long_q) return RCB_ENOMEM;
+    }
+    k_sort_near<<<grid, kBlock, 0, s>>>(L, t->near_off, t->near_list, t->dflag, long_q);
     RCB_LAUNCH_CHECK("k_sort_near");
-    RCB_HIP(hipMemcpyAsync(&flag, t->dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    RCB_HIP(hipStreamSynchronize(s));
-    if (flag) {
-        set_error("walk: a near list longer than 2048 cells (a smoothing length reaches too far)");
-        return RCB_ECAPACITY;
+    if (nlong > 0) {
+        k_sort_long<<<nlong, 1024, 0, s>>>(long_q, t->near_off, t->near_list);
+        RCB_LAUNCH_CHECK("k_sort_long");
     }
     for (void *p : tmp) RCB_HIP(hipFreeAsync(p, s));
     t->near_total = tot[0];
