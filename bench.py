@@ -1,0 +1,213 @@
+"""Benchmark: particles/s for build + neighbours + gravity of the RCB tree on
+one MI355X, 4,194,304-particle Plummer sphere in a 10% uniform background
+(density contrast ~1e4), N_ll = 12, theta = 0.7, mixed form (FP32
+leaf-relative interactions, FP64 moments and Taylor shift), next to the FP64
+form and the FP64 CPU oracle.
+
+One step = rcb_build + rcb_neighbours_count + rcb_neighbours_fill +
+rcb_gravity on inputs already resident in HBM, tree destroyed at the end.
+
+Prints ONE JSON line (rank 0). Extra fields: the FP64-form throughput, the
+mixed form's error against the FP64 form, per-phase times, the roofline of
+the dominant kernel (timed with HIP events on its stream inside the timed
+region) and the oracle's CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks and the derived vector peak available to this build
+# (packed FP32 is disabled, so FP32 issues at the FP64 rate):
+# 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s.
+PEAK_HBM_GBS = 8000.0
+PEAK_VALU_TFLOPS = 78.6
+
+# Operation counts of one interaction, counted on the implemented formulas
+# (k_grav.hip, far_math.h): an FMA counts as 2, a reciprocal / rsqrt as 1.
+FLOP_P2P = 38          # near pair: offset, r^2, rsqrt, rcp, q, both spline branches, m F v
+FLOP_M2L = 226         # far pair: D1..D5, Q x, x.Q.x, 3 f + 6 J + 10 H coefficients
+FLOP_L2P = 66          # per sink: f + J d + H[d, d]/2
+# HBM bytes that one launch of k_gravity<mixed> must move at least once:
+# particles (FP32 d, m, h + int32 id), FP32 outputs, interaction lists and
+# node records (first, count, com, M, Q).
+BYTES_PER_PARTICLE = 20 + 4 + 12
+BYTES_PER_NEAR_ENTRY = 4
+BYTES_PER_FAR_ENTRY = 4
+BYTES_PER_NODE = 8 + 24 + 8 + 48
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--theta", type=float, default=0.7)
+    ap.add_argument("--n-ll", type=int, default=12)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-leaves", type=int, default=2048)
+    return ap.parse_args()
+
+
+def main():
+    a = _args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1108_0028_amd import Tree
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    cloud = W.plummer_background()
+    n = cloud.n
+    arrs = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in cloud.arrays()]
+    torch.cuda.synchronize()
+
+    def step(prec, ev=None):
+        t = Tree(*arrs, n_ll=a.n_ll, theta=a.theta, precision=prec)
+        off, ids = t.neighbours()
+        if ev is not None:
+            ev[0].record()
+        acc = t.gravity()
+        if ev is not None:
+            ev[1].record()
+        t.destroy()
+        return acc, off
+
+    def timed(prec, steps, warmup):
+        for _ in range(warmup):
+            step(prec)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(prec, evs[i])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kern_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
+        return (t1 - t0) / steps, kern_ms
+
+    sec, grav_ms = timed(a.precision, a.steps, a.warmup)
+    value = n / sec
+
+    # per-phase split (one extra, untimed step)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    t = Tree(*arrs, n_ll=a.n_ll, theta=a.theta, precision=a.precision)
+    torch.cuda.synchronize()
+    p1 = time.perf_counter()
+    off, ids = t.neighbours()
+    torch.cuda.synchronize()
+    p2 = time.perf_counter()
+    acc = t.gravity()
+    torch.cuda.synchronize()
+    p3 = time.perf_counter()
+    # work counts of this tree for the roofline (outside the timed region)
+    inf = t.info()
+    cnt = t.export("count").to(torch.int64)
+    near = t.export("near").to(torch.int64) & 0x7FFFFFFF
+    noff = t.export("near_off")
+    nleaf = 1 << inf["k"]
+    per_entry_particles = cnt[near]
+    leaf_of_entry = torch.repeat_interleave(torch.arange(nleaf, device=dev), noff[1:] - noff[:-1])
+    sinks = cnt[nleaf + leaf_of_entry]
+    pairs = int((per_entry_particles * sinks).sum())
+    t.destroy()
+    far_total = inf["far_total"]
+    near_total = inf["near_total"]
+
+    flops = FLOP_P2P * pairs + FLOP_M2L * far_total + FLOP_L2P * n
+    achieved_tf = flops / (grav_ms * 1e-3) / 1e12
+    alg_bytes = (BYTES_PER_PARTICLE * n + BYTES_PER_NEAR_ENTRY * near_total +
+                 BYTES_PER_FAR_ENTRY * far_total + BYTES_PER_NODE * 2 * nleaf)
+    achieved_gbs = alg_bytes / (grav_ms * 1e-3) / 1e9
+    roofline = {"kernel": f"k_gravity<{a.precision}>", "bound": "alu", "achieved": achieved_tf,
+                "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tf / PEAK_VALU_TFLOPS,
+                "traffic": None, "kernel_ms": grav_ms, "pairs": pairs, "far_pairs": far_total,
+                "hbm_floor_gbs": achieved_gbs}
+
+    # the other form and the mixed-vs-FP64 error
+    other = "fp64" if a.precision == "mixed" else "mixed"
+    sec_o, _ = timed(other, max(2, a.steps // 3), 1)
+    acc_m, _ = step("mixed")
+    acc_d, _ = step("fp64")
+    am = torch.stack([v.double() for v in acc_m], 1)
+    ad = torch.stack([v.double() for v in acc_d], 1)
+    da = (am - ad).norm(dim=1)
+    na = ad.norm(dim=1)
+    rms = float(na.pow(2).mean().sqrt())
+    rel = da / na.clamp_min(1e-300)
+    err = {"gate_max": float((da / na.clamp_min(1e-3 * rms)).max()),
+           "mean": float(rel.mean()), "p99": float(torch.quantile(rel.float(), 0.99))}
+
+    out = {
+        "metric": "particles/sec (build+neighbours+gravity), 4M Plummer: mixed FP32 vs FP64 at stated err",
+        "value": value,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64 (mixed)" if a.precision == "mixed" else "f64",
+        "data": "synthetic (seeded Plummer + uniform background)",
+        "config": {"workload": "plummer_background N=4194304: 90% Plummer (b=1, r<=20) + 10% uniform "
+                               "sphere R=10.357, equal masses, analytic h for ~50 neighbours",
+                   "n": n, "n_ll": a.n_ll, "theta": a.theta, "precision": a.precision},
+        "phases_ms": {"build": (p1 - p0) * 1e3, "neighbours": (p2 - p1) * 1e3, "gravity": (p3 - p2) * 1e3},
+        "other_form": {"precision": other, "value": n / sec_o, "ms_per_step": sec_o * 1e3},
+        "mixed_vs_fp64_error": err,
+        "neighbours_total": int(off[-1]),
+        "roofline": roofline,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cloud, a)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(cloud, a):
+    """The FP64 oracle (unchanged) on the host: full tree build, then walk,
+    neighbours and gravity for a random sample of leaves; throughput scaled to
+    particles/s of build + neighbours + gravity."""
+    import numpy as np
+
+    from oracle import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    ot = O.OracleTree(*cloud.arrays(), n_ll=a.n_ll)
+    t1 = time.perf_counter()
+    rng = np.random.default_rng(0)
+    leaves = np.sort(rng.choice(ot.n_leaves, min(a.cpu_leaves, ot.n_leaves), replace=False)) + ot.n_leaves
+    ot.walk(a.theta, leaves)
+    t2 = time.perf_counter()
+    off, ids, valid = ot.neighbours()
+    t3 = time.perf_counter()
+    ot.gravity()
+    t4 = time.perf_counter()
+    n_s = int(valid.sum())
+    per_particle = (t1 - t0) / cloud.n + (t4 - t1) / max(1, n_s)
+    return {"value": 1.0 / per_particle, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle build of all {cloud.n} particles (serial, {t1 - t0:.1f} s) + walk, "
+                      f"neighbours and gravity of {len(leaves)} random leaves ({n_s} particles, "
+                      f"{t4 - t1:.1f} s, OpenMP {threads} threads)"}
+
+
+if __name__ == "__main__":
+    main()
