@@ -3,20 +3,20 @@
 // quadrupole cell-cell interaction, Taylor-expanded about the sink leaf's
 // centre of mass).
 //
-// One wave per sink leaf A:
-//  far:  lanes run over far(A); each evaluates the field of node B at
-//        R = com_A - com_B in FP64 -- f_i, J_il, H_ilm of the potential
-//        Phi = -M/r - Q_jk x_j x_k / (2 r^5) (Eq. 5) -- and the 19 unique
-//        coefficients are summed over the wave.
-//  near: lanes are (sink slot, slice) as in the neighbour search; slice j of
-//        sink a runs over particles first_B + t J + j of every near cell B:
+// One wave per group of up to 8 sibling leaves (k_walk.hip):
+//  far:  lanes are (far entry e = lane/8, leaf slot i = lane%8); the lane
+//        evaluates node B of entry e at R = com_A(i) - com_B in FP64 if leaf i
+//        accepted B (mask bit), accumulating f_i, J_il, H_ilm of Eq. 5's field
+//        (far_math.h). B's record is loaded once for the 8 leaves. Lanes of
+//        the same leaf are summed at the end; coefficients go to LDS.
+//  near: lanes are (sink slot, slice) over the group's particles (contiguous
+//        in tree order); slice j of sink a runs over particles
+//        first_B + t J + j of every near entry B whose mask has a's leaf:
 //        a_a -= m_b F(r, h_ab) (r_a - r_b), F = S(q)/r (Sec. 2.4.3).
 //  L2P:  a_a += f + J d + H[d, d] / 2,  d = r_a - com_A  (Eq. 6).
 // FP64 form: everything in FP64. Mixed form: particles as FP32 offsets from
 // their leaf's centre of mass; per (A, B) the FP64 offset com_A - com_B is
 // rounded to FP32 once; P2P, accumulation and L2P in FP32; M2L in FP64.
-//
-// The far-field closed forms are in far_math.h.
 #include "far_math.h"
 #include "rcb_internal.h"
 
@@ -30,7 +30,7 @@ using rcbfar::hidx;
 using rcbfar::jidx;
 using rcbfar::m2l_accumulate;
 
-// F = S(q)/r of the cubic-spline softening; FP64
+// F = S(q)/r of the cubic-spline softening
 __device__ __forceinline__ double soft_F(double r2, double hab) {
     const double rinv = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
     const double r = r2 * rinv;
@@ -59,59 +59,101 @@ __device__ __forceinline__ float soft_Ff(float r2, float hab) {
 
 struct GravArgs {
     int64_t nleaf;
+    int gk;
+    int64_t ngroup;
     const int32_t *nfirst, *ncount;
     const double *ncom, *nM, *nQ;
-    const int64_t *near_off, *far_off;
-    const int32_t *near_list, *far_list;
+    const int64_t *gnear_off, *gfar_off;
+    const uint64_t *gnear, *gfar;
     const double *px, *py, *pz, *pm, *ph;
     const float *fdx, *fdy, *fdz, *fm, *fh;
     const int32_t *pid;
     void *ax, *ay, *az;
 };
 
-template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
-    const int64_t li = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
-    if (li >= g.nleaf) return;
+// Far-field coefficients of the group's leaves into coef[8][19] (LDS).
+__device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, double (*coef)[19]) {
     const int lane = lane_id();
-    const int64_t A = g.nleaf + li;
-    const int32_t sA = g.nfirst[A], nA = g.ncount[A];
-    if (nA == 0) return;
-    const double cAx = g.ncom[3 * A], cAy = g.ncom[3 * A + 1], cAz = g.ncom[3 * A + 2];
-
-    // far field: 19 FP64 coefficients at com_A
+    const int slot = lane >> 3, li = lane & 7;
+    const int G = 1 << g.gk;
+    const int64_t A = g.nleaf + gi * G + (li < G ? li : 0);
+    const double cA[3] = {g.ncom[3 * A], g.ncom[3 * A + 1], g.ncom[3 * A + 2]};
     double c[19];
 #pragma unroll
     for (int q = 0; q < 19; ++q) c[q] = 0.0;
-    const int64_t f0 = g.far_off[li], f1 = g.far_off[li + 1];
-    for (int64_t e = f0 + lane; e < f1; e += kWave) {
-        const int64_t B = g.far_list[e];
-        double qq[6];
+    const int64_t f0 = g.gfar_off[gi], f1 = g.gfar_off[gi + 1];
+    for (int64_t e0 = f0; e0 < f1; e0 += 8) {
+        const int64_t e = e0 + slot;
+        if (e < f1) {
+            const uint64_t ent = g.gfar[e];
+            if ((ent >> (32 + li)) & 1ull) {
+                const int64_t B = (uint32_t)ent & 0x7fffffffu;
+                double qq[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) qq[q] = g.nQ[6 * B + q];
-        m2l_accumulate(cAx - g.ncom[3 * B], cAy - g.ncom[3 * B + 1], cAz - g.ncom[3 * B + 2], g.nM[B],
-                       qq, c);
+                for (int q = 0; q < 6; ++q) qq[q] = g.nQ[6 * B + q];
+                m2l_accumulate(cA[0] - g.ncom[3 * B], cA[1] - g.ncom[3 * B + 1],
+                               cA[2] - g.ncom[3 * B + 2], g.nM[B], qq, c);
+            }
+        }
     }
 #pragma unroll
-    for (int q = 0; q < 19; ++q) c[q] = wave_sum(c[q]);
+    for (int q = 0; q < 19; ++q) {
+        double v = c[q];
+        v += __shfl_xor(v, 8, kWave);
+        v += __shfl_xor(v, 16, kWave);
+        v += __shfl_xor(v, 32, kWave);
+        c[q] = v;
+    }
+    if (slot == 0) {
+#pragma unroll
+        for (int q = 0; q < 19; ++q) coef[li][q] = c[q];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
 
-    // near field
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
+    __shared__ double coef_all[kWaves][8][19];
+    double(*coef)[19] = coef_all[threadIdx.x / kWave];
+    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (gi >= g.ngroup) return;
+    const int lane = lane_id();
+    const int G = 1 << g.gk;
+    const int64_t GL = (g.nleaf >> g.gk) + gi;   // group node label
+    const int32_t sG = g.nfirst[GL], nG = g.ncount[GL];
+    if (nG == 0) return;
+    group_far(g, gi, coef);
+
+    // leaf boundaries of the group (leaf ranges are contiguous and ordered)
+    int32_t lf[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lf[i] = i < G ? g.nfirst[g.nleaf + gi * G + i] : 0x7fffffff;
     int S = 1;
-    while (S < nA && S < kWave) S <<= 1;
+    while (S < nG && S < kWave) S <<= 1;
     const int J = kWave / S;
     const int sslot = lane / J;
     const int slice = lane % J;
-    const int64_t l0 = g.near_off[li], l1 = g.near_off[li + 1];
-    for (int g0 = 0; g0 < nA; g0 += kWave) {
+    const int64_t n0 = g.gnear_off[gi], n1 = g.gnear_off[gi + 1];
+    for (int g0 = 0; g0 < nG; g0 += S) {
         const int si = g0 + sslot;
-        const bool has_sink = si < nA;
-        const int64_t pa = (int64_t)sA + (has_sink ? si : 0);
+        const bool has_sink = si < nG;
+        const int32_t pa = sG + (has_sink ? si : 0);
+        int la = 0;
+#pragma unroll
+        for (int i = 1; i < 8; ++i)
+            if (lf[i] <= pa) la = i;
+        const uint32_t bit = has_sink ? (1u << la) : 0u;
+        const int64_t A = g.nleaf + gi * G + la;
+        const double cAx = g.ncom[3 * A], cAy = g.ncom[3 * A + 1], cAz = g.ncom[3 * A + 2];
         if constexpr (!MIXED) {
             const double xa = g.px[pa], ya = g.py[pa], za = g.pz[pa], ha = g.ph[pa];
             double ax = 0.0, ay = 0.0, az = 0.0;
-            for (int64_t e = l0; e < l1; ++e) {
-                const int64_t B = (uint32_t)g.near_list[e] & 0x7fffffffu;
+            for (int64_t e = n0; e < n1; ++e) {
+                const uint64_t ent = g.gnear[e];
+                const int64_t B = (uint32_t)ent & 0x7fffffffu;
                 const int32_t fB = g.nfirst[B], cB = g.ncount[B];
+                if (!(((uint32_t)(ent >> 32)) & bit)) continue;
                 for (int32_t t0 = slice; t0 < cB; t0 += J) {
                     const int64_t pb = (int64_t)fB + t0;
                     const double vx = xa - g.px[pb], vy = ya - g.py[pb], vz = za - g.pz[pb];
@@ -129,34 +171,27 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
             }
             if (has_sink && slice == 0) {
                 const double d[3] = {xa - cAx, ya - cAy, za - cAz};
-                double out[3] = {ax, ay, az};
+                double c[19];
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    double t1 = c[i];
-                    double t2 = 0.0;
-#pragma unroll
-                    for (int l = 0; l < 3; ++l) {
-                        t1 += c[3 + jidx(i, l)] * d[l];
-#pragma unroll
-                        for (int m = 0; m < 3; ++m) t2 += c[9 + hidx(i, l, m)] * d[l] * d[m];
-                    }
-                    out[i] += t1 + 0.5 * t2;
-                }
+                for (int q = 0; q < 19; ++q) c[q] = coef[la][q];
+                double out[3];
+                rcbfar::l2p<double>(c, d, out);
                 const int32_t o = g.pid[pa];
-                ((double *)g.ax)[o] = out[0];
-                ((double *)g.ay)[o] = out[1];
-                ((double *)g.az)[o] = out[2];
+                ((double *)g.ax)[o] = ax + out[0];
+                ((double *)g.ay)[o] = ay + out[1];
+                ((double *)g.az)[o] = az + out[2];
             }
         } else {
             const float xa = g.fdx[pa], ya = g.fdy[pa], za = g.fdz[pa], ha = g.fh[pa];
             float ax = 0.0f, ay = 0.0f, az = 0.0f;
-            for (int64_t e = l0; e < l1; ++e) {
-                const int64_t B = (uint32_t)g.near_list[e] & 0x7fffffffu;
+            for (int64_t e = n0; e < n1; ++e) {
+                const uint64_t ent = g.gnear[e];
+                const int64_t B = (uint32_t)ent & 0x7fffffffu;
                 const int32_t fB = g.nfirst[B], cB = g.ncount[B];
-                const float ox = (float)(cAx - g.ncom[3 * B]);
-                const float oy = (float)(cAy - g.ncom[3 * B + 1]);
-                const float oz = (float)(cAz - g.ncom[3 * B + 2]);
-                const float bx = xa + ox, by = ya + oy, bz = za + oz;
+                if (!(((uint32_t)(ent >> 32)) & bit)) continue;
+                const float bx = xa + (float)(cAx - g.ncom[3 * B]);
+                const float by = ya + (float)(cAy - g.ncom[3 * B + 1]);
+                const float bz = za + (float)(cAz - g.ncom[3 * B + 2]);
                 for (int32_t t0 = slice; t0 < cB; t0 += J) {
                     const int64_t pb = (int64_t)fB + t0;
                     const float vx = bx - g.fdx[pb], vy = by - g.fdy[pb], vz = bz - g.fdz[pb];
@@ -174,23 +209,15 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
             }
             if (has_sink && slice == 0) {
                 const float d[3] = {xa, ya, za};
-                float out[3] = {ax, ay, az};
+                double c[19];
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    float t1 = (float)c[i];
-                    float t2 = 0.0f;
-#pragma unroll
-                    for (int l = 0; l < 3; ++l) {
-                        t1 += (float)c[3 + jidx(i, l)] * d[l];
-#pragma unroll
-                        for (int m = 0; m < 3; ++m) t2 += (float)c[9 + hidx(i, l, m)] * d[l] * d[m];
-                    }
-                    out[i] += t1 + 0.5f * t2;
-                }
+                for (int q = 0; q < 19; ++q) c[q] = coef[la][q];
+                float out[3];
+                rcbfar::l2p<float>(c, d, out);
                 const int32_t o = g.pid[pa];
-                ((float *)g.ax)[o] = out[0];
-                ((float *)g.ay)[o] = out[1];
-                ((float *)g.az)[o] = out[2];
+                ((float *)g.ax)[o] = ax + out[0];
+                ((float *)g.ay)[o] = ay + out[1];
+                ((float *)g.az)[o] = az + out[2];
             }
         }
     }
@@ -201,10 +228,10 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
 rcb_status gravity(rcb_tree *t, void *ax, void *ay, void *az, hipStream_t s) {
     rcb_status st = ensure_walk(t, s);
     if (st != RCB_OK) return st;
-    GravArgs g{t->nleaf, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ, t->near_off, t->far_off,
-               t->near_list, t->far_list, t->px, t->py, t->pz, t->pm, t->ph, t->fdx, t->fdy,
-               t->fdz, t->fm, t->fh, t->pid, ax, ay, az};
-    const unsigned grid = (unsigned)((t->nleaf + kWaves - 1) / kWaves);
+    GravArgs g{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
+               t->gnear_off, t->gfar_off, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
+               t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, ax, ay, az};
+    const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     if (t->p.precision == RCB_MIXED) {
         k_gravity<true><<<grid, kBlock, 0, s>>>(g);
     } else {

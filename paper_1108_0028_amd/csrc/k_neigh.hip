@@ -2,12 +2,14 @@
 // (Sec. 2.3: "Neighbour walk" culled to the true neighbours, and the
 // one-dimensional "Neighbour list").
 //
-// One wave per sink leaf A. Lanes are (sink slot s, slice j): S = the next
-// power of two >= min(n_A, 64) sinks, J = 64 / S slices. The wave walks the
-// candidate cells in ascending label order; for each cell, slice j of sink s
-// tests the particles first_B + t J + j. A pair is a neighbour iff b != a and
-// |r_a - r_b|^2 < (2 h_a)^2 in FP64 on the tree's copy of the inputs, the
-// same predicate for every precision mode. Count mode writes per-particle
+// One wave per group of sibling leaves (k_walk.hip). Lanes are (sink slot
+// s, slice j) over the group's particles: S = the next power of two
+// >= min(n_group, 64) sinks, J = 64 / S slices. The wave runs through the
+// group's near list in ascending label order; for an entry whose candidate
+// mask holds the sink's leaf, slice j of sink s tests the particles
+// first_B + t J + j. A pair is a neighbour iff b != a and
+// |r_a - r_b|^2 < (2 h_a)^2 in FP64 on the tree's copy of the inputs (the
+// same predicate for every precision mode). Count mode writes per-particle
 // counts; fill mode writes ids at offsets[a] + rank, ranks taken by ballot
 // within the sink's lane segment so each list keeps tree order.
 #include "rcb_internal.h"
@@ -18,60 +20,69 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
 
+struct NeighArgs {
+    int64_t nleaf;
+    int gk;
+    int64_t ngroup;
+    const int32_t *nfirst, *ncount;
+    const int64_t *gnear_off;
+    const uint64_t *gnear;
+    const double *px, *py, *pz, *ph;
+    const int32_t *pid;
+    int64_t *counts;
+    const int64_t *offsets;
+    int32_t *ids;
+};
+
 template <bool FILL>
-__global__ __launch_bounds__(kBlock) void k_neigh(int64_t nleaf, const int32_t *__restrict__ nfirst,
-                                                  const int32_t *__restrict__ ncount,
-                                                  const int64_t *__restrict__ near_off,
-                                                  const int32_t *__restrict__ near_list,
-                                                  const double *__restrict__ px,
-                                                  const double *__restrict__ py,
-                                                  const double *__restrict__ pz,
-                                                  const double *__restrict__ ph,
-                                                  const int32_t *__restrict__ pid,
-                                                  int64_t *__restrict__ counts,
-                                                  const int64_t *__restrict__ offsets,
-                                                  int32_t *__restrict__ ids) {
-    const int64_t li = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
-    if (li >= nleaf) return;
+__global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
+    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (gi >= a.ngroup) return;
     const int lane = lane_id();
-    const int64_t A = nleaf + li;
-    const int32_t sA = nfirst[A], nA = ncount[A];
-    if (nA == 0) return;
-    const int64_t l0 = near_off[li], l1 = near_off[li + 1];
+    const int G = 1 << a.gk;
+    const int64_t GL = (a.nleaf >> a.gk) + gi;
+    const int32_t sG = a.nfirst[GL], nG = a.ncount[GL];
+    if (nG == 0) return;
+    int32_t lf[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lf[i] = i < G ? a.nfirst[a.nleaf + gi * G + i] : 0x7fffffff;
     int S = 1;
-    while (S < nA && S < kWave) S <<= 1;
+    while (S < nG && S < kWave) S <<= 1;
     const int J = kWave / S;
-    const int sslot = lane / J;   // sink slot
+    const int sslot = lane / J;
     const int slice = lane % J;
     const uint64_t segmask = (J == 64) ? ~0ull : (((1ull << J) - 1ull) << (sslot * J));
-    for (int g0 = 0; g0 < nA; g0 += kWave) {
+    const int64_t n0 = a.gnear_off[gi], n1 = a.gnear_off[gi + 1];
+    for (int g0 = 0; g0 < nG; g0 += S) {
         const int si = g0 + sslot;
-        const bool has_sink = si < nA;
-        const int64_t pa = (int64_t)sA + (has_sink ? si : 0);
-        const double xa = px[pa], ya = py[pa], za = pz[pa];
-        const double two_h = 2.0 * ph[pa];
+        const bool has_sink = si < nG;
+        const int32_t pa = sG + (has_sink ? si : 0);
+        int la = 0;
+#pragma unroll
+        for (int i = 1; i < 8; ++i)
+            if (lf[i] <= pa) la = i;
+        const uint32_t bit = has_sink ? (1u << (8 + la)) : 0u;   // candidate-mask bit
+        const double xa = a.px[pa], ya = a.py[pa], za = a.pz[pa];
+        const double two_h = 2.0 * a.ph[pa];
         const double lim = two_h * two_h;
         int64_t cnt = 0;
         int64_t obase = 0;
-        if (FILL && has_sink) obase = offsets[pid[pa]];
-        for (int64_t e = l0; e < l1; ++e) {
-            const uint32_t ent = (uint32_t)near_list[e];
-            if (!(ent >> 31)) continue;
-            const int64_t B = ent & 0x7fffffffu;
-            const int32_t fB = nfirst[B], cB = ncount[B];
+        if (FILL && has_sink) obase = a.offsets[a.pid[pa]];
+        for (int64_t e = n0; e < n1; ++e) {
+            const uint64_t ent = a.gnear[e];
+            const uint32_t masks = (uint32_t)(ent >> 32);
+            if (!(masks & 0xff00u)) continue;          // no candidate for any leaf
+            const int64_t B = (uint32_t)ent & 0x7fffffffu;
+            const bool mine = (masks & bit) != 0;
+            const int32_t fB = a.nfirst[B], cB = a.ncount[B];
             for (int32_t t0 = 0; t0 < cB; t0 += J) {
                 const int32_t ob = t0 + slice;
-                const int64_t pb = (int64_t)fB + ob;
+                const int32_t pb = fB + ob;
                 bool hit = false;
-                if (has_sink && ob < cB && pb != pa) {
-                    hit = dist2(xa, ya, za, px[pb], py[pb], pz[pb]) < lim;
-                }
+                if (mine && ob < cB && pb != pa) hit = dist2(xa, ya, za, a.px[pb], a.py[pb], a.pz[pb]) < lim;
                 if (FILL) {
                     const uint64_t bal = ballot(hit) & segmask;
-                    if (hit) {
-                        const int r = rank_below(bal);
-                        ids[obase + cnt + r] = pid[pb];
-                    }
+                    if (hit) a.ids[obase + cnt + rank_below(bal)] = a.pid[pb];
                     cnt += __popcll(bal);
                 } else {
                     cnt += hit;
@@ -79,9 +90,8 @@ __global__ __launch_bounds__(kBlock) void k_neigh(int64_t nleaf, const int32_t *
             }
         }
         if (!FILL) {
-            // reduce the J slices of each sink
             for (int o = 1; o < J; o <<= 1) cnt += __shfl_xor(cnt, o, kWave);
-            if (has_sink && slice == 0) counts[pid[pa]] = cnt;
+            if (has_sink && slice == 0) a.counts[a.pid[pa]] = cnt;
         }
     }
 }
@@ -94,34 +104,37 @@ rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipSt
     std::vector<void *> tmp;
     int64_t *counts = (int64_t *)dalloc(t, sizeof(int64_t) * t->n, s, tmp);
     if (!counts) return RCB_ENOMEM;
-    const unsigned grid = (unsigned)((t->nleaf + kWaves - 1) / kWaves);
-    k_neigh<false><<<grid, kBlock, 0, s>>>(t->nleaf, t->nfirst, t->ncount, t->near_off, t->near_list,
-                                           t->px, t->py, t->pz, t->ph, t->pid, counts, nullptr,
-                                           nullptr);
+    NeighArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->gnear_off, t->gnear,
+                t->px, t->py, t->pz, t->ph, t->pid, counts, nullptr, nullptr};
+    const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
+    k_neigh<false><<<grid, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_neigh<count>");
     st = scan_i64(t, counts, offsets, t->n, s);
     if (st != RCB_OK) return st;
     RCB_HIP(hipMemcpyAsync(total, offsets + t->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RCB_HIP(hipFreeAsync(counts, s));
     RCB_HIP(hipStreamSynchronize(s));
+    t->nb_total = *total;
     return RCB_OK;
 }
 
 rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, int64_t cap,
                            hipStream_t s) {
-    rcb_status st = ensure_walk(t, s);
-    if (st != RCB_OK) return st;
-    int64_t total = 0;
-    RCB_HIP(hipMemcpyAsync(&total, offsets + t->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RCB_HIP(hipStreamSynchronize(s));
-    if (total > cap) {
+    if (t->nb_total < 0) {
+        set_error("rcb_neighbours_fill: call rcb_neighbours_count on this tree first");
+        return RCB_ESTATE;
+    }
+    if (t->nb_total > cap) {
         set_error("rcb_neighbours_fill: capacity " + std::to_string(cap) + " < total " +
-                  std::to_string(total));
+                  std::to_string(t->nb_total));
         return RCB_ECAPACITY;
     }
-    const unsigned grid = (unsigned)((t->nleaf + kWaves - 1) / kWaves);
-    k_neigh<true><<<grid, kBlock, 0, s>>>(t->nleaf, t->nfirst, t->ncount, t->near_off, t->near_list,
-                                          t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids);
+    rcb_status st = ensure_walk(t, s);
+    if (st != RCB_OK) return st;
+    NeighArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->gnear_off, t->gnear,
+                t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids};
+    const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
+    k_neigh<true><<<grid, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_neigh<fill>");
     return RCB_OK;
 }

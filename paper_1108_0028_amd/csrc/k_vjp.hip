@@ -13,12 +13,14 @@
 //   dr_a += J g_a + H[g_a, d_a]                       (d_a = r_a - com_A)
 //   com_A receives cot = sum_B d(G2:H/2)/dR  ->  dr_a += m_a/M_A cot,
 //                                              dm_a += cot . d_a / M_A
-//   node B receives dM, -dPsi/dR, dQ (FP64 atomics).
+//   node B receives dM, -dPsi/dR, dQ: summed over the group's leaves that
+//   accepted B, then added with FP64 atomics.
 // Push: every node's adjoint reaches its particles b through
 //   M = sum m, COM = sum m r / M, Q = sum m (3 d d^T - |d|^2 I), d = r - COM:
 //   dr_b += aR m_b / M + m_b (6 aQ d - 2 tr(aQ) d)
 //   dm_b += aM + aR . d / M + 3 d.aQ.d - |d|^2 tr(aQ)
 // (dQ/dCOM = 0 because sum m d = 0).
+// Kernels: moments (per group) -> far (per group) -> near (per group) -> push.
 #include "far_math.h"
 #include "rcb_internal.h"
 
@@ -27,7 +29,9 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kAdj = 10;   // M, R(3), Q(6)
+constexpr int kAdj = 10;    // M, R(3), Q(6)
+constexpr int kMom = 30;    // G0(3), G1(9), G2(18)
+constexpr int kLeafC = 22;  // 19 far coefficients + cot(3)
 
 using rcbfar::hidx;
 using rcbfar::jidx;
@@ -56,14 +60,18 @@ __device__ __forceinline__ void soft_FdF(T r2, T hab, T &F, T &dFr) {
 
 struct VjpArgs {
     int64_t nleaf;
+    int gk;
+    int64_t ngroup;
     const int32_t *nfirst, *ncount;
     const double *ncom, *nM, *nQ;
-    const int64_t *near_off, *far_off;
-    const int32_t *near_list, *far_list;
+    const int64_t *gnear_off, *gfar_off;
+    const uint64_t *gnear, *gfar;
     const double *px, *py, *pz, *pm, *ph;
     const float *fdx, *fdy, *fdz, *fm, *fh;
     const int32_t *pid;
     const void *gx, *gy, *gz;
+    double *mom;    // kMom per leaf
+    double *leafc;  // kLeafC per leaf
     double *sink;   // 4 n, tree order: dx dy dz dm
     double *src;    // 4 n, tree order, atomics
     double *adj;    // kAdj per label, atomics
@@ -76,94 +84,179 @@ __device__ __forceinline__ double load_g(const void *p, int32_t i) {
     else return ((const double *)p)[i];
 }
 
-template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_vjp_leaf(VjpArgs a) {
-    const int64_t li = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
-    if (li >= a.nleaf) return;
-    const int lane = lane_id();
-    const int64_t A = a.nleaf + li;
-    const int32_t sA = a.nfirst[A], nA = a.ncount[A];
-    if (nA == 0) return;
-    const double cA[3] = {a.ncom[3 * A], a.ncom[3 * A + 1], a.ncom[3 * A + 2]};
-    const double MA = a.nM[A];
-
-    // cotangent moments of the sink leaf
-    rcbfar::SinkMoments G;
-    {
-        double m[30];
+// leaf slot (within the group) of tree position pa
+__device__ __forceinline__ int leaf_slot(const int32_t (&lf)[8], int32_t pa) {
+    int la = 0;
 #pragma unroll
-        for (int q = 0; q < 30; ++q) m[q] = 0.0;
-        for (int i = lane; i < nA; i += kWave) {
-            const int64_t p = (int64_t)sA + i;
+    for (int i = 1; i < 8; ++i)
+        if (lf[i] <= pa) la = i;
+    return la;
+}
+
+// cotangent moments G0, G1, G2 of every leaf of the group
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_vjp_moments(VjpArgs a) {
+    __shared__ double acc_all[kWaves][8][kMom];
+    double(*acc)[kMom] = acc_all[threadIdx.x / kWave];
+    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (gi >= a.ngroup) return;
+    const int lane = lane_id();
+    const int G = 1 << a.gk;
+    const int64_t GL = (a.nleaf >> a.gk) + gi;
+    const int32_t sG = a.nfirst[GL], nG = a.ncount[GL];
+    for (int i = lane; i < 8 * kMom; i += kWave) acc[i / kMom][i % kMom] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    int32_t lf[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lf[i] = i < G ? a.nfirst[a.nleaf + gi * G + i] : 0x7fffffff;
+    for (int s0 = 0; s0 < nG; s0 += kWave) {
+        const int si = s0 + lane;
+        if (si < nG) {
+            const int32_t p = sG + si;
+            const int la = leaf_slot(lf, p);
+            const int64_t A = a.nleaf + gi * G + la;
             const int32_t o = a.pid[p];
             const double g[3] = {load_g<MIXED>(a.gx, o), load_g<MIXED>(a.gy, o), load_g<MIXED>(a.gz, o)};
-            const double d[3] = {a.px[p] - cA[0], a.py[p] - cA[1], a.pz[p] - cA[2]};
+            const double d[3] = {a.px[p] - a.ncom[3 * A], a.py[p] - a.ncom[3 * A + 1],
+                                 a.pz[p] - a.ncom[3 * A + 2]};
+            double *m = acc[la];
 #pragma unroll
             for (int u = 0; u < 3; ++u) {
-                m[u] += g[u];
+                atomicAdd(&m[u], g[u]);
 #pragma unroll
-                for (int l = 0; l < 3; ++l) m[3 + 3 * u + l] += g[u] * d[l];
+                for (int l = 0; l < 3; ++l) atomicAdd(&m[3 + 3 * u + l], g[u] * d[l]);
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
                     const int l = k < 3 ? 0 : (k < 5 ? 1 : 2);
                     const int mm = k < 3 ? k : (k < 5 ? k - 2 : 2);
-                    m[12 + 6 * u + k] += g[u] * d[l] * d[mm];
+                    atomicAdd(&m[12 + 6 * u + k], g[u] * d[l] * d[mm]);
                 }
             }
         }
-#pragma unroll
-        for (int q = 0; q < 30; ++q) m[q] = wave_sum(m[q]);
-#pragma unroll
-        for (int q = 0; q < 3; ++q) G.G0[q] = m[q];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) G.G1[q] = m[3 + q];
-#pragma unroll
-        for (int q = 0; q < 18; ++q) G.G2[q] = m[12 + q];
-        rcbfar::sink_traces(G);
     }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int i = lane; i < G * kMom; i += kWave)
+        a.mom[(gi * G + i / kMom) * kMom + i % kMom] = acc[i / kMom][i % kMom];
+}
 
-    // far field: forward coefficients, the sink-centre term, node adjoints
+// far field: per group, lanes = (far entry, leaf)
+__global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
+    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (gi >= a.ngroup) return;
+    const int lane = lane_id();
+    const int slot = lane >> 3, li = lane & 7;
+    const int G = 1 << a.gk;
+    const int64_t leaf = gi * G + (li < G ? li : 0);
+    const int64_t A = a.nleaf + leaf;
+    const double cA[3] = {a.ncom[3 * A], a.ncom[3 * A + 1], a.ncom[3 * A + 2]};
+    rcbfar::SinkMoments Gm;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Gm.G0[q] = a.mom[leaf * kMom + q];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Gm.G1[q] = a.mom[leaf * kMom + 3 + q];
+#pragma unroll
+    for (int q = 0; q < 18; ++q) Gm.G2[q] = a.mom[leaf * kMom + 12 + q];
+    rcbfar::sink_traces(Gm);
     double c[19];
 #pragma unroll
     for (int q = 0; q < 19; ++q) c[q] = 0.0;
     double cot[3] = {0.0, 0.0, 0.0};
-    const int64_t f0 = a.far_off[li], f1 = a.far_off[li + 1];
-    for (int64_t e = f0 + lane; e < f1; e += kWave) {
-        const int64_t B = a.far_list[e];
-        double qq[6];
+    const int64_t f0 = a.gfar_off[gi], f1 = a.gfar_off[gi + 1];
+    for (int64_t e0 = f0; e0 < f1; e0 += 8) {
+        const int64_t e = e0 + slot;
+        const uint64_t ent = e < f1 ? a.gfar[e] : 0ull;
+        const bool mine = (ent >> (32 + li)) & 1ull;
+        const int64_t B = (uint32_t)ent & 0x7fffffffu;
+        double ad[kAdj];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) qq[q] = a.nQ[6 * B + q];
-        const double R[3] = {cA[0] - a.ncom[3 * B], cA[1] - a.ncom[3 * B + 1], cA[2] - a.ncom[3 * B + 2]};
-        const double MB = a.nM[B];
-        rcbfar::m2l_accumulate(R[0], R[1], R[2], MB, qq, c);
-        double rho[3], ct[3], aM, aQ[6];
-        rcbfar::far_pair_adjoint(R[0], R[1], R[2], MB, qq, G, rho, ct, aM, aQ);
-        double *ad = a.adj + kAdj * B;
-        atomicAdd(ad + 0, aM);
+        for (int q = 0; q < kAdj; ++q) ad[q] = 0.0;
+        if (mine) {
+            double qq[6];
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            atomicAdd(ad + 1 + u, -rho[u]);
-            cot[u] += ct[u];
+            for (int q = 0; q < 6; ++q) qq[q] = a.nQ[6 * B + q];
+            const double R[3] = {cA[0] - a.ncom[3 * B], cA[1] - a.ncom[3 * B + 1], cA[2] - a.ncom[3 * B + 2]};
+            const double MB = a.nM[B];
+            rcbfar::m2l_accumulate(R[0], R[1], R[2], MB, qq, c);
+            double rho[3], ct[3], aM, aQ[6];
+            rcbfar::far_pair_adjoint(R[0], R[1], R[2], MB, qq, Gm, rho, ct, aM, aQ);
+            ad[0] = aM;
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                ad[1 + u] = -rho[u];
+                cot[u] += ct[u];
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) ad[4 + q] = aQ[q];
         }
+        // sum over the 8 leaves of the entry, one set of atomics per entry
 #pragma unroll
-        for (int k = 0; k < 6; ++k) atomicAdd(ad + 4 + k, aQ[k]);
+        for (int q = 0; q < kAdj; ++q) {
+            double v = ad[q];
+            v += __shfl_xor(v, 1, kWave);
+            v += __shfl_xor(v, 2, kWave);
+            v += __shfl_xor(v, 4, kWave);
+            ad[q] = v;
+        }
+        if (li == 0 && e < f1) {
+            double *dst = a.adj + kAdj * B;
+#pragma unroll
+            for (int q = 0; q < kAdj; ++q) atomicAdd(dst + q, ad[q]);
+        }
+    }
+    // sum the leaf's lanes
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        double v = c[q];
+        v += __shfl_xor(v, 8, kWave);
+        v += __shfl_xor(v, 16, kWave);
+        v += __shfl_xor(v, 32, kWave);
+        c[q] = v;
     }
 #pragma unroll
-    for (int q = 0; q < 19; ++q) c[q] = wave_sum(c[q]);
+    for (int u = 0; u < 3; ++u) {
+        double v = cot[u];
+        v += __shfl_xor(v, 8, kWave);
+        v += __shfl_xor(v, 16, kWave);
+        v += __shfl_xor(v, 32, kWave);
+        cot[u] = v;
+    }
+    if (slot == 0 && li < G) {
+        double *dst = a.leafc + leaf * kLeafC;
 #pragma unroll
-    for (int u = 0; u < 3; ++u) cot[u] = wave_sum(cot[u]);
+        for (int q = 0; q < 19; ++q) dst[q] = c[q];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) dst[19 + u] = cot[u];
+    }
+}
 
-    // near field
+// near field and the sink-side far terms: per group, lanes = (sink, slice)
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
+    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (gi >= a.ngroup) return;
+    const int lane = lane_id();
+    const int G = 1 << a.gk;
+    const int64_t GL = (a.nleaf >> a.gk) + gi;
+    const int32_t sG = a.nfirst[GL], nG = a.ncount[GL];
+    if (nG == 0) return;
+    int32_t lf[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lf[i] = i < G ? a.nfirst[a.nleaf + gi * G + i] : 0x7fffffff;
     int S = 1;
-    while (S < nA && S < kWave) S <<= 1;
+    while (S < nG && S < kWave) S <<= 1;
     const int J = kWave / S;
     const int sslot = lane / J;
     const int slice = lane % J;
-    const int64_t l0 = a.near_off[li], l1 = a.near_off[li + 1];
-    for (int g0 = 0; g0 < nA; g0 += kWave) {
+    const int64_t n0 = a.gnear_off[gi], n1 = a.gnear_off[gi + 1];
+    for (int g0 = 0; g0 < nG; g0 += S) {
         const int si = g0 + sslot;
-        const bool has_sink = si < nA;
-        const int64_t pa = (int64_t)sA + (has_sink ? si : 0);
+        const bool has_sink = si < nG;
+        const int32_t pa = sG + (has_sink ? si : 0);
+        const int la = leaf_slot(lf, pa);
+        const uint32_t bit = has_sink ? (1u << la) : 0u;
+        const int64_t A = a.nleaf + gi * G + la;
+        const double cA[3] = {a.ncom[3 * A], a.ncom[3 * A + 1], a.ncom[3 * A + 2]};
         const int32_t oa = a.pid[pa];
         double ga[3] = {0.0, 0.0, 0.0};
         if (has_sink) {
@@ -172,8 +265,10 @@ __global__ __launch_bounds__(kBlock) void k_vjp_leaf(VjpArgs a) {
             ga[2] = load_g<MIXED>(a.gz, oa);
         }
         double acc[3] = {0.0, 0.0, 0.0};
-        for (int64_t e = l0; e < l1; ++e) {
-            const int64_t B = (uint32_t)a.near_list[e] & 0x7fffffffu;
+        for (int64_t e = n0; e < n1; ++e) {
+            const uint64_t ent = a.gnear[e];
+            const int64_t B = (uint32_t)ent & 0x7fffffffu;
+            const bool mine = (((uint32_t)(ent >> 32)) & bit) != 0;
             const int32_t fB = a.nfirst[B], cB = a.ncount[B];
             float off[3] = {0.f, 0.f, 0.f};
             if constexpr (MIXED) {
@@ -184,45 +279,47 @@ __global__ __launch_bounds__(kBlock) void k_vjp_leaf(VjpArgs a) {
             for (int32_t t0 = 0; t0 < cB; t0 += J) {
                 const int32_t ob = t0 + slice;
                 const bool valid = ob < cB;
-                const int64_t pb = (int64_t)fB + (valid ? ob : 0);
-                double s[4];   // source-side contributions of this pair
-                if constexpr (!MIXED) {
-                    const double v[3] = {a.px[pa] - a.px[pb], a.py[pa] - a.py[pb], a.pz[pa] - a.pz[pb]};
-                    const double r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
-                    double F, dFr;
-                    soft_FdF<double>(r2, 0.5 * (a.ph[pa] + a.ph[pb]), F, dFr);
-                    const double vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
-                    const double mb = valid ? a.pm[pb] : 0.0;
+                const int32_t pb = fB + (valid ? ob : 0);
+                double s[4] = {0.0, 0.0, 0.0, 0.0};
+                if (mine && valid) {
+                    if constexpr (!MIXED) {
+                        const double v[3] = {a.px[pa] - a.px[pb], a.py[pa] - a.py[pb], a.pz[pa] - a.pz[pb]};
+                        const double r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+                        double F, dFr;
+                        soft_FdF<double>(r2, 0.5 * (a.ph[pa] + a.ph[pb]), F, dFr);
+                        const double vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
+                        const double mb = a.pm[pb];
 #pragma unroll
-                    for (int u = 0; u < 3; ++u) {
-                        const double Kg = mb * (F * ga[u] + dFr * v[u] * vg);
-                        acc[u] -= Kg;
-                        s[u] = Kg;
-                    }
-                    s[3] = valid ? -F * vg : 0.0;
-                } else {
-                    const float v[3] = {(a.fdx[pa] + off[0]) - a.fdx[pb], (a.fdy[pa] + off[1]) - a.fdy[pb],
-                                        (a.fdz[pa] + off[2]) - a.fdz[pb]};
-                    const float r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
-                    float F, dFr;
-                    soft_FdF<float>(r2, 0.5f * (a.fh[pa] + a.fh[pb]), F, dFr);
-                    const float gf[3] = {(float)ga[0], (float)ga[1], (float)ga[2]};
-                    const float vg = v[0] * gf[0] + v[1] * gf[1] + v[2] * gf[2];
-                    const float mb = valid ? a.fm[pb] : 0.0f;
+                        for (int u = 0; u < 3; ++u) {
+                            const double Kg = mb * (F * ga[u] + dFr * v[u] * vg);
+                            acc[u] -= Kg;
+                            s[u] = Kg;
+                        }
+                        s[3] = -F * vg;
+                    } else {
+                        const float v[3] = {(a.fdx[pa] + off[0]) - a.fdx[pb], (a.fdy[pa] + off[1]) - a.fdy[pb],
+                                            (a.fdz[pa] + off[2]) - a.fdz[pb]};
+                        const float r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+                        float F, dFr;
+                        soft_FdF<float>(r2, 0.5f * (a.fh[pa] + a.fh[pb]), F, dFr);
+                        const float gf[3] = {(float)ga[0], (float)ga[1], (float)ga[2]};
+                        const float vg = v[0] * gf[0] + v[1] * gf[1] + v[2] * gf[2];
+                        const float mb = a.fm[pb];
 #pragma unroll
-                    for (int u = 0; u < 3; ++u) {
-                        const float Kg = mb * (F * gf[u] + dFr * v[u] * vg);
-                        acc[u] -= (double)Kg;
-                        s[u] = (double)Kg;
+                        for (int u = 0; u < 3; ++u) {
+                            const float Kg = mb * (F * gf[u] + dFr * v[u] * vg);
+                            acc[u] -= (double)Kg;
+                            s[u] = (double)Kg;
+                        }
+                        s[3] = (double)(-F * vg);
                     }
-                    s[3] = valid ? (double)(-F * vg) : 0.0;
                 }
                 // sum the contributions of the wave's sinks to source pb
                 for (int o = J; o < kWave; o <<= 1) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) s[u] += __shfl_xor(s[u], o, kWave);
                 }
-                if (sslot == 0 && valid) {
+                if (sslot == 0 && valid && (s[0] != 0.0 || s[1] != 0.0 || s[2] != 0.0 || s[3] != 0.0)) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) atomicAdd(a.src + u * a.n + pb, s[u]);
                 }
@@ -233,17 +330,20 @@ __global__ __launch_bounds__(kBlock) void k_vjp_leaf(VjpArgs a) {
             for (int u = 0; u < 3; ++u) acc[u] += __shfl_xor(acc[u], o, kWave);
         }
         if (has_sink && slice == 0) {
+            const double *lc = a.leafc + (gi * G + la) * kLeafC;
             const double d[3] = {a.px[pa] - cA[0], a.py[pa] - cA[1], a.pz[pa] - cA[2]};
             const double ma = a.pm[pa];
+            const double MA = a.nM[A];
+            const double cot[3] = {lc[19], lc[20], lc[21]};
             double out[3];
 #pragma unroll
             for (int l = 0; l < 3; ++l) {
                 double v = acc[l] + ma / MA * cot[l];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    v += ga[i] * c[3 + jidx(i, l)];
+                    v += ga[i] * lc[3 + jidx(i, l)];
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) v += ga[i] * c[9 + hidx(i, l, m)] * d[m];
+                    for (int m = 0; m < 3; ++m) v += ga[i] * lc[9 + hidx(i, l, m)] * d[m];
                 }
                 out[l] = v;
             }
@@ -258,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp_leaf(VjpArgs a) {
 // node adjoints -> particles along each particle's ancestor chain; then the
 // three parts are summed and written in caller order.
 template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_vjp_push(VjpArgs a, int k, void *dx, void *dy, void *dz,
+__global__ __launch_bounds__(kBlock) void k_vjp_push(VjpArgs a, void *dx, void *dy, void *dz,
                                                      void *dm) {
     const int64_t li = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
     if (li >= a.nleaf) return;
@@ -301,7 +401,6 @@ __global__ __launch_bounds__(kBlock) void k_vjp_push(VjpArgs a, int k, void *dx,
             ((double *)dm)[o] = dmb;
         }
     }
-    (void)k;
 }
 
 }  // namespace
@@ -315,22 +414,27 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     double *sink = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
     double *src = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
     double *adj = (double *)dalloc(t, sizeof(double) * kAdj * t->nlab, s, tmp);
-    if (!sink || !src || !adj) return RCB_ENOMEM;
+    double *mom = (double *)dalloc(t, sizeof(double) * kMom * t->nleaf, s, tmp);
+    double *leafc = (double *)dalloc(t, sizeof(double) * kLeafC * t->nleaf, s, tmp);
+    if (!sink || !src || !adj || !mom || !leafc) return RCB_ENOMEM;
     RCB_HIP(hipMemsetAsync(src, 0, sizeof(double) * 4 * n, s));
     RCB_HIP(hipMemsetAsync(adj, 0, sizeof(double) * kAdj * t->nlab, s));
-    VjpArgs a{t->nleaf, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ, t->near_off, t->far_off,
-              t->near_list, t->far_list, t->px, t->py, t->pz, t->pm, t->ph, t->fdx, t->fdy, t->fdz,
-              t->fm, t->fh, t->pid, gx, gy, gz, sink, src, adj, n};
-    const unsigned grid = (unsigned)((t->nleaf + kWaves - 1) / kWaves);
-    if (t->p.precision == RCB_MIXED) {
-        k_vjp_leaf<true><<<grid, kBlock, 0, s>>>(a);
-        RCB_LAUNCH_CHECK("k_vjp_leaf");
-        k_vjp_push<true><<<grid, kBlock, 0, s>>>(a, t->k, dx, dy, dz, dm);
-    } else {
-        k_vjp_leaf<false><<<grid, kBlock, 0, s>>>(a);
-        RCB_LAUNCH_CHECK("k_vjp_leaf");
-        k_vjp_push<false><<<grid, kBlock, 0, s>>>(a, t->k, dx, dy, dz, dm);
-    }
+    VjpArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
+              t->gnear_off, t->gfar_off, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
+              t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, src, adj, n};
+    const unsigned gridg = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
+    const unsigned gridl = (unsigned)((t->nleaf + kWaves - 1) / kWaves);
+    const bool mixed = t->p.precision == RCB_MIXED;
+    if (mixed) k_vjp_moments<true><<<gridg, kBlock, 0, s>>>(a);
+    else k_vjp_moments<false><<<gridg, kBlock, 0, s>>>(a);
+    RCB_LAUNCH_CHECK("k_vjp_moments");
+    k_vjp_far<<<gridg, kBlock, 0, s>>>(a);
+    RCB_LAUNCH_CHECK("k_vjp_far");
+    if (mixed) k_vjp_near<true><<<gridg, kBlock, 0, s>>>(a);
+    else k_vjp_near<false><<<gridg, kBlock, 0, s>>>(a);
+    RCB_LAUNCH_CHECK("k_vjp_near");
+    if (mixed) k_vjp_push<true><<<gridl, kBlock, 0, s>>>(a, dx, dy, dz, dm);
+    else k_vjp_push<false><<<gridl, kBlock, 0, s>>>(a, dx, dy, dz, dm);
     RCB_LAUNCH_CHECK("k_vjp_push");
     for (void *p : tmp) RCB_HIP(hipFreeAsync(p, s));
     return RCB_OK;

@@ -1,24 +1,24 @@
-// k_walk.hip -- per-leaf tree walk producing the interaction lists
+// k_walk.hip -- tree walk producing the interaction lists
 // (Sec. 2.2 "Tree walk", Sec. 2.3.1 reachability, Sec. 2.4.1 MAC).
 //
-// One wave walks for one sink leaf A. The paper's walk is a depth-first
-// traversal that starts at nodes 2 and 3 and either accepts, discards or
-// opens each node. Here the wave keeps a LIFO stack of pending labels in LDS
-// and tests up to 64 of them at once; opened nodes push both children
-// (ballot + mbcnt compaction). The decisions per node B are exactly those of
-// the serial walk, so the lists are the same sets:
-//   empty B                             -> skipped (Sec. 2.1 "Load balancing")
+// The paper walks the tree once per lowest-level cell. Here one wave walks
+// for a GROUP of up to 8 sibling leaves (the leaves below one node of level
+// k-3) at once: lanes are (pending entry e = lane/8, leaf slot i = lane%8),
+// so every node record is loaded once for the whole group and tested
+// against each leaf whose own walk reaches it. Stack entries carry the node
+// label and the mask of leaves that visit it; per leaf the decisions are
+// exactly those of the serial walk:
+//   empty B                              -> skipped (Sec. 2.1 "Load balancing")
 //   reach(A,B): |g_A - g_B| < h_node(A) + h_node_int(B)
-//       leaf -> near list, candidate bit set; else open
-//   else H_B^2 < theta^2 |com_A - com_B|^2 -> far list
-//   else leaf -> near list (no candidate bit); else open
+//       leaf -> near, candidate; else open
+//   else H_B^2 < theta^2 |com_A - com_B|^2 -> far
+//   else leaf -> near (no candidate); else open
 // reach is evaluated squared with the radius sum padded by (1 + 2^-32).
-// Near lists are then sorted by label, so candidate cells (and hence the
-// neighbour lists) come out in tree order.
-//
-// Two launches: count (list sizes per leaf) and fill (after a scan of the
-// sizes). The stack holds at most ~64 (k + 2) labels: each round pops the 64
-// newest entries and pushes at most 128 children one level deeper.
+// Output per group: a near list of (label, near mask, candidate mask) and a
+// far list of (label, far mask) -- the union of the group's per-leaf lists.
+// Near lists are sorted by label, so each leaf's candidates (and neighbour
+// lists) come out in tree order. Two launches: count, then fill after a
+// scan of the sizes. Per-leaf lists for inspection are expanded on demand.
 #include "rcb_internal.h"
 
 namespace rcb {
@@ -26,145 +26,160 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
+constexpr int kGStack = 1024;        // (label, mask) entries per wave
 constexpr uint32_t kLabelMask = 0x7fffffffu;
 
+struct WalkArgs {
+    const double4 *rec;
+    const double *hnode;
+    int k, gk;
+    int64_t ngroup;
+    double theta2;
+    int64_t *near_cnt, *far_cnt;
+    const int64_t *near_off, *far_off;
+    uint64_t *near_list, *far_list;
+    int32_t *flag;
+};
+
 template <bool FILL>
-__global__ __launch_bounds__(kBlock) void k_walk(const double4 *__restrict__ rec,
-                                                 const double *__restrict__ hnode, int k,
-                                                 int64_t nleaf, double theta2,
-                                                 int64_t *__restrict__ near_cnt,
-                                                 int64_t *__restrict__ far_cnt,
-                                                 const int64_t *__restrict__ near_off,
-                                                 const int64_t *__restrict__ far_off,
-                                                 int32_t *__restrict__ near_list,
-                                                 int32_t *__restrict__ far_list,
-                                                 int32_t *__restrict__ flag) {
-    __shared__ int32_t stk_all[kWaves][kStackCap];
-    int32_t *stk = stk_all[threadIdx.x / kWave];
-    const int64_t li = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
-    if (li >= nleaf) return;
+__global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
+    __shared__ uint64_t stk_all[kWaves][kGStack];
+    uint64_t *stk = stk_all[threadIdx.x / kWave];
+    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (gi >= w.ngroup) return;
     const int lane = lane_id();
-    const int64_t A = nleaf + li;
-    const double4 ga = rec[2 * A], ca = rec[2 * A + 1];
-    if (ga.w < 0.0) {   // empty leaf: no lists
+    const int G = 1 << w.gk;
+    const int slot = lane >> 3;      // pending entry handled by this lane
+    const int li = lane & 7;         // leaf slot within the group
+    const int64_t nleaf = (int64_t)1 << w.k;
+    const int64_t A = nleaf + gi * G + (li < G ? li : 0);
+    const double4 ga = w.rec[2 * A], ca = w.rec[2 * A + 1];
+    const double hA = w.hnode[A];
+    const bool leaf_live = li < G && ga.w >= 0.0;
+    const uint32_t live_mask = (uint32_t)(ballot(leaf_live) & 0xffull);
+    int64_t nn = 0, nf = 0, nbase = 0, fbase = 0;
+    if (FILL) {
+        nbase = w.near_off[gi];
+        fbase = w.far_off[gi];
+    }
+    if (live_mask == 0) {
         if (!FILL && lane == 0) {
-            near_cnt[li] = 0;
-            far_cnt[li] = 0;
+            w.near_cnt[gi] = 0;
+            w.far_cnt[gi] = 0;
         }
         return;
     }
-    const double hA = hnode[A];
-    int sp;
-    if (k == 0) {
-        if (lane == 0) stk[0] = 1;
-        sp = 1;
-    } else {
-        if (lane == 0) {
-            stk[0] = 3;
-            stk[1] = 2;
+    if (lane == 0) {
+        if (w.k == 0) {
+            stk[0] = 1ull | ((uint64_t)live_mask << 32);
+        } else {
+            stk[0] = 3ull | ((uint64_t)live_mask << 32);
+            stk[1] = 2ull | ((uint64_t)live_mask << 32);
         }
-        sp = 2;
     }
+    int sp = w.k == 0 ? 1 : 2;
     __builtin_amdgcn_wave_barrier();
-    int64_t nn = 0, nf = 0;
-    int64_t nbase = 0, fbase = 0;
-    if (FILL) {
-        nbase = near_off[li];
-        fbase = far_off[li];
-    }
     bool overflow = false;
     while (sp > 0) {
-        const int b = sp < kWave ? sp : kWave;
+        const int b = sp < 8 ? sp : 8;
         sp -= b;
-        const bool act = lane < b;
-        const int32_t node = act ? stk[sp + lane] : 0;
+        const bool act = slot < b;
+        const uint64_t ent = act ? stk[sp + slot] : 0ull;
+        const int32_t node = (int32_t)(ent & 0xffffffffull);
+        const uint32_t emask = (uint32_t)(ent >> 32);
+        const bool mine = act && ((emask >> li) & 1u);
         double4 gb = make_double4(0.0, 0.0, 0.0, -1.0), cb = make_double4(0.0, 0.0, 0.0, 0.0);
         if (act) {
-            gb = rec[2 * (int64_t)node];
-            cb = rec[2 * (int64_t)node + 1];
+            gb = w.rec[2 * (int64_t)node];
+            cb = w.rec[2 * (int64_t)node + 1];
         }
-        const bool live = act && gb.w >= 0.0;
+        const bool live = mine && gb.w >= 0.0;
         const bool leafB = node >= nleaf;
         const double dg2 = dist2(ga.x, ga.y, ga.z, gb.x, gb.y, gb.z);
         const double rs = (hA + gb.w) * kReachPad;
         const bool reach = dg2 < rs * rs;
         const double R2 = dist2(ca.x, ca.y, ca.z, cb.x, cb.y, cb.z);
-        const bool mac = cb.w * cb.w < theta2 * R2;
+        const bool mac = cb.w * cb.w < w.theta2 * R2;
         const bool open = live && !leafB && (reach || !mac);
         const bool nearf = live && leafB && (reach || !mac);
         const bool farf = live && !reach && mac;
-        const uint64_t bo = ballot(open);
-        const int no = __popcll(bo);
-        if (sp + 2 * no > kStackCap) {
+        const uint64_t bo = ballot(open), bn = ballot(nearf), bc = ballot(nearf && reach),
+                       bf = ballot(farf);
+        // one lane per entry (li == 0) turns the 8 decision bits into list entries
+        const uint32_t om = (uint32_t)((bo >> (8 * slot)) & 0xffull);
+        const uint32_t nm = (uint32_t)((bn >> (8 * slot)) & 0xffull);
+        const uint32_t cm = (uint32_t)((bc >> (8 * slot)) & 0xffull);
+        const uint32_t fm = (uint32_t)((bf >> (8 * slot)) & 0xffull);
+        const bool lead = act && li == 0;
+        const uint64_t b_open = ballot(lead && om != 0);
+        const uint64_t b_near = ballot(lead && nm != 0);
+        const uint64_t b_far = ballot(lead && fm != 0);
+        const int no = __popcll(b_open);
+        if (sp + 2 * no > kGStack) {
             overflow = true;
             break;
         }
         __builtin_amdgcn_wave_barrier();
-        if (open) {
-            const int r = rank_below(bo);
-            stk[sp + 2 * r] = 2 * node;
-            stk[sp + 2 * r + 1] = 2 * node + 1;
+        if (lead && om != 0) {
+            const int r = rank_below(b_open);
+            stk[sp + 2 * r] = (uint64_t)(2 * node) | ((uint64_t)om << 32);
+            stk[sp + 2 * r + 1] = (uint64_t)(2 * node + 1) | ((uint64_t)om << 32);
         }
         __builtin_amdgcn_wave_barrier();
         sp += 2 * no;
-        const uint64_t bn = ballot(nearf);
-        const uint64_t bf = ballot(farf);
         if (FILL) {
-            if (nearf)
-                near_list[nbase + nn + rank_below(bn)] =
-                    (int32_t)((uint32_t)node | ((uint32_t)reach << 31));
-            if (farf) far_list[fbase + nf + rank_below(bf)] = node;
+            if (lead && nm != 0)
+                w.near_list[nbase + nn + rank_below(b_near)] =
+                    (uint64_t)(uint32_t)node | ((uint64_t)nm << 32) | ((uint64_t)cm << 40);
+            if (lead && fm != 0)
+                w.far_list[fbase + nf + rank_below(b_far)] = (uint64_t)(uint32_t)node | ((uint64_t)fm << 32);
         }
-        nn += __popcll(bn);
-        nf += __popcll(bf);
+        nn += __popcll(b_near);
+        nf += __popcll(b_far);
     }
     if (overflow) {
-        if (lane == 0) atomicOr(flag, 1);
+        if (lane == 0) atomicOr(w.flag, 1);
         if (!FILL && lane == 0) {
-            near_cnt[li] = 0;
-            far_cnt[li] = 0;
+            w.near_cnt[gi] = 0;
+            w.far_cnt[gi] = 0;
         }
         return;
     }
-    if (!FILL) {
-        if (lane == 0) {
-            near_cnt[li] = nn;
-            far_cnt[li] = nf;
-            if (nn > kStackCap) atomicAdd(&flag[1], 1);
-        }
-        return;
+    if (!FILL && lane == 0) {
+        w.near_cnt[gi] = nn;
+        w.far_cnt[gi] = nf;
+        if (nn > kGStack) atomicAdd(&w.flag[1], 1);
     }
 }
 
-// Sort each leaf's near list by label (bitonic network in LDS, one wave per
-// leaf). Lists longer than the LDS tile are queued for k_sort_long.
-__global__ __launch_bounds__(kBlock) void k_sort_near(int64_t nleaf, const int64_t *__restrict__ near_off,
-                                                      int32_t *__restrict__ near_list,
+// Sort each group's near list by label (bitonic network in LDS, one wave per
+// group). Longer lists are queued for k_sort_long.
+__global__ __launch_bounds__(kBlock) void k_sort_near(int64_t ngroup, const int64_t *__restrict__ near_off,
+                                                      uint64_t *__restrict__ near_list,
                                                       int32_t *__restrict__ flag,
                                                       int32_t *__restrict__ long_q) {
-    __shared__ int32_t buf_all[kWaves][kStackCap];
-    int32_t *buf = buf_all[threadIdx.x / kWave];
-    const int64_t li = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
-    if (li >= nleaf) return;
+    __shared__ uint64_t buf_all[kWaves][kGStack];
+    uint64_t *buf = buf_all[threadIdx.x / kWave];
+    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (gi >= ngroup) return;
     const int lane = lane_id();
-    const int64_t nbase = near_off[li];
-    const int64_t nn = near_off[li + 1] - nbase;
+    const int64_t nbase = near_off[gi];
+    const int64_t nn = near_off[gi + 1] - nbase;
     if (nn <= 1) return;
-    if (nn > kStackCap) {
-        if (lane == 0) long_q[atomicAdd(&flag[2], 1)] = (int32_t)li;
+    if (nn > kGStack) {
+        if (lane == 0) long_q[atomicAdd(&flag[2], 1)] = (int32_t)gi;
         return;
     }
     int P = 1;
     while (P < nn) P <<= 1;
-    for (int i = lane; i < P; i += kWave)
-        buf[i] = i < nn ? near_list[nbase + i] : (int32_t)kLabelMask;
+    for (int i = lane; i < P; i += kWave) buf[i] = i < nn ? near_list[nbase + i] : (uint64_t)kLabelMask;
     __builtin_amdgcn_wave_barrier();
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int q = lane; q < (P >> 1); q += kWave) {
                 const int i = 2 * stride * (q / stride) + (q % stride);
                 const int j = i + stride;
-                const int32_t a = buf[i], c = buf[j];
+                const uint64_t a = buf[i], c = buf[j];
                 const bool up = (i & size) == 0;
                 const uint32_t la = (uint32_t)a & kLabelMask, lc = (uint32_t)c & kLabelMask;
                 if (up ? la > lc : la < lc) {
@@ -184,10 +199,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_near(int64_t nleaf, const int64
 // list end never moves and pairs reaching past the end are simply skipped.
 __global__ __launch_bounds__(1024) void k_sort_long(const int32_t *__restrict__ long_q,
                                                     const int64_t *__restrict__ near_off,
-                                                    int32_t *__restrict__ near_list) {
-    const int64_t li = long_q[blockIdx.x];
-    int32_t *v = near_list + near_off[li];
-    const int64_t nn = near_off[li + 1] - near_off[li];
+                                                    uint64_t *__restrict__ near_list) {
+    const int64_t gi = long_q[blockIdx.x];
+    uint64_t *v = near_list + near_off[gi];
+    const int64_t nn = near_off[gi + 1] - near_off[gi];
     int64_t P = 1;
     while (P < nn) P <<= 1;
     for (int64_t size = 2; size <= P; size <<= 1) {
@@ -196,7 +211,7 @@ __global__ __launch_bounds__(1024) void k_sort_long(const int32_t *__restrict__ 
                 const int64_t i = 2 * stride * (q / stride) + (q % stride);
                 const int64_t j = stride == (size >> 1) ? (i ^ (size - 1)) : i + stride;
                 if (j < nn) {
-                    const int32_t a = v[i], c = v[j];
+                    const uint64_t a = v[i], c = v[j];
                     if (((uint32_t)a & kLabelMask) > ((uint32_t)c & kLabelMask)) {
                         v[i] = c;
                         v[j] = a;
@@ -209,10 +224,115 @@ __global__ __launch_bounds__(1024) void k_sort_long(const int32_t *__restrict__ 
     }
 }
 
+// Per-leaf lists from the group lists (inspection only): a leaf keeps the
+// entries whose mask has its bit; near entries become label | candidate << 31.
+template <bool FILL>
+__global__ __launch_bounds__(kBlock) void k_expand(int64_t nleaf, int gk,
+                                                   const int64_t *__restrict__ gnear_off,
+                                                   const uint64_t *__restrict__ gnear,
+                                                   const int64_t *__restrict__ gfar_off,
+                                                   const uint64_t *__restrict__ gfar,
+                                                   int64_t *__restrict__ ncnt, int64_t *__restrict__ fcnt,
+                                                   const int64_t *__restrict__ noff,
+                                                   const int64_t *__restrict__ foff,
+                                                   int32_t *__restrict__ nlist,
+                                                   int32_t *__restrict__ flist) {
+    const int64_t li = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (li >= nleaf) return;
+    const int64_t gi = li >> gk;
+    const int bit = (int)(li & ((1 << gk) - 1));
+    const int lane = lane_id();
+    int64_t nn = 0, nf = 0;
+    const int64_t n0 = gnear_off[gi], n1 = gnear_off[gi + 1];
+    for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
+        const int64_t e = e0 + lane;
+        const uint64_t ent = e < n1 ? gnear[e] : 0ull;
+        const bool has = (ent >> (32 + bit)) & 1ull;
+        const uint64_t bl = ballot(has);
+        if (FILL && has) {
+            const uint32_t cand = (uint32_t)((ent >> (40 + bit)) & 1ull);
+            nlist[noff[li] + nn + rank_below(bl)] = (int32_t)(((uint32_t)ent & kLabelMask) | (cand << 31));
+        }
+        nn += __popcll(bl);
+    }
+    const int64_t f0 = gfar_off[gi], f1 = gfar_off[gi + 1];
+    for (int64_t e0 = f0; e0 < f1; e0 += kWave) {
+        const int64_t e = e0 + lane;
+        const uint64_t ent = e < f1 ? gfar[e] : 0ull;
+        const bool has = (ent >> (32 + bit)) & 1ull;
+        const uint64_t bl = ballot(has);
+        if (FILL && has) flist[foff[li] + nf + rank_below(bl)] = (int32_t)((uint32_t)ent & kLabelMask);
+        nf += __popcll(bl);
+    }
+    if (!FILL && lane == 0) {
+        ncnt[li] = nn;
+        fcnt[li] = nf;
+    }
+}
+
 }  // namespace
 
 rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     if (t->walked) return RCB_OK;
+    const int64_t NG = t->ngroup;
+    std::vector<void *> tmp;
+    int64_t *ncnt = (int64_t *)dalloc(t, sizeof(int64_t) * NG, s, tmp);
+    int64_t *fcnt = (int64_t *)dalloc(t, sizeof(int64_t) * NG, s, tmp);
+    t->gnear_off = (int64_t *)dalloc(t, sizeof(int64_t) * (NG + 1), s, t->list_allocs);
+    t->gfar_off = (int64_t *)dalloc(t, sizeof(int64_t) * (NG + 1), s, t->list_allocs);
+    if (!ncnt || !fcnt || !t->gnear_off || !t->gfar_off) return RCB_ENOMEM;
+    WalkArgs w{t->wrec, t->nhnode, t->k, t->gk, NG, t->p.theta * t->p.theta, ncnt, fcnt,
+               nullptr, nullptr, nullptr, nullptr, t->dflag};
+    const unsigned grid = (unsigned)((NG + kWaves - 1) / kWaves);
+    RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 4, s));
+    k_walk_group<false><<<grid, kBlock, 0, s>>>(w);
+    RCB_LAUNCH_CHECK("k_walk_group<count>");
+    rcb_status st = scan_i64(t, ncnt, t->gnear_off, NG, s);
+    if (st != RCB_OK) return st;
+    st = scan_i64(t, fcnt, t->gfar_off, NG, s);
+    if (st != RCB_OK) return st;
+    int64_t tot[2] = {0, 0};
+    int32_t flags[4] = {0, 0, 0, 0};
+    RCB_HIP(hipMemcpyAsync(&tot[0], t->gnear_off + NG, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RCB_HIP(hipMemcpyAsync(&tot[1], t->gfar_off + NG, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
+    RCB_HIP(hipStreamSynchronize(s));
+    const int32_t nlong = flags[1];
+    if (flags[0]) {
+        set_error("walk: stack overflow (tree deeper than the walk stack supports)");
+        return RCB_ECAPACITY;
+    }
+    t->gnear = (uint64_t *)dalloc(t, sizeof(uint64_t) * std::max<int64_t>(1, tot[0]), s, t->list_allocs);
+    t->gfar = (uint64_t *)dalloc(t, sizeof(uint64_t) * std::max<int64_t>(1, tot[1]), s, t->list_allocs);
+    if (!t->gnear || !t->gfar) return RCB_ENOMEM;
+    w.near_off = t->gnear_off;
+    w.far_off = t->gfar_off;
+    w.near_list = t->gnear;
+    w.far_list = t->gfar;
+    k_walk_group<true><<<grid, kBlock, 0, s>>>(w);
+    RCB_LAUNCH_CHECK("k_walk_group<fill>");
+    int32_t *long_q = nullptr;
+    if (nlong > 0) {
+        long_q = (int32_t *)dalloc(t, sizeof(int32_t) * nlong, s, tmp);
+        if (!long_q) return RCB_ENOMEM;
+    }
+    k_sort_near<<<grid, kBlock, 0, s>>>(NG, t->gnear_off, t->gnear, t->dflag, long_q);
+    RCB_LAUNCH_CHECK("k_sort_near");
+    if (nlong > 0) {
+        k_sort_long<<<nlong, 1024, 0, s>>>(long_q, t->gnear_off, t->gnear);
+        RCB_LAUNCH_CHECK("k_sort_long");
+    }
+    for (void *p : tmp) RCB_HIP(hipFreeAsync(p, s));
+    t->gnear_total = tot[0];
+    t->gfar_total = tot[1];
+    t->walked = true;
+    return RCB_OK;
+}
+
+rcb_status ensure_leaf_lists(rcb_tree *t, hipStream_t s) {
+    rcb_status st = ensure_walk(t, s);
+    if (st != RCB_OK) return st;
+    if (t->leaf_lists) return RCB_OK;
     const int64_t L = t->nleaf;
     std::vector<void *> tmp;
     int64_t *ncnt = (int64_t *)dalloc(t, sizeof(int64_t) * L, s, tmp);
@@ -220,48 +340,29 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     t->near_off = (int64_t *)dalloc(t, sizeof(int64_t) * (L + 1), s, t->list_allocs);
     t->far_off = (int64_t *)dalloc(t, sizeof(int64_t) * (L + 1), s, t->list_allocs);
     if (!ncnt || !fcnt || !t->near_off || !t->far_off) return RCB_ENOMEM;
-    const double theta2 = t->p.theta * t->p.theta;
     const unsigned grid = (unsigned)((L + kWaves - 1) / kWaves);
-    RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 4, s));
-    k_walk<false><<<grid, kBlock, 0, s>>>(t->wrec, t->nhnode, t->k, L, theta2, ncnt, fcnt, nullptr,
-                                          nullptr, nullptr, nullptr, t->dflag);
-    RCB_LAUNCH_CHECK("k_walk<count>");
-    rcb_status st = scan_i64(t, ncnt, t->near_off, L, s);
+    k_expand<false><<<grid, kBlock, 0, s>>>(L, t->gk, t->gnear_off, t->gnear, t->gfar_off, t->gfar,
+                                            ncnt, fcnt, nullptr, nullptr, nullptr, nullptr);
+    RCB_LAUNCH_CHECK("k_expand<count>");
+    st = scan_i64(t, ncnt, t->near_off, L, s);
     if (st != RCB_OK) return st;
     st = scan_i64(t, fcnt, t->far_off, L, s);
     if (st != RCB_OK) return st;
     int64_t tot[2] = {0, 0};
-    int32_t flags[4] = {0, 0, 0, 0};
     RCB_HIP(hipMemcpyAsync(&tot[0], t->near_off + L, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RCB_HIP(hipMemcpyAsync(&tot[1], t->far_off + L, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
     RCB_HIP(hipStreamSynchronize(s));
-    const int32_t nlong = flags[1];
-    if (flags[0]) {
-        set_error("walk: LIFO stack overflow (tree deeper than the stack supports)");
-        return RCB_ECAPACITY;
-    }
     t->near_list = (int32_t *)dalloc(t, sizeof(int32_t) * std::max<int64_t>(1, tot[0]), s, t->list_allocs);
     t->far_list = (int32_t *)dalloc(t, sizeof(int32_t) * std::max<int64_t>(1, tot[1]), s, t->list_allocs);
     if (!t->near_list || !t->far_list) return RCB_ENOMEM;
-    k_walk<true><<<grid, kBlock, 0, s>>>(t->wrec, t->nhnode, t->k, L, theta2, nullptr, nullptr,
-                                         t->near_off, t->far_off, t->near_list, t->far_list, t->dflag);
-    RCB_LAUNCH_CHECK("k_walk<fill>");
-    int32_t *long_q = nullptr;
-    if (nlong > 0) {
-        long_q = (int32_t *)dalloc(t, sizeof(int32_t) * nlong, s, tmp);
-        if (!long_q) return RCB_ENOMEM;
-    }
-    k_sort_near<<<grid, kBlock, 0, s>>>(L, t->near_off, t->near_list, t->dflag, long_q);
-    RCB_LAUNCH_CHECK("k_sort_near");
-    if (nlong > 0) {
-        k_sort_long<<<nlong, 1024, 0, s>>>(long_q, t->near_off, t->near_list);
-        RCB_LAUNCH_CHECK("k_sort_long");
-    }
+    k_expand<true><<<grid, kBlock, 0, s>>>(L, t->gk, t->gnear_off, t->gnear, t->gfar_off, t->gfar,
+                                           nullptr, nullptr, t->near_off, t->far_off, t->near_list,
+                                           t->far_list);
+    RCB_LAUNCH_CHECK("k_expand<fill>");
     for (void *p : tmp) RCB_HIP(hipFreeAsync(p, s));
     t->near_total = tot[0];
     t->far_total = tot[1];
-    t->walked = true;
+    t->leaf_lists = true;
     return RCB_OK;
 }
 

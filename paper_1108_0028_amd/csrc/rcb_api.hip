@@ -112,6 +112,8 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
     t->k = k;
     t->nleaf = (int64_t)1 << k;
     t->nlab = (int64_t)2 << k;
+    t->gk = k < 3 ? k : 3;
+    t->ngroup = (int64_t)1 << (k - t->gk);
     t->p = *p;
     t->stream = (hipStream_t)stream;
     if (hipGetDevice(&t->device) != hipSuccess) t->device = 0;
@@ -182,8 +184,8 @@ rcb_status rcb_get_info(const rcb_tree *t, rcb_tree_info *info) {
     info->k = t->k;
     info->precision = t->p.precision;
     info->n_labels = t->nlab;
-    info->near_total = t->walked ? t->near_total : -1;
-    info->far_total = t->walked ? t->far_total : -1;
+    info->near_total = t->leaf_lists ? t->near_total : -1;
+    info->far_total = t->leaf_lists ? t->far_total : -1;
     info->theta = t->p.theta;
     return RCB_OK;
 }
@@ -197,7 +199,7 @@ rcb_status rcb_tree_export(rcb_tree *t, int32_t field, void *dst, size_t bytes, 
     hipStream_t s = (hipStream_t)stream;
     t->stream = s;
     if (field >= RCB_FIELD_NEAR_OFF) {
-        rcb_status st = ensure_walk(t, s);
+        rcb_status st = ensure_leaf_lists(t, s);
         if (st != RCB_OK) return st;
     }
     const void *src = nullptr;

@@ -66,10 +66,21 @@ struct rcb_tree {
     double *nhint = nullptr, *nhnode = nullptr;
     double4 *wrec = nullptr;
 
+    // interaction lists per group of 2^gk sibling leaves (gk = min(3, k)):
+    // near entries label | near_mask << 32 | candidate_mask << 40 (sorted by
+    // label), far entries label | far_mask << 32
+    int gk = 0;
+    int64_t ngroup = 0;
     bool walked = false;
+    int64_t gnear_total = -1, gfar_total = -1;
+    int64_t *gnear_off = nullptr, *gfar_off = nullptr;
+    uint64_t *gnear = nullptr, *gfar = nullptr;
+    // per-leaf lists, expanded from the group lists on demand (inspection)
+    bool leaf_lists = false;
     int64_t near_total = -1, far_total = -1;
     int64_t *near_off = nullptr, *far_off = nullptr;
     int32_t *near_list = nullptr, *far_list = nullptr;
+    int64_t nb_total = -1;             // neighbour total of the last count call
     int32_t *dflag = nullptr;          // device error flags (walk overflow etc.)
 
     std::vector<void *> allocs;        // everything to free on destroy
@@ -89,6 +100,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
 rcb_status scan_i64(rcb_tree *t, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
 // walk (k_walk.hip)
 rcb_status ensure_walk(rcb_tree *t, hipStream_t s);
+rcb_status ensure_leaf_lists(rcb_tree *t, hipStream_t s);
 // neighbours (k_neigh.hip)
 rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipStream_t s);
 rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, int64_t cap,
