@@ -242,4 +242,136 @@ RCB_HD void far_pair_adjoint(double x, double y, double z, double M, const doubl
     adjQ[5] = A[2][2];
 }
 
+
+// Closed-form version of far_pair_adjoint (no dual numbers). With ' = d/dR
+// and the recursions dD_k/dx_n = D_(k+1) x_n, ds/dx_n = 2 q_n, dq_i/dx_n = Q_in,
+//   e4 = M D4 + s D6/6, c3 = D5/3,
+// the fourth derivative T4_ilmn = dH_ilm/dx_n contracted with G2/2 gives
+//   2 cot_n = (e4 x_n + c3 q_n) w2 + e3 (p_n + 2 pt_n) + (e3 x_n + c2 q_n)(2 sig.x + tau.x)
+//           + b2 (2 sig_n + tau_n) + c3 x_n (q.p + 2 q.pt)
+//           + c2 [Q p + 2 Rm^T q + 2 Q pt + 2 Rm q + 2 P q]_n
+//           + c2 x_n (Q:P + 2 Q:Rm + tau.q + 2 sig.q)
+//           + c1 [G2_n..:Q + 2 sum_im G2_inm Q_im + Q tau + 2 Q sig]_n
+// with w2 = G2_ilm x_i x_l x_m, p_i = G2_ilm x_l x_m, pt_l = G2_ilm x_i x_m,
+// P_lm = G2_ilm x_i, Rm_il = G2_ilm x_m; and
+//   (G0.J)_n  = b2 u0 x_n + a1 G0_n + c1 ((G0.q) x_n + q_n u0) + c0 (Q G0)_n
+//   (G1:H)_n  = e3 w11 x_n + b2 (t1 x_n + v1_n + v1t_n) + c2 ((q.v1 + q.v1t) x_n + q_n w11)
+//             + c1 ((Q v1t)_n + (Q v1)_n + (G1:Q) x_n + (G1^T q)_n + (G1 q)_n + t1 q_n)
+//   rho = G0.J + G1:H + cot.
+RCB_HD void far_pair_adjoint_cf(double x, double y, double z, double M, const double qq[6],
+                                const SinkMoments &G, double rho[3], double cot[3], double &adjM,
+                                double adjQ[6]) {
+    const double X[3] = {x, y, z};
+    const double r2 = (x * x + y * y) + z * z;
+    const double ri = 1.0 / sqrt(r2);
+    const double ri2 = ri * ri;
+    const double D1 = -ri * ri2;
+    const double D2 = -3.0 * D1 * ri2;
+    const double D3 = -5.0 * D2 * ri2;
+    const double D4 = -7.0 * D3 * ri2;
+    const double D5 = -9.0 * D4 * ri2;
+    const double D6 = -11.0 * D5 * ri2;
+    const double Qm[3][3] = {{qq[0], qq[1], qq[2]}, {qq[1], qq[3], qq[4]}, {qq[2], qq[4], qq[5]}};
+    double q[3];
+    for (int i = 0; i < 3; ++i) q[i] = Qm[i][0] * x + Qm[i][1] * y + Qm[i][2] * z;
+    const double s = q[0] * x + q[1] * y + q[2] * z;
+    const double sixth = 1.0 / 6.0, third = 1.0 / 3.0;
+    const double a1 = M * D1 + sixth * D3 * s;
+    const double b2 = M * D2 + sixth * D4 * s;
+    const double e3 = M * D3 + sixth * D5 * s;
+    const double e4 = M * D4 + sixth * D6 * s;
+    const double c0 = third * D2, c1 = third * D3, c2 = third * D4, c3 = third * D5;
+    // sink contractions
+    const double u0 = G.G0[0] * x + G.G0[1] * y + G.G0[2] * z;
+    double v1[3], v1t[3];
+    for (int i = 0; i < 3; ++i) {
+        v1[i] = G.G1[3 * i] * x + G.G1[3 * i + 1] * y + G.G1[3 * i + 2] * z;
+        v1t[i] = G.G1[i] * x + G.G1[3 + i] * y + G.G1[6 + i] * z;
+    }
+    const double w11 = x * v1[0] + y * v1[1] + z * v1[2];
+    double P[6];
+    for (int k = 0; k < 6; ++k) P[k] = G.G2[k] * x + G.G2[6 + k] * y + G.G2[12 + k] * z;
+    double Rm[9];
+    for (int i = 0; i < 3; ++i)
+        for (int l = 0; l < 3; ++l)
+            Rm[3 * i + l] = G.G2[6 * i + jidx(l, 0)] * x + G.G2[6 * i + jidx(l, 1)] * y +
+                            G.G2[6 * i + jidx(l, 2)] * z;
+    double p[3], pt[3];
+    for (int i = 0; i < 3; ++i) {
+        p[i] = Rm[3 * i] * x + Rm[3 * i + 1] * y + Rm[3 * i + 2] * z;
+        pt[i] = P[jidx(i, 0)] * x + P[jidx(i, 1)] * y + P[jidx(i, 2)] * z;
+    }
+    const double w2 = p[0] * x + p[1] * y + p[2] * z;
+    const double sx = G.sig[0] * x + G.sig[1] * y + G.sig[2] * z;
+    const double tx = G.tau[0] * x + G.tau[1] * y + G.tau[2] * z;
+    double G1Q = 0.0, QP = 0.0, QRm = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int l = 0; l < 3; ++l) {
+            G1Q += G.G1[3 * i + l] * Qm[i][l];
+            QP += Qm[i][l] * P[jidx(i, l)];
+            QRm += Qm[i][l] * Rm[3 * i + l];
+        }
+    const double G0q = G.G0[0] * q[0] + G.G0[1] * q[1] + G.G0[2] * q[2];
+    const double qv1 = q[0] * v1[0] + q[1] * v1[1] + q[2] * v1[2];
+    const double qv1t = q[0] * v1t[0] + q[1] * v1t[1] + q[2] * v1t[2];
+    const double tq = G.tau[0] * q[0] + G.tau[1] * q[1] + G.tau[2] * q[2];
+    const double sq = G.sig[0] * q[0] + G.sig[1] * q[1] + G.sig[2] * q[2];
+    const double qp = q[0] * p[0] + q[1] * p[1] + q[2] * p[2];
+    const double qpt = q[0] * pt[0] + q[1] * pt[1] + q[2] * pt[2];
+    const double k3 = 2.0 * sx + tx;
+    const double k7 = QP + 2.0 * QRm + tq + 2.0 * sq;
+    const double k5 = qp + 2.0 * qpt;
+    for (int n = 0; n < 3; ++n) {
+        double Qp = 0.0, RmTq = 0.0, Qpt = 0.0, Rmq = 0.0, Pq = 0.0, QG0 = 0.0, Qv1t = 0.0, Qv1 = 0.0;
+        double G1Tq = 0.0, G1q = 0.0, Qtau = 0.0, Qsig = 0.0, G2nQ = 0.0, G2inmQ = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            Qp += Qm[n][i] * p[i];
+            RmTq += Rm[3 * i + n] * q[i];
+            Qpt += Qm[n][i] * pt[i];
+            Rmq += Rm[3 * n + i] * q[i];
+            Pq += P[jidx(n, i)] * q[i];
+            QG0 += Qm[n][i] * G.G0[i];
+            Qv1t += Qm[n][i] * v1t[i];
+            Qv1 += Qm[n][i] * v1[i];
+            G1Tq += G.G1[3 * i + n] * q[i];
+            G1q += G.G1[3 * n + i] * q[i];
+            Qtau += Qm[n][i] * G.tau[i];
+            Qsig += Qm[n][i] * G.sig[i];
+            for (int m = 0; m < 3; ++m) {
+                G2nQ += G.G2[6 * n + jidx(i, m)] * Qm[i][m];
+                G2inmQ += G.G2[6 * i + jidx(n, m)] * Qm[i][m];
+            }
+        }
+        const double two_cot = (e4 * X[n] + c3 * q[n]) * w2 + e3 * (p[n] + 2.0 * pt[n]) +
+                               (e3 * X[n] + c2 * q[n]) * k3 + b2 * (2.0 * G.sig[n] + G.tau[n]) +
+                               c3 * X[n] * k5 + c2 * (Qp + 2.0 * RmTq + 2.0 * Qpt + 2.0 * Rmq + 2.0 * Pq) +
+                               c2 * X[n] * k7 + c1 * (G2nQ + 2.0 * G2inmQ + Qtau + 2.0 * Qsig);
+        const double g0j = b2 * u0 * X[n] + a1 * G.G0[n] + c1 * (G0q * X[n] + q[n] * u0) + c0 * QG0;
+        const double g1h = e3 * w11 * X[n] + b2 * (G.t1 * X[n] + v1[n] + v1t[n]) +
+                           c2 * ((qv1 + qv1t) * X[n] + q[n] * w11) +
+                           c1 * (Qv1t + Qv1 + G1Q * X[n] + G1Tq + G1q + G.t1 * q[n]);
+        cot[n] = 0.5 * two_cot;
+        rho[n] = g0j + g1h + cot[n];
+    }
+    const double kA = u0 + G.t1;
+    const double kB = w11 + sx + 0.5 * tx;
+    const double kE = 0.5 * w2;
+    adjM = D1 * kA + D2 * kB + D3 * kE;
+    const double sig_s = sixth * (D3 * kA + D4 * kB + D5 * kE);
+    double psq[3];
+    for (int j = 0; j < 3; ++j)
+        psq[j] = c0 * G.G0[j] + c1 * (v1[j] + v1t[j] + 0.5 * G.tau[j] + G.sig[j]) + 0.5 * c2 * (p[j] + 2.0 * pt[j]);
+    double A[3][3];
+    for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k)
+            A[j][k] = sig_s * X[j] * X[k] + psq[j] * X[k] + c0 * G.G1[3 * j + k] +
+                      c1 * (0.5 * P[jidx(j, k)] + Rm[3 * j + k]);
+    adjQ[0] = A[0][0];
+    adjQ[1] = 0.5 * (A[0][1] + A[1][0]);
+    adjQ[2] = 0.5 * (A[0][2] + A[2][0]);
+    adjQ[3] = A[1][1];
+    adjQ[4] = 0.5 * (A[1][2] + A[2][1]);
+    adjQ[5] = A[2][2];
+}
+
 }  // namespace rcbfar

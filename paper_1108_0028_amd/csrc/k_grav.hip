@@ -10,14 +10,17 @@
 //        (far_math.h). B's record is loaded once for the 8 leaves. Lanes of
 //        the same leaf are summed at the end; coefficients go to LDS.
 //  near: lanes are (sink slot, slice) over the group's particles (contiguous
-//        in tree order); slice j of sink a runs over particles
-//        first_B + t J + j of every near entry B whose mask has a's leaf:
-//        a_a -= m_b F(r, h_ab) (r_a - r_b), F = S(q)/r (Sec. 2.4.3).
+//        in tree order). Sources are staged 64 at a time in LDS (near_tile.h);
+//        slice j of sink a takes tile entries j, j + J, ... whose near mask
+//        has a's leaf: a_a -= m_b F(r, h_ab) (r_a - r_b), F = S(q)/r
+//        (Sec. 2.4.3).
 //  L2P:  a_a += f + J d + H[d, d] / 2,  d = r_a - com_A  (Eq. 6).
-// FP64 form: everything in FP64. Mixed form: particles as FP32 offsets from
-// their leaf's centre of mass; per (A, B) the FP64 offset com_A - com_B is
-// rounded to FP32 once; P2P, accumulation and L2P in FP32; M2L in FP64.
+// FP64 form: everything in FP64. Mixed form: FP32 offsets from the leaf
+// centre of mass are moved into the group's frame by adding the FP64 offset
+// com_leaf - com_group rounded to FP32; pairs, accumulation and L2P in FP32;
+// M2L in FP64.
 #include "far_math.h"
+#include "near_tile.h"
 #include "rcb_internal.h"
 
 namespace rcb {
@@ -108,14 +111,29 @@ __device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, double 
 #pragma unroll
         for (int q = 0; q < 19; ++q) coef[li][q] = c[q];
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    tile_sync();
 }
+
+struct alignas(16) SrcF {
+    float x, y, z, m, h;
+    uint32_t mask;
+};
+struct alignas(16) SrcD {
+    double x, y, z, m, h;
+    uint32_t mask;
+};
+
+template <bool MIXED>
+struct GravShared {
+    double coef[8][19];
+    EntryChunk ec;
+    typename std::conditional<MIXED, SrcF, SrcD>::type tile[kWave];
+};
 
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
-    __shared__ double coef_all[kWaves][8][19];
-    double(*coef)[19] = coef_all[threadIdx.x / kWave];
+    __shared__ GravShared<MIXED> sh_all[kWaves];
+    GravShared<MIXED> &sh = sh_all[threadIdx.x / kWave];
     const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
     if (gi >= g.ngroup) return;
     const int lane = lane_id();
@@ -123,7 +141,8 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
     const int64_t GL = (g.nleaf >> g.gk) + gi;   // group node label
     const int32_t sG = g.nfirst[GL], nG = g.ncount[GL];
     if (nG == 0) return;
-    group_far(g, gi, coef);
+    group_far(g, gi, sh.coef);
+    const double cG[3] = {g.ncom[3 * GL], g.ncom[3 * GL + 1], g.ncom[3 * GL + 2]};
 
     // leaf boundaries of the group (leaf ranges are contiguous and ordered)
     int32_t lf[8];
@@ -145,85 +164,118 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
             if (lf[i] <= pa) la = i;
         const uint32_t bit = has_sink ? (1u << la) : 0u;
         const int64_t A = g.nleaf + gi * G + la;
-        const double cAx = g.ncom[3 * A], cAy = g.ncom[3 * A + 1], cAz = g.ncom[3 * A + 2];
-        if constexpr (!MIXED) {
-            const double xa = g.px[pa], ya = g.py[pa], za = g.pz[pa], ha = g.ph[pa];
-            double ax = 0.0, ay = 0.0, az = 0.0;
-            for (int64_t e = n0; e < n1; ++e) {
-                const uint64_t ent = g.gnear[e];
-                const int64_t B = (uint32_t)ent & 0x7fffffffu;
-                const int32_t fB = g.nfirst[B], cB = g.ncount[B];
-                if (!(((uint32_t)(ent >> 32)) & bit)) continue;
-                for (int32_t t0 = slice; t0 < cB; t0 += J) {
-                    const int64_t pb = (int64_t)fB + t0;
-                    const double vx = xa - g.px[pb], vy = ya - g.py[pb], vz = za - g.pz[pb];
-                    const double r2 = (vx * vx + vy * vy) + vz * vz;
-                    const double F = soft_F(r2, 0.5 * (ha + g.ph[pb])) * g.pm[pb];
-                    ax -= F * vx;
-                    ay -= F * vy;
-                    az -= F * vz;
-                }
-            }
-            for (int o = 1; o < J; o <<= 1) {
-                ax += __shfl_xor(ax, o, kWave);
-                ay += __shfl_xor(ay, o, kWave);
-                az += __shfl_xor(az, o, kWave);
-            }
-            if (has_sink && slice == 0) {
-                const double d[3] = {xa - cAx, ya - cAy, za - cAz};
-                double c[19];
-#pragma unroll
-                for (int q = 0; q < 19; ++q) c[q] = coef[la][q];
-                double out[3];
-                rcbfar::l2p<double>(c, d, out);
-                const int32_t o = g.pid[pa];
-                ((double *)g.ax)[o] = ax + out[0];
-                ((double *)g.ay)[o] = ay + out[1];
-                ((double *)g.az)[o] = az + out[2];
-            }
+        using T = typename std::conditional<MIXED, float, double>::type;
+        T xa, ya, za, ha;
+        if constexpr (MIXED) {
+            xa = (float)(g.ncom[3 * A] - cG[0]) + g.fdx[pa];
+            ya = (float)(g.ncom[3 * A + 1] - cG[1]) + g.fdy[pa];
+            za = (float)(g.ncom[3 * A + 2] - cG[2]) + g.fdz[pa];
+            ha = g.fh[pa];
         } else {
-            const float xa = g.fdx[pa], ya = g.fdy[pa], za = g.fdz[pa], ha = g.fh[pa];
-            float ax = 0.0f, ay = 0.0f, az = 0.0f;
-            for (int64_t e = n0; e < n1; ++e) {
-                const uint64_t ent = g.gnear[e];
-                const int64_t B = (uint32_t)ent & 0x7fffffffu;
-                const int32_t fB = g.nfirst[B], cB = g.ncount[B];
-                if (!(((uint32_t)(ent >> 32)) & bit)) continue;
-                const float bx = xa + (float)(cAx - g.ncom[3 * B]);
-                const float by = ya + (float)(cAy - g.ncom[3 * B + 1]);
-                const float bz = za + (float)(cAz - g.ncom[3 * B + 2]);
-                for (int32_t t0 = slice; t0 < cB; t0 += J) {
-                    const int64_t pb = (int64_t)fB + t0;
-                    const float vx = bx - g.fdx[pb], vy = by - g.fdy[pb], vz = bz - g.fdz[pb];
-                    const float r2 = (vx * vx + vy * vy) + vz * vz;
-                    const float F = soft_Ff(r2, 0.5f * (ha + g.fh[pb])) * g.fm[pb];
-                    ax -= F * vx;
-                    ay -= F * vy;
-                    az -= F * vz;
+            xa = g.px[pa];
+            ya = g.py[pa];
+            za = g.pz[pa];
+            ha = g.ph[pa];
+        }
+        T ax = 0, ay = 0, az = 0;
+        for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
+            const int tot = load_entry_chunk(g.gnear, g.nfirst, g.ncount, e0, n1, 0xffu, sh.ec);
+            for (int t = 0; t < tot; t += kWave) {
+                const int q = t + lane;
+                if (q < tot) {
+                    const int k = entry_of(sh.ec, q);
+                    const int64_t pb = (int64_t)sh.ec.fB[k] + (q - sh.ec.pos[k]);
+                    if constexpr (MIXED) {
+                        const int64_t B = sh.ec.label[k];
+                        SrcF s;
+                        s.x = (float)(g.ncom[3 * B] - cG[0]) + g.fdx[pb];
+                        s.y = (float)(g.ncom[3 * B + 1] - cG[1]) + g.fdy[pb];
+                        s.z = (float)(g.ncom[3 * B + 2] - cG[2]) + g.fdz[pb];
+                        s.m = g.fm[pb];
+                        s.h = g.fh[pb];
+                        s.mask = sh.ec.mask[k];
+                        sh.tile[lane] = s;
+                    } else {
+                        SrcD s;
+                        s.x = g.px[pb];
+                        s.y = g.py[pb];
+                        s.z = g.pz[pb];
+                        s.m = g.pm[pb];
+                        s.h = g.ph[pb];
+                        s.mask = sh.ec.mask[k];
+                        sh.tile[lane] = s;
+                    }
                 }
+                tile_sync();
+                const int nt = tot - t < kWave ? tot - t : kWave;
+                for (int u = slice; u < nt; u += J) {
+                    const auto s = sh.tile[u];
+                    if (s.mask & bit) {
+                        const T vx = xa - s.x, vy = ya - s.y, vz = za - s.z;
+                        const T r2 = (vx * vx + vy * vy) + vz * vz;
+                        T F;
+                        if constexpr (MIXED) F = soft_Ff(r2, 0.5f * (ha + s.h)) * s.m;
+                        else F = soft_F(r2, 0.5 * (ha + s.h)) * s.m;
+                        ax -= F * vx;
+                        ay -= F * vy;
+                        az -= F * vz;
+                    }
+                }
+                tile_sync();
             }
-            for (int o = 1; o < J; o <<= 1) {
-                ax += __shfl_xor(ax, o, kWave);
-                ay += __shfl_xor(ay, o, kWave);
-                az += __shfl_xor(az, o, kWave);
-            }
-            if (has_sink && slice == 0) {
-                const float d[3] = {xa, ya, za};
-                double c[19];
+        }
+        for (int o = 1; o < J; o <<= 1) {
+            ax += __shfl_xor(ax, o, kWave);
+            ay += __shfl_xor(ay, o, kWave);
+            az += __shfl_xor(az, o, kWave);
+        }
+        if (has_sink && slice == 0) {
+            double c[19];
 #pragma unroll
-                for (int q = 0; q < 19; ++q) c[q] = coef[la][q];
-                float out[3];
-                rcbfar::l2p<float>(c, d, out);
-                const int32_t o = g.pid[pa];
-                ((float *)g.ax)[o] = ax + out[0];
-                ((float *)g.ay)[o] = ay + out[1];
-                ((float *)g.az)[o] = az + out[2];
+            for (int q = 0; q < 19; ++q) c[q] = sh.coef[la][q];
+            T d[3], out[3];
+            if constexpr (MIXED) {
+                d[0] = g.fdx[pa];
+                d[1] = g.fdy[pa];
+                d[2] = g.fdz[pa];
+            } else {
+                d[0] = xa - g.ncom[3 * A];
+                d[1] = ya - g.ncom[3 * A + 1];
+                d[2] = za - g.ncom[3 * A + 2];
             }
+            rcbfar::l2p<T>(c, d, out);
+            const int32_t o = g.pid[pa];
+            ((T *)g.ax)[o] = ax + out[0];
+            ((T *)g.ay)[o] = ay + out[1];
+            ((T *)g.az)[o] = az + out[2];
         }
     }
 }
 
+// far-field coefficients of every leaf, stride doubles per leaf (first 19 used)
+__global__ __launch_bounds__(kBlock) void k_far_coeffs(GravArgs g, double *out, int stride) {
+    __shared__ double coef_all[kWaves][8][19];
+    double(*coef)[19] = coef_all[threadIdx.x / kWave];
+    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    if (gi >= g.ngroup) return;
+    const int G = 1 << g.gk;
+    group_far(g, gi, coef);
+    for (int i = lane_id(); i < G * 19; i += kWave) out[(gi * G + i / 19) * stride + i % 19] = coef[i / 19][i % 19];
+}
+
 }  // namespace
+
+rcb_status far_coefficients(rcb_tree *t, double *out, int stride, hipStream_t s) {
+    rcb_status st = ensure_walk(t, s);
+    if (st != RCB_OK) return st;
+    GravArgs g{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
+               t->gnear_off, t->gfar_off, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
+               t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, nullptr, nullptr, nullptr};
+    const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
+    k_far_coeffs<<<grid, kBlock, 0, s>>>(g, out, stride);
+    RCB_LAUNCH_CHECK("k_far_coeffs");
+    return RCB_OK;
+}
 
 rcb_status gravity(rcb_tree *t, void *ax, void *ay, void *az, hipStream_t s) {
     rcb_status st = ensure_walk(t, s);

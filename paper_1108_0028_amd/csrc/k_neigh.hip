@@ -4,14 +4,15 @@
 //
 // One wave per group of sibling leaves (k_walk.hip). Lanes are (sink slot
 // s, slice j) over the group's particles: S = the next power of two
-// >= min(n_group, 64) sinks, J = 64 / S slices. The wave runs through the
-// group's near list in ascending label order; for an entry whose candidate
-// mask holds the sink's leaf, slice j of sink s tests the particles
-// first_B + t J + j. A pair is a neighbour iff b != a and
-// |r_a - r_b|^2 < (2 h_a)^2 in FP64 on the tree's copy of the inputs (the
-// same predicate for every precision mode). Count mode writes per-particle
-// counts; fill mode writes ids at offsets[a] + rank, ranks taken by ballot
-// within the sink's lane segment so each list keeps tree order.
+// >= min(n_group, 64) sinks, J = 64 / S slices. The candidate cells of the
+// group's near list (ascending labels) are staged through LDS 64 particles at
+// a time (near_tile.h); slice j of sink s tests tile entries j, j + J, ...
+// whose candidate mask holds the sink's leaf. A pair is a neighbour iff
+// b != a and |r_a - r_b|^2 < (2 h_a)^2 in FP64 on the tree's copy of the
+// inputs (the same predicate for every precision mode). Count mode writes
+// per-particle counts; fill mode writes ids at offsets[a] + rank, ranks taken
+// by ballot within the sink's lane segment so each list keeps tree order.
+#include "near_tile.h"
 #include "rcb_internal.h"
 
 namespace rcb {
@@ -34,8 +35,21 @@ struct NeighArgs {
     int32_t *ids;
 };
 
+struct alignas(16) SrcN {
+    double x, y, z;
+    int32_t pb;
+    uint32_t mask;
+};
+
+struct NeighShared {
+    EntryChunk ec;
+    SrcN tile[kWave];
+};
+
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
+    __shared__ NeighShared sh_all[kWaves];
+    NeighShared &sh = sh_all[threadIdx.x / kWave];
     const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
     if (gi >= a.ngroup) return;
     const int lane = lane_id();
@@ -68,25 +82,41 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
         int64_t cnt = 0;
         int64_t obase = 0;
         if (FILL && has_sink) obase = a.offsets[a.pid[pa]];
-        for (int64_t e = n0; e < n1; ++e) {
-            const uint64_t ent = a.gnear[e];
-            const uint32_t masks = (uint32_t)(ent >> 32);
-            if (!(masks & 0xff00u)) continue;          // no candidate for any leaf
-            const int64_t B = (uint32_t)ent & 0x7fffffffu;
-            const bool mine = (masks & bit) != 0;
-            const int32_t fB = a.nfirst[B], cB = a.ncount[B];
-            for (int32_t t0 = 0; t0 < cB; t0 += J) {
-                const int32_t ob = t0 + slice;
-                const int32_t pb = fB + ob;
-                bool hit = false;
-                if (mine && ob < cB && pb != pa) hit = dist2(xa, ya, za, a.px[pb], a.py[pb], a.pz[pb]) < lim;
-                if (FILL) {
-                    const uint64_t bal = ballot(hit) & segmask;
-                    if (hit) a.ids[obase + cnt + rank_below(bal)] = a.pid[pb];
-                    cnt += __popcll(bal);
-                } else {
-                    cnt += hit;
+        for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
+            const int tot = load_entry_chunk(a.gnear, a.nfirst, a.ncount, e0, n1, 0xff00u, sh.ec);
+            for (int t = 0; t < tot; t += kWave) {
+                const int q = t + lane;
+                if (q < tot) {
+                    const int k = entry_of(sh.ec, q);
+                    const int32_t pb = sh.ec.fB[k] + (q - sh.ec.pos[k]);
+                    SrcN s;
+                    s.x = a.px[pb];
+                    s.y = a.py[pb];
+                    s.z = a.pz[pb];
+                    s.pb = pb;
+                    s.mask = sh.ec.mask[k];
+                    sh.tile[lane] = s;
                 }
+                tile_sync();
+                const int nt = tot - t < kWave ? tot - t : kWave;
+                for (int u0 = 0; u0 < nt; u0 += J) {
+                    const int u = u0 + slice;
+                    bool hit = false;
+                    int32_t pb = 0;
+                    if (u < nt) {
+                        const SrcN s = sh.tile[u];
+                        pb = s.pb;
+                        hit = (s.mask & bit) && pb != pa && dist2(xa, ya, za, s.x, s.y, s.z) < lim;
+                    }
+                    if (FILL) {
+                        const uint64_t bal = ballot(hit) & segmask;
+                        if (hit) a.ids[obase + cnt + rank_below(bal)] = a.pid[pb];
+                        cnt += __popcll(bal);
+                    } else {
+                        cnt += hit;
+                    }
+                }
+                tile_sync();
             }
         }
         if (!FILL) {

@@ -22,6 +22,7 @@
 // (dQ/dCOM = 0 because sum m d = 0).
 // Kernels: moments (per group) -> far (per group) -> near (per group) -> push.
 #include "far_math.h"
+#include "near_tile.h"
 #include "rcb_internal.h"
 
 namespace rcb {
@@ -140,99 +141,106 @@ __global__ __launch_bounds__(kBlock) void k_vjp_moments(VjpArgs a) {
         a.mom[(gi * G + i / kMom) * kMom + i % kMom] = acc[i / kMom][i % kMom];
 }
 
-// far field: per group, lanes = (far entry, leaf)
+// far field: per group, lanes = far entries; the group's leaves are taken in
+// turn with their centre of mass and cotangent moments held uniform, so each
+// lane sums its entry's node adjoint over the leaves that accepted it and
+// issues one set of atomics; the sink-centre term is summed per leaf.
 __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
     const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
     if (gi >= a.ngroup) return;
     const int lane = lane_id();
-    const int slot = lane >> 3, li = lane & 7;
     const int G = 1 << a.gk;
-    const int64_t leaf = gi * G + (li < G ? li : 0);
-    const int64_t A = a.nleaf + leaf;
-    const double cA[3] = {a.ncom[3 * A], a.ncom[3 * A + 1], a.ncom[3 * A + 2]};
-    rcbfar::SinkMoments Gm;
+    double cotl[8][3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) Gm.G0[q] = a.mom[leaf * kMom + q];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) Gm.G1[q] = a.mom[leaf * kMom + 3 + q];
-#pragma unroll
-    for (int q = 0; q < 18; ++q) Gm.G2[q] = a.mom[leaf * kMom + 12 + q];
-    rcbfar::sink_traces(Gm);
-    double c[19];
-#pragma unroll
-    for (int q = 0; q < 19; ++q) c[q] = 0.0;
-    double cot[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 8; ++i) cotl[i][0] = cotl[i][1] = cotl[i][2] = 0.0;
     const int64_t f0 = a.gfar_off[gi], f1 = a.gfar_off[gi + 1];
-    for (int64_t e0 = f0; e0 < f1; e0 += 8) {
-        const int64_t e = e0 + slot;
+    for (int64_t e0 = f0; e0 < f1; e0 += kWave) {
+        const int64_t e = e0 + lane;
         const uint64_t ent = e < f1 ? a.gfar[e] : 0ull;
-        const bool mine = (ent >> (32 + li)) & 1ull;
+        const uint32_t emask = (uint32_t)(ent >> 32) & 0xffu;
         const int64_t B = (uint32_t)ent & 0x7fffffffu;
+        double qq[6], cB[3], MB = 0.0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) qq[q] = 0.0;
+        cB[0] = cB[1] = cB[2] = 0.0;
+        if (emask) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) qq[q] = a.nQ[6 * B + q];
+            cB[0] = a.ncom[3 * B];
+            cB[1] = a.ncom[3 * B + 1];
+            cB[2] = a.ncom[3 * B + 2];
+            MB = a.nM[B];
+        }
         double ad[kAdj];
 #pragma unroll
         for (int q = 0; q < kAdj; ++q) ad[q] = 0.0;
-        if (mine) {
-            double qq[6];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) qq[q] = a.nQ[6 * B + q];
-            const double R[3] = {cA[0] - a.ncom[3 * B], cA[1] - a.ncom[3 * B + 1], cA[2] - a.ncom[3 * B + 2]};
-            const double MB = a.nM[B];
-            rcbfar::m2l_accumulate(R[0], R[1], R[2], MB, qq, c);
-            double rho[3], ct[3], aM, aQ[6];
-            rcbfar::far_pair_adjoint(R[0], R[1], R[2], MB, qq, Gm, rho, ct, aM, aQ);
-            ad[0] = aM;
+        for (int i = 0; i < 8; ++i) {
+            if (i >= G) break;
+            const bool mine = (emask >> i) & 1u;
+            if (ballot(mine) == 0) continue;
+            const int64_t leaf = gi * G + i;
+            const int64_t A = a.nleaf + leaf;
+            rcbfar::SinkMoments Gm;
 #pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                ad[1 + u] = -rho[u];
-                cot[u] += ct[u];
+            for (int q = 0; q < 3; ++q) Gm.G0[q] = a.mom[leaf * kMom + q];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) Gm.G1[q] = a.mom[leaf * kMom + 3 + q];
+#pragma unroll
+            for (int q = 0; q < 18; ++q) Gm.G2[q] = a.mom[leaf * kMom + 12 + q];
+            rcbfar::sink_traces(Gm);
+            double ct[3] = {0.0, 0.0, 0.0};
+            if (mine) {
+                double rho[3], aM, aQ[6];
+                rcbfar::far_pair_adjoint_cf(a.ncom[3 * A] - cB[0], a.ncom[3 * A + 1] - cB[1],
+                                            a.ncom[3 * A + 2] - cB[2], MB, qq, Gm, rho, ct, aM, aQ);
+                ad[0] += aM;
+#pragma unroll
+                for (int u = 0; u < 3; ++u) ad[1 + u] -= rho[u];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) ad[4 + q] += aQ[q];
             }
 #pragma unroll
-            for (int q = 0; q < 6; ++q) ad[4 + q] = aQ[q];
+            for (int u = 0; u < 3; ++u) cotl[i][u] += wave_sum(ct[u]);
         }
-        // sum over the 8 leaves of the entry, one set of atomics per entry
-#pragma unroll
-        for (int q = 0; q < kAdj; ++q) {
-            double v = ad[q];
-            v += __shfl_xor(v, 1, kWave);
-            v += __shfl_xor(v, 2, kWave);
-            v += __shfl_xor(v, 4, kWave);
-            ad[q] = v;
-        }
-        if (li == 0 && e < f1) {
+        if (emask) {
             double *dst = a.adj + kAdj * B;
 #pragma unroll
             for (int q = 0; q < kAdj; ++q) atomicAdd(dst + q, ad[q]);
         }
     }
-    // sum the leaf's lanes
+    if (lane < G) {
+        double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < 19; ++q) {
-        double v = c[q];
-        v += __shfl_xor(v, 8, kWave);
-        v += __shfl_xor(v, 16, kWave);
-        v += __shfl_xor(v, 32, kWave);
-        c[q] = v;
-    }
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-        double v = cot[u];
-        v += __shfl_xor(v, 8, kWave);
-        v += __shfl_xor(v, 16, kWave);
-        v += __shfl_xor(v, 32, kWave);
-        cot[u] = v;
-    }
-    if (slot == 0 && li < G) {
-        double *dst = a.leafc + leaf * kLeafC;
-#pragma unroll
-        for (int q = 0; q < 19; ++q) dst[q] = c[q];
-#pragma unroll
-        for (int u = 0; u < 3; ++u) dst[19 + u] = cot[u];
+        for (int i = 0; i < 8; ++i)
+            if (i == lane) {
+                v[0] = cotl[i][0];
+                v[1] = cotl[i][1];
+                v[2] = cotl[i][2];
+            }
+        double *dst = a.leafc + (gi * G + lane) * kLeafC;
+        dst[19] = v[0];
+        dst[20] = v[1];
+        dst[21] = v[2];
     }
 }
 
-// near field and the sink-side far terms: per group, lanes = (sink, slice)
+// near field and the sink-side far terms: per group, lanes = (sink, slice);
+// sources staged through LDS as in the forward kernel (near_tile.h).
+struct alignas(16) VSrc {
+    double x, y, z, m, h;
+    int32_t pb;
+    uint32_t mask;
+};
+struct VjpShared {
+    EntryChunk ec;
+    VSrc tile[kWave];
+};
+
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
+    __shared__ VjpShared sh_all[kWaves];
+    VjpShared &sh = sh_all[threadIdx.x / kWave];
     const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
     if (gi >= a.ngroup) return;
     const int lane = lane_id();
@@ -240,6 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
     const int64_t GL = (a.nleaf >> a.gk) + gi;
     const int32_t sG = a.nfirst[GL], nG = a.ncount[GL];
     if (nG == 0) return;
+    const double cG[3] = {a.ncom[3 * GL], a.ncom[3 * GL + 1], a.ncom[3 * GL + 2]};
     int32_t lf[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) lf[i] = i < G ? a.nfirst[a.nleaf + gi * G + i] : 0x7fffffff;
@@ -264,70 +273,104 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
             ga[1] = load_g<MIXED>(a.gy, oa);
             ga[2] = load_g<MIXED>(a.gz, oa);
         }
+        // sink in the group frame (mixed) or absolute (FP64)
+        double sx, sy, sz, sh_a;
+        if constexpr (MIXED) {
+            sx = (double)((float)(cA[0] - cG[0]) + a.fdx[pa]);
+            sy = (double)((float)(cA[1] - cG[1]) + a.fdy[pa]);
+            sz = (double)((float)(cA[2] - cG[2]) + a.fdz[pa]);
+            sh_a = a.fh[pa];
+        } else {
+            sx = a.px[pa];
+            sy = a.py[pa];
+            sz = a.pz[pa];
+            sh_a = a.ph[pa];
+        }
         double acc[3] = {0.0, 0.0, 0.0};
-        for (int64_t e = n0; e < n1; ++e) {
-            const uint64_t ent = a.gnear[e];
-            const int64_t B = (uint32_t)ent & 0x7fffffffu;
-            const bool mine = (((uint32_t)(ent >> 32)) & bit) != 0;
-            const int32_t fB = a.nfirst[B], cB = a.ncount[B];
-            float off[3] = {0.f, 0.f, 0.f};
-            if constexpr (MIXED) {
-                off[0] = (float)(cA[0] - a.ncom[3 * B]);
-                off[1] = (float)(cA[1] - a.ncom[3 * B + 1]);
-                off[2] = (float)(cA[2] - a.ncom[3 * B + 2]);
-            }
-            for (int32_t t0 = 0; t0 < cB; t0 += J) {
-                const int32_t ob = t0 + slice;
-                const bool valid = ob < cB;
-                const int32_t pb = fB + (valid ? ob : 0);
-                double s[4] = {0.0, 0.0, 0.0, 0.0};
-                if (mine && valid) {
-                    if constexpr (!MIXED) {
-                        const double v[3] = {a.px[pa] - a.px[pb], a.py[pa] - a.py[pb], a.pz[pa] - a.pz[pb]};
-                        const double r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
-                        double F, dFr;
-                        soft_FdF<double>(r2, 0.5 * (a.ph[pa] + a.ph[pb]), F, dFr);
-                        const double vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
-                        const double mb = a.pm[pb];
-#pragma unroll
-                        for (int u = 0; u < 3; ++u) {
-                            const double Kg = mb * (F * ga[u] + dFr * v[u] * vg);
-                            acc[u] -= Kg;
-                            s[u] = Kg;
-                        }
-                        s[3] = -F * vg;
+        for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
+            const int tot = load_entry_chunk(a.gnear, a.nfirst, a.ncount, e0, n1, 0xffu, sh.ec);
+            for (int t = 0; t < tot; t += kWave) {
+                const int q = t + lane;
+                if (q < tot) {
+                    const int k = entry_of(sh.ec, q);
+                    const int32_t pb = sh.ec.fB[k] + (q - sh.ec.pos[k]);
+                    VSrc s;
+                    if constexpr (MIXED) {
+                        const int64_t B = sh.ec.label[k];
+                        s.x = (double)((float)(a.ncom[3 * B] - cG[0]) + a.fdx[pb]);
+                        s.y = (double)((float)(a.ncom[3 * B + 1] - cG[1]) + a.fdy[pb]);
+                        s.z = (double)((float)(a.ncom[3 * B + 2] - cG[2]) + a.fdz[pb]);
+                        s.m = a.fm[pb];
+                        s.h = a.fh[pb];
                     } else {
-                        const float v[3] = {(a.fdx[pa] + off[0]) - a.fdx[pb], (a.fdy[pa] + off[1]) - a.fdy[pb],
-                                            (a.fdz[pa] + off[2]) - a.fdz[pb]};
-                        const float r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
-                        float F, dFr;
-                        soft_FdF<float>(r2, 0.5f * (a.fh[pa] + a.fh[pb]), F, dFr);
-                        const float gf[3] = {(float)ga[0], (float)ga[1], (float)ga[2]};
-                        const float vg = v[0] * gf[0] + v[1] * gf[1] + v[2] * gf[2];
-                        const float mb = a.fm[pb];
+                        s.x = a.px[pb];
+                        s.y = a.py[pb];
+                        s.z = a.pz[pb];
+                        s.m = a.pm[pb];
+                        s.h = a.ph[pb];
+                    }
+                    s.pb = pb;
+                    s.mask = sh.ec.mask[k];
+                    sh.tile[lane] = s;
+                }
+                tile_sync();
+                const int nt = tot - t < kWave ? tot - t : kWave;
+                for (int u0 = 0; u0 < nt; u0 += J) {
+                    const int u = u0 + slice;
+                    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+                    int32_t pb = 0;
+                    if (u < nt) {
+                        const VSrc src = sh.tile[u];
+                        pb = src.pb;
+                        if (src.mask & bit) {
+                            if constexpr (!MIXED) {
+                                const double v[3] = {sx - src.x, sy - src.y, sz - src.z};
+                                const double r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+                                double F, dFr;
+                                soft_FdF<double>(r2, 0.5 * (sh_a + src.h), F, dFr);
+                                const double vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
 #pragma unroll
-                        for (int u = 0; u < 3; ++u) {
-                            const float Kg = mb * (F * gf[u] + dFr * v[u] * vg);
-                            acc[u] -= (double)Kg;
-                            s[u] = (double)Kg;
+                                for (int c = 0; c < 3; ++c) {
+                                    const double Kg = src.m * (F * ga[c] + dFr * v[c] * vg);
+                                    acc[c] -= Kg;
+                                    s4[c] = Kg;
+                                }
+                                s4[3] = -F * vg;
+                            } else {
+                                const float v[3] = {(float)sx - (float)src.x, (float)sy - (float)src.y,
+                                                    (float)sz - (float)src.z};
+                                const float r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+                                float F, dFr;
+                                soft_FdF<float>(r2, 0.5f * ((float)sh_a + (float)src.h), F, dFr);
+                                const float gf[3] = {(float)ga[0], (float)ga[1], (float)ga[2]};
+                                const float vg = v[0] * gf[0] + v[1] * gf[1] + v[2] * gf[2];
+                                const float mb = (float)src.m;
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) {
+                                    const float Kg = mb * (F * gf[c] + dFr * v[c] * vg);
+                                    acc[c] -= (double)Kg;
+                                    s4[c] = (double)Kg;
+                                }
+                                s4[3] = (double)(-F * vg);
+                            }
                         }
-                        s[3] = (double)(-F * vg);
+                    }
+                    // sum the contributions of the wave's sinks to source pb
+                    for (int o = J; o < kWave; o <<= 1) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) s4[c] += __shfl_xor(s4[c], o, kWave);
+                    }
+                    if (sslot == 0 && u < nt && (s4[0] != 0.0 || s4[1] != 0.0 || s4[2] != 0.0 || s4[3] != 0.0)) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) atomicAdd(a.src + c * a.n + pb, s4[c]);
                     }
                 }
-                // sum the contributions of the wave's sinks to source pb
-                for (int o = J; o < kWave; o <<= 1) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) s[u] += __shfl_xor(s[u], o, kWave);
-                }
-                if (sslot == 0 && valid && (s[0] != 0.0 || s[1] != 0.0 || s[2] != 0.0 || s[3] != 0.0)) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) atomicAdd(a.src + u * a.n + pb, s[u]);
-                }
+                tile_sync();
             }
         }
         for (int o = 1; o < J; o <<= 1) {
 #pragma unroll
-            for (int u = 0; u < 3; ++u) acc[u] += __shfl_xor(acc[u], o, kWave);
+            for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], o, kWave);
         }
         if (has_sink && slice == 0) {
             const double *lc = a.leafc + (gi * G + la) * kLeafC;
@@ -428,6 +471,8 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     if (mixed) k_vjp_moments<true><<<gridg, kBlock, 0, s>>>(a);
     else k_vjp_moments<false><<<gridg, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_vjp_moments");
+    st = far_coefficients(t, leafc, kLeafC, s);
+    if (st != RCB_OK) return st;
     k_vjp_far<<<gridg, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_vjp_far");
     if (mixed) k_vjp_near<true><<<gridg, kBlock, 0, s>>>(a);

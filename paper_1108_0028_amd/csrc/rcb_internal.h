@@ -107,6 +107,8 @@ rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, in
                            hipStream_t s);
 // gravity (k_grav.hip)
 rcb_status gravity(rcb_tree *t, void *ax, void *ay, void *az, hipStream_t s);
+// far-field coefficients f, J, H (19 per leaf, at stride) of every leaf
+rcb_status far_coefficients(rcb_tree *t, double *out, int stride, hipStream_t s);
 // vjp (k_vjp.hip)
 rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *gz, void *dx,
                        void *dy, void *dz, void *dm, hipStream_t s);

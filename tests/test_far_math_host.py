@@ -27,6 +27,7 @@ def _shim():
     dp = C.POINTER(C.c_double)
     L.shim_m2l.argtypes = [C.c_double] * 4 + [dp, dp]
     L.shim_pair_adjoint.argtypes = [C.c_double] * 4 + [dp] * 8
+    L.shim_pair_adjoint_cf.argtypes = [C.c_double] * 4 + [dp] * 8
     L.shim_jidx.argtypes = [C.c_int, C.c_int]
     L.shim_hidx.argtypes = [C.c_int] * 3
     return L
@@ -69,8 +70,9 @@ def test_forward_m2l_matches_oracle(seed):
         assert c[9 + k] == pytest.approx(H[i, l, m], rel=1e-11, abs=1e-13 * np.abs(H).max())
 
 
+@pytest.mark.parametrize("form", ["shim_pair_adjoint", "shim_pair_adjoint_cf"])
 @pytest.mark.parametrize("seed", range(6))
-def test_pair_adjoint_matches_oracle_tensors(seed):
+def test_pair_adjoint_matches_oracle_tensors(seed, form):
     L = _shim()
     rng = np.random.default_rng(100 + seed)
     R = rng.normal(size=3) * 2.5
@@ -83,8 +85,8 @@ def test_pair_adjoint_matches_oracle_tensors(seed):
     G2 = 0.5 * (G2 + G2.transpose(0, 2, 1))   # symmetric in the last two indices
     G2u = np.array([[G2[i, l, m] for (l, m) in JI] for i in range(3)]).ravel()
     rho = np.zeros(3); cot = np.zeros(3); aM = np.zeros(1); aQ = np.zeros(6)
-    L.shim_pair_adjoint(R[0], R[1], R[2], M, _p(q), _p(G0), _p(np.ascontiguousarray(G1.ravel())),
-                        _p(G2u), _p(rho), _p(cot), _p(aM), _p(aQ))
+    getattr(L, form)(R[0], R[1], R[2], M, _p(q), _p(G0), _p(np.ascontiguousarray(G1.ravel())),
+                     _p(G2u), _p(rho), _p(cot), _p(aM), _p(aQ))
     f, J, H, T4 = O.far_coeffs(M, q, R, with_t4=True)
     g = [None] + [O.deriv_tensor(n, R) for n in range(1, 6)]
     rho_ref = (np.einsum("i,il->l", G0, J) + np.einsum("im,iml->l", G1, H)
