@@ -1,8 +1,9 @@
 """Build librcb.so (HIP, gfx950) in-tree with hipcc.
 
-Every kernel file is compiled with -ffp-contract=off: the build's canonical
-sums and the walk's predicates must round exactly like their definitions.
-Packed FP32 instructions are disabled.
+The build, walk and neighbour kernels are compiled with -ffp-contract=off:
+their canonical sums and predicates must round exactly like their
+definitions. The interaction kernels (gravity, VJP) allow multiply-add
+contraction. Packed FP32 instructions are disabled everywhere.
 """
 from __future__ import annotations
 
@@ -21,14 +22,16 @@ ARCH = os.environ.get("RCB_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["rcb_api.hip", "k_build.hip", "k_scan.hip", "k_walk.hip", "k_neigh.hip", "k_grav.hip",
            "k_vjp.hip"]
-FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-ffp-contract=off",
+CONTRACT = {"k_grav.hip": "-ffp-contract=fast", "k_vjp.hip": "-ffp-contract=fast"}
+FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result",
          "-I", INCLUDE, "-I", CSRC]
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, src.replace(".hip", ".o"))
-    cmd = ["hipcc", "-c", *FLAGS, "-o", obj, os.path.join(CSRC, src)]
+    cmd = ["hipcc", "-c", *FLAGS, CONTRACT.get(src, "-ffp-contract=off"), "-o", obj,
+           os.path.join(CSRC, src)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -35,6 +35,31 @@
 
 namespace rcbfar {
 
+// 1/sqrt(x) and 1/x in FP64: the hardware estimates refined by two Newton
+// steps on the device (the estimate's error squares each step); the plain
+// expressions on the host.
+RCB_HD double rsqrt64(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * (1.5 - h * y * y);
+    y = y * (1.5 - h * y * y);
+    return y;
+#else
+    return 1.0 / sqrt(x);
+#endif
+}
+RCB_HD double rcp64(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rcp(x);
+    y = y * (2.0 - x * y);
+    y = y * (2.0 - x * y);
+    return y;
+#else
+    return 1.0 / x;
+#endif
+}
+
 RCB_HD constexpr int jidx(int i, int l) {
     // (00)(01)(02)(11)(12)(22)
     return (i < l ? i : l) == 0 ? (i < l ? l : i) : ((i < l ? i : l) == 1 ? 2 + (i < l ? l : i) : 5);
@@ -51,7 +76,7 @@ RCB_HD constexpr int hidx(int i, int l, int m) {
 // f (0..2), J (3..8, jidx), H (9..18, hidx) of one source, accumulated.
 RCB_HD void m2l_accumulate(double x, double y, double z, double M, const double qq[6], double (&c)[19]) {
     const double r2 = (x * x + y * y) + z * z;
-    const double rinv = 1.0 / sqrt(r2);
+    const double rinv = rsqrt64(r2);
     const double rinv2 = rinv * rinv;
     const double D1 = -rinv * rinv2;
     const double D2 = -3.0 * D1 * rinv2;
@@ -263,7 +288,7 @@ RCB_HD void far_pair_adjoint_cf(double x, double y, double z, double M, const do
                                 double adjQ[6]) {
     const double X[3] = {x, y, z};
     const double r2 = (x * x + y * y) + z * z;
-    const double ri = 1.0 / sqrt(r2);
+    const double ri = rsqrt64(r2);
     const double ri2 = ri * ri;
     const double D1 = -ri * ri2;
     const double D2 = -3.0 * D1 * ri2;

@@ -278,38 +278,36 @@ struct PartOut {
     int32_t *id;
 };
 
-// Stable partition of the elements [base, end) held 8-per-lane; `lb` is the
-// number of left elements before base within the node, `rb` the right ones.
+// Stable partition of the elements [base, end): `lb` left and `rb` right
+// elements of the node precede base. Elements are taken 64 at a time in
+// order (lane l holds base + 64 t + l), ranks come from ballots, so the
+// stores of a side are contiguous across lanes.
 __device__ __forceinline__ void scatter_chunk(const PartIn &in, const int32_t *__restrict__ id,
                                               const PartOut &out, int64_t base, int64_t end,
                                               int ax, double plane, int64_t node_first,
                                               int64_t nleft_total, int64_t lb, int64_t rb) {
-    const int64_t p0 = base + 8 * (int64_t)lane_id();
     const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
-    bool left[8];
-    int nl = 0, nv = 0;
+    const int l = lane_id();
+    int64_t rl = lb, rr = rb;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-        const int64_t i = p0 + t;
+        const int64_t i = base + 64 * t + l;
         const bool valid = i < end;
-        left[t] = valid && (xa[i] < plane);
-        nl += left[t];
-        nv += valid;
-    }
-    const int el = wave_excl_scan(nl);
-    const int ev = wave_excl_scan(nv);
-    int rl = lb + el, rr = rb + (ev - el);
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const int64_t i = p0 + t;
-        if (i < end) {
-            const int64_t dst = left[t] ? node_first + (rl++) : node_first + nleft_total + (rr++);
+        const bool left = valid && (xa[i] < plane);
+        const uint64_t bl = ballot(left);
+        const int nl = __popcll(bl);
+        const int nv = (int)min<int64_t>(64, max<int64_t>(0, end - (base + 64 * t)));
+        if (valid) {
+            const int rk = rank_below(bl);
+            const int64_t dst = left ? node_first + rl + rk : node_first + nleft_total + rr + (l - rk);
             out.x[dst] = in.x[i];
             out.y[dst] = in.y[i];
             out.z[dst] = in.z[i];
             out.m[dst] = in.m[i];
             out.id[dst] = id[i];
         }
+        rl += nl;
+        rr += nv - nl;
     }
 }
 

@@ -35,9 +35,9 @@ using rcbfar::m2l_accumulate;
 
 // F = S(q)/r of the cubic-spline softening
 __device__ __forceinline__ double soft_F(double r2, double hab) {
-    const double rinv = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
+    const double rinv = r2 > 0.0 ? rcbfar::rsqrt64(r2) : 0.0;
     const double r = r2 * rinv;
-    const double hinv = 1.0 / hab;
+    const double hinv = rcbfar::rcp64(hab);
     const double q = r * hinv;
     const double h3 = hinv * hinv * hinv;
     const double r3 = rinv * rinv * rinv;

@@ -39,9 +39,15 @@ using rcbfar::jidx;
 
 template <typename T>
 __device__ __forceinline__ void soft_FdF(T r2, T hab, T &F, T &dFr) {
-    const T rinv = r2 > (T)0 ? (T)1 / sqrt(r2) : (T)0;
+    T rinv, hinv;
+    if constexpr (sizeof(T) == 8) {
+        rinv = r2 > (T)0 ? rcbfar::rsqrt64(r2) : (T)0;
+        hinv = rcbfar::rcp64(hab);
+    } else {
+        rinv = r2 > (T)0 ? __frsqrt_rn(r2) : (T)0;
+        hinv = __frcp_rn(hab);
+    }
     const T r = r2 * rinv;
-    const T hinv = (T)1 / hab;
     const T q = r * hinv;
     const T h2 = hinv * hinv;
     const T h3 = h2 * hinv;
@@ -144,15 +150,16 @@ __global__ __launch_bounds__(kBlock) void k_vjp_moments(VjpArgs a) {
 // far field: per group, lanes = far entries; the group's leaves are taken in
 // turn with their centre of mass and cotangent moments held uniform, so each
 // lane sums its entry's node adjoint over the leaves that accepted it and
-// issues one set of atomics; the sink-centre term is summed per leaf.
+// issues one set of atomics; the sink-centre term is summed per leaf (LDS).
 __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
+    __shared__ double cot_all[kWaves][8][3];
+    double(*cotl)[3] = cot_all[threadIdx.x / kWave];
     const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
     if (gi >= a.ngroup) return;
     const int lane = lane_id();
     const int G = 1 << a.gk;
-    double cotl[8][3];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) cotl[i][0] = cotl[i][1] = cotl[i][2] = 0.0;
+    if (lane < 24) cotl[lane / 3][lane % 3] = 0.0;
+    tile_sync();
     const int64_t f0 = a.gfar_off[gi], f1 = a.gfar_off[gi + 1];
     for (int64_t e0 = f0; e0 < f1; e0 += kWave) {
         const int64_t e = e0 + lane;
@@ -174,9 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
         double ad[kAdj];
 #pragma unroll
         for (int q = 0; q < kAdj; ++q) ad[q] = 0.0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            if (i >= G) break;
+        for (int i = 0; i < G; ++i) {
             const bool mine = (emask >> i) & 1u;
             if (ballot(mine) == 0) continue;
             const int64_t leaf = gi * G + i;
@@ -201,7 +206,10 @@ __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
                 for (int q = 0; q < 6; ++q) ad[4 + q] += aQ[q];
             }
 #pragma unroll
-            for (int u = 0; u < 3; ++u) cotl[i][u] += wave_sum(ct[u]);
+            for (int u = 0; u < 3; ++u) {
+                const double v = wave_sum(ct[u]);
+                if (lane == 0) cotl[i][u] += v;
+            }
         }
         if (emask) {
             double *dst = a.adj + kAdj * B;
@@ -209,38 +217,37 @@ __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
             for (int q = 0; q < kAdj; ++q) atomicAdd(dst + q, ad[q]);
         }
     }
-    if (lane < G) {
-        double v[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-            if (i == lane) {
-                v[0] = cotl[i][0];
-                v[1] = cotl[i][1];
-                v[2] = cotl[i][2];
-            }
-        double *dst = a.leafc + (gi * G + lane) * kLeafC;
-        dst[19] = v[0];
-        dst[20] = v[1];
-        dst[21] = v[2];
+    tile_sync();
+    if (lane < 3 * G) {
+        const int i = lane / 3, u = lane % 3;
+        a.leafc[(gi * G + i) * kLeafC + 19 + u] = cotl[i][u];
     }
 }
 
-// near field and the sink-side far terms: per group, lanes = (sink, slice);
-// sources staged through LDS as in the forward kernel (near_tile.h).
-struct alignas(16) VSrc {
-    double x, y, z, m, h;
-    int32_t pb;
-    uint32_t mask;
+// near field and the sink-side far terms: per group, one sink per lane.
+// Sources are staged 64 at a time in LDS (near_tile.h); lane j visits the
+// tile in the rotated order (j + u) mod 64, so at each step the 64 lanes
+// touch 64 different sources and the source-side terms are summed with LDS
+// atomics without conflicts; each tile's sums then go out with one set of
+// FP64 atomics per source.
+template <typename T>
+struct VjpTile {
+    T x[kWave], y[kWave], z[kWave], m[kWave], h[kWave];
+    int32_t pb[kWave];
+    uint32_t mask[kWave];
+    double acc[4][kWave];
 };
+template <typename T>
 struct VjpShared {
     EntryChunk ec;
-    VSrc tile[kWave];
+    VjpTile<T> t;
 };
 
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
-    __shared__ VjpShared sh_all[kWaves];
-    VjpShared &sh = sh_all[threadIdx.x / kWave];
+    using T = typename std::conditional<MIXED, float, double>::type;
+    __shared__ VjpShared<T> sh_all[kWaves];
+    VjpShared<T> &sh = sh_all[threadIdx.x / kWave];
     const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
     if (gi >= a.ngroup) return;
     const int lane = lane_id();
@@ -252,14 +259,9 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
     int32_t lf[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) lf[i] = i < G ? a.nfirst[a.nleaf + gi * G + i] : 0x7fffffff;
-    int S = 1;
-    while (S < nG && S < kWave) S <<= 1;
-    const int J = kWave / S;
-    const int sslot = lane / J;
-    const int slice = lane % J;
     const int64_t n0 = a.gnear_off[gi], n1 = a.gnear_off[gi + 1];
-    for (int g0 = 0; g0 < nG; g0 += S) {
-        const int si = g0 + sslot;
+    for (int g0 = 0; g0 < nG; g0 += kWave) {
+        const int si = g0 + lane;
         const bool has_sink = si < nG;
         const int32_t pa = sG + (has_sink ? si : 0);
         const int la = leaf_slot(lf, pa);
@@ -267,24 +269,27 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
         const int64_t A = a.nleaf + gi * G + la;
         const double cA[3] = {a.ncom[3 * A], a.ncom[3 * A + 1], a.ncom[3 * A + 2]};
         const int32_t oa = a.pid[pa];
-        double ga[3] = {0.0, 0.0, 0.0};
+        T ga[3] = {(T)0, (T)0, (T)0};
+        double gd[3] = {0.0, 0.0, 0.0};
         if (has_sink) {
-            ga[0] = load_g<MIXED>(a.gx, oa);
-            ga[1] = load_g<MIXED>(a.gy, oa);
-            ga[2] = load_g<MIXED>(a.gz, oa);
+            gd[0] = load_g<MIXED>(a.gx, oa);
+            gd[1] = load_g<MIXED>(a.gy, oa);
+            gd[2] = load_g<MIXED>(a.gz, oa);
+            ga[0] = (T)gd[0];
+            ga[1] = (T)gd[1];
+            ga[2] = (T)gd[2];
         }
-        // sink in the group frame (mixed) or absolute (FP64)
-        double sx, sy, sz, sh_a;
+        T sx, sy, sz, ha;
         if constexpr (MIXED) {
-            sx = (double)((float)(cA[0] - cG[0]) + a.fdx[pa]);
-            sy = (double)((float)(cA[1] - cG[1]) + a.fdy[pa]);
-            sz = (double)((float)(cA[2] - cG[2]) + a.fdz[pa]);
-            sh_a = a.fh[pa];
+            sx = (float)(cA[0] - cG[0]) + a.fdx[pa];
+            sy = (float)(cA[1] - cG[1]) + a.fdy[pa];
+            sz = (float)(cA[2] - cG[2]) + a.fdz[pa];
+            ha = a.fh[pa];
         } else {
             sx = a.px[pa];
             sy = a.py[pa];
             sz = a.pz[pa];
-            sh_a = a.ph[pa];
+            ha = a.ph[pa];
         }
         double acc[3] = {0.0, 0.0, 0.0};
         for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
@@ -294,85 +299,61 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
                 if (q < tot) {
                     const int k = entry_of(sh.ec, q);
                     const int32_t pb = sh.ec.fB[k] + (q - sh.ec.pos[k]);
-                    VSrc s;
                     if constexpr (MIXED) {
                         const int64_t B = sh.ec.label[k];
-                        s.x = (double)((float)(a.ncom[3 * B] - cG[0]) + a.fdx[pb]);
-                        s.y = (double)((float)(a.ncom[3 * B + 1] - cG[1]) + a.fdy[pb]);
-                        s.z = (double)((float)(a.ncom[3 * B + 2] - cG[2]) + a.fdz[pb]);
-                        s.m = a.fm[pb];
-                        s.h = a.fh[pb];
+                        sh.t.x[lane] = (float)(a.ncom[3 * B] - cG[0]) + a.fdx[pb];
+                        sh.t.y[lane] = (float)(a.ncom[3 * B + 1] - cG[1]) + a.fdy[pb];
+                        sh.t.z[lane] = (float)(a.ncom[3 * B + 2] - cG[2]) + a.fdz[pb];
+                        sh.t.m[lane] = a.fm[pb];
+                        sh.t.h[lane] = a.fh[pb];
                     } else {
-                        s.x = a.px[pb];
-                        s.y = a.py[pb];
-                        s.z = a.pz[pb];
-                        s.m = a.pm[pb];
-                        s.h = a.ph[pb];
+                        sh.t.x[lane] = a.px[pb];
+                        sh.t.y[lane] = a.py[pb];
+                        sh.t.z[lane] = a.pz[pb];
+                        sh.t.m[lane] = a.pm[pb];
+                        sh.t.h[lane] = a.ph[pb];
                     }
-                    s.pb = pb;
-                    s.mask = sh.ec.mask[k];
-                    sh.tile[lane] = s;
+                    sh.t.pb[lane] = pb;
+                    sh.t.mask[lane] = sh.ec.mask[k];
                 }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sh.t.acc[c][lane] = 0.0;
                 tile_sync();
                 const int nt = tot - t < kWave ? tot - t : kWave;
-                for (int u0 = 0; u0 < nt; u0 += J) {
-                    const int u = u0 + slice;
-                    double s4[4] = {0.0, 0.0, 0.0, 0.0};
-                    int32_t pb = 0;
-                    if (u < nt) {
-                        const VSrc src = sh.tile[u];
-                        pb = src.pb;
-                        if (src.mask & bit) {
-                            if constexpr (!MIXED) {
-                                const double v[3] = {sx - src.x, sy - src.y, sz - src.z};
-                                const double r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
-                                double F, dFr;
-                                soft_FdF<double>(r2, 0.5 * (sh_a + src.h), F, dFr);
-                                const double vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
+                for (int u = 0; u < kWave; ++u) {
+                    const int j = (lane + u) & (kWave - 1);
+                    if (j < nt && (sh.t.mask[j] & bit)) {
+                        const T v[3] = {sx - sh.t.x[j], sy - sh.t.y[j], sz - sh.t.z[j]};
+                        const T r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+                        T F, dFr;
+                        soft_FdF<T>(r2, (T)0.5 * (ha + sh.t.h[j]), F, dFr);
+                        const T vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
+                        const T mb = sh.t.m[j];
 #pragma unroll
-                                for (int c = 0; c < 3; ++c) {
-                                    const double Kg = src.m * (F * ga[c] + dFr * v[c] * vg);
-                                    acc[c] -= Kg;
-                                    s4[c] = Kg;
-                                }
-                                s4[3] = -F * vg;
-                            } else {
-                                const float v[3] = {(float)sx - (float)src.x, (float)sy - (float)src.y,
-                                                    (float)sz - (float)src.z};
-                                const float r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
-                                float F, dFr;
-                                soft_FdF<float>(r2, 0.5f * ((float)sh_a + (float)src.h), F, dFr);
-                                const float gf[3] = {(float)ga[0], (float)ga[1], (float)ga[2]};
-                                const float vg = v[0] * gf[0] + v[1] * gf[1] + v[2] * gf[2];
-                                const float mb = (float)src.m;
-#pragma unroll
-                                for (int c = 0; c < 3; ++c) {
-                                    const float Kg = mb * (F * gf[c] + dFr * v[c] * vg);
-                                    acc[c] -= (double)Kg;
-                                    s4[c] = (double)Kg;
-                                }
-                                s4[3] = (double)(-F * vg);
-                            }
+                        for (int c = 0; c < 3; ++c) {
+                            const T Kg = mb * (F * ga[c] + dFr * v[c] * vg);
+                            acc[c] -= (double)Kg;
+                            atomicAdd(&sh.t.acc[c][j], (double)Kg);
                         }
+                        atomicAdd(&sh.t.acc[3][j], (double)(-F * vg));
                     }
-                    // sum the contributions of the wave's sinks to source pb
-                    for (int o = J; o < kWave; o <<= 1) {
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) s4[c] += __shfl_xor(s4[c], o, kWave);
-                    }
-                    if (sslot == 0 && u < nt && (s4[0] != 0.0 || s4[1] != 0.0 || s4[2] != 0.0 || s4[3] != 0.0)) {
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) atomicAdd(a.src + c * a.n + pb, s4[c]);
+                }
+                tile_sync();
+                if (lane < nt) {
+                    const double s0 = sh.t.acc[0][lane], s1 = sh.t.acc[1][lane], s2 = sh.t.acc[2][lane],
+                                 s3 = sh.t.acc[3][lane];
+                    if (s0 != 0.0 || s1 != 0.0 || s2 != 0.0 || s3 != 0.0) {
+                        const int32_t pb = sh.t.pb[lane];
+                        atomicAdd(a.src + pb, s0);
+                        atomicAdd(a.src + a.n + pb, s1);
+                        atomicAdd(a.src + 2 * a.n + pb, s2);
+                        atomicAdd(a.src + 3 * a.n + pb, s3);
                     }
                 }
                 tile_sync();
             }
         }
-        for (int o = 1; o < J; o <<= 1) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], o, kWave);
-        }
-        if (has_sink && slice == 0) {
+        if (has_sink) {
             const double *lc = a.leafc + (gi * G + la) * kLeafC;
             const double d[3] = {a.px[pa] - cA[0], a.py[pa] - cA[1], a.pz[pa] - cA[2]};
             const double ma = a.pm[pa];
@@ -384,9 +365,9 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
                 double v = acc[l] + ma / MA * cot[l];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    v += ga[i] * lc[3 + jidx(i, l)];
+                    v += gd[i] * lc[3 + jidx(i, l)];
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) v += ga[i] * lc[9 + hidx(i, l, m)] * d[m];
+                    for (int m = 0; m < 3; ++m) v += gd[i] * lc[9 + hidx(i, l, m)] * d[m];
                 }
                 out[l] = v;
             }
