@@ -55,6 +55,8 @@ def _args():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-leaves", type=int, default=2048)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration for profiles)")
     return ap.parse_args()
 
 
@@ -102,6 +104,12 @@ def main():
         kern_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
         return (t1 - t0) / steps, kern_ms
 
+    if a.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     sec, grav_ms = timed(a.precision, a.steps, a.warmup)
     value = n / sec
 

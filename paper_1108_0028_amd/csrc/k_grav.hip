@@ -9,16 +9,17 @@
 //        accepted B (mask bit), accumulating f_i, J_il, H_ilm of Eq. 5's field
 //        (far_math.h). B's record is loaded once for the 8 leaves. Lanes of
 //        the same leaf are summed at the end; coefficients go to LDS.
-//  near: lanes are (sink slot, slice) over the group's particles (contiguous
-//        in tree order). Sources are staged 64 at a time in LDS (near_tile.h);
-//        slice j of sink a takes tile entries j, j + J, ... whose near mask
-//        has a's leaf: a_a -= m_b F(r, h_ab) (r_a - r_b), F = S(q)/r
-//        (Sec. 2.4.3).
+//  near: the group's leaves in turn. Lanes are (sink slot, slice) over the
+//        leaf's particles (near_tile.h: S = min(c, 64) sinks, J = 64 / S
+//        slices). The cells of the group's near list whose mask has the leaf
+//        are staged 64 sources at a time in LDS; slice j of a sink takes tile
+//        entries j, j + J, ...: a_a -= m_b F(r, h_ab) (r_a - r_b),
+//        F = S(q)/r (Sec. 2.4.3); the slices are summed at the end.
 //  L2P:  a_a += f + J d + H[d, d] / 2,  d = r_a - com_A  (Eq. 6).
-// FP64 form: everything in FP64. Mixed form: FP32 offsets from the leaf
-// centre of mass are moved into the group's frame by adding the FP64 offset
-// com_leaf - com_group rounded to FP32; pairs, accumulation and L2P in FP32;
-// M2L in FP64.
+// FP64 form: everything in FP64. Mixed form: the sink leaf's frame. Sinks
+// are their FP32 offsets from the leaf centre of mass; a source of cell B is
+// its FP32 offset plus the FP64 difference com_B - com_A rounded to FP32;
+// pairs, accumulation and L2P in FP32; M2L in FP64.
 #include "far_math.h"
 #include "near_tile.h"
 #include "rcb_internal.h"
@@ -116,11 +117,9 @@ __device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, double 
 
 struct alignas(16) SrcF {
     float x, y, z, m, h;
-    uint32_t mask;
 };
 struct alignas(16) SrcD {
     double x, y, z, m, h;
-    uint32_t mask;
 };
 
 template <bool MIXED>
@@ -132,6 +131,7 @@ struct GravShared {
 
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
+    using T = typename std::conditional<MIXED, float, double>::type;
     __shared__ GravShared<MIXED> sh_all[kWaves];
     GravShared<MIXED> &sh = sh_all[threadIdx.x / kWave];
     const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
@@ -139,78 +139,62 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
     const int lane = lane_id();
     const int G = 1 << g.gk;
     const int64_t GL = (g.nleaf >> g.gk) + gi;   // group node label
-    const int32_t sG = g.nfirst[GL], nG = g.ncount[GL];
-    if (nG == 0) return;
+    if (g.ncount[GL] == 0) return;
     group_far(g, gi, sh.coef);
-    const double cG[3] = {g.ncom[3 * GL], g.ncom[3 * GL + 1], g.ncom[3 * GL + 2]};
-
-    // leaf boundaries of the group (leaf ranges are contiguous and ordered)
-    int32_t lf[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) lf[i] = i < G ? g.nfirst[g.nleaf + gi * G + i] : 0x7fffffff;
-    int S = 1;
-    while (S < nG && S < kWave) S <<= 1;
-    const int J = kWave / S;
-    const int sslot = lane / J;
-    const int slice = lane % J;
     const int64_t n0 = g.gnear_off[gi], n1 = g.gnear_off[gi + 1];
-    for (int g0 = 0; g0 < nG; g0 += S) {
-        const int si = g0 + sslot;
-        const bool has_sink = si < nG;
-        const int32_t pa = sG + (has_sink ? si : 0);
-        int la = 0;
-#pragma unroll
-        for (int i = 1; i < 8; ++i)
-            if (lf[i] <= pa) la = i;
-        const uint32_t bit = has_sink ? (1u << la) : 0u;
-        const int64_t A = g.nleaf + gi * G + la;
-        using T = typename std::conditional<MIXED, float, double>::type;
-        T xa, ya, za, ha;
-        if constexpr (MIXED) {
-            xa = (float)(g.ncom[3 * A] - cG[0]) + g.fdx[pa];
-            ya = (float)(g.ncom[3 * A + 1] - cG[1]) + g.fdy[pa];
-            za = (float)(g.ncom[3 * A + 2] - cG[2]) + g.fdz[pa];
-            ha = g.fh[pa];
-        } else {
-            xa = g.px[pa];
-            ya = g.py[pa];
-            za = g.pz[pa];
-            ha = g.ph[pa];
-        }
-        T ax = 0, ay = 0, az = 0;
-        for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
-            const int tot = load_entry_chunk(g.gnear, g.nfirst, g.ncount, e0, n1, 0xffu, sh.ec);
-            for (int t = 0; t < tot; t += kWave) {
-                const int q = t + lane;
-                if (q < tot) {
-                    const int k = entry_of(sh.ec, q);
-                    const int64_t pb = (int64_t)sh.ec.fB[k] + (q - sh.ec.pos[k]);
-                    if constexpr (MIXED) {
-                        const int64_t B = sh.ec.label[k];
-                        SrcF s;
-                        s.x = (float)(g.ncom[3 * B] - cG[0]) + g.fdx[pb];
-                        s.y = (float)(g.ncom[3 * B + 1] - cG[1]) + g.fdy[pb];
-                        s.z = (float)(g.ncom[3 * B + 2] - cG[2]) + g.fdz[pb];
-                        s.m = g.fm[pb];
-                        s.h = g.fh[pb];
-                        s.mask = sh.ec.mask[k];
-                        sh.tile[lane] = s;
-                    } else {
-                        SrcD s;
-                        s.x = g.px[pb];
-                        s.y = g.py[pb];
-                        s.z = g.pz[pb];
-                        s.m = g.pm[pb];
-                        s.h = g.ph[pb];
-                        s.mask = sh.ec.mask[k];
-                        sh.tile[lane] = s;
+    for (int li = 0; li < G; ++li) {
+        const int64_t A = g.nleaf + gi * G + li;
+        const int32_t sA = g.nfirst[A], c = g.ncount[A];
+        if (c == 0) continue;
+        const LeafLanes L = leaf_lanes(c);
+        const double cA[3] = {g.ncom[3 * A], g.ncom[3 * A + 1], g.ncom[3 * A + 2]};
+        for (int g0 = 0; g0 < c; g0 += L.S) {
+            const int si = g0 + L.sslot;
+            const bool has_sink = L.sslot < L.S && si < c;
+            const int32_t pa = sA + (has_sink ? si : 0);
+            T xa, ya, za, ha;
+            if constexpr (MIXED) {   // leaf frame
+                xa = g.fdx[pa];
+                ya = g.fdy[pa];
+                za = g.fdz[pa];
+                ha = g.fh[pa];
+            } else {
+                xa = g.px[pa];
+                ya = g.py[pa];
+                za = g.pz[pa];
+                ha = g.ph[pa];
+            }
+            T ax = 0, ay = 0, az = 0;
+            for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
+                const int tot = load_entry_chunk(g.gnear, g.nfirst, g.ncount, e0, n1, 1u << li, sh.ec);
+                for (int t = 0; t < tot; t += kWave) {
+                    const int q = t + lane;
+                    if (q < tot) {
+                        const int k = entry_of(sh.ec, q);
+                        const int64_t pb = (int64_t)sh.ec.fB[k] + (q - sh.ec.pos[k]);
+                        if constexpr (MIXED) {
+                            const int64_t B = sh.ec.label[k];
+                            SrcF s;
+                            s.x = (float)(g.ncom[3 * B] - cA[0]) + g.fdx[pb];
+                            s.y = (float)(g.ncom[3 * B + 1] - cA[1]) + g.fdy[pb];
+                            s.z = (float)(g.ncom[3 * B + 2] - cA[2]) + g.fdz[pb];
+                            s.m = g.fm[pb];
+                            s.h = g.fh[pb];
+                            sh.tile[lane] = s;
+                        } else {
+                            SrcD s;
+                            s.x = g.px[pb];
+                            s.y = g.py[pb];
+                            s.z = g.pz[pb];
+                            s.m = g.pm[pb];
+                            s.h = g.ph[pb];
+                            sh.tile[lane] = s;
+                        }
                     }
-                }
-                tile_sync();
-                const int nt = tot - t < kWave ? tot - t : kWave;
-                for (int u = slice; u < nt; u += J) {
-                    const auto s = sh.tile[u];
-                    if (s.mask & bit) {
+                    tile_sync();
+                    const int nt = tot - t < kWave ? tot - t : kWave;
+                    for (int u = L.slice; u < nt; u += L.J) {
+                        const auto s = sh.tile[u];
                         const T vx = xa - s.x, vy = ya - s.y, vz = za - s.z;
                         const T r2 = (vx * vx + vy * vy) + vz * vz;
                         T F;
@@ -220,34 +204,32 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
                         ay -= F * vy;
                         az -= F * vz;
                     }
+                    tile_sync();
                 }
-                tile_sync();
             }
-        }
-        for (int o = 1; o < J; o <<= 1) {
-            ax += __shfl_xor(ax, o, kWave);
-            ay += __shfl_xor(ay, o, kWave);
-            az += __shfl_xor(az, o, kWave);
-        }
-        if (has_sink && slice == 0) {
-            double c[19];
+            ax = seg_sum(ax, L.slice, L.J);
+            ay = seg_sum(ay, L.slice, L.J);
+            az = seg_sum(az, L.slice, L.J);
+            if (has_sink && L.slice == 0) {
+                double c19[19];
 #pragma unroll
-            for (int q = 0; q < 19; ++q) c[q] = sh.coef[la][q];
-            T d[3], out[3];
-            if constexpr (MIXED) {
-                d[0] = g.fdx[pa];
-                d[1] = g.fdy[pa];
-                d[2] = g.fdz[pa];
-            } else {
-                d[0] = xa - g.ncom[3 * A];
-                d[1] = ya - g.ncom[3 * A + 1];
-                d[2] = za - g.ncom[3 * A + 2];
+                for (int q = 0; q < 19; ++q) c19[q] = sh.coef[li][q];
+                T d[3], out[3];
+                if constexpr (MIXED) {
+                    d[0] = xa;
+                    d[1] = ya;
+                    d[2] = za;
+                } else {
+                    d[0] = xa - cA[0];
+                    d[1] = ya - cA[1];
+                    d[2] = za - cA[2];
+                }
+                rcbfar::l2p<T>(c19, d, out);
+                const int32_t o = g.pid[pa];
+                ((T *)g.ax)[o] = ax + out[0];
+                ((T *)g.ay)[o] = ay + out[1];
+                ((T *)g.az)[o] = az + out[2];
             }
-            rcbfar::l2p<T>(c, d, out);
-            const int32_t o = g.pid[pa];
-            ((T *)g.ax)[o] = ax + out[0];
-            ((T *)g.ay)[o] = ay + out[1];
-            ((T *)g.az)[o] = az + out[2];
         }
     }
 }

@@ -2,16 +2,17 @@
 // (Sec. 2.3: "Neighbour walk" culled to the true neighbours, and the
 // one-dimensional "Neighbour list").
 //
-// One wave per group of sibling leaves (k_walk.hip). Lanes are (sink slot
-// s, slice j) over the group's particles: S = the next power of two
-// >= min(n_group, 64) sinks, J = 64 / S slices. The candidate cells of the
-// group's near list (ascending labels) are staged through LDS 64 particles at
-// a time (near_tile.h); slice j of sink s tests tile entries j, j + J, ...
-// whose candidate mask holds the sink's leaf. A pair is a neighbour iff
-// b != a and |r_a - r_b|^2 < (2 h_a)^2 in FP64 on the tree's copy of the
-// inputs (the same predicate for every precision mode). Count mode writes
-// per-particle counts; fill mode writes ids at offsets[a] + rank, ranks taken
-// by ballot within the sink's lane segment so each list keeps tree order.
+// One wave per group of sibling leaves (k_walk.hip), taking the group's
+// leaves in turn. Lanes are (sink slot s, slice j) over the leaf's particles
+// (near_tile.h: S = min(c, 64) sinks, J = 64 / S slices). The candidate
+// cells of the leaf (cells of the group's near list, ascending labels, whose
+// candidate mask has the leaf) are staged through LDS 64 particles at a
+// time; slice j of sink s tests tile entries j, j + J, .... A pair is a
+// neighbour iff b != a and |r_a - r_b|^2 < (2 h_a)^2 in FP64 on the tree's
+// copy of the inputs (the same predicate for every precision mode). Count
+// mode writes per-particle counts; fill mode writes ids at offsets[a] + rank,
+// ranks taken by ballot within the sink's lane segment so each list keeps
+// tree order.
 #include "near_tile.h"
 #include "rcb_internal.h"
 
@@ -38,7 +39,6 @@ struct NeighArgs {
 struct alignas(16) SrcN {
     double x, y, z;
     int32_t pb;
-    uint32_t mask;
 };
 
 struct NeighShared {
@@ -55,73 +55,65 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
     const int lane = lane_id();
     const int G = 1 << a.gk;
     const int64_t GL = (a.nleaf >> a.gk) + gi;
-    const int32_t sG = a.nfirst[GL], nG = a.ncount[GL];
-    if (nG == 0) return;
-    int32_t lf[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) lf[i] = i < G ? a.nfirst[a.nleaf + gi * G + i] : 0x7fffffff;
-    int S = 1;
-    while (S < nG && S < kWave) S <<= 1;
-    const int J = kWave / S;
-    const int sslot = lane / J;
-    const int slice = lane % J;
-    const uint64_t segmask = (J == 64) ? ~0ull : (((1ull << J) - 1ull) << (sslot * J));
+    if (a.ncount[GL] == 0) return;
     const int64_t n0 = a.gnear_off[gi], n1 = a.gnear_off[gi + 1];
-    for (int g0 = 0; g0 < nG; g0 += S) {
-        const int si = g0 + sslot;
-        const bool has_sink = si < nG;
-        const int32_t pa = sG + (has_sink ? si : 0);
-        int la = 0;
-#pragma unroll
-        for (int i = 1; i < 8; ++i)
-            if (lf[i] <= pa) la = i;
-        const uint32_t bit = has_sink ? (1u << (8 + la)) : 0u;   // candidate-mask bit
-        const double xa = a.px[pa], ya = a.py[pa], za = a.pz[pa];
-        const double two_h = 2.0 * a.ph[pa];
-        const double lim = two_h * two_h;
-        int64_t cnt = 0;
-        int64_t obase = 0;
-        if (FILL && has_sink) obase = a.offsets[a.pid[pa]];
-        for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
-            const int tot = load_entry_chunk(a.gnear, a.nfirst, a.ncount, e0, n1, 0xff00u, sh.ec);
-            for (int t = 0; t < tot; t += kWave) {
-                const int q = t + lane;
-                if (q < tot) {
-                    const int k = entry_of(sh.ec, q);
-                    const int32_t pb = sh.ec.fB[k] + (q - sh.ec.pos[k]);
-                    SrcN s;
-                    s.x = a.px[pb];
-                    s.y = a.py[pb];
-                    s.z = a.pz[pb];
-                    s.pb = pb;
-                    s.mask = sh.ec.mask[k];
-                    sh.tile[lane] = s;
-                }
-                tile_sync();
-                const int nt = tot - t < kWave ? tot - t : kWave;
-                for (int u0 = 0; u0 < nt; u0 += J) {
-                    const int u = u0 + slice;
-                    bool hit = false;
-                    int32_t pb = 0;
-                    if (u < nt) {
-                        const SrcN s = sh.tile[u];
-                        pb = s.pb;
-                        hit = (s.mask & bit) && pb != pa && dist2(xa, ya, za, s.x, s.y, s.z) < lim;
+    for (int li = 0; li < G; ++li) {
+        const int64_t A = a.nleaf + gi * G + li;
+        const int32_t sA = a.nfirst[A], c = a.ncount[A];
+        if (c == 0) continue;
+        const LeafLanes L = leaf_lanes(c);
+        const uint64_t segmask = seg_mask(L);
+        for (int g0 = 0; g0 < c; g0 += L.S) {
+            const int si = g0 + L.sslot;
+            const bool has_sink = L.sslot < L.S && si < c;
+            const int32_t pa = sA + (has_sink ? si : 0);
+            const double xa = a.px[pa], ya = a.py[pa], za = a.pz[pa];
+            const double two_h = 2.0 * a.ph[pa];
+            const double lim = has_sink ? two_h * two_h : -1.0;
+            int cnt = 0;
+            int64_t obase = 0;
+            if (FILL && has_sink) obase = a.offsets[a.pid[pa]];
+            for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
+                const int tot =
+                    load_entry_chunk(a.gnear, a.nfirst, a.ncount, e0, n1, 1u << (8 + li), sh.ec);
+                for (int t = 0; t < tot; t += kWave) {
+                    const int q = t + lane;
+                    if (q < tot) {
+                        const int k = entry_of(sh.ec, q);
+                        const int32_t pb = sh.ec.fB[k] + (q - sh.ec.pos[k]);
+                        SrcN s;
+                        s.x = a.px[pb];
+                        s.y = a.py[pb];
+                        s.z = a.pz[pb];
+                        s.pb = pb;
+                        sh.tile[lane] = s;
                     }
-                    if (FILL) {
-                        const uint64_t bal = ballot(hit) & segmask;
-                        if (hit) a.ids[obase + cnt + rank_below(bal)] = a.pid[pb];
-                        cnt += __popcll(bal);
-                    } else {
-                        cnt += hit;
+                    tile_sync();
+                    const int nt = tot - t < kWave ? tot - t : kWave;
+                    for (int u0 = 0; u0 < nt; u0 += L.J) {
+                        const int u = u0 + L.slice;
+                        bool hit = false;
+                        int32_t pb = 0;
+                        if (u < nt) {
+                            const SrcN s = sh.tile[u];
+                            pb = s.pb;
+                            hit = pb != pa && dist2(xa, ya, za, s.x, s.y, s.z) < lim;
+                        }
+                        if (FILL) {
+                            const uint64_t bal = ballot(hit) & segmask;
+                            if (hit) a.ids[obase + cnt + rank_below(bal)] = a.pid[pb];
+                            cnt += __popcll(bal);
+                        } else {
+                            cnt += hit;
+                        }
                     }
+                    tile_sync();
                 }
-                tile_sync();
             }
-        }
-        if (!FILL) {
-            for (int o = 1; o < J; o <<= 1) cnt += __shfl_xor(cnt, o, kWave);
-            if (has_sink && slice == 0) a.counts[a.pid[pa]] = cnt;
+            if (!FILL) {
+                cnt = seg_sum(cnt, L.slice, L.J);
+                if (has_sink && L.slice == 0) a.counts[a.pid[pa]] = cnt;
+            }
         }
     }
 }

@@ -20,7 +20,8 @@
 //   dr_b += aR m_b / M + m_b (6 aQ d - 2 tr(aQ) d)
 //   dm_b += aM + aR . d / M + 3 d.aQ.d - |d|^2 tr(aQ)
 // (dQ/dCOM = 0 because sum m d = 0).
-// Kernels: moments (per group) -> far (per group) -> near (per group) -> push.
+// Kernels: moments (per group) -> far (per group) -> near (per group, leaf by
+// leaf) -> push.
 #include "far_math.h"
 #include "near_tile.h"
 #include "rcb_internal.h"
@@ -224,17 +225,18 @@ __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
     }
 }
 
-// near field and the sink-side far terms: per group, one sink per lane.
-// Sources are staged 64 at a time in LDS (near_tile.h); lane j visits the
-// tile in the rotated order (j + u) mod 64, so at each step the 64 lanes
-// touch 64 different sources and the source-side terms are summed with LDS
-// atomics without conflicts; each tile's sums then go out with one set of
-// FP64 atomics per source.
+// near field and the sink-side far terms: per group, the leaves in turn, lanes
+// (sink slot, slice) over the leaf's particles as in the forward kernel
+// (near_tile.h). Sources of the leaf's near cells are staged 64 at a time in
+// LDS as T = ceil(nt / J) rows of J. Sink slot s visits the rows in the
+// rotated order (s + t) mod T, so at each step the lanes of one slice touch
+// different sources and the source-side terms are summed with LDS atomics
+// without conflicts; each tile's sums then go out with one set of FP64
+// atomics per source.
 template <typename T>
 struct VjpTile {
     T x[kWave], y[kWave], z[kWave], m[kWave], h[kWave];
     int32_t pb[kWave];
-    uint32_t mask[kWave];
     double acc[4][kWave];
 };
 template <typename T>
@@ -253,128 +255,131 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
     const int lane = lane_id();
     const int G = 1 << a.gk;
     const int64_t GL = (a.nleaf >> a.gk) + gi;
-    const int32_t sG = a.nfirst[GL], nG = a.ncount[GL];
-    if (nG == 0) return;
-    const double cG[3] = {a.ncom[3 * GL], a.ncom[3 * GL + 1], a.ncom[3 * GL + 2]};
-    int32_t lf[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) lf[i] = i < G ? a.nfirst[a.nleaf + gi * G + i] : 0x7fffffff;
+    if (a.ncount[GL] == 0) return;
     const int64_t n0 = a.gnear_off[gi], n1 = a.gnear_off[gi + 1];
-    for (int g0 = 0; g0 < nG; g0 += kWave) {
-        const int si = g0 + lane;
-        const bool has_sink = si < nG;
-        const int32_t pa = sG + (has_sink ? si : 0);
-        const int la = leaf_slot(lf, pa);
-        const uint32_t bit = has_sink ? (1u << la) : 0u;
-        const int64_t A = a.nleaf + gi * G + la;
+    for (int li = 0; li < G; ++li) {
+        const int64_t A = a.nleaf + gi * G + li;
+        const int32_t sA = a.nfirst[A], c = a.ncount[A];
+        if (c == 0) continue;
+        const LeafLanes L = leaf_lanes(c);
         const double cA[3] = {a.ncom[3 * A], a.ncom[3 * A + 1], a.ncom[3 * A + 2]};
-        const int32_t oa = a.pid[pa];
-        T ga[3] = {(T)0, (T)0, (T)0};
-        double gd[3] = {0.0, 0.0, 0.0};
-        if (has_sink) {
-            gd[0] = load_g<MIXED>(a.gx, oa);
-            gd[1] = load_g<MIXED>(a.gy, oa);
-            gd[2] = load_g<MIXED>(a.gz, oa);
-            ga[0] = (T)gd[0];
-            ga[1] = (T)gd[1];
-            ga[2] = (T)gd[2];
-        }
-        T sx, sy, sz, ha;
-        if constexpr (MIXED) {
-            sx = (float)(cA[0] - cG[0]) + a.fdx[pa];
-            sy = (float)(cA[1] - cG[1]) + a.fdy[pa];
-            sz = (float)(cA[2] - cG[2]) + a.fdz[pa];
-            ha = a.fh[pa];
-        } else {
-            sx = a.px[pa];
-            sy = a.py[pa];
-            sz = a.pz[pa];
-            ha = a.ph[pa];
-        }
-        double acc[3] = {0.0, 0.0, 0.0};
-        for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
-            const int tot = load_entry_chunk(a.gnear, a.nfirst, a.ncount, e0, n1, 0xffu, sh.ec);
-            for (int t = 0; t < tot; t += kWave) {
-                const int q = t + lane;
-                if (q < tot) {
-                    const int k = entry_of(sh.ec, q);
-                    const int32_t pb = sh.ec.fB[k] + (q - sh.ec.pos[k]);
-                    if constexpr (MIXED) {
-                        const int64_t B = sh.ec.label[k];
-                        sh.t.x[lane] = (float)(a.ncom[3 * B] - cG[0]) + a.fdx[pb];
-                        sh.t.y[lane] = (float)(a.ncom[3 * B + 1] - cG[1]) + a.fdy[pb];
-                        sh.t.z[lane] = (float)(a.ncom[3 * B + 2] - cG[2]) + a.fdz[pb];
-                        sh.t.m[lane] = a.fm[pb];
-                        sh.t.h[lane] = a.fh[pb];
-                    } else {
-                        sh.t.x[lane] = a.px[pb];
-                        sh.t.y[lane] = a.py[pb];
-                        sh.t.z[lane] = a.pz[pb];
-                        sh.t.m[lane] = a.pm[pb];
-                        sh.t.h[lane] = a.ph[pb];
-                    }
-                    sh.t.pb[lane] = pb;
-                    sh.t.mask[lane] = sh.ec.mask[k];
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c) sh.t.acc[c][lane] = 0.0;
-                tile_sync();
-                const int nt = tot - t < kWave ? tot - t : kWave;
-                for (int u = 0; u < kWave; ++u) {
-                    const int j = (lane + u) & (kWave - 1);
-                    if (j < nt && (sh.t.mask[j] & bit)) {
-                        const T v[3] = {sx - sh.t.x[j], sy - sh.t.y[j], sz - sh.t.z[j]};
-                        const T r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
-                        T F, dFr;
-                        soft_FdF<T>(r2, (T)0.5 * (ha + sh.t.h[j]), F, dFr);
-                        const T vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
-                        const T mb = sh.t.m[j];
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            const T Kg = mb * (F * ga[c] + dFr * v[c] * vg);
-                            acc[c] -= (double)Kg;
-                            atomicAdd(&sh.t.acc[c][j], (double)Kg);
+        for (int g0 = 0; g0 < c; g0 += L.S) {
+            const int si = g0 + L.sslot;
+            const bool has_sink = L.sslot < L.S && si < c;
+            const int32_t pa = sA + (has_sink ? si : 0);
+            const int32_t oa = a.pid[pa];
+            T ga[3] = {(T)0, (T)0, (T)0};
+            double gd[3] = {0.0, 0.0, 0.0};
+            if (has_sink) {
+                gd[0] = load_g<MIXED>(a.gx, oa);
+                gd[1] = load_g<MIXED>(a.gy, oa);
+                gd[2] = load_g<MIXED>(a.gz, oa);
+                ga[0] = (T)gd[0];
+                ga[1] = (T)gd[1];
+                ga[2] = (T)gd[2];
+            }
+            T sx, sy, sz, ha;
+            if constexpr (MIXED) {   // leaf frame
+                sx = a.fdx[pa];
+                sy = a.fdy[pa];
+                sz = a.fdz[pa];
+                ha = a.fh[pa];
+            } else {
+                sx = a.px[pa];
+                sy = a.py[pa];
+                sz = a.pz[pa];
+                ha = a.ph[pa];
+            }
+            double acc[3] = {0.0, 0.0, 0.0};
+            for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
+                const int tot = load_entry_chunk(a.gnear, a.nfirst, a.ncount, e0, n1, 1u << li, sh.ec);
+                for (int t = 0; t < tot; t += kWave) {
+                    const int q = t + lane;
+                    if (q < tot) {
+                        const int k = entry_of(sh.ec, q);
+                        const int32_t pb = sh.ec.fB[k] + (q - sh.ec.pos[k]);
+                        if constexpr (MIXED) {
+                            const int64_t B = sh.ec.label[k];
+                            sh.t.x[lane] = (float)(a.ncom[3 * B] - cA[0]) + a.fdx[pb];
+                            sh.t.y[lane] = (float)(a.ncom[3 * B + 1] - cA[1]) + a.fdy[pb];
+                            sh.t.z[lane] = (float)(a.ncom[3 * B + 2] - cA[2]) + a.fdz[pb];
+                            sh.t.m[lane] = a.fm[pb];
+                            sh.t.h[lane] = a.fh[pb];
+                        } else {
+                            sh.t.x[lane] = a.px[pb];
+                            sh.t.y[lane] = a.py[pb];
+                            sh.t.z[lane] = a.pz[pb];
+                            sh.t.m[lane] = a.pm[pb];
+                            sh.t.h[lane] = a.ph[pb];
                         }
-                        atomicAdd(&sh.t.acc[3][j], (double)(-F * vg));
+                        sh.t.pb[lane] = pb;
                     }
-                }
-                tile_sync();
-                if (lane < nt) {
-                    const double s0 = sh.t.acc[0][lane], s1 = sh.t.acc[1][lane], s2 = sh.t.acc[2][lane],
-                                 s3 = sh.t.acc[3][lane];
-                    if (s0 != 0.0 || s1 != 0.0 || s2 != 0.0 || s3 != 0.0) {
-                        const int32_t pb = sh.t.pb[lane];
-                        atomicAdd(a.src + pb, s0);
-                        atomicAdd(a.src + a.n + pb, s1);
-                        atomicAdd(a.src + 2 * a.n + pb, s2);
-                        atomicAdd(a.src + 3 * a.n + pb, s3);
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) sh.t.acc[cc][lane] = 0.0;
+                    tile_sync();
+                    const int nt = tot - t < kWave ? tot - t : kWave;
+                    const int rows = (nt + L.J - 1) / L.J;
+                    const int r0 = L.sslot % rows;
+                    for (int st = 0; st < rows; ++st) {
+                        int r = r0 + st;
+                        if (r >= rows) r -= rows;
+                        const int j = r * L.J + L.slice;
+                        if (has_sink && j < nt) {
+                            const T v[3] = {sx - sh.t.x[j], sy - sh.t.y[j], sz - sh.t.z[j]};
+                            const T r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+                            T F, dFr;
+                            soft_FdF<T>(r2, (T)0.5 * (ha + sh.t.h[j]), F, dFr);
+                            const T vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
+                            const T mb = sh.t.m[j];
+#pragma unroll
+                            for (int cc = 0; cc < 3; ++cc) {
+                                const T Kg = mb * (F * ga[cc] + dFr * v[cc] * vg);
+                                acc[cc] -= (double)Kg;
+                                atomicAdd(&sh.t.acc[cc][j], (double)Kg);
+                            }
+                            atomicAdd(&sh.t.acc[3][j], (double)(-F * vg));
+                        }
                     }
+                    tile_sync();
+                    if (lane < nt) {
+                        const double s0 = sh.t.acc[0][lane], s1 = sh.t.acc[1][lane],
+                                     s2 = sh.t.acc[2][lane], s3 = sh.t.acc[3][lane];
+                        if (s0 != 0.0 || s1 != 0.0 || s2 != 0.0 || s3 != 0.0) {
+                            const int32_t pb = sh.t.pb[lane];
+                            atomicAdd(a.src + pb, s0);
+                            atomicAdd(a.src + a.n + pb, s1);
+                            atomicAdd(a.src + 2 * a.n + pb, s2);
+                            atomicAdd(a.src + 3 * a.n + pb, s3);
+                        }
+                    }
+                    tile_sync();
                 }
-                tile_sync();
             }
-        }
-        if (has_sink) {
-            const double *lc = a.leafc + (gi * G + la) * kLeafC;
-            const double d[3] = {a.px[pa] - cA[0], a.py[pa] - cA[1], a.pz[pa] - cA[2]};
-            const double ma = a.pm[pa];
-            const double MA = a.nM[A];
-            const double cot[3] = {lc[19], lc[20], lc[21]};
-            double out[3];
 #pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                double v = acc[l] + ma / MA * cot[l];
+            for (int cc = 0; cc < 3; ++cc) acc[cc] = seg_sum(acc[cc], L.slice, L.J);
+            if (has_sink && L.slice == 0) {
+                const double *lc = a.leafc + (gi * G + li) * kLeafC;
+                const double d[3] = {a.px[pa] - cA[0], a.py[pa] - cA[1], a.pz[pa] - cA[2]};
+                const double ma = a.pm[pa];
+                const double MA = a.nM[A];
+                const double cot[3] = {lc[19], lc[20], lc[21]};
+                double out[3];
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    v += gd[i] * lc[3 + jidx(i, l)];
+                for (int l = 0; l < 3; ++l) {
+                    double v = acc[l] + ma / MA * cot[l];
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) v += gd[i] * lc[9 + hidx(i, l, m)] * d[m];
+                    for (int i = 0; i < 3; ++i) {
+                        v += gd[i] * lc[3 + jidx(i, l)];
+#pragma unroll
+                        for (int m = 0; m < 3; ++m) v += gd[i] * lc[9 + hidx(i, l, m)] * d[m];
+                    }
+                    out[l] = v;
                 }
-                out[l] = v;
+                a.sink[pa] = out[0];
+                a.sink[a.n + pa] = out[1];
+                a.sink[2 * a.n + pa] = out[2];
+                a.sink[3 * a.n + pa] = (cot[0] * d[0] + cot[1] * d[1] + cot[2] * d[2]) / MA;
             }
-            a.sink[pa] = out[0];
-            a.sink[a.n + pa] = out[1];
-            a.sink[2 * a.n + pa] = out[2];
-            a.sink[3 * a.n + pa] = (cot[0] * d[0] + cot[1] * d[1] + cot[2] * d[2]) / MA;
         }
     }
 }

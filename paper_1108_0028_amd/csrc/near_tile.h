@@ -68,4 +68,37 @@ __device__ __forceinline__ void tile_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
+// Lanes of a wave over the sinks of one leaf of c > 0 particles: S = min(c, 64)
+// sinks per pass, J = 64 / S slices per sink, lane = sslot * J + slice. Lanes
+// with sslot >= S hold no sink. Slice j of a sink takes tile sources
+// j, j + J, j + 2J, ...
+struct LeafLanes {
+    int S, J, sslot, slice;
+};
+__device__ __forceinline__ LeafLanes leaf_lanes(int c) {
+    LeafLanes L;
+    L.S = c < kWave ? c : kWave;
+    L.J = kWave / L.S;
+    L.sslot = lane_id() / L.J;
+    L.slice = lane_id() - L.sslot * L.J;
+    return L;
+}
+
+// Sum over the J consecutive lanes of each segment; the total lands on the
+// segment's first lane (slice 0). After the step with offset o, lane i holds
+// the sum of its segment's lanes [i, min(i + 2o, end)).
+template <typename T>
+__device__ __forceinline__ T seg_sum(T v, int slice, int J) {
+    for (int o = 1; o < J; o <<= 1) {
+        const T w = __shfl_down(v, o, kWave);
+        if (slice + o < J) v += w;
+    }
+    return v;
+}
+
+// ballot bits of the lanes of this lane's segment
+__device__ __forceinline__ uint64_t seg_mask(const LeafLanes &L) {
+    return L.J == kWave ? ~0ull : (((1ull << L.J) - 1ull) << (L.sslot * L.J));
+}
+
 }  // namespace rcb
