@@ -18,10 +18,11 @@
 //   G0_i = sum_a g_ai, G1_il = sum_a g_ai d_al, G2_ilm = sum_a g_ai d_al d_am
 // (d_a = r_a - com_A), leaf A's far-field share of L = sum g . a is, per B,
 //   Psi = G0.f + G1:J + G2:H / 2,
-// and the backward pass needs dPsi/dM, dPsi/dQ (closed forms below),
-// dPsi/dR (forward-mode dual numbers through the same closed forms, which
-// carries the fourth derivative of the field without forming it), and
-// d(G2:H/2)/dR, the part that moves with the sink's centre of mass.
+// and the backward pass needs dPsi/dM, dPsi/dQ, dPsi/dR and d(G2:H/2)/dR,
+// the part that moves with the sink's centre of mass. far_pair_adjoint
+// carries dPsi/dR by forward-mode dual numbers through the forward closed
+// forms (a cross-check for the tests); far_pair_adjoint_sym, used by the
+// kernels, has every output in closed form over symmetrised moments.
 #pragma once
 
 #include <math.h>
@@ -268,24 +269,56 @@ RCB_HD void far_pair_adjoint(double x, double y, double z, double M, const doubl
 }
 
 
-// Closed-form version of far_pair_adjoint (no dual numbers). With ' = d/dR
-// and the recursions dD_k/dx_n = D_(k+1) x_n, ds/dx_n = 2 q_n, dq_i/dx_n = Q_in,
-//   e4 = M D4 + s D6/6, c3 = D5/3,
-// the fourth derivative T4_ilmn = dH_ilm/dx_n contracted with G2/2 gives
-//   2 cot_n = (e4 x_n + c3 q_n) w2 + e3 (p_n + 2 pt_n) + (e3 x_n + c2 q_n)(2 sig.x + tau.x)
-//           + b2 (2 sig_n + tau_n) + c3 x_n (q.p + 2 q.pt)
-//           + c2 [Q p + 2 Rm^T q + 2 Q pt + 2 Rm q + 2 P q]_n
-//           + c2 x_n (Q:P + 2 Q:Rm + tau.q + 2 sig.q)
-//           + c1 [G2_n..:Q + 2 sum_im G2_inm Q_im + Q tau + 2 Q sig]_n
-// with w2 = G2_ilm x_i x_l x_m, p_i = G2_ilm x_l x_m, pt_l = G2_ilm x_i x_m,
-// P_lm = G2_ilm x_i, Rm_il = G2_ilm x_m; and
-//   (G0.J)_n  = b2 u0 x_n + a1 G0_n + c1 ((G0.q) x_n + q_n u0) + c0 (Q G0)_n
-//   (G1:H)_n  = e3 w11 x_n + b2 (t1 x_n + v1_n + v1t_n) + c2 ((q.v1 + q.v1t) x_n + q_n w11)
-//             + c1 ((Q v1t)_n + (Q v1)_n + (G1:Q) x_n + (G1^T q)_n + (G1 q)_n + t1 q_n)
-//   rho = G0.J + G1:H + cot.
-RCB_HD void far_pair_adjoint_cf(double x, double y, double z, double M, const double qq[6],
-                                const SinkMoments &G, double rho[3], double cot[3], double &adjM,
-                                double adjQ[6]) {
+// Symmetrised sink moments. Psi contracts G1 with the symmetric J and G2
+// with the fully symmetric H, so only sym(G1) and the full symmetrisation of
+// G2 enter Psi and all its derivatives:
+//   S1 = G0, S2_il = (G1_il + G1_li)/2, S3_ilm = (G2_ilm + G2_lim + G2_mil)/3,
+//   t1 = tr S2, sg_m = sum_i S3_iim.
+struct SymMoments {
+    double S1[3];
+    double S2[6];    // jidx order
+    double S3[10];   // hidx order
+    double t1;
+    double sg[3];
+};
+
+RCB_HD void sym_moments(const double G0[3], const double G1[9], const double G2[18], SymMoments &S) {
+    for (int i = 0; i < 3; ++i) S.S1[i] = G0[i];
+    for (int i = 0; i < 3; ++i)
+        for (int l = i; l < 3; ++l) S.S2[jidx(i, l)] = 0.5 * (G1[3 * i + l] + G1[3 * l + i]);
+    for (int i = 0; i < 3; ++i)
+        for (int l = i; l < 3; ++l)
+            for (int m = l; m < 3; ++m)
+                S.S3[hidx(i, l, m)] =
+                    (G2[6 * i + jidx(l, m)] + G2[6 * l + jidx(i, m)] + G2[6 * m + jidx(i, l)]) / 3.0;
+    S.t1 = S.S2[0] + S.S2[3] + S.S2[5];
+    for (int m = 0; m < 3; ++m) S.sg[m] = S.S3[hidx(0, 0, m)] + S.S3[hidx(1, 1, m)] + S.S3[hidx(2, 2, m)];
+}
+
+// Closed form of the pair adjoint with symmetrised moments (no dual numbers).
+// With u0 = S1.x, v = S2 x, w11 = x.v, sx = sg.x, P_lm = S3_ilm x_i, p = P x,
+// w2 = x.p, q = Q x, s = x.q and the scalars of the forward pass, the pair's
+// share of L is
+//   Psi = a1 K1 + b2 K2 + e3 w2/2 + c0 K3 + 2 c1 q.v + 3/2 c1 K4 + 3/2 c2 q.p,
+//   K1 = u0 + t1, K2 = w11 + 3/2 sx, K3 = S1.q + S2:Q, K4 = Q:P + sg.q.
+// Using dD_k/dx = D_(k+1) x, ds/dx = 2 q, dq_i/dx_n = Q_in and
+//   da1 = b2 x + c1 q, db2 = e3 x + c2 q, de3 = e4 x + c3 q, dc_k = c_(k+1) x
+// (e4 = M D4 + s D6/6, c3 = D5/3):
+//   dPsi/dM = D1 K1 + D2 K2 + D3 w2/2
+//   dPsi/dQ = sym[ ss x x^T + psq x^T ] + c0 S2 + 3/2 c1 P,
+//             ss = (D3 K1 + D4 K2 + D5 w2/2)/6,
+//             psq = c0 S1 + 2 c1 v + 3/2 c1 sg + 3/2 c2 p
+//   rho = dPsi/dR = ax x + aq q + a1 S1 + b2 (2 v + 3/2 sg) + 3/2 e3 p + Q psq
+//                   + 2 c1 S2 q + 3/2 c1 (S3:Q) + 3 c2 P q,
+//         ax = b2 K1 + e3 K2 + e4 w2/2 + c1 K3 + 2 c2 q.v + 3/2 c2 K4 + 3/2 c3 q.p,
+//         aq = c1 K1 + c2 K2 + c3 w2/2
+//   cot = d(S3:H/2)/dR = bx x + bq q + 3/2 b2 sg + 3/2 e3 p + 3/2 c1 (S3:Q)
+//                        + Q (3/2 c1 sg + 3/2 c2 p) + 3 c2 P q,
+//         bx = 3/2 e3 sx + 3/2 c2 K4 + e4 w2/2 + 3/2 c3 q.p, bq = 3/2 c2 sx + c3 w2/2
+// where (S3:Q)_n = S3_nlm Q_lm.
+RCB_HD void far_pair_adjoint_sym(double x, double y, double z, double M, const double qq[6],
+                                 const SymMoments &S, double rho[3], double cot[3], double &adjM,
+                                 double adjQ[6]) {
     const double X[3] = {x, y, z};
     const double r2 = (x * x + y * y) + z * z;
     const double ri = rsqrt64(r2);
@@ -296,9 +329,8 @@ RCB_HD void far_pair_adjoint_cf(double x, double y, double z, double M, const do
     const double D4 = -7.0 * D3 * ri2;
     const double D5 = -9.0 * D4 * ri2;
     const double D6 = -11.0 * D5 * ri2;
-    const double Qm[3][3] = {{qq[0], qq[1], qq[2]}, {qq[1], qq[3], qq[4]}, {qq[2], qq[4], qq[5]}};
     double q[3];
-    for (int i = 0; i < 3; ++i) q[i] = Qm[i][0] * x + Qm[i][1] * y + Qm[i][2] * z;
+    for (int i = 0; i < 3; ++i) q[i] = qq[jidx(i, 0)] * x + qq[jidx(i, 1)] * y + qq[jidx(i, 2)] * z;
     const double s = q[0] * x + q[1] * y + q[2] * z;
     const double sixth = 1.0 / 6.0, third = 1.0 / 3.0;
     const double a1 = M * D1 + sixth * D3 * s;
@@ -306,97 +338,60 @@ RCB_HD void far_pair_adjoint_cf(double x, double y, double z, double M, const do
     const double e3 = M * D3 + sixth * D5 * s;
     const double e4 = M * D4 + sixth * D6 * s;
     const double c0 = third * D2, c1 = third * D3, c2 = third * D4, c3 = third * D5;
-    // sink contractions
-    const double u0 = G.G0[0] * x + G.G0[1] * y + G.G0[2] * z;
-    double v1[3], v1t[3];
-    for (int i = 0; i < 3; ++i) {
-        v1[i] = G.G1[3 * i] * x + G.G1[3 * i + 1] * y + G.G1[3 * i + 2] * z;
-        v1t[i] = G.G1[i] * x + G.G1[3 + i] * y + G.G1[6 + i] * z;
-    }
-    const double w11 = x * v1[0] + y * v1[1] + z * v1[2];
+    // sink contractions with x
+    const double u0 = S.S1[0] * x + S.S1[1] * y + S.S1[2] * z;
+    double v[3];
+    for (int i = 0; i < 3; ++i) v[i] = S.S2[jidx(i, 0)] * x + S.S2[jidx(i, 1)] * y + S.S2[jidx(i, 2)] * z;
+    const double w11 = v[0] * x + v[1] * y + v[2] * z;
+    const double sx = S.sg[0] * x + S.sg[1] * y + S.sg[2] * z;
     double P[6];
-    for (int k = 0; k < 6; ++k) P[k] = G.G2[k] * x + G.G2[6 + k] * y + G.G2[12 + k] * z;
-    double Rm[9];
-    for (int i = 0; i < 3; ++i)
-        for (int l = 0; l < 3; ++l)
-            Rm[3 * i + l] = G.G2[6 * i + jidx(l, 0)] * x + G.G2[6 * i + jidx(l, 1)] * y +
-                            G.G2[6 * i + jidx(l, 2)] * z;
-    double p[3], pt[3];
-    for (int i = 0; i < 3; ++i) {
-        p[i] = Rm[3 * i] * x + Rm[3 * i + 1] * y + Rm[3 * i + 2] * z;
-        pt[i] = P[jidx(i, 0)] * x + P[jidx(i, 1)] * y + P[jidx(i, 2)] * z;
-    }
+    for (int l = 0; l < 3; ++l)
+        for (int m = l; m < 3; ++m)
+            P[jidx(l, m)] = S.S3[hidx(0, l, m)] * x + S.S3[hidx(1, l, m)] * y + S.S3[hidx(2, l, m)] * z;
+    double p[3];
+    for (int l = 0; l < 3; ++l) p[l] = P[jidx(l, 0)] * x + P[jidx(l, 1)] * y + P[jidx(l, 2)] * z;
     const double w2 = p[0] * x + p[1] * y + p[2] * z;
-    const double sx = G.sig[0] * x + G.sig[1] * y + G.sig[2] * z;
-    const double tx = G.tau[0] * x + G.tau[1] * y + G.tau[2] * z;
-    double G1Q = 0.0, QP = 0.0, QRm = 0.0;
-    for (int i = 0; i < 3; ++i)
-        for (int l = 0; l < 3; ++l) {
-            G1Q += G.G1[3 * i + l] * Qm[i][l];
-            QP += Qm[i][l] * P[jidx(i, l)];
-            QRm += Qm[i][l] * Rm[3 * i + l];
-        }
-    const double G0q = G.G0[0] * q[0] + G.G0[1] * q[1] + G.G0[2] * q[2];
-    const double qv1 = q[0] * v1[0] + q[1] * v1[1] + q[2] * v1[2];
-    const double qv1t = q[0] * v1t[0] + q[1] * v1t[1] + q[2] * v1t[2];
-    const double tq = G.tau[0] * q[0] + G.tau[1] * q[1] + G.tau[2] * q[2];
-    const double sq = G.sig[0] * q[0] + G.sig[1] * q[1] + G.sig[2] * q[2];
+    // contractions with Q (symmetric: off-diagonal pairs counted twice)
+    const double S2Q = (S.S2[0] * qq[0] + S.S2[3] * qq[3] + S.S2[5] * qq[5]) +
+                       2.0 * (S.S2[1] * qq[1] + S.S2[2] * qq[2] + S.S2[4] * qq[4]);
+    const double QP = (P[0] * qq[0] + P[3] * qq[3] + P[5] * qq[5]) +
+                      2.0 * (P[1] * qq[1] + P[2] * qq[2] + P[4] * qq[4]);
+    const double K1 = u0 + S.t1;
+    const double K2 = w11 + 1.5 * sx;
+    const double K3 = (S.S1[0] * q[0] + S.S1[1] * q[1] + S.S1[2] * q[2]) + S2Q;
+    const double K4 = QP + (S.sg[0] * q[0] + S.sg[1] * q[1] + S.sg[2] * q[2]);
+    const double qv = q[0] * v[0] + q[1] * v[1] + q[2] * v[2];
     const double qp = q[0] * p[0] + q[1] * p[1] + q[2] * p[2];
-    const double qpt = q[0] * pt[0] + q[1] * pt[1] + q[2] * pt[2];
-    const double k3 = 2.0 * sx + tx;
-    const double k7 = QP + 2.0 * QRm + tq + 2.0 * sq;
-    const double k5 = qp + 2.0 * qpt;
-    for (int n = 0; n < 3; ++n) {
-        double Qp = 0.0, RmTq = 0.0, Qpt = 0.0, Rmq = 0.0, Pq = 0.0, QG0 = 0.0, Qv1t = 0.0, Qv1 = 0.0;
-        double G1Tq = 0.0, G1q = 0.0, Qtau = 0.0, Qsig = 0.0, G2nQ = 0.0, G2inmQ = 0.0;
-        for (int i = 0; i < 3; ++i) {
-            Qp += Qm[n][i] * p[i];
-            RmTq += Rm[3 * i + n] * q[i];
-            Qpt += Qm[n][i] * pt[i];
-            Rmq += Rm[3 * n + i] * q[i];
-            Pq += P[jidx(n, i)] * q[i];
-            QG0 += Qm[n][i] * G.G0[i];
-            Qv1t += Qm[n][i] * v1t[i];
-            Qv1 += Qm[n][i] * v1[i];
-            G1Tq += G.G1[3 * i + n] * q[i];
-            G1q += G.G1[3 * n + i] * q[i];
-            Qtau += Qm[n][i] * G.tau[i];
-            Qsig += Qm[n][i] * G.sig[i];
-            for (int m = 0; m < 3; ++m) {
-                G2nQ += G.G2[6 * n + jidx(i, m)] * Qm[i][m];
-                G2inmQ += G.G2[6 * i + jidx(n, m)] * Qm[i][m];
-            }
-        }
-        const double two_cot = (e4 * X[n] + c3 * q[n]) * w2 + e3 * (p[n] + 2.0 * pt[n]) +
-                               (e3 * X[n] + c2 * q[n]) * k3 + b2 * (2.0 * G.sig[n] + G.tau[n]) +
-                               c3 * X[n] * k5 + c2 * (Qp + 2.0 * RmTq + 2.0 * Qpt + 2.0 * Rmq + 2.0 * Pq) +
-                               c2 * X[n] * k7 + c1 * (G2nQ + 2.0 * G2inmQ + Qtau + 2.0 * Qsig);
-        const double g0j = b2 * u0 * X[n] + a1 * G.G0[n] + c1 * (G0q * X[n] + q[n] * u0) + c0 * QG0;
-        const double g1h = e3 * w11 * X[n] + b2 * (G.t1 * X[n] + v1[n] + v1t[n]) +
-                           c2 * ((qv1 + qv1t) * X[n] + q[n] * w11) +
-                           c1 * (Qv1t + Qv1 + G1Q * X[n] + G1Tq + G1q + G.t1 * q[n]);
-        cot[n] = 0.5 * two_cot;
-        rho[n] = g0j + g1h + cot[n];
+    adjM = D1 * K1 + D2 * K2 + 0.5 * D3 * w2;
+    const double ss = sixth * (D3 * K1 + D4 * K2 + 0.5 * D5 * w2);
+    double psq[3], psc[3];
+    for (int j = 0; j < 3; ++j) {
+        psc[j] = 1.5 * (c1 * S.sg[j] + c2 * p[j]);
+        psq[j] = c0 * S.S1[j] + 2.0 * c1 * v[j] + psc[j];
     }
-    const double kA = u0 + G.t1;
-    const double kB = w11 + sx + 0.5 * tx;
-    const double kE = 0.5 * w2;
-    adjM = D1 * kA + D2 * kB + D3 * kE;
-    const double sig_s = sixth * (D3 * kA + D4 * kB + D5 * kE);
-    double psq[3];
     for (int j = 0; j < 3; ++j)
-        psq[j] = c0 * G.G0[j] + c1 * (v1[j] + v1t[j] + 0.5 * G.tau[j] + G.sig[j]) + 0.5 * c2 * (p[j] + 2.0 * pt[j]);
-    double A[3][3];
-    for (int j = 0; j < 3; ++j)
-        for (int k = 0; k < 3; ++k)
-            A[j][k] = sig_s * X[j] * X[k] + psq[j] * X[k] + c0 * G.G1[3 * j + k] +
-                      c1 * (0.5 * P[jidx(j, k)] + Rm[3 * j + k]);
-    adjQ[0] = A[0][0];
-    adjQ[1] = 0.5 * (A[0][1] + A[1][0]);
-    adjQ[2] = 0.5 * (A[0][2] + A[2][0]);
-    adjQ[3] = A[1][1];
-    adjQ[4] = 0.5 * (A[1][2] + A[2][1]);
-    adjQ[5] = A[2][2];
+        for (int k = j; k < 3; ++k)
+            adjQ[jidx(j, k)] = ss * X[j] * X[k] + 0.5 * (psq[j] * X[k] + psq[k] * X[j]) +
+                               c0 * S.S2[jidx(j, k)] + 1.5 * c1 * P[jidx(j, k)];
+    const double ax = b2 * K1 + e3 * K2 + 0.5 * e4 * w2 + c1 * K3 + 2.0 * c2 * qv + 1.5 * c2 * K4 +
+                      1.5 * c3 * qp;
+    const double aq = c1 * K1 + c2 * K2 + 0.5 * c3 * w2;
+    const double bx = 1.5 * e3 * sx + 1.5 * c2 * K4 + 0.5 * e4 * w2 + 1.5 * c3 * qp;
+    const double bq = 1.5 * c2 * sx + 0.5 * c3 * w2;
+    for (int n = 0; n < 3; ++n) {
+        double S3Q = 0.0, Pq = 0.0, S2q = 0.0, Qpsq = 0.0, Qpsc = 0.0;
+        for (int m = 0; m < 3; ++m) {
+            for (int l = 0; l < 3; ++l) S3Q += S.S3[hidx(n, l, m)] * qq[jidx(l, m)];
+            Pq += P[jidx(n, m)] * q[m];
+            S2q += S.S2[jidx(n, m)] * q[m];
+            Qpsq += qq[jidx(n, m)] * psq[m];
+            Qpsc += qq[jidx(n, m)] * psc[m];
+        }
+        const double common = 1.5 * e3 * p[n] + 1.5 * c1 * S3Q + 3.0 * c2 * Pq;
+        cot[n] = bx * X[n] + bq * q[n] + 1.5 * b2 * S.sg[n] + Qpsc + common;
+        rho[n] = ax * X[n] + aq * q[n] + a1 * S.S1[n] + b2 * (2.0 * v[n] + 1.5 * S.sg[n]) + Qpsq +
+                 2.0 * c1 * S2q + common;
+    }
 }
 
 }  // namespace rcbfar

@@ -323,7 +323,7 @@ struct BigCtl {
 __global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level, PartIn in,
                                                         const int32_t *__restrict__ id,
                                                         PartOut out, NodeOut o, BigCtl bc) {
-    const int64_t w = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t w = wave_index();
     const int64_t nodes = (int64_t)1 << lvl;
     if (w >= nodes) return;
     const int64_t lab = nodes + w;
@@ -403,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level,
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_chunk_reduce(PartIn in, NodeOut o, BigCtl bc,
                                                          double *__restrict__ part) {
-    const int64_t w = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t w = wave_index();
     if (w >= bc.ctl[1]) return;
     const int bi = bc.item_big[w];
     const int64_t lab = bc.big_node[bi];
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_big_finalize(int leaf_level, NodeOut
     constexpr int NS = Pay<P>::NS;
     __shared__ double stk[kWavesPerBlock][32][NS];
     const int wv = threadIdx.x / kWave;
-    const int64_t bi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t bi = wave_index();
     if (bi >= bc.ctl[0]) return;
     const int64_t lab = bc.big_node[bi];
     const int64_t base = bc.big_base[bi];
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_big_finalize(int leaf_level, NodeOut
 
 __global__ __launch_bounds__(kBlock) void k_part_count(PartIn in, NodeOut o, BigCtl bc,
                                                        int32_t *__restrict__ part_left) {
-    const int64_t w = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t w = wave_index();
     if (w >= bc.ctl[1]) return;
     const int bi = bc.item_big[w];
     const int64_t lab = bc.big_node[bi];
@@ -513,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_part_count(PartIn in, NodeOut o, Big
 
 __global__ __launch_bounds__(kBlock) void k_part_scan(NodeOut o, BigCtl bc,
                                                       int32_t *__restrict__ part_left) {
-    const int64_t bi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t bi = wave_index();
     if (bi >= bc.ctl[0]) return;
     const int64_t lab = bc.big_node[bi];
     const int64_t base = bc.big_base[bi];
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(kBlock) void k_part_scan(NodeOut o, BigCtl bc,
 __global__ __launch_bounds__(kBlock) void k_part_scatter(PartIn in, const int32_t *__restrict__ id,
                                                          PartOut out, NodeOut o, BigCtl bc,
                                                          const int32_t *__restrict__ part_left) {
-    const int64_t w = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t w = wave_index();
     if (w >= bc.ctl[1]) return;
     const int bi = bc.item_big[w];
     const int64_t lab = bc.big_node[bi];
@@ -608,7 +608,7 @@ __global__ void k_mixed_prep(int64_t nleaf, const int32_t *__restrict__ nfirst,
                              const double *__restrict__ ph, float *__restrict__ fdx,
                              float *__restrict__ fdy, float *__restrict__ fdz,
                              float *__restrict__ fm, float *__restrict__ fh) {
-    const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t w = wave_index();
     if (w >= nleaf) return;
     const int64_t lab = nleaf + w;
     const int64_t s = nfirst[lab], c = ncount[lab];

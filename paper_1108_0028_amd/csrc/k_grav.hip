@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
     using T = typename std::conditional<MIXED, float, double>::type;
     __shared__ GravShared<MIXED> sh_all[kWaves];
     GravShared<MIXED> &sh = sh_all[threadIdx.x / kWave];
-    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t gi = wave_index();
     if (gi >= g.ngroup) return;
     const int lane = lane_id();
     const int G = 1 << g.gk;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
 __global__ __launch_bounds__(kBlock) void k_far_coeffs(GravArgs g, double *out, int stride) {
     __shared__ double coef_all[kWaves][8][19];
     double(*coef)[19] = coef_all[threadIdx.x / kWave];
-    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t gi = wave_index();
     if (gi >= g.ngroup) return;
     const int G = 1 << g.gk;
     group_far(g, gi, coef);

@@ -50,7 +50,7 @@ template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
     __shared__ NeighShared sh_all[kWaves];
     NeighShared &sh = sh_all[threadIdx.x / kWave];
-    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t gi = wave_index();
     if (gi >= a.ngroup) return;
     const int lane = lane_id();
     const int G = 1 << a.gk;

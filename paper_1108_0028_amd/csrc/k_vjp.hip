@@ -9,7 +9,8 @@
 // Pairs are recomputed from the lists, not stored. The source-side terms
 // are summed over the wave's sinks and added with FP64 atomics.
 // Far field (Sec. 2.4.2, Eq. 6): per sink leaf the cotangent moments G0, G1,
-// G2 (far_math.h), then
+// G2, stored symmetrised (far_math.h: only their symmetric parts reach Psi),
+// then
 //   dr_a += J g_a + H[g_a, d_a]                       (d_a = r_a - com_A)
 //   com_A receives cot = sum_B d(G2:H/2)/dR  ->  dr_a += m_a/M_A cot,
 //                                              dm_a += cot . d_a / M_A
@@ -32,7 +33,8 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kAdj = 10;    // M, R(3), Q(6)
-constexpr int kMom = 30;    // G0(3), G1(9), G2(18)
+constexpr int kAcc = 30;    // G0(3), G1(9), G2(18) while accumulating
+constexpr int kMom = 23;    // S1(3), S2(6), S3(10), t1, sg(3): far_math.h SymMoments
 constexpr int kLeafC = 22;  // 19 far coefficients + cot(3)
 
 using rcbfar::hidx;
@@ -78,12 +80,13 @@ struct VjpArgs {
     const float *fdx, *fdy, *fdz, *fm, *fh;
     const int32_t *pid;
     const void *gx, *gy, *gz;
-    double *mom;    // kMom per leaf
+    double *mom;    // kMom per leaf: symmetrised cotangent moments
     double *leafc;  // kLeafC per leaf
     double *sink;   // 4 n, tree order: dx dy dz dm
     double *src;    // 4 n, tree order, atomics
-    double *adj;    // kAdj per label, atomics
+    double *adj;    // kAdj per label, atomics; component q of label B at q * nlab + B
     int64_t n;
+    int64_t nlab;
 };
 
 template <bool MIXED>
@@ -101,18 +104,18 @@ __device__ __forceinline__ int leaf_slot(const int32_t (&lf)[8], int32_t pa) {
     return la;
 }
 
-// cotangent moments G0, G1, G2 of every leaf of the group
+// cotangent moments G0, G1, G2 of every leaf of the group, stored symmetrised
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_vjp_moments(VjpArgs a) {
-    __shared__ double acc_all[kWaves][8][kMom];
-    double(*acc)[kMom] = acc_all[threadIdx.x / kWave];
-    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    __shared__ double acc_all[kWaves][8][kAcc];
+    double(*acc)[kAcc] = acc_all[threadIdx.x / kWave];
+    const int64_t gi = wave_index();
     if (gi >= a.ngroup) return;
     const int lane = lane_id();
     const int G = 1 << a.gk;
     const int64_t GL = (a.nleaf >> a.gk) + gi;
     const int32_t sG = a.nfirst[GL], nG = a.ncount[GL];
-    for (int i = lane; i < 8 * kMom; i += kWave) acc[i / kMom][i % kMom] = 0.0;
+    for (int i = lane; i < 8 * kAcc; i += kWave) acc[i / kAcc][i % kAcc] = 0.0;
     __builtin_amdgcn_wave_barrier();
     int32_t lf[8];
 #pragma unroll
@@ -144,22 +147,45 @@ __global__ __launch_bounds__(kBlock) void k_vjp_moments(VjpArgs a) {
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (int i = lane; i < G * kMom; i += kWave)
-        a.mom[(gi * G + i / kMom) * kMom + i % kMom] = acc[i / kMom][i % kMom];
+    if (lane < G) {
+        const double *m = acc[lane];
+        rcbfar::SymMoments S;
+        rcbfar::sym_moments(m, m + 3, m + 12, S);
+        double *o = a.mom + (gi * G + lane) * kMom;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) o[q] = S.S1[q];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) o[3 + q] = S.S2[q];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) o[9 + q] = S.S3[q];
+        o[19] = S.t1;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) o[20 + q] = S.sg[q];
+    }
 }
 
 // far field: per group, lanes = far entries; the group's leaves are taken in
-// turn with their centre of mass and cotangent moments held uniform, so each
-// lane sums its entry's node adjoint over the leaves that accepted it and
-// issues one set of atomics; the sink-centre term is summed per leaf (LDS).
+// turn with their centre of mass and cotangent moments held uniform (scalar
+// registers), so each lane sums its entry's node adjoint over the leaves that
+// accepted it and issues one set of atomics. The sink-centre term is kept per
+// lane and leaf in LDS and summed over the lanes once per group.
+struct VjpFarShared {
+    double cot[8][3][kWave / 2];   // per lane pair and leaf
+    double mom[8][kMom];       // the group's leaves: symmetrised moments
+    double com[8][3];          // and centres of mass
+};
+
 __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
-    __shared__ double cot_all[kWaves][8][3];
-    double(*cotl)[3] = cot_all[threadIdx.x / kWave];
-    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    __shared__ VjpFarShared sh_all[kWaves];
+    VjpFarShared &sh = sh_all[threadIdx.x / kWave];
+    double(*cotp)[3][kWave / 2] = sh.cot;
+    const int64_t gi = wave_index();
     if (gi >= a.ngroup) return;
     const int lane = lane_id();
     const int G = 1 << a.gk;
-    if (lane < 24) cotl[lane / 3][lane % 3] = 0.0;
+    for (int i = lane; i < 8 * 3 * (kWave / 2); i += kWave) (&cotp[0][0][0])[i] = 0.0;
+    for (int i = lane; i < G * kMom; i += kWave) sh.mom[i / kMom][i % kMom] = a.mom[gi * G * kMom + i];
+    if (lane < 3 * G) sh.com[lane / 3][lane % 3] = a.ncom[3 * (a.nleaf + gi * G) + lane];
     tile_sync();
     const int64_t f0 = a.gfar_off[gi], f1 = a.gfar_off[gi + 1];
     for (int64_t e0 = f0; e0 < f1; e0 += kWave) {
@@ -187,41 +213,49 @@ __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
             if (ballot(mine) == 0) continue;
             const int64_t leaf = gi * G + i;
             const int64_t A = a.nleaf + leaf;
-            rcbfar::SinkMoments Gm;
+            // the leaf's moments and centre are the same on every lane
+            const double *mo = sh.mom[i];
+            rcbfar::SymMoments Sm;
 #pragma unroll
-            for (int q = 0; q < 3; ++q) Gm.G0[q] = a.mom[leaf * kMom + q];
+            for (int q = 0; q < 3; ++q) Sm.S1[q] = uniform_f64(mo[q]);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) Gm.G1[q] = a.mom[leaf * kMom + 3 + q];
+            for (int q = 0; q < 6; ++q) Sm.S2[q] = uniform_f64(mo[3 + q]);
 #pragma unroll
-            for (int q = 0; q < 18; ++q) Gm.G2[q] = a.mom[leaf * kMom + 12 + q];
-            rcbfar::sink_traces(Gm);
+            for (int q = 0; q < 10; ++q) Sm.S3[q] = uniform_f64(mo[9 + q]);
+            Sm.t1 = uniform_f64(mo[19]);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) Sm.sg[q] = uniform_f64(mo[20 + q]);
+            const double cA[3] = {uniform_f64(sh.com[i][0]), uniform_f64(sh.com[i][1]),
+                                  uniform_f64(sh.com[i][2])};
             double ct[3] = {0.0, 0.0, 0.0};
             if (mine) {
                 double rho[3], aM, aQ[6];
-                rcbfar::far_pair_adjoint_cf(a.ncom[3 * A] - cB[0], a.ncom[3 * A + 1] - cB[1],
-                                            a.ncom[3 * A + 2] - cB[2], MB, qq, Gm, rho, ct, aM, aQ);
+                rcbfar::far_pair_adjoint_sym(cA[0] - cB[0], cA[1] - cB[1], cA[2] - cB[2], MB, qq, Sm,
+                                             rho, ct, aM, aQ);
                 ad[0] += aM;
 #pragma unroll
                 for (int u = 0; u < 3; ++u) ad[1 + u] -= rho[u];
 #pragma unroll
                 for (int q = 0; q < 6; ++q) ad[4 + q] += aQ[q];
             }
+            // lanes 2j and 2j + 1 add their terms, the even lane keeps the sum
 #pragma unroll
             for (int u = 0; u < 3; ++u) {
-                const double v = wave_sum(ct[u]);
-                if (lane == 0) cotl[i][u] += v;
+                const double t = ct[u] + swap_adjacent_lanes(ct[u]);
+                if (!(lane & 1)) cotp[i][u][lane >> 1] += t;
             }
         }
         if (emask) {
-            double *dst = a.adj + kAdj * B;
 #pragma unroll
-            for (int q = 0; q < kAdj; ++q) atomicAdd(dst + q, ad[q]);
+            for (int q = 0; q < kAdj; ++q) atomicAdd(a.adj + q * a.nlab + B, ad[q]);
         }
     }
     tile_sync();
     if (lane < 3 * G) {
         const int i = lane / 3, u = lane % 3;
-        a.leafc[(gi * G + i) * kLeafC + 19 + u] = cotl[i][u];
+        double v = 0.0;
+        for (int l = 0; l < kWave / 2; ++l) v += cotp[i][u][l];
+        a.leafc[(gi * G + i) * kLeafC + 19 + u] = v;
     }
 }
 
@@ -250,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
     using T = typename std::conditional<MIXED, float, double>::type;
     __shared__ VjpShared<T> sh_all[kWaves];
     VjpShared<T> &sh = sh_all[threadIdx.x / kWave];
-    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t gi = wave_index();
     if (gi >= a.ngroup) return;
     const int lane = lane_id();
     const int G = 1 << a.gk;
@@ -389,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_vjp_push(VjpArgs a, void *dx, void *dy, void *dz,
                                                      void *dm) {
-    const int64_t li = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t li = wave_index();
     if (li >= a.nleaf) return;
     const int64_t A = a.nleaf + li;
     const int32_t sA = a.nfirst[A], nA = a.ncount[A];
@@ -401,7 +435,9 @@ __global__ __launch_bounds__(kBlock) void k_vjp_push(VjpArgs a, void *dx, void *
                         a.sink[2 * a.n + p] + a.src[2 * a.n + p]};
         double dmb = a.sink[3 * a.n + p] + a.src[3 * a.n + p];
         for (int64_t B = A; B >= 1; B >>= 1) {
-            const double *ad = a.adj + kAdj * B;
+            double ad[kAdj];
+#pragma unroll
+            for (int q = 0; q < kAdj; ++q) ad[q] = a.adj[q * a.nlab + B];
             const double aM = ad[0];
             const double aR[3] = {ad[1], ad[2], ad[3]};
             const double Q[3][3] = {{ad[4], ad[5], ad[6]}, {ad[5], ad[7], ad[8]}, {ad[6], ad[8], ad[9]}};
@@ -450,7 +486,7 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     RCB_HIP(hipMemsetAsync(adj, 0, sizeof(double) * kAdj * t->nlab, s));
     VjpArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
               t->gnear_off, t->gfar_off, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
-              t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, src, adj, n};
+              t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, src, adj, n, t->nlab};
     const unsigned gridg = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     const unsigned gridl = (unsigned)((t->nleaf + kWaves - 1) / kWaves);
     const bool mixed = t->p.precision == RCB_MIXED;
@@ -459,6 +495,7 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     RCB_LAUNCH_CHECK("k_vjp_moments");
     st = far_coefficients(t, leafc, kLeafC, s);
     if (st != RCB_OK) return st;
+
     k_vjp_far<<<gridg, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_vjp_far");
     if (mixed) k_vjp_near<true><<<gridg, kBlock, 0, s>>>(a);

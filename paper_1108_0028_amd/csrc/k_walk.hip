@@ -45,7 +45,7 @@ template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
     __shared__ uint64_t stk_all[kWaves][kGStack];
     uint64_t *stk = stk_all[threadIdx.x / kWave];
-    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t gi = wave_index();
     if (gi >= w.ngroup) return;
     const int lane = lane_id();
     const int G = 1 << w.gk;
@@ -152,27 +152,29 @@ __global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
     }
 }
 
-// Sort each group's near list by label (bitonic network in LDS, one wave per
-// group). Longer lists are queued for k_sort_long.
-__global__ __launch_bounds__(kBlock) void k_sort_near(int64_t ngroup, const int64_t *__restrict__ near_off,
-                                                      uint64_t *__restrict__ near_list,
-                                                      int32_t *__restrict__ flag,
-                                                      int32_t *__restrict__ long_q) {
-    __shared__ uint64_t buf_all[kWaves][kGStack];
+// Sort each group's list by label (bitonic network in LDS, one wave per
+// group, CAP entries at most). Longer lists are queued for k_sort_long.
+template <int CAP, int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void k_sort_lists(int64_t ngroup,
+                                                              const int64_t *__restrict__ off,
+                                                              uint64_t *__restrict__ list,
+                                                              int32_t *__restrict__ nqueued,
+                                                              int32_t *__restrict__ long_q) {
+    __shared__ uint64_t buf_all[WAVES][CAP];
     uint64_t *buf = buf_all[threadIdx.x / kWave];
-    const int64_t gi = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t gi = wave_index();
     if (gi >= ngroup) return;
     const int lane = lane_id();
-    const int64_t nbase = near_off[gi];
-    const int64_t nn = near_off[gi + 1] - nbase;
+    const int64_t nbase = off[gi];
+    const int64_t nn = off[gi + 1] - nbase;
     if (nn <= 1) return;
-    if (nn > kGStack) {
-        if (lane == 0) long_q[atomicAdd(&flag[2], 1)] = (int32_t)gi;
+    if (nn > CAP) {
+        if (lane == 0) long_q[atomicAdd(nqueued, 1)] = (int32_t)gi;
         return;
     }
     int P = 1;
     while (P < nn) P <<= 1;
-    for (int i = lane; i < P; i += kWave) buf[i] = i < nn ? near_list[nbase + i] : (uint64_t)kLabelMask;
+    for (int i = lane; i < P; i += kWave) buf[i] = i < nn ? list[nbase + i] : (uint64_t)kLabelMask;
     __builtin_amdgcn_wave_barrier();
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -190,19 +192,19 @@ __global__ __launch_bounds__(kBlock) void k_sort_near(int64_t ngroup, const int6
             __builtin_amdgcn_wave_barrier();
         }
     }
-    for (int i = lane; i < nn; i += kWave) near_list[nbase + i] = buf[i];
+    for (int i = lane; i < nn; i += kWave) list[nbase + i] = buf[i];
 }
 
-// Sort of the queued long near lists, one block each, in global memory:
+// Sort of the queued long lists, one block each, in global memory:
 // bitonic network in its all-ascending form (the first merge step of each
 // stage compares i with i ^ (size - 1)), so the virtual +inf padding past the
 // list end never moves and pairs reaching past the end are simply skipped.
 __global__ __launch_bounds__(1024) void k_sort_long(const int32_t *__restrict__ long_q,
-                                                    const int64_t *__restrict__ near_off,
-                                                    uint64_t *__restrict__ near_list) {
+                                                    const int64_t *__restrict__ off,
+                                                    uint64_t *__restrict__ list) {
     const int64_t gi = long_q[blockIdx.x];
-    uint64_t *v = near_list + near_off[gi];
-    const int64_t nn = near_off[gi + 1] - near_off[gi];
+    uint64_t *v = list + off[gi];
+    const int64_t nn = off[gi + 1] - off[gi];
     int64_t P = 1;
     while (P < nn) P <<= 1;
     for (int64_t size = 2; size <= P; size <<= 1) {
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(int64_t nleaf, int gk,
                                                    const int64_t *__restrict__ foff,
                                                    int32_t *__restrict__ nlist,
                                                    int32_t *__restrict__ flist) {
-    const int64_t li = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+    const int64_t li = wave_index();
     if (li >= nleaf) return;
     const int64_t gi = li >> gk;
     const int bit = (int)(li & ((1 << gk) - 1));
@@ -316,8 +318,8 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
         long_q = (int32_t *)dalloc(t, sizeof(int32_t) * nlong, s, tmp);
         if (!long_q) return RCB_ENOMEM;
     }
-    k_sort_near<<<grid, kBlock, 0, s>>>(NG, t->gnear_off, t->gnear, t->dflag, long_q);
-    RCB_LAUNCH_CHECK("k_sort_near");
+    k_sort_lists<kGStack, kWaves><<<grid, kBlock, 0, s>>>(NG, t->gnear_off, t->gnear, t->dflag + 2, long_q);
+    RCB_LAUNCH_CHECK("k_sort_lists<near>");
     if (nlong > 0) {
         k_sort_long<<<nlong, 1024, 0, s>>>(long_q, t->gnear_off, t->gnear);
         RCB_LAUNCH_CHECK("k_sort_long");

@@ -118,6 +118,14 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Index of this wave in the grid, passed through readfirstlane so that the
+// compiler treats it, and everything derived from it, as wave-uniform
+// (scalar registers and scalar loads).
+__device__ __forceinline__ int64_t wave_index() {
+    const uint32_t w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    return (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)w);
+}
+
 // Canonical sum of the 64 lane values: adjacent lanes first, then pairs of
 // pairs (xor butterfly; both partners of a pair get the same, commutative sum).
 __device__ __forceinline__ double wave_sum(double v) {
@@ -160,6 +168,28 @@ __device__ __forceinline__ int64_t wave_excl_scan64(int64_t v) {
         if (l >= o) x += y;
     }
     return x - v;
+}
+// A value known to be equal on every lane, moved to scalar registers.
+__device__ __forceinline__ double uniform_f64(double v) {
+    union {
+        double d;
+        int w[2];
+    } u;
+    u.d = v;
+    u.w[0] = __builtin_amdgcn_readfirstlane(u.w[0]);
+    u.w[1] = __builtin_amdgcn_readfirstlane(u.w[1]);
+    return u.d;
+}
+// The value of the other lane of this lane's pair (2j, 2j + 1), by DPP.
+__device__ __forceinline__ double swap_adjacent_lanes(double v) {
+    union {
+        double d;
+        int w[2];
+    } u, r;
+    u.d = v;
+    r.w[0] = __builtin_amdgcn_mov_dpp(u.w[0], 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    r.w[1] = __builtin_amdgcn_mov_dpp(u.w[1], 0xB1, 0xF, 0xF, false);
+    return r.d;
 }
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 __device__ __forceinline__ int rank_below(uint64_t mask) {

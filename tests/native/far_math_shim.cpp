@@ -22,15 +22,12 @@ void shim_pair_adjoint(double x, double y, double z, double M, const double *q6,
     rcbfar::far_pair_adjoint(x, y, z, M, q6, G, rho, cot, *adjM, adjQ);
 }
 
-void shim_pair_adjoint_cf(double x, double y, double z, double M, const double *q6, const double *G0,
-                          const double *G1, const double *G2, double *rho, double *cot, double *adjM,
-                          double *adjQ) {
-    rcbfar::SinkMoments G;
-    for (int i = 0; i < 3; ++i) G.G0[i] = G0[i];
-    for (int i = 0; i < 9; ++i) G.G1[i] = G1[i];
-    for (int i = 0; i < 18; ++i) G.G2[i] = G2[i];
-    rcbfar::sink_traces(G);
-    rcbfar::far_pair_adjoint_cf(x, y, z, M, q6, G, rho, cot, *adjM, adjQ);
+void shim_pair_adjoint_sym(double x, double y, double z, double M, const double *q6, const double *G0,
+                           const double *G1, const double *G2, double *rho, double *cot, double *adjM,
+                           double *adjQ) {
+    rcbfar::SymMoments S;
+    rcbfar::sym_moments(G0, G1, G2, S);
+    rcbfar::far_pair_adjoint_sym(x, y, z, M, q6, S, rho, cot, *adjM, adjQ);
 }
 
 int shim_jidx(int i, int l) { return rcbfar::jidx(i, l); }

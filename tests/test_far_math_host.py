@@ -27,7 +27,7 @@ def _shim():
     dp = C.POINTER(C.c_double)
     L.shim_m2l.argtypes = [C.c_double] * 4 + [dp, dp]
     L.shim_pair_adjoint.argtypes = [C.c_double] * 4 + [dp] * 8
-    L.shim_pair_adjoint_cf.argtypes = [C.c_double] * 4 + [dp] * 8
+    L.shim_pair_adjoint_sym.argtypes = [C.c_double] * 4 + [dp] * 8
     L.shim_jidx.argtypes = [C.c_int, C.c_int]
     L.shim_hidx.argtypes = [C.c_int] * 3
     return L
@@ -70,7 +70,7 @@ def test_forward_m2l_matches_oracle(seed):
         assert c[9 + k] == pytest.approx(H[i, l, m], rel=1e-11, abs=1e-13 * np.abs(H).max())
 
 
-@pytest.mark.parametrize("form", ["shim_pair_adjoint", "shim_pair_adjoint_cf"])
+@pytest.mark.parametrize("form", ["shim_pair_adjoint", "shim_pair_adjoint_sym"])
 @pytest.mark.parametrize("seed", range(6))
 def test_pair_adjoint_matches_oracle_tensors(seed, form):
     L = _shim()
