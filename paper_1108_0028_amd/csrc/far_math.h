@@ -75,7 +75,14 @@ RCB_HD constexpr int hidx(int i, int l, int m) {
 }
 
 // f (0..2), J (3..8, jidx), H (9..18, hidx) of one source, accumulated.
+// With g = b2 x + c1 q, u = e3 x / 3 + c2 q and Qc = c1 Q the closed forms
+// above regroup as
+//   f_i = a1 x_i + c0 q_i
+//   J_il = g_i x_l + c1 q_l x_i + c0 Q_il + a1 d_il
+//   H_ilm = sum over the three choices of the single index j (the other
+//           two, k and n): u_j x_k x_n + Qc_kn x_j + d_kn g_j
 RCB_HD void m2l_accumulate(double x, double y, double z, double M, const double qq[6], double (&c)[19]) {
+    const double X[3] = {x, y, z};
     const double r2 = (x * x + y * y) + z * z;
     const double rinv = rsqrt64(r2);
     const double rinv2 = rinv * rinv;
@@ -84,39 +91,51 @@ RCB_HD void m2l_accumulate(double x, double y, double z, double M, const double 
     const double D3 = -5.0 * D2 * rinv2;
     const double D4 = -7.0 * D3 * rinv2;
     const double D5 = -9.0 * D4 * rinv2;
-    const double X[3] = {x, y, z};
-    const double Qm[3][3] = {{qq[0], qq[1], qq[2]}, {qq[1], qq[3], qq[4]}, {qq[2], qq[4], qq[5]}};
-    double qv[3];
-    for (int i = 0; i < 3; ++i) qv[i] = Qm[i][0] * x + Qm[i][1] * y + Qm[i][2] * z;
-    const double s = qv[0] * x + qv[1] * y + qv[2] * z;
+    double q[3];
+    for (int i = 0; i < 3; ++i) q[i] = qq[jidx(i, 0)] * x + qq[jidx(i, 1)] * y + qq[jidx(i, 2)] * z;
+    const double s = q[0] * x + q[1] * y + q[2] * z;
     const double sixth = 1.0 / 6.0, third = 1.0 / 3.0;
     const double a1 = M * D1 + sixth * D3 * s;
     const double b2 = M * D2 + sixth * D4 * s;
     const double e3 = M * D3 + sixth * D5 * s;
     const double c0 = third * D2, c1 = third * D3, c2 = third * D4;
-    for (int i = 0; i < 3; ++i) c[i] += a1 * X[i] + c0 * qv[i];
+    double g[3], u[3], cq[3], xx[6], Qc[6];
+    for (int i = 0; i < 3; ++i) {
+        g[i] = b2 * X[i] + c1 * q[i];
+        u[i] = (third * e3) * X[i] + c2 * q[i];
+        cq[i] = c1 * q[i];
+    }
     for (int i = 0; i < 3; ++i)
         for (int l = i; l < 3; ++l) {
-            double v = b2 * X[i] * X[l] + c1 * (qv[i] * X[l] + qv[l] * X[i]) + c0 * Qm[i][l];
+            xx[jidx(i, l)] = X[i] * X[l];
+            Qc[jidx(i, l)] = c1 * qq[jidx(i, l)];
+        }
+    // every term goes straight into its accumulator (one FMA each)
+    for (int i = 0; i < 3; ++i) {
+        c[i] += a1 * X[i];
+        c[i] += c0 * q[i];
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int l = i; l < 3; ++l) {
+            double &v = c[3 + jidx(i, l)];
+            v += g[i] * X[l];
+            v += cq[l] * X[i];
+            v += c0 * qq[jidx(i, l)];
             if (i == l) v += a1;
-            c[3 + jidx(i, l)] += v;
         }
     for (int i = 0; i < 3; ++i)
         for (int l = i; l < 3; ++l)
             for (int m = l; m < 3; ++m) {
-                double v = e3 * X[i] * X[l] * X[m];
-                double dd = 0.0;
-                if (i == l) dd += X[m];
-                if (i == m) dd += X[l];
-                if (l == m) dd += X[i];
-                v += b2 * dd;
-                v += c2 * (qv[i] * X[l] * X[m] + qv[l] * X[i] * X[m] + qv[m] * X[i] * X[l]);
-                double w = Qm[l][m] * X[i] + Qm[i][m] * X[l] + Qm[i][l] * X[m];
-                if (l == m) w += qv[i];
-                if (i == m) w += qv[l];
-                if (i == l) w += qv[m];
-                v += c1 * w;
-                c[9 + hidx(i, l, m)] += v;
+                double &v = c[9 + hidx(i, l, m)];
+                v += u[i] * xx[jidx(l, m)];
+                v += u[l] * xx[jidx(i, m)];
+                v += u[m] * xx[jidx(i, l)];
+                v += Qc[jidx(l, m)] * X[i];
+                v += Qc[jidx(i, m)] * X[l];
+                v += Qc[jidx(i, l)] * X[m];
+                if (l == m) v += g[i];
+                if (i == m) v += g[l];
+                if (i == l) v += g[m];
             }
 }
 

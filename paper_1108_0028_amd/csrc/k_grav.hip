@@ -23,6 +23,7 @@
 #include "far_math.h"
 #include "near_tile.h"
 #include "rcb_internal.h"
+#include "soft.h"
 
 namespace rcb {
 namespace {
@@ -33,33 +34,6 @@ constexpr int kWaves = kBlock / kWave;
 using rcbfar::hidx;
 using rcbfar::jidx;
 using rcbfar::m2l_accumulate;
-
-// F = S(q)/r of the cubic-spline softening
-__device__ __forceinline__ double soft_F(double r2, double hab) {
-    const double rinv = r2 > 0.0 ? rcbfar::rsqrt64(r2) : 0.0;
-    const double r = r2 * rinv;
-    const double hinv = rcbfar::rcp64(hab);
-    const double q = r * hinv;
-    const double h3 = hinv * hinv * hinv;
-    const double r3 = rinv * rinv * rinv;
-    const double in = h3 * (4.0 / 3.0 + q * q * (-6.0 / 5.0 + 0.5 * q));
-    const double mid = h3 * (8.0 / 3.0 + q * (-3.0 + q * (6.0 / 5.0 - q * (1.0 / 6.0)))) -
-                       r3 * (1.0 / 15.0);
-    return q < 1.0 ? in : (q < 2.0 ? mid : r3);
-}
-
-__device__ __forceinline__ float soft_Ff(float r2, float hab) {
-    const float rinv = r2 > 0.0f ? __frsqrt_rn(r2) : 0.0f;
-    const float r = r2 * rinv;
-    const float hinv = __frcp_rn(hab);
-    const float q = r * hinv;
-    const float h3 = hinv * hinv * hinv;
-    const float r3 = rinv * rinv * rinv;
-    const float in = h3 * (4.0f / 3.0f + q * q * (-1.2f + 0.5f * q));
-    const float mid = h3 * (8.0f / 3.0f + q * (-3.0f + q * (1.2f - q * (1.0f / 6.0f)))) -
-                      r3 * (1.0f / 15.0f);
-    return q < 1.0f ? in : (q < 2.0f ? mid : r3);
-}
 
 struct GravArgs {
     int64_t nleaf;
@@ -122,11 +96,13 @@ struct alignas(16) SrcD {
     double x, y, z, m, h;
 };
 
+// tile: 64 staged sources, then 64 zero-mass sources that pad the last
+// partial row of slices, so the pair loop needs no bounds test
 template <bool MIXED>
 struct GravShared {
     double coef[8][19];
     EntryChunk ec;
-    typename std::conditional<MIXED, SrcF, SrcD>::type tile[kWave];
+    typename std::conditional<MIXED, SrcF, SrcD>::type tile[2 * kWave];
 };
 
 template <bool MIXED>
@@ -141,6 +117,11 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
     const int64_t GL = (g.nleaf >> g.gk) + gi;   // group node label
     if (g.ncount[GL] == 0) return;
     group_far(g, gi, sh.coef);
+    using Src = typename std::conditional<MIXED, SrcF, SrcD>::type;
+    Src dummy;
+    dummy.x = dummy.y = dummy.z = dummy.m = 0;
+    dummy.h = 1;
+    sh.tile[kWave + lane] = dummy;
     const int64_t n0 = g.gnear_off[gi], n1 = g.gnear_off[gi + 1];
     for (int li = 0; li < G; ++li) {
         const int64_t A = g.nleaf + gi * G + li;
@@ -169,6 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
                 const int tot = load_entry_chunk(g.gnear, g.nfirst, g.ncount, e0, n1, 1u << li, sh.ec);
                 for (int t = 0; t < tot; t += kWave) {
                     const int q = t + lane;
+                    if (q >= tot) sh.tile[lane] = dummy;
                     if (q < tot) {
                         const int k = entry_of(sh.ec, q);
                         const int64_t pb = (int64_t)sh.ec.fB[k] + (q - sh.ec.pos[k]);
@@ -193,13 +175,12 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
                     }
                     tile_sync();
                     const int nt = tot - t < kWave ? tot - t : kWave;
-                    for (int u = L.slice; u < nt; u += L.J) {
-                        const auto s = sh.tile[u];
+                    const int rows = (nt + L.J - 1) / L.J;
+                    for (int r = 0; r < rows; ++r) {
+                        const auto s = sh.tile[r * L.J + L.slice];
                         const T vx = xa - s.x, vy = ya - s.y, vz = za - s.z;
                         const T r2 = (vx * vx + vy * vy) + vz * vz;
-                        T F;
-                        if constexpr (MIXED) F = soft_Ff(r2, 0.5f * (ha + s.h)) * s.m;
-                        else F = soft_F(r2, 0.5 * (ha + s.h)) * s.m;
+                        const T F = soft_F<T>(r2, ha + s.h) * s.m;
                         ax -= F * vx;
                         ay -= F * vy;
                         az -= F * vz;

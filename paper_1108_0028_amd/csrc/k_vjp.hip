@@ -26,6 +26,7 @@
 #include "far_math.h"
 #include "near_tile.h"
 #include "rcb_internal.h"
+#include "soft.h"
 
 namespace rcb {
 namespace {
@@ -39,34 +40,6 @@ constexpr int kLeafC = 22;  // 19 far coefficients + cot(3)
 
 using rcbfar::hidx;
 using rcbfar::jidx;
-
-template <typename T>
-__device__ __forceinline__ void soft_FdF(T r2, T hab, T &F, T &dFr) {
-    T rinv, hinv;
-    if constexpr (sizeof(T) == 8) {
-        rinv = r2 > (T)0 ? rcbfar::rsqrt64(r2) : (T)0;
-        hinv = rcbfar::rcp64(hab);
-    } else {
-        rinv = r2 > (T)0 ? __frsqrt_rn(r2) : (T)0;
-        hinv = __frcp_rn(hab);
-    }
-    const T r = r2 * rinv;
-    const T q = r * hinv;
-    const T h2 = hinv * hinv;
-    const T h3 = h2 * hinv;
-    const T h4 = h2 * h2;
-    const T h5 = h4 * hinv;
-    const T r3 = rinv * rinv * rinv;
-    const T r5 = r3 * rinv * rinv;
-    const T Fin = h3 * ((T)(4.0 / 3.0) + q * q * ((T)(-6.0 / 5.0) + (T)0.5 * q));
-    const T dFin = h5 * ((T)(-12.0 / 5.0) + (T)1.5 * q);
-    const T Fmid = h3 * ((T)(8.0 / 3.0) + q * ((T)-3.0 + q * ((T)(6.0 / 5.0) - q * (T)(1.0 / 6.0)))) -
-                   r3 * (T)(1.0 / 15.0);
-    const T dFmid = h5 * ((T)(12.0 / 5.0) - (T)0.5 * q) - (T)3.0 * h4 * rinv + (T)0.2 * r5;
-    const bool in = q < (T)1, mid = q < (T)2;
-    F = in ? Fin : (mid ? Fmid : r3);
-    dFr = in ? dFin : (mid ? dFmid : (T)-3.0 * r5);
-}
 
 struct VjpArgs {
     int64_t nleaf;
@@ -362,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
                             const T v[3] = {sx - sh.t.x[j], sy - sh.t.y[j], sz - sh.t.z[j]};
                             const T r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
                             T F, dFr;
-                            soft_FdF<T>(r2, (T)0.5 * (ha + sh.t.h[j]), F, dFr);
+                            soft_FdF<T>(r2, ha + sh.t.h[j], F, dFr);
                             const T vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
                             const T mb = sh.t.m[j];
 #pragma unroll

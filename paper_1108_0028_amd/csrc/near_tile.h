@@ -51,7 +51,7 @@ __device__ __forceinline__ int load_entry_chunk(const uint64_t *__restrict__ gne
     if (lane == kWave - 1) ec.pos[kWave] = p + cB;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    return ec.pos[kWave];
+    return __builtin_amdgcn_readfirstlane(ec.pos[kWave]);   // the same on every lane
 }
 
 // entry k of the chunk holding source q (largest k with pos[k] <= q)
