@@ -41,9 +41,11 @@ struct alignas(16) SrcN {
     int32_t pb;
 };
 
+// tile: 64 staged sources, then 64 sources that can never be neighbours
+// (pb = -1 at infinite distance), padding the last partial row of slices
 struct NeighShared {
     EntryChunk ec;
-    SrcN tile[kWave];
+    SrcN tile[2 * kWave];
 };
 
 template <bool FILL>
@@ -56,6 +58,10 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
     const int G = 1 << a.gk;
     const int64_t GL = (a.nleaf >> a.gk) + gi;
     if (a.ncount[GL] == 0) return;
+    SrcN dummy;
+    dummy.x = dummy.y = dummy.z = __builtin_inf();
+    dummy.pb = -1;
+    sh.tile[kWave + lane] = dummy;
     const int64_t n0 = a.gnear_off[gi], n1 = a.gnear_off[gi + 1];
     for (int li = 0; li < G; ++li) {
         const int64_t A = a.nleaf + gi * G + li;
@@ -78,6 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
                     load_entry_chunk(a.gnear, a.nfirst, a.ncount, e0, n1, 1u << (8 + li), sh.ec);
                 for (int t = 0; t < tot; t += kWave) {
                     const int q = t + lane;
+                    if (q >= tot) sh.tile[lane] = dummy;
                     if (q < tot) {
                         const int k = entry_of(sh.ec, q);
                         const int32_t pb = sh.ec.fB[k] + (q - sh.ec.pos[k]);
@@ -91,14 +98,9 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
                     tile_sync();
                     const int nt = tot - t < kWave ? tot - t : kWave;
                     for (int u0 = 0; u0 < nt; u0 += L.J) {
-                        const int u = u0 + L.slice;
-                        bool hit = false;
-                        int32_t pb = 0;
-                        if (u < nt) {
-                            const SrcN s = sh.tile[u];
-                            pb = s.pb;
-                            hit = pb != pa && dist2(xa, ya, za, s.x, s.y, s.z) < lim;
-                        }
+                        const SrcN s = sh.tile[u0 + L.slice];
+                        const int32_t pb = s.pb;
+                        const bool hit = pb != pa && dist2(xa, ya, za, s.x, s.y, s.z) < lim;
                         if (FILL) {
                             const uint64_t bal = ballot(hit) & segmask;
                             if (hit) a.ids[obase + cnt + rank_below(bal)] = a.pid[pb];

@@ -391,40 +391,64 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
     }
 }
 
+// One node's adjoint (aM, aR, aQ) pushed to a particle at r of mass mb
+// through M, COM and Q of the node.
+__device__ __forceinline__ void push_node(const double (&ad)[kAdj], double MB, const double (&cB)[3],
+                                          const double (&r)[3], double mb, double (&dr)[3],
+                                          double &dmb) {
+    const double Q[3][3] = {{ad[4], ad[5], ad[6]}, {ad[5], ad[7], ad[8]}, {ad[6], ad[8], ad[9]}};
+    const double d[3] = {r[0] - cB[0], r[1] - cB[1], r[2] - cB[2]};
+    const double trQ = Q[0][0] + Q[1][1] + Q[2][2];
+    const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+    double Qd[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) Qd[l] = Q[l][0] * d[0] + Q[l][1] * d[1] + Q[l][2] * d[2];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) dr[l] += ad[1 + l] * mb / MB + mb * (6.0 * Qd[l] - 2.0 * trQ * d[l]);
+    dmb += ad[0] + (ad[1] * d[0] + ad[2] * d[1] + ad[3] * d[2]) / MB +
+           3.0 * (d[0] * Qd[0] + d[1] * Qd[1] + d[2] * Qd[2]) - d2 * trQ;
+}
+
 // node adjoints -> particles along each particle's ancestor chain; then the
-// three parts are summed and written in caller order.
+// three parts are summed and written in caller order. One wave per group,
+// lanes over the group's particles: the chain below the group node differs
+// per lane, the chain from the group node up is the same for every lane.
 template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_vjp_push(VjpArgs a, void *dx, void *dy, void *dz,
-                                                     void *dm) {
-    const int64_t li = wave_index();
-    if (li >= a.nleaf) return;
-    const int64_t A = a.nleaf + li;
-    const int32_t sA = a.nfirst[A], nA = a.ncount[A];
-    for (int i = lane_id(); i < nA; i += kWave) {
-        const int64_t p = (int64_t)sA + i;
+__global__ __launch_bounds__(kBlock) void k_vjp_push(VjpArgs a, const double *__restrict__ adj,
+                                                     const double *__restrict__ ncom,
+                                                     const double *__restrict__ nM, void *dx, void *dy,
+                                                     void *dz, void *dm) {
+    const int64_t gi = wave_index();
+    if (gi >= a.ngroup) return;
+    const int G = 1 << a.gk;
+    const int64_t GL = (a.nleaf >> a.gk) + gi;
+    const int32_t sG = a.nfirst[GL], nG = a.ncount[GL];
+    int32_t lf[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lf[i] = i < G ? a.nfirst[a.nleaf + gi * G + i] : 0x7fffffff;
+    for (int s0 = 0; s0 < nG; s0 += kWave) {
+        const int si = s0 + lane_id();
+        if (si >= nG) continue;
+        const int64_t p = (int64_t)sG + si;
         const double r[3] = {a.px[p], a.py[p], a.pz[p]};
         const double mb = a.pm[p];
         double dr[3] = {a.sink[p] + a.src[p], a.sink[a.n + p] + a.src[a.n + p],
                         a.sink[2 * a.n + p] + a.src[2 * a.n + p]};
         double dmb = a.sink[3 * a.n + p] + a.src[3 * a.n + p];
-        for (int64_t B = A; B >= 1; B >>= 1) {
+        const int64_t A = a.nleaf + gi * G + leaf_slot(lf, (int32_t)p);
+        for (int64_t B = A; B > GL; B >>= 1) {
             double ad[kAdj];
 #pragma unroll
-            for (int q = 0; q < kAdj; ++q) ad[q] = a.adj[q * a.nlab + B];
-            const double aM = ad[0];
-            const double aR[3] = {ad[1], ad[2], ad[3]};
-            const double Q[3][3] = {{ad[4], ad[5], ad[6]}, {ad[5], ad[7], ad[8]}, {ad[6], ad[8], ad[9]}};
-            const double MB = a.nM[B];
-            const double d[3] = {r[0] - a.ncom[3 * B], r[1] - a.ncom[3 * B + 1], r[2] - a.ncom[3 * B + 2]};
-            const double trQ = Q[0][0] + Q[1][1] + Q[2][2];
-            const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-            double Qd[3];
+            for (int q = 0; q < kAdj; ++q) ad[q] = adj[q * a.nlab + B];
+            const double cB[3] = {ncom[3 * B], ncom[3 * B + 1], ncom[3 * B + 2]};
+            push_node(ad, nM[B], cB, r, mb, dr, dmb);
+        }
+        for (int64_t B = GL; B >= 1; B >>= 1) {   // wave-uniform
+            double ad[kAdj];
 #pragma unroll
-            for (int l = 0; l < 3; ++l) Qd[l] = Q[l][0] * d[0] + Q[l][1] * d[1] + Q[l][2] * d[2];
-#pragma unroll
-            for (int l = 0; l < 3; ++l) dr[l] += aR[l] * mb / MB + mb * (6.0 * Qd[l] - 2.0 * trQ * d[l]);
-            dmb += aM + (aR[0] * d[0] + aR[1] * d[1] + aR[2] * d[2]) / MB +
-                   3.0 * (d[0] * Qd[0] + d[1] * Qd[1] + d[2] * Qd[2]) - d2 * trQ;
+            for (int q = 0; q < kAdj; ++q) ad[q] = adj[q * a.nlab + B];
+            const double cB[3] = {ncom[3 * B], ncom[3 * B + 1], ncom[3 * B + 2]};
+            push_node(ad, nM[B], cB, r, mb, dr, dmb);
         }
         const int32_t o = a.pid[p];
         if constexpr (MIXED) {
@@ -461,7 +485,6 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
               t->gnear_off, t->gfar_off, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
               t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, src, adj, n, t->nlab};
     const unsigned gridg = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
-    const unsigned gridl = (unsigned)((t->nleaf + kWaves - 1) / kWaves);
     const bool mixed = t->p.precision == RCB_MIXED;
     if (mixed) k_vjp_moments<true><<<gridg, kBlock, 0, s>>>(a);
     else k_vjp_moments<false><<<gridg, kBlock, 0, s>>>(a);
@@ -474,8 +497,8 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     if (mixed) k_vjp_near<true><<<gridg, kBlock, 0, s>>>(a);
     else k_vjp_near<false><<<gridg, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_vjp_near");
-    if (mixed) k_vjp_push<true><<<gridl, kBlock, 0, s>>>(a, dx, dy, dz, dm);
-    else k_vjp_push<false><<<gridl, kBlock, 0, s>>>(a, dx, dy, dz, dm);
+    if (mixed) k_vjp_push<true><<<gridg, kBlock, 0, s>>>(a, adj, t->ncom, t->nM, dx, dy, dz, dm);
+    else k_vjp_push<false><<<gridg, kBlock, 0, s>>>(a, adj, t->ncom, t->nM, dx, dy, dz, dm);
     RCB_LAUNCH_CHECK("k_vjp_push");
     for (void *p : tmp) RCB_HIP(hipFreeAsync(p, s));
     return RCB_OK;
