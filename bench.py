@@ -4,19 +4,19 @@ one MI355X, 4,194,304-particle Plummer sphere in a 10% uniform background
 leaf-relative interactions, FP64 moments and Taylor shift), next to the FP64
 form and the FP64 CPU oracle.
 
-One step = rcb_build + rcb_neighbours_count + rcb_neighbours_fill +
-rcb_gravity on inputs already resident in HBM, tree destroyed at the end.
+One step = rcb_build + rcb_walk + rcb_neighbours_count + rcb_neighbours_fill
++ rcb_gravity on inputs already resident in HBM, tree destroyed at the end.
 
 Prints ONE JSON line (rank 0). Extra fields: the FP64-form throughput, the
-mixed form's error against the FP64 form, per-phase times, the roofline of
-the dominant kernel (timed with HIP events on its stream inside the timed
-region) and the oracle's CPU baseline.
+mixed form's error against the FP64 form, per-phase times (HIP events on the
+library's stream inside the timed region), the roofline of the dominant
+kernel (k_gravity, one launch per step), the per-leaf HBM model of walk +
+gravity, and the oracle's CPU baseline.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -31,18 +31,13 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TFLOPS = 78.6
 
-# Operation counts of one interaction, counted on the implemented formulas
-# (k_grav.hip, far_math.h): an FMA counts as 2, a reciprocal / rsqrt as 1.
+# Algorithmic operation counts of one interaction, frozen from one count of
+# the straightforward formulas (an FMA counts as 2, a reciprocal or
+# reciprocal square root as 1); kernel rewrites that need fewer instructions
+# do not change them.
 FLOP_P2P = 38          # near pair: offset, r^2, rsqrt, rcp, q, both spline branches, m F v
 FLOP_M2L = 226         # far pair: D1..D5, Q x, x.Q.x, 3 f + 6 J + 10 H coefficients
 FLOP_L2P = 66          # per sink: f + J d + H[d, d]/2
-# HBM bytes that one launch of k_gravity<mixed> must move at least once:
-# particles (FP32 d, m, h + int32 id), FP32 outputs, interaction lists and
-# node records (first, count, com, M, Q).
-BYTES_PER_PARTICLE = 20 + 4 + 12
-BYTES_PER_NEAR_ENTRY = 4
-BYTES_PER_FAR_ENTRY = 4
-BYTES_PER_NODE = 8 + 24 + 8 + 48
 
 
 def _args():
@@ -80,29 +75,33 @@ def main():
     torch.cuda.synchronize()
 
     def step(prec, ev=None):
+        """One step: build, walk, neighbour search, gravity; events (if given)
+        bracket each phase on the stream the library launches on."""
+        rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
+        rec(0)
         t = Tree(*arrs, n_ll=a.n_ll, theta=a.theta, precision=prec)
+        rec(1)
+        t.walk()
+        rec(2)
         off, ids = t.neighbours()
-        if ev is not None:
-            ev[0].record()
+        rec(3)
         acc = t.gravity()
-        if ev is not None:
-            ev[1].record()
+        rec(4)
         t.destroy()
         return acc, off
 
     def timed(prec, steps, warmup):
         for _ in range(warmup):
             step(prec)
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(steps):
             step(prec, evs[i])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        kern_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
-        return (t1 - t0) / steps, kern_ms
+        ph = [sum(e[j].elapsed_time(e[j + 1]) for e in evs) / steps for j in range(4)]
+        return (t1 - t0) / steps, dict(zip(("build", "walk", "neighbours", "gravity"), ph))
 
     if a.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
@@ -110,49 +109,51 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    sec, grav_ms = timed(a.precision, a.steps, a.warmup)
+    sec, phases = timed(a.precision, a.steps, a.warmup)
     value = n / sec
+    grav_ms = phases["gravity"]   # one launch of k_gravity per step
 
-    # per-phase split (one extra, untimed step)
-    torch.cuda.synchronize()
-    p0 = time.perf_counter()
-    t = Tree(*arrs, n_ll=a.n_ll, theta=a.theta, precision=a.precision)
-    torch.cuda.synchronize()
-    p1 = time.perf_counter()
-    off, ids = t.neighbours()
-    torch.cuda.synchronize()
-    p2 = time.perf_counter()
-    acc = t.gravity()
-    torch.cuda.synchronize()
-    p3 = time.perf_counter()
     # work counts of this tree for the roofline (outside the timed region)
-    inf = t.info()
+    t = Tree(*arrs, n_ll=a.n_ll, theta=a.theta, precision=a.precision)
     cnt = t.export("count").to(torch.int64)
     near = t.export("near").to(torch.int64) & 0x7FFFFFFF
     noff = t.export("near_off")
+    foff = t.export("far_off")
+    inf = t.info()              # list totals are known once the lists exist
     nleaf = 1 << inf["k"]
-    per_entry_particles = cnt[near]
-    leaf_of_entry = torch.repeat_interleave(torch.arange(nleaf, device=dev), noff[1:] - noff[:-1])
-    sinks = cnt[nleaf + leaf_of_entry]
-    pairs = int((per_entry_particles * sinks).sum())
+    leaf = torch.arange(nleaf, device=dev)
+    L_A = noff[1:] - noff[:-1]
+    F_A = foff[1:] - foff[:-1]
+    n_A = cnt[nleaf:2 * nleaf]
+    P_A = torch.zeros(nleaf, dtype=torch.int64, device=dev).index_add_(
+        0, torch.repeat_interleave(leaf, L_A), cnt[near])
+    pairs = int((P_A * n_A).sum())
     t.destroy()
     far_total = inf["far_total"]
     near_total = inf["near_total"]
 
     flops = FLOP_P2P * pairs + FLOP_M2L * far_total + FLOP_L2P * n
     achieved_tf = flops / (grav_ms * 1e-3) / 1e12
-    alg_bytes = (BYTES_PER_PARTICLE * n + BYTES_PER_NEAR_ENTRY * near_total +
-                 BYTES_PER_FAR_ENTRY * far_total + BYTES_PER_NODE * 2 * nleaf)
-    achieved_gbs = alg_bytes / (grav_ms * 1e-3) / 1e9
+    traffic = _profiled_traffic("k_gravity_mixed") if a.precision == "mixed" else None
     roofline = {"kernel": f"k_gravity<{a.precision}>", "bound": "alu", "achieved": achieved_tf,
                 "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tf / PEAK_VALU_TFLOPS,
-                "traffic": None, "kernel_ms": grav_ms, "pairs": pairs, "far_pairs": far_total,
-                "hbm_floor_gbs": achieved_gbs}
+                "traffic": traffic, "kernel_ms": grav_ms, "pairs": pairs, "far_pairs": far_total,
+                "near_cells": near_total}
+    # the per-leaf streaming model of the walk + gravity (bytes each lowest-level
+    # cell would read on its own): nodes tested V ~ 2 (F + L) in a binary walk
+    V_A = 2 * (F_A + L_A)
+    if a.precision == "mixed":
+        model_b = int((32 * V_A + 8 * L_A + 80 * F_A + 20 * P_A + 32 * n_A).sum())
+    else:
+        model_b = int((64 * V_A + 8 * L_A + 80 * F_A + 40 * P_A + 64 * n_A).sum())
+    wg_ms = phases["walk"] + phases["gravity"]
+    walk_model = {"bytes": model_b, "ms": wg_ms, "floor_ms": model_b / (PEAK_HBM_GBS * 1e9) * 1e3,
+                  "frac": model_b / (PEAK_HBM_GBS * 1e9) / (wg_ms * 1e-3)}
 
     # the other form and the mixed-vs-FP64 error
     other = "fp64" if a.precision == "mixed" else "mixed"
     sec_o, _ = timed(other, max(2, a.steps // 3), 1)
-    acc_m, _ = step("mixed")
+    acc_m, off = step("mixed")
     acc_d, _ = step("fp64")
     am = torch.stack([v.double() for v in acc_m], 1)
     ad = torch.stack([v.double() for v in acc_d], 1)
@@ -179,15 +180,40 @@ def main():
         "config": {"workload": "plummer_background N=4194304: 90% Plummer (b=1, r<=20) + 10% uniform "
                                "sphere R=10.357, equal masses, analytic h for ~50 neighbours",
                    "n": n, "n_ll": a.n_ll, "theta": a.theta, "precision": a.precision},
-        "phases_ms": {"build": (p1 - p0) * 1e3, "neighbours": (p2 - p1) * 1e3, "gravity": (p3 - p2) * 1e3},
+        "phases_ms": phases,
         "other_form": {"precision": other, "value": n / sec_o, "ms_per_step": sec_o * 1e3},
         "mixed_vs_fp64_error": err,
         "neighbours_total": int(off[-1]),
         "roofline": roofline,
+        "walk_gravity_hbm_model": walk_model,
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cloud, a)
     print(json.dumps(out), flush=True)
+
+
+def _profiled_traffic(name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    profiles/<name>_counters.md, if the kernel's sources are unchanged since
+    the counters were taken (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{name}_counters.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            rec[k.strip()] = v.strip().strip("`")
+    try:
+        h = hashlib.sha256()
+        for f in rec["sources"].split(", "):
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None
+        return int(rec["hbm_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
 
 
 def cpu_baseline(cloud, a):

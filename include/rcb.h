@@ -84,6 +84,17 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
                      rcb_tree **out);
 
 /*
+ * Tree walk (Sec. 2.2, with the reachability test of Sec. 2.3.1 and the MAC
+ * of Sec. 2.4.1): makes the near and far interaction lists of every
+ * lowest-level cell and keeps them in the tree. The neighbour and gravity
+ * calls run it themselves when it has not run yet; calling it first only
+ * moves the work. Synchronises `stream` (the list sizes are read back).
+ * Errors: RCB_ECAPACITY if a walk stack overflows (a tree deeper than the
+ * walk supports), RCB_ENOMEM.
+ */
+rcb_status rcb_walk(rcb_tree *t, void *stream);
+
+/*
  * Neighbour search, step 1 (Sec. 2.3): for every particle a the number of
  * particles b != a with |r_a - r_b| < 2 h_a, found among the cells that the
  * reachability test of Sec. 2.3.1 keeps.

@@ -33,7 +33,7 @@ class RcbTreeInfo(C.Structure):
                 ("theta", C.c_double)]
 
 
-EXPORTED = ["rcb_params_default", "rcb_build", "rcb_neighbours_count", "rcb_neighbours_fill",
+EXPORTED = ["rcb_params_default", "rcb_build", "rcb_walk", "rcb_neighbours_count", "rcb_neighbours_fill",
             "rcb_gravity", "rcb_gravity_vjp", "rcb_get_info", "rcb_tree_export", "rcb_destroy",
             "rcb_last_error"]
 
@@ -58,6 +58,8 @@ def lib():
         L.rcb_params_default.restype = None
         L.rcb_build.argtypes = [P, P, P, P, P, C.c_int64, C.POINTER(RcbParams), P, C.POINTER(P)]
         L.rcb_build.restype = C.c_int
+        L.rcb_walk.argtypes = [P, P]
+        L.rcb_walk.restype = C.c_int
         L.rcb_neighbours_count.argtypes = [P, P, C.POINTER(C.c_int64), P]
         L.rcb_neighbours_count.restype = C.c_int
         L.rcb_neighbours_fill.argtypes = [P, P, P, C.c_int64, P]
@@ -139,6 +141,10 @@ class Tree:
 
     def out_dtype(self):
         return torch.float32 if self.precision == "mixed" else torch.float64
+
+    def walk(self):
+        """Make the interaction lists now (the other calls make them on demand)."""
+        _check(lib().rcb_walk(self.handle, _stream()), "rcb_walk")
 
     def neighbours(self):
         """(offsets int64[n+1], ids int32[total]) -- caller particle order."""

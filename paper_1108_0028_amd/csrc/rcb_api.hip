@@ -129,6 +129,16 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
     return RCB_OK;
 }
 
+rcb_status rcb_walk(rcb_tree *t, void *stream) {
+    g_last_error.clear();
+    if (!t) {
+        set_error("rcb_walk: NULL tree");
+        return RCB_EINVAL;
+    }
+    t->stream = (hipStream_t)stream;
+    return ensure_walk(t, t->stream);
+}
+
 rcb_status rcb_neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, void *stream) {
     g_last_error.clear();
     if (!t || !offsets || !total) {
