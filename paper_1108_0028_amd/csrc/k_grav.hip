@@ -41,7 +41,7 @@ struct GravArgs {
     int64_t ngroup;
     const int32_t *nfirst, *ncount;
     const double *ncom, *nM, *nQ;
-    const int64_t *gnear_off, *gfar_off;
+    const int64_t *gnear_beg, *gnear_end, *gfar_beg, *gfar_end;
     const uint64_t *gnear, *gfar;
     const double *px, *py, *pz, *pm, *ph;
     const float *fdx, *fdy, *fdz, *fm, *fh;
@@ -59,7 +59,7 @@ __device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, double 
     double c[19];
 #pragma unroll
     for (int q = 0; q < 19; ++q) c[q] = 0.0;
-    const int64_t f0 = g.gfar_off[gi], f1 = g.gfar_off[gi + 1];
+    const int64_t f0 = g.gfar_beg[gi], f1 = g.gfar_end[gi];
     for (int64_t e0 = f0; e0 < f1; e0 += 8) {
         const int64_t e = e0 + slot;
         if (e < f1) {
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
     dummy.x = dummy.y = dummy.z = dummy.m = 0;
     dummy.h = 1;
     sh.tile[kWave + lane] = dummy;
-    const int64_t n0 = g.gnear_off[gi], n1 = g.gnear_off[gi + 1];
+    const int64_t n0 = g.gnear_beg[gi], n1 = g.gnear_end[gi];
     for (int li = 0; li < G; ++li) {
         const int64_t A = g.nleaf + gi * G + li;
         const int32_t sA = g.nfirst[A], c = g.ncount[A];
@@ -232,7 +232,7 @@ rcb_status far_coefficients(rcb_tree *t, double *out, int stride, hipStream_t s)
     rcb_status st = ensure_walk(t, s);
     if (st != RCB_OK) return st;
     GravArgs g{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
-               t->gnear_off, t->gfar_off, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
+               t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
                t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, nullptr, nullptr, nullptr};
     const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     k_far_coeffs<<<grid, kBlock, 0, s>>>(g, out, stride);
@@ -244,7 +244,7 @@ rcb_status gravity(rcb_tree *t, void *ax, void *ay, void *az, hipStream_t s) {
     rcb_status st = ensure_walk(t, s);
     if (st != RCB_OK) return st;
     GravArgs g{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
-               t->gnear_off, t->gfar_off, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
+               t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
                t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, ax, ay, az};
     const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     if (t->p.precision == RCB_MIXED) {

@@ -27,7 +27,7 @@ struct NeighArgs {
     int gk;
     int64_t ngroup;
     const int32_t *nfirst, *ncount;
-    const int64_t *gnear_off;
+    const int64_t *gnear_beg, *gnear_end;
     const uint64_t *gnear;
     const double *px, *py, *pz, *ph;
     const int32_t *pid;
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
     dummy.x = dummy.y = dummy.z = __builtin_inf();
     dummy.pb = -1;
     sh.tile[kWave + lane] = dummy;
-    const int64_t n0 = a.gnear_off[gi], n1 = a.gnear_off[gi + 1];
+    const int64_t n0 = a.gnear_beg[gi], n1 = a.gnear_end[gi];
     for (int li = 0; li < G; ++li) {
         const int64_t A = a.nleaf + gi * G + li;
         const int32_t sA = a.nfirst[A], c = a.ncount[A];
@@ -128,7 +128,7 @@ rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipSt
     std::vector<void *> tmp;
     int64_t *counts = (int64_t *)dalloc(t, sizeof(int64_t) * t->n, s, tmp);
     if (!counts) return RCB_ENOMEM;
-    NeighArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->gnear_off, t->gnear,
+    NeighArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->gnear_beg, t->gnear_end, t->gnear,
                 t->px, t->py, t->pz, t->ph, t->pid, counts, nullptr, nullptr};
     const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     k_neigh<false><<<grid, kBlock, 0, s>>>(a);
@@ -155,7 +155,7 @@ rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, in
     }
     rcb_status st = ensure_walk(t, s);
     if (st != RCB_OK) return st;
-    NeighArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->gnear_off, t->gnear,
+    NeighArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->gnear_beg, t->gnear_end, t->gnear,
                 t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids};
     const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     k_neigh<true><<<grid, kBlock, 0, s>>>(a);

@@ -47,7 +47,7 @@ struct VjpArgs {
     int64_t ngroup;
     const int32_t *nfirst, *ncount;
     const double *ncom, *nM, *nQ;
-    const int64_t *gnear_off, *gfar_off;
+    const int64_t *gnear_beg, *gnear_end, *gfar_beg, *gfar_end;
     const uint64_t *gnear, *gfar;
     const double *px, *py, *pz, *pm, *ph;
     const float *fdx, *fdy, *fdz, *fm, *fh;
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
     for (int i = lane; i < G * kMom; i += kWave) sh.mom[i / kMom][i % kMom] = a.mom[gi * G * kMom + i];
     if (lane < 3 * G) sh.com[lane / 3][lane % 3] = a.ncom[3 * (a.nleaf + gi * G) + lane];
     tile_sync();
-    const int64_t f0 = a.gfar_off[gi], f1 = a.gfar_off[gi + 1];
+    const int64_t f0 = a.gfar_beg[gi], f1 = a.gfar_end[gi];
     for (int64_t e0 = f0; e0 < f1; e0 += kWave) {
         const int64_t e = e0 + lane;
         const uint64_t ent = e < f1 ? a.gfar[e] : 0ull;
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
     const int G = 1 << a.gk;
     const int64_t GL = (a.nleaf >> a.gk) + gi;
     if (a.ncount[GL] == 0) return;
-    const int64_t n0 = a.gnear_off[gi], n1 = a.gnear_off[gi + 1];
+    const int64_t n0 = a.gnear_beg[gi], n1 = a.gnear_end[gi];
     for (int li = 0; li < G; ++li) {
         const int64_t A = a.nleaf + gi * G + li;
         const int32_t sA = a.nfirst[A], c = a.ncount[A];
@@ -482,7 +482,7 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     RCB_HIP(hipMemsetAsync(src, 0, sizeof(double) * 4 * n, s));
     RCB_HIP(hipMemsetAsync(adj, 0, sizeof(double) * kAdj * t->nlab, s));
     VjpArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
-              t->gnear_off, t->gfar_off, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
+              t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
               t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, src, adj, n, t->nlab};
     const unsigned gridg = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     const bool mixed = t->p.precision == RCB_MIXED;

@@ -26,9 +26,17 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kGStack = 1024;        // (label, mask) entries per wave
+// (label, mask) entries per wave. Depth never decreases up the stack (children
+// are pushed in the order of their parents), and a round that pops an entry of
+// level d - 1 pops every entry above it, so at most 16 entries of each level
+// are ever on the stack: <= 16 k <= 464 for k <= 29.
+constexpr int kGStack = 512;
+constexpr int kSortCap = 1024;       // near lists sorted in LDS up to this size
 constexpr uint32_t kLabelMask = 0x7fffffffu;
 
+// Lists are written at near_beg[g] / far_beg[g] if those are given, else at
+// g * cap (fixed-capacity slabs); entries past the capacity are counted but
+// not written, and such groups are counted in flag[3].
 struct WalkArgs {
     const double4 *rec;
     const double *hnode;
@@ -36,12 +44,12 @@ struct WalkArgs {
     int64_t ngroup;
     double theta2;
     int64_t *near_cnt, *far_cnt;
-    const int64_t *near_off, *far_off;
+    const int64_t *near_beg, *far_beg;
+    int64_t near_cap, far_cap;
     uint64_t *near_list, *far_list;
     int32_t *flag;
 };
 
-template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
     __shared__ uint64_t stk_all[kWaves][kGStack];
     uint64_t *stk = stk_all[threadIdx.x / kWave];
@@ -57,13 +65,11 @@ __global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
     const double hA = w.hnode[A];
     const bool leaf_live = li < G && ga.w >= 0.0;
     const uint32_t live_mask = (uint32_t)(ballot(leaf_live) & 0xffull);
-    int64_t nn = 0, nf = 0, nbase = 0, fbase = 0;
-    if (FILL) {
-        nbase = w.near_off[gi];
-        fbase = w.far_off[gi];
-    }
+    int64_t nn = 0, nf = 0;
+    const int64_t nbase = w.near_beg ? w.near_beg[gi] : gi * w.near_cap;
+    const int64_t fbase = w.far_beg ? w.far_beg[gi] : gi * w.far_cap;
     if (live_mask == 0) {
-        if (!FILL && lane == 0) {
+        if (lane == 0) {
             w.near_cnt[gi] = 0;
             w.far_cnt[gi] = 0;
         }
@@ -127,36 +133,55 @@ __global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
         }
         __builtin_amdgcn_wave_barrier();
         sp += 2 * no;
-        if (FILL) {
-            if (lead && nm != 0)
-                w.near_list[nbase + nn + rank_below(b_near)] =
+        if (lead && nm != 0) {
+            const int64_t i = nn + rank_below(b_near);
+            if (i < w.near_cap)
+                w.near_list[nbase + i] =
                     (uint64_t)(uint32_t)node | ((uint64_t)nm << 32) | ((uint64_t)cm << 40);
-            if (lead && fm != 0)
-                w.far_list[fbase + nf + rank_below(b_far)] = (uint64_t)(uint32_t)node | ((uint64_t)fm << 32);
+        }
+        if (lead && fm != 0) {
+            const int64_t i = nf + rank_below(b_far);
+            if (i < w.far_cap) w.far_list[fbase + i] = (uint64_t)(uint32_t)node | ((uint64_t)fm << 32);
         }
         nn += __popcll(b_near);
         nf += __popcll(b_far);
     }
     if (overflow) {
-        if (lane == 0) atomicOr(w.flag, 1);
-        if (!FILL && lane == 0) {
+        if (lane == 0) {
+            atomicOr(w.flag, 1);
             w.near_cnt[gi] = 0;
             w.far_cnt[gi] = 0;
         }
         return;
     }
-    if (!FILL && lane == 0) {
+    if (lane == 0) {
         w.near_cnt[gi] = nn;
         w.far_cnt[gi] = nf;
-        if (nn > kGStack) atomicAdd(&w.flag[1], 1);
+        if (nn > kSortCap) atomicAdd(&w.flag[1], 1);
+        if (nn > w.near_cap || nf > w.far_cap) atomicAdd(&w.flag[3], 1);
     }
+}
+
+// ends of the slab lists: [g cap, g cap + count)
+__global__ __launch_bounds__(kBlock) void k_slab_ends(int64_t ngroup, int64_t near_cap, int64_t far_cap,
+                                                      const int64_t *__restrict__ ncnt,
+                                                      const int64_t *__restrict__ fcnt,
+                                                      int64_t *__restrict__ nbeg, int64_t *__restrict__ nend,
+                                                      int64_t *__restrict__ fbeg, int64_t *__restrict__ fend) {
+    const int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (g >= ngroup) return;
+    nbeg[g] = g * near_cap;
+    nend[g] = g * near_cap + ncnt[g];
+    fbeg[g] = g * far_cap;
+    fend[g] = g * far_cap + fcnt[g];
 }
 
 // Sort each group's list by label (bitonic network in LDS, one wave per
 // group, CAP entries at most). Longer lists are queued for k_sort_long.
 template <int CAP, int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void k_sort_lists(int64_t ngroup,
-                                                              const int64_t *__restrict__ off,
+                                                              const int64_t *__restrict__ beg,
+                                                              const int64_t *__restrict__ end,
                                                               uint64_t *__restrict__ list,
                                                               int32_t *__restrict__ nqueued,
                                                               int32_t *__restrict__ long_q) {
@@ -165,8 +190,8 @@ __global__ __launch_bounds__(WAVES * kWave) void k_sort_lists(int64_t ngroup,
     const int64_t gi = wave_index();
     if (gi >= ngroup) return;
     const int lane = lane_id();
-    const int64_t nbase = off[gi];
-    const int64_t nn = off[gi + 1] - nbase;
+    const int64_t nbase = beg[gi];
+    const int64_t nn = end[gi] - nbase;
     if (nn <= 1) return;
     if (nn > CAP) {
         if (lane == 0) long_q[atomicAdd(nqueued, 1)] = (int32_t)gi;
@@ -200,11 +225,12 @@ __global__ __launch_bounds__(WAVES * kWave) void k_sort_lists(int64_t ngroup,
 // stage compares i with i ^ (size - 1)), so the virtual +inf padding past the
 // list end never moves and pairs reaching past the end are simply skipped.
 __global__ __launch_bounds__(1024) void k_sort_long(const int32_t *__restrict__ long_q,
-                                                    const int64_t *__restrict__ off,
+                                                    const int64_t *__restrict__ beg,
+                                                    const int64_t *__restrict__ end,
                                                     uint64_t *__restrict__ list) {
     const int64_t gi = long_q[blockIdx.x];
-    uint64_t *v = list + off[gi];
-    const int64_t nn = off[gi + 1] - off[gi];
+    uint64_t *v = list + beg[gi];
+    const int64_t nn = end[gi] - beg[gi];
     int64_t P = 1;
     while (P < nn) P <<= 1;
     for (int64_t size = 2; size <= P; size <<= 1) {
@@ -230,9 +256,11 @@ __global__ __launch_bounds__(1024) void k_sort_long(const int32_t *__restrict__ 
 // entries whose mask has its bit; near entries become label | candidate << 31.
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_expand(int64_t nleaf, int gk,
-                                                   const int64_t *__restrict__ gnear_off,
+                                                   const int64_t *__restrict__ gnear_beg,
+                                                   const int64_t *__restrict__ gnear_end,
                                                    const uint64_t *__restrict__ gnear,
-                                                   const int64_t *__restrict__ gfar_off,
+                                                   const int64_t *__restrict__ gfar_beg,
+                                                   const int64_t *__restrict__ gfar_end,
                                                    const uint64_t *__restrict__ gfar,
                                                    int64_t *__restrict__ ncnt, int64_t *__restrict__ fcnt,
                                                    const int64_t *__restrict__ noff,
@@ -245,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(int64_t nleaf, int gk,
     const int bit = (int)(li & ((1 << gk) - 1));
     const int lane = lane_id();
     int64_t nn = 0, nf = 0;
-    const int64_t n0 = gnear_off[gi], n1 = gnear_off[gi + 1];
+    const int64_t n0 = gnear_beg[gi], n1 = gnear_end[gi];
     for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
         const int64_t e = e0 + lane;
         const uint64_t ent = e < n1 ? gnear[e] : 0ull;
@@ -257,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(int64_t nleaf, int gk,
         }
         nn += __popcll(bl);
     }
-    const int64_t f0 = gfar_off[gi], f1 = gfar_off[gi + 1];
+    const int64_t f0 = gfar_beg[gi], f1 = gfar_end[gi];
     for (int64_t e0 = f0; e0 < f1; e0 += kWave) {
         const int64_t e = e0 + lane;
         const uint64_t ent = e < f1 ? gfar[e] : 0ull;
@@ -274,59 +302,99 @@ __global__ __launch_bounds__(kBlock) void k_expand(int64_t nleaf, int gk,
 
 }  // namespace
 
+// Slab capacities: 1024 near and up to 16384 far entries per group, within
+// a budget of about 8 GB for both slabs (at 4M particles and theta = 0.7 the
+// group lists average ~170 near and ~2150 far entries).
+static void slab_caps(int64_t ngroup, int64_t &cn, int64_t &cf) {
+    const int64_t budget = (int64_t)8 << 30;
+    cn = 1024;
+    cf = budget / (8 * ngroup) - cn;
+    cf = std::min<int64_t>(16384, std::max<int64_t>(1024, cf & ~(int64_t)63));
+}
+
+// One walk into fixed-capacity slabs; if any group's list is longer than its
+// slab, the counts of that walk size exact lists and a second walk fills them.
 rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     if (t->walked) return RCB_OK;
     const int64_t NG = t->ngroup;
     std::vector<void *> tmp;
     int64_t *ncnt = (int64_t *)dalloc(t, sizeof(int64_t) * NG, s, tmp);
     int64_t *fcnt = (int64_t *)dalloc(t, sizeof(int64_t) * NG, s, tmp);
-    t->gnear_off = (int64_t *)dalloc(t, sizeof(int64_t) * (NG + 1), s, t->list_allocs);
-    t->gfar_off = (int64_t *)dalloc(t, sizeof(int64_t) * (NG + 1), s, t->list_allocs);
-    if (!ncnt || !fcnt || !t->gnear_off || !t->gfar_off) return RCB_ENOMEM;
+    int64_t cn, cf;
+    slab_caps(NG, cn, cf);
+    std::vector<void *> slabs;
+    uint64_t *nslab = (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cn, s, slabs);
+    uint64_t *fslab = (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cf, s, slabs);
+    for (void *p : slabs) tmp.push_back(p);   // freed at the end unless kept
+    if (!ncnt || !fcnt || !nslab || !fslab) return RCB_ENOMEM;
     WalkArgs w{t->wrec, t->nhnode, t->k, t->gk, NG, t->p.theta * t->p.theta, ncnt, fcnt,
-               nullptr, nullptr, nullptr, nullptr, t->dflag};
+               nullptr, nullptr, cn, cf, nslab, fslab, t->dflag};
     const unsigned grid = (unsigned)((NG + kWaves - 1) / kWaves);
     RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 4, s));
-    k_walk_group<false><<<grid, kBlock, 0, s>>>(w);
-    RCB_LAUNCH_CHECK("k_walk_group<count>");
-    rcb_status st = scan_i64(t, ncnt, t->gnear_off, NG, s);
-    if (st != RCB_OK) return st;
-    st = scan_i64(t, fcnt, t->gfar_off, NG, s);
-    if (st != RCB_OK) return st;
-    int64_t tot[2] = {0, 0};
+    k_walk_group<<<grid, kBlock, 0, s>>>(w);
+    RCB_LAUNCH_CHECK("k_walk_group<slab>");
     int32_t flags[4] = {0, 0, 0, 0};
-    RCB_HIP(hipMemcpyAsync(&tot[0], t->gnear_off + NG, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RCB_HIP(hipMemcpyAsync(&tot[1], t->gfar_off + NG, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
     RCB_HIP(hipStreamSynchronize(s));
-    const int32_t nlong = flags[1];
     if (flags[0]) {
         set_error("walk: stack overflow (tree deeper than the walk stack supports)");
         return RCB_ECAPACITY;
     }
-    t->gnear = (uint64_t *)dalloc(t, sizeof(uint64_t) * std::max<int64_t>(1, tot[0]), s, t->list_allocs);
-    t->gfar = (uint64_t *)dalloc(t, sizeof(uint64_t) * std::max<int64_t>(1, tot[1]), s, t->list_allocs);
-    if (!t->gnear || !t->gfar) return RCB_ENOMEM;
-    w.near_off = t->gnear_off;
-    w.far_off = t->gfar_off;
-    w.near_list = t->gnear;
-    w.far_list = t->gfar;
-    k_walk_group<true><<<grid, kBlock, 0, s>>>(w);
-    RCB_LAUNCH_CHECK("k_walk_group<fill>");
+    const int32_t nlong = flags[1];
+    if (flags[3] == 0) {
+        int64_t *ends = (int64_t *)dalloc(t, sizeof(int64_t) * 4 * NG, s, t->list_allocs);
+        if (!ends) return RCB_ENOMEM;
+        t->gnear_beg = ends;
+        t->gnear_end = ends + NG;
+        t->gfar_beg = ends + 2 * NG;
+        t->gfar_end = ends + 3 * NG;
+        k_slab_ends<<<(unsigned)((NG + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+            NG, cn, cf, ncnt, fcnt, t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end);
+        RCB_LAUNCH_CHECK("k_slab_ends");
+        t->gnear = nslab;
+        t->gfar = fslab;
+        tmp.resize(tmp.size() - slabs.size());
+        for (void *p : slabs) t->list_allocs.push_back(p);
+    } else {
+        int64_t *noff = (int64_t *)dalloc(t, sizeof(int64_t) * (NG + 1), s, t->list_allocs);
+        int64_t *foff = (int64_t *)dalloc(t, sizeof(int64_t) * (NG + 1), s, t->list_allocs);
+        if (!noff || !foff) return RCB_ENOMEM;
+        rcb_status st = scan_i64(t, ncnt, noff, NG, s);
+        if (st != RCB_OK) return st;
+        st = scan_i64(t, fcnt, foff, NG, s);
+        if (st != RCB_OK) return st;
+        int64_t tot[2] = {0, 0};
+        RCB_HIP(hipMemcpyAsync(&tot[0], noff + NG, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        RCB_HIP(hipMemcpyAsync(&tot[1], foff + NG, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        RCB_HIP(hipStreamSynchronize(s));
+        t->gnear = (uint64_t *)dalloc(t, sizeof(uint64_t) * std::max<int64_t>(1, tot[0]), s, t->list_allocs);
+        t->gfar = (uint64_t *)dalloc(t, sizeof(uint64_t) * std::max<int64_t>(1, tot[1]), s, t->list_allocs);
+        if (!t->gnear || !t->gfar) return RCB_ENOMEM;
+        t->gnear_beg = noff;
+        t->gnear_end = noff + 1;
+        t->gfar_beg = foff;
+        t->gfar_end = foff + 1;
+        w.near_beg = noff;
+        w.far_beg = foff;
+        w.near_cap = w.far_cap = INT64_MAX;
+        w.near_list = t->gnear;
+        w.far_list = t->gfar;
+        k_walk_group<<<grid, kBlock, 0, s>>>(w);
+        RCB_LAUNCH_CHECK("k_walk_group<exact>");
+    }
     int32_t *long_q = nullptr;
     if (nlong > 0) {
         long_q = (int32_t *)dalloc(t, sizeof(int32_t) * nlong, s, tmp);
         if (!long_q) return RCB_ENOMEM;
     }
-    k_sort_lists<kGStack, kWaves><<<grid, kBlock, 0, s>>>(NG, t->gnear_off, t->gnear, t->dflag + 2, long_q);
+    k_sort_lists<kSortCap, kWaves><<<grid, kBlock, 0, s>>>(NG, t->gnear_beg, t->gnear_end, t->gnear,
+                                                           t->dflag + 2, long_q);
     RCB_LAUNCH_CHECK("k_sort_lists<near>");
     if (nlong > 0) {
-        k_sort_long<<<nlong, 1024, 0, s>>>(long_q, t->gnear_off, t->gnear);
+        k_sort_long<<<nlong, 1024, 0, s>>>(long_q, t->gnear_beg, t->gnear_end, t->gnear);
         RCB_LAUNCH_CHECK("k_sort_long");
     }
     for (void *p : tmp) RCB_HIP(hipFreeAsync(p, s));
-    t->gnear_total = tot[0];
-    t->gfar_total = tot[1];
     t->walked = true;
     return RCB_OK;
 }
@@ -343,7 +411,8 @@ rcb_status ensure_leaf_lists(rcb_tree *t, hipStream_t s) {
     t->far_off = (int64_t *)dalloc(t, sizeof(int64_t) * (L + 1), s, t->list_allocs);
     if (!ncnt || !fcnt || !t->near_off || !t->far_off) return RCB_ENOMEM;
     const unsigned grid = (unsigned)((L + kWaves - 1) / kWaves);
-    k_expand<false><<<grid, kBlock, 0, s>>>(L, t->gk, t->gnear_off, t->gnear, t->gfar_off, t->gfar,
+    k_expand<false><<<grid, kBlock, 0, s>>>(L, t->gk, t->gnear_beg, t->gnear_end, t->gnear,
+                                            t->gfar_beg, t->gfar_end, t->gfar,
                                             ncnt, fcnt, nullptr, nullptr, nullptr, nullptr);
     RCB_LAUNCH_CHECK("k_expand<count>");
     st = scan_i64(t, ncnt, t->near_off, L, s);
@@ -357,7 +426,8 @@ rcb_status ensure_leaf_lists(rcb_tree *t, hipStream_t s) {
     t->near_list = (int32_t *)dalloc(t, sizeof(int32_t) * std::max<int64_t>(1, tot[0]), s, t->list_allocs);
     t->far_list = (int32_t *)dalloc(t, sizeof(int32_t) * std::max<int64_t>(1, tot[1]), s, t->list_allocs);
     if (!t->near_list || !t->far_list) return RCB_ENOMEM;
-    k_expand<true><<<grid, kBlock, 0, s>>>(L, t->gk, t->gnear_off, t->gnear, t->gfar_off, t->gfar,
+    k_expand<true><<<grid, kBlock, 0, s>>>(L, t->gk, t->gnear_beg, t->gnear_end, t->gnear,
+                                           t->gfar_beg, t->gfar_end, t->gfar,
                                            nullptr, nullptr, t->near_off, t->far_off, t->near_list,
                                            t->far_list);
     RCB_LAUNCH_CHECK("k_expand<fill>");

@@ -72,8 +72,8 @@ struct rcb_tree {
     int gk = 0;
     int64_t ngroup = 0;
     bool walked = false;
-    int64_t gnear_total = -1, gfar_total = -1;
-    int64_t *gnear_off = nullptr, *gfar_off = nullptr;
+    // group list of group g: gnear[gnear_beg[g] .. gnear_end[g]) (likewise far)
+    int64_t *gnear_beg = nullptr, *gnear_end = nullptr, *gfar_beg = nullptr, *gfar_end = nullptr;
     uint64_t *gnear = nullptr, *gfar = nullptr;
     // per-leaf lists, expanded from the group lists on demand (inspection)
     bool leaf_lists = false;
