@@ -646,7 +646,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     t->nhnode = (double *)A(sizeof(double) * t->nlab, t->allocs);
     t->wrec = (double4 *)A(sizeof(double4) * 2 * t->nlab, t->allocs);
     t->ph = (double *)A(sizeof(double) * n, t->allocs);
-    t->dflag = (int32_t *)A(sizeof(int32_t) * 4, t->allocs);
+    t->dflag = (int32_t *)A(sizeof(int32_t) * 8, t->allocs);
     BuildScratch b{};
     for (int i = 0; i < 2; ++i) {
         b.x[i] = (double *)A(sizeof(double) * n, tmp);
@@ -672,7 +672,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     for (void *p : tmp)
         if (!p) return RCB_ENOMEM;
 
-    RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 4, s));
+    RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 8, s));
     if (t->p.validate) {
         k_validate<<<nbp, kBlock, 0, s>>>(x, y, z, m, h, n, t->dflag);
         RCB_LAUNCH_CHECK("k_validate");

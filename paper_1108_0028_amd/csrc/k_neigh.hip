@@ -9,10 +9,12 @@
 // candidate mask has the leaf) are staged through LDS 64 particles at a
 // time; slice j of sink s tests tile entries j, j + J, .... A pair is a
 // neighbour iff b != a and |r_a - r_b|^2 < (2 h_a)^2 in FP64 on the tree's
-// copy of the inputs (the same predicate for every precision mode). Count
-// mode writes per-particle counts; fill mode writes ids at offsets[a] + rank,
-// ranks taken by ballot within the sink's lane segment so each list keeps
-// tree order.
+// copy of the inputs (the same predicate for every precision mode). Ranks
+// are taken by ballot within the sink's lane segment, so each list keeps tree
+// order. The count call writes the ids into a slab of kNbCap slots per
+// particle as well as the counts; the fill call then compacts the slab into
+// the caller's CSR; the groups holding a particle with more neighbours than
+// the slab takes are searched again, writing at offsets[a] + rank.
 #include "near_tile.h"
 #include "rcb_internal.h"
 
@@ -21,6 +23,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
+constexpr int64_t kNbCap = 192;   // slab slots per particle (~50 neighbours expected)
 
 struct NeighArgs {
     int64_t nleaf;
@@ -31,9 +34,11 @@ struct NeighArgs {
     const uint64_t *gnear;
     const double *px, *py, *pz, *ph;
     const int32_t *pid;
-    int64_t *counts;
-    const int64_t *offsets;
-    int32_t *ids;
+    int64_t *counts;          // slab mode: per-particle counts (caller order)
+    const int64_t *offsets;   // fill mode: list starts (caller order)
+    int32_t *ids;             // fill mode: final lists; slab mode: kNbCap slots per particle
+    int32_t *flag;            // slab mode: particles with more than kNbCap neighbours
+    int32_t *gover;           // per group: 1 if one of its particles outgrew the slab
 };
 
 struct alignas(16) SrcN {
@@ -48,7 +53,10 @@ struct NeighShared {
     SrcN tile[2 * kWave];
 };
 
-template <bool FILL>
+// SLAB: ids go to slot (tree position) * kNbCap + rank (ranks >= kNbCap are
+// only counted), counts are stored in caller order. Otherwise ids go to
+// offsets[pid] + rank.
+template <bool SLAB>
 __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
     __shared__ NeighShared sh_all[kWaves];
     NeighShared &sh = sh_all[threadIdx.x / kWave];
@@ -58,6 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
     const int G = 1 << a.gk;
     const int64_t GL = (a.nleaf >> a.gk) + gi;
     if (a.ncount[GL] == 0) return;
+    if (!SLAB && a.gover && a.gover[gi] == 0) return;   // its lists came from the slab
     SrcN dummy;
     dummy.x = dummy.y = dummy.z = __builtin_inf();
     dummy.pb = -1;
@@ -77,8 +86,8 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
             const double two_h = 2.0 * a.ph[pa];
             const double lim = has_sink ? two_h * two_h : -1.0;
             int cnt = 0;
-            int64_t obase = 0;
-            if (FILL && has_sink) obase = a.offsets[a.pid[pa]];
+            const int32_t oa = a.pid[pa];
+            const int64_t obase = SLAB ? (int64_t)pa * kNbCap : (has_sink ? a.offsets[oa] : 0);
             for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
                 const int tot =
                     load_entry_chunk(a.gnear, a.nfirst, a.ncount, e0, n1, 1u << (8 + li), sh.ec);
@@ -101,44 +110,72 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
                         const SrcN s = sh.tile[u0 + L.slice];
                         const int32_t pb = s.pb;
                         const bool hit = pb != pa && dist2(xa, ya, za, s.x, s.y, s.z) < lim;
-                        if (FILL) {
-                            const uint64_t bal = ballot(hit) & segmask;
-                            if (hit) a.ids[obase + cnt + rank_below(bal)] = a.pid[pb];
-                            cnt += __popcll(bal);
-                        } else {
-                            cnt += hit;
-                        }
+                        const uint64_t bal = ballot(hit) & segmask;
+                        const int r = cnt + rank_below(bal);
+                        if (hit && (!SLAB || r < kNbCap)) a.ids[obase + r] = a.pid[pb];
+                        cnt += __popcll(bal);
                     }
                     tile_sync();
                 }
             }
-            if (!FILL) {
-                cnt = seg_sum(cnt, L.slice, L.J);
-                if (has_sink && L.slice == 0) a.counts[a.pid[pa]] = cnt;
+            if (SLAB && has_sink && L.slice == 0) {
+                a.counts[oa] = cnt;
+                if (cnt > kNbCap) {
+                    atomicAdd(a.flag, 1);
+                    a.gover[gi] = 1;
+                }
             }
         }
     }
 }
 
+// slab lists (tree order) -> the caller's CSR: 16 lanes per particle
+__global__ __launch_bounds__(kBlock) void k_nb_compact(int64_t n, const int32_t *__restrict__ pid,
+                                                       const int64_t *__restrict__ offsets,
+                                                       const int32_t *__restrict__ slab,
+                                                       int32_t *__restrict__ ids) {
+    const int64_t p = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / 16;
+    const int j0 = threadIdx.x % 16;
+    if (p >= n) return;
+    const int32_t a = pid[p];
+    const int64_t o = offsets[a], c = offsets[a + 1] - o;
+    if (c > kNbCap) return;   // searched again by its group
+    for (int64_t j = j0; j < c; j += 16) ids[o + j] = slab[p * kNbCap + j];
+}
+
 }  // namespace
 
+// Count: one search that also writes every particle's ids into a slab of
+// kNbCap slots; fill then compacts the slab and searches again only the
+// groups holding a particle with more neighbours than that.
 rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipStream_t s) {
     rcb_status st = ensure_walk(t, s);
     if (st != RCB_OK) return st;
     std::vector<void *> tmp;
     int64_t *counts = (int64_t *)dalloc(t, sizeof(int64_t) * t->n, s, tmp);
     if (!counts) return RCB_ENOMEM;
+    if (!t->nb_slab) {
+        t->nb_slab = (int32_t *)dalloc(t, sizeof(int32_t) * t->n * kNbCap, s, t->list_allocs);
+        t->nb_gover = (int32_t *)dalloc(t, sizeof(int32_t) * t->ngroup, s, t->list_allocs);
+        if (!t->nb_slab || !t->nb_gover) return RCB_ENOMEM;
+    }
+    RCB_HIP(hipMemsetAsync(t->dflag + 4, 0, sizeof(int32_t), s));
+    RCB_HIP(hipMemsetAsync(t->nb_gover, 0, sizeof(int32_t) * t->ngroup, s));
     NeighArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->gnear_beg, t->gnear_end, t->gnear,
-                t->px, t->py, t->pz, t->ph, t->pid, counts, nullptr, nullptr};
+                t->px, t->py, t->pz, t->ph, t->pid, counts, nullptr, t->nb_slab, t->dflag + 4,
+                t->nb_gover};
     const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
-    k_neigh<false><<<grid, kBlock, 0, s>>>(a);
-    RCB_LAUNCH_CHECK("k_neigh<count>");
+    k_neigh<true><<<grid, kBlock, 0, s>>>(a);
+    RCB_LAUNCH_CHECK("k_neigh<slab>");
     st = scan_i64(t, counts, offsets, t->n, s);
     if (st != RCB_OK) return st;
+    int32_t over = 0;
     RCB_HIP(hipMemcpyAsync(total, offsets + t->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RCB_HIP(hipFreeAsync(counts, s));
+    RCB_HIP(hipMemcpyAsync(&over, t->dflag + 4, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    for (void *p : tmp) RCB_HIP(hipFreeAsync(p, s));
     RCB_HIP(hipStreamSynchronize(s));
     t->nb_total = *total;
+    t->nb_over = over;
     return RCB_OK;
 }
 
@@ -153,13 +190,16 @@ rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, in
                   std::to_string(t->nb_total));
         return RCB_ECAPACITY;
     }
-    rcb_status st = ensure_walk(t, s);
-    if (st != RCB_OK) return st;
-    NeighArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->gnear_beg, t->gnear_end, t->gnear,
-                t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids};
-    const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
-    k_neigh<true><<<grid, kBlock, 0, s>>>(a);
-    RCB_LAUNCH_CHECK("k_neigh<fill>");
+    const unsigned gridc = (unsigned)((t->n * 16 + kBlock - 1) / kBlock);
+    k_nb_compact<<<gridc, kBlock, 0, s>>>(t->n, t->pid, offsets, t->nb_slab, ids);
+    RCB_LAUNCH_CHECK("k_nb_compact");
+    if (t->nb_over > 0) {
+        NeighArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->gnear_beg, t->gnear_end, t->gnear,
+                    t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids, nullptr, t->nb_gover};
+        const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
+        k_neigh<false><<<grid, kBlock, 0, s>>>(a);
+        RCB_LAUNCH_CHECK("k_neigh<fill>");
+    }
     return RCB_OK;
 }
 

@@ -81,7 +81,13 @@ struct rcb_tree {
     int64_t *near_off = nullptr, *far_off = nullptr;
     int32_t *near_list = nullptr, *far_list = nullptr;
     int64_t nb_total = -1;             // neighbour total of the last count call
-    int32_t *dflag = nullptr;          // device error flags (walk overflow etc.)
+    int32_t *nb_slab = nullptr;        // neighbour ids of the count call, kNbCap per particle
+    int32_t *nb_gover = nullptr;       // groups with a particle of more than kNbCap neighbours
+    int32_t nb_over = 0;               // particles with more than kNbCap neighbours
+    // device flags: [0] walk stack overflow, [1] long near lists, [2] their
+    // queue, [3] groups outgrowing the list slabs, [4] particles outgrowing
+    // the neighbour slab
+    int32_t *dflag = nullptr;
 
     std::vector<void *> allocs;        // everything to free on destroy
     std::vector<void *> list_allocs;
