@@ -133,19 +133,80 @@ struct PartIn {
     const double *x, *y, *z, *m, *h;
 };
 
-template <int P>
+// Sum and max over the LANES lanes of this lane's group (xor butterfly: the
+// canonical pairwise tree across lanes, as for the whole wave).
+template <int LANES>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = 1; o < LANES; o <<= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+template <int LANES>
+__device__ __forceinline__ double group_max(double v) {
+#pragma unroll
+    for (int o = 1; o < LANES; o <<= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// LANES = 64: one node per wave (512 elements); LANES = 8: one node per 8-lane
+// group (64 elements). Narrower trees padded with zeros give the same bits.
+// Wave-private LDS staging of one 512-element chunk: elements are loaded
+// coalesced (lane l takes base + 64 t + l) and read back as each lane's 8
+// consecutive ones; one pad slot per 8 keeps the read-back off shared banks.
+constexpr int kStage = kChunk + kChunk / 8;
+__device__ __forceinline__ int stage_slot(int e) { return e + (e >> 3); }
+
+__device__ __forceinline__ void stage8(const double *__restrict__ a, int64_t base, int64_t end,
+                                       double *buf, double (&out)[8]) {
+    const int l = lane_id();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int e = 64 * t + l;
+        buf[stage_slot(e)] = base + e < end ? a[base + e] : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int t = 0; t < 8; ++t) out[t] = buf[stage_slot(8 * l + t)];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// `stage`: a wave-private buffer of kStage doubles (LANES == 64) or null
+// (direct loads of each lane's 8 consecutive elements).
+template <int P, int LANES = kWave>
 __device__ __forceinline__ void chunk_sums(const PartIn &in, int64_t base, int64_t end,
                                            const double g[3], const double c[3],
-                                           double (&sums)[Pay<P>::NS], double &mx) {
+                                           double (&sums)[Pay<P>::NS], double &mx,
+                                           double *stage = nullptr) {
     constexpr int NS = Pay<P>::NS;
     double v[8][NS];
     double ml = -1.0;
-    const int64_t p0 = base + 8 * (int64_t)lane_id();
+    const int64_t p0 = base + 8 * (int64_t)(lane_id() % LANES);
+    double X[8], Y[8], Z[8], Mm[8], H[8];
+    if (stage) {
+        stage8(in.x, base, end, stage, X);
+        stage8(in.y, base, end, stage, Y);
+        stage8(in.z, base, end, stage, Z);
+        stage8(in.m, base, end, stage, Mm);
+        if constexpr (P == 1) stage8(in.h, base, end, stage, H);
+    } else {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int64_t i = p0 + t;
+            const bool ok = i < end;
+            X[t] = ok ? in.x[i] : 0.0;
+            Y[t] = ok ? in.y[i] : 0.0;
+            Z[t] = ok ? in.z[i] : 0.0;
+            Mm[t] = ok ? in.m[i] : 0.0;
+            if constexpr (P == 1) H[t] = ok ? in.h[i] : 0.0;
+        }
+    }
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int64_t i = p0 + t;
         if (i < end) {
-            const double xi = in.x[i], yi = in.y[i], zi = in.z[i], mi = in.m[i];
+            const double xi = X[t], yi = Y[t], zi = Z[t], mi = Mm[t];
             if constexpr (P == 0) {
                 v[t][0] = mi;
                 v[t][1] = mi * xi;
@@ -164,7 +225,7 @@ __device__ __forceinline__ void chunk_sums(const PartIn &in, int64_t base, int64
                 v[t][4] = (m3 * d1) * d2;
                 v[t][5] = (m3 * d2) * d2 - mr2;
                 const double rg = sqrt(dist2(xi, yi, zi, g[0], g[1], g[2]));
-                ml = fmax(ml, rg + 2.0 * in.h[i]);
+                ml = fmax(ml, rg + 2.0 * H[t]);
             }
         } else {
 #pragma unroll
@@ -175,9 +236,9 @@ __device__ __forceinline__ void chunk_sums(const PartIn &in, int64_t base, int64
     for (int s = 0; s < NS; ++s) {
         const double a = (v[0][s] + v[1][s]) + (v[2][s] + v[3][s]);
         const double b = (v[4][s] + v[5][s]) + (v[6][s] + v[7][s]);
-        sums[s] = wave_sum(a + b);
+        sums[s] = group_sum<LANES>(a + b);
     }
-    mx = wave_max(ml);
+    mx = group_max<LANES>(ml);
 }
 
 struct NodeOut {
@@ -194,12 +255,14 @@ __device__ __forceinline__ void box_centre(const NodeOut &o, int64_t lab, double
 
 // Payload-A result of a non-empty node: mass, centre of mass, h_node_int,
 // and for an internal node the split axis/plane and the children's boxes.
+template <int LANES = kWave>
 __device__ void finish_a(const NodeOut &o, int64_t lab, bool leaf, const double s[4], double mx) {
     const double M = s[0] + 0.0;
     double com[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) com[d] = (s[1 + d] + 0.0) / M;
-    if (lane_id() == 0) {
+    const int l = lane_id() % LANES;
+    if (l == 0) {
         o.nM[lab] = M;
 #pragma unroll
         for (int d = 0; d < 3; ++d) o.ncom[3 * lab + d] = com[d];
@@ -221,15 +284,16 @@ __device__ void finish_a(const NodeOut &o, int64_t lab, bool leaf, const double 
     }
     if (hi[2] - lo[2] > best) ax = 2;
     const double plane = ax == 0 ? com[0] : (ax == 1 ? com[1] : com[2]);
-    if (lane_id() == 0) {
+    if (l == 0) {
         o.naxis[lab] = ax;
         o.nplane[lab] = plane;
     }
-    const int l = lane_id();
     if (l < 6) {   // children boxes: lanes 0-2 lower corners, 3-5 upper corners
         const int d = l % 3;
         const bool upper = l >= 3;
-        const double v = upper ? hi[d] : lo[d];
+        const double vl = d == 0 ? lo[0] : (d == 1 ? lo[1] : lo[2]);   // no dynamic indexing
+        const double vh = d == 0 ? hi[0] : (d == 1 ? hi[1] : hi[2]);
+        const double v = upper ? vh : vl;
         const int64_t L = 2 * lab, R = 2 * lab + 1;
         double *dL = upper ? o.nhi : o.nlo;
         dL[3 * L + d] = (upper && d == ax) ? plane : v;
@@ -237,14 +301,16 @@ __device__ void finish_a(const NodeOut &o, int64_t lab, bool leaf, const double 
     }
 }
 
+template <int LANES = kWave>
 __device__ void finish_b(const NodeOut &o, int64_t lab, const double s[6], double mx) {
-    const int l = lane_id();
+    const int l = lane_id() % LANES;
     if (l < 6) o.nQ[6 * lab + l] = (l == 0 ? s[0] : l == 1 ? s[1] : l == 2 ? s[2] : l == 3 ? s[3] : l == 4 ? s[4] : s[5]) + 0.0;
     if (l == 0) o.nhnode[lab] = mx;
 }
 
+template <int LANES = kWave>
 __device__ void finish_empty(const NodeOut &o, int64_t lab, bool leaf, int32_t first) {
-    const int l = lane_id();
+    const int l = lane_id() % LANES;
     double g[3];
     box_centre(o, lab, g);
     if (l == 0) {
@@ -320,16 +386,10 @@ struct BigCtl {
     int32_t *big_node, *big_base, *item_big;
 };
 
-__global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level, PartIn in,
-                                                        const int32_t *__restrict__ id,
-                                                        PartOut out, NodeOut o, BigCtl bc) {
-    const int64_t w = wave_index();
-    const int64_t nodes = (int64_t)1 << lvl;
-    if (w >= nodes) return;
-    const int64_t lab = nodes + w;
+__device__ __forceinline__ void level_node(int64_t lab, bool leaf, const PartIn &in, const int32_t *__restrict__ id,
+                           const PartOut &out, const NodeOut &o, const BigCtl &bc, double *stage) {
     const int32_t s = o.nfirst[lab];
     const int32_t c = o.ncount[lab];
-    const bool leaf = leaf_level != 0;
     if (c > kChunk) {
         int bi = 0, base = 0;
         const int nch = (c + kChunk - 1) / kChunk;
@@ -351,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level,
     double g[3];
     box_centre(o, lab, g);
     double sa[4], mx;
-    chunk_sums<0>(in, s, (int64_t)s + c, g, g, sa, mx);
+    chunk_sums<0>(in, s, (int64_t)s + c, g, g, sa, mx, stage);
     finish_a(o, lab, leaf, sa, mx);
     if (leaf) {
         double com[3];
@@ -359,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level,
 #pragma unroll
         for (int d = 0; d < 3; ++d) com[d] = (sa[1 + d] + 0.0) / M;
         double sb[6], hn;
-        chunk_sums<1>(in, s, (int64_t)s + c, g, com, sb, hn);
+        chunk_sums<1>(in, s, (int64_t)s + c, g, com, sb, hn, stage);
         finish_b(o, lab, sb, hn);
         return;
     }
@@ -381,15 +441,132 @@ __global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level,
     // count the left side first (needed for the right side's base)
     const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
     int nl = 0;
-    const int64_t p0 = (int64_t)s + 8 * (int64_t)lane_id();
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-        const int64_t i = p0 + t;
+        const int64_t i = (int64_t)s + 64 * t + lane_id();
         nl += (i < (int64_t)s + c) && (xa[i] < plane);
     }
     const int nleft = wave_sum_i(nl);
     scatter_chunk(in, id, out, s, (int64_t)s + c, ax, plane, s, nleft, 0, 0);
     if (lane_id() == 0) {
+        o.nfirst[2 * lab] = s;
+        o.ncount[2 * lab] = nleft;
+        o.nfirst[2 * lab + 1] = s + nleft;
+        o.ncount[2 * lab + 1] = c - nleft;
+    }
+}
+
+// One node per wave: every node of the level, or (packed levels) the nodes of
+// the groups of npg nodes that k_level_packed left to it (group indices).
+__global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level, PartIn in,
+                                                        const int32_t *__restrict__ id,
+                                                        PartOut out, NodeOut o, BigCtl bc,
+                                                        const int32_t *__restrict__ groups, int npg) {
+    const int64_t w = wave_index();
+    const int64_t nodes = (int64_t)1 << lvl;
+    int64_t j = w;
+    if (groups) {
+        if (w / npg >= bc.ctl[2]) return;
+        j = (int64_t)groups[w / npg] * npg + w % npg;
+    }
+    if (j >= nodes) return;
+    __shared__ double stage_all[kWavesPerBlock][kStage];
+    level_node(nodes + j, leaf_level != 0, in, id, out, o, bc, stage_all[threadIdx.x / kWave]);
+}
+
+// Deep levels: 64 / GW nodes per wave, one per GW-lane group, when all of
+// them hold <= 8 GW particles (else the wave's nodes go on a list for
+// k_level_small). Lane j of a group holds the node's elements [8 j, 8 j + 8);
+// the stable partition ranks come from a scan of the lanes' left counts
+// within the group.
+template <int GW>
+__global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int leaf_level, PartIn in,
+                                                         const int32_t *__restrict__ id,
+                                                         PartOut out, NodeOut o, BigCtl bc,
+                                                         int32_t *__restrict__ groups) {
+    constexpr int kPack = kWave / GW;   // nodes per wave
+    const int64_t w = wave_index();
+    const int64_t nodes = (int64_t)1 << lvl;
+    if (w * kPack >= nodes) return;
+    const bool leaf = leaf_level != 0;
+    const int lane = lane_id();
+    const int gslot = lane / GW, gl = lane % GW;
+    const int64_t j = w * kPack + gslot;
+    const bool valid = j < nodes;
+    const int64_t lab = nodes + (valid ? j : 0);
+    const int32_t s = o.nfirst[lab];
+    const int32_t c = valid ? o.ncount[lab] : 0;
+    int cmax = c;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) cmax = max(cmax, __shfl_xor(cmax, off, kWave));
+    if (cmax > GW * 8) {
+        if (lane == 0) groups[atomicAdd(&bc.ctl[2], 1)] = (int32_t)w;
+        return;
+    }
+    if (!valid) return;   // whole 8-lane groups leave together
+    if (c == 0) {
+        finish_empty<GW>(o, lab, leaf, s);
+        return;
+    }
+    double g[3];
+    box_centre(o, lab, g);
+    double sa[4], mx;
+    chunk_sums<0, GW>(in, s, (int64_t)s + c, g, g, sa, mx);
+    finish_a<GW>(o, lab, leaf, sa, mx);
+    if (leaf) {
+        double com[3];
+        const double M = sa[0] + 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) com[d] = (sa[1 + d] + 0.0) / M;
+        double sb[6], hn;
+        chunk_sums<1, GW>(in, s, (int64_t)s + c, g, com, sb, hn);
+        finish_b<GW>(o, lab, sb, hn);
+        return;
+    }
+    double lo[3], hi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = o.nlo[3 * lab + d];
+        hi[d] = o.nhi[3 * lab + d];
+    }
+    int ax = 0;
+    double best = hi[0] - lo[0];
+    if (hi[1] - lo[1] > best) {
+        best = hi[1] - lo[1];
+        ax = 1;
+    }
+    if (hi[2] - lo[2] > best) ax = 2;
+    const double plane = (sa[1 + ax] + 0.0) / (sa[0] + 0.0);
+    const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
+    const int64_t e0 = (int64_t)s + 8 * gl, end = (int64_t)s + c;
+    uint32_t lb = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+        if (e0 + t < end && xa[e0 + t] < plane) lb |= 1u << t;
+    const int nl = __popc(lb);
+    int incl = nl;   // inclusive scan of the left counts over the group
+#pragma unroll
+    for (int off = 1; off < GW; off <<= 1) {
+        const int y = __shfl_up(incl, off, kWave);
+        if (gl >= off) incl += y;
+    }
+    const int excl = incl - nl;
+    const int nleft = __shfl(incl, gslot * GW + GW - 1, kWave);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int64_t i = e0 + t;
+        if (i < end) {
+            const int lbefore = excl + __popc(lb & ((1u << t) - 1u));
+            const int e = 8 * gl + t;
+            const int64_t dst = (lb >> t) & 1u ? (int64_t)s + lbefore : (int64_t)s + nleft + (e - lbefore);
+            out.x[dst] = in.x[i];
+            out.y[dst] = in.y[i];
+            out.z[dst] = in.z[i];
+            out.m[dst] = in.m[i];
+            out.id[dst] = id[i];
+        }
+    }
+    if (gl == 0) {
         o.nfirst[2 * lab] = s;
         o.ncount[2 * lab] = nleft;
         o.nfirst[2 * lab + 1] = s + nleft;
@@ -418,8 +595,9 @@ __global__ __launch_bounds__(kBlock) void k_chunk_reduce(PartIn in, NodeOut o, B
         for (int d = 0; d < 3; ++d) com[d] = o.ncom[3 * lab + d];
     }
     constexpr int NS = Pay<P>::NS;
+    __shared__ double stage_all[kWavesPerBlock][kStage];
     double sums[NS], mx;
-    chunk_sums<P>(in, base, end, g, com, sums, mx);
+    chunk_sums<P>(in, base, end, g, com, sums, mx, stage_all[threadIdx.x / kWave]);
     const int l = lane_id();
     if (l < NS) {
         double v = sums[0];
@@ -501,10 +679,9 @@ __global__ __launch_bounds__(kBlock) void k_part_count(PartIn in, NodeOut o, Big
     const double plane = o.nplane[lab];
     const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
     int nl = 0;
-    const int64_t p0 = base + 8 * (int64_t)lane_id();
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-        const int64_t i = p0 + t;
+        const int64_t i = base + 64 * t + lane_id();
         nl += (i < end) && (xa[i] < plane);
     }
     nl = wave_sum_i(nl);
@@ -663,6 +840,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     b.item_big = (int32_t *)A(sizeof(int32_t) * b.max_items, tmp);
     b.part = (double *)A(sizeof(double) * 8 * b.max_items, tmp);
     b.part_left = (int32_t *)A(sizeof(int32_t) * b.max_items, tmp);
+    b.pack_groups = (int32_t *)A(sizeof(int32_t) * (t->nleaf / 2 + 1), tmp);
     b.naxis = (int32_t *)A(sizeof(int32_t) * t->nlab, tmp);
     b.nplane = (double *)A(sizeof(double) * t->nlab, tmp);
     const int nbp = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
@@ -710,8 +888,30 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         PartOut out{b.x[cur ^ 1], b.y[cur ^ 1], b.z[cur ^ 1], b.m[cur ^ 1], b.id[cur ^ 1]};
         RCB_HIP(hipMemsetAsync(b.ctl, 0, sizeof(int32_t) * 4, s));
         const int64_t nodes = (int64_t)1 << lvl;
-        k_level_small<<<blocks_for_waves(nodes), kBlock, 0, s>>>(lvl, leaf, in, b.id[cur], out, o, bc);
-        RCB_LAUNCH_CHECK("k_level_small");
+        // group width: 8, 16 or 32 lanes per node while the average node
+        // holds at most 4 GW particles (capacity 8 GW)
+        const int gw = n <= 32 * nodes ? 8 : (n <= 64 * nodes ? 16 : (n <= 128 * nodes ? 32 : 0));
+        if (gw) {
+            const int npg = kWave / gw;
+            const int64_t ng = (nodes + npg - 1) / npg;
+            if (gw == 8)
+                k_level_packed<8><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, leaf, in, b.id[cur], out,
+                                                                           o, bc, b.pack_groups);
+            else if (gw == 16)
+                k_level_packed<16><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, leaf, in, b.id[cur], out,
+                                                                            o, bc, b.pack_groups);
+            else
+                k_level_packed<32><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, leaf, in, b.id[cur], out,
+                                                                            o, bc, b.pack_groups);
+            RCB_LAUNCH_CHECK("k_level_packed");
+            k_level_small<<<blocks_for_waves(ng * npg), kBlock, 0, s>>>(lvl, leaf, in, b.id[cur], out, o,
+                                                                        bc, b.pack_groups, npg);
+            RCB_LAUNCH_CHECK("k_level_small<list>");
+        } else {
+            k_level_small<<<blocks_for_waves(nodes), kBlock, 0, s>>>(lvl, leaf, in, b.id[cur], out, o, bc,
+                                                                     nullptr, 1);
+            RCB_LAUNCH_CHECK("k_level_small");
+        }
         const int64_t bw = std::min<int64_t>(big_waves, nodes);
         k_chunk_reduce<0><<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part);
         RCB_LAUNCH_CHECK("k_chunk_reduce<0>");

@@ -33,7 +33,7 @@ struct BuildScratch {
     double *x[2], *y[2], *z[2], *m[2];
     int32_t *id[2];
     // big-node machinery
-    int32_t *ctl;          // [0] big-node count, [1] item count, [2] error flag
+    int32_t *ctl;          // [0] big-node count, [1] item count, [2] groups left by the packed pass
     int32_t *big_node;     // big-node list (labels)
     int32_t *big_base;     // first item of each big node
     int32_t *item_big;     // item -> big-node index
@@ -42,6 +42,7 @@ struct BuildScratch {
     int32_t *naxis;        // split axis per label
     double *nplane;        // split coordinate per label
     double *bounds;        // per-block min/max partials (6 per block)
+    int32_t *pack_groups;  // 8-node groups the packed pass leaves to k_level_small
     int64_t max_items;
     int64_t max_big;
 };
