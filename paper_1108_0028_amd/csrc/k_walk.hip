@@ -50,6 +50,14 @@ struct WalkArgs {
     int32_t *flag;
 };
 
+// bit 8 s set iff byte s of x is non-zero (the lead lane of entry s)
+__device__ __forceinline__ uint64_t byte_any(uint64_t x) {
+    x |= x >> 4;
+    x |= x >> 2;
+    x |= x >> 1;
+    return x & 0x0101010101010101ull;
+}
+
 __global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
     __shared__ uint64_t stk_all[kWaves][kGStack];
     uint64_t *stk = stk_all[threadIdx.x / kWave];
@@ -90,36 +98,34 @@ __global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
         const int b = sp < 8 ? sp : 8;
         sp -= b;
         const bool act = slot < b;
-        const uint64_t ent = act ? stk[sp + slot] : 0ull;
+        // lanes past the popped entries read the top entry again and are masked
+        const uint64_t ent = stk[sp + (act ? slot : 0)];
         const int32_t node = (int32_t)(ent & 0xffffffffull);
         const uint32_t emask = (uint32_t)(ent >> 32);
         const bool mine = act && ((emask >> li) & 1u);
-        double4 gb = make_double4(0.0, 0.0, 0.0, -1.0), cb = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (act) {
-            gb = w.rec[2 * (int64_t)node];
-            cb = w.rec[2 * (int64_t)node + 1];
-        }
+        const double4 gb = w.rec[2 * (int64_t)node];
+        const double4 cb = w.rec[2 * (int64_t)node + 1];
         const bool live = mine && gb.w >= 0.0;
-        const bool leafB = node >= nleaf;
         const double dg2 = dist2(ga.x, ga.y, ga.z, gb.x, gb.y, gb.z);
         const double rs = (hA + gb.w) * kReachPad;
-        const bool reach = dg2 < rs * rs;
         const double R2 = dist2(ca.x, ca.y, ca.z, cb.x, cb.y, cb.z);
-        const bool mac = cb.w * cb.w < w.theta2 * R2;
-        const bool open = live && !leafB && (reach || !mac);
-        const bool nearf = live && leafB && (reach || !mac);
-        const bool farf = live && !reach && mac;
-        const uint64_t bo = ballot(open), bn = ballot(nearf), bc = ballot(nearf && reach),
-                       bf = ballot(farf);
+        // the per-lane tests as wave masks; the decisions are bit logic on them
+        const uint64_t B_live = ballot(live);
+        const uint64_t B_leaf = ballot(node >= nleaf);
+        const uint64_t B_reach = ballot(dg2 < rs * rs);
+        const uint64_t B_mac = ballot(cb.w * cb.w < w.theta2 * R2);
+        const uint64_t refine = B_reach | ~B_mac;   // reachable or MAC failed
+        const uint64_t bo = B_live & ~B_leaf & refine;   // open
+        const uint64_t bn = B_live & B_leaf & refine;    // near leaf
+        const uint64_t bc = bn & B_reach;                // near leaf, neighbour candidate
+        const uint64_t bf = B_live & ~B_reach & B_mac;   // far
         // one lane per entry (li == 0) turns the 8 decision bits into list entries
         const uint32_t om = (uint32_t)((bo >> (8 * slot)) & 0xffull);
         const uint32_t nm = (uint32_t)((bn >> (8 * slot)) & 0xffull);
         const uint32_t cm = (uint32_t)((bc >> (8 * slot)) & 0xffull);
         const uint32_t fm = (uint32_t)((bf >> (8 * slot)) & 0xffull);
         const bool lead = act && li == 0;
-        const uint64_t b_open = ballot(lead && om != 0);
-        const uint64_t b_near = ballot(lead && nm != 0);
-        const uint64_t b_far = ballot(lead && fm != 0);
+        const uint64_t b_open = byte_any(bo), b_near = byte_any(bn), b_far = byte_any(bf);
         const int no = __popcll(b_open);
         if (sp + 2 * no > kGStack) {
             overflow = true;

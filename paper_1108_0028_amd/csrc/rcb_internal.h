@@ -198,7 +198,7 @@ __device__ __forceinline__ double swap_adjacent_lanes(double v) {
     r.w[1] = __builtin_amdgcn_mov_dpp(u.w[1], 0xB1, 0xF, 0xF, false);
     return r.d;
 }
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 __device__ __forceinline__ int rank_below(uint64_t mask) {
     const int l = lane_id();
     uint64_t below = l ? (mask & ((~0ull) >> (64 - l))) : 0ull;
