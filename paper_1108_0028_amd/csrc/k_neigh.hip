@@ -43,7 +43,8 @@ struct NeighArgs {
 
 struct alignas(16) SrcN {
     double x, y, z;
-    int32_t pb;
+    int32_t pb;   // tree position
+    int32_t id;   // caller index
 };
 
 // tile: 64 staged sources, then 64 sources that can never be neighbours
@@ -70,6 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
     SrcN dummy;
     dummy.x = dummy.y = dummy.z = __builtin_inf();
     dummy.pb = -1;
+    dummy.id = -1;
     sh.tile[kWave + lane] = dummy;
     const int64_t n0 = a.gnear_beg[gi], n1 = a.gnear_end[gi];
     for (int li = 0; li < G; ++li) {
@@ -102,17 +104,17 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
                         s.y = a.py[pb];
                         s.z = a.pz[pb];
                         s.pb = pb;
+                        s.id = a.pid[pb];
                         sh.tile[lane] = s;
                     }
                     tile_sync();
                     const int nt = tot - t < kWave ? tot - t : kWave;
                     for (int u0 = 0; u0 < nt; u0 += L.J) {
                         const SrcN s = sh.tile[u0 + L.slice];
-                        const int32_t pb = s.pb;
-                        const bool hit = pb != pa && dist2(xa, ya, za, s.x, s.y, s.z) < lim;
+                        const bool hit = s.pb != pa && dist2(xa, ya, za, s.x, s.y, s.z) < lim;
                         const uint64_t bal = ballot(hit) & segmask;
                         const int r = cnt + rank_below(bal);
-                        if (hit && (!SLAB || r < kNbCap)) a.ids[obase + r] = a.pid[pb];
+                        if (hit && (!SLAB || r < kNbCap)) a.ids[obase + r] = s.id;
                         cnt += __popcll(bal);
                     }
                     tile_sync();
