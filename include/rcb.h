@@ -84,6 +84,23 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
                      rcb_tree **out);
 
 /*
+ * Moments-only refresh with the tree held fixed (Sec. 2.1 "Updating the
+ * tree": when no particle has left its lowest-level cell the tree is kept and
+ * only its moments are recomputed). New positions, masses and smoothing
+ * lengths replace the build's inputs, particle by particle in caller order;
+ * topology (cell ranges, boxes, splits) and the interaction lists stay as
+ * they are, and every node's mass, centre of mass, h_node_int, the leaves'
+ * Eq. 1 quadrupole and h_node and the Eq. 2 quadrupoles above are recomputed
+ * by the same canonical sums as rcb_build. Neighbour lists must be counted
+ * again afterwards (rcb_neighbours_fill returns RCB_ESTATE until then).
+ *  x, y, z, m, h: n FP64 values each (device), n == the built n.
+ * Errors: RCB_EINVAL (NULL pointer), RCB_ESTATE (n differs from the built n),
+ * RCB_EINPUT (validate set and an input non-finite or m, h <= 0).
+ */
+rcb_status rcb_refresh(rcb_tree *t, const double *x, const double *y, const double *z,
+                       const double *m, const double *h, int64_t n, void *stream);
+
+/*
  * Tree walk (Sec. 2.2, with the reachability test of Sec. 2.3.1 and the MAC
  * of Sec. 2.4.1): makes the near and far interaction lists of every
  * lowest-level cell and keeps them in the tree. The neighbour and gravity

@@ -111,6 +111,24 @@ __global__ void k_gather_h(const double *__restrict__ h, const int32_t *__restri
         oh[i] = h[id[i]];
 }
 
+// refresh: new inputs into one level's particle order (h only if ph != null)
+__global__ void k_refresh_gather(const double *__restrict__ x, const double *__restrict__ y,
+                                 const double *__restrict__ z, const double *__restrict__ m,
+                                 const double *__restrict__ h, const int32_t *__restrict__ id, int64_t n,
+                                 double *__restrict__ px, double *__restrict__ py,
+                                 double *__restrict__ pz, double *__restrict__ pm,
+                                 double *__restrict__ ph) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = id[i];
+        px[i] = x[j];
+        py[i] = y[j];
+        pz[i] = z[j];
+        pm[i] = m[j];
+        if (ph) ph[i] = h[j];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // chunk sums. Payload A: m, m x, m y, m z and max |r - g|^2 (g = box centre).
 // Payload B (leaves): the six Eq. 1 components about the leaf centre of mass
@@ -255,8 +273,11 @@ __device__ __forceinline__ void box_centre(const NodeOut &o, int64_t lab, double
 
 // Payload-A result of a non-empty node: mass, centre of mass, h_node_int,
 // and for an internal node the split axis/plane and the children's boxes.
+// split = false (moments-only refresh): the node's box, split and children
+// stay as built.
 template <int LANES = kWave>
-__device__ void finish_a(const NodeOut &o, int64_t lab, bool leaf, const double s[4], double mx) {
+__device__ void finish_a(const NodeOut &o, int64_t lab, bool leaf, const double s[4], double mx,
+                         bool split = true) {
     const double M = s[0] + 0.0;
     double com[3];
 #pragma unroll
@@ -269,7 +290,7 @@ __device__ void finish_a(const NodeOut &o, int64_t lab, bool leaf, const double 
         o.nhint[lab] = sqrt(mx);
         o.nhnode[lab] = -1.0;
     }
-    if (leaf) return;
+    if (leaf || !split) return;
     double lo[3], hi[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -309,7 +330,8 @@ __device__ void finish_b(const NodeOut &o, int64_t lab, const double s[6], doubl
 }
 
 template <int LANES = kWave>
-__device__ void finish_empty(const NodeOut &o, int64_t lab, bool leaf, int32_t first) {
+__device__ void finish_empty(const NodeOut &o, int64_t lab, bool leaf, int32_t first,
+                             bool split = true) {
     const int l = lane_id() % LANES;
     double g[3];
     box_centre(o, lab, g);
@@ -322,7 +344,7 @@ __device__ void finish_empty(const NodeOut &o, int64_t lab, bool leaf, int32_t f
         o.nhnode[lab] = -1.0;
         if (leaf) {
             for (int q = 0; q < 6; ++q) o.nQ[6 * lab + q] = 0.0;
-        } else {
+        } else if (split) {
             o.naxis[lab] = -1;
             o.nfirst[2 * lab] = first;
             o.ncount[2 * lab] = 0;
@@ -330,7 +352,7 @@ __device__ void finish_empty(const NodeOut &o, int64_t lab, bool leaf, int32_t f
             o.ncount[2 * lab + 1] = 0;
         }
     }
-    if (!leaf && l < 6) {
+    if (!leaf && split && l < 6) {
         const int d = l % 3;
         double *dst = l >= 3 ? o.nhi : o.nlo;
         const double v = dst[3 * lab + d];
@@ -386,8 +408,9 @@ struct BigCtl {
     int32_t *big_node, *big_base, *item_big;
 };
 
-__device__ __forceinline__ void level_node(int64_t lab, bool leaf, const PartIn &in, const int32_t *__restrict__ id,
-                           const PartOut &out, const NodeOut &o, const BigCtl &bc, double *stage) {
+__device__ __forceinline__ void level_node(int64_t lab, bool leaf, bool split, const PartIn &in,
+                                           const int32_t *__restrict__ id, const PartOut &out,
+                                           const NodeOut &o, const BigCtl &bc, double *stage) {
     const int32_t s = o.nfirst[lab];
     const int32_t c = o.ncount[lab];
     if (c > kChunk) {
@@ -405,14 +428,14 @@ __device__ __forceinline__ void level_node(int64_t lab, bool leaf, const PartIn 
         return;
     }
     if (c == 0) {
-        finish_empty(o, lab, leaf, s);
+        finish_empty(o, lab, leaf, s, split);
         return;
     }
     double g[3];
     box_centre(o, lab, g);
     double sa[4], mx;
     chunk_sums<0>(in, s, (int64_t)s + c, g, g, sa, mx, stage);
-    finish_a(o, lab, leaf, sa, mx);
+    finish_a(o, lab, leaf, sa, mx, split);
     if (leaf) {
         double com[3];
         const double M = sa[0] + 0.0;
@@ -423,6 +446,7 @@ __device__ __forceinline__ void level_node(int64_t lab, bool leaf, const PartIn 
         finish_b(o, lab, sb, hn);
         return;
     }
+    if (!split) return;
     // split: axis and plane as finish_a computed them (recomputed in-wave)
     double lo[3], hi[3];
 #pragma unroll
@@ -458,7 +482,7 @@ __device__ __forceinline__ void level_node(int64_t lab, bool leaf, const PartIn 
 
 // One node per wave: every node of the level, or (packed levels) the nodes of
 // the groups of npg nodes that k_level_packed left to it (group indices).
-__global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level, PartIn in,
+__global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level, int split, PartIn in,
                                                         const int32_t *__restrict__ id,
                                                         PartOut out, NodeOut o, BigCtl bc,
                                                         const int32_t *__restrict__ groups, int npg) {
@@ -471,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level,
     }
     if (j >= nodes) return;
     __shared__ double stage_all[kWavesPerBlock][kStage];
-    level_node(nodes + j, leaf_level != 0, in, id, out, o, bc, stage_all[threadIdx.x / kWave]);
+    level_node(nodes + j, leaf_level != 0, split != 0, in, id, out, o, bc, stage_all[threadIdx.x / kWave]);
 }
 
 // Deep levels: 64 / GW nodes per wave, one per GW-lane group, when all of
@@ -480,7 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level,
 // the stable partition ranks come from a scan of the lanes' left counts
 // within the group.
 template <int GW>
-__global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int leaf_level, PartIn in,
+__global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int leaf_level, int split, PartIn in,
                                                          const int32_t *__restrict__ id,
                                                          PartOut out, NodeOut o, BigCtl bc,
                                                          int32_t *__restrict__ groups) {
@@ -505,14 +529,14 @@ __global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int leaf_level
     }
     if (!valid) return;   // whole 8-lane groups leave together
     if (c == 0) {
-        finish_empty<GW>(o, lab, leaf, s);
+        finish_empty<GW>(o, lab, leaf, s, split != 0);
         return;
     }
     double g[3];
     box_centre(o, lab, g);
     double sa[4], mx;
     chunk_sums<0, GW>(in, s, (int64_t)s + c, g, g, sa, mx);
-    finish_a<GW>(o, lab, leaf, sa, mx);
+    finish_a<GW>(o, lab, leaf, sa, mx, split != 0);
     if (leaf) {
         double com[3];
         const double M = sa[0] + 0.0;
@@ -523,6 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int leaf_level
         finish_b<GW>(o, lab, sb, hn);
         return;
     }
+    if (!split) return;
     double lo[3], hi[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -614,7 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_reduce(PartIn in, NodeOut o, B
 // (LDS) that merges equal-size neighbours left + right; the group count is
 // padded with zero groups to a power of two.
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_big_finalize(int leaf_level, NodeOut o, BigCtl bc,
+__global__ __launch_bounds__(kBlock) void k_big_finalize(int leaf_level, int split, NodeOut o, BigCtl bc,
                                                          const double *__restrict__ part) {
     constexpr int NS = Pay<P>::NS;
     __shared__ double stk[kWavesPerBlock][32][NS];
@@ -659,7 +684,7 @@ __global__ __launch_bounds__(kBlock) void k_big_finalize(int leaf_level, NodeOut
     for (int q = 0; q < NS; ++q) s[q] = stk[wv][top][q];
     mx = wave_max(mx);
     if constexpr (P == 0) {
-        finish_a(o, lab, leaf_level != 0, s, mx);
+        finish_a(o, lab, leaf_level != 0, s, mx, split != 0);
     } else {
         finish_b(o, lab, s, mx);
     }
@@ -805,6 +830,64 @@ inline unsigned blocks_for_waves(int64_t waves) {
 
 }  // namespace
 
+// One level's node pass: payload A of every node (and B at the leaf level)
+// by small-node, packed and big-node kernels; with split, the partition of
+// the big nodes into `out` (the small ones partition themselves).
+static rcb_status level_pass(rcb_tree *t, BuildScratch &b, const NodeOut &o, const BigCtl &bc, int lvl,
+                             bool split, const PartIn &in, const int32_t *id, const PartOut &out,
+                             hipStream_t s) {
+    const int64_t n = t->n;
+    const bool leaf = lvl == t->k;
+    const int64_t item_waves = b.max_items;
+    const int64_t big_waves = b.max_big;
+    RCB_HIP(hipMemsetAsync(b.ctl, 0, sizeof(int32_t) * 4, s));
+    const int64_t nodes = (int64_t)1 << lvl;
+    // group width: 8, 16 or 32 lanes per node while the average node
+    // holds at most 4 GW particles (capacity 8 GW)
+    const int gw = n <= 32 * nodes ? 8 : (n <= 64 * nodes ? 16 : (n <= 128 * nodes ? 32 : 0));
+    if (gw) {
+        const int npg = kWave / gw;
+        const int64_t ng = (nodes + npg - 1) / npg;
+        if (gw == 8)
+            k_level_packed<8><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, leaf, split, in, id, out,
+                                                                       o, bc, b.pack_groups);
+        else if (gw == 16)
+            k_level_packed<16><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, leaf, split, in, id, out,
+                                                                        o, bc, b.pack_groups);
+        else
+            k_level_packed<32><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, leaf, split, in, id, out,
+                                                                        o, bc, b.pack_groups);
+        RCB_LAUNCH_CHECK("k_level_packed");
+        k_level_small<<<blocks_for_waves(ng * npg), kBlock, 0, s>>>(lvl, leaf, split, in, id, out, o,
+                                                                    bc, b.pack_groups, npg);
+        RCB_LAUNCH_CHECK("k_level_small<list>");
+    } else {
+        k_level_small<<<blocks_for_waves(nodes), kBlock, 0, s>>>(lvl, leaf, split, in, id, out, o, bc,
+                                                                 nullptr, 1);
+        RCB_LAUNCH_CHECK("k_level_small");
+    }
+    const int64_t bw = std::min<int64_t>(big_waves, nodes);
+    k_chunk_reduce<0><<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part);
+    RCB_LAUNCH_CHECK("k_chunk_reduce<0>");
+    k_big_finalize<0><<<blocks_for_waves(bw), kBlock, 0, s>>>(leaf, split, o, bc, b.part);
+    RCB_LAUNCH_CHECK("k_big_finalize<0>");
+    if (leaf) {
+        k_chunk_reduce<1><<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part);
+        RCB_LAUNCH_CHECK("k_chunk_reduce<1>");
+        k_big_finalize<1><<<blocks_for_waves(bw), kBlock, 0, s>>>(leaf, split, o, bc, b.part);
+        RCB_LAUNCH_CHECK("k_big_finalize<1>");
+    } else if (split) {
+        k_part_count<<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part_left);
+        RCB_LAUNCH_CHECK("k_part_count");
+        k_part_scan<<<blocks_for_waves(bw), kBlock, 0, s>>>(o, bc, b.part_left);
+        RCB_LAUNCH_CHECK("k_part_scan");
+        k_part_scatter<<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, id, out, o, bc,
+                                                                       b.part_left);
+        RCB_LAUNCH_CHECK("k_part_scatter");
+    }
+    return RCB_OK;
+}
+
 rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const double *z,
                       const double *m, const double *h, hipStream_t s) {
     const int64_t n = t->n;
@@ -823,6 +906,8 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     t->nhnode = (double *)A(sizeof(double) * t->nlab, t->allocs);
     t->wrec = (double4 *)A(sizeof(double4) * 2 * t->nlab, t->allocs);
     t->ph = (double *)A(sizeof(double) * n, t->allocs);
+    // particle order (caller indices) at every level; the last one is pid
+    t->lvl_id = (int32_t *)A(sizeof(int32_t) * n * (t->k + 1), t->allocs);
     t->dflag = (int32_t *)A(sizeof(int32_t) * 8, t->allocs);
     BuildScratch b{};
     for (int i = 0; i < 2; ++i) {
@@ -830,7 +915,6 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         b.y[i] = (double *)A(sizeof(double) * n, tmp);
         b.z[i] = (double *)A(sizeof(double) * n, tmp);
         b.m[i] = (double *)A(sizeof(double) * n, tmp);
-        b.id[i] = (int32_t *)A(sizeof(int32_t) * n, tmp);
     }
     b.max_big = std::min<int64_t>(t->nleaf, n / (kChunk + 1) + 1);
     b.max_items = n / kChunk + b.max_big + 1;
@@ -864,7 +948,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         }
     }
     const unsigned gN = (unsigned)std::min<int64_t>(4096, (n + kBlock - 1) / kBlock);
-    k_init<<<gN, kBlock, 0, s>>>(x, y, z, m, n, b.x[0], b.y[0], b.z[0], b.m[0], b.id[0]);
+    k_init<<<gN, kBlock, 0, s>>>(x, y, z, m, n, b.x[0], b.y[0], b.z[0], b.m[0], t->lvl_id);
     RCB_LAUNCH_CHECK("k_init");
     k_bounds_partial<<<nbp, kBlock, 0, s>>>(x, y, z, n, b.bounds);
     RCB_LAUNCH_CHECK("k_bounds_partial");
@@ -881,55 +965,15 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     for (int lvl = 0; lvl <= t->k; ++lvl) {
         const bool leaf = lvl == t->k;
         if (leaf) {
-            k_gather_h<<<gN, kBlock, 0, s>>>(h, b.id[cur], n, t->ph);
+            k_gather_h<<<gN, kBlock, 0, s>>>(h, t->lvl_id + lvl * n, n, t->ph);
             RCB_LAUNCH_CHECK("k_gather_h");
         }
         PartIn in{b.x[cur], b.y[cur], b.z[cur], b.m[cur], t->ph};
-        PartOut out{b.x[cur ^ 1], b.y[cur ^ 1], b.z[cur ^ 1], b.m[cur ^ 1], b.id[cur ^ 1]};
-        RCB_HIP(hipMemsetAsync(b.ctl, 0, sizeof(int32_t) * 4, s));
-        const int64_t nodes = (int64_t)1 << lvl;
-        // group width: 8, 16 or 32 lanes per node while the average node
-        // holds at most 4 GW particles (capacity 8 GW)
-        const int gw = n <= 32 * nodes ? 8 : (n <= 64 * nodes ? 16 : (n <= 128 * nodes ? 32 : 0));
-        if (gw) {
-            const int npg = kWave / gw;
-            const int64_t ng = (nodes + npg - 1) / npg;
-            if (gw == 8)
-                k_level_packed<8><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, leaf, in, b.id[cur], out,
-                                                                           o, bc, b.pack_groups);
-            else if (gw == 16)
-                k_level_packed<16><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, leaf, in, b.id[cur], out,
-                                                                            o, bc, b.pack_groups);
-            else
-                k_level_packed<32><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, leaf, in, b.id[cur], out,
-                                                                            o, bc, b.pack_groups);
-            RCB_LAUNCH_CHECK("k_level_packed");
-            k_level_small<<<blocks_for_waves(ng * npg), kBlock, 0, s>>>(lvl, leaf, in, b.id[cur], out, o,
-                                                                        bc, b.pack_groups, npg);
-            RCB_LAUNCH_CHECK("k_level_small<list>");
-        } else {
-            k_level_small<<<blocks_for_waves(nodes), kBlock, 0, s>>>(lvl, leaf, in, b.id[cur], out, o, bc,
-                                                                     nullptr, 1);
-            RCB_LAUNCH_CHECK("k_level_small");
-        }
-        const int64_t bw = std::min<int64_t>(big_waves, nodes);
-        k_chunk_reduce<0><<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part);
-        RCB_LAUNCH_CHECK("k_chunk_reduce<0>");
-        k_big_finalize<0><<<blocks_for_waves(bw), kBlock, 0, s>>>(leaf, o, bc, b.part);
-        RCB_LAUNCH_CHECK("k_big_finalize<0>");
-        if (leaf) {
-            k_chunk_reduce<1><<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part);
-            RCB_LAUNCH_CHECK("k_chunk_reduce<1>");
-            k_big_finalize<1><<<blocks_for_waves(bw), kBlock, 0, s>>>(leaf, o, bc, b.part);
-            RCB_LAUNCH_CHECK("k_big_finalize<1>");
-        } else {
-            k_part_count<<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part_left);
-            RCB_LAUNCH_CHECK("k_part_count");
-            k_part_scan<<<blocks_for_waves(bw), kBlock, 0, s>>>(o, bc, b.part_left);
-            RCB_LAUNCH_CHECK("k_part_scan");
-            k_part_scatter<<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, b.id[cur], out, o, bc,
-                                                                           b.part_left);
-            RCB_LAUNCH_CHECK("k_part_scatter");
+        int32_t *id_next = leaf ? nullptr : t->lvl_id + (int64_t)(lvl + 1) * n;
+        PartOut out{b.x[cur ^ 1], b.y[cur ^ 1], b.z[cur ^ 1], b.m[cur ^ 1], id_next};
+        rcb_status st = level_pass(t, b, o, bc, lvl, true, in, t->lvl_id + (int64_t)lvl * n, out, s);
+        if (st != RCB_OK) return st;
+        if (!leaf) {
             cur ^= 1;
         }
     }
@@ -946,9 +990,8 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     t->py = b.y[cur];
     t->pz = b.z[cur];
     t->pm = b.m[cur];
-    t->pid = b.id[cur];
-    for (void *p : {(void *)b.x[cur], (void *)b.y[cur], (void *)b.z[cur], (void *)b.m[cur],
-                    (void *)b.id[cur]}) {
+    t->pid = t->lvl_id + (int64_t)t->k * n;
+    for (void *p : {(void *)b.x[cur], (void *)b.y[cur], (void *)b.z[cur], (void *)b.m[cur]}) {
         t->allocs.push_back(p);
         for (auto &q : tmp)
             if (q == p) q = nullptr;
@@ -967,6 +1010,78 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     }
     for (void *p : tmp)
         if (p) RCB_HIP(hipFreeAsync(p, s));
+    return RCB_OK;
+}
+
+// Moments-only refresh (the tree held fixed): new inputs in the built order,
+// then every node's M, centre of mass, h_node_int, leaf Eq. 1 quadrupole and
+// h_node by the same canonical sums as the build, Eq. 2 upwards, and the walk
+// records; boxes, splits, ranges and interaction lists stay.
+rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const double *z,
+                        const double *m, const double *h, hipStream_t s) {
+    const int64_t n = t->n;
+    std::vector<void *> tmp;
+    auto A = [&](size_t bytes) { return dalloc(t, bytes, s, tmp); };
+    BuildScratch b{};
+    b.max_big = std::min<int64_t>(t->nleaf, n / (kChunk + 1) + 1);
+    b.max_items = n / kChunk + b.max_big + 1;
+    b.ctl = (int32_t *)A(sizeof(int32_t) * 4);
+    b.big_node = (int32_t *)A(sizeof(int32_t) * b.max_big);
+    b.big_base = (int32_t *)A(sizeof(int32_t) * b.max_big);
+    b.item_big = (int32_t *)A(sizeof(int32_t) * b.max_items);
+    b.part = (double *)A(sizeof(double) * 8 * b.max_items);
+    b.pack_groups = (int32_t *)A(sizeof(int32_t) * (t->nleaf / 2 + 1));
+    double *rx = (double *)A(sizeof(double) * n), *ry = (double *)A(sizeof(double) * n);
+    double *rz = (double *)A(sizeof(double) * n), *rm = (double *)A(sizeof(double) * n);
+    for (void *p : tmp)
+        if (!p) return RCB_ENOMEM;
+    if (t->p.validate) {
+        const int nbp = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
+        RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t), s));
+        k_validate<<<nbp, kBlock, 0, s>>>(x, y, z, m, h, n, t->dflag);
+        RCB_LAUNCH_CHECK("k_validate");
+        int32_t flag = 0;
+        RCB_HIP(hipMemcpyAsync(&flag, t->dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        RCB_HIP(hipStreamSynchronize(s));
+        if (flag) {
+            set_error("rcb_refresh: input has a non-finite coordinate, m <= 0 or h <= 0");
+            for (void *p : tmp) hipFreeAsync(p, s);
+            return RCB_EINPUT;
+        }
+    }
+    const unsigned gN = (unsigned)std::min<int64_t>(4096, (n + kBlock - 1) / kBlock);
+    NodeOut o{t->nfirst, t->ncount, t->nlo, t->nhi, t->ncom, t->nM, t->nhint, t->nhnode, t->nQ,
+              nullptr, nullptr};
+    BigCtl bc{b.ctl, b.big_node, b.big_base, b.item_big};
+    const PartOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
+    // each level sums its nodes in that level's order of the build (ascending
+    // caller index within every node), like the build itself
+    for (int lvl = 0; lvl <= t->k; ++lvl) {
+        const int32_t *idl = t->lvl_id + (int64_t)lvl * n;
+        const bool leaf = lvl == t->k;
+        PartIn in{rx, ry, rz, rm, nullptr};
+        if (leaf) in = PartIn{t->px, t->py, t->pz, t->pm, t->ph};
+        k_refresh_gather<<<gN, kBlock, 0, s>>>(x, y, z, m, h, idl, n, (double *)in.x, (double *)in.y,
+                                               (double *)in.z, (double *)in.m, leaf ? t->ph : nullptr);
+        RCB_LAUNCH_CHECK("k_refresh_gather");
+        rcb_status st = level_pass(t, b, o, bc, lvl, false, in, idl, none, s);
+        if (st != RCB_OK) return st;
+    }
+    for (int lvl = t->k - 1; lvl >= 0; --lvl) {
+        const int64_t nodes = (int64_t)1 << lvl;
+        k_upward<<<(unsigned)((nodes + 255) / 256), 256, 0, s>>>(lvl, o);
+        RCB_LAUNCH_CHECK("k_upward");
+    }
+    k_records<<<(unsigned)((t->nlab + 255) / 256), 256, 0, s>>>(t->nlab, o, t->wrec);
+    RCB_LAUNCH_CHECK("k_records");
+    if (t->p.precision == RCB_MIXED) {
+        k_mixed_prep<<<blocks_for_waves(t->nleaf), kBlock, 0, s>>>(
+            t->nleaf, t->nfirst, t->ncount, t->ncom, t->px, t->py, t->pz, t->pm, t->ph, t->fdx,
+            t->fdy, t->fdz, t->fm, t->fh);
+        RCB_LAUNCH_CHECK("k_mixed_prep");
+    }
+    t->nb_total = -1;   // neighbour counts belong to the old positions
+    for (void *p : tmp) RCB_HIP(hipFreeAsync(p, s));
     return RCB_OK;
 }
 

@@ -129,6 +129,22 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
     return RCB_OK;
 }
 
+rcb_status rcb_refresh(rcb_tree *t, const double *x, const double *y, const double *z,
+                       const double *m, const double *h, int64_t n, void *stream) {
+    g_last_error.clear();
+    if (!t || !x || !y || !z || !m || !h) {
+        set_error("rcb_refresh: NULL argument");
+        return RCB_EINVAL;
+    }
+    if (n != t->n) {
+        set_error("rcb_refresh: n = " + std::to_string(n) + " differs from the built n = " +
+                  std::to_string(t->n));
+        return RCB_ESTATE;
+    }
+    t->stream = (hipStream_t)stream;
+    return refresh_tree(t, x, y, z, m, h, t->stream);
+}
+
 rcb_status rcb_walk(rcb_tree *t, void *stream) {
     g_last_error.clear();
     if (!t) {

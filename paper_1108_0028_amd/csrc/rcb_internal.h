@@ -31,7 +31,6 @@ constexpr double kReachPad = 1.0 + 0x1p-32;
 struct BuildScratch {
     // ping-pong particle buffers
     double *x[2], *y[2], *z[2], *m[2];
-    int32_t *id[2];
     // big-node machinery
     int32_t *ctl;          // [0] big-node count, [1] item count, [2] groups left by the packed pass
     int32_t *big_node;     // big-node list (labels)
@@ -59,7 +58,8 @@ struct rcb_tree {
     int device = 0;
 
     double *px = nullptr, *py = nullptr, *pz = nullptr, *pm = nullptr, *ph = nullptr;
-    int32_t *pid = nullptr;
+    int32_t *pid = nullptr;            // tree position -> caller index (= lvl_id of level k)
+    int32_t *lvl_id = nullptr;         // (k + 1) x n: the order at each level of the build
     float *fdx = nullptr, *fdy = nullptr, *fdz = nullptr, *fm = nullptr, *fh = nullptr;
 
     int32_t *nfirst = nullptr, *ncount = nullptr;
@@ -103,6 +103,9 @@ void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owne
 // build (k_build.hip)
 rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const double *z,
                       const double *m, const double *h, hipStream_t s);
+// moments-only refresh with new inputs, topology and lists held fixed (k_build.hip)
+rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const double *z,
+                        const double *m, const double *h, hipStream_t s);
 // device exclusive scan of int64 counts in place-free form: out[0..n] (k_scan.hip)
 rcb_status scan_i64(rcb_tree *t, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
 // walk (k_walk.hip)

@@ -95,3 +95,73 @@ def test_autograd_function_uses_the_vjp():
     ref, _ = _gpu_vjp(c, g, 6, 0.6, "fp64")
     for t, r in zip((x, y, z, m), ref):
         assert np.abs(_np(t.grad) - r).max() <= 1e-9 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_refresh_matches_oracle_refresh(prec):
+    """rcb_refresh on moved inputs: every node moment bit-identical to the
+    oracle's refresh of the same tree, and the accelerations on the kept lists
+    within the forward bar."""
+    from test_gpu_parity import TOL as FTOL, compare_trees, gate
+    from paper_1108_0028_amd import Tree
+    c = W.small_random(3000, 41, "clustered")
+    _say("refresh", prec)
+    tree = Tree(*[_t(a) for a in c.arrays()], n_ll=8, theta=0.6, precision=prec)
+    tree.walk()
+    ot = O.OracleTree(*c.arrays(), n_ll=8)
+    ot.walk(0.6)
+    rng = np.random.default_rng(5)
+    moved = [c.x + 2e-3 * rng.normal(size=c.n), c.y + 2e-3 * rng.normal(size=c.n),
+             c.z + 2e-3 * rng.normal(size=c.n), c.m * rng.uniform(0.9, 1.1, c.n),
+             c.h * rng.uniform(0.9, 1.1, c.n)]
+    tree.refresh(*[_t(a) for a in moved])
+    ot.refresh(*moved)
+    compare_trees(tree, ot)
+    a = np.stack([_np(v) for v in tree.gravity()], 1)
+    ref = np.stack(ot.gravity(), 1)
+    assert gate(a, ref) <= FTOL[prec]
+
+
+def test_vjp_matches_finite_differences_on_refreshed_tree():
+    """Central differences of L = sum g . a on the GPU itself: perturb one input,
+    rcb_refresh (tree held fixed), rcb_gravity; compare with rcb_gravity_vjp."""
+    from paper_1108_0028_amd import Tree
+    c = W.small_random(400, 43, "clustered")
+    g = W.cotangents(c.n, seed=7)
+    _say("gpu finite differences", c.n)
+    base = [np.array(a, dtype=np.float64) for a in c.arrays()]
+    tree = Tree(*[_t(a) for a in base], n_ll=6, theta=0.6, precision="fp64")
+    tree.walk()
+    dx, dy, dz, dm = [_np(o) for o in tree.vjp(*[_t(a) for a in g])]
+
+    def L(vals):
+        tree.refresh(*[_t(a) for a in vals])
+        acc = [_np(v) for v in tree.gravity()]
+        return float(sum(np.dot(gi, ai) for gi, ai in zip(g, acc)))
+
+    rng = np.random.default_rng(3)
+    for b in rng.choice(c.n, 6, replace=False):
+        for comp, grad in ((0, dx), (1, dy), (2, dz), (3, dm)):
+            eps = 1e-6 if comp < 3 else 1e-6 * base[3][b]
+            plus = [a.copy() for a in base]
+            minus = [a.copy() for a in base]
+            plus[comp][b] += eps
+            minus[comp][b] -= eps
+            fd = (L(plus) - L(minus)) / (2 * eps)
+            scale = np.max(np.abs(grad)) if comp < 3 else np.max(np.abs(grad * base[3]))
+            err = abs(fd - grad[b]) * (1.0 if comp < 3 else base[3][b])
+            assert err <= 1e-6 * scale, (int(b), comp, fd, grad[b])
+
+
+def test_refresh_with_the_build_inputs_reproduces_the_build():
+    """A refresh with unchanged inputs recomputes every moment bit for bit
+    (each level sums in the build's own order)."""
+    from paper_1108_0028_amd import Tree
+    c = W.small_random(5000, 47, "plummer")
+    _say("refresh identity")
+    args = [_t(a) for a in c.arrays()]
+    tree = Tree(*args, n_ll=6, theta=0.6)
+    before = {f: _np(tree.export(f)).copy() for f in ("com", "mass", "quad", "hint", "hnode")}
+    tree.refresh(*args)
+    for f, v in before.items():
+        np.testing.assert_array_equal(_np(tree.export(f)).view(np.int64), v.view(np.int64), err_msg=f)
