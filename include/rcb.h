@@ -84,6 +84,19 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
                      rcb_tree **out);
 
 /*
+ * Integrity check of Sec. 2.1 "Updating the tree": how many particles, at
+ * the new positions x, y, z (n FP64 each, device, caller order, n == the
+ * built n), lie outside their lowest-level cell. A cell is its box with the
+ * build's side rule: lo <= x < hi on each axis (closed at the root box's
+ * upper faces), so 0 means the tree is still the tree these positions would
+ * build with the same splits and rcb_refresh can replace a rebuild.
+ *  outside: host int64, receives the count. Synchronises `stream`.
+ * Errors: RCB_EINVAL (NULL pointer), RCB_ESTATE (n differs from the built n).
+ */
+rcb_status rcb_check_cells(rcb_tree *t, const double *x, const double *y, const double *z,
+                           int64_t n, int64_t *outside, void *stream);
+
+/*
  * Moments-only refresh with the tree held fixed (Sec. 2.1 "Updating the
  * tree": when no particle has left its lowest-level cell the tree is kept and
  * only its moments are recomputed). New positions, masses and smoothing

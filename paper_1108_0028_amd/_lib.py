@@ -33,7 +33,7 @@ class RcbTreeInfo(C.Structure):
                 ("theta", C.c_double)]
 
 
-EXPORTED = ["rcb_params_default", "rcb_build", "rcb_refresh", "rcb_walk", "rcb_neighbours_count", "rcb_neighbours_fill",
+EXPORTED = ["rcb_params_default", "rcb_build", "rcb_check_cells", "rcb_refresh", "rcb_walk", "rcb_neighbours_count", "rcb_neighbours_fill",
             "rcb_gravity", "rcb_gravity_vjp", "rcb_get_info", "rcb_tree_export", "rcb_destroy",
             "rcb_last_error"]
 
@@ -58,6 +58,8 @@ def lib():
         L.rcb_params_default.restype = None
         L.rcb_build.argtypes = [P, P, P, P, P, C.c_int64, C.POINTER(RcbParams), P, C.POINTER(P)]
         L.rcb_build.restype = C.c_int
+        L.rcb_check_cells.argtypes = [P, P, P, P, C.c_int64, C.POINTER(C.c_int64), P]
+        L.rcb_check_cells.restype = C.c_int
         L.rcb_refresh.argtypes = [P, P, P, P, P, P, C.c_int64, P]
         L.rcb_refresh.restype = C.c_int
         L.rcb_walk.argtypes = [P, P]
@@ -143,6 +145,14 @@ class Tree:
 
     def out_dtype(self):
         return torch.float32 if self.precision == "mixed" else torch.float64
+
+    def cells_left(self, x, y, z) -> int:
+        """Particles whose new position is outside their lowest-level cell."""
+        xs = [_dev(a, torch.float64, nm) for a, nm in zip((x, y, z), "xyz")]
+        out = C.c_int64()
+        _check(lib().rcb_check_cells(self.handle, *[_ptr(a) for a in xs], self.n, C.byref(out),
+                                     _stream()), "rcb_check_cells")
+        return out.value
 
     def refresh(self, x, y, z, m, h):
         """New inputs on the same tree: moments recomputed, topology and lists kept."""

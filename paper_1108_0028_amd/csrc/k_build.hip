@@ -824,6 +824,40 @@ __global__ void k_mixed_prep(int64_t nleaf, const int32_t *__restrict__ nfirst,
     }
 }
 
+// Sec. 2.1 "Updating the tree": has a particle left its lowest-level cell?
+// The cell of tree position p is [lo, hi) on each axis (the split rule sends
+// coordinate < plane to the lower child), closed at the root box's upper
+// faces. Counts the particles whose new position is outside.
+__global__ void k_outside(int64_t nleaf, const int32_t *__restrict__ nfirst,
+                          const int32_t *__restrict__ ncount, const double *__restrict__ nlo,
+                          const double *__restrict__ nhi, const int32_t *__restrict__ pid,
+                          const double *__restrict__ x, const double *__restrict__ y,
+                          const double *__restrict__ z, unsigned long long *__restrict__ out) {
+    const int64_t w = wave_index();
+    if (w >= nleaf) return;
+    const int64_t lab = nleaf + w;
+    const int64_t s = nfirst[lab], c = ncount[lab];
+    double lo[3], hi[3], rhi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = nlo[3 * lab + d];
+        hi[d] = nhi[3 * lab + d];
+        rhi[d] = nhi[3 + d];   // root box (label 1)
+    }
+    int bad = 0;
+    for (int64_t i = s + lane_id(); i < s + c; i += kWave) {
+        const int32_t j = pid[i];
+        const double r[3] = {x[j], y[j], z[j]};
+        bool in = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            in = in && r[d] >= lo[d] && (r[d] < hi[d] || (hi[d] == rhi[d] && r[d] == hi[d]));
+        bad += !in;
+    }
+    bad = wave_sum_i(bad);
+    if (lane_id() == 0 && bad) atomicAdd(out, (unsigned long long)bad);
+}
+
 inline unsigned blocks_for_waves(int64_t waves) {
     return (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
 }
@@ -1010,6 +1044,23 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     }
     for (void *p : tmp)
         if (p) RCB_HIP(hipFreeAsync(p, s));
+    return RCB_OK;
+}
+
+rcb_status count_outside(rcb_tree *t, const double *x, const double *y, const double *z,
+                         int64_t *outside, hipStream_t s) {
+    std::vector<void *> tmp;
+    unsigned long long *cnt = (unsigned long long *)dalloc(t, sizeof(unsigned long long), s, tmp);
+    if (!cnt) return RCB_ENOMEM;
+    RCB_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
+    k_outside<<<blocks_for_waves(t->nleaf), kBlock, 0, s>>>(t->nleaf, t->nfirst, t->ncount, t->nlo,
+                                                            t->nhi, t->pid, x, y, z, cnt);
+    RCB_LAUNCH_CHECK("k_outside");
+    unsigned long long h = 0;
+    RCB_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    for (void *p : tmp) RCB_HIP(hipFreeAsync(p, s));
+    RCB_HIP(hipStreamSynchronize(s));
+    *outside = (int64_t)h;
     return RCB_OK;
 }
 

@@ -129,6 +129,22 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
     return RCB_OK;
 }
 
+rcb_status rcb_check_cells(rcb_tree *t, const double *x, const double *y, const double *z,
+                           int64_t n, int64_t *outside, void *stream) {
+    g_last_error.clear();
+    if (!t || !x || !y || !z || !outside) {
+        set_error("rcb_check_cells: NULL argument");
+        return RCB_EINVAL;
+    }
+    if (n != t->n) {
+        set_error("rcb_check_cells: n = " + std::to_string(n) + " differs from the built n = " +
+                  std::to_string(t->n));
+        return RCB_ESTATE;
+    }
+    t->stream = (hipStream_t)stream;
+    return count_outside(t, x, y, z, outside, t->stream);
+}
+
 rcb_status rcb_refresh(rcb_tree *t, const double *x, const double *y, const double *z,
                        const double *m, const double *h, int64_t n, void *stream) {
     g_last_error.clear();

@@ -103,6 +103,9 @@ void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owne
 // build (k_build.hip)
 rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const double *z,
                       const double *m, const double *h, hipStream_t s);
+// particles whose new position lies outside their lowest-level cell (k_build.hip)
+rcb_status count_outside(rcb_tree *t, const double *x, const double *y, const double *z,
+                         int64_t *outside, hipStream_t s);
 // moments-only refresh with new inputs, topology and lists held fixed (k_build.hip)
 rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const double *z,
                         const double *m, const double *h, hipStream_t s);

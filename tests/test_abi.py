@@ -27,7 +27,7 @@ def _lib():
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for req in ("rcb_build", "rcb_refresh", "rcb_walk", "rcb_neighbours_count", "rcb_neighbours_fill", "rcb_gravity",
+    for req in ("rcb_build", "rcb_check_cells", "rcb_refresh", "rcb_walk", "rcb_neighbours_count", "rcb_neighbours_fill", "rcb_gravity",
                 "rcb_gravity_vjp", "rcb_destroy", "rcb_last_error"):
         assert req in names
 
@@ -89,6 +89,7 @@ def test_null_tree_arguments():
     tot = C.c_int64()
     assert L.rcb_walk(None, None) == 1
     assert L.rcb_refresh(None, *([C.c_void_p(8)] * 5), 1, None) == 1
+    assert L.rcb_check_cells(None, *([C.c_void_p(8)] * 3), 1, C.byref(tot), None) == 1
     assert L.rcb_neighbours_count(None, C.c_void_p(8), C.byref(tot), None) == 1
     assert L.rcb_neighbours_fill(None, C.c_void_p(8), C.c_void_p(8), 1, None) == 1
     assert L.rcb_gravity(None, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None) == 1

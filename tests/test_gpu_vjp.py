@@ -165,3 +165,34 @@ def test_refresh_with_the_build_inputs_reproduces_the_build():
     tree.refresh(*args)
     for f, v in before.items():
         np.testing.assert_array_equal(_np(tree.export(f)).view(np.int64), v.view(np.int64), err_msg=f)
+
+
+@pytest.mark.parametrize("kind", ["clustered", "uniform"])
+def test_check_cells_counts_particles_that_left_their_cell(kind):
+    """rcb_check_cells: 0 for the build inputs; for moved inputs the count of
+    the host's box test on the exported cells (lo <= x < hi, closed at the
+    root's upper faces)."""
+    from paper_1108_0028_amd import Tree
+    c = W.small_random(4000, 53, kind)
+    _say("check cells", kind)
+    tree = Tree(*[_t(a) for a in c.arrays()], n_ll=8, theta=0.6)
+    assert tree.cells_left(_t(c.x), _t(c.y), _t(c.z)) == 0
+    k = tree.info()["k"]
+    nleaf = 1 << k
+    lo = _np(tree.export("lo")).reshape(-1, 3)
+    hi = _np(tree.export("hi")).reshape(-1, 3)
+    first = _np(tree.export("first")).astype(np.int64)
+    count = _np(tree.export("count")).astype(np.int64)
+    perm = _np(tree.export("perm")).astype(np.int64)
+    rng = np.random.default_rng(9)
+    for step in (1e-4, 3e-3, 3e-2):
+        r = np.stack([c.x, c.y, c.z], 1) + step * rng.normal(size=(c.n, 3))
+        want = 0
+        for L in range(nleaf, 2 * nleaf):
+            ids = perm[first[L]:first[L] + count[L]]
+            p = r[ids]
+            inside = (p >= lo[L]) & ((p < hi[L]) | ((hi[L] == hi[1]) & (p == hi[L])))
+            want += int((~inside.all(1)).sum())
+        got = tree.cells_left(_t(r[:, 0]), _t(r[:, 1]), _t(r[:, 2]))
+        assert got == want, (step, got, want)
+        assert step < 1e-3 or got > 0
