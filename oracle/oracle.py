@@ -48,7 +48,7 @@ def lib():
         L.orc_depth_for.restype = C.c_int
         L.orc_topology.argtypes = [P, i64p, i64p, i64p, i32p]
         L.orc_nodes.argtypes = [P, dp, dp, dp, dp, dp, dp, dp]
-        L.orc_walk.argtypes = [P, C.c_double, i64p, C.c_int64]
+        L.orc_walk.argtypes = [P, C.c_double, i64p, C.c_int64, C.c_int]
         L.orc_list_sizes.argtypes = [P, i64p, i64p, i64p]
         L.orc_leaf_lists.argtypes = [P, C.c_int64, i32p, i32p]
         L.orc_neighbours_count.argtypes = [P, i64p]
@@ -162,13 +162,15 @@ class OracleTree:
         lib().orc_nodes(self.ptr, *[a.ctypes.data_as(dp) for a in (lo, hi, com, M, Q, hint, hnode)])
         return dict(lo=lo, hi=hi, com=com, M=M, Q=Q, hint=hint, hnode=hnode)
 
-    def walk(self, theta: float, leaves=None):
-        """Walk all leaves, or only the given leaf labels."""
+    def walk(self, theta: float, leaves=None, pure_mac: bool = False):
+        """Walk all leaves, or only the given leaf labels. pure_mac: gravity by
+        the geometric MAC alone (Sec. 2.5 variant), neighbours by reachability."""
+        pm = 1 if pure_mac else 0
         if leaves is None:
-            lib().orc_walk(self.ptr, theta, None, 0)
+            lib().orc_walk(self.ptr, theta, None, 0, pm)
         else:
             lv = np.ascontiguousarray(leaves, dtype=np.int64)
-            lib().orc_walk(self.ptr, theta, _i64(lv), lv.shape[0])
+            lib().orc_walk(self.ptr, theta, _i64(lv), lv.shape[0], pm)
         self.theta = theta
         self.walked = leaves
 

@@ -61,8 +61,14 @@ static double dist2(double ax, double ay, double az, double bx, double by, doubl
 /* Tree storage. Labels follow Sec. 2.1 "Node labelling": root = 1, children */
 /* of n are 2n and 2n+1, level l holds labels 2^l .. 2^(l+1)-1.              */
 /* ------------------------------------------------------------------------ */
+/* Near-list entries: leaf label | flags. NEAR_NBONLY marks a leaf that only
+   the neighbour search uses (set by the pure-MAC walk alone). */
+#define NEAR_CAND 0x80000000u     /* neighbour candidate (reachable) */
+#define NEAR_NBONLY 0x40000000u   /* not part of the gravity near field */
+#define NEAR_LABEL 0x3fffffffu
+
 typedef struct {
-    int32_t *near;     /* leaf label | (candidate << 31) */
+    int32_t *near;     /* leaf label | NEAR_CAND | NEAR_NBONLY */
     int64_t nnear;
     int64_t capnear;
     int32_t *far;      /* node label */
@@ -85,6 +91,7 @@ typedef struct otree {
     double *M, *com, *Q;           /* Q: xx xy xz yy yz zz per label */
     double *hint, *hnode;
     double theta;
+    int pure_mac;                  /* walk mode of the last orc_walk */
     leaf_lists *lists;             /* one per leaf, index label - 2^k */
 } otree;
 
@@ -366,13 +373,13 @@ void orc_nodes(const otree *t, double *lo, double *hi, double *com, double *M, d
 /* ------------------------------------------------------------------------ */
 /* Walk (Sec. 2.2, 2.3.1, 2.4.1): depth-first from nodes 2 and 3.            */
 /* ------------------------------------------------------------------------ */
-static void push_near(leaf_lists *L, int64_t lab, int cand)
+static void push_near(leaf_lists *L, int64_t lab, uint32_t flags)
 {
     if (L->nnear == L->capnear) {
         L->capnear = L->capnear ? 2 * L->capnear : 64;
         L->near = (int32_t *)realloc(L->near, (size_t)L->capnear * sizeof(int32_t));
     }
-    L->near[L->nnear++] = (int32_t)((uint32_t)lab | ((uint32_t)(cand != 0) << 31));
+    L->near[L->nnear++] = (int32_t)((uint32_t)lab | flags);
 }
 
 static void push_far(leaf_lists *L, int64_t lab)
@@ -384,12 +391,10 @@ static void push_far(leaf_lists *L, int64_t lab)
     L->far[L->nfar++] = (int32_t)lab;
 }
 
-static void visit(const otree *t, int64_t A, int64_t B, double theta, leaf_lists *L)
+/* Sec. 2.3.1: B is reachable from A if the spheres around the geometric     */
+/* centres with radii h_node(A) and h_node_int(B) overlap.                   */
+static int reachable(const otree *t, int64_t A, int64_t B)
 {
-    if (t->count[B] == 0) return;              /* empty cells are ignored */
-    L->visited++;
-    int64_t leaf0 = (int64_t)1 << t->k;
-    int is_leaf = B >= leaf0;
     double gA[3], gB[3];
     for (int d = 0; d < 3; ++d) {
         gA[d] = 0.5 * (t->lo[3 * A + d] + t->hi[3 * A + d]);
@@ -397,12 +402,13 @@ static void visit(const otree *t, int64_t A, int64_t B, double theta, leaf_lists
     }
     double dg2 = dist2(gA[0], gA[1], gA[2], gB[0], gB[1], gB[2]);
     double rs = (t->hnode[A] + t->hint[B]) * REACH_PAD;
-    int reach = dg2 < rs * rs;
-    if (reach) {                               /* reachable: never accepted */
-        if (is_leaf) push_near(L, B, 1);
-        else { visit(t, A, 2 * B, theta, L); visit(t, A, 2 * B + 1, theta, L); }
-        return;
-    }
+    return dg2 < rs * rs;
+}
+
+/* Sec. 2.4.1, Eq. 4: H_B / R_AB < theta, H_B the longest side of B, R_AB   */
+/* the distance of the centres of mass.                                      */
+static int mac_accepts(const otree *t, int64_t A, int64_t B, double theta)
+{
     double HB = t->hi[3 * B] - t->lo[3 * B];
     for (int d = 1; d < 3; ++d) {
         double side = t->hi[3 * B + d] - t->lo[3 * B + d];
@@ -410,12 +416,90 @@ static void visit(const otree *t, int64_t A, int64_t B, double theta, leaf_lists
     }
     const double *cA = &t->com[3 * A], *cB = &t->com[3 * B];
     double R2 = dist2(cA[0], cA[1], cA[2], cB[0], cB[1], cB[2]);
-    if (HB * HB < (theta * theta) * R2) {      /* geometric MAC */
+    return HB * HB < (theta * theta) * R2;
+}
+
+/* Combined walk of the paper (Sec. 2.4.1): a reachable cell is never       */
+/* accepted; its leaves are neighbour candidates and belong to the near     */
+/* field.                                                                   */
+static void visit(const otree *t, int64_t A, int64_t B, double theta, leaf_lists *L)
+{
+    if (t->count[B] == 0) return;              /* empty cells are ignored */
+    L->visited++;
+    int is_leaf = B >= ((int64_t)1 << t->k);
+    if (reachable(t, A, B)) {                  /* reachable: never accepted */
+        if (is_leaf) push_near(L, B, NEAR_CAND);
+        else { visit(t, A, 2 * B, theta, L); visit(t, A, 2 * B + 1, theta, L); }
+        return;
+    }
+    if (mac_accepts(t, A, B, theta)) {         /* geometric MAC */
         push_far(L, B);
         return;
     }
     if (is_leaf) push_near(L, B, 0);
     else { visit(t, A, 2 * B, theta, L); visit(t, A, 2 * B + 1, theta, L); }
+}
+
+/* B is A or one of A's ancestors (labels of Sec. 2.1). */
+static int contains(int64_t B, int64_t A)
+{
+    while (A > B) A >>= 1;
+    return A == B;
+}
+
+/* Gravity walk with the geometric MAC alone (the variant of Sec. 2.5 where  */
+/* reachability does not override the MAC). A cell that contains A itself   */
+/* is never accepted: the combined walk never accepts one either, since a    */
+/* particle of A lies in both cells and the triangle inequality then makes   */
+/* the cell reachable.                                                       */
+static void visit_mac(const otree *t, int64_t A, int64_t B, double theta, leaf_lists *L)
+{
+    if (t->count[B] == 0) return;
+    L->visited++;
+    if (!contains(B, A) && mac_accepts(t, A, B, theta)) {
+        push_far(L, B);
+        return;
+    }
+    if (B >= ((int64_t)1 << t->k)) push_near(L, B, 0);
+    else { visit_mac(t, A, 2 * B, theta, L); visit_mac(t, A, 2 * B + 1, theta, L); }
+}
+
+/* Neighbour walk (Sec. 2.3): descend through reachable cells only; the     */
+/* reachable leaves are the candidates.                                     */
+static void visit_reach(const otree *t, int64_t A, int64_t B, leaf_lists *L)
+{
+    if (t->count[B] == 0) return;
+    L->visited++;
+    if (!reachable(t, A, B)) return;
+    if (B >= ((int64_t)1 << t->k)) push_near(L, B, NEAR_CAND);
+    else { visit_reach(t, A, 2 * B, L); visit_reach(t, A, 2 * B + 1, L); }
+}
+
+/* Pure-MAC lists of leaf A: the gravity walk's near leaves and the          */
+/* neighbour walk's candidates merged into one list by ascending label       */
+/* (both walks emit leaves in ascending order); a candidate outside the      */
+/* gravity near field carries NEAR_NBONLY.                                   */
+static void walk_leaf_pure(const otree *t, int64_t A, leaf_lists *L)
+{
+    leaf_lists cand = {0};
+    int64_t r0 = t->k == 0 ? 1 : 2, r1 = t->k == 0 ? 1 : 3;
+    for (int64_t B = r0; B <= r1; ++B) visit_mac(t, A, B, t->theta, L);
+    for (int64_t B = r0; B <= r1; ++B) visit_reach(t, A, B, &cand);
+    int32_t *grav = L->near;
+    int64_t ng = L->nnear;
+    L->near = NULL;
+    L->nnear = L->capnear = 0;
+    int64_t i = 0, j = 0;
+    while (i < ng || j < cand.nnear) {
+        uint32_t lg = i < ng ? (uint32_t)grav[i] & NEAR_LABEL : UINT32_MAX;
+        uint32_t lc = j < cand.nnear ? (uint32_t)cand.near[j] & NEAR_LABEL : UINT32_MAX;
+        if (lg == lc) { push_near(L, lg, NEAR_CAND); ++i; ++j; }
+        else if (lg < lc) { push_near(L, lg, 0); ++i; }
+        else { push_near(L, lc, NEAR_CAND | NEAR_NBONLY); ++j; }
+    }
+    L->visited += cand.visited;
+    free(grav);
+    free(cand.near);
 }
 
 static void walk_leaf(otree *t, int64_t A)
@@ -424,7 +508,9 @@ static void walk_leaf(otree *t, int64_t A)
     L->nnear = L->nfar = L->visited = 0;
     L->walked = 1;
     if (t->count[A] == 0) return;
-    if (t->k == 0) {
+    if (t->pure_mac) {
+        walk_leaf_pure(t, A, L);
+    } else if (t->k == 0) {
         visit(t, A, 1, t->theta, L);
     } else {
         visit(t, A, 2, t->theta, L);
@@ -432,10 +518,13 @@ static void walk_leaf(otree *t, int64_t A)
     }
 }
 
-/* Walk the given leaves (labels); with leaves == NULL walk every leaf. */
-void orc_walk(otree *t, double theta, const int64_t *leaves, int64_t nleaves)
+/* Walk the given leaves (labels); with leaves == NULL walk every leaf.      */
+/* pure_mac = 0: the paper's walk (reachability overrides the MAC);          */
+/* pure_mac = 1: gravity by the MAC alone, neighbours by reachability.       */
+void orc_walk(otree *t, double theta, const int64_t *leaves, int64_t nleaves, int pure_mac)
 {
     free_lists(t);
+    t->pure_mac = pure_mac != 0;
     int64_t nleaf = (int64_t)1 << t->k;
     t->lists = (leaf_lists *)calloc((size_t)nleaf, sizeof(leaf_lists));
     t->theta = theta;
@@ -449,7 +538,8 @@ void orc_walk(otree *t, double theta, const int64_t *leaves, int64_t nleaves)
 }
 
 /* Per-leaf list sizes (0 for leaves not walked); stats[5*i..] =            */
-/* {nodes tested, near leaves, far nodes, near particles, candidate particles}*/
+/* {nodes tested, near leaves, far nodes, near-field particles, candidate   */
+/* particles}; near leaves count every list entry.                          */
 void orc_list_sizes(const otree *t, int64_t *nnear, int64_t *nfar, int64_t *stats)
 {
     int64_t nleaf = (int64_t)1 << t->k;
@@ -460,9 +550,10 @@ void orc_list_sizes(const otree *t, int64_t *nnear, int64_t *nfar, int64_t *stat
         if (stats) {
             int64_t P = 0, C = 0;
             for (int64_t j = 0; j < L->nnear; ++j) {
-                int64_t lab = (int64_t)((uint32_t)L->near[j] & 0x7fffffffu);
-                P += t->count[lab];
-                if ((uint32_t)L->near[j] >> 31) C += t->count[lab];
+                uint32_t e = (uint32_t)L->near[j];
+                int64_t lab = (int64_t)(e & NEAR_LABEL);
+                if (!(e & NEAR_NBONLY)) P += t->count[lab];
+                if (e & NEAR_CAND) C += t->count[lab];
             }
             stats[5 * i + 0] = L->visited;
             stats[5 * i + 1] = L->nnear;
@@ -493,8 +584,8 @@ static int64_t cull_particle(const otree *t, const leaf_lists *L, int64_t a, int
     double two_h = 2.0 * t->h[a];
     double lim = two_h * two_h;
     for (int64_t j = 0; j < L->nnear; ++j) {
-        if (!((uint32_t)L->near[j] >> 31)) continue;
-        int64_t B = (int64_t)((uint32_t)L->near[j] & 0x7fffffffu);
+        if (!((uint32_t)L->near[j] & NEAR_CAND)) continue;
+        int64_t B = (int64_t)((uint32_t)L->near[j] & NEAR_LABEL);
         for (int64_t p = t->first[B]; p < t->first[B] + t->count[B]; ++p) {
             int64_t b = t->perm[p];
             if (b == a) continue;
@@ -748,7 +839,8 @@ void orc_gravity(const otree *t, double *ax, double *ay, double *az)
             int64_t a = t->perm[p];
             double acc[3] = {0.0, 0.0, 0.0};
             for (int64_t j = 0; j < L->nnear; ++j) {
-                int64_t B = (int64_t)((uint32_t)L->near[j] & 0x7fffffffu);
+                if ((uint32_t)L->near[j] & NEAR_NBONLY) continue;   /* neighbour search only */
+                int64_t B = (int64_t)((uint32_t)L->near[j] & NEAR_LABEL);
                 for (int64_t q = t->first[B]; q < t->first[B] + t->count[B]; ++q) {
                     int64_t b = t->perm[q];
                     double v[3] = {t->x[a] - t->x[b], t->y[a] - t->y[b], t->z[a] - t->z[b]};
@@ -804,7 +896,8 @@ void orc_vjp(const otree *t, const double *gx, const double *gy, const double *g
             int64_t a = t->perm[p];
             double ga[3] = {gx[a], gy[a], gz[a]};
             for (int64_t j = 0; j < LL->nnear; ++j) {
-                int64_t B = (int64_t)((uint32_t)LL->near[j] & 0x7fffffffu);
+                if ((uint32_t)LL->near[j] & NEAR_NBONLY) continue;
+                int64_t B = (int64_t)((uint32_t)LL->near[j] & NEAR_LABEL);
                 for (int64_t q = t->first[B]; q < t->first[B] + t->count[B]; ++q) {
                     int64_t b = t->perm[q];
                     double v[3] = {t->x[a] - t->x[b], t->y[a] - t->y[b], t->z[a] - t->z[b]};
