@@ -61,10 +61,15 @@ typedef struct {
     int32_t precision;  /* rcb_precision */
     double theta;       /* opening angle of the geometric MAC, Sec. 2.4.1 (paper default 0.7) */
     int32_t validate;   /* 1: check inputs on the device first (one extra pass) */
-    int32_t reserved;   /* must be 0 */
+    int32_t pure_mac;   /* 0: reachable cells are never accepted, whatever the MAC
+                           (the paper's walk, Sec. 2.4.1); 1: the gravity lists follow
+                           the MAC alone (the variant of Sec. 2.5) -- a cell is
+                           accepted when the MAC holds unless it contains the sink
+                           cell; neighbour candidates are then the leaves reached
+                           through reachable cells only */
 } rcb_params;
 
-/* Paper defaults: n_ll = 12, theta = 0.7, FP64, validate = 0. */
+/* Paper defaults: n_ll = 12, theta = 0.7, FP64, validate = 0, pure_mac = 0. */
 void rcb_params_default(rcb_params *p);
 
 /*
@@ -193,7 +198,8 @@ typedef enum {
     RCB_FIELD_HNODE = 9,     /* f64[n_labels] h_node of leaves (-1 elsewhere) */
     RCB_FIELD_NEAR_OFF = 10, /* int64[2^k + 1] per-leaf offsets into NEAR (needs the walk) */
     RCB_FIELD_FAR_OFF = 11,  /* int64[2^k + 1] per-leaf offsets into FAR */
-    RCB_FIELD_NEAR = 12,     /* int32[near_total] leaf label | candidate << 31, ascending labels */
+    RCB_FIELD_NEAR = 12,     /* int32[near_total] leaf label | candidate << 31 | (not in the
+                                gravity near field, pure_mac only) << 30, ascending labels */
     RCB_FIELD_FAR = 13       /* int32[far_total] accepted node labels, unordered */
 } rcb_field;
 

@@ -24,7 +24,7 @@ STATUS = {0: "RCB_OK", 1: "RCB_EINVAL", 2: "RCB_ENOMEM", 3: "RCB_EHIP", 4: "RCB_
 
 class RcbParams(C.Structure):
     _fields_ = [("n_ll", C.c_int32), ("precision", C.c_int32), ("theta", C.c_double),
-                ("validate", C.c_int32), ("reserved", C.c_int32)]
+                ("validate", C.c_int32), ("pure_mac", C.c_int32)]
 
 
 class RcbTreeInfo(C.Structure):
@@ -109,7 +109,7 @@ class Tree:
     """An RCB tree built on the GPU (rcb_build) and its evaluations."""
 
     def __init__(self, x, y, z, m, h, n_ll: int = 12, theta: float = 0.7, precision: str = "fp64",
-                 validate: bool = False):
+                 validate: bool = False, pure_mac: bool = False):
         L = lib()
         arrs = [_dev(a, torch.float64, nm) for a, nm in zip((x, y, z, m, h), "xyzmh")]
         n = arrs[0].numel()
@@ -122,6 +122,7 @@ class Tree:
         p.theta = float(theta)
         p.precision = RCB_MIXED if precision == "mixed" else RCB_FP64
         p.validate = 1 if validate else 0
+        p.pure_mac = 1 if pure_mac else 0
         self.precision = precision
         self.device = arrs[0].device
         self.n = n
@@ -242,9 +243,9 @@ class RCBGravity(torch.autograd.Function):
     lists held fixed). h receives no gradient."""
 
     @staticmethod
-    def forward(ctx, x, y, z, m, h, n_ll=12, theta=0.7, precision="fp64"):
+    def forward(ctx, x, y, z, m, h, n_ll=12, theta=0.7, precision="fp64", pure_mac=False):
         tree = Tree(x.detach(), y.detach(), z.detach(), m.detach(), h.detach(), n_ll=n_ll,
-                    theta=theta, precision=precision)
+                    theta=theta, precision=precision, pure_mac=pure_mac)
         ax, ay, az = tree.gravity()
         ctx.tree = tree
         return ax, ay, az
@@ -258,9 +259,10 @@ class RCBGravity(torch.autograd.Function):
         dx, dy, dz, dm = tree.vjp(*g)
         tree.destroy()
         ctx.tree = None
-        return dx, dy, dz, dm, None, None, None, None
+        return dx, dy, dz, dm, None, None, None, None, None
 
 
-def gravity(x, y, z, m, h, n_ll: int = 12, theta: float = 0.7, precision: str = "fp64"):
+def gravity(x, y, z, m, h, n_ll: int = 12, theta: float = 0.7, precision: str = "fp64",
+            pure_mac: bool = False):
     """Differentiable accelerations (see RCBGravity)."""
-    return RCBGravity.apply(x, y, z, m, h, n_ll, theta, precision)
+    return RCBGravity.apply(x, y, z, m, h, n_ll, theta, precision, pure_mac)

@@ -14,6 +14,15 @@
 //   else H_B^2 < theta^2 |com_A - com_B|^2 -> far
 //   else leaf -> near (no candidate); else open
 // reach is evaluated squared with the radius sum padded by (1 + 2^-32).
+//
+// Pure-MAC mode (the variant of Sec. 2.5: reachability does not override
+// the MAC) runs two walks in one traversal. An entry carries two leaf
+// masks: gravity (the MAC walk: accepted -> far unless B contains the leaf,
+// else leaf -> near, internal -> open) and neighbour (the reachability
+// walk: reachable -> leaf is a candidate, internal -> open; else dropped).
+// A near entry then may be a candidate without being in a leaf's gravity
+// near field (candidate bit set, near bit clear).
+//
 // Output per group: a near list of (label, near mask, candidate mask) and a
 // far list of (label, far mask) -- the union of the group's per-leaf lists.
 // Near lists are sorted by label, so each leaf's candidates (and neighbour
@@ -58,6 +67,8 @@ __device__ __forceinline__ uint64_t byte_any(uint64_t x) {
     return x & 0x0101010101010101ull;
 }
 
+// stack entry: label | gravity mask << 32 | neighbour mask << 40
+template <bool PURE>
 __global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
     __shared__ uint64_t stk_all[kWaves][kGStack];
     uint64_t *stk = stk_all[threadIdx.x / kWave];
@@ -83,12 +94,13 @@ __global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
         }
         return;
     }
+    const uint64_t root_masks = ((uint64_t)live_mask << 32) | (PURE ? (uint64_t)live_mask << 40 : 0ull);
     if (lane == 0) {
         if (w.k == 0) {
-            stk[0] = 1ull | ((uint64_t)live_mask << 32);
+            stk[0] = 1ull | root_masks;
         } else {
-            stk[0] = 3ull | ((uint64_t)live_mask << 32);
-            stk[1] = 2ull | ((uint64_t)live_mask << 32);
+            stk[0] = 3ull | root_masks;
+            stk[1] = 2ull | root_masks;
         }
     }
     int sp = w.k == 0 ? 1 : 2;
@@ -101,27 +113,40 @@ __global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
         // lanes past the popped entries read the top entry again and are masked
         const uint64_t ent = stk[sp + (act ? slot : 0)];
         const int32_t node = (int32_t)(ent & 0xffffffffull);
-        const uint32_t emask = (uint32_t)(ent >> 32);
-        const bool mine = act && ((emask >> li) & 1u);
+        const bool gbit = act && ((ent >> (32 + li)) & 1ull);
         const double4 gb = w.rec[2 * (int64_t)node];
         const double4 cb = w.rec[2 * (int64_t)node + 1];
-        const bool live = mine && gb.w >= 0.0;
+        const bool nonempty = gb.w >= 0.0;
         const double dg2 = dist2(ga.x, ga.y, ga.z, gb.x, gb.y, gb.z);
         const double rs = (hA + gb.w) * kReachPad;
         const double R2 = dist2(ca.x, ca.y, ca.z, cb.x, cb.y, cb.z);
         // the per-lane tests as wave masks; the decisions are bit logic on them
-        const uint64_t B_live = ballot(live);
+        const uint64_t B_g = ballot(gbit && nonempty);          // gravity walk reaches B
         const uint64_t B_leaf = ballot(node >= nleaf);
         const uint64_t B_reach = ballot(dg2 < rs * rs);
         const uint64_t B_mac = ballot(cb.w * cb.w < w.theta2 * R2);
-        const uint64_t refine = B_reach | ~B_mac;   // reachable or MAC failed
-        const uint64_t bo = B_live & ~B_leaf & refine;   // open
-        const uint64_t bn = B_live & B_leaf & refine;    // near leaf
-        const uint64_t bc = bn & B_reach;                // near leaf, neighbour candidate
-        const uint64_t bf = B_live & ~B_reach & B_mac;   // far
+        uint64_t acc, B_n;
+        if constexpr (PURE) {
+            // B contains leaf A iff A's ancestor on B's level is B
+            const int lvl = 31 - __builtin_clz((uint32_t)node);
+            const uint64_t B_anc = ballot((A >> (w.k - lvl)) == (int64_t)node);
+            acc = B_g & B_mac & ~B_anc;
+            B_n = ballot(act && ((ent >> (40 + li)) & 1ull) && nonempty);
+        } else {
+            acc = B_g & B_mac & ~B_reach;
+            B_n = B_g;
+        }
+        const uint64_t bf = acc;                                  // far
+        const uint64_t grav = B_g & ~acc;                         // near or open for gravity
+        const uint64_t bc = B_n & B_leaf & B_reach;               // neighbour candidate
+        const uint64_t bn = (grav & B_leaf) | bc;                 // near entry
+        const uint64_t bog = grav & ~B_leaf;                      // open for gravity
+        const uint64_t bon = PURE ? (B_n & ~B_leaf & B_reach) : 0ull;   // open for neighbours
+        const uint64_t bo = bog | bon;
         // one lane per entry (li == 0) turns the 8 decision bits into list entries
-        const uint32_t om = (uint32_t)((bo >> (8 * slot)) & 0xffull);
-        const uint32_t nm = (uint32_t)((bn >> (8 * slot)) & 0xffull);
+        const uint32_t ogm = (uint32_t)((bog >> (8 * slot)) & 0xffull);
+        const uint32_t onm = (uint32_t)((bon >> (8 * slot)) & 0xffull);
+        const uint32_t nm = (uint32_t)(((grav & B_leaf) >> (8 * slot)) & 0xffull);
         const uint32_t cm = (uint32_t)((bc >> (8 * slot)) & 0xffull);
         const uint32_t fm = (uint32_t)((bf >> (8 * slot)) & 0xffull);
         const bool lead = act && li == 0;
@@ -132,14 +157,15 @@ __global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
             break;
         }
         __builtin_amdgcn_wave_barrier();
-        if (lead && om != 0) {
+        if (lead && (ogm | onm) != 0) {
             const int r = rank_below(b_open);
-            stk[sp + 2 * r] = (uint64_t)(2 * node) | ((uint64_t)om << 32);
-            stk[sp + 2 * r + 1] = (uint64_t)(2 * node + 1) | ((uint64_t)om << 32);
+            const uint64_t masks = ((uint64_t)ogm << 32) | ((uint64_t)onm << 40);
+            stk[sp + 2 * r] = (uint64_t)(2 * node) | masks;
+            stk[sp + 2 * r + 1] = (uint64_t)(2 * node + 1) | masks;
         }
         __builtin_amdgcn_wave_barrier();
         sp += 2 * no;
-        if (lead && nm != 0) {
+        if (lead && (nm | cm) != 0) {
             const int64_t i = nn + rank_below(b_near);
             if (i < w.near_cap)
                 w.near_list[nbase + i] =
@@ -259,7 +285,8 @@ __global__ __launch_bounds__(1024) void k_sort_long(const int32_t *__restrict__ 
 }
 
 // Per-leaf lists from the group lists (inspection only): a leaf keeps the
-// entries whose mask has its bit; near entries become label | candidate << 31.
+// entries whose near or candidate mask has its bit; near entries become
+// label | candidate << 31 | (candidate only, not in the near field) << 30.
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_expand(int64_t nleaf, int gk,
                                                    const int64_t *__restrict__ gnear_beg,
@@ -283,12 +310,13 @@ __global__ __launch_bounds__(kBlock) void k_expand(int64_t nleaf, int gk,
     for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
         const int64_t e = e0 + lane;
         const uint64_t ent = e < n1 ? gnear[e] : 0ull;
-        const bool has = (ent >> (32 + bit)) & 1ull;
+        const uint32_t nb = (uint32_t)((ent >> (32 + bit)) & 1ull);
+        const uint32_t cand = (uint32_t)((ent >> (40 + bit)) & 1ull);
+        const bool has = (nb | cand) != 0;
         const uint64_t bl = ballot(has);
-        if (FILL && has) {
-            const uint32_t cand = (uint32_t)((ent >> (40 + bit)) & 1ull);
-            nlist[noff[li] + nn + rank_below(bl)] = (int32_t)(((uint32_t)ent & kLabelMask) | (cand << 31));
-        }
+        if (FILL && has)
+            nlist[noff[li] + nn + rank_below(bl)] =
+                (int32_t)(((uint32_t)ent & kLabelMask) | (cand << 31) | ((nb ^ 1u) << 30));
         nn += __popcll(bl);
     }
     const int64_t f0 = gfar_beg[gi], f1 = gfar_end[gi];
@@ -337,7 +365,9 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
                nullptr, nullptr, cn, cf, nslab, fslab, t->dflag};
     const unsigned grid = (unsigned)((NG + kWaves - 1) / kWaves);
     RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 4, s));
-    k_walk_group<<<grid, kBlock, 0, s>>>(w);
+    const bool pure = t->p.pure_mac != 0;
+    if (pure) k_walk_group<true><<<grid, kBlock, 0, s>>>(w);
+    else k_walk_group<false><<<grid, kBlock, 0, s>>>(w);
     RCB_LAUNCH_CHECK("k_walk_group<slab>");
     int32_t flags[4] = {0, 0, 0, 0};
     RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
@@ -385,7 +415,8 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
         w.near_cap = w.far_cap = INT64_MAX;
         w.near_list = t->gnear;
         w.far_list = t->gfar;
-        k_walk_group<<<grid, kBlock, 0, s>>>(w);
+        if (pure) k_walk_group<true><<<grid, kBlock, 0, s>>>(w);
+        else k_walk_group<false><<<grid, kBlock, 0, s>>>(w);
         RCB_LAUNCH_CHECK("k_walk_group<exact>");
     }
     int32_t *long_q = nullptr;

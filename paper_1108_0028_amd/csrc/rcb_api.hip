@@ -63,7 +63,7 @@ void rcb_params_default(rcb_params *p) {
     p->precision = RCB_FP64;
     p->theta = 0.7;
     p->validate = 0;
-    p->reserved = 0;
+    p->pure_mac = 0;
 }
 
 const char *rcb_last_error(void) { return g_last_error.c_str(); }
@@ -97,8 +97,8 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
         set_error("rcb_build: unknown precision");
         return RCB_EINVAL;
     }
-    if (p->reserved != 0) {
-        set_error("rcb_build: reserved field must be 0");
+    if (p->pure_mac != 0 && p->pure_mac != 1) {
+        set_error("rcb_build: pure_mac must be 0 or 1");
         return RCB_EINVAL;
     }
     int k = 0;

@@ -47,7 +47,7 @@ def test_params_default_is_the_paper_default():
 
 
 @pytest.mark.parametrize("case", ["null_out", "null_x", "n_zero", "n_neg", "n_huge", "nll_zero",
-                                  "theta_neg", "theta_nan", "precision", "reserved"])
+                                  "theta_neg", "theta_nan", "precision", "pure_mac"])
 def test_build_rejects_bad_arguments_on_host(case):
     from paper_1108_0028_amd._lib import RcbParams
     L = _lib()
@@ -76,8 +76,8 @@ def test_build_rejects_bad_arguments_on_host(case):
         p.theta = float("nan")
     elif case == "precision":
         p.precision = 7
-    elif case == "reserved":
-        p.reserved = 1
+    elif case == "pure_mac":
+        p.pure_mac = 2
     st = L.rcb_build(*ptrs, n, C.byref(p), None, outp)
     assert st == 1   # RCB_EINVAL
     assert L.rcb_last_error().decode().startswith("rcb_build")

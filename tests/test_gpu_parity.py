@@ -33,13 +33,13 @@ def _torch():
     return torch
 
 
-def _gpu_tree(c, n_ll, theta, precision="fp64"):
+def _gpu_tree(c, n_ll, theta, precision="fp64", pure_mac=False):
     torch = _torch()
     from paper_1108_0028_amd import Tree
     dev = torch.device("cuda:0")
     cv = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
     return Tree(cv(c.x), cv(c.y), cv(c.z), cv(c.m), cv(c.h), n_ll=n_ll, theta=theta,
-                precision=precision)
+                precision=precision, pure_mac=pure_mac)
 
 
 def _np(t):
