@@ -48,6 +48,8 @@ def _args():
     ap.add_argument("--theta", type=float, default=0.7)
     ap.add_argument("--n-ll", type=int, default=12)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--pure-mac", action="store_true",
+                    help="gravity lists from the geometric MAC alone (reachable cells may be accepted)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-leaves", type=int, default=2048)
     ap.add_argument("--calib-copy", action="store_true",
@@ -79,7 +81,7 @@ def main():
         bracket each phase on the stream the library launches on."""
         rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
         rec(0)
-        t = Tree(*arrs, n_ll=a.n_ll, theta=a.theta, precision=prec)
+        t = Tree(*arrs, n_ll=a.n_ll, theta=a.theta, precision=prec, pure_mac=a.pure_mac)
         rec(1)
         t.walk()
         rec(2)
@@ -114,9 +116,11 @@ def main():
     grav_ms = phases["gravity"]   # one launch of k_gravity per step
 
     # work counts of this tree for the roofline (outside the timed region)
-    t = Tree(*arrs, n_ll=a.n_ll, theta=a.theta, precision=a.precision)
+    t = Tree(*arrs, n_ll=a.n_ll, theta=a.theta, precision=a.precision, pure_mac=a.pure_mac)
     cnt = t.export("count").to(torch.int64)
-    near = t.export("near").to(torch.int64) & 0x7FFFFFFF
+    near = t.export("near").to(torch.int64)
+    in_field = (near & (1 << 30)) == 0     # entries of the gravity near field
+    near = near & 0x3FFFFFFF
     noff = t.export("near_off")
     foff = t.export("far_off")
     inf = t.info()              # list totals are known once the lists exist
@@ -126,7 +130,7 @@ def main():
     F_A = foff[1:] - foff[:-1]
     n_A = cnt[nleaf:2 * nleaf]
     P_A = torch.zeros(nleaf, dtype=torch.int64, device=dev).index_add_(
-        0, torch.repeat_interleave(leaf, L_A), cnt[near])
+        0, torch.repeat_interleave(leaf, L_A), cnt[near] * in_field)
     pairs = int((P_A * n_A).sum())
     t.destroy()
     far_total = inf["far_total"]
@@ -179,7 +183,8 @@ def main():
         "data": "synthetic (seeded Plummer + uniform background)",
         "config": {"workload": "plummer_background N=4194304: 90% Plummer (b=1, r<=20) + 10% uniform "
                                "sphere R=10.357, equal masses, analytic h for ~50 neighbours",
-                   "n": n, "n_ll": a.n_ll, "theta": a.theta, "precision": a.precision},
+                   "n": n, "n_ll": a.n_ll, "theta": a.theta, "precision": a.precision,
+                   "walk": "pure MAC" if a.pure_mac else "reachability overrides MAC (paper)"},
         "phases_ms": phases,
         "other_form": {"precision": other, "value": n / sec_o, "ms_per_step": sec_o * 1e3},
         "mixed_vs_fp64_error": err,
@@ -229,7 +234,7 @@ def cpu_baseline(cloud, a):
     t1 = time.perf_counter()
     rng = np.random.default_rng(0)
     leaves = np.sort(rng.choice(ot.n_leaves, min(a.cpu_leaves, ot.n_leaves), replace=False)) + ot.n_leaves
-    ot.walk(a.theta, leaves)
+    ot.walk(a.theta, leaves, pure_mac=a.pure_mac)
     t2 = time.perf_counter()
     off, ids, valid = ot.neighbours()
     t3 = time.perf_counter()
