@@ -39,7 +39,7 @@ def lib():
         i64p = C.POINTER(C.c_int64)
         i32p = C.POINTER(C.c_int32)
         L.orc_build.restype = P
-        L.orc_build.argtypes = [C.c_int64, dp, dp, dp, dp, dp, C.c_int]
+        L.orc_build.argtypes = [C.c_int64, dp, dp, dp, dp, dp, C.c_int, C.c_int]
         L.orc_free.argtypes = [P]
         L.orc_refresh.argtypes = [P, dp, dp, dp, dp, dp]
         L.orc_k.argtypes = [P]
@@ -122,13 +122,15 @@ def far_coeffs(M: float, q6, R, with_t4: bool = False):
 class OracleTree:
     """The oracle's RCB tree for one particle set (FP64, CPU)."""
 
-    def __init__(self, x, y, z, m, h, n_ll: int):
+    def __init__(self, x, y, z, m, h, n_ll: int, split: str = "mass"):
+        """split: "mass" (centre of mass, the paper's choice) or "number"
+        (centre of number, Sec. 2.1 "Load balancing")."""
         L = lib()
         self._keep = [_d(a) for a in (x, y, z, m, h)]
         ps = [k[1] for k in self._keep]
         self.n = int(self._keep[0][0].shape[0])
         self.n_ll = n_ll
-        self.ptr = L.orc_build(self.n, *ps, n_ll)
+        self.ptr = L.orc_build(self.n, *ps, n_ll, {"mass": 0, "number": 1}[split])
         if not self.ptr:
             raise ValueError("oracle build rejected its arguments")
         self.k = int(L.orc_k(self.ptr))

@@ -91,6 +91,7 @@ typedef struct otree {
     double *M, *com, *Q;           /* Q: xx xy xz yy yz zz per label */
     double *hint, *hnode;
     double theta;
+    int split;                     /* 0: centre of mass, 1: centre of number */
     int pure_mac;                  /* walk mode of the last orc_walk */
     leaf_lists *lists;             /* one per leaf, index label - 2^k */
 } otree;
@@ -133,8 +134,24 @@ static void node_mass_com(const otree *t, int64_t lab, double *M, double com[3])
     free(ids);
 }
 
-/* Split one node through its centre of mass, perpendicular to its longest */
-/* side (Sec. 2.1 "Load balancing", "Particle sorting").                    */
+/* Centre of number of a node along one axis (Sec. 2.1 "Load balancing":   */
+/* the centre of mass with every weight replaced by 1), i.e. the mean        */
+/* coordinate, summed canonically in ascending original index.              */
+static double node_mean(const otree *t, int64_t lab, const double *xa)
+{
+    int64_t c = t->count[lab];
+    int64_t *ids = node_members_sorted(t, lab);
+    double *v = (double *)malloc((size_t)(c > 0 ? c : 1) * sizeof(double));
+    for (int64_t i = 0; i < c; ++i) v[i] = xa[ids[i]];
+    double mean = orc_psum(v, c) / (double)c;
+    free(v);
+    free(ids);
+    return mean;
+}
+
+/* Split one node perpendicular to its longest side through its centre of  */
+/* mass, or its centre of number (Sec. 2.1 "Load balancing", "Particle      */
+/* sorting").                                                               */
 static void split_node(otree *t, int64_t lab)
 {
     int64_t s = t->first[lab], c = t->count[lab];
@@ -161,7 +178,7 @@ static void split_node(otree *t, int64_t lab)
     }
     t->axis[lab] = ax;
     const double *xa = ax == 0 ? t->x : (ax == 1 ? t->y : t->z);
-    double plane = com[ax];
+    double plane = t->split == 1 ? node_mean(t, lab, xa) : com[ax];
     int64_t *tmp = (int64_t *)malloc((size_t)c * sizeof(int64_t));
     int64_t nl = 0;
     for (int64_t i = 0; i < c; ++i)
@@ -290,13 +307,15 @@ int orc_depth_for(int64_t n, int n_ll)
 
 /* Top-down build (Sec. 2.1): root box = bounding box of all particles;   */
 /* levels 0 .. k-1 are split in turn; then the node moments.             */
+/* split: 0 = through the centre of mass, 1 = through the centre of number. */
 otree *orc_build(int64_t n, const double *x, const double *y, const double *z,
-                 const double *m, const double *h, int n_ll)
+                 const double *m, const double *h, int n_ll, int split)
 {
-    if (n < 1 || n_ll < 1) return NULL;
+    if (n < 1 || n_ll < 1 || split < 0 || split > 1) return NULL;
     otree *t = (otree *)calloc(1, sizeof(otree));
     t->n = n;
     t->n_ll = n_ll;
+    t->split = split;
     t->k = orc_depth_for(n, n_ll);
     t->nlab = (int64_t)2 << t->k;
     t->x = dup(x, n); t->y = dup(y, n); t->z = dup(z, n); t->m = dup(m, n); t->h = dup(h, n);

@@ -212,11 +212,12 @@ def test_taylor_error_falls_as_third_power():
 # --------------------------------------------------------------------------
 # tree build, Sec. 2.1
 # --------------------------------------------------------------------------
+@pytest.mark.parametrize("split", ["mass", "number"])
 @pytest.mark.parametrize("n,nll,kind", [(1, 12, "uniform"), (5, 12, "uniform"), (300, 4, "clustered"),
                                         (1001, 8, "plummer"), (777, 3, "uniform")])
-def test_tree_rules(n, nll, kind):
+def test_tree_rules(n, nll, kind, split):
     c = W.small_random(n, 10 + n, kind)
-    t = O.OracleTree(*c.arrays(), n_ll=nll)
+    t = O.OracleTree(*c.arrays(), n_ll=nll, split=split)
     topo, nd = t.topology(), t.nodes()
     perm, first, count, axis = topo["perm"], topo["first"], topo["count"], topo["axis"]
     assert sorted(perm) == list(range(n))
@@ -235,7 +236,10 @@ def test_tree_rules(n, nll, kind):
         ax = int(np.argmax(side))                       # first maximum
         assert axis[lab] == ax
         ids = np.sort(perm[first[lab]:first[lab] + count[lab]])
-        com = np.array([math.fsum(c.m[ids] * P[ids, d]) / math.fsum(c.m[ids]) for d in range(3)])
+        if split == "mass":
+            com = np.array([math.fsum(c.m[ids] * P[ids, d]) / math.fsum(c.m[ids]) for d in range(3)])
+        else:                                            # centre of number: weights 1
+            com = np.array([math.fsum(P[ids, d]) / len(ids) for d in range(3)])
         plane = nd["hi"][L][ax]
         assert plane == nd["lo"][R][ax]
         assert abs(plane - com[ax]) <= 1e-14 * (1 + abs(com[ax]))
@@ -251,6 +255,22 @@ def test_tree_rules(n, nll, kind):
             d = np.linalg.norm(P[ids] - g, axis=1)
             assert nd["hint"][lab] == pytest.approx(d.max(), rel=1e-15)
             assert nd["hnode"][lab] == pytest.approx((d + 2 * c.h[ids]).max(), rel=1e-15)
+
+
+def test_centre_of_number_split_equals_mass_split_for_equal_power_of_two_masses():
+    # m = 2^-j scales every product m x exactly, so both planes are the same number
+    c = W.small_random(1500, 12, "clustered")
+    c.m[:] = 2.0 ** -11
+    a = O.OracleTree(*c.arrays(), n_ll=5, split="mass")
+    b = O.OracleTree(*c.arrays(), n_ll=5, split="number")
+    np.testing.assert_array_equal(a.topology()["perm"], b.topology()["perm"])
+    for key in ("lo", "hi", "com", "M", "Q", "hint", "hnode"):
+        np.testing.assert_array_equal(a.nodes()[key], b.nodes()[key])
+    # with unequal masses the planes differ and so do the trees
+    c2 = W.small_random(1500, 12, "clustered")
+    a2 = O.OracleTree(*c2.arrays(), n_ll=5, split="mass")
+    b2 = O.OracleTree(*c2.arrays(), n_ll=5, split="number")
+    assert not np.array_equal(a2.nodes()["hi"], b2.nodes()["hi"])
 
 
 def test_quadrupole_eq1_traceless_and_eq2_equals_direct():

@@ -160,6 +160,23 @@ def clumpy_cube(n: int = 100_000_000, seed: int = SEED_BASE + 4,
     return Cloud("clumpy_cube", x, y, z, m, _h_from_density(dens))
 
 
+def sobol_sphere(n: int = 500_000, n_neigh: int = 105, seed: int = SEED_BASE + 6) -> Cloud:
+    """Quasi-random sphere (Sec. 3: a Sobol sequence filling a sphere): a
+    scrambled 3-D Sobol sequence on [-1, 1]^3, points with |r| < 1 kept in
+    sequence order until n are found; equal masses, h for n_neigh
+    neighbours at the mean density (Table 1 uses 105)."""
+    from scipy.stats import qmc
+    sob = qmc.Sobol(d=3, scramble=True, seed=seed)
+    pts = np.empty((0, 3))
+    while pts.shape[0] < n:
+        block = 2.0 * sob.random(1 << max(10, int(math.ceil(math.log2(2 * n))))) - 1.0
+        pts = np.concatenate([pts, block[(block * block).sum(1) < 1.0]])
+    pts = pts[:n]
+    dens = np.full(n, n / (4.0 / 3.0 * math.pi))
+    return Cloud("sobol_sphere", np.ascontiguousarray(pts[:, 0]), np.ascontiguousarray(pts[:, 1]),
+                 np.ascontiguousarray(pts[:, 2]), np.full(n, 1.0 / n), _h_from_density(dens, n_neigh))
+
+
 def plummer_subset(n_sub: int = 4096, seed: int = SEED_BASE + 5,
                    parent_n: int = 1 << 20) -> Cloud:
     """Random subset of the Plummer cloud, m = 1/n_sub, h from exact kNN."""
