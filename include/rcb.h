@@ -56,6 +56,11 @@ typedef enum {
     RCB_MIXED = 1       /* FP32 leaf-relative interactions; FP64 moments and Taylor shift */
 } rcb_precision;
 
+typedef enum {
+    RCB_SPLIT_MASS = 0,     /* split planes through the centre of mass (the paper's CMS) */
+    RCB_SPLIT_NUMBER = 1    /* through the centre of number: unit weights (Sec. 2.1 "Load balancing") */
+} rcb_split;
+
 typedef struct {
     int32_t n_ll;       /* average particles per lowest-level cell, Sec. 3.2.1 (paper: 12) */
     int32_t precision;  /* rcb_precision */
@@ -67,15 +72,18 @@ typedef struct {
                            accepted when the MAC holds unless it contains the sink
                            cell; neighbour candidates are then the leaves reached
                            through reachable cells only */
+    int32_t split;      /* rcb_split: where a cell is cut; moments always use the masses */
 } rcb_params;
 
-/* Paper defaults: n_ll = 12, theta = 0.7, FP64, validate = 0, pure_mac = 0. */
+/* Paper defaults: n_ll = 12, theta = 0.7, FP64, validate = 0, pure_mac = 0,
+   split = RCB_SPLIT_MASS. */
 void rcb_params_default(rcb_params *p);
 
 /*
  * Build the tree top-down (Sec. 2.1): the root cell is the particles'
  * bounding box; each cell is split perpendicular to its longest side through
- * its centre of mass, particles with coordinate < plane going to the lower
+ * its centre of mass (or, with split = RCB_SPLIT_NUMBER, its centre of number:
+ * the mean coordinate), particles with coordinate < plane going to the lower
  * child 2n (stable), the rest to 2n+1, until level k = min{k : n <= n_ll 2^k}.
  * Every node gets its mass, centre of mass (canonical pairwise sums over its
  * particles in ascending input index), traceless quadrupole (Eq. 1 at the

@@ -12,6 +12,11 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 
+__global__ void k_fill_f64(double *v, int64_t n, double value) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) v[i] = value;
+}
+
 rcb_status hip_fail(hipError_t e, const char *what) {
     set_error(std::string(what) + ": " + hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? RCB_ENOMEM : RCB_EHIP;
@@ -64,6 +69,7 @@ void rcb_params_default(rcb_params *p) {
     p->theta = 0.7;
     p->validate = 0;
     p->pure_mac = 0;
+    p->split = RCB_SPLIT_MASS;
 }
 
 const char *rcb_last_error(void) { return g_last_error.c_str(); }
@@ -101,6 +107,10 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
         set_error("rcb_build: pure_mac must be 0 or 1");
         return RCB_EINVAL;
     }
+    if (p->split != RCB_SPLIT_MASS && p->split != RCB_SPLIT_NUMBER) {
+        set_error("rcb_build: unknown split");
+        return RCB_EINVAL;
+    }
     int k = 0;
     while ((int64_t)p->n_ll * ((int64_t)1 << k) < n) ++k;
     if (k > 29) {
@@ -117,7 +127,25 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
     t->p = *p;
     t->stream = (hipStream_t)stream;
     if (hipGetDevice(&t->device) != hipSuccess) t->device = 0;
-    rcb_status st = build_tree(t, x, y, z, m, h, t->stream);
+    rcb_status st;
+    if (p->split == RCB_SPLIT_NUMBER) {
+        // planes through the centre of number: build with unit weights (the
+        // canonical sums then give sum(x) / count exactly), then recompute
+        // every moment with the masses on the fixed tree
+        std::vector<void *> tmp;
+        double *ones = (double *)dalloc(t, sizeof(double) * (size_t)n, t->stream, tmp);
+        if (!ones) {
+            st = RCB_ENOMEM;
+        } else {
+            k_fill_f64<<<(unsigned)((n + 255) / 256), 256, 0, t->stream>>>(ones, n, 1.0);
+            st = hipGetLastError() == hipSuccess ? RCB_OK : RCB_EHIP;
+            if (st == RCB_OK) st = build_tree(t, x, y, z, ones, h, t->stream);
+            if (st == RCB_OK) st = refresh_tree(t, x, y, z, m, h, t->stream);
+            hipFreeAsync(ones, t->stream);
+        }
+    } else {
+        st = build_tree(t, x, y, z, m, h, t->stream);
+    }
     if (st != RCB_OK) {
         std::string msg = g_last_error;
         free_all(t);

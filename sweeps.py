@@ -1,0 +1,149 @@
+"""Paper-shaped sweeps of the RCB tree on one GPU (Sec. 3).
+
+* ``table1``: the N_ll sweep of Table 1 -- depth L, fraction of particles with
+  a relative force error below 1%, and the time of the build (TB), the walk,
+  the neighbour search (N) and the gravity (G, near and far field fused in one
+  kernel), with the near-pair and far-pair counts that split G.
+* ``accuracy``: the cumulative distribution of relative errors
+  eps_i = |da_i| / |a_i| for theta from 0.4 to 1.0 (Fig. accuracy).
+
+Workload: a quasi-random Sobol sphere (500,000 particles, smoothing lengths
+for ~105 neighbours, as in Table 1). The reference accelerations are the FP64
+tree at theta = 0, which is the direct kernel-smoothed sum (no cell is
+accepted, so every pair is summed directly; Sec. 2.4.1). Prints a markdown
+table and one JSON line per row.
+
+    python sweeps.py table1 [--n 500000] [--precision fp64]
+    python sweeps.py accuracy [--pure-mac]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["table1", "accuracy"])
+    ap.add_argument("--n", type=int, default=500_000)
+    ap.add_argument("--neighbours", type=int, default=105)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--theta", type=float, default=0.7, help="theta of the table1 sweep")
+    ap.add_argument("--n-ll", type=int, default=12, help="N_ll of the accuracy sweep")
+    ap.add_argument("--nll-list", default="1,3,6,12,24,48,64,128")
+    ap.add_argument("--theta-list", default="0.4,0.5,0.6,0.7,0.8,0.9,1.0")
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--pure-mac", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    a = _args()
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1108_0028_amd import Tree
+
+    assert torch.cuda.is_available(), "sweeps.py needs a GPU"
+    dev = torch.device("cuda:0")
+    cloud = W.sobol_sphere(a.n, a.neighbours)
+    arrs = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in cloud.arrays()]
+
+    def run(n_ll, theta, prec, ev=None):
+        rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
+        rec(0)
+        t = Tree(*arrs, n_ll=n_ll, theta=theta, precision=prec, pure_mac=a.pure_mac)
+        rec(1)
+        t.walk()
+        rec(2)
+        off, _ = t.neighbours()
+        rec(3)
+        acc = t.gravity()
+        rec(4)
+        return t, off, acc
+
+    def timed(n_ll, theta, prec):
+        run(n_ll, theta, prec)[0].destroy()                      # warm-up
+        rows = []
+        for _ in range(a.reps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            t, off, acc = run(n_ll, theta, prec, ev)
+            torch.cuda.synchronize()
+            rows.append([ev[j].elapsed_time(ev[j + 1]) for j in range(4)])
+            t.destroy()
+        med = np.median(np.array(rows), 0)
+        return dict(zip(("TB", "walk", "N", "G"), (float(v) for v in med)))
+
+    def pairs(t):
+        cnt = t.export("count").to(torch.int64)
+        near = t.export("near").to(torch.int64)
+        in_field = (near & (1 << 30)) == 0
+        near = near & 0x3FFFFFFF
+        noff, foff = t.export("near_off"), t.export("far_off")
+        nleaf = 1 << t.info()["k"]
+        L_A = noff[1:] - noff[:-1]
+        P_A = torch.zeros(nleaf, dtype=torch.int64, device=dev).index_add_(
+            0, torch.repeat_interleave(torch.arange(nleaf, device=dev), L_A), cnt[near] * in_field)
+        n_A = cnt[nleaf:2 * nleaf]
+        return int((P_A * n_A).sum()), int(foff[-1])
+
+    def errors(acc, ref):
+        am = torch.stack([v.double() for v in acc], 1)
+        da = (am - ref).norm(dim=1)
+        na = ref.norm(dim=1)
+        eps = (da / na).cpu().numpy()
+        return {"mean": float(eps.mean()), "p99": float(np.quantile(eps, 0.99)),
+                "max": float(eps.max()),
+                "P<1e-4": float((eps < 1e-4).mean()), "P<1e-3": float((eps < 1e-3).mean()),
+                "P<2e-3": float((eps < 2e-3).mean()), "P<1e-2": float((eps < 1e-2).mean())}
+
+    t0 = time.perf_counter()
+    rt, _, racc = run(12, 0.0, "fp64")
+    ref = torch.stack(racc, 1)
+    torch.cuda.synchronize()
+    ref_s = time.perf_counter() - t0
+    rt.destroy()
+    head = {"workload": f"sobol_sphere N={a.n}, ~{a.neighbours} neighbours", "precision": a.precision,
+            "walk": "pure MAC" if a.pure_mac else "reachability overrides MAC",
+            "reference": f"FP64 tree at theta = 0 (direct sum), {ref_s:.1f} s"}
+    print(json.dumps(head), flush=True)
+
+    if a.what == "table1":
+        print(f"\n| N_ll | L | P<1% | mean eps | TB ms | walk ms | N ms | G ms | near pairs | far pairs | "
+              f"neighbours/particle |\n|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|", flush=True)
+        for nll in [int(v) for v in a.nll_list.split(",")]:
+            ph = timed(nll, a.theta, a.precision)
+            t, off, acc = run(nll, a.theta, a.precision)
+            e = errors(acc, ref)
+            npair, nfar = pairs(t)
+            k = t.info()["k"]
+            nb = float(off[-1]) / a.n
+            t.destroy()
+            row = {"n_ll": nll, "L": k, **ph, "near_pairs": npair, "far_pairs": nfar,
+                   "neighbours_per_particle": nb, **e}
+            print(f"| {nll} | {k} | {e['P<1e-2']:.4f} | {e['mean']:.2e} | {ph['TB']:.2f} | {ph['walk']:.2f} | "
+                  f"{ph['N']:.2f} | {ph['G']:.2f} | {npair:.3e} | {nfar:.3e} | {nb:.1f} |", flush=True)
+            print(json.dumps(row), flush=True)
+    else:
+        print(f"\n| theta | P<1e-4 | P<1e-3 | P<2e-3 | P<1e-2 | mean | p99 | max | G ms |\n"
+              f"|---:|---:|---:|---:|---:|---:|---:|---:|---:|", flush=True)
+        for th in [float(v) for v in a.theta_list.split(",")]:
+            ph = timed(a.n_ll, th, a.precision)
+            t, _, acc = run(a.n_ll, th, a.precision)
+            e = errors(acc, ref)
+            t.destroy()
+            print(f"| {th} | {e['P<1e-4']:.4f} | {e['P<1e-3']:.4f} | {e['P<2e-3']:.4f} | {e['P<1e-2']:.4f} | "
+                  f"{e['mean']:.2e} | {e['p99']:.2e} | {e['max']:.2e} | {ph['G']:.2f} |", flush=True)
+            print(json.dumps({"theta": th, "n_ll": a.n_ll, **ph, **e}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
