@@ -74,13 +74,19 @@ RCB_HD constexpr int hidx(int i, int l, int m) {
     return a == 0 ? (b == 0 ? c : (b == 1 ? 2 + c : 5)) : (a == 1 ? (b == 1 ? 5 + c : 8) : 9);
 }
 
-// f (0..2), J (3..8, jidx), H (9..18, hidx) of one source, accumulated.
-// With g = b2 x + c1 q, u = e3 x / 3 + c2 q and Qc = c1 Q the closed forms
-// above regroup as
+// One source's f, J, H added into a reduced accumulator of 19 doubles. With
+// g = b2 x + c1 q, u = e3 x / 3 + c2 q and Qc = c1 Q the closed forms above
+// regroup as
 //   f_i = a1 x_i + c0 q_i
 //   J_il = g_i x_l + c1 q_l x_i + c0 Q_il + a1 d_il
 //   H_ilm = sum over the three choices of the single index j (the other
 //           two, k and n): u_j x_k x_n + Qc_kn x_j + d_kn g_j
+// The field of Eq. 5 is harmonic, so J and H are traceless in every index
+// pair; only 5 components of J and 7 of H are accumulated, and the
+// Kronecker-delta terms are summed once (sum of a1, sum of g) instead of
+// into every diagonal component. Layout: f (0..2); J xx xy xz yy yz
+// without a1 (3..7); H xxx xxy xxz xyy xyz yyy yyz without the g terms
+// (8..14); sum g (15..17); sum a1 (18). m2l_finish expands it.
 RCB_HD void m2l_accumulate(double x, double y, double z, double M, const double qq[6], double (&c)[19]) {
     const double X[3] = {x, y, z};
     const double r2 = (x * x + y * y) + z * z;
@@ -115,28 +121,49 @@ RCB_HD void m2l_accumulate(double x, double y, double z, double M, const double 
         c[i] += a1 * X[i];
         c[i] += c0 * q[i];
     }
-    for (int i = 0; i < 3; ++i)
-        for (int l = i; l < 3; ++l) {
+    for (int i = 0; i < 2; ++i)
+        for (int l = i; l < 3; ++l) {            // xx xy xz yy yz
             double &v = c[3 + jidx(i, l)];
             v += g[i] * X[l];
             v += cq[l] * X[i];
             v += c0 * qq[jidx(i, l)];
-            if (i == l) v += a1;
         }
-    for (int i = 0; i < 3; ++i)
-        for (int l = i; l < 3; ++l)
-            for (int m = l; m < 3; ++m) {
-                double &v = c[9 + hidx(i, l, m)];
-                v += u[i] * xx[jidx(l, m)];
-                v += u[l] * xx[jidx(i, m)];
-                v += u[m] * xx[jidx(i, l)];
-                v += Qc[jidx(l, m)] * X[i];
-                v += Qc[jidx(i, m)] * X[l];
-                v += Qc[jidx(i, l)] * X[m];
-                if (l == m) v += g[i];
-                if (i == m) v += g[l];
-                if (i == l) v += g[m];
-            }
+    constexpr int H7[7][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 1, 1}, {0, 1, 2}, {1, 1, 1}, {1, 1, 2}};
+    for (int t = 0; t < 7; ++t) {
+        const int i = H7[t][0], l = H7[t][1], m = H7[t][2];
+        double &v = c[8 + t];
+        v += u[i] * xx[jidx(l, m)];
+        v += u[l] * xx[jidx(i, m)];
+        v += u[m] * xx[jidx(i, l)];
+        v += Qc[jidx(l, m)] * X[i];
+        v += Qc[jidx(i, m)] * X[l];
+        v += Qc[jidx(i, l)] * X[m];
+    }
+    for (int i = 0; i < 3; ++i) c[15 + i] += g[i];
+    c[18] += a1;
+}
+
+// the reduced accumulator of m2l_accumulate -> f (0..2), J (3..8, jidx),
+// H (9..18, hidx)
+RCB_HD void m2l_finish(const double (&a)[19], double (&c)[19]) {
+    for (int i = 0; i < 3; ++i) c[i] = a[i];
+    const double *G = a + 15;
+    c[3 + jidx(0, 0)] = a[3] + a[18];
+    c[3 + jidx(0, 1)] = a[4];
+    c[3 + jidx(0, 2)] = a[5];
+    c[3 + jidx(1, 1)] = a[6] + a[18];
+    c[3 + jidx(1, 2)] = a[7];
+    c[3 + jidx(2, 2)] = -(c[3 + jidx(0, 0)] + c[3 + jidx(1, 1)]);
+    c[9 + hidx(0, 0, 0)] = a[8] + 3.0 * G[0];
+    c[9 + hidx(0, 0, 1)] = a[9] + G[1];
+    c[9 + hidx(0, 0, 2)] = a[10] + G[2];
+    c[9 + hidx(0, 1, 1)] = a[11] + G[0];
+    c[9 + hidx(0, 1, 2)] = a[12];
+    c[9 + hidx(1, 1, 1)] = a[13] + 3.0 * G[1];
+    c[9 + hidx(1, 1, 2)] = a[14] + G[2];
+    c[9 + hidx(0, 2, 2)] = -(c[9 + hidx(0, 0, 0)] + c[9 + hidx(0, 1, 1)]);
+    c[9 + hidx(1, 2, 2)] = -(c[9 + hidx(0, 0, 1)] + c[9 + hidx(1, 1, 1)]);
+    c[9 + hidx(2, 2, 2)] = -(c[9 + hidx(0, 0, 2)] + c[9 + hidx(1, 1, 2)]);
 }
 
 // a + J d + H[d, d] / 2 for the 19 stored coefficients

@@ -83,8 +83,10 @@ __device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, double 
         c[q] = v;
     }
     if (slot == 0) {
+        double full[19];
+        rcbfar::m2l_finish(c, full);
 #pragma unroll
-        for (int q = 0; q < 19; ++q) coef[li][q] = c[q];
+        for (int q = 0; q < 19; ++q) coef[li][q] = full[q];
     }
     tile_sync();
 }

@@ -5,9 +5,10 @@
 extern "C" {
 
 void shim_m2l(double x, double y, double z, double M, const double *q6, double *c19) {
-    double c[19];
-    for (int i = 0; i < 19; ++i) c[i] = 0.0;
-    rcbfar::m2l_accumulate(x, y, z, M, q6, c);
+    double a[19], c[19];
+    for (int i = 0; i < 19; ++i) a[i] = 0.0;
+    rcbfar::m2l_accumulate(x, y, z, M, q6, a);
+    rcbfar::m2l_finish(a, c);
     for (int i = 0; i < 19; ++i) c19[i] = c[i];
 }
 
