@@ -50,7 +50,18 @@ struct GravArgs {
 };
 
 // Far-field coefficients of the group's leaves into coef[8][19] (LDS).
-__device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, double (*coef)[19]) {
+// The union far list is taken in windows of kFarWin entries. For each window
+// every leaf gets the list of the window positions whose mask has it
+// (ballot ranks, in list order); then lane (s, i) evaluates entries s, s + 8,
+// ... of leaf i's list, so a leaf's lanes only idle at the end of the window
+// rather than on every entry the leaf did not accept.
+constexpr int kFarWin = 256;
+struct FarWindow {
+    int32_t lab[kFarWin];
+    uint8_t idx[8][kFarWin];
+};
+
+__device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, FarWindow &fw, double (*coef)[19]) {
     const int lane = lane_id();
     const int slot = lane >> 3, li = lane & 7;
     const int G = 1 << g.gk;
@@ -60,12 +71,39 @@ __device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, double 
 #pragma unroll
     for (int q = 0; q < 19; ++q) c[q] = 0.0;
     const int64_t f0 = g.gfar_beg[gi], f1 = g.gfar_end[gi];
-    for (int64_t e0 = f0; e0 < f1; e0 += 8) {
-        const int64_t e = e0 + slot;
-        if (e < f1) {
-            const uint64_t ent = g.gfar[e];
-            if ((ent >> (32 + li)) & 1ull) {
-                const int64_t B = (uint32_t)ent & 0x7fffffffu;
+    for (int64_t w0 = f0; w0 < f1; w0 += kFarWin) {
+        const int nw = (int)(f1 - w0 < kFarWin ? f1 - w0 : kFarWin);
+        int base[8];
+#pragma unroll
+        for (int l = 0; l < 8; ++l) base[l] = 0;
+        for (int p0 = 0; p0 < nw; p0 += kWave) {
+            const int p = p0 + lane;
+            uint32_t m = 0;
+            if (p < nw) {
+                const uint64_t ent = g.gfar[w0 + p];
+                fw.lab[p] = (int32_t)((uint32_t)ent & 0x7fffffffu);
+                m = (uint32_t)(ent >> 32) & 0xffu;
+            }
+#pragma unroll
+            for (int l = 0; l < 8; ++l) {
+                const bool has = (m >> l) & 1u;
+                const uint64_t bl = ballot(has);
+                if (has) fw.idx[l][base[l] + rank_below(bl)] = (uint8_t)p;
+                base[l] += __popcll(bl);
+            }
+        }
+        int most = 0, mine = 0;
+#pragma unroll
+        for (int l = 0; l < 8; ++l) {
+            most = base[l] > most ? base[l] : most;
+            mine = li == l ? base[l] : mine;
+        }
+        tile_sync();
+        const int rounds = (most + 7) >> 3;
+        for (int r = 0; r < rounds; ++r) {
+            const int k = 8 * r + slot;
+            if (k < mine) {
+                const int64_t B = fw.lab[fw.idx[li][k]];
                 double qq[6];
 #pragma unroll
                 for (int q = 0; q < 6; ++q) qq[q] = g.nQ[6 * B + q];
@@ -73,6 +111,7 @@ __device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, double 
                                cA[2] - g.ncom[3 * B + 2], g.nM[B], qq, c);
             }
         }
+        tile_sync();
     }
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
@@ -101,10 +140,18 @@ struct alignas(16) SrcD {
 // tile: 64 staged sources, then 64 zero-mass sources that pad the last
 // partial row of slices, so the pair loop needs no bounds test
 template <bool MIXED>
-struct GravShared {
-    double coef[8][19];
+struct NearStage {
     EntryChunk ec;
     typename std::conditional<MIXED, SrcF, SrcD>::type tile[2 * kWave];
+};
+// the far window and the near staging are used one after the other
+template <bool MIXED>
+struct GravShared {
+    double coef[8][19];
+    union {
+        FarWindow fw;
+        NearStage<MIXED> np;
+    };
 };
 
 template <bool MIXED>
@@ -118,12 +165,12 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
     const int G = 1 << g.gk;
     const int64_t GL = (g.nleaf >> g.gk) + gi;   // group node label
     if (g.ncount[GL] == 0) return;
-    group_far(g, gi, sh.coef);
+    group_far(g, gi, sh.fw, sh.coef);
     using Src = typename std::conditional<MIXED, SrcF, SrcD>::type;
     Src dummy;
     dummy.x = dummy.y = dummy.z = dummy.m = 0;
     dummy.h = 1;
-    sh.tile[kWave + lane] = dummy;
+    sh.np.tile[kWave + lane] = dummy;
     const int64_t n0 = g.gnear_beg[gi], n1 = g.gnear_end[gi];
     for (int li = 0; li < G; ++li) {
         const int64_t A = g.nleaf + gi * G + li;
@@ -149,22 +196,22 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
             }
             T ax = 0, ay = 0, az = 0;
             for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
-                const int tot = load_entry_chunk(g.gnear, g.nfirst, g.ncount, e0, n1, 1u << li, sh.ec);
+                const int tot = load_entry_chunk(g.gnear, g.nfirst, g.ncount, e0, n1, 1u << li, sh.np.ec);
                 for (int t = 0; t < tot; t += kWave) {
                     const int q = t + lane;
-                    if (q >= tot) sh.tile[lane] = dummy;
+                    if (q >= tot) sh.np.tile[lane] = dummy;
                     if (q < tot) {
-                        const int k = entry_of(sh.ec, q);
-                        const int64_t pb = (int64_t)sh.ec.fB[k] + (q - sh.ec.pos[k]);
+                        const int k = entry_of(sh.np.ec, q);
+                        const int64_t pb = (int64_t)sh.np.ec.fB[k] + (q - sh.np.ec.pos[k]);
                         if constexpr (MIXED) {
-                            const int64_t B = sh.ec.label[k];
+                            const int64_t B = sh.np.ec.label[k];
                             SrcF s;
                             s.x = (float)(g.ncom[3 * B] - cA[0]) + g.fdx[pb];
                             s.y = (float)(g.ncom[3 * B + 1] - cA[1]) + g.fdy[pb];
                             s.z = (float)(g.ncom[3 * B + 2] - cA[2]) + g.fdz[pb];
                             s.m = g.fm[pb];
                             s.h = g.fh[pb];
-                            sh.tile[lane] = s;
+                            sh.np.tile[lane] = s;
                         } else {
                             SrcD s;
                             s.x = g.px[pb];
@@ -172,14 +219,14 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
                             s.z = g.pz[pb];
                             s.m = g.pm[pb];
                             s.h = g.ph[pb];
-                            sh.tile[lane] = s;
+                            sh.np.tile[lane] = s;
                         }
                     }
                     tile_sync();
                     const int nt = tot - t < kWave ? tot - t : kWave;
                     const int rows = (nt + L.J - 1) / L.J;
                     for (int r = 0; r < rows; ++r) {
-                        const auto s = sh.tile[r * L.J + L.slice];
+                        const auto s = sh.np.tile[r * L.J + L.slice];
                         const T vx = xa - s.x, vy = ya - s.y, vz = za - s.z;
                         const T r2 = (vx * vx + vy * vy) + vz * vz;
                         const T F = soft_F<T>(r2, ha + s.h) * s.m;
@@ -218,13 +265,18 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
 }
 
 // far-field coefficients of every leaf, stride doubles per leaf (first 19 used)
+struct FarShared {
+    double coef[8][19];
+    FarWindow fw;
+};
 __global__ __launch_bounds__(kBlock) void k_far_coeffs(GravArgs g, double *out, int stride) {
-    __shared__ double coef_all[kWaves][8][19];
-    double(*coef)[19] = coef_all[threadIdx.x / kWave];
+    __shared__ FarShared sh_all[kWaves];
+    FarShared &sh = sh_all[threadIdx.x / kWave];
+    double(*coef)[19] = sh.coef;
     const int64_t gi = wave_index();
     if (gi >= g.ngroup) return;
     const int G = 1 << g.gk;
-    group_far(g, gi, coef);
+    group_far(g, gi, sh.fw, coef);
     for (int i = lane_id(); i < G * 19; i += kWave) out[(gi * G + i / 19) * stride + i % 19] = coef[i / 19][i % 19];
 }
 
