@@ -9,7 +9,12 @@
 // candidate mask has the leaf) are staged through LDS 64 particles at a
 // time; slice j of sink s tests tile entries j, j + J, .... A pair is a
 // neighbour iff b != a and |r_a - r_b|^2 < (2 h_a)^2 in FP64 on the tree's
-// copy of the inputs (the same predicate for every precision mode). Ranks
+// copy of the inputs (the same predicate for every precision mode).
+// Staging keeps only the sources inside the leaf's sphere (centre g_A,
+// radius h_node(A) padded by 2^-32, Sec. 2.3.1): a neighbour b of a sink a
+// has |r_b - g_A| <= |r_b - r_a| + |r_a - g_A| < 2 h_a + |r_a - g_A|
+// <= h_node(A), so no neighbour is dropped, and the sources that stay are
+// compacted in order. Ranks
 // are taken by ballot within the sink's lane segment, so each list keeps tree
 // order. The count call writes the ids into a slab of kNbCap slots per
 // particle as well as the counts; the fill call then compacts the slab into
@@ -29,6 +34,8 @@ struct NeighArgs {
     int64_t nleaf;
     int gk;
     int64_t ngroup;
+    const double4 *rec;       // walk records: rec[2 label] = (box centre, h_node_int)
+    const double *hnode;
     const int32_t *nfirst, *ncount;
     const int64_t *gnear_beg, *gnear_end;
     const uint64_t *gnear;
@@ -47,8 +54,9 @@ struct alignas(16) SrcN {
     int32_t id;   // caller index
 };
 
-// tile: 64 staged sources, then 64 sources that can never be neighbours
-// (pb = -1 at infinite distance), padding the last partial row of slices
+// tile: kept sources accumulate until at least 64 wait (at most 127); the
+// last partial row is padded with sources that can never be neighbours
+// (pb = -1 at infinite distance)
 struct NeighShared {
     EntryChunk ec;
     SrcN tile[2 * kWave];
@@ -68,11 +76,6 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
     const int64_t GL = (a.nleaf >> a.gk) + gi;
     if (a.ncount[GL] == 0) return;
     if (!SLAB && a.gover && a.gover[gi] == 0) return;   // its lists came from the slab
-    SrcN dummy;
-    dummy.x = dummy.y = dummy.z = __builtin_inf();
-    dummy.pb = -1;
-    dummy.id = -1;
-    sh.tile[kWave + lane] = dummy;
     const int64_t n0 = a.gnear_beg[gi], n1 = a.gnear_end[gi];
     for (int li = 0; li < G; ++li) {
         const int64_t A = a.nleaf + gi * G + li;
@@ -80,6 +83,9 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
         if (c == 0) continue;
         const LeafLanes L = leaf_lanes(c);
         const uint64_t segmask = seg_mask(L);
+        const double4 gA = a.rec[2 * A];
+        const double rA = a.hnode[A] * kReachPad;
+        const double rA2 = rA * rA;
         for (int g0 = 0; g0 < c; g0 += L.S) {
             const int si = g0 + L.sslot;
             const bool has_sink = L.sslot < L.S && si < c;
@@ -90,36 +96,85 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
             int cnt = 0;
             const int32_t oa = a.pid[pa];
             const int64_t obase = SLAB ? (int64_t)pa * kNbCap : (has_sink ? a.offsets[oa] : 0);
+            // rows [0, np) of the tile: slice j of a sink tests entries j, j + J, ...
+            auto rows = [&](int np) {
+                for (int u0 = 0; u0 < np; u0 += L.J) {
+                    const SrcN s = sh.tile[u0 + L.slice];
+                    const bool hit = s.pb != pa && dist2(xa, ya, za, s.x, s.y, s.z) < lim;
+                    const uint64_t bal = ballot(hit) & segmask;
+                    const int r = cnt + rank_below(bal);
+                    if (hit && (!SLAB || r < kNbCap)) a.ids[obase + r] = s.id;
+                    cnt += __popcll(bal);
+                }
+            };
+            int fill = 0;   // kept sources waiting in tile[0, fill)
             for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
                 const int tot =
                     load_entry_chunk(a.gnear, a.nfirst, a.ncount, e0, n1, 1u << (8 + li), sh.ec);
                 for (int t = 0; t < tot; t += kWave) {
                     const int q = t + lane;
-                    if (q >= tot) sh.tile[lane] = dummy;
+                    double sx = 0.0, sy = 0.0, sz = 0.0;
+                    int32_t spb = -1, sid = -1;
                     if (q < tot) {
                         const int k = entry_of(sh.ec, q);
                         const int32_t pb = sh.ec.fB[k] + (q - sh.ec.pos[k]);
-                        SrcN s;
-                        s.x = a.px[pb];
-                        s.y = a.py[pb];
-                        s.z = a.pz[pb];
-                        s.pb = pb;
-                        s.id = a.pid[pb];
-                        sh.tile[lane] = s;
+                        sx = a.px[pb];
+                        sy = a.py[pb];
+                        sz = a.pz[pb];
+                        spb = pb;
+                        sid = a.pid[pb];
                     }
-                    tile_sync();
-                    const int nt = tot - t < kWave ? tot - t : kWave;
-                    for (int u0 = 0; u0 < nt; u0 += L.J) {
-                        const SrcN s = sh.tile[u0 + L.slice];
-                        const bool hit = s.pb != pa && dist2(xa, ya, za, s.x, s.y, s.z) < lim;
-                        const uint64_t bal = ballot(hit) & segmask;
-                        const int r = cnt + rank_below(bal);
-                        if (hit && (!SLAB || r < kNbCap)) a.ids[obase + r] = s.id;
-                        cnt += __popcll(bal);
+                    const bool keep = q < tot && dist2(gA.x, gA.y, gA.z, sx, sy, sz) < rA2;
+                    const uint64_t kb = ballot(keep);
+                    if (keep) {   // appended in order after the waiting ones
+                        SrcN &dst = sh.tile[fill + rank_below(kb)];
+                        dst.x = sx;
+                        dst.y = sy;
+                        dst.z = sz;
+                        dst.pb = spb;
+                        dst.id = sid;
                     }
+                    const int avail = fill + __popcll(kb);
                     tile_sync();
+                    if (avail >= kWave) {   // whole rows only; the rest waits
+                        const int np = avail - avail % L.J;
+                        rows(np);
+                        fill = avail - np;
+                        tile_sync();
+                        double vx = 0.0, vy = 0.0, vz = 0.0;
+                        int32_t vpb = -1, vid = -1;
+                        if (lane < fill) {
+                            const SrcN &src = sh.tile[np + lane];
+                            vx = src.x;
+                            vy = src.y;
+                            vz = src.z;
+                            vpb = src.pb;
+                            vid = src.id;
+                        }
+                        tile_sync();
+                        if (lane < fill) {
+                            SrcN &dst = sh.tile[lane];
+                            dst.x = vx;
+                            dst.y = vy;
+                            dst.z = vz;
+                            dst.pb = vpb;
+                            dst.id = vid;
+                        }
+                        tile_sync();
+                    } else {
+                        fill = avail;
+                    }
                 }
             }
+            {   // pads the last partial row
+                SrcN &dst = sh.tile[fill + lane];
+                dst.x = dst.y = dst.z = __builtin_inf();
+                dst.pb = -1;
+                dst.id = -1;
+            }
+            tile_sync();
+            rows(fill);
+            tile_sync();
             if (SLAB && has_sink && L.slice == 0) {
                 a.counts[oa] = cnt;
                 if (cnt > kNbCap) {
@@ -163,9 +218,9 @@ rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipSt
     }
     RCB_HIP(hipMemsetAsync(t->dflag + 4, 0, sizeof(int32_t), s));
     RCB_HIP(hipMemsetAsync(t->nb_gover, 0, sizeof(int32_t) * t->ngroup, s));
-    NeighArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->gnear_beg, t->gnear_end, t->gnear,
-                t->px, t->py, t->pz, t->ph, t->pid, counts, nullptr, t->nb_slab, t->dflag + 4,
-                t->nb_gover};
+    NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
+                t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, counts, nullptr, t->nb_slab,
+                t->dflag + 4, t->nb_gover};
     const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     k_neigh<true><<<grid, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_neigh<slab>");
@@ -196,8 +251,9 @@ rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, in
     k_nb_compact<<<gridc, kBlock, 0, s>>>(t->n, t->pid, offsets, t->nb_slab, ids);
     RCB_LAUNCH_CHECK("k_nb_compact");
     if (t->nb_over > 0) {
-        NeighArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->gnear_beg, t->gnear_end, t->gnear,
-                    t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids, nullptr, t->nb_gover};
+        NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
+                    t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids, nullptr,
+                    t->nb_gover};
         const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
         k_neigh<false><<<grid, kBlock, 0, s>>>(a);
         RCB_LAUNCH_CHECK("k_neigh<fill>");
