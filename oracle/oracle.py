@@ -123,14 +123,15 @@ class OracleTree:
     """The oracle's RCB tree for one particle set (FP64, CPU)."""
 
     def __init__(self, x, y, z, m, h, n_ll: int, split: str = "mass"):
-        """split: "mass" (centre of mass, the paper's choice) or "number"
-        (centre of number, Sec. 2.1 "Load balancing")."""
+        """split: "mass" (centre of mass, the paper's choice), "number"
+        (centre of number) or "median" (median position split, equal halves;
+        Sec. 2.1 "Load balancing")."""
         L = lib()
         self._keep = [_d(a) for a in (x, y, z, m, h)]
         ps = [k[1] for k in self._keep]
         self.n = int(self._keep[0][0].shape[0])
         self.n_ll = n_ll
-        self.ptr = L.orc_build(self.n, *ps, n_ll, {"mass": 0, "number": 1}[split])
+        self.ptr = L.orc_build(self.n, *ps, n_ll, {"mass": 0, "number": 1, "median": 2}[split])
         if not self.ptr:
             raise ValueError("oracle build rejected its arguments")
         self.k = int(L.orc_k(self.ptr))

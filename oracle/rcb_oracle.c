@@ -91,7 +91,7 @@ typedef struct otree {
     double *M, *com, *Q;           /* Q: xx xy xz yy yz zz per label */
     double *hint, *hnode;
     double theta;
-    int split;                     /* 0: centre of mass, 1: centre of number */
+    int split;                     /* 0: centre of mass, 1: centre of number, 2: median */
     int pure_mac;                  /* walk mode of the last orc_walk */
     leaf_lists *lists;             /* one per leaf, index label - 2^k */
 } otree;
@@ -149,9 +149,23 @@ static double node_mean(const otree *t, int64_t lab, const double *xa)
     return mean;
 }
 
+/* Order of the median split: coordinate, then original index (numerical  */
+/* comparison, so -0 and +0 tie and the index decides).                     */
+static const double *g_sort_key;
+static int cmp_by_key_then_index(const void *a, const void *b)
+{
+    int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
+    double xi = g_sort_key[i], xj = g_sort_key[j];
+    if (xi < xj) return -1;
+    if (xi > xj) return 1;
+    return (i > j) - (i < j);
+}
+
 /* Split one node perpendicular to its longest side through its centre of  */
-/* mass, or its centre of number (Sec. 2.1 "Load balancing", "Particle      */
-/* sorting").                                                               */
+/* mass, its centre of number, or its median (Sec. 2.1 "Load balancing",    */
+/* "Particle sorting"). The median split (MPS) sends the floor(c/2)        */
+/* particles that come first in (coordinate, original index) order to the  */
+/* lower child; its plane is the coordinate of the first upper particle.    */
 static void split_node(otree *t, int64_t lab)
 {
     int64_t s = t->first[lab], c = t->count[lab];
@@ -178,14 +192,30 @@ static void split_node(otree *t, int64_t lab)
     }
     t->axis[lab] = ax;
     const double *xa = ax == 0 ? t->x : (ax == 1 ? t->y : t->z);
-    double plane = t->split == 1 ? node_mean(t, lab, xa) : com[ax];
+    double plane;
+    int64_t tie = -1;          /* median split: (x, index) pairs below (plane, tie) go left */
+    if (t->split == 2) {
+        int64_t *ord = (int64_t *)malloc((size_t)c * sizeof(int64_t));
+        memcpy(ord, t->perm + s, (size_t)c * sizeof(int64_t));
+        g_sort_key = xa;
+        qsort(ord, (size_t)c, sizeof(int64_t), cmp_by_key_then_index);
+        plane = xa[ord[c / 2]] + 0.0;
+        tie = ord[c / 2];
+        free(ord);
+    } else {
+        plane = t->split == 1 ? node_mean(t, lab, xa) : com[ax];
+    }
     int64_t *tmp = (int64_t *)malloc((size_t)c * sizeof(int64_t));
     int64_t nl = 0;
-    for (int64_t i = 0; i < c; ++i)
-        if (xa[t->perm[s + i]] < plane) tmp[nl++] = t->perm[s + i];
+    for (int64_t i = 0; i < c; ++i) {
+        int64_t b = t->perm[s + i];
+        if (xa[b] < plane || (xa[b] == plane && b < tie)) tmp[nl++] = b;
+    }
     int64_t j = nl;
-    for (int64_t i = 0; i < c; ++i)
-        if (!(xa[t->perm[s + i]] < plane)) tmp[j++] = t->perm[s + i];
+    for (int64_t i = 0; i < c; ++i) {
+        int64_t b = t->perm[s + i];
+        if (!(xa[b] < plane || (xa[b] == plane && b < tie))) tmp[j++] = b;
+    }
     memcpy(t->perm + s, tmp, (size_t)c * sizeof(int64_t));
     free(tmp);
     t->first[L] = s; t->count[L] = nl;
@@ -307,11 +337,12 @@ int orc_depth_for(int64_t n, int n_ll)
 
 /* Top-down build (Sec. 2.1): root box = bounding box of all particles;   */
 /* levels 0 .. k-1 are split in turn; then the node moments.             */
-/* split: 0 = through the centre of mass, 1 = through the centre of number. */
+/* split: 0 = through the centre of mass, 1 = through the centre of number, */
+/* 2 = median position split (equal halves).                                */
 otree *orc_build(int64_t n, const double *x, const double *y, const double *z,
                  const double *m, const double *h, int n_ll, int split)
 {
-    if (n < 1 || n_ll < 1 || split < 0 || split > 1) return NULL;
+    if (n < 1 || n_ll < 1 || split < 0 || split > 2) return NULL;
     otree *t = (otree *)calloc(1, sizeof(otree));
     t->n = n;
     t->n_ll = n_ll;

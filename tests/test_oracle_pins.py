@@ -212,11 +212,17 @@ def test_taylor_error_falls_as_third_power():
 # --------------------------------------------------------------------------
 # tree build, Sec. 2.1
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("split", ["mass", "number"])
+@pytest.mark.parametrize("split", ["mass", "number", "median"])
 @pytest.mark.parametrize("n,nll,kind", [(1, 12, "uniform"), (5, 12, "uniform"), (300, 4, "clustered"),
-                                        (1001, 8, "plummer"), (777, 3, "uniform")])
+                                        (1001, 8, "plummer"), (777, 3, "uniform"), (600, 5, "ties")])
 def test_tree_rules(n, nll, kind, split):
-    c = W.small_random(n, 10 + n, kind)
+    if kind == "ties":          # many equal coordinates: the median split's tie rule
+        c = W.small_random(n, 10 + n, "uniform")
+        c.x[:] = np.round(c.x * 4) / 4
+        c.y[:] = np.round(c.y * 3) / 3
+        c.z[::3] = -0.0
+    else:
+        c = W.small_random(n, 10 + n, kind)
     t = O.OracleTree(*c.arrays(), n_ll=nll, split=split)
     topo, nd = t.topology(), t.nodes()
     perm, first, count, axis = topo["perm"], topo["first"], topo["count"], topo["axis"]
@@ -236,15 +242,24 @@ def test_tree_rules(n, nll, kind, split):
         ax = int(np.argmax(side))                       # first maximum
         assert axis[lab] == ax
         ids = np.sort(perm[first[lab]:first[lab] + count[lab]])
+        plane = nd["hi"][L][ax]
+        assert plane == nd["lo"][R][ax]
+        left = perm[first[L]:first[L] + count[L]]
+        right = perm[first[R]:first[R] + count[R]]
+        if split == "median":
+            # equal halves: the floor(c/2) first in (coordinate, index) order go left
+            order = np.lexsort((ids, P[ids, ax]))
+            assert count[L] == len(ids) // 2
+            np.testing.assert_array_equal(np.sort(left), np.sort(ids[order[:len(ids) // 2]]))
+            assert plane == P[ids[order[len(ids) // 2]], ax]
+            assert plane != 0.0 or math.copysign(1.0, plane) == 1.0     # -0 is stored as +0
+            assert np.all(P[left, ax] <= plane) and np.all(P[right, ax] >= plane)
+            continue
         if split == "mass":
             com = np.array([math.fsum(c.m[ids] * P[ids, d]) / math.fsum(c.m[ids]) for d in range(3)])
         else:                                            # centre of number: weights 1
             com = np.array([math.fsum(P[ids, d]) / len(ids) for d in range(3)])
-        plane = nd["hi"][L][ax]
-        assert plane == nd["lo"][R][ax]
         assert abs(plane - com[ax]) <= 1e-14 * (1 + abs(com[ax]))
-        left = perm[first[L]:first[L] + count[L]]
-        right = perm[first[R]:first[R] + count[R]]
         assert np.all(P[left, ax] < plane) and np.all(P[right, ax] >= plane)
     for lab in range(1 << t.k, 2 << t.k):
         ids = perm[first[lab]:first[lab] + count[lab]]
@@ -271,6 +286,22 @@ def test_centre_of_number_split_equals_mass_split_for_equal_power_of_two_masses(
     a2 = O.OracleTree(*c2.arrays(), n_ll=5, split="mass")
     b2 = O.OracleTree(*c2.arrays(), n_ll=5, split="number")
     assert not np.array_equal(a2.nodes()["hi"], b2.nodes()["hi"])
+
+
+def test_median_split_renegades_cost_accuracy():
+    # Sec. 2.1 "Load balancing": in a binary with more particles in one star the
+    # median split cuts the heavier star and puts part of it into the lighter
+    # star's cell; the centre-of-mass split keeps the stars apart. The
+    # truncation errors of the median tree are larger.
+    c = W.binary_clumps()
+    ref = brute.direct_accel(c.x, c.y, c.z, c.m, c.h)
+    err = {}
+    for split in ("mass", "median"):
+        t = O.OracleTree(*c.arrays(), n_ll=8, split=split)
+        t.walk(0.7)
+        err[split] = brute.error_stats(np.stack(t.gravity(), 1), ref)
+    assert err["median"]["mean"] > 1.5 * err["mass"]["mean"]
+    assert err["median"]["p99"] > 1.5 * err["mass"]["p99"]
 
 
 def test_quadrupole_eq1_traceless_and_eq2_equals_direct():

@@ -177,6 +177,20 @@ def sobol_sphere(n: int = 500_000, n_neigh: int = 105, seed: int = SEED_BASE + 6
                  np.ascontiguousarray(pts[:, 2]), np.full(n, 1.0 / n), _h_from_density(dens, n_neigh))
 
 
+def binary_clumps(n1: int = 3000, n2: int = 1000, seed: int = SEED_BASE + 7) -> Cloud:
+    """A binary of two Gaussian clumps with unequal particle numbers (3000 at
+    the origin, sigma 0.5; 1000 at (6, 0.3, 0), sigma 0.35), equal masses,
+    h = 0.08: the case where a median split cuts the heavier clump
+    (Sec. 2.1 "Load balancing")."""
+    rng = np.random.default_rng(seed)
+    a = 0.5 * rng.standard_normal((n1, 3))
+    b = 0.35 * rng.standard_normal((n2, 3)) + np.array([6.0, 0.3, 0.0])
+    p = np.concatenate([a, b])
+    n = n1 + n2
+    return Cloud("binary_clumps", np.ascontiguousarray(p[:, 0]), np.ascontiguousarray(p[:, 1]),
+                 np.ascontiguousarray(p[:, 2]), np.full(n, 1.0 / n), np.full(n, 0.08))
+
+
 def plummer_subset(n_sub: int = 4096, seed: int = SEED_BASE + 5,
                    parent_n: int = 1 << 20) -> Cloud:
     """Random subset of the Plummer cloud, m = 1/n_sub, h from exact kNN."""
