@@ -58,7 +58,12 @@ typedef enum {
 
 typedef enum {
     RCB_SPLIT_MASS = 0,     /* split planes through the centre of mass (the paper's CMS) */
-    RCB_SPLIT_NUMBER = 1    /* through the centre of number: unit weights (Sec. 2.1 "Load balancing") */
+    RCB_SPLIT_NUMBER = 1,   /* through the centre of number: unit weights (Sec. 2.1 "Load balancing") */
+    RCB_SPLIT_MEDIAN = 2    /* median position split (MPS, Sec. 2.1): the floor(c/2) particles first in
+                               (coordinate, caller index) order go to the lower child, so the halves
+                               are exact; the plane is the first upper particle's coordinate. Particles
+                               tied with it may then sit on their cell's upper face, which
+                               rcb_check_cells counts as outside (a rebuild is never missed) */
 } rcb_split;
 
 typedef struct {
@@ -83,8 +88,9 @@ void rcb_params_default(rcb_params *p);
  * Build the tree top-down (Sec. 2.1): the root cell is the particles'
  * bounding box; each cell is split perpendicular to its longest side through
  * its centre of mass (or, with split = RCB_SPLIT_NUMBER, its centre of number:
- * the mean coordinate), particles with coordinate < plane going to the lower
- * child 2n (stable), the rest to 2n+1, until level k = min{k : n <= n_ll 2^k}.
+ * the mean coordinate; with RCB_SPLIT_MEDIAN, its median), particles with
+ * coordinate < plane going to the lower child 2n (stable), the rest to 2n+1,
+ * until level k = min{k : n <= n_ll 2^k}.
  * Every node gets its mass, centre of mass (canonical pairwise sums over its
  * particles in ascending input index), traceless quadrupole (Eq. 1 at the
  * leaves, Eq. 2 upwards), h_node_int and, for leaves, h_node (Sec. 2.3.1).

@@ -111,8 +111,9 @@ class Tree:
 
     def __init__(self, x, y, z, m, h, n_ll: int = 12, theta: float = 0.7, precision: str = "fp64",
                  validate: bool = False, pure_mac: bool = False, split: str = "mass"):
-        """split: "mass" (planes through the centre of mass, the paper's) or
-        "number" (through the centre of number)."""
+        """split: "mass" (planes through the centre of mass, the paper's),
+        "number" (through the centre of number) or "median" (median position
+        split: equal halves)."""
         L = lib()
         arrs = [_dev(a, torch.float64, nm) for a, nm in zip((x, y, z, m, h), "xyzmh")]
         n = arrs[0].numel()
@@ -126,7 +127,7 @@ class Tree:
         p.precision = RCB_MIXED if precision == "mixed" else RCB_FP64
         p.validate = 1 if validate else 0
         p.pure_mac = 1 if pure_mac else 0
-        p.split = {"mass": 0, "number": 1}[split]
+        p.split = {"mass": 0, "number": 1, "median": 2}[split]
         self.precision = precision
         self.device = arrs[0].device
         self.n = n

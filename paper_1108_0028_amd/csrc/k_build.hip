@@ -264,7 +264,22 @@ struct NodeOut {
     double *nlo, *nhi, *ncom, *nM, *nhint, *nhnode, *nQ;
     int32_t *naxis;
     double *nplane;
+    // median split only (else null): plane and caller index of the first
+    // upper particle of each node, computed before the node's level pass
+    const double *mplane;
+    const int32_t *mtie;
 };
+
+// The side rule: a particle goes to the lower child iff (x, caller index)
+// comes before (plane, tie). Splits through a centre use tie = INT32_MIN,
+// i.e. x < plane; the median split's tie makes the halves exact.
+__device__ __forceinline__ int32_t node_tie(const NodeOut &o, int64_t lab) {
+    return o.mplane ? o.mtie[lab] : INT32_MIN;
+}
+__device__ __forceinline__ bool goes_left(double x, const int32_t *__restrict__ id, int64_t i,
+                                          double plane, int32_t tie) {
+    return x < plane || (tie != INT32_MIN && x == plane && id[i] < tie);
+}
 
 __device__ __forceinline__ void box_centre(const NodeOut &o, int64_t lab, double g[3]) {
 #pragma unroll
@@ -304,7 +319,7 @@ __device__ void finish_a(const NodeOut &o, int64_t lab, bool leaf, const double 
         ax = 1;
     }
     if (hi[2] - lo[2] > best) ax = 2;
-    const double plane = ax == 0 ? com[0] : (ax == 1 ? com[1] : com[2]);
+    const double plane = o.mplane ? o.mplane[lab] : (ax == 0 ? com[0] : (ax == 1 ? com[1] : com[2]));
     if (l == 0) {
         o.naxis[lab] = ax;
         o.nplane[lab] = plane;
@@ -372,7 +387,7 @@ struct PartOut {
 // stores of a side are contiguous across lanes.
 __device__ __forceinline__ void scatter_chunk(const PartIn &in, const int32_t *__restrict__ id,
                                               const PartOut &out, int64_t base, int64_t end,
-                                              int ax, double plane, int64_t node_first,
+                                              int ax, double plane, int32_t tie, int64_t node_first,
                                               int64_t nleft_total, int64_t lb, int64_t rb) {
     const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
     const int l = lane_id();
@@ -381,7 +396,7 @@ __device__ __forceinline__ void scatter_chunk(const PartIn &in, const int32_t *_
     for (int t = 0; t < 8; ++t) {
         const int64_t i = base + 64 * t + l;
         const bool valid = i < end;
-        const bool left = valid && (xa[i] < plane);
+        const bool left = valid && goes_left(xa[i], id, i, plane, tie);
         const uint64_t bl = ballot(left);
         const int nl = __popcll(bl);
         const int nv = (int)min<int64_t>(64, max<int64_t>(0, end - (base + 64 * t)));
@@ -461,17 +476,18 @@ __device__ __forceinline__ void level_node(int64_t lab, bool leaf, bool split, c
         ax = 1;
     }
     if (hi[2] - lo[2] > best) ax = 2;
-    const double plane = (sa[1 + ax] + 0.0) / (sa[0] + 0.0);
+    const double plane = o.mplane ? o.mplane[lab] : (sa[1 + ax] + 0.0) / (sa[0] + 0.0);
+    const int32_t tie = node_tie(o, lab);
     // count the left side first (needed for the right side's base)
     const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
     int nl = 0;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int64_t i = (int64_t)s + 64 * t + lane_id();
-        nl += (i < (int64_t)s + c) && (xa[i] < plane);
+        nl += (i < (int64_t)s + c) && goes_left(xa[i], id, i, plane, tie);
     }
     const int nleft = wave_sum_i(nl);
-    scatter_chunk(in, id, out, s, (int64_t)s + c, ax, plane, s, nleft, 0, 0);
+    scatter_chunk(in, id, out, s, (int64_t)s + c, ax, plane, tie, s, nleft, 0, 0);
     if (lane_id() == 0) {
         o.nfirst[2 * lab] = s;
         o.ncount[2 * lab] = nleft;
@@ -561,13 +577,14 @@ __global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int leaf_level
         ax = 1;
     }
     if (hi[2] - lo[2] > best) ax = 2;
-    const double plane = (sa[1 + ax] + 0.0) / (sa[0] + 0.0);
+    const double plane = o.mplane ? o.mplane[lab] : (sa[1 + ax] + 0.0) / (sa[0] + 0.0);
+    const int32_t tie = node_tie(o, lab);
     const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
     const int64_t e0 = (int64_t)s + 8 * gl, end = (int64_t)s + c;
     uint32_t lb = 0;
 #pragma unroll
     for (int t = 0; t < 8; ++t)
-        if (e0 + t < end && xa[e0 + t] < plane) lb |= 1u << t;
+        if (e0 + t < end && goes_left(xa[e0 + t], id, e0 + t, plane, tie)) lb |= 1u << t;
     const int nl = __popc(lb);
     int incl = nl;   // inclusive scan of the left counts over the group
 #pragma unroll
@@ -690,7 +707,8 @@ __global__ __launch_bounds__(kBlock) void k_big_finalize(int leaf_level, int spl
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_part_count(PartIn in, NodeOut o, BigCtl bc,
+__global__ __launch_bounds__(kBlock) void k_part_count(PartIn in, const int32_t *__restrict__ id,
+                                                       NodeOut o, BigCtl bc,
                                                        int32_t *__restrict__ part_left) {
     const int64_t w = wave_index();
     if (w >= bc.ctl[1]) return;
@@ -702,12 +720,13 @@ __global__ __launch_bounds__(kBlock) void k_part_count(PartIn in, NodeOut o, Big
     const int64_t end = min(base + kChunk, s + c);
     const int ax = o.naxis[lab];
     const double plane = o.nplane[lab];
+    const int32_t tie = node_tie(o, lab);
     const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
     int nl = 0;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int64_t i = base + 64 * t + lane_id();
-        nl += (i < end) && (xa[i] < plane);
+        nl += (i < end) && goes_left(xa[i], id, i, plane, tie);
     }
     nl = wave_sum_i(nl);
     if (lane_id() == 0) part_left[w] = nl;
@@ -751,7 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(PartIn in, const int32_
     const int64_t lb = part_left[w];
     const int64_t rb = j * kChunk - lb;
     const int64_t nleft = o.ncount[2 * lab];
-    scatter_chunk(in, id, out, base, end, o.naxis[lab], o.nplane[lab], s, nleft, lb, rb);
+    scatter_chunk(in, id, out, base, end, o.naxis[lab], o.nplane[lab], node_tie(o, lab), s, nleft, lb, rb);
 }
 
 // Eq. 2: parent quadrupole from the non-empty children, shifted by the
@@ -862,6 +881,182 @@ inline unsigned blocks_for_waves(int64_t waves) {
     return (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
+// ---------------------------------------------------------------------------
+// median position split (Sec. 2.1 "Load balancing"): before a level's pass,
+// the particle of rank floor(c/2) of every node in (coordinate, caller
+// index) order along the node's split axis, i.e. the first particle of the
+// upper child. With this split every node of level l holds floor(n / 2^l)
+// or ceil(n / 2^l) particles, so a level is all small (one wave ranks each
+// element by counting) or all big (radix select over the 12 bytes of a
+// 96-bit key: order-preserving coordinate bits, then the caller index).
+// ---------------------------------------------------------------------------
+constexpr int kSelSmall = 1024;
+
+__device__ __forceinline__ void tile_sync_build() {
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+__device__ __forceinline__ int node_axis(const NodeOut &o, int64_t lab) {
+    const double sx = o.nhi[3 * lab] - o.nlo[3 * lab];
+    const double sy = o.nhi[3 * lab + 1] - o.nlo[3 * lab + 1];
+    const double sz = o.nhi[3 * lab + 2] - o.nlo[3 * lab + 2];
+    int ax = 0;
+    double best = sx;
+    if (sy > best) {
+        best = sy;
+        ax = 1;
+    }
+    if (sz > best) ax = 2;
+    return ax;
+}
+
+// x + 0.0 turns -0 into +0, so numerically equal coordinates get equal keys
+__device__ __forceinline__ uint64_t order_key(double x) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x + 0.0);
+    return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+__device__ __forceinline__ double key_value(uint64_t k) {
+    const uint64_t u = (k >> 63) ? (k & ~(1ull << 63)) : ~k;
+    return __longlong_as_double((long long)u);
+}
+
+// one wave (block) per node of <= kSelSmall particles
+__global__ __launch_bounds__(kWave) void k_median_small(int lvl, PartIn in, const int32_t *__restrict__ id,
+                                                        NodeOut o, double *__restrict__ mplane,
+                                                        int32_t *__restrict__ mtie, int32_t *__restrict__ flag) {
+    __shared__ double sx[kSelSmall];
+    __shared__ int32_t sid[kSelSmall];
+    const int64_t lab = ((int64_t)1 << lvl) + blockIdx.x;
+    const int32_t s = o.nfirst[lab], c = o.ncount[lab];
+    if (c == 0) return;
+    if (c > kSelSmall) {   // cannot happen: node sizes follow from n and the level
+        if (threadIdx.x == 0) atomicOr(flag, 1);
+        return;
+    }
+    const int ax = node_axis(o, lab);
+    const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
+    for (int i = threadIdx.x; i < c; i += kWave) {
+        sx[i] = xa[s + i] + 0.0;
+        sid[i] = id[s + i];
+    }
+    __syncthreads();
+    const int target = c / 2;
+    for (int i = threadIdx.x; i < c; i += kWave) {
+        const double xi = sx[i];
+        const int32_t ii = sid[i];
+        int r = 0;
+        for (int j = 0; j < c; ++j) {
+            const double xj = sx[j];
+            r += (xj < xi) || (xj == xi && sid[j] < ii);
+        }
+        if (r == target) {
+            mplane[lab] = xi;
+            mtie[lab] = ii;
+        }
+    }
+}
+
+struct MedSel {
+    uint64_t *khi;    // per node of the level: coordinate key bytes found so far
+    uint32_t *klo;    // caller-index bytes found so far
+    int32_t *rank;    // rank still sought among the elements matching the prefix
+    uint32_t *hist;   // 256 bins per node
+};
+
+__global__ void k_msel_init(int lvl, NodeOut o, MedSel m) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= ((int64_t)1 << lvl)) return;
+    m.khi[j] = 0;
+    m.klo[j] = 0;
+    m.rank[j] = o.ncount[((int64_t)1 << lvl) + j] / 2;
+}
+
+// histogram of byte `pass` over the elements that match the prefix; one
+// wave per kChunk elements of a node (cpn waves per node)
+__global__ __launch_bounds__(kBlock) void k_msel_hist(int lvl, int cpn, int pass, PartIn in,
+                                                      const int32_t *__restrict__ id, NodeOut o, MedSel m) {
+    __shared__ uint32_t hist_all[kWavesPerBlock][256];
+    uint32_t *hh = hist_all[threadIdx.x / kWave];
+    const int64_t nodes = (int64_t)1 << lvl;
+    const int64_t w = wave_index();
+    if (w >= nodes * cpn) return;
+    const int64_t j = w / cpn, ch = w % cpn;
+    const int64_t lab = nodes + j;
+    const int64_t s = o.nfirst[lab], c = o.ncount[lab];
+    const int64_t b0 = s + ch * kChunk, e = min(b0 + kChunk, s + c);
+    const int lane = lane_id();
+    for (int q = lane; q < 256; q += kWave) hh[q] = 0;
+    tile_sync_build();
+    if (b0 < e) {
+        const int ax = node_axis(o, lab);
+        const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
+        const uint64_t phi = m.khi[j];
+        const uint32_t plo = m.klo[j];
+        for (int64_t i = b0 + lane; i < e; i += kWave) {
+            const uint64_t kx = order_key(xa[i]);
+            const uint32_t kid = (uint32_t)id[i];
+            bool match;
+            int digit;
+            if (pass < 8) {
+                match = pass == 0 || (kx >> (64 - 8 * pass)) == (phi >> (64 - 8 * pass));
+                digit = (int)((kx >> (56 - 8 * pass)) & 0xffu);
+            } else {
+                const int p2 = pass - 8;
+                match = kx == phi && (p2 == 0 || (kid >> (32 - 8 * p2)) == (plo >> (32 - 8 * p2)));
+                digit = (int)((kid >> (24 - 8 * p2)) & 0xffu);
+            }
+            if (match) atomicAdd(&hh[digit], 1u);
+        }
+    }
+    tile_sync_build();
+    for (int q = lane; q < 256; q += kWave)
+        if (hh[q]) atomicAdd(&m.hist[j * 256 + q], hh[q]);
+}
+
+// the byte of the sought element: the bin where the running count passes
+// the rank; bins are cleared for the next pass
+__global__ __launch_bounds__(kBlock) void k_msel_pick(int lvl, int pass, MedSel m, double *__restrict__ mplane,
+                                                      int32_t *__restrict__ mtie) {
+    const int64_t nodes = (int64_t)1 << lvl;
+    const int64_t j = wave_index();
+    if (j >= nodes) return;
+    const int lane = lane_id();
+    uint32_t v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v[q] = m.hist[j * 256 + 4 * lane + q];
+        m.hist[j * 256 + 4 * lane + q] = 0;
+    }
+    const int tot = (int)(v[0] + v[1] + v[2] + v[3]);
+    const int excl = wave_excl_scan(tot);
+    const int r = m.rank[j];
+    if (excl <= r && r < excl + tot) {
+        int acc = excl, d = 4 * lane;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (r < acc + (int)v[q]) {
+                d = 4 * lane + q;
+                break;
+            }
+            acc += (int)v[q];
+        }
+        uint64_t khi = m.khi[j];
+        uint32_t klo = m.klo[j];
+        if (pass < 8)
+            khi |= (uint64_t)d << (56 - 8 * pass);
+        else
+            klo |= (uint32_t)d << (24 - 8 * (pass - 8));
+        m.khi[j] = khi;
+        m.klo[j] = klo;
+        m.rank[j] = r - acc;
+        if (pass == 11) {
+            mplane[nodes + j] = key_value(khi);
+            mtie[nodes + j] = (int32_t)klo;
+        }
+    }
+}
+
 }  // namespace
 
 // One level's node pass: payload A of every node (and B at the leaf level)
@@ -911,7 +1106,7 @@ static rcb_status level_pass(rcb_tree *t, BuildScratch &b, const NodeOut &o, con
         k_big_finalize<1><<<blocks_for_waves(bw), kBlock, 0, s>>>(leaf, split, o, bc, b.part);
         RCB_LAUNCH_CHECK("k_big_finalize<1>");
     } else if (split) {
-        k_part_count<<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part_left);
+        k_part_count<<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, id, o, bc, b.part_left);
         RCB_LAUNCH_CHECK("k_part_count");
         k_part_scan<<<blocks_for_waves(bw), kBlock, 0, s>>>(o, bc, b.part_left);
         RCB_LAUNCH_CHECK("k_part_scan");
@@ -990,8 +1185,27 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     RCB_LAUNCH_CHECK("k_bounds_final");
     k_set_root<<<1, 1, 0, s>>>(t->nfirst, t->ncount, (int32_t)n);
     RCB_LAUNCH_CHECK("k_set_root");
+    // median split: planes and ties per label, radix-select state for the
+    // levels whose nodes exceed kSelSmall (at most n / kSelSmall nodes)
+    const bool median = t->p.split == RCB_SPLIT_MEDIAN;
+    double *mplane = nullptr;
+    int32_t *mtie = nullptr;
+    MedSel ms{};
+    const int64_t max_sel = n / kSelSmall + 1;
+    if (median) {
+        mplane = (double *)A(sizeof(double) * t->nlab, tmp);
+        mtie = (int32_t *)A(sizeof(int32_t) * t->nlab, tmp);
+        ms.khi = (uint64_t *)A(sizeof(uint64_t) * max_sel, tmp);
+        ms.klo = (uint32_t *)A(sizeof(uint32_t) * max_sel, tmp);
+        ms.rank = (int32_t *)A(sizeof(int32_t) * max_sel, tmp);
+        ms.hist = (uint32_t *)A(sizeof(uint32_t) * 256 * max_sel, tmp);
+        for (void *p : {(void *)mplane, (void *)mtie, (void *)ms.khi, (void *)ms.klo, (void *)ms.rank,
+                        (void *)ms.hist})
+            if (!p) return RCB_ENOMEM;
+        RCB_HIP(hipMemsetAsync(ms.hist, 0, sizeof(uint32_t) * 256 * max_sel, s));
+    }
     NodeOut o{t->nfirst, t->ncount, t->nlo, t->nhi, t->ncom, t->nM, t->nhint, t->nhnode, t->nQ,
-              b.naxis, b.nplane};
+              b.naxis, b.nplane, mplane, mtie};
     BigCtl bc{b.ctl, b.big_node, b.big_base, b.item_big};
     int cur = 0;
     const int64_t item_waves = b.max_items;
@@ -1005,7 +1219,26 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         PartIn in{b.x[cur], b.y[cur], b.z[cur], b.m[cur], t->ph};
         int32_t *id_next = leaf ? nullptr : t->lvl_id + (int64_t)(lvl + 1) * n;
         PartOut out{b.x[cur ^ 1], b.y[cur ^ 1], b.z[cur ^ 1], b.m[cur ^ 1], id_next};
-        rcb_status st = level_pass(t, b, o, bc, lvl, true, in, t->lvl_id + (int64_t)lvl * n, out, s);
+        const int32_t *id_cur = t->lvl_id + (int64_t)lvl * n;
+        if (median && !leaf) {
+            const int64_t nodes = (int64_t)1 << lvl;
+            const int64_t cmax = (n + nodes - 1) / nodes;   // ceil(n / 2^lvl): the largest node
+            if (cmax <= kSelSmall) {
+                k_median_small<<<(unsigned)nodes, kWave, 0, s>>>(lvl, in, id_cur, o, mplane, mtie, t->dflag + 5);
+                RCB_LAUNCH_CHECK("k_median_small");
+            } else {
+                const int cpn = (int)((cmax + kChunk - 1) / kChunk);
+                k_msel_init<<<(unsigned)((nodes + 255) / 256), 256, 0, s>>>(lvl, o, ms);
+                RCB_LAUNCH_CHECK("k_msel_init");
+                for (int pass = 0; pass < 12; ++pass) {
+                    k_msel_hist<<<blocks_for_waves(nodes * cpn), kBlock, 0, s>>>(lvl, cpn, pass, in, id_cur, o, ms);
+                    RCB_LAUNCH_CHECK("k_msel_hist");
+                    k_msel_pick<<<blocks_for_waves(nodes), kBlock, 0, s>>>(lvl, pass, ms, mplane, mtie);
+                    RCB_LAUNCH_CHECK("k_msel_pick");
+                }
+            }
+        }
+        rcb_status st = level_pass(t, b, o, bc, lvl, true, in, id_cur, out, s);
         if (st != RCB_OK) return st;
         if (!leaf) {
             cur ^= 1;

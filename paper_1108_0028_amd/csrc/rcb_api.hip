@@ -107,7 +107,7 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
         set_error("rcb_build: pure_mac must be 0 or 1");
         return RCB_EINVAL;
     }
-    if (p->split != RCB_SPLIT_MASS && p->split != RCB_SPLIT_NUMBER) {
+    if (p->split != RCB_SPLIT_MASS && p->split != RCB_SPLIT_NUMBER && p->split != RCB_SPLIT_MEDIAN) {
         set_error("rcb_build: unknown split");
         return RCB_EINVAL;
     }

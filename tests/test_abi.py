@@ -80,7 +80,7 @@ def test_build_rejects_bad_arguments_on_host(case):
     elif case == "pure_mac":
         p.pure_mac = 2
     elif case == "split":
-        p.split = 2
+        p.split = 3
     st = L.rcb_build(*ptrs, n, C.byref(p), None, outp)
     assert st == 1   # RCB_EINVAL
     assert L.rcb_last_error().decode().startswith("rcb_build")
