@@ -6,6 +6,10 @@
   kernel), with the near-pair and far-pair counts that split G.
 * ``accuracy``: the cumulative distribution of relative errors
   eps_i = |da_i| / |a_i| for theta from 0.4 to 1.0 (Fig. accuracy).
+* ``splits``: the three ways to cut a cell (centre of mass, centre of number,
+  median position; Sec. 2.1 "Load balancing") on the Sobol sphere and on an
+  unequal binary, where the median split creates "renegades": error
+  statistics and build time of each.
 
 Workload: a quasi-random Sobol sphere (500,000 particles, smoothing lengths
 for ~105 neighbours, as in Table 1). The reference accelerations are the FP64
@@ -15,6 +19,7 @@ table and one JSON line per row.
 
     python sweeps.py table1 [--n 500000] [--precision fp64]
     python sweeps.py accuracy [--pure-mac]
+    python sweeps.py splits
 """
 from __future__ import annotations
 
@@ -31,7 +36,7 @@ if ROOT not in sys.path:
 
 def _args():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["table1", "accuracy"])
+    ap.add_argument("what", choices=["table1", "accuracy", "splits"])
     ap.add_argument("--n", type=int, default=500_000)
     ap.add_argument("--neighbours", type=int, default=105)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
@@ -56,6 +61,9 @@ def main():
     dev = torch.device("cuda:0")
     cloud = W.sobol_sphere(a.n, a.neighbours)
     arrs = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in cloud.arrays()]
+
+    if a.what == "splits":
+        return splits(a, np, torch, W, Tree, dev)
 
     def run(n_ll, theta, prec, ev=None):
         rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
@@ -143,6 +151,36 @@ def main():
             print(f"| {th} | {e['P<1e-4']:.4f} | {e['P<1e-3']:.4f} | {e['P<2e-3']:.4f} | {e['P<1e-2']:.4f} | "
                   f"{e['mean']:.2e} | {e['p99']:.2e} | {e['max']:.2e} | {ph['G']:.2f} |", flush=True)
             print(json.dumps({"theta": th, "n_ll": a.n_ll, **ph, **e}), flush=True)
+
+
+def splits(a, np, torch, W, Tree, dev):
+    """Error against the direct sum (FP64 tree at theta = 0) and build time
+    for each split rule, FP64 form, theta = 0.7."""
+    print(f"| workload | split | build ms | mean eps | p99 | max | P<1e-2 |\n"
+          f"|---|---|---:|---:|---:|---:|---:|", flush=True)
+    for name, cloud, n_ll in (("sobol_sphere 500k", W.sobol_sphere(a.n, a.neighbours), 12),
+                              ("binary 3000 + 1000", W.binary_clumps(), 8)):
+        arrs = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in cloud.arrays()]
+        rt = Tree(*arrs, n_ll=n_ll, theta=0.0, precision="fp64")
+        ref = torch.stack(rt.gravity(), 1)
+        rt.destroy()
+        na = ref.norm(dim=1)
+        for split in ("mass", "number", "median"):
+            Tree(*arrs, n_ll=n_ll, theta=0.7, split=split).destroy()          # warm-up
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            t = Tree(*arrs, n_ll=n_ll, theta=0.7, split=split)
+            e1.record()
+            acc = torch.stack(t.gravity(), 1)
+            torch.cuda.synchronize()
+            eps = ((acc - ref).norm(dim=1) / na).cpu().numpy()
+            row = {"workload": name, "split": split, "build_ms": e0.elapsed_time(e1),
+                   "mean": float(eps.mean()), "p99": float(np.quantile(eps, 0.99)),
+                   "max": float(eps.max()), "P<1e-2": float((eps < 1e-2).mean())}
+            t.destroy()
+            print(f"| {name} | {split} | {row['build_ms']:.2f} | {row['mean']:.2e} | {row['p99']:.2e} | "
+                  f"{row['max']:.2e} | {row['P<1e-2']:.4f} |", flush=True)
+            print(json.dumps(row), flush=True)
 
 
 if __name__ == "__main__":
