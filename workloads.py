@@ -150,9 +150,20 @@ def clumpy_cube(n: int = 100_000_000, seed: int = SEED_BASE + 4,
     dens = np.where(inside, float(n_u), 0.0)
     norm = (2.0 * math.pi * sigma * sigma) ** -1.5
     cut = 8.0 * sigma
+    # particles binned on a grid of cells no smaller than the cut, so each
+    # clump only looks at the cells its cut box touches
+    G = max(1, int(1.0 / cut))
+    cell = lambda v: np.clip(np.floor(v * G), 0, G - 1).astype(np.int16)
+    key = (cell(x) * G + cell(y)) * G + cell(z)
+    order = np.argsort(key, kind="stable")
+    bounds = np.searchsorted(key[order], np.arange(G ** 3 + 1))
     for c in range(n_clumps):
         cx, cy, cz = centres[c]
-        sel = np.nonzero((np.abs(x - cx) < cut) & (np.abs(y - cy) < cut) & (np.abs(z - cz) < cut))[0]
+        lo = [int(np.clip(np.floor((v - cut) * G), 0, G - 1)) for v in (cx, cy, cz)]
+        hi = [int(np.clip(np.floor((v + cut) * G), 0, G - 1)) for v in (cx, cy, cz)]
+        cand = np.concatenate([order[bounds[(i * G + j) * G + lo[2]]:bounds[(i * G + j) * G + hi[2] + 1]]
+                               for i in range(lo[0], hi[0] + 1) for j in range(lo[1], hi[1] + 1)])
+        sel = cand[(np.abs(x[cand] - cx) < cut) & (np.abs(y[cand] - cy) < cut) & (np.abs(z[cand] - cz) < cut)]
         d2 = (x[sel] - cx) ** 2 + (y[sel] - cy) ** 2 + (z[sel] - cz) ** 2
         dens[sel] += per[c] * norm * np.exp(-0.5 * d2 / (sigma * sigma))
     dens = np.maximum(dens, 1.0)         # particles that strayed outside every component
