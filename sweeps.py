@@ -6,6 +6,11 @@
   kernel), with the near-pair and far-pair counts that split G.
 * ``accuracy``: the cumulative distribution of relative errors
   eps_i = |da_i| / |a_i| for theta from 0.4 to 1.0 (Fig. accuracy).
+* ``scaling``: build + walk + neighbours + gravity on the clumpy unit cube
+  (50% uniform, 64 Gaussian clumps) from 2^20 to 10^8 particles, mixed and
+  FP64 forms: particles/s per size (the O(N) claim of Sec. 3.2.3), with the
+  neighbour lists of sampled particles checked against an all-pairs search
+  and their accelerations against the direct sum over all particles.
 * ``splits``: the three ways to cut a cell (centre of mass, centre of number,
   median position; Sec. 2.1 "Load balancing") on the Sobol sphere and on an
   unequal binary, where the median split creates "renegades": error
@@ -20,6 +25,7 @@ table and one JSON line per row.
     python sweeps.py table1 [--n 500000] [--precision fp64]
     python sweeps.py accuracy [--pure-mac]
     python sweeps.py splits
+    python sweeps.py scaling [--sizes 1048576,...]
 """
 from __future__ import annotations
 
@@ -36,7 +42,9 @@ if ROOT not in sys.path:
 
 def _args():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["table1", "accuracy", "splits"])
+    ap.add_argument("what", choices=["table1", "accuracy", "splits", "scaling"])
+    ap.add_argument("--sizes", default="1048576,4194304,16777216,67108864,100000000")
+    ap.add_argument("--samples", type=int, default=256)
     ap.add_argument("--n", type=int, default=500_000)
     ap.add_argument("--neighbours", type=int, default=105)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
@@ -59,6 +67,8 @@ def main():
 
     assert torch.cuda.is_available(), "sweeps.py needs a GPU"
     dev = torch.device("cuda:0")
+    if a.what == "scaling":
+        return scaling(a, np, torch, W, Tree, dev)
     cloud = W.sobol_sphere(a.n, a.neighbours)
     arrs = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in cloud.arrays()]
 
@@ -181,6 +191,93 @@ def splits(a, np, torch, W, Tree, dev):
             print(f"| {name} | {split} | {row['build_ms']:.2f} | {row['mean']:.2e} | {row['p99']:.2e} | "
                   f"{row['max']:.2e} | {row['P<1e-2']:.4f} |", flush=True)
             print(json.dumps(row), flush=True)
+
+
+def _direct(torch, P, m, h, sel, chunk=1 << 17):
+    """Direct kernel-smoothed sum (Sec. 2.4.3: a -= m_b S(q)/r (r_a - r_b),
+    h_ab = (h_a + h_b)/2, q = r/h_ab) for the sinks `sel`, FP64, by chunks of
+    sources."""
+    out = torch.zeros(len(sel), 3, dtype=torch.float64, device=P.device)
+    pa, ha = P[sel], h[sel]
+    for s0 in range(0, P.shape[0], chunk):
+        pb, mb, hb = P[s0:s0 + chunk], m[s0:s0 + chunk], h[s0:s0 + chunk]
+        v = pa[:, None, :] - pb[None, :, :]
+        r2 = (v * v).sum(2)
+        r = r2.sqrt()
+        hab = 0.5 * (ha[:, None] + hb[None, :])
+        q = r / hab
+        inner = (4.0 / 3.0 - 1.2 * q * q + 0.5 * q ** 3) / hab ** 3
+        outer = (8.0 / 3.0 - 3.0 * q + 1.2 * q * q - q ** 3 / 6.0) / hab ** 3 - 1.0 / (15.0 * r2 * r)
+        newton = 1.0 / (r2 * r)
+        F = torch.where(q < 1.0, inner, torch.where(q < 2.0, outer, newton))
+        F = torch.where(r2 > 0.0, F, torch.zeros_like(F))
+        out -= ((mb[None, :] * F)[:, :, None] * v).sum(1)
+    return out
+
+
+def scaling(a, np, torch, W, Tree, dev):
+    print(f"| N | L | form | ms/step | build | walk | neighbours | gravity | particles/s | "
+          f"nb check | mean eps | max eps |\n|---:|---:|---|---:|---:|---:|---:|---:|---:|---|---:|---:|",
+          flush=True)
+    rng = np.random.default_rng(7)
+    for n in [int(v) for v in a.sizes.split(",")]:
+        t0 = time.perf_counter()
+        cloud = W.clumpy_cube(n)
+        print(f"[progress] generated N={n} in {time.perf_counter() - t0:.0f} s", flush=True)
+        arrs = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in cloud.arrays()]
+        del cloud
+        P = torch.stack(arrs[:3], 1)
+        sel = torch.from_numpy(np.sort(rng.choice(n, a.samples, replace=False))).to(dev)
+        ref = _direct(torch, P, arrs[3], arrs[4], sel)
+        torch.cuda.synchronize()
+        print(f"[progress] direct sum of {a.samples} sinks done", flush=True)
+        for prec in ("mixed", "fp64"):
+            def step(ev=None):
+                rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
+                rec(0)
+                t = Tree(*arrs, n_ll=12, theta=0.7, precision=prec)
+                rec(1)
+                t.walk()
+                rec(2)
+                off, ids = t.neighbours()
+                rec(3)
+                acc = t.gravity()
+                rec(4)
+                return t, off, ids, acc
+            t, off, ids, acc = step()            # warm-up; its outputs are checked
+            k = t.info()["k"]
+            # neighbours of 32 sampled particles against an all-pairs search
+            ok = True
+            for i in sel[:32].tolist():
+                dx, dy, dz = P[:, 0] - P[i, 0], P[:, 1] - P[i, 1], P[:, 2] - P[i, 2]
+                d2 = (dx * dx + dy * dy) + dz * dz          # the kernels' order, no fused multiply-add
+                lim = (2.0 * arrs[4][i]) ** 2
+                exact = torch.nonzero((d2 < lim) & (torch.arange(n, device=dev) != i)).flatten()
+                got = ids[off[i]:off[i + 1]].long()
+                ok &= bool(torch.equal(torch.sort(got).values, exact))
+            am = torch.stack([v.double() for v in acc], 1)[sel]
+            eps = ((am - ref).norm(dim=1) / ref.norm(dim=1)).cpu().numpy()
+            t.destroy()
+            del off, ids, acc
+            rows = []
+            for _ in range(3):
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+                torch.cuda.synchronize()
+                w0 = time.perf_counter()
+                t, _, _, _ = step(ev)
+                torch.cuda.synchronize()
+                rows.append([time.perf_counter() - w0] + [ev[j].elapsed_time(ev[j + 1]) for j in range(4)])
+                t.destroy()
+            med = np.median(np.array(rows), 0)
+            row = {"n": n, "L": k, "form": prec, "ms_per_step": med[0] * 1e3, "build": med[1], "walk": med[2],
+                   "neighbours": med[3], "gravity": med[4], "particles_per_s": n / med[0],
+                   "neighbours_match": ok, "mean_eps": float(eps.mean()), "max_eps": float(eps.max())}
+            print(f"| {n} | {k} | {prec} | {row['ms_per_step']:.1f} | {med[1]:.1f} | {med[2]:.1f} | {med[3]:.1f} | "
+                  f"{med[4]:.1f} | {row['particles_per_s']:.3g} | {'identical' if ok else 'DIFFER'} | "
+                  f"{row['mean_eps']:.2e} | {row['max_eps']:.2e} |", flush=True)
+            print(json.dumps(row), flush=True)
+        del arrs, P, ref
+        torch.cuda.empty_cache()
 
 
 if __name__ == "__main__":
