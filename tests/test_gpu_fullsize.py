@@ -89,3 +89,40 @@ def test_vjp_properties_1m(precision):
     euler = float((m * dm.double()).sum())
     assert abs(euler - L) <= tol * float((m * dm.double()).abs().sum()), (euler, L)
     gt.destroy()
+
+
+def test_clumpy_cube_1e8_properties():
+    """10^8 particles (the scaling workload's largest size), mixed and FP64:
+    the neighbour lists of sampled particles equal an all-pairs search over
+    all particles, and the two forms agree within the mixed form's bar on
+    sampled particles (each form is checked against the oracle at the sizes
+    above)."""
+    import torch
+    from paper_1108_0028_amd import Tree
+    n = 100_000_000
+    c = W.clumpy_cube(n)
+    _say("clumpy cube", n)
+    dev = torch.device("cuda:0")
+    arrs = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in c.arrays()]
+    del c
+    rng = np.random.default_rng(8)
+    sel = torch.from_numpy(np.sort(rng.choice(n, 4096, replace=False))).to(dev)
+    acc = {}
+    for prec in ("mixed", "fp64"):
+        t = Tree(*arrs, n_ll=12, theta=0.7, precision=prec)
+        assert t.info()["k"] == 23
+        off, ids = t.neighbours()
+        if prec == "mixed":
+            x, y, z, h = arrs[0], arrs[1], arrs[2], arrs[4]
+            for i in sel[:24].tolist():
+                dx, dy, dz = x - x[i], y - y[i], z - z[i]
+                d2 = (dx * dx + dy * dy) + dz * dz
+                exact = torch.nonzero((d2 < (2.0 * h[i]) ** 2) & (torch.arange(n, device=dev) != i)).flatten()
+                got = ids[int(off[i]):int(off[i + 1])].long()
+                assert torch.equal(torch.sort(got).values, exact), i
+        del off, ids
+        acc[prec] = torch.stack([v.double() for v in t.gravity()], 1)[sel].cpu().numpy()
+        t.destroy()
+        torch.cuda.empty_cache()
+    g = gate(acc["mixed"], acc["fp64"])
+    assert g <= TOL["mixed"], g
