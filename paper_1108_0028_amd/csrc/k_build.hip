@@ -64,14 +64,32 @@ __global__ __launch_bounds__(kBlock) void k_bounds_partial(const double *__restr
     }
 }
 
-__global__ void k_bounds_final(const double *__restrict__ part, int nb, double *__restrict__ nlo,
-                               double *__restrict__ nhi) {
-    int d = threadIdx.x;
-    if (d >= 6) return;
-    double r = part[d];
-    for (int b = 1; b < nb; ++b) r = d < 3 ? fmin(r, part[6 * b + d]) : fmax(r, part[6 * b + d]);
-    if (d < 3) nlo[3 + d] = r;   // label 1
-    else nhi[3 + d - 3] = r;
+// one block of 256 threads: per-thread minima / maxima over the partials,
+// then a tree over the block (min and max do not depend on the order)
+__global__ __launch_bounds__(256) void k_bounds_final(const double *__restrict__ part, int nb,
+                                                      double *__restrict__ nlo, double *__restrict__ nhi) {
+    __shared__ double red[6][256];
+    const int t = threadIdx.x;
+    double r[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) r[d] = part[d];
+    for (int b = t; b < nb; b += 256) {
+#pragma unroll
+        for (int d = 0; d < 6; ++d) r[d] = d < 3 ? fmin(r[d], part[6 * b + d]) : fmax(r[d], part[6 * b + d]);
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) red[d][t] = r[d];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d)
+                red[d][t] = d < 3 ? fmin(red[d][t], red[d][t + w]) : fmax(red[d][t], red[d][t + w]);
+        }
+        __syncthreads();
+    }
+    if (t < 3) nlo[3 + t] = red[t][0];   // label 1
+    else if (t < 6) nhi[3 + t - 3] = red[t][0];
 }
 
 __global__ void k_validate(const double *__restrict__ x, const double *__restrict__ y,
@@ -651,17 +669,24 @@ __global__ __launch_bounds__(kBlock) void k_chunk_reduce(PartIn in, NodeOut o, B
     if (l == 7) part[8 * w + 7] = mx;
 }
 
-// Canonical combination of a big node's chunk sums: groups of 64 chunks are
-// summed across lanes, then the group sums enter a binary-counter stack
-// (LDS) that merges equal-size neighbours left + right; the group count is
-// padded with zero groups to a power of two.
+// Canonical combination of a big node's chunk sums, one block of kFinWaves
+// waves per big node. Groups of 64 chunks are summed across lanes (an
+// adjacent-pair butterfly); the group count is padded with zero groups to a
+// power of two gp, and wave w merges the aligned block of gp / kFinWaves
+// groups it owns with a binary-counter stack (equal-size neighbours, left +
+// right); the wave results are then merged pairwise. Every step combines
+// aligned neighbours, so the result is the canonical pairwise sum.
+constexpr int kFinWaves = 16;
+
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_big_finalize(int leaf_level, int split, NodeOut o, BigCtl bc,
-                                                         const double *__restrict__ part) {
+__global__ __launch_bounds__(kFinWaves * kWave) void k_big_finalize(int leaf_level, int split, NodeOut o,
+                                                                    BigCtl bc,
+                                                                    const double *__restrict__ part) {
     constexpr int NS = Pay<P>::NS;
-    __shared__ double stk[kWavesPerBlock][32][NS];
+    __shared__ double stk[kFinWaves][32][NS];
+    __shared__ double res[kFinWaves][NS + 1];
     const int wv = threadIdx.x / kWave;
-    const int64_t bi = wave_index();
+    const int64_t bi = blockIdx.x;
     if (bi >= bc.ctl[0]) return;
     const int64_t lab = bc.big_node[bi];
     const int64_t base = bc.big_base[bi];
@@ -670,36 +695,61 @@ __global__ __launch_bounds__(kBlock) void k_big_finalize(int leaf_level, int spl
     const int64_t ngroups = (nch + kWave - 1) / kWave;
     int64_t gp = 1;
     while (gp < ngroups) gp <<= 1;
-    double mx = -1.0;
-    for (int64_t gi = 0; gi < gp; ++gi) {
-        const int64_t j = gi * kWave + lane_id();
-        double v[NS];
-        const bool ok = j < nch;
+    const int64_t per = gp >= kFinWaves ? gp / kFinWaves : 1;   // groups per wave
+    const int active = gp >= kFinWaves ? kFinWaves : (int)gp;
+    if (wv < active) {
+        double mx = -1.0;
+        for (int64_t k = 0; k < per; ++k) {
+            const int64_t gi = wv * per + k;
+            const int64_t j = gi * kWave + lane_id();
+            double v[NS];
+            const bool ok = j < nch;
 #pragma unroll
-        for (int q = 0; q < NS; ++q) v[q] = ok ? part[8 * (base + j) + q] : 0.0;
-        if (ok) mx = fmax(mx, part[8 * (base + j) + 7]);
+            for (int q = 0; q < NS; ++q) v[q] = ok ? part[8 * (base + j) + q] : 0.0;
+            if (ok) mx = fmax(mx, part[8 * (base + j) + 7]);
 #pragma unroll
-        for (int q = 0; q < NS; ++q) v[q] = wave_sum(v[q]);
-        int L = 0;
-        while ((gi >> L) & 1) {
+            for (int q = 0; q < NS; ++q) v[q] = wave_sum(v[q]);
+            int L = 0;
+            while ((k >> L) & 1) {
 #pragma unroll
-            for (int q = 0; q < NS; ++q) v[q] = stk[wv][L][q] + v[q];
-            ++L;
+                for (int q = 0; q < NS; ++q) v[q] = stk[wv][L][q] + v[q];
+                ++L;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane_id() == 0) {
+#pragma unroll
+                for (int q = 0; q < NS; ++q) stk[wv][L][q] = v[q];
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
-        __builtin_amdgcn_wave_barrier();
+        int top = 0;
+        while ((1ll << top) < per) ++top;
+        mx = wave_max(mx);
         if (lane_id() == 0) {
 #pragma unroll
-            for (int q = 0; q < NS; ++q) stk[wv][L][q] = v[q];
+            for (int q = 0; q < NS; ++q) res[wv][q] = stk[wv][top][q];
+            res[wv][NS] = mx;
+        }
+    }
+    __syncthreads();
+    if (wv != 0) return;
+    // pairwise over the active waves' results (a power of two of them)
+    double s[NS];
+    double mx = -1.0;
+    for (int w = 0; w < active; ++w) mx = fmax(mx, res[w][NS]);
+    for (int width = 1; width < active; width <<= 1) {
+        __builtin_amdgcn_wave_barrier();
+        if (lane_id() == 0) {
+            for (int w = 0; w + width < active; w += 2 * width)
+#pragma unroll
+                for (int q = 0; q < NS; ++q) res[w][q] = res[w][q] + res[w + width][q];
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
-    int top = 0;
-    while ((1ll << top) < gp) ++top;
-    double s[NS];
 #pragma unroll
-    for (int q = 0; q < NS; ++q) s[q] = stk[wv][top][q];
-    mx = wave_max(mx);
+    for (int q = 0; q < NS; ++q) s[q] = res[0][q];
     if constexpr (P == 0) {
         finish_a(o, lab, leaf_level != 0, s, mx, split != 0);
     } else {
@@ -732,27 +782,44 @@ __global__ __launch_bounds__(kBlock) void k_part_count(PartIn in, const int32_t 
     if (lane_id() == 0) part_left[w] = nl;
 }
 
-__global__ __launch_bounds__(kBlock) void k_part_scan(NodeOut o, BigCtl bc,
-                                                      int32_t *__restrict__ part_left) {
-    const int64_t bi = wave_index();
+// exclusive offsets of a big node's chunk left-counts, one block of
+// kFinWaves waves per big node: each wave scans a contiguous run of chunks
+// after an exclusive scan of the waves' totals
+__global__ __launch_bounds__(kFinWaves * kWave) void k_part_scan(NodeOut o, BigCtl bc,
+                                                                 int32_t *__restrict__ part_left) {
+    __shared__ int64_t tot[kFinWaves];
+    const int wv = threadIdx.x / kWave;
+    const int64_t bi = blockIdx.x;
     if (bi >= bc.ctl[0]) return;
     const int64_t lab = bc.big_node[bi];
     const int64_t base = bc.big_base[bi];
     const int64_t s = o.nfirst[lab], c = o.ncount[lab];
     const int64_t nch = (c + kChunk - 1) / kChunk;
-    int64_t run = 0;
-    for (int64_t g0 = 0; g0 < nch; g0 += kWave) {
+    const int64_t seg = (nch + kFinWaves - 1) / kFinWaves;
+    const int64_t c0 = wv * seg, c1 = min(nch, c0 + seg);
+    int64_t mine = 0;
+    for (int64_t g0 = c0; g0 < c1; g0 += kWave) {
         const int64_t j = g0 + lane_id();
-        const int v = j < nch ? part_left[base + j] : 0;
+        mine += wave_sum_i(j < c1 ? part_left[base + j] : 0);
+    }
+    if (lane_id() == 0) tot[wv] = mine;
+    __syncthreads();
+    int64_t run = 0;
+    for (int w = 0; w < wv; ++w) run += tot[w];
+    for (int64_t g0 = c0; g0 < c1; g0 += kWave) {
+        const int64_t j = g0 + lane_id();
+        const int v = j < c1 ? part_left[base + j] : 0;
         const int e = wave_excl_scan(v);
-        if (j < nch) part_left[base + j] = (int32_t)(run + e);
+        if (j < c1) part_left[base + j] = (int32_t)(run + e);
         run += wave_sum_i(v);
     }
-    if (lane_id() == 0) {
+    if (wv == kFinWaves - 1 && lane_id() == 0) {
+        int64_t all = 0;
+        for (int w = 0; w < kFinWaves; ++w) all += tot[w];
         o.nfirst[2 * lab] = (int32_t)s;
-        o.ncount[2 * lab] = (int32_t)run;
-        o.nfirst[2 * lab + 1] = (int32_t)(s + run);
-        o.ncount[2 * lab + 1] = (int32_t)(c - run);
+        o.ncount[2 * lab] = (int32_t)all;
+        o.nfirst[2 * lab + 1] = (int32_t)(s + all);
+        o.ncount[2 * lab + 1] = (int32_t)(c - all);
     }
 }
 
@@ -821,7 +888,9 @@ __global__ void k_records(int64_t nlab, NodeOut o, double4 *__restrict__ rec) {
     rec[2 * lab + 1] = make_double4(o.ncom[3 * lab], o.ncom[3 * lab + 1], o.ncom[3 * lab + 2], hb);
 }
 
-// mixed form: FP32 offsets from the leaf centre of mass, FP32 m and h
+// mixed form: FP32 offsets from the leaf centre of mass, FP32 m and h. One
+// wave per 8 consecutive leaves (their particles are contiguous): a lane's
+// leaf is the last of the 8 whose first position is <= its own.
 __global__ void k_mixed_prep(int64_t nleaf, const int32_t *__restrict__ nfirst,
                              const int32_t *__restrict__ ncount, const double *__restrict__ ncom,
                              const double *__restrict__ px, const double *__restrict__ py,
@@ -830,14 +899,22 @@ __global__ void k_mixed_prep(int64_t nleaf, const int32_t *__restrict__ nfirst,
                              float *__restrict__ fdy, float *__restrict__ fdz,
                              float *__restrict__ fm, float *__restrict__ fh) {
     const int64_t w = wave_index();
-    if (w >= nleaf) return;
-    const int64_t lab = nleaf + w;
-    const int64_t s = nfirst[lab], c = ncount[lab];
-    const double cx = ncom[3 * lab], cy = ncom[3 * lab + 1], cz = ncom[3 * lab + 2];
-    for (int64_t i = s + lane_id(); i < s + c; i += kWave) {
-        fdx[i] = (float)(px[i] - cx);
-        fdy[i] = (float)(py[i] - cy);
-        fdz[i] = (float)(pz[i] - cz);
+    const int64_t L0 = 8 * w;
+    if (L0 >= nleaf) return;
+    const int nl = nleaf - L0 < 8 ? (int)(nleaf - L0) : 8;
+    int32_t f[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) f[j] = j < nl ? nfirst[nleaf + L0 + j] : INT32_MAX;
+    const int64_t s = f[0];
+    const int64_t e = (int64_t)nfirst[nleaf + L0 + nl - 1] + ncount[nleaf + L0 + nl - 1];
+    for (int64_t i = s + lane_id(); i < e; i += kWave) {
+        int j = 0;
+#pragma unroll
+        for (int q = 1; q < 8; ++q) j += f[q] <= i;
+        const int64_t lab = nleaf + L0 + j;
+        fdx[i] = (float)(px[i] - ncom[3 * lab]);
+        fdy[i] = (float)(py[i] - ncom[3 * lab + 1]);
+        fdz[i] = (float)(pz[i] - ncom[3 * lab + 2]);
         fm[i] = (float)pm[i];
         fh[i] = (float)ph[i];
     }
@@ -1098,17 +1175,17 @@ static rcb_status level_pass(rcb_tree *t, BuildScratch &b, const NodeOut &o, con
     const int64_t bw = std::min<int64_t>(big_waves, nodes);
     k_chunk_reduce<0><<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part);
     RCB_LAUNCH_CHECK("k_chunk_reduce<0>");
-    k_big_finalize<0><<<blocks_for_waves(bw), kBlock, 0, s>>>(leaf, split, o, bc, b.part);
+    k_big_finalize<0><<<(unsigned)bw, kFinWaves * kWave, 0, s>>>(leaf, split, o, bc, b.part);
     RCB_LAUNCH_CHECK("k_big_finalize<0>");
     if (leaf) {
         k_chunk_reduce<1><<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part);
         RCB_LAUNCH_CHECK("k_chunk_reduce<1>");
-        k_big_finalize<1><<<blocks_for_waves(bw), kBlock, 0, s>>>(leaf, split, o, bc, b.part);
+        k_big_finalize<1><<<(unsigned)bw, kFinWaves * kWave, 0, s>>>(leaf, split, o, bc, b.part);
         RCB_LAUNCH_CHECK("k_big_finalize<1>");
     } else if (split) {
         k_part_count<<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, id, o, bc, b.part_left);
         RCB_LAUNCH_CHECK("k_part_count");
-        k_part_scan<<<blocks_for_waves(bw), kBlock, 0, s>>>(o, bc, b.part_left);
+        k_part_scan<<<(unsigned)bw, kFinWaves * kWave, 0, s>>>(o, bc, b.part_left);
         RCB_LAUNCH_CHECK("k_part_scan");
         k_part_scatter<<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, id, out, o, bc,
                                                                        b.part_left);
@@ -1181,7 +1258,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     RCB_LAUNCH_CHECK("k_init");
     k_bounds_partial<<<nbp, kBlock, 0, s>>>(x, y, z, n, b.bounds);
     RCB_LAUNCH_CHECK("k_bounds_partial");
-    k_bounds_final<<<1, 64, 0, s>>>(b.bounds, nbp, t->nlo, t->nhi);
+    k_bounds_final<<<1, 256, 0, s>>>(b.bounds, nbp, t->nlo, t->nhi);
     RCB_LAUNCH_CHECK("k_bounds_final");
     k_set_root<<<1, 1, 0, s>>>(t->nfirst, t->ncount, (int32_t)n);
     RCB_LAUNCH_CHECK("k_set_root");
@@ -1270,7 +1347,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         t->fm = (float *)A(sizeof(float) * n, t->allocs);
         t->fh = (float *)A(sizeof(float) * n, t->allocs);
         if (!t->fdx || !t->fdy || !t->fdz || !t->fm || !t->fh) return RCB_ENOMEM;
-        k_mixed_prep<<<blocks_for_waves(t->nleaf), kBlock, 0, s>>>(
+        k_mixed_prep<<<blocks_for_waves((t->nleaf + 7) / 8), kBlock, 0, s>>>(
             t->nleaf, t->nfirst, t->ncount, t->ncom, t->px, t->py, t->pz, t->pm, t->ph, t->fdx,
             t->fdy, t->fdz, t->fm, t->fh);
         RCB_LAUNCH_CHECK("k_mixed_prep");
@@ -1359,7 +1436,7 @@ rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const dou
     k_records<<<(unsigned)((t->nlab + 255) / 256), 256, 0, s>>>(t->nlab, o, t->wrec);
     RCB_LAUNCH_CHECK("k_records");
     if (t->p.precision == RCB_MIXED) {
-        k_mixed_prep<<<blocks_for_waves(t->nleaf), kBlock, 0, s>>>(
+        k_mixed_prep<<<blocks_for_waves((t->nleaf + 7) / 8), kBlock, 0, s>>>(
             t->nleaf, t->nfirst, t->ncount, t->ncom, t->px, t->py, t->pz, t->pm, t->ph, t->fdx,
             t->fdy, t->fdz, t->fm, t->fh);
         RCB_LAUNCH_CHECK("k_mixed_prep");
