@@ -34,6 +34,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kAdj = 10;    // M, R(3), Q(6)
+constexpr int kAdjCopies = 8;   // node-adjoint copies filled by k_vjp_far
 constexpr int kAcc = 30;    // G0(3), G1(9), G2(18) while accumulating
 constexpr int kMom = 23;    // S1(3), S2(6), S3(10), t1, sg(3): far_math.h SymMoments
 constexpr int kLeafC = 22;  // 19 far coefficients + cot(3)
@@ -219,8 +220,11 @@ __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
             }
         }
         if (emask) {
+            // each of the kAdjCopies copies takes the blocks of one residue
+            // mod kAdjCopies, i.e. of one XCD under round-robin dispatch
+            double *adj = a.adj + (int64_t)(blockIdx.x % kAdjCopies) * kAdj * a.nlab;
 #pragma unroll
-            for (int q = 0; q < kAdj; ++q) atomicAdd(a.adj + q * a.nlab + B, ad[q]);
+            for (int q = 0; q < kAdj; ++q) atomicAdd(adj + q * a.nlab + B, ad[q]);
         }
     }
     tile_sync();
@@ -465,6 +469,15 @@ __global__ __launch_bounds__(kBlock) void k_vjp_push(VjpArgs a, const double *__
     }
 }
 
+// node adjoints: the copies summed into the first (fixed order)
+__global__ void k_adj_reduce(double *__restrict__ adj, int64_t len) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    double v = adj[i];
+    for (int c = 1; c < kAdjCopies; ++c) v += adj[(int64_t)c * len + i];
+    adj[i] = v;
+}
+
 }  // namespace
 
 rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *gz, void *dx,
@@ -475,12 +488,12 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     const int64_t n = t->n;
     double *sink = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
     double *src = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
-    double *adj = (double *)dalloc(t, sizeof(double) * kAdj * t->nlab, s, tmp);
+    double *adj = (double *)dalloc(t, sizeof(double) * kAdjCopies * kAdj * t->nlab, s, tmp);
     double *mom = (double *)dalloc(t, sizeof(double) * kMom * t->nleaf, s, tmp);
     double *leafc = (double *)dalloc(t, sizeof(double) * kLeafC * t->nleaf, s, tmp);
     if (!sink || !src || !adj || !mom || !leafc) return RCB_ENOMEM;
     RCB_HIP(hipMemsetAsync(src, 0, sizeof(double) * 4 * n, s));
-    RCB_HIP(hipMemsetAsync(adj, 0, sizeof(double) * kAdj * t->nlab, s));
+    RCB_HIP(hipMemsetAsync(adj, 0, sizeof(double) * kAdjCopies * kAdj * t->nlab, s));
     VjpArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
               t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
               t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, src, adj, n, t->nlab};
@@ -494,6 +507,9 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
 
     k_vjp_far<<<gridg, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_vjp_far");
+    const int64_t alen = kAdj * t->nlab;
+    k_adj_reduce<<<(unsigned)((alen + 255) / 256), 256, 0, s>>>(adj, alen);
+    RCB_LAUNCH_CHECK("k_adj_reduce");
     if (mixed) k_vjp_near<true><<<gridg, kBlock, 0, s>>>(a);
     else k_vjp_near<false><<<gridg, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_vjp_near");
