@@ -17,6 +17,8 @@
 // combines the chunk sums, and the partition runs as count / scan / scatter
 // over the same chunks. Kernels are HBM-bound: each level reads 32 B and
 // writes 36 B per particle.
+#include <type_traits>
+
 #include "rcb_internal.h"
 
 namespace rcb {
@@ -516,7 +518,8 @@ __device__ __forceinline__ void level_node(int64_t lab, bool leaf, bool split, c
 
 // One node per wave: every node of the level, or (packed levels) the nodes of
 // the groups of npg nodes that k_level_packed left to it (group indices).
-__global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level, int split, PartIn in,
+template <bool LEAF>
+__global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int split, PartIn in,
                                                         const int32_t *__restrict__ id,
                                                         PartOut out, NodeOut o, BigCtl bc,
                                                         const int32_t *__restrict__ groups, int npg) {
@@ -529,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level,
     }
     if (j >= nodes) return;
     __shared__ double stage_all[kWavesPerBlock][kStage];
-    level_node(nodes + j, leaf_level != 0, split != 0, in, id, out, o, bc, stage_all[threadIdx.x / kWave]);
+    level_node(nodes + j, LEAF, split != 0, in, id, out, o, bc, stage_all[threadIdx.x / kWave]);
 }
 
 // Deep levels: 64 / GW nodes per wave, one per GW-lane group, when all of
@@ -537,8 +540,8 @@ __global__ __launch_bounds__(kBlock) void k_level_small(int lvl, int leaf_level,
 // k_level_small). Lane j of a group holds the node's elements [8 j, 8 j + 8);
 // the stable partition ranks come from a scan of the lanes' left counts
 // within the group.
-template <int GW>
-__global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int leaf_level, int split, PartIn in,
+template <int GW, bool LEAF>
+__global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int split, PartIn in,
                                                          const int32_t *__restrict__ id,
                                                          PartOut out, NodeOut o, BigCtl bc,
                                                          int32_t *__restrict__ groups) {
@@ -546,7 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int leaf_level
     const int64_t w = wave_index();
     const int64_t nodes = (int64_t)1 << lvl;
     if (w * kPack >= nodes) return;
-    const bool leaf = leaf_level != 0;
+    constexpr bool leaf = LEAF;
     const int lane = lane_id();
     const int gslot = lane / GW, gl = lane % GW;
     const int64_t j = w * kPack + gslot;
@@ -1154,22 +1157,32 @@ static rcb_status level_pass(rcb_tree *t, BuildScratch &b, const NodeOut &o, con
     if (gw) {
         const int npg = kWave / gw;
         const int64_t ng = (nodes + npg - 1) / npg;
-        if (gw == 8)
-            k_level_packed<8><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, leaf, split, in, id, out,
-                                                                       o, bc, b.pack_groups);
-        else if (gw == 16)
-            k_level_packed<16><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, leaf, split, in, id, out,
-                                                                        o, bc, b.pack_groups);
-        else
-            k_level_packed<32><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, leaf, split, in, id, out,
-                                                                        o, bc, b.pack_groups);
-        RCB_LAUNCH_CHECK("k_level_packed");
-        k_level_small<<<blocks_for_waves(ng * npg), kBlock, 0, s>>>(lvl, leaf, split, in, id, out, o,
-                                                                    bc, b.pack_groups, npg);
-        RCB_LAUNCH_CHECK("k_level_small<list>");
+        // the leaf level's kernels carry the quadrupole payload; the others
+        // are compiled without it (fewer registers)
+        auto packed = [&](auto leaf_c) {
+            constexpr bool L = decltype(leaf_c)::value;
+            if (gw == 8)
+                k_level_packed<8, L><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, split, in, id, out, o, bc,
+                                                                           b.pack_groups);
+            else if (gw == 16)
+                k_level_packed<16, L><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, split, in, id, out, o, bc,
+                                                                            b.pack_groups);
+            else
+                k_level_packed<32, L><<<blocks_for_waves(ng), kBlock, 0, s>>>(lvl, split, in, id, out, o, bc,
+                                                                            b.pack_groups);
+            k_level_small<L><<<blocks_for_waves(ng * npg), kBlock, 0, s>>>(lvl, split, in, id, out, o, bc,
+                                                                         b.pack_groups, npg);
+        };
+        if (leaf) packed(std::true_type{});
+        else packed(std::false_type{});
+        RCB_LAUNCH_CHECK("k_level_packed + k_level_small<list>");
     } else {
-        k_level_small<<<blocks_for_waves(nodes), kBlock, 0, s>>>(lvl, leaf, split, in, id, out, o, bc,
-                                                                 nullptr, 1);
+        if (leaf)
+            k_level_small<true><<<blocks_for_waves(nodes), kBlock, 0, s>>>(lvl, split, in, id, out, o, bc,
+                                                                         nullptr, 1);
+        else
+            k_level_small<false><<<blocks_for_waves(nodes), kBlock, 0, s>>>(lvl, split, in, id, out, o, bc,
+                                                                          nullptr, 1);
         RCB_LAUNCH_CHECK("k_level_small");
     }
     const int64_t bw = std::min<int64_t>(big_waves, nodes);
