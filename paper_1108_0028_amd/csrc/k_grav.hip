@@ -50,15 +50,17 @@ struct GravArgs {
 };
 
 // Far-field coefficients of the group's leaves into coef[8][19] (LDS).
-// The union far list is taken in windows of kFarWin entries. For each window
-// every leaf gets the list of the window positions whose mask has it
-// (ballot ranks, in list order); then lane (s, i) evaluates entries s, s + 8,
-// ... of leaf i's list, so a leaf's lanes only idle at the end of the window
-// rather than on every entry the leaf did not accept.
-constexpr int kFarWin = 256;
+// The union far list is taken in windows of kFarWin entries, whose node data
+// (centre of mass, mass, quadrupole) are staged in LDS by one coalesced pass.
+// For each window every leaf gets the list of the window positions whose mask
+// has it (ballot ranks, in list order); then lane (s, i) evaluates entries
+// s, s + 8, ... of leaf i's list, so a leaf's lanes only idle at the end of
+// the window rather than on every entry the leaf did not accept.
+constexpr int kFarWin = 64;
 struct FarWindow {
     int32_t lab[kFarWin];
     uint8_t idx[8][kFarWin];
+    double nd[kFarWin][10];
 };
 
 __device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, FarWindow &fw, double (*coef)[19]) {
@@ -83,6 +85,13 @@ __device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, FarWind
                 const uint64_t ent = g.gfar[w0 + p];
                 fw.lab[p] = (int32_t)((uint32_t)ent & 0x7fffffffu);
                 m = (uint32_t)(ent >> 32) & 0xffu;
+                const int64_t Bn = (uint32_t)ent & 0x7fffffffu;
+                fw.nd[p][0] = g.ncom[3 * Bn];
+                fw.nd[p][1] = g.ncom[3 * Bn + 1];
+                fw.nd[p][2] = g.ncom[3 * Bn + 2];
+                fw.nd[p][3] = g.nM[Bn];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) fw.nd[p][4 + q] = g.nQ[6 * Bn + q];
             }
 #pragma unroll
             for (int l = 0; l < 8; ++l) {
@@ -103,12 +112,11 @@ __device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, FarWind
         for (int r = 0; r < rounds; ++r) {
             const int k = 8 * r + slot;
             if (k < mine) {
-                const int64_t B = fw.lab[fw.idx[li][k]];
+                const double *nd = fw.nd[fw.idx[li][k]];
                 double qq[6];
 #pragma unroll
-                for (int q = 0; q < 6; ++q) qq[q] = g.nQ[6 * B + q];
-                m2l_accumulate(cA[0] - g.ncom[3 * B], cA[1] - g.ncom[3 * B + 1],
-                               cA[2] - g.ncom[3 * B + 2], g.nM[B], qq, c);
+                for (int q = 0; q < 6; ++q) qq[q] = nd[4 + q];
+                m2l_accumulate(cA[0] - nd[0], cA[1] - nd[1], cA[2] - nd[2], nd[3], qq, c);
             }
         }
         tile_sync();
