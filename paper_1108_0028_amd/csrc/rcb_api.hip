@@ -2,7 +2,10 @@
 // host, tree lifetime, stream-ordered device memory.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
+#include <vector>
 
 #include "rcb_internal.h"
 
@@ -23,9 +26,42 @@ rcb_status hip_fail(hipError_t e, const char *what) {
 }
 
 // Stream-ordered allocation from the device's default pool, which keeps
-// freed memory for reuse (release threshold raised once per device).
+// freed memory for reuse (release threshold raised once per device). Blocks
+// of at least kCacheMin bytes are also kept by the library once freed and
+// handed out again for a request on the same device and stream that they fit
+// within a factor of two: allocating and freeing tens of GB through the pool
+// maps and unmaps memory on every tree at 10^8 particles. If an allocation
+// fails, the cached blocks are released and it is tried once more.
+namespace {
+constexpr size_t kCacheMin = (size_t)1 << 30;
+struct CachedBlock {
+    void *p;
+    size_t bytes;
+    int device;
+    hipStream_t stream;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cached;                   // free, kept for reuse
+std::unordered_map<void *, CachedBlock> g_large;     // large blocks in use
+
+void release_cached(int device) {
+    std::vector<hipStream_t> streams;
+    for (auto it = g_cached.begin(); it != g_cached.end();) {
+        if (it->device == device) {
+            (void)hipFreeAsync(it->p, it->stream);
+            streams.push_back(it->stream);
+            it = g_cached.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    for (hipStream_t st : streams) (void)hipStreamSynchronize(st);
+}
+}  // namespace
+
 void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owner) {
     static bool pool_set[64] = {false};
+    std::lock_guard<std::mutex> lock(g_cache_mu);
     if (t->device >= 0 && t->device < 64 && !pool_set[t->device]) {
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, t->device) == hipSuccess) {
@@ -36,21 +72,57 @@ void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owne
     }
     void *p = nullptr;
     if (bytes == 0) bytes = 16;
+    if (bytes >= kCacheMin) {
+        size_t best = SIZE_MAX;
+        auto pick = g_cached.end();
+        for (auto it = g_cached.begin(); it != g_cached.end(); ++it)
+            if (it->device == t->device && it->stream == s && it->bytes >= bytes && it->bytes <= 2 * bytes &&
+                it->bytes < best) {
+                best = it->bytes;
+                pick = it;
+            }
+        if (pick != g_cached.end()) {
+            p = pick->p;
+            g_large[p] = *pick;
+            g_cached.erase(pick);
+            owner.push_back(p);
+            return p;
+        }
+    }
     hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess && !g_cached.empty()) {
+        (void)hipGetLastError();
+        release_cached(t->device);
+        e = hipMallocAsync(&p, bytes, s);
+    }
     if (e != hipSuccess) {
         set_error(std::string("hipMallocAsync(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
         (void)hipGetLastError();
         p = nullptr;
+    } else if (bytes >= kCacheMin) {
+        g_large[p] = CachedBlock{p, bytes, t->device, s};
     }
     owner.push_back(p);
     return p;
 }
 
+void dfree(void *p, hipStream_t s) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto it = g_large.find(p);
+    if (it != g_large.end()) {
+        CachedBlock b = it->second;
+        b.stream = s;   // later work on s is ordered after its last use
+        g_large.erase(it);
+        g_cached.push_back(b);
+        return;
+    }
+    (void)hipFreeAsync(p, s);
+}
+
 static void free_all(rcb_tree *t) {
-    for (void *p : t->list_allocs)
-        if (p) (void)hipFreeAsync(p, t->stream);
-    for (void *p : t->allocs)
-        if (p) (void)hipFreeAsync(p, t->stream);
+    for (void *p : t->list_allocs) dfree(p, t->stream);
+    for (void *p : t->allocs) dfree(p, t->stream);
     t->list_allocs.clear();
     t->allocs.clear();
     (void)hipStreamSynchronize(t->stream);
@@ -141,7 +213,7 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
             st = hipGetLastError() == hipSuccess ? RCB_OK : RCB_EHIP;
             if (st == RCB_OK) st = build_tree(t, x, y, z, ones, h, t->stream);
             if (st == RCB_OK) st = refresh_tree(t, x, y, z, m, h, t->stream);
-            hipFreeAsync(ones, t->stream);
+            dfree(ones, t->stream);
         }
     } else {
         st = build_tree(t, x, y, z, m, h, t->stream);
