@@ -49,6 +49,7 @@ def lib():
         L.orc_topology.argtypes = [P, i64p, i64p, i64p, i32p]
         L.orc_nodes.argtypes = [P, dp, dp, dp, dp, dp, dp, dp]
         L.orc_walk.argtypes = [P, C.c_double, i64p, C.c_int64, C.c_int]
+        L.orc_set_reading.argtypes = [P, C.c_int]
         L.orc_list_sizes.argtypes = [P, i64p, i64p, i64p]
         L.orc_leaf_lists.argtypes = [P, C.c_int64, i32p, i32p]
         L.orc_neighbours_count.argtypes = [P, i64p]
@@ -207,6 +208,12 @@ class OracleTree:
         lib().orc_neighbours_fill(self.ptr, _i64(off), _i32(ids))
         return off, ids[: int(off[-1])], valid
 
+    def set_reading(self, reading: str):
+        """Taylor coefficients of Eq. 6: "A" (J, H of the full field, default)
+        or "B" (J, H of the monopole field only)."""
+        self.reading = reading
+        lib().orc_set_reading(self.ptr, {"A": 0, "B": 1}[reading])
+
     def gravity(self):
         ax = np.zeros(self.n); ay = np.zeros(self.n); az = np.zeros(self.n)
         dp = C.POINTER(C.c_double)
@@ -214,6 +221,8 @@ class OracleTree:
         return ax, ay, az
 
     def vjp(self, gx, gy, gz):
+        if getattr(self, "reading", "A") != "A":
+            raise ValueError("the vector-Jacobian product is defined for reading A")
         g = [_d(a) for a in (gx, gy, gz)]
         out = [np.zeros(self.n) for _ in range(4)]
         dp = C.POINTER(C.c_double)

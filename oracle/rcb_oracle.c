@@ -93,6 +93,7 @@ typedef struct otree {
     double theta;
     int split;                     /* 0: centre of mass, 1: centre of number, 2: median */
     int pure_mac;                  /* walk mode of the last orc_walk */
+    int reading;                   /* Taylor coefficients: 0 = reading A, 1 = reading B */
     leaf_lists *lists;             /* one per leaf, index label - 2^k */
 } otree;
 
@@ -397,6 +398,9 @@ void orc_refresh(otree *t, const double *x, const double *y, const double *z,
 }
 
 int orc_k(const otree *t) { return t->k; }
+
+/* Taylor reading of the sink coefficients used by orc_gravity: 0 = A, 1 = B. */
+void orc_set_reading(otree *t, int reading) { t->reading = reading; }
 int64_t orc_n(const otree *t) { return t->n; }
 
 void orc_topology(const otree *t, int64_t *perm, int64_t *first, int64_t *count, int32_t *axis)
@@ -853,8 +857,13 @@ void orc_far_coeffs(double M, const double *q6, const double *R, double *f, doub
 }
 
 /* Sink-leaf expansion coefficients: sums over the far list of leaf A. */
+/* Sink coefficients of leaf A (Eq. 6). Reading A (default): J and H are the */
+/* Jacobian and Hessian of the monopole + quadrupole field f. Reading B (the  */
+/* order-consistent alternative): the quadrupole enters f only, J and H are  */
+/* those of the monopole field.                                              */
 static void leaf_far(const otree *t, int64_t A, const leaf_lists *L, double f[3], double J[9], double H[27])
 {
+    static const double no_quad[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     memset(f, 0, 3 * sizeof(double));
     memset(J, 0, 9 * sizeof(double));
     memset(H, 0, 27 * sizeof(double));
@@ -863,6 +872,10 @@ static void leaf_far(const otree *t, int64_t A, const leaf_lists *L, double f[3]
         double R[3], fb[3], Jb[9], Hb[27];
         for (int d = 0; d < 3; ++d) R[d] = t->com[3 * A + d] - t->com[3 * B + d];
         orc_far_coeffs(t->M[B], &t->Q[6 * B], R, fb, Jb, Hb, NULL);
+        if (t->reading == 1) {
+            double fm[3];
+            orc_far_coeffs(t->M[B], no_quad, R, fm, Jb, Hb, NULL);
+        }
         for (int i = 0; i < 3; ++i) f[i] += fb[i];
         for (int i = 0; i < 9; ++i) J[i] += Jb[i];
         for (int i = 0; i < 27; ++i) H[i] += Hb[i];
@@ -931,6 +944,10 @@ void orc_vjp(const otree *t, const double *gx, const double *gy, const double *g
     int64_t n = t->n, leaf0 = (int64_t)1 << t->k;
     const double *g[3] = {gx, gy, gz};
     double *dr[3] = {dx, dy, dz};
+    if (t->reading != 0) {          /* defined for reading A only */
+        for (int64_t i = 0; i < n; ++i) dx[i] = dy[i] = dz[i] = dm[i] = NAN;
+        return;
+    }
     for (int64_t i = 0; i < n; ++i) dx[i] = dy[i] = dz[i] = dm[i] = 0.0;
     int64_t L = t->nlab;
     double *adjM = (double *)calloc((size_t)L, sizeof(double));

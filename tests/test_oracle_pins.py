@@ -420,6 +420,44 @@ def test_theta_zero_equals_brute_force(n, nll, kind):
     assert np.abs(tq).max() < 1e-13 * scale * np.abs(P).max()
 
 
+def test_reading_b_changes_only_the_sink_expansion():
+    # Reading B keeps f and takes J, H from the monopole field: a particle alone
+    # in its cell sits at the cell's centre of mass (d = 0 up to the rounding
+    # of m x / m), where Eq. 6 is f alone, so both readings agree to rounding;
+    # the others differ by the quadrupole parts of J d + H[d, d] / 2.
+    c = W.small_random(3000, 77, "plummer")
+    t = O.OracleTree(*c.arrays(), n_ll=1)
+    t.walk(0.7)
+    t.set_reading("A")
+    aA = np.stack(t.gravity(), 1)
+    t.set_reading("B")
+    aB = np.stack(t.gravity(), 1)
+    topo = t.topology()
+    cnt = topo["count"][t.n_leaves:]
+    first = topo["first"][t.n_leaves:]
+    alone = topo["perm"][first[cnt == 1]]
+    shared = np.setdiff1d(np.arange(c.n), alone)
+    assert len(alone) > 100 and len(shared) > 100
+    np.testing.assert_allclose(aA[alone], aB[alone], rtol=1e-13, atol=1e-15 * np.abs(aA).max())
+    d = np.linalg.norm(aA[shared] - aB[shared], axis=1) / np.linalg.norm(aA[shared], axis=1)
+    assert np.count_nonzero(d) > len(shared) // 2 and d.max() < 0.05
+    with pytest.raises(ValueError):
+        t.vjp(*W.cotangents(c.n, seed=1))
+
+
+def test_reading_a_is_the_more_accurate_at_the_working_angles():
+    c = W.uniform_sphere()
+    t = O.OracleTree(*c.arrays(), n_ll=8)
+    ref = brute.direct_accel(c.x, c.y, c.z, c.m, c.h)
+    for th in (0.5, 0.7):
+        t.walk(th)
+        err = {}
+        for r in "AB":
+            t.set_reading(r)
+            err[r] = brute.error_stats(np.stack(t.gravity(), 1), ref)
+        assert err["A"]["mean"] < err["B"]["mean"] and err["A"]["p99"] < err["B"]["p99"], th
+
+
 def test_accuracy_on_uniform_sphere():
     # Sec. 3.1: error falls with theta; at theta = 0.5 on the homogeneous
     # sphere the mean relative error is well below 0.1%.
