@@ -66,6 +66,14 @@ typedef enum {
                                rcb_check_cells counts as outside (a rebuild is never missed) */
 } rcb_split;
 
+typedef enum {
+    RCB_READING_A = 0,      /* J and H of Eq. 6 are the Jacobian and Hessian of the monopole +
+                               quadrupole field f (Sec. 2.4.2 read literally; the default) */
+    RCB_READING_B = 1       /* the quadrupole enters f only; J and H are those of the monopole
+                               field (order-consistent alternative). rcb_gravity_vjp is defined
+                               for reading A only */
+} rcb_taylor_reading;
+
 typedef struct {
     int32_t n_ll;       /* average particles per lowest-level cell, Sec. 3.2.1 (paper: 12) */
     int32_t precision;  /* rcb_precision */
@@ -78,10 +86,11 @@ typedef struct {
                            cell; neighbour candidates are then the leaves reached
                            through reachable cells only */
     int32_t split;      /* rcb_split: where a cell is cut; moments always use the masses */
+    int32_t taylor_reading;   /* rcb_taylor_reading of the far-field sink coefficients */
 } rcb_params;
 
 /* Paper defaults: n_ll = 12, theta = 0.7, FP64, validate = 0, pure_mac = 0,
-   split = RCB_SPLIT_MASS. */
+   split = RCB_SPLIT_MASS, taylor_reading = RCB_READING_A. */
 void rcb_params_default(rcb_params *p);
 
 /*
@@ -171,7 +180,8 @@ rcb_status rcb_neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids
  * with h_ab = (h_a + h_b)/2, d_a = r_a - COM_A, and f_A, J_A, H_A the field,
  * Jacobian and Hessian at COM_A of the quadrupole expansions (Eq. 5) of the
  * cells accepted by the MAC H_B / R_AB < theta (reachable cells are never
- * accepted). ax, ay, az: n values, FP64 for RCB_FP64, FP32 for RCB_MIXED.
+ * accepted unless pure_mac; with RCB_READING_B, J_A and H_A of the monopole
+ * parts only). ax, ay, az: n values, FP64 for RCB_FP64, FP32 for RCB_MIXED.
  */
 rcb_status rcb_gravity(rcb_tree *t, void *ax, void *ay, void *az, void *stream);
 
@@ -182,6 +192,7 @@ rcb_status rcb_gravity(rcb_tree *t, void *ax, void *ay, void *az, void *stream);
  * writes dL/dx, dL/dy, dL/dz and dL/dm. h gets no gradient. Near-field pairs
  * are recomputed, not stored. g*: n values, d*: n values, FP64 for RCB_FP64
  * and FP32 for RCB_MIXED. Valid after rcb_build() (gravity need not have run).
+ * Errors: RCB_EINVAL (NULL argument, or a tree built with RCB_READING_B).
  */
 rcb_status rcb_gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *gz,
                            void *dx, void *dy, void *dz, void *dm, void *stream);

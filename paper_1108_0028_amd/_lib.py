@@ -25,7 +25,7 @@ STATUS = {0: "RCB_OK", 1: "RCB_EINVAL", 2: "RCB_ENOMEM", 3: "RCB_EHIP", 4: "RCB_
 class RcbParams(C.Structure):
     _fields_ = [("n_ll", C.c_int32), ("precision", C.c_int32), ("theta", C.c_double),
                 ("validate", C.c_int32), ("pure_mac", C.c_int32),
-                ("split", C.c_int32)]
+                ("split", C.c_int32), ("taylor_reading", C.c_int32)]
 
 
 class RcbTreeInfo(C.Structure):
@@ -110,10 +110,12 @@ class Tree:
     """An RCB tree built on the GPU (rcb_build) and its evaluations."""
 
     def __init__(self, x, y, z, m, h, n_ll: int = 12, theta: float = 0.7, precision: str = "fp64",
-                 validate: bool = False, pure_mac: bool = False, split: str = "mass"):
+                 validate: bool = False, pure_mac: bool = False, split: str = "mass",
+                 taylor_reading: str = "A"):
         """split: "mass" (planes through the centre of mass, the paper's),
         "number" (through the centre of number) or "median" (median position
-        split: equal halves)."""
+        split: equal halves). taylor_reading: "A" (J, H of the full field) or
+        "B" (J, H of the monopole field; no VJP)."""
         L = lib()
         arrs = [_dev(a, torch.float64, nm) for a, nm in zip((x, y, z, m, h), "xyzmh")]
         n = arrs[0].numel()
@@ -128,6 +130,7 @@ class Tree:
         p.validate = 1 if validate else 0
         p.pure_mac = 1 if pure_mac else 0
         p.split = {"mass": 0, "number": 1, "median": 2}[split]
+        p.taylor_reading = {"A": 0, "B": 1}[taylor_reading]
         self.precision = precision
         self.device = arrs[0].device
         self.n = n

@@ -87,6 +87,11 @@ RCB_HD constexpr int hidx(int i, int l, int m) {
 // into every diagonal component. Layout: f (0..2); J xx xy xz yy yz
 // without a1 (3..7); H xxx xxy xxz xyy xyz yyy yyz without the g terms
 // (8..14); sum g (15..17); sum a1 (18). m2l_finish expands it.
+//
+// RB (Taylor reading B): f as above, but J and H of the monopole field
+// alone, J_il = M g_il and H_ilm = M g_ilm, i.e. the same expressions with
+// Q = 0 in them (g = M D2 x, u = M D3 x / 3, a1 = M D1).
+template <bool RB = false>
 RCB_HD void m2l_accumulate(double x, double y, double z, double M, const double qq[6], double (&c)[19]) {
     const double X[3] = {x, y, z};
     const double r2 = (x * x + y * y) + z * z;
@@ -120,6 +125,22 @@ RCB_HD void m2l_accumulate(double x, double y, double z, double M, const double 
     for (int i = 0; i < 3; ++i) {
         c[i] += a1 * X[i];
         c[i] += c0 * q[i];
+    }
+    if constexpr (RB) {
+        const double gm = M * D2, um = third * (M * D3), am = M * D1;
+        for (int i = 0; i < 2; ++i)
+            for (int l = i; l < 3; ++l) c[3 + jidx(i, l)] += (gm * X[i]) * X[l];
+        constexpr int H7[7][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 1, 1}, {0, 1, 2}, {1, 1, 1}, {1, 1, 2}};
+        for (int t = 0; t < 7; ++t) {
+            const int i = H7[t][0], l = H7[t][1], m = H7[t][2];
+            double &v = c[8 + t];
+            v += (um * X[i]) * xx[jidx(l, m)];
+            v += (um * X[l]) * xx[jidx(i, m)];
+            v += (um * X[m]) * xx[jidx(i, l)];
+        }
+        for (int i = 0; i < 3; ++i) c[15 + i] += gm * X[i];
+        c[18] += am;
+        return;
     }
     for (int i = 0; i < 2; ++i)
         for (int l = i; l < 3; ++l) {            // xx xy xz yy yz

@@ -63,6 +63,7 @@ struct FarWindow {
     double nd[kFarWin][10];
 };
 
+template <bool RB>
 __device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, FarWindow &fw, double (*coef)[19]) {
     const int lane = lane_id();
     const int slot = lane >> 3, li = lane & 7;
@@ -116,7 +117,7 @@ __device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, FarWind
                 double qq[6];
 #pragma unroll
                 for (int q = 0; q < 6; ++q) qq[q] = nd[4 + q];
-                m2l_accumulate(cA[0] - nd[0], cA[1] - nd[1], cA[2] - nd[2], nd[3], qq, c);
+                m2l_accumulate<RB>(cA[0] - nd[0], cA[1] - nd[1], cA[2] - nd[2], nd[3], qq, c);
             }
         }
         tile_sync();
@@ -162,7 +163,8 @@ struct GravShared {
     };
 };
 
-template <bool MIXED>
+// RB: Taylor reading B for the sink coefficients (J, H of the monopole field)
+template <bool MIXED, bool RB>
 __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
     using T = typename std::conditional<MIXED, float, double>::type;
     __shared__ GravShared<MIXED> sh_all[kWaves];
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
     const int G = 1 << g.gk;
     const int64_t GL = (g.nleaf >> g.gk) + gi;   // group node label
     if (g.ncount[GL] == 0) return;
-    group_far(g, gi, sh.fw, sh.coef);
+    group_far<RB>(g, gi, sh.fw, sh.coef);
     using Src = typename std::conditional<MIXED, SrcF, SrcD>::type;
     Src dummy;
     dummy.x = dummy.y = dummy.z = dummy.m = 0;
@@ -284,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_far_coeffs(GravArgs g, double *out, 
     const int64_t gi = wave_index();
     if (gi >= g.ngroup) return;
     const int G = 1 << g.gk;
-    group_far(g, gi, sh.fw, coef);
+    group_far<false>(g, gi, sh.fw, coef);
     for (int i = lane_id(); i < G * 19; i += kWave) out[(gi * G + i / 19) * stride + i % 19] = coef[i / 19][i % 19];
 }
 
@@ -309,10 +311,13 @@ rcb_status gravity(rcb_tree *t, void *ax, void *ay, void *az, hipStream_t s) {
                t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
                t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, ax, ay, az};
     const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
+    const bool rb = t->p.taylor_reading == RCB_READING_B;
     if (t->p.precision == RCB_MIXED) {
-        k_gravity<true><<<grid, kBlock, 0, s>>>(g);
+        if (rb) k_gravity<true, true><<<grid, kBlock, 0, s>>>(g);
+        else k_gravity<true, false><<<grid, kBlock, 0, s>>>(g);
     } else {
-        k_gravity<false><<<grid, kBlock, 0, s>>>(g);
+        if (rb) k_gravity<false, true><<<grid, kBlock, 0, s>>>(g);
+        else k_gravity<false, false><<<grid, kBlock, 0, s>>>(g);
     }
     RCB_LAUNCH_CHECK("k_gravity");
     return RCB_OK;

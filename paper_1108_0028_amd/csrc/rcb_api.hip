@@ -142,6 +142,7 @@ void rcb_params_default(rcb_params *p) {
     p->validate = 0;
     p->pure_mac = 0;
     p->split = RCB_SPLIT_MASS;
+    p->taylor_reading = RCB_READING_A;
 }
 
 const char *rcb_last_error(void) { return g_last_error.c_str(); }
@@ -177,6 +178,10 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
     }
     if (p->pure_mac != 0 && p->pure_mac != 1) {
         set_error("rcb_build: pure_mac must be 0 or 1");
+        return RCB_EINVAL;
+    }
+    if (p->taylor_reading != RCB_READING_A && p->taylor_reading != RCB_READING_B) {
+        set_error("rcb_build: taylor_reading must be RCB_READING_A or RCB_READING_B");
         return RCB_EINVAL;
     }
     if (p->split != RCB_SPLIT_MASS && p->split != RCB_SPLIT_NUMBER && p->split != RCB_SPLIT_MEDIAN) {
@@ -311,6 +316,10 @@ rcb_status rcb_gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const vo
     g_last_error.clear();
     if (!t || !gx || !gy || !gz || !dx || !dy || !dz || !dm) {
         set_error("rcb_gravity_vjp: NULL argument");
+        return RCB_EINVAL;
+    }
+    if (t->p.taylor_reading != RCB_READING_A) {
+        set_error("rcb_gravity_vjp: defined for Taylor reading A only");
         return RCB_EINVAL;
     }
     t->stream = (hipStream_t)stream;

@@ -26,6 +26,7 @@ def _shim():
     L = C.CDLL(OUT)
     dp = C.POINTER(C.c_double)
     L.shim_m2l.argtypes = [C.c_double] * 4 + [dp, dp]
+    L.shim_m2l_b.argtypes = [C.c_double] * 4 + [dp, dp]
     L.shim_pair_adjoint.argtypes = [C.c_double] * 4 + [dp] * 8
     L.shim_pair_adjoint_sym.argtypes = [C.c_double] * 4 + [dp] * 8
     L.shim_jidx.argtypes = [C.c_int, C.c_int]
@@ -63,6 +64,26 @@ def test_forward_m2l_matches_oracle(seed):
     c = np.zeros(19)
     L.shim_m2l(R[0], R[1], R[2], M, _p(q), _p(c))
     f, J, H = O.far_coeffs(M, q, R)
+    np.testing.assert_allclose(c[:3], f, rtol=1e-12, atol=1e-14 * np.abs(f).max())
+    for k, (i, l) in enumerate(JI):
+        assert c[3 + k] == pytest.approx(J[i, l], rel=1e-11, abs=1e-13 * np.abs(J).max())
+    for k, (i, l, m) in enumerate(HI):
+        assert c[9 + k] == pytest.approx(H[i, l, m], rel=1e-11, abs=1e-13 * np.abs(H).max())
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_forward_m2l_reading_b_matches_oracle(seed):
+    # reading B: f of the full field, J and H of the monopole field
+    L = _shim()
+    rng = np.random.default_rng(50 + seed)
+    R = rng.normal(size=3) * 3
+    M = rng.uniform(0.1, 2)
+    q = rng.normal(size=6)
+    q[5] = -(q[0] + q[3])
+    c = np.zeros(19)
+    L.shim_m2l_b(R[0], R[1], R[2], M, _p(q), _p(c))
+    f, _, _ = O.far_coeffs(M, q, R)
+    _, J, H = O.far_coeffs(M, np.zeros(6), R)
     np.testing.assert_allclose(c[:3], f, rtol=1e-12, atol=1e-14 * np.abs(f).max())
     for k, (i, l) in enumerate(JI):
         assert c[3 + k] == pytest.approx(J[i, l], rel=1e-11, abs=1e-13 * np.abs(J).max())
