@@ -87,6 +87,16 @@ typedef struct {
                            through reachable cells only */
     int32_t split;      /* rcb_split: where a cell is cut; moments always use the masses */
     int32_t taylor_reading;   /* rcb_taylor_reading of the far-field sink coefficients */
+    /* Optional workspace allocator, both or neither (NULL: the library
+       allocates from the device's stream-ordered pool and keeps blocks of
+       1 GiB and more for reuse). alloc(bytes, stream, ctx) returns device
+       memory usable in stream order on `stream`, or NULL (the call then fails
+       with RCB_ENOMEM); free(ptr, stream, ctx) releases it in stream order.
+       Every block is freed by the call that allocated it or by
+       rcb_destroy(). */
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *stream, void *ctx);
+    void *alloc_ctx;
 } rcb_params;
 
 /* Paper defaults: n_ll = 12, theta = 0.7, FP64, validate = 0, pure_mac = 0,

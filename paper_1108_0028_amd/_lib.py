@@ -22,10 +22,31 @@ STATUS = {0: "RCB_OK", 1: "RCB_EINVAL", 2: "RCB_ENOMEM", 3: "RCB_EHIP", 4: "RCB_
           5: "RCB_ESTATE", 6: "RCB_EINPUT"}
 
 
+# workspace allocator callbacks (rcb_params.alloc / free)
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), stream or 0)
+    except Exception:       # out of memory: the library reports RCB_ENOMEM
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+_TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+_TORCH_FREE = _FREE_FN(_torch_free)
+
+
 class RcbParams(C.Structure):
     _fields_ = [("n_ll", C.c_int32), ("precision", C.c_int32), ("theta", C.c_double),
                 ("validate", C.c_int32), ("pure_mac", C.c_int32),
-                ("split", C.c_int32), ("taylor_reading", C.c_int32)]
+                ("split", C.c_int32), ("taylor_reading", C.c_int32),
+                ("alloc", _ALLOC_FN), ("free", _FREE_FN), ("alloc_ctx", C.c_void_p)]
 
 
 class RcbTreeInfo(C.Structure):
@@ -111,11 +132,13 @@ class Tree:
 
     def __init__(self, x, y, z, m, h, n_ll: int = 12, theta: float = 0.7, precision: str = "fp64",
                  validate: bool = False, pure_mac: bool = False, split: str = "mass",
-                 taylor_reading: str = "A"):
+                 taylor_reading: str = "A", allocator: str = "library"):
         """split: "mass" (planes through the centre of mass, the paper's),
         "number" (through the centre of number) or "median" (median position
         split: equal halves). taylor_reading: "A" (J, H of the full field) or
-        "B" (J, H of the monopole field; no VJP)."""
+        "B" (J, H of the monopole field; no VJP). allocator: "library" (the
+        library's stream-ordered pool) or "torch" (workspace from PyTorch's
+        caching allocator through rcb_params.alloc / free)."""
         L = lib()
         arrs = [_dev(a, torch.float64, nm) for a, nm in zip((x, y, z, m, h), "xyzmh")]
         n = arrs[0].numel()
@@ -131,6 +154,11 @@ class Tree:
         p.pure_mac = 1 if pure_mac else 0
         p.split = {"mass": 0, "number": 1, "median": 2}[split]
         p.taylor_reading = {"A": 0, "B": 1}[taylor_reading]
+        if allocator == "torch":
+            p.alloc = _TORCH_ALLOC
+            p.free = _TORCH_FREE
+        elif allocator != "library":
+            raise ValueError(f"unknown allocator {allocator!r}")
         self.precision = precision
         self.device = arrs[0].device
         self.n = n

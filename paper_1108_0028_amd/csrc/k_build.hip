@@ -1262,7 +1262,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         RCB_HIP(hipStreamSynchronize(s));
         if (flag) {
             set_error("rcb_build: input has a non-finite coordinate, m <= 0 or h <= 0");
-            for (void *p : tmp) dfree(p, s);
+            for (void *p : tmp) dfree(t, p, s);
             return RCB_EINPUT;
         }
     }
@@ -1366,7 +1366,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         RCB_LAUNCH_CHECK("k_mixed_prep");
     }
     for (void *p : tmp)
-        if (p) dfree(p, s);
+        if (p) dfree(t, p, s);
     return RCB_OK;
 }
 
@@ -1381,7 +1381,7 @@ rcb_status count_outside(rcb_tree *t, const double *x, const double *y, const do
     RCB_LAUNCH_CHECK("k_outside");
     unsigned long long h = 0;
     RCB_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
-    for (void *p : tmp) dfree(p, s);
+    for (void *p : tmp) dfree(t, p, s);
     RCB_HIP(hipStreamSynchronize(s));
     *outside = (int64_t)h;
     return RCB_OK;
@@ -1419,7 +1419,7 @@ rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const dou
         RCB_HIP(hipStreamSynchronize(s));
         if (flag) {
             set_error("rcb_refresh: input has a non-finite coordinate, m <= 0 or h <= 0");
-            for (void *p : tmp) dfree(p, s);
+            for (void *p : tmp) dfree(t, p, s);
             return RCB_EINPUT;
         }
     }
@@ -1455,7 +1455,7 @@ rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const dou
         RCB_LAUNCH_CHECK("k_mixed_prep");
     }
     t->nb_total = -1;   // neighbour counts belong to the old positions
-    for (void *p : tmp) dfree(p, s);
+    for (void *p : tmp) dfree(t, p, s);
     return RCB_OK;
 }
 

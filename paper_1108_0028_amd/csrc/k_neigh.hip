@@ -229,7 +229,7 @@ rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipSt
     int32_t over = 0;
     RCB_HIP(hipMemcpyAsync(total, offsets + t->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RCB_HIP(hipMemcpyAsync(&over, t->dflag + 4, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    for (void *p : tmp) dfree(p, s);
+    for (void *p : tmp) dfree(t, p, s);
     RCB_HIP(hipStreamSynchronize(s));
     t->nb_total = *total;
     t->nb_over = over;

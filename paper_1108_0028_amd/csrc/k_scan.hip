@@ -93,7 +93,7 @@ rcb_status scan_i64(rcb_tree *t, const int64_t *in, int64_t *out, int64_t n, hip
     RCB_LAUNCH_CHECK("k_scan_top");
     k_scan_apply<<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, bsum, out);
     RCB_LAUNCH_CHECK("k_scan_apply");
-    dfree(bsum, s);
+    dfree(t, bsum, s);
     return RCB_OK;
 }
 

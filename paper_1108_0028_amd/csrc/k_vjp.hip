@@ -516,7 +516,7 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     if (mixed) k_vjp_push<true><<<gridg, kBlock, 0, s>>>(a, adj, t->ncom, t->nM, dx, dy, dz, dm);
     else k_vjp_push<false><<<gridg, kBlock, 0, s>>>(a, adj, t->ncom, t->nM, dx, dy, dz, dm);
     RCB_LAUNCH_CHECK("k_vjp_push");
-    for (void *p : tmp) dfree(p, s);
+    for (void *p : tmp) dfree(t, p, s);
     return RCB_OK;
 }
 

@@ -431,7 +431,7 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
         k_sort_long<<<nlong, 1024, 0, s>>>(long_q, t->gnear_beg, t->gnear_end, t->gnear);
         RCB_LAUNCH_CHECK("k_sort_long");
     }
-    for (void *p : tmp) dfree(p, s);
+    for (void *p : tmp) dfree(t, p, s);
     t->walked = true;
     return RCB_OK;
 }
@@ -468,7 +468,7 @@ rcb_status ensure_leaf_lists(rcb_tree *t, hipStream_t s) {
                                            nullptr, nullptr, t->near_off, t->far_off, t->near_list,
                                            t->far_list);
     RCB_LAUNCH_CHECK("k_expand<fill>");
-    for (void *p : tmp) dfree(p, s);
+    for (void *p : tmp) dfree(t, p, s);
     t->near_total = tot[0];
     t->far_total = tot[1];
     t->leaf_lists = true;

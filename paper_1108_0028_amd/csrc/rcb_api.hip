@@ -60,6 +60,12 @@ void release_cached(int device) {
 }  // namespace
 
 void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owner) {
+    if (t->p.alloc) {   // the caller's allocator
+        void *q = t->p.alloc(bytes ? bytes : 16, (void *)s, t->p.alloc_ctx);
+        if (!q) set_error("workspace allocator returned NULL for " + std::to_string(bytes) + " bytes");
+        owner.push_back(q);
+        return q;
+    }
     static bool pool_set[64] = {false};
     std::lock_guard<std::mutex> lock(g_cache_mu);
     if (t->device >= 0 && t->device < 64 && !pool_set[t->device]) {
@@ -106,8 +112,12 @@ void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owne
     return p;
 }
 
-void dfree(void *p, hipStream_t s) {
+void dfree(rcb_tree *t, void *p, hipStream_t s) {
     if (!p) return;
+    if (t->p.free) {   // the caller's allocator
+        t->p.free(p, (void *)s, t->p.alloc_ctx);
+        return;
+    }
     std::lock_guard<std::mutex> lock(g_cache_mu);
     auto it = g_large.find(p);
     if (it != g_large.end()) {
@@ -121,8 +131,8 @@ void dfree(void *p, hipStream_t s) {
 }
 
 static void free_all(rcb_tree *t) {
-    for (void *p : t->list_allocs) dfree(p, t->stream);
-    for (void *p : t->allocs) dfree(p, t->stream);
+    for (void *p : t->list_allocs) dfree(t, p, t->stream);
+    for (void *p : t->allocs) dfree(t, p, t->stream);
     t->list_allocs.clear();
     t->allocs.clear();
     (void)hipStreamSynchronize(t->stream);
@@ -143,6 +153,9 @@ void rcb_params_default(rcb_params *p) {
     p->pure_mac = 0;
     p->split = RCB_SPLIT_MASS;
     p->taylor_reading = RCB_READING_A;
+    p->alloc = nullptr;
+    p->free = nullptr;
+    p->alloc_ctx = nullptr;
 }
 
 const char *rcb_last_error(void) { return g_last_error.c_str(); }
@@ -178,6 +191,10 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
     }
     if (p->pure_mac != 0 && p->pure_mac != 1) {
         set_error("rcb_build: pure_mac must be 0 or 1");
+        return RCB_EINVAL;
+    }
+    if ((p->alloc == nullptr) != (p->free == nullptr)) {
+        set_error("rcb_build: alloc and free must be given together");
         return RCB_EINVAL;
     }
     if (p->taylor_reading != RCB_READING_A && p->taylor_reading != RCB_READING_B) {
@@ -218,7 +235,7 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
             st = hipGetLastError() == hipSuccess ? RCB_OK : RCB_EHIP;
             if (st == RCB_OK) st = build_tree(t, x, y, z, ones, h, t->stream);
             if (st == RCB_OK) st = refresh_tree(t, x, y, z, m, h, t->stream);
-            dfree(ones, t->stream);
+            dfree(t, ones, t->stream);
         }
     } else {
         st = build_tree(t, x, y, z, m, h, t->stream);

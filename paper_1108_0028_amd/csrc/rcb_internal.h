@@ -100,7 +100,7 @@ void set_error(const std::string &msg);
 rcb_status hip_fail(hipError_t e, const char *what);
 void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owner);
 // releases a dalloc block in stream order (large blocks stay cached for reuse)
-void dfree(void *p, hipStream_t s);
+void dfree(rcb_tree *t, void *p, hipStream_t s);
 
 // build (k_build.hip)
 rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const double *z,
