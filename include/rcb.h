@@ -18,8 +18,10 @@
  *    order; every per-particle output is also in the caller's order.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    All work is enqueued on it; inputs must stay valid and outputs must not
- *    be read until the stream has passed the call. Only
- *    rcb_neighbours_count() synchronises the stream (it returns a host total).
+ *    be read until the stream has passed the call. The calls that return
+ *    host values or size device lists synchronise the stream: rcb_walk()
+ *    (and the first call that runs the walk on demand), rcb_check_cells(),
+ *    rcb_neighbours_count() and rcb_destroy().
  *  - Inputs stay owned by the caller. rcb_build() copies what it needs, so
  *    the tree never aliases caller memory after the call returns.
  *  - Calls return rcb_status; nothing throws across the ABI. Argument errors
