@@ -21,7 +21,8 @@
  *    be read until the stream has passed the call. The calls that return
  *    host values or size device lists synchronise the stream: rcb_walk()
  *    (and the first call that runs the walk on demand), rcb_check_cells(),
- *    rcb_neighbours_count() and rcb_destroy().
+ *    rcb_neighbours_count(), rcb_destroy(), and rcb_build() / rcb_refresh()
+ *    with validate = 1.
  *  - Inputs stay owned by the caller. rcb_build() copies what it needs, so
  *    the tree never aliases caller memory after the call returns.
  *  - Calls return rcb_status; nothing throws across the ABI. Argument errors
