@@ -222,30 +222,51 @@ def _profiled_traffic(name):
 
 
 def cpu_baseline(cloud, a):
-    """The FP64 oracle (unchanged) on the host: full tree build, then walk,
-    neighbours and gravity for a random sample of leaves; throughput scaled to
+    """The FP64 oracle (unchanged) on the host: full tree build (serial), then
+    walk, neighbours and gravity for a random sample of leaves (OpenMP over
+    leaves), with all threads and again with one; throughput scaled to
     particles/s of build + neighbours + gravity."""
     import numpy as np
 
     from oracle import oracle as O
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    threads = O.threads()
     t0 = time.perf_counter()
     ot = O.OracleTree(*cloud.arrays(), n_ll=a.n_ll)
     t1 = time.perf_counter()
     rng = np.random.default_rng(0)
     leaves = np.sort(rng.choice(ot.n_leaves, min(a.cpu_leaves, ot.n_leaves), replace=False)) + ot.n_leaves
-    ot.walk(a.theta, leaves, pure_mac=a.pure_mac)
-    t2 = time.perf_counter()
-    off, ids, valid = ot.neighbours()
-    t3 = time.perf_counter()
-    ot.gravity()
-    t4 = time.perf_counter()
-    n_s = int(valid.sum())
-    per_particle = (t1 - t0) / cloud.n + (t4 - t1) / max(1, n_s)
-    return {"value": 1.0 / per_particle, "unit": "particles/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle build of all {cloud.n} particles (serial, {t1 - t0:.1f} s) + walk, "
+
+    def sampled():
+        s0 = time.perf_counter()
+        ot.walk(a.theta, leaves, pure_mac=a.pure_mac)
+        s1 = time.perf_counter()
+        _, _, valid = ot.neighbours()
+        s2 = time.perf_counter()
+        ot.gravity()
+        s3 = time.perf_counter()
+        return int(valid.sum()), (s1 - s0, s2 - s1, s3 - s2)
+
+    n_s, ph = sampled()
+    O.set_threads(1)
+    _, ph1 = sampled()
+    O.set_threads(threads)
+    build = t1 - t0
+    rate = lambda p: 1.0 / (build / cloud.n + sum(p) / max(1, n_s))
+    return {"value": rate(ph), "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": rate(ph1), "cpu": model,
+            "phases_s": {"build_all": build, "walk": ph[0], "neighbours": ph[1], "gravity": ph[2],
+                         "walk_1thread": ph1[0], "neighbours_1thread": ph1[1], "gravity_1thread": ph1[2]},
+            "sample": f"oracle build of all {cloud.n} particles (serial, {build:.1f} s) + walk, "
                       f"neighbours and gravity of {len(leaves)} random leaves ({n_s} particles, "
-                      f"{t4 - t1:.1f} s, OpenMP {threads} threads)"}
+                      f"{sum(ph):.1f} s on {threads} OpenMP threads, {sum(ph1):.1f} s on 1)"}
 
 
 if __name__ == "__main__":

@@ -50,6 +50,8 @@ def lib():
         L.orc_nodes.argtypes = [P, dp, dp, dp, dp, dp, dp, dp]
         L.orc_walk.argtypes = [P, C.c_double, i64p, C.c_int64, C.c_int]
         L.orc_set_reading.argtypes = [P, C.c_int]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_threads.restype = C.c_int
         L.orc_list_sizes.argtypes = [P, i64p, i64p, i64p]
         L.orc_leaf_lists.argtypes = [P, C.c_int64, i32p, i32p]
         L.orc_neighbours_count.argtypes = [P, i64p]
@@ -78,6 +80,15 @@ def _i64(a):
 
 def _i32(a):
     return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def set_threads(n: int):
+    """Threads of the oracle's OpenMP loops."""
+    lib().orc_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(lib().orc_threads())
 
 
 def depth_for(n: int, n_ll: int) -> int:

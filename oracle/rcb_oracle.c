@@ -25,6 +25,9 @@
  *     monopole + quadrupole field (Sec. 2.4.2).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -398,6 +401,25 @@ void orc_refresh(otree *t, const double *x, const double *y, const double *z,
 }
 
 int orc_k(const otree *t) { return t->k; }
+
+/* Threads of the OpenMP loops (walk, neighbours, gravity); the build is serial. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* Taylor reading of the sink coefficients used by orc_gravity: 0 = A, 1 = B. */
 void orc_set_reading(otree *t, int reading) { t->reading = reading; }
