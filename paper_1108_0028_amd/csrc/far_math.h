@@ -74,114 +74,155 @@ RCB_HD constexpr int hidx(int i, int l, int m) {
     return a == 0 ? (b == 0 ? c : (b == 1 ? 2 + c : 5)) : (a == 1 ? (b == 1 ? 5 + c : 8) : 9);
 }
 
-// One source's f, J, H added into a reduced accumulator of 19 doubles. With
-// g = b2 x + c1 q, u = e3 x / 3 + c2 q and Qc = c1 Q the closed forms above
-// regroup as
+// One source's f, J, H added into a reduced accumulator of kAcc doubles.
+// With ri = 1/r the coefficients are powers of ri:
+//   c0 = ri^5, c1 = -5 ri^7, c2 = 35 ri^9,
+//   a1 = -M ri^3 + c1 s / 2, b2 = 3 M ri^5 + c2 s / 2,
+//   e3 / 3 = M c1 - 105 ri^11 s / 2,
+// and with g = b2 x + c1 q, u = e3 x / 3 + c2 q and cx = c1 x the closed
+// forms above regroup as
 //   f_i = a1 x_i + c0 q_i
-//   J_il = g_i x_l + c1 q_l x_i + c0 Q_il + a1 d_il
+//   J_il = g_i x_l + q_l cx_i + c0 Q_il + a1 d_il
 //   H_ilm = sum over the three choices of the single index j (the other
-//           two, k and n): u_j x_k x_n + Qc_kn x_j + d_kn g_j
+//           two, k and n): u_j x_k x_n + Q_kn cx_j + d_kn g_j
 // The field of Eq. 5 is harmonic, so J and H are traceless in every index
 // pair; only 5 components of J and 7 of H are accumulated, and the
 // Kronecker-delta terms are summed once (sum of a1, sum of g) instead of
-// into every diagonal component. Layout: f (0..2); J xx xy xz yy yz
-// without a1 (3..7); H xxx xxy xxz xyy xyz yyy yyz without the g terms
-// (8..14); sum g (15..17); sum a1 (18). m2l_finish expands it.
+// into every diagonal component. Within one H component the three choices
+// of j coincide in pairs or all three when indices repeat; such terms are
+// accumulated once and weighted by their multiplicity in m2l_finish:
+//   H_000 = 3 [u0 x0x0 + Q00 cx0]            (h0)
+//   H_001 = 2 [u0 x0x1 + Q01 cx0] + [u1 x0x0 + Q00 cx1]   (h1, h2)
+//   H_002 = 2 [u0 x0x2 + Q02 cx0] + [u2 x0x0 + Q00 cx2]   (h3, h4)
+//   H_011 = [u0 x1x1 + Q11 cx0] + 2 [u1 x0x1 + Q01 cx1]   (h5, h6)
+//   H_012 = u0 x1x2 + u1 x0x2 + u2 x0x1 + Q12 cx0 + Q02 cx1 + Q01 cx2 (h7)
+//   H_111 = 3 [u1 x1x1 + Q11 cx1]            (h8)
+//   H_112 = 2 [u1 x1x2 + Q12 cx1] + [u2 x1x1 + Q11 cx2]   (h9, h10)
+// (each plus its delta terms). Layout: f (0..2); J xx xy xz yy yz without
+// a1 (3..7); h0..h10 (8..18); sum g (19..21); sum a1 (22).
 //
 // RB (Taylor reading B): f as above, but J and H of the monopole field
 // alone, J_il = M g_il and H_ilm = M g_ilm, i.e. the same expressions with
 // Q = 0 in them (g = M D2 x, u = M D3 x / 3, a1 = M D1).
+constexpr int kAcc = 23;
+
 template <bool RB = false>
-RCB_HD void m2l_accumulate(double x, double y, double z, double M, const double qq[6], double (&c)[19]) {
+RCB_HD void m2l_accumulate(double x, double y, double z, double M, const double qq[6], double (&c)[kAcc]) {
     const double X[3] = {x, y, z};
     const double r2 = (x * x + y * y) + z * z;
-    const double rinv = rsqrt64(r2);
-    const double rinv2 = rinv * rinv;
-    const double D1 = -rinv * rinv2;
-    const double D2 = -3.0 * D1 * rinv2;
-    const double D3 = -5.0 * D2 * rinv2;
-    const double D4 = -7.0 * D3 * rinv2;
-    const double D5 = -9.0 * D4 * rinv2;
+    const double ri = rsqrt64(r2);
+    const double w = ri * ri;
+    const double p3 = ri * w;
+    const double c0 = p3 * w;
+    const double p7 = c0 * w;
+    const double p9 = p7 * w;
+    const double c1 = -5.0 * p7;
+    const double c2 = 35.0 * p9;
     double q[3];
     for (int i = 0; i < 3; ++i) q[i] = qq[jidx(i, 0)] * x + qq[jidx(i, 1)] * y + qq[jidx(i, 2)] * z;
-    const double s = q[0] * x + q[1] * y + q[2] * z;
-    const double sixth = 1.0 / 6.0, third = 1.0 / 3.0;
-    const double a1 = M * D1 + sixth * D3 * s;
-    const double b2 = M * D2 + sixth * D4 * s;
-    const double e3 = M * D3 + sixth * D5 * s;
-    const double c0 = third * D2, c1 = third * D3, c2 = third * D4;
-    double g[3], u[3], cq[3], xx[6], Qc[6];
-    for (int i = 0; i < 3; ++i) {
-        g[i] = b2 * X[i] + c1 * q[i];
-        u[i] = (third * e3) * X[i] + c2 * q[i];
-        cq[i] = c1 * q[i];
-    }
-    for (int i = 0; i < 3; ++i)
-        for (int l = i; l < 3; ++l) {
-            xx[jidx(i, l)] = X[i] * X[l];
-            Qc[jidx(i, l)] = c1 * qq[jidx(i, l)];
-        }
-    // every term goes straight into its accumulator (one FMA each)
+    const double hs = 0.5 * ((q[0] * x + q[1] * y) + q[2] * z);
+    const double a1 = hs * c1 - M * p3;
+    // f (both readings)
     for (int i = 0; i < 3; ++i) {
         c[i] += a1 * X[i];
         c[i] += c0 * q[i];
     }
+    const double xx[5] = {x * x, x * y, x * z, y * y, y * z};   // 00 01 02 11 12
+    double g[3], u[3];
     if constexpr (RB) {
-        const double gm = M * D2, um = third * (M * D3), am = M * D1;
-        for (int i = 0; i < 2; ++i)
-            for (int l = i; l < 3; ++l) c[3 + jidx(i, l)] += (gm * X[i]) * X[l];
-        constexpr int H7[7][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 1, 1}, {0, 1, 2}, {1, 1, 1}, {1, 1, 2}};
-        for (int t = 0; t < 7; ++t) {
-            const int i = H7[t][0], l = H7[t][1], m = H7[t][2];
-            double &v = c[8 + t];
-            v += (um * X[i]) * xx[jidx(l, m)];
-            v += (um * X[l]) * xx[jidx(i, m)];
-            v += (um * X[m]) * xx[jidx(i, l)];
+        const double gm = 3.0 * (M * c0), um = M * c1, am = -(M * p3);
+        for (int i = 0; i < 3; ++i) {
+            g[i] = gm * X[i];
+            u[i] = um * X[i];
         }
-        for (int i = 0; i < 3; ++i) c[15 + i] += gm * X[i];
-        c[18] += am;
+        c[3] += g[0] * x;
+        c[4] += g[0] * y;
+        c[5] += g[0] * z;
+        c[6] += g[1] * y;
+        c[7] += g[1] * z;
+        c[8] += u[0] * xx[0];
+        c[9] += u[0] * xx[1];
+        c[10] += u[1] * xx[0];
+        c[11] += u[0] * xx[2];
+        c[12] += u[2] * xx[0];
+        c[13] += u[0] * xx[3];
+        c[14] += u[1] * xx[1];
+        c[15] += u[0] * xx[4];
+        c[15] += u[1] * xx[2];
+        c[15] += u[2] * xx[1];
+        c[16] += u[1] * xx[3];
+        c[17] += u[1] * xx[4];
+        c[18] += u[2] * xx[3];
+        for (int i = 0; i < 3; ++i) c[19 + i] += g[i];
+        c[22] += am;
         return;
     }
+    const double b2 = hs * c2 + 3.0 * (M * c0);
+    const double e3t = (hs * (p9 * w)) * -105.0 + M * c1;
+    double cx[3];
+    for (int i = 0; i < 3; ++i) {
+        const double cq = c1 * q[i];
+        g[i] = b2 * X[i] + cq;
+        u[i] = e3t * X[i] + c2 * q[i];
+        cx[i] = c1 * X[i];
+    }
+    // J: xx xy xz yy yz
     for (int i = 0; i < 2; ++i)
-        for (int l = i; l < 3; ++l) {            // xx xy xz yy yz
+        for (int l = i; l < 3; ++l) {
             double &v = c[3 + jidx(i, l)];
             v += g[i] * X[l];
-            v += cq[l] * X[i];
+            v += q[l] * cx[i];
             v += c0 * qq[jidx(i, l)];
         }
-    constexpr int H7[7][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 1, 1}, {0, 1, 2}, {1, 1, 1}, {1, 1, 2}};
-    for (int t = 0; t < 7; ++t) {
-        const int i = H7[t][0], l = H7[t][1], m = H7[t][2];
-        double &v = c[8 + t];
-        v += u[i] * xx[jidx(l, m)];
-        v += u[l] * xx[jidx(i, m)];
-        v += u[m] * xx[jidx(i, l)];
-        v += Qc[jidx(l, m)] * X[i];
-        v += Qc[jidx(i, m)] * X[l];
-        v += Qc[jidx(i, l)] * X[m];
-    }
-    for (int i = 0; i < 3; ++i) c[15 + i] += g[i];
-    c[18] += a1;
+    const double Q00 = qq[0], Q01 = qq[1], Q02 = qq[2], Q11 = qq[3], Q12 = qq[4];
+    c[8] += u[0] * xx[0];
+    c[8] += Q00 * cx[0];
+    c[9] += u[0] * xx[1];
+    c[9] += Q01 * cx[0];
+    c[10] += u[1] * xx[0];
+    c[10] += Q00 * cx[1];
+    c[11] += u[0] * xx[2];
+    c[11] += Q02 * cx[0];
+    c[12] += u[2] * xx[0];
+    c[12] += Q00 * cx[2];
+    c[13] += u[0] * xx[3];
+    c[13] += Q11 * cx[0];
+    c[14] += u[1] * xx[1];
+    c[14] += Q01 * cx[1];
+    c[15] += u[0] * xx[4];
+    c[15] += u[1] * xx[2];
+    c[15] += u[2] * xx[1];
+    c[15] += Q12 * cx[0];
+    c[15] += Q02 * cx[1];
+    c[15] += Q01 * cx[2];
+    c[16] += u[1] * xx[3];
+    c[16] += Q11 * cx[1];
+    c[17] += u[1] * xx[4];
+    c[17] += Q12 * cx[1];
+    c[18] += u[2] * xx[3];
+    c[18] += Q11 * cx[2];
+    for (int i = 0; i < 3; ++i) c[19 + i] += g[i];
+    c[22] += a1;
 }
 
 // the reduced accumulator of m2l_accumulate -> f (0..2), J (3..8, jidx),
 // H (9..18, hidx)
-RCB_HD void m2l_finish(const double (&a)[19], double (&c)[19]) {
+RCB_HD void m2l_finish(const double (&a)[kAcc], double (&c)[19]) {
     for (int i = 0; i < 3; ++i) c[i] = a[i];
-    const double *G = a + 15;
-    c[3 + jidx(0, 0)] = a[3] + a[18];
+    const double *G = a + 19;
+    c[3 + jidx(0, 0)] = a[3] + a[22];
     c[3 + jidx(0, 1)] = a[4];
     c[3 + jidx(0, 2)] = a[5];
-    c[3 + jidx(1, 1)] = a[6] + a[18];
+    c[3 + jidx(1, 1)] = a[6] + a[22];
     c[3 + jidx(1, 2)] = a[7];
     c[3 + jidx(2, 2)] = -(c[3 + jidx(0, 0)] + c[3 + jidx(1, 1)]);
-    c[9 + hidx(0, 0, 0)] = a[8] + 3.0 * G[0];
-    c[9 + hidx(0, 0, 1)] = a[9] + G[1];
-    c[9 + hidx(0, 0, 2)] = a[10] + G[2];
-    c[9 + hidx(0, 1, 1)] = a[11] + G[0];
-    c[9 + hidx(0, 1, 2)] = a[12];
-    c[9 + hidx(1, 1, 1)] = a[13] + 3.0 * G[1];
-    c[9 + hidx(1, 1, 2)] = a[14] + G[2];
+    c[9 + hidx(0, 0, 0)] = 3.0 * (a[8] + G[0]);
+    c[9 + hidx(0, 0, 1)] = (2.0 * a[9] + a[10]) + G[1];
+    c[9 + hidx(0, 0, 2)] = (2.0 * a[11] + a[12]) + G[2];
+    c[9 + hidx(0, 1, 1)] = (a[13] + 2.0 * a[14]) + G[0];
+    c[9 + hidx(0, 1, 2)] = a[15];
+    c[9 + hidx(1, 1, 1)] = 3.0 * (a[16] + G[1]);
+    c[9 + hidx(1, 1, 2)] = (2.0 * a[17] + a[18]) + G[2];
     c[9 + hidx(0, 2, 2)] = -(c[9 + hidx(0, 0, 0)] + c[9 + hidx(0, 1, 1)]);
     c[9 + hidx(1, 2, 2)] = -(c[9 + hidx(0, 0, 1)] + c[9 + hidx(1, 1, 1)]);
     c[9 + hidx(2, 2, 2)] = -(c[9 + hidx(0, 0, 2)] + c[9 + hidx(1, 1, 2)]);

@@ -70,9 +70,9 @@ __device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, FarWind
     const int G = 1 << g.gk;
     const int64_t A = g.nleaf + gi * G + (li < G ? li : 0);
     const double cA[3] = {g.ncom[3 * A], g.ncom[3 * A + 1], g.ncom[3 * A + 2]};
-    double c[19];
+    double c[rcbfar::kAcc];
 #pragma unroll
-    for (int q = 0; q < 19; ++q) c[q] = 0.0;
+    for (int q = 0; q < rcbfar::kAcc; ++q) c[q] = 0.0;
     const int64_t f0 = g.gfar_beg[gi], f1 = g.gfar_end[gi];
     for (int64_t w0 = f0; w0 < f1; w0 += kFarWin) {
         const int nw = (int)(f1 - w0 < kFarWin ? f1 - w0 : kFarWin);
@@ -123,7 +123,7 @@ __device__ __forceinline__ void group_far(const GravArgs &g, int64_t gi, FarWind
         tile_sync();
     }
 #pragma unroll
-    for (int q = 0; q < 19; ++q) {
+    for (int q = 0; q < rcbfar::kAcc; ++q) {
         double v = c[q];
         v += __shfl_xor(v, 8, kWave);
         v += __shfl_xor(v, 16, kWave);

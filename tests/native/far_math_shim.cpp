@@ -5,16 +5,16 @@
 extern "C" {
 
 void shim_m2l(double x, double y, double z, double M, const double *q6, double *c19) {
-    double a[19], c[19];
-    for (int i = 0; i < 19; ++i) a[i] = 0.0;
+    double a[rcbfar::kAcc], c[19];
+    for (int i = 0; i < rcbfar::kAcc; ++i) a[i] = 0.0;
     rcbfar::m2l_accumulate(x, y, z, M, q6, a);
     rcbfar::m2l_finish(a, c);
     for (int i = 0; i < 19; ++i) c19[i] = c[i];
 }
 
 void shim_m2l_b(double x, double y, double z, double M, const double *q6, double *c19) {
-    double a[19], c[19];
-    for (int i = 0; i < 19; ++i) a[i] = 0.0;
+    double a[rcbfar::kAcc], c[19];
+    for (int i = 0; i < rcbfar::kAcc; ++i) a[i] = 0.0;
     rcbfar::m2l_accumulate<true>(x, y, z, M, q6, a);
     rcbfar::m2l_finish(a, c);
     for (int i = 0; i < 19; ++i) c19[i] = c[i];
