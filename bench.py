@@ -142,7 +142,7 @@ def main():
     roofline = {"kernel": f"k_gravity<{a.precision}>", "bound": "alu", "achieved": achieved_tf,
                 "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tf / PEAK_VALU_TFLOPS,
                 "traffic": traffic, "kernel_ms": grav_ms, "pairs": pairs, "far_pairs": far_total,
-                "near_cells": near_total}
+                "near_cells": near_total, "walk_requeued_groups": inf["walk_requeued"]}
     # the per-leaf streaming model of the walk + gravity (bytes each lowest-level
     # cell would read on its own): nodes tested V ~ 2 (F + L) in a binary walk
     V_A = 2 * (F_A + L_A)

@@ -218,6 +218,9 @@ typedef struct {
     int64_t near_total;   /* interaction-list sizes, -1 until the walk has run */
     int64_t far_total;
     double theta;
+    int64_t walk_requeued; /* groups of the last walk whose stack outgrew the wide walk's
+                              and that the 8-wide walk took instead (same lists); -1 before
+                              the walk */
 } rcb_tree_info;
 
 rcb_status rcb_get_info(const rcb_tree *t, rcb_tree_info *info /* host */);

@@ -18,8 +18,12 @@
 // are taken by ballot within the sink's lane segment, so each list keeps tree
 // order. The count call writes the ids into a slab of kNbCap slots per
 // particle as well as the counts; the fill call then compacts the slab into
-// the caller's CSR; the groups holding a particle with more neighbours than
-// the slab takes are searched again, writing at offsets[a] + rank.
+// the caller's CSR. Ids of rank >= kNbCap go as (particle, rank, id) into an
+// overflow pool that the fill call places directly; only if the pool itself
+// runs out are the groups holding such a particle searched again, writing at
+// offsets[a] + rank.
+#include <algorithm>
+
 #include "near_tile.h"
 #include "rcb_internal.h"
 
@@ -46,6 +50,9 @@ struct NeighArgs {
     int32_t *ids;             // fill mode: final lists; slab mode: kNbCap slots per particle
     int32_t *flag;            // slab mode: particles with more than kNbCap neighbours
     int32_t *gover;           // per group: 1 if one of its particles outgrew the slab
+    int32_t *ovf;             // slab mode: overflow pool, (caller index, rank, id) per entry
+    unsigned long long *ovf_n;   // entries claimed in the pool (may pass ovf_cap)
+    int64_t ovf_cap;
 };
 
 struct alignas(16) SrcN {
@@ -104,6 +111,14 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
                     const uint64_t bal = ballot(hit) & segmask;
                     const int r = cnt + rank_below(bal);
                     if (hit && (!SLAB || r < kNbCap)) a.ids[obase + r] = s.id;
+                    if (SLAB && hit && r >= kNbCap) {
+                        const unsigned long long o = atomicAdd(a.ovf_n, 1ull);
+                        if (o < (unsigned long long)a.ovf_cap) {
+                            a.ovf[3 * o] = oa;
+                            a.ovf[3 * o + 1] = r;
+                            a.ovf[3 * o + 2] = s.id;
+                        }
+                    }
                     cnt += __popcll(bal);
                 }
             };
@@ -195,9 +210,17 @@ __global__ __launch_bounds__(kBlock) void k_nb_compact(int64_t n, const int32_t 
     const int j0 = threadIdx.x % 16;
     if (p >= n) return;
     const int32_t a = pid[p];
-    const int64_t o = offsets[a], c = offsets[a + 1] - o;
-    if (c > kNbCap) return;   // searched again by its group
+    const int64_t o = offsets[a], c = std::min<int64_t>(offsets[a + 1] - o, kNbCap);
     for (int64_t j = j0; j < c; j += 16) ids[o + j] = slab[p * kNbCap + j];
+}
+
+// overflow pool entries to their places in the CSR
+__global__ __launch_bounds__(kBlock) void k_nb_ovf(int64_t cnt, const int32_t *__restrict__ ovf,
+                                                   const int64_t *__restrict__ offsets,
+                                                   int32_t *__restrict__ ids) {
+    const int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (e >= cnt) return;
+    ids[offsets[ovf[3 * e]] + ovf[3 * e + 1]] = ovf[3 * e + 2];
 }
 
 }  // namespace
@@ -211,28 +234,36 @@ rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipSt
     std::vector<void *> tmp;
     int64_t *counts = (int64_t *)dalloc(t, sizeof(int64_t) * t->n, s, tmp);
     if (!counts) return RCB_ENOMEM;
+    const int64_t ovf_cap = std::max<int64_t>(int64_t(1) << 20, t->n / 4);
     if (!t->nb_slab) {
         t->nb_slab = (int32_t *)dalloc(t, sizeof(int32_t) * t->n * kNbCap, s, t->list_allocs);
         t->nb_gover = (int32_t *)dalloc(t, sizeof(int32_t) * t->ngroup, s, t->list_allocs);
-        if (!t->nb_slab || !t->nb_gover) return RCB_ENOMEM;
+        t->nb_ovf = (int32_t *)dalloc(t, sizeof(int32_t) * 3 * ovf_cap, s, t->list_allocs);
+        t->nb_ovf_cnt = (unsigned long long *)dalloc(t, sizeof(unsigned long long), s, t->list_allocs);
+        if (!t->nb_slab || !t->nb_gover || !t->nb_ovf || !t->nb_ovf_cnt) return RCB_ENOMEM;
     }
     RCB_HIP(hipMemsetAsync(t->dflag + 4, 0, sizeof(int32_t), s));
+    RCB_HIP(hipMemsetAsync(t->nb_ovf_cnt, 0, sizeof(unsigned long long), s));
     RCB_HIP(hipMemsetAsync(t->nb_gover, 0, sizeof(int32_t) * t->ngroup, s));
     NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
                 t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, counts, nullptr, t->nb_slab,
-                t->dflag + 4, t->nb_gover};
+                t->dflag + 4, t->nb_gover, t->nb_ovf, t->nb_ovf_cnt, ovf_cap};
     const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     k_neigh<true><<<grid, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_neigh<slab>");
     st = scan_i64(t, counts, offsets, t->n, s);
     if (st != RCB_OK) return st;
     int32_t over = 0;
+    unsigned long long novf = 0;
     RCB_HIP(hipMemcpyAsync(total, offsets + t->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RCB_HIP(hipMemcpyAsync(&over, t->dflag + 4, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    RCB_HIP(hipMemcpyAsync(&novf, t->nb_ovf_cnt, sizeof(novf), hipMemcpyDeviceToHost, s));
     for (void *p : tmp) dfree(t, p, s);
     RCB_HIP(hipStreamSynchronize(s));
     t->nb_total = *total;
     t->nb_over = over;
+    t->nb_ovf_ok = novf <= (unsigned long long)ovf_cap;
+    t->nb_ovf_n = t->nb_ovf_ok ? (int64_t)novf : 0;
     return RCB_OK;
 }
 
@@ -250,10 +281,14 @@ rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, in
     const unsigned gridc = (unsigned)((t->n * 16 + kBlock - 1) / kBlock);
     k_nb_compact<<<gridc, kBlock, 0, s>>>(t->n, t->pid, offsets, t->nb_slab, ids);
     RCB_LAUNCH_CHECK("k_nb_compact");
-    if (t->nb_over > 0) {
+    if (t->nb_over > 0 && t->nb_ovf_ok) {
+        k_nb_ovf<<<(unsigned)((t->nb_ovf_n + kBlock - 1) / kBlock), kBlock, 0, s>>>(t->nb_ovf_n, t->nb_ovf,
+                                                                                    offsets, ids);
+        RCB_LAUNCH_CHECK("k_nb_ovf");
+    } else if (t->nb_over > 0) {
         NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
                     t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids, nullptr,
-                    t->nb_gover};
+                    t->nb_gover, nullptr, nullptr, 0};
         const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
         k_neigh<false><<<grid, kBlock, 0, s>>>(a);
         RCB_LAUNCH_CHECK("k_neigh<fill>");

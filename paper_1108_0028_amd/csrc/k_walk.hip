@@ -23,11 +23,22 @@
 // A near entry then may be a candidate without being in a leaf's gravity
 // near field (candidate bit set, near bit clear).
 //
+// Two kernels walk a group. k_walk_wide, the one normally run, gives each
+// lane one popped stack entry (up to 64 per round) and tests it against all
+// the group's leaves in turn, so a node costs one record load and one set
+// of list/stack bookkeeping for 8 leaf tests; its LDS stack holds kWStack
+// entries, and a group that would outgrow it is queued and walked again by
+// k_walk_group, whose lanes are (pending entry, leaf) and whose stack bound
+// is proved below. Both make the same per-leaf decisions; their lists differ
+// only in order.
+//
 // Output per group: a near list of (label, near mask, candidate mask) and a
 // far list of (label, far mask) -- the union of the group's per-leaf lists.
 // Near lists are sorted by label, so each leaf's candidates (and neighbour
 // lists) come out in tree order. Two launches: count, then fill after a
 // scan of the sizes. Per-leaf lists for inspection are expanded on demand.
+#include <cstdlib>
+
 #include "rcb_internal.h"
 
 namespace rcb {
@@ -57,6 +68,7 @@ struct WalkArgs {
     int64_t near_cap, far_cap;
     uint64_t *near_list, *far_list;
     int32_t *flag;
+    int wcap;   // k_walk_wide: stack entries used (<= kWStack)
 };
 
 // bit 8 s set iff byte s of x is non-zero (the lead lane of entry s)
@@ -68,12 +80,14 @@ __device__ __forceinline__ uint64_t byte_any(uint64_t x) {
 }
 
 // stack entry: label | gravity mask << 32 | neighbour mask << 40
+// only: if given, wave i walks group only[i] (i < nonly), else group i
 template <bool PURE>
-__global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
+__global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w, const int32_t *only, int64_t nonly) {
     __shared__ uint64_t stk_all[kWaves][kGStack];
     uint64_t *stk = stk_all[threadIdx.x / kWave];
-    const int64_t gi = wave_index();
-    if (gi >= w.ngroup) return;
+    const int64_t wi = wave_index();
+    if (wi >= (only ? nonly : w.ngroup)) return;
+    const int64_t gi = only ? (int64_t)only[wi] : wi;
     const int lane = lane_id();
     const int G = 1 << w.gk;
     const int slot = lane >> 3;      // pending entry handled by this lane
@@ -184,6 +198,145 @@ __global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w) {
             w.near_cnt[gi] = 0;
             w.far_cnt[gi] = 0;
         }
+        return;
+    }
+    if (lane == 0) {
+        w.near_cnt[gi] = nn;
+        w.far_cnt[gi] = nf;
+        if (nn > kSortCap) atomicAdd(&w.flag[1], 1);
+        if (nn > w.near_cap || nf > w.far_cap) atomicAdd(&w.flag[3], 1);
+    }
+}
+
+// Wide walk: lane j holds the j-th popped entry; its node record is loaded
+// once and tested against each leaf of the group (records in LDS), and the
+// per-leaf decisions of the header become 8-bit masks per lane. The stack
+// keeps the order argument of k_walk_group (children pushed in the order of
+// their parents), with up to 64 pops per round; at 4M particles its depth
+// stays near 300 entries. A group whose pushes would pass kWStack stops: if
+// queue is given its index is appended (flag[6] counts them) for k_walk_group
+// to walk again, writing counts and lists over whatever this one wrote.
+constexpr int kWStack = 768;
+
+template <bool PURE>
+__global__ __launch_bounds__(kBlock) void k_walk_wide(WalkArgs w, int32_t *queue) {
+    __shared__ uint64_t stk_all[kWaves][kWStack];
+    __shared__ double4 leaf_all[kWaves][16];   // per leaf: (g, h_node), (com, -)
+    uint64_t *stk = stk_all[threadIdx.x / kWave];
+    double4 *lf = leaf_all[threadIdx.x / kWave];
+    const int64_t gi = wave_index();
+    if (gi >= w.ngroup) return;
+    const int lane = lane_id();
+    const int G = 1 << w.gk;
+    const int64_t nleaf = (int64_t)1 << w.k;
+    const int64_t A0 = nleaf + gi * G;
+    bool leaf_live = false;
+    if (lane < 8) {
+        const int64_t A = A0 + (lane < G ? lane : 0);
+        const double4 ga = w.rec[2 * A];
+        leaf_live = lane < G && ga.w >= 0.0;
+        lf[lane] = make_double4(ga.x, ga.y, ga.z, w.hnode[A]);
+        lf[8 + lane] = w.rec[2 * A + 1];
+    }
+    const uint32_t live_mask = (uint32_t)(ballot(leaf_live) & 0xffull);
+    int64_t nn = 0, nf = 0;
+    const int64_t nbase = w.near_beg ? w.near_beg[gi] : gi * w.near_cap;
+    const int64_t fbase = w.far_beg ? w.far_beg[gi] : gi * w.far_cap;
+    if (live_mask == 0) {
+        if (lane == 0) {
+            w.near_cnt[gi] = 0;
+            w.far_cnt[gi] = 0;
+        }
+        return;
+    }
+    const uint64_t root_masks = ((uint64_t)live_mask << 32) | (PURE ? (uint64_t)live_mask << 40 : 0ull);
+    if (lane == 0) {
+        if (w.k == 0) {
+            stk[0] = 1ull | root_masks;
+        } else {
+            stk[0] = 3ull | root_masks;
+            stk[1] = 2ull | root_masks;
+        }
+    }
+    int sp = w.k == 0 ? 1 : 2;
+    __builtin_amdgcn_wave_barrier();
+    bool overflow = false;
+    while (sp > 0) {
+        const int b = sp < kWave ? sp : kWave;
+        sp -= b;
+        const bool act = lane < b;
+        const uint64_t ent = stk[sp + (act ? lane : 0)];
+        const int32_t node = act ? (int32_t)(ent & 0xffffffffull) : 1;
+        const double4 gb = w.rec[2 * (int64_t)node];
+        const double4 cb = w.rec[2 * (int64_t)node + 1];
+        const bool live = act && gb.w >= 0.0;   // popped and non-empty
+        const bool isleaf = node >= nleaf;
+        const uint32_t gmask = live ? (uint32_t)(ent >> 32) & 0xffu : 0u;
+        const uint32_t nmask = PURE && live ? (uint32_t)(ent >> 40) & 0xffu : 0u;
+        const double H2 = cb.w * cb.w;
+        const int lvl = 31 - __builtin_clz((uint32_t)node);
+        uint32_t far = 0, keep = 0, cand = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const double4 ga = lf[i];
+            const double4 ca = lf[8 + i];
+            const double dg2 = dist2(ga.x, ga.y, ga.z, gb.x, gb.y, gb.z);
+            const double rs = (ga.w + gb.w) * kReachPad;
+            const bool reach = dg2 < rs * rs;
+            const double R2 = dist2(ca.x, ca.y, ca.z, cb.x, cb.y, cb.z);
+            const bool mac = H2 < w.theta2 * R2;
+            const bool g = (gmask >> i) & 1u;
+            bool acc, c;
+            if constexpr (PURE) {
+                const bool contains = ((A0 + i) >> (w.k - lvl)) == (int64_t)node;
+                acc = g && mac && !contains;
+                c = ((nmask >> i) & 1u) && reach;
+            } else {
+                acc = g && mac && !reach;
+                c = g && reach;
+            }
+            far |= (uint32_t)acc << i;
+            keep |= (uint32_t)(g && !acc) << i;
+            cand |= (uint32_t)c << i;
+        }
+        const uint32_t ogm = isleaf ? 0u : keep;                    // open for gravity
+        const uint32_t onm = PURE && !isleaf ? cand : 0u;           // open for neighbours
+        const uint32_t nm = isleaf ? keep : 0u;                     // near field
+        const uint32_t cm = isleaf ? cand : 0u;                     // neighbour candidate
+        const bool op = (ogm | onm) != 0u;
+        const uint64_t b_open = ballot(op);
+        const int no = __popcll(b_open);
+        if (sp + 2 * no > w.wcap) {
+            overflow = true;
+            break;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (op) {
+            const int r = rank_below(b_open);
+            const uint64_t masks = ((uint64_t)ogm << 32) | ((uint64_t)onm << 40);
+            stk[sp + 2 * r] = (uint64_t)(2 * node) | masks;
+            stk[sp + 2 * r + 1] = (uint64_t)(2 * node + 1) | masks;
+        }
+        __builtin_amdgcn_wave_barrier();
+        sp += 2 * no;
+        const bool hn = (nm | cm) != 0u;
+        const uint64_t b_near = ballot(hn);
+        if (hn) {
+            const int64_t i = nn + rank_below(b_near);
+            if (i < w.near_cap)
+                w.near_list[nbase + i] = (uint64_t)(uint32_t)node | ((uint64_t)nm << 32) | ((uint64_t)cm << 40);
+        }
+        nn += __popcll(b_near);
+        const bool hf = far != 0u;
+        const uint64_t b_far = ballot(hf);
+        if (hf) {
+            const int64_t i = nf + rank_below(b_far);
+            if (i < w.far_cap) w.far_list[fbase + i] = (uint64_t)(uint32_t)node | ((uint64_t)far << 32);
+        }
+        nf += __popcll(b_far);
+    }
+    if (overflow) {
+        if (lane == 0 && queue) queue[atomicAdd(&w.flag[6], 1)] = (int32_t)gi;
         return;
     }
     if (lane == 0) {
@@ -354,24 +507,43 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     std::vector<void *> tmp;
     int64_t *ncnt = (int64_t *)dalloc(t, sizeof(int64_t) * NG, s, tmp);
     int64_t *fcnt = (int64_t *)dalloc(t, sizeof(int64_t) * NG, s, tmp);
+    int32_t *queue = (int32_t *)dalloc(t, sizeof(int32_t) * NG, s, tmp);   // groups for k_walk_group
     int64_t cn, cf;
     slab_caps(NG, cn, cf);
     std::vector<void *> slabs;
     uint64_t *nslab = (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cn, s, slabs);
     uint64_t *fslab = (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cf, s, slabs);
     for (void *p : slabs) tmp.push_back(p);   // freed at the end unless kept
-    if (!ncnt || !fcnt || !nslab || !fslab) return RCB_ENOMEM;
+    if (!ncnt || !fcnt || !queue || !nslab || !fslab) return RCB_ENOMEM;
+    // RCB_WALK_WIDE_STACK (testing): a smaller wide-walk stack, so that more
+    // groups take the 8-wide walk
+    int wcap = kWStack;
+    if (const char *e = getenv("RCB_WALK_WIDE_STACK")) {
+        const int v = atoi(e);
+        if (v >= 2 && v < kWStack) wcap = v;
+    }
     WalkArgs w{t->wrec, t->nhnode, t->k, t->gk, NG, t->p.theta * t->p.theta, ncnt, fcnt,
-               nullptr, nullptr, cn, cf, nslab, fslab, t->dflag};
+               nullptr, nullptr, cn, cf, nslab, fslab, t->dflag, wcap};
     const unsigned grid = (unsigned)((NG + kWaves - 1) / kWaves);
     RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 4, s));
+    RCB_HIP(hipMemsetAsync(t->dflag + 6, 0, sizeof(int32_t), s));
     const bool pure = t->p.pure_mac != 0;
-    if (pure) k_walk_group<true><<<grid, kBlock, 0, s>>>(w);
-    else k_walk_group<false><<<grid, kBlock, 0, s>>>(w);
-    RCB_LAUNCH_CHECK("k_walk_group<slab>");
-    int32_t flags[4] = {0, 0, 0, 0};
-    RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
+    if (pure) k_walk_wide<true><<<grid, kBlock, 0, s>>>(w, queue);
+    else k_walk_wide<false><<<grid, kBlock, 0, s>>>(w, queue);
+    RCB_LAUNCH_CHECK("k_walk_wide<slab>");
+    int32_t flags[7] = {0, 0, 0, 0, 0, 0, 0};
+    RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 7, hipMemcpyDeviceToHost, s));
     RCB_HIP(hipStreamSynchronize(s));
+    const int64_t nq = flags[6];   // groups that outgrew the wide walk's stack
+    const unsigned gridq = (unsigned)((nq + kWaves - 1) / kWaves);
+    if (nq > 0) {
+        if (pure) k_walk_group<true><<<gridq, kBlock, 0, s>>>(w, queue, nq);
+        else k_walk_group<false><<<gridq, kBlock, 0, s>>>(w, queue, nq);
+        RCB_LAUNCH_CHECK("k_walk_group<slab>");
+        RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
+        RCB_HIP(hipStreamSynchronize(s));
+    }
+    t->walk_requeued = nq;
     if (flags[0]) {
         set_error("walk: stack overflow (tree deeper than the walk stack supports)");
         return RCB_ECAPACITY;
@@ -415,9 +587,14 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
         w.near_cap = w.far_cap = INT64_MAX;
         w.near_list = t->gnear;
         w.far_list = t->gfar;
-        if (pure) k_walk_group<true><<<grid, kBlock, 0, s>>>(w);
-        else k_walk_group<false><<<grid, kBlock, 0, s>>>(w);
-        RCB_LAUNCH_CHECK("k_walk_group<exact>");
+        if (pure) k_walk_wide<true><<<grid, kBlock, 0, s>>>(w, nullptr);
+        else k_walk_wide<false><<<grid, kBlock, 0, s>>>(w, nullptr);
+        RCB_LAUNCH_CHECK("k_walk_wide<exact>");
+        if (nq > 0) {
+            if (pure) k_walk_group<true><<<gridq, kBlock, 0, s>>>(w, queue, nq);
+            else k_walk_group<false><<<gridq, kBlock, 0, s>>>(w, queue, nq);
+            RCB_LAUNCH_CHECK("k_walk_group<exact>");
+        }
     }
     int32_t *long_q = nullptr;
     if (nlong > 0) {

@@ -355,6 +355,7 @@ rcb_status rcb_get_info(const rcb_tree *t, rcb_tree_info *info) {
     info->near_total = t->leaf_lists ? t->near_total : -1;
     info->far_total = t->leaf_lists ? t->far_total : -1;
     info->theta = t->p.theta;
+    info->walk_requeued = t->walked ? t->walk_requeued : -1;
     return RCB_OK;
 }
 
