@@ -18,12 +18,9 @@
 // are taken by ballot within the sink's lane segment, so each list keeps tree
 // order. The count call writes the ids into a slab of kNbCap slots per
 // particle as well as the counts; the fill call then compacts the slab into
-// the caller's CSR. Ids of rank >= kNbCap go as (particle, rank, id) into an
-// overflow pool that the fill call places directly; only if the pool itself
-// runs out are the groups holding such a particle searched again, writing at
-// offsets[a] + rank.
-#include <algorithm>
-
+// the caller's CSR; the lowest-level cells holding a particle with more
+// neighbours than the slab takes (queued by the count call) are searched
+// again, one wave each, writing at offsets[a] + rank.
 #include "near_tile.h"
 #include "rcb_internal.h"
 
@@ -49,10 +46,10 @@ struct NeighArgs {
     const int64_t *offsets;   // fill mode: list starts (caller order)
     int32_t *ids;             // fill mode: final lists; slab mode: kNbCap slots per particle
     int32_t *flag;            // slab mode: particles with more than kNbCap neighbours
-    int32_t *gover;           // per group: 1 if one of its particles outgrew the slab
-    int32_t *ovf;             // slab mode: overflow pool, (caller index, rank, id) per entry
-    unsigned long long *ovf_n;   // entries claimed in the pool (may pass ovf_cap)
-    int64_t ovf_cap;
+    int32_t *queue;           // leaves (index from 0) holding such a particle: appended in slab
+                              // mode, searched again (wave i: queue[i]) otherwise
+    int32_t *nqueue;          // slab mode: entries appended
+    int64_t nq;               // fill mode: entries to search
 };
 
 struct alignas(16) SrcN {
@@ -76,18 +73,31 @@ template <bool SLAB>
 __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
     __shared__ NeighShared sh_all[kWaves];
     NeighShared &sh = sh_all[threadIdx.x / kWave];
-    const int64_t gi = wave_index();
-    if (gi >= a.ngroup) return;
     const int lane = lane_id();
     const int G = 1 << a.gk;
+    int64_t gi;
+    int li0, li1;   // the group's leaves to search
+    if constexpr (SLAB) {
+        gi = wave_index();
+        if (gi >= a.ngroup) return;
+        li0 = 0;
+        li1 = G;
+    } else {
+        const int64_t q = wave_index();
+        if (q >= a.nq) return;
+        const int32_t l = a.queue[q];
+        gi = l >> a.gk;
+        li0 = l & (G - 1);
+        li1 = li0 + 1;
+    }
     const int64_t GL = (a.nleaf >> a.gk) + gi;
     if (a.ncount[GL] == 0) return;
-    if (!SLAB && a.gover && a.gover[gi] == 0) return;   // its lists came from the slab
     const int64_t n0 = a.gnear_beg[gi], n1 = a.gnear_end[gi];
-    for (int li = 0; li < G; ++li) {
+    for (int li = li0; li < li1; ++li) {
         const int64_t A = a.nleaf + gi * G + li;
         const int32_t sA = a.nfirst[A], c = a.ncount[A];
         if (c == 0) continue;
+        bool leaf_over = false;   // slab mode: a sink of this leaf outgrew the slab
         const LeafLanes L = leaf_lanes(c);
         const uint64_t segmask = seg_mask(L);
         const double4 gA = a.rec[2 * A];
@@ -111,14 +121,6 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
                     const uint64_t bal = ballot(hit) & segmask;
                     const int r = cnt + rank_below(bal);
                     if (hit && (!SLAB || r < kNbCap)) a.ids[obase + r] = s.id;
-                    if (SLAB && hit && r >= kNbCap) {
-                        const unsigned long long o = atomicAdd(a.ovf_n, 1ull);
-                        if (o < (unsigned long long)a.ovf_cap) {
-                            a.ovf[3 * o] = oa;
-                            a.ovf[3 * o + 1] = r;
-                            a.ovf[3 * o + 2] = s.id;
-                        }
-                    }
                     cnt += __popcll(bal);
                 }
             };
@@ -194,10 +196,11 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
                 a.counts[oa] = cnt;
                 if (cnt > kNbCap) {
                     atomicAdd(a.flag, 1);
-                    a.gover[gi] = 1;
+                    leaf_over = true;
                 }
             }
         }
+        if (SLAB && ballot(leaf_over) != 0ull && lane == 0) a.queue[atomicAdd(a.nqueue, 1)] = (int32_t)(A - a.nleaf);
     }
 }
 
@@ -210,17 +213,9 @@ __global__ __launch_bounds__(kBlock) void k_nb_compact(int64_t n, const int32_t 
     const int j0 = threadIdx.x % 16;
     if (p >= n) return;
     const int32_t a = pid[p];
-    const int64_t o = offsets[a], c = std::min<int64_t>(offsets[a + 1] - o, kNbCap);
+    const int64_t o = offsets[a], c = offsets[a + 1] - o;
+    if (c > kNbCap) return;   // searched again by its group
     for (int64_t j = j0; j < c; j += 16) ids[o + j] = slab[p * kNbCap + j];
-}
-
-// overflow pool entries to their places in the CSR
-__global__ __launch_bounds__(kBlock) void k_nb_ovf(int64_t cnt, const int32_t *__restrict__ ovf,
-                                                   const int64_t *__restrict__ offsets,
-                                                   int32_t *__restrict__ ids) {
-    const int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (e >= cnt) return;
-    ids[offsets[ovf[3 * e]] + ovf[3 * e + 1]] = ovf[3 * e + 2];
 }
 
 }  // namespace
@@ -234,36 +229,29 @@ rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipSt
     std::vector<void *> tmp;
     int64_t *counts = (int64_t *)dalloc(t, sizeof(int64_t) * t->n, s, tmp);
     if (!counts) return RCB_ENOMEM;
-    const int64_t ovf_cap = std::max<int64_t>(int64_t(1) << 20, t->n / 4);
     if (!t->nb_slab) {
         t->nb_slab = (int32_t *)dalloc(t, sizeof(int32_t) * t->n * kNbCap, s, t->list_allocs);
-        t->nb_gover = (int32_t *)dalloc(t, sizeof(int32_t) * t->ngroup, s, t->list_allocs);
-        t->nb_ovf = (int32_t *)dalloc(t, sizeof(int32_t) * 3 * ovf_cap, s, t->list_allocs);
-        t->nb_ovf_cnt = (unsigned long long *)dalloc(t, sizeof(unsigned long long), s, t->list_allocs);
-        if (!t->nb_slab || !t->nb_gover || !t->nb_ovf || !t->nb_ovf_cnt) return RCB_ENOMEM;
+        t->nb_queue = (int32_t *)dalloc(t, sizeof(int32_t) * t->nleaf, s, t->list_allocs);
+        if (!t->nb_slab || !t->nb_queue) return RCB_ENOMEM;
     }
     RCB_HIP(hipMemsetAsync(t->dflag + 4, 0, sizeof(int32_t), s));
-    RCB_HIP(hipMemsetAsync(t->nb_ovf_cnt, 0, sizeof(unsigned long long), s));
-    RCB_HIP(hipMemsetAsync(t->nb_gover, 0, sizeof(int32_t) * t->ngroup, s));
+    RCB_HIP(hipMemsetAsync(t->dflag + 7, 0, sizeof(int32_t), s));
     NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
                 t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, counts, nullptr, t->nb_slab,
-                t->dflag + 4, t->nb_gover, t->nb_ovf, t->nb_ovf_cnt, ovf_cap};
+                t->dflag + 4, t->nb_queue, t->dflag + 7, 0};
     const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     k_neigh<true><<<grid, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_neigh<slab>");
     st = scan_i64(t, counts, offsets, t->n, s);
     if (st != RCB_OK) return st;
-    int32_t over = 0;
-    unsigned long long novf = 0;
+    int32_t over[4] = {0, 0, 0, 0};   // dflag[4..7]: particles past the slab, ..., leaves queued
     RCB_HIP(hipMemcpyAsync(total, offsets + t->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RCB_HIP(hipMemcpyAsync(&over, t->dflag + 4, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    RCB_HIP(hipMemcpyAsync(&novf, t->nb_ovf_cnt, sizeof(novf), hipMemcpyDeviceToHost, s));
+    RCB_HIP(hipMemcpyAsync(over, t->dflag + 4, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
     for (void *p : tmp) dfree(t, p, s);
     RCB_HIP(hipStreamSynchronize(s));
     t->nb_total = *total;
-    t->nb_over = over;
-    t->nb_ovf_ok = novf <= (unsigned long long)ovf_cap;
-    t->nb_ovf_n = t->nb_ovf_ok ? (int64_t)novf : 0;
+    t->nb_over = over[0];
+    t->nb_nq = over[3];
     return RCB_OK;
 }
 
@@ -281,15 +269,11 @@ rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, in
     const unsigned gridc = (unsigned)((t->n * 16 + kBlock - 1) / kBlock);
     k_nb_compact<<<gridc, kBlock, 0, s>>>(t->n, t->pid, offsets, t->nb_slab, ids);
     RCB_LAUNCH_CHECK("k_nb_compact");
-    if (t->nb_over > 0 && t->nb_ovf_ok) {
-        k_nb_ovf<<<(unsigned)((t->nb_ovf_n + kBlock - 1) / kBlock), kBlock, 0, s>>>(t->nb_ovf_n, t->nb_ovf,
-                                                                                    offsets, ids);
-        RCB_LAUNCH_CHECK("k_nb_ovf");
-    } else if (t->nb_over > 0) {
+    if (t->nb_nq > 0) {
         NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
                     t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids, nullptr,
-                    t->nb_gover, nullptr, nullptr, 0};
-        const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
+                    t->nb_queue, nullptr, t->nb_nq};
+        const unsigned grid = (unsigned)((t->nb_nq + kWaves - 1) / kWaves);
         k_neigh<false><<<grid, kBlock, 0, s>>>(a);
         RCB_LAUNCH_CHECK("k_neigh<fill>");
     }

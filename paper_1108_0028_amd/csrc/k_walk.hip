@@ -275,9 +275,11 @@ __global__ __launch_bounds__(kBlock) void k_walk_wide(WalkArgs w, int32_t *queue
         const uint32_t nmask = PURE && live ? (uint32_t)(ent >> 40) & 0xffu : 0u;
         const double H2 = cb.w * cb.w;
         const int lvl = 31 - __builtin_clz((uint32_t)node);
-        uint32_t far = 0, keep = 0, cand = 0;
+        // per leaf (last to first, shifted in): accepted were it visited, and
+        // reachable; the visit masks are applied afterwards
+        uint32_t acc_raw = 0, reach_raw = 0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 7; i >= 0; --i) {
             const double4 ga = lf[i];
             const double4 ca = lf[8 + i];
             const double dg2 = dist2(ga.x, ga.y, ga.z, gb.x, gb.y, gb.z);
@@ -285,20 +287,19 @@ __global__ __launch_bounds__(kBlock) void k_walk_wide(WalkArgs w, int32_t *queue
             const bool reach = dg2 < rs * rs;
             const double R2 = dist2(ca.x, ca.y, ca.z, cb.x, cb.y, cb.z);
             const bool mac = H2 < w.theta2 * R2;
-            const bool g = (gmask >> i) & 1u;
-            bool acc, c;
+            bool acc;
             if constexpr (PURE) {
                 const bool contains = ((A0 + i) >> (w.k - lvl)) == (int64_t)node;
-                acc = g && mac && !contains;
-                c = ((nmask >> i) & 1u) && reach;
+                acc = mac && !contains;
             } else {
-                acc = g && mac && !reach;
-                c = g && reach;
+                acc = mac && !reach;
             }
-            far |= (uint32_t)acc << i;
-            keep |= (uint32_t)(g && !acc) << i;
-            cand |= (uint32_t)c << i;
+            acc_raw = acc_raw + acc_raw + (uint32_t)acc;
+            reach_raw = reach_raw + reach_raw + (uint32_t)reach;
         }
+        const uint32_t far = acc_raw & gmask;
+        const uint32_t keep = gmask & ~far;
+        const uint32_t cand = reach_raw & (PURE ? nmask : gmask);
         const uint32_t ogm = isleaf ? 0u : keep;                    // open for gravity
         const uint32_t onm = PURE && !isleaf ? cand : 0u;           // open for neighbours
         const uint32_t nm = isleaf ? keep : 0u;                     // near field

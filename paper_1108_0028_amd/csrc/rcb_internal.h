@@ -83,8 +83,9 @@ struct rcb_tree {
     int32_t *near_list = nullptr, *far_list = nullptr;
     int64_t nb_total = -1;             // neighbour total of the last count call
     int32_t *nb_slab = nullptr;        // neighbour ids of the count call, kNbCap per particle
-    int32_t *nb_gover = nullptr;       // groups with a particle of more than kNbCap neighbours
+    int32_t *nb_queue = nullptr;       // leaves with a particle of more than kNbCap neighbours
     int32_t nb_over = 0;               // particles with more than kNbCap neighbours
+    int32_t nb_nq = 0;                 // entries of nb_queue
     int32_t *nb_ovf = nullptr;         // their ids past kNbCap: (caller index, rank, id) triples
     unsigned long long *nb_ovf_cnt = nullptr;   // triples claimed (may exceed the pool)
     int64_t nb_ovf_n = 0;              // triples claimed by the last count call
@@ -92,7 +93,7 @@ struct rcb_tree {
     // device flags: [0] walk stack overflow, [1] long near lists, [2] their
     // queue, [3] groups outgrowing the list slabs, [4] particles outgrowing
     // the neighbour slab, [5] median selection, [6] groups outgrowing the
-    // wide walk's stack
+    // wide walk's stack, [7] leaves queued for the neighbour re-search
     int32_t *dflag = nullptr;
     int64_t walk_requeued = 0;         // groups of the last walk taken by k_walk_group
 

@@ -1,13 +1,12 @@
 """Neighbour lists longer than the per-particle slab of the count call
-(Sec. 2.3 "Neighbour list"): the ranks past it go through an overflow pool
-that the fill call places, and when the pool itself runs out the groups
-holding such particles are searched again. Both routes must give the
-oracle's CSR exactly (lists in tree order), and the all-pairs sets.
+(Sec. 2.3 "Neighbour list"): the count call keeps the first 192 ids of each
+particle and queues the lowest-level cells holding a longer list; the fill
+call searches those cells again, one wave each, writing whole lists. The CSR
+must be the oracle's exactly (lists in tree order), and the all-pairs sets.
 
-  uniform, h x 2:    mean ~190, max ~680 neighbours; ~3.5e5 entries past the
-                     slab, which the pool (>= 2^20 entries) holds
-  uniform, h x 40:   every pair; ~8.4e6 entries past the slab, more than the
-                     pool: the re-search route
+  uniform, h x 2:    mean ~190, max ~680 neighbours (~40% of the particles
+                     past the slab)
+  uniform, h x 40:   every pair (all cells queued)
 """
 import numpy as np
 import pytest
