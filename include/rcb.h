@@ -195,6 +195,9 @@ rcb_status rcb_neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids
  * cells accepted by the MAC H_B / R_AB < theta (reachable cells are never
  * accepted unless pure_mac; with RCB_READING_B, J_A and H_A of the monopole
  * parts only). ax, ay, az: n values, FP64 for RCB_FP64, FP32 for RCB_MIXED.
+ * The tree keeps f_A, J_A, H_A of every lowest-level cell (22 doubles per
+ * cell, allocated on the first call) for a later rcb_gravity_vjp on the same
+ * moments; rcb_refresh discards them.
  */
 rcb_status rcb_gravity(rcb_tree *t, void *ax, void *ay, void *az, void *stream);
 

@@ -1394,6 +1394,7 @@ rcb_status count_outside(rcb_tree *t, const double *x, const double *y, const do
 rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const double *z,
                         const double *m, const double *h, hipStream_t s) {
     const int64_t n = t->n;
+    t->farc_valid = false;   // the kept far coefficients belong to the old moments
     std::vector<void *> tmp;
     auto A = [&](size_t bytes) { return dalloc(t, bytes, s, tmp); };
     BuildScratch b{};

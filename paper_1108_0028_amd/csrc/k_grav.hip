@@ -47,6 +47,7 @@ struct GravArgs {
     const float *fdx, *fdy, *fdz, *fm, *fh;
     const int32_t *pid;
     void *ax, *ay, *az;
+    double *farc;   // if given: each leaf's far coefficients at farc[leaf * kLeafC]
 };
 
 // Far-field coefficients of the group's leaves into coef[8][19] (LDS).
@@ -176,6 +177,8 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
     const int64_t GL = (g.nleaf >> g.gk) + gi;   // group node label
     if (g.ncount[GL] == 0) return;
     group_far<RB>(g, gi, sh.fw, sh.coef);
+    if (g.farc)
+        for (int i = lane; i < G * 19; i += kWave) g.farc[(gi * G + i / 19) * kLeafC + i % 19] = sh.coef[i / 19][i % 19];
     using Src = typename std::conditional<MIXED, SrcF, SrcD>::type;
     Src dummy;
     dummy.x = dummy.y = dummy.z = dummy.m = 0;
@@ -305,7 +308,7 @@ rcb_status far_coefficients(rcb_tree *t, double *out, int stride, hipStream_t s)
     if (st != RCB_OK) return st;
     GravArgs g{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
                t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
-               t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, nullptr, nullptr, nullptr};
+               t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, nullptr, nullptr, nullptr, nullptr};
     const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     k_far_coeffs<<<grid, kBlock, 0, s>>>(g, out, stride);
     RCB_LAUNCH_CHECK("k_far_coeffs");
@@ -315,11 +318,17 @@ rcb_status far_coefficients(rcb_tree *t, double *out, int stride, hipStream_t s)
 rcb_status gravity(rcb_tree *t, void *ax, void *ay, void *az, hipStream_t s) {
     rcb_status st = ensure_walk(t, s);
     if (st != RCB_OK) return st;
+    const bool rb = t->p.taylor_reading == RCB_READING_B;
+    // the far coefficients are kept for a VJP on the same moments
+    if (!rb && !t->farc) {
+        t->farc = (double *)dalloc(t, sizeof(double) * kLeafC * t->nleaf, s, t->list_allocs);
+        if (!t->farc) return RCB_ENOMEM;
+    }
+    double *farc = rb ? nullptr : t->farc;
     GravArgs g{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
                t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
-               t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, ax, ay, az};
+               t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, ax, ay, az, farc};
     const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
-    const bool rb = t->p.taylor_reading == RCB_READING_B;
     if (t->p.precision == RCB_MIXED) {
         if (rb) k_gravity<true, true><<<grid, kBlock, 0, s>>>(g);
         else k_gravity<true, false><<<grid, kBlock, 0, s>>>(g);
@@ -328,6 +337,7 @@ rcb_status gravity(rcb_tree *t, void *ax, void *ay, void *az, hipStream_t s) {
         else k_gravity<false, false><<<grid, kBlock, 0, s>>>(g);
     }
     RCB_LAUNCH_CHECK("k_gravity");
+    if (farc) t->farc_valid = true;
     return RCB_OK;
 }
 

@@ -37,7 +37,6 @@ constexpr int kAdj = 10;    // M, R(3), Q(6)
 constexpr int kAdjCopies = 8;   // node-adjoint copies filled by k_vjp_far
 constexpr int kAcc = 30;    // G0(3), G1(9), G2(18) while accumulating
 constexpr int kMom = 23;    // S1(3), S2(6), S3(10), t1, sg(3): far_math.h SymMoments
-constexpr int kLeafC = 22;  // 19 far coefficients + cot(3)
 
 using rcbfar::hidx;
 using rcbfar::jidx;
@@ -490,7 +489,11 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     double *src = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
     double *adj = (double *)dalloc(t, sizeof(double) * kAdjCopies * kAdj * t->nlab, s, tmp);
     double *mom = (double *)dalloc(t, sizeof(double) * kMom * t->nleaf, s, tmp);
-    double *leafc = (double *)dalloc(t, sizeof(double) * kLeafC * t->nleaf, s, tmp);
+    if (!t->farc) {
+        t->farc = (double *)dalloc(t, sizeof(double) * kLeafC * t->nleaf, s, t->list_allocs);
+        t->farc_valid = false;
+    }
+    double *leafc = t->farc;   // 19 far coefficients + the leaf's cotangent sum per leaf
     if (!sink || !src || !adj || !mom || !leafc) return RCB_ENOMEM;
     RCB_HIP(hipMemsetAsync(src, 0, sizeof(double) * 4 * n, s));
     RCB_HIP(hipMemsetAsync(adj, 0, sizeof(double) * kAdjCopies * kAdj * t->nlab, s));
@@ -502,8 +505,11 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     if (mixed) k_vjp_moments<true><<<gridg, kBlock, 0, s>>>(a);
     else k_vjp_moments<false><<<gridg, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_vjp_moments");
-    st = far_coefficients(t, leafc, kLeafC, s);
-    if (st != RCB_OK) return st;
+    if (!t->farc_valid) {   // else kept by the last rcb_gravity on these moments
+        st = far_coefficients(t, leafc, kLeafC, s);
+        if (st != RCB_OK) return st;
+        t->farc_valid = true;
+    }
 
     k_vjp_far<<<gridg, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_vjp_far");

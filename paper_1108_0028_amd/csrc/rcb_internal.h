@@ -23,6 +23,8 @@
 
 namespace rcb {
 
+constexpr int kLeafC = 22;   // doubles per leaf in rcb_tree::farc
+
 constexpr int kWave = 64;
 constexpr int kChunk = 512;          // elements per wave item of the big-node passes
 constexpr int kStackCap = 2048;      // LIFO walk stack entries per wave (LDS)
@@ -96,6 +98,10 @@ struct rcb_tree {
     // wide walk's stack, [7] leaves queued for the neighbour re-search
     int32_t *dflag = nullptr;
     int64_t walk_requeued = 0;         // groups of the last walk taken by k_walk_group
+    // per leaf: the 19 far-field coefficients of the current moments (written
+    // by rcb_gravity, or by the VJP if no gravity call has) and 3 VJP scratch values
+    double *farc = nullptr;
+    bool farc_valid = false;
 
     std::vector<void *> allocs;        // everything to free on destroy
     std::vector<void *> list_allocs;
