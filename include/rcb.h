@@ -221,9 +221,9 @@ typedef struct {
     int64_t near_total;   /* interaction-list sizes, -1 until the walk has run */
     int64_t far_total;
     double theta;
-    int64_t walk_requeued; /* groups of the last walk whose stack outgrew the wide walk's
-                              and that the 8-wide walk took instead (same lists); -1 before
-                              the walk */
+    int64_t walk_requeued; /* groups of 8 lowest-level cells whose walk outgrew the first
+                              FIFO (1024 nodes) and was redone with a larger one or, past
+                              8192 nodes, by the 8-wide walk (same lists); -1 before the walk */
 } rcb_tree_info;
 
 rcb_status rcb_get_info(const rcb_tree *t, rcb_tree_info *info /* host */);

@@ -26,17 +26,19 @@
 // Two kernels walk a group. k_walk_wide, the one normally run, gives each
 // lane one popped stack entry (up to 64 per round) and tests it against all
 // the group's leaves in turn, so a node costs one record load and one set
-// of list/stack bookkeeping for 8 leaf tests; its LDS stack holds kWStack
+// of list/stack bookkeeping for 8 leaf tests; its LDS ring holds kWQueue
 // entries, and a group that would outgrow it is queued and walked again by
 // k_walk_group, whose lanes are (pending entry, leaf) and whose stack bound
 // is proved below. Both make the same per-leaf decisions; their lists differ
-// only in order.
+// only in order (the wide walk's near lists are sorted by label, the 8-wide
+// walk's are sorted afterwards).
 //
 // Output per group: a near list of (label, near mask, candidate mask) and a
 // far list of (label, far mask) -- the union of the group's per-leaf lists.
 // Near lists are sorted by label, so each leaf's candidates (and neighbour
 // lists) come out in tree order. Two launches: count, then fill after a
 // scan of the sizes. Per-leaf lists for inspection are expanded on demand.
+#include <algorithm>
 #include <cstdlib>
 
 #include "rcb_internal.h"
@@ -68,7 +70,6 @@ struct WalkArgs {
     int64_t near_cap, far_cap;
     uint64_t *near_list, *far_list;
     int32_t *flag;
-    int wcap;   // k_walk_wide: stack entries used (<= kWStack)
 };
 
 // bit 8 s set iff byte s of x is non-zero (the lead lane of entry s)
@@ -208,24 +209,34 @@ __global__ __launch_bounds__(kBlock) void k_walk_group(WalkArgs w, const int32_t
     }
 }
 
-// Wide walk: lane j holds the j-th popped entry; its node record is loaded
-// once and tested against each leaf of the group (records in LDS), and the
-// per-leaf decisions of the header become 8-bit masks per lane. The stack
-// keeps the order argument of k_walk_group (children pushed in the order of
-// their parents), with up to 64 pops per round; at 4M particles its depth
-// stays near 300 entries. A group whose pushes would pass kWStack stops: if
-// queue is given its index is appended (flag[6] counts them) for k_walk_group
-// to walk again, writing counts and lists over whatever this one wrote.
-constexpr int kWStack = 768;
+// Wide walk: lane j holds the j-th entry taken from the front of a FIFO ring
+// in LDS; its node record is loaded once and tested against each leaf of the
+// group (records in LDS), and the per-leaf decisions of the header become
+// 8-bit masks per lane. Children are appended in the order of their parents,
+// so nodes are visited level by level and, within a level, by increasing
+// label: near entries (always lowest-level cells) come out sorted by label,
+// as the neighbour lists' tree order needs, with no sort. At 4M particles
+// the ring holds up to ~800 entries. A group whose appends would pass the
+// ring stops: if queue is given its index is appended (flag[6] counts them)
+// for the next tier to walk again, writing counts and lists over whatever
+// this one wrote: the same kernel with a ring of kWQueue2 entries (one wave
+// per block), then k_walk_group (and k_sort_lists for its near lists).
+// only: if given, wave i walks group only[i] (i < nonly).
+constexpr int kWQueue = 1024;    // powers of two
+constexpr int kWQueue2 = 8192;
 
-template <bool PURE>
-__global__ __launch_bounds__(kBlock) void k_walk_wide(WalkArgs w, int32_t *queue) {
-    __shared__ uint64_t stk_all[kWaves][kWStack];
-    __shared__ double4 leaf_all[kWaves][16];   // per leaf: (g, h_node), (com, -)
-    uint64_t *stk = stk_all[threadIdx.x / kWave];
+template <bool PURE, int QCAP, int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void k_walk_wide(WalkArgs w, int32_t *queue, int32_t *nqueue,
+                                                             const int32_t *only, int64_t nonly, int cap) {
+    __shared__ uint32_t qlab_all[WAVES][QCAP];   // ring: node label
+    __shared__ uint16_t qmsk_all[WAVES][QCAP];   // and gravity | neighbour << 8 masks
+    __shared__ double4 leaf_all[WAVES][16];      // per leaf: (g, h_node), (com, -)
+    uint32_t *qlab = qlab_all[threadIdx.x / kWave];
+    uint16_t *qmsk = qmsk_all[threadIdx.x / kWave];
     double4 *lf = leaf_all[threadIdx.x / kWave];
-    const int64_t gi = wave_index();
-    if (gi >= w.ngroup) return;
+    const int64_t wi = wave_index();
+    if (wi >= (only ? nonly : w.ngroup)) return;
+    const int64_t gi = only ? (int64_t)only[wi] : wi;
     const int lane = lane_id();
     const int G = 1 << w.gk;
     const int64_t nleaf = (int64_t)1 << w.k;
@@ -249,30 +260,35 @@ __global__ __launch_bounds__(kBlock) void k_walk_wide(WalkArgs w, int32_t *queue
         }
         return;
     }
-    const uint64_t root_masks = ((uint64_t)live_mask << 32) | (PURE ? (uint64_t)live_mask << 40 : 0ull);
+    const uint16_t root_masks = (uint16_t)(live_mask | (PURE ? live_mask << 8 : 0u));
     if (lane == 0) {
         if (w.k == 0) {
-            stk[0] = 1ull | root_masks;
+            qlab[0] = 1u;
+            qmsk[0] = root_masks;
         } else {
-            stk[0] = 3ull | root_masks;
-            stk[1] = 2ull | root_masks;
+            qlab[0] = 2u;
+            qlab[1] = 3u;
+            qmsk[0] = qmsk[1] = root_masks;
         }
     }
-    int sp = w.k == 0 ? 1 : 2;
+    int head = 0, cnt = w.k == 0 ? 1 : 2;   // ring [head, head + cnt), indices mod kWQueue
     __builtin_amdgcn_wave_barrier();
     bool overflow = false;
-    while (sp > 0) {
-        const int b = sp < kWave ? sp : kWave;
-        sp -= b;
+    while (cnt > 0) {
+        const int b = cnt < kWave ? cnt : kWave;
         const bool act = lane < b;
-        const uint64_t ent = stk[sp + (act ? lane : 0)];
-        const int32_t node = act ? (int32_t)(ent & 0xffffffffull) : 1;
+        const int slot = (head + (act ? lane : 0)) & (QCAP - 1);
+        const uint32_t qm = qmsk[slot];
+        const int32_t node = act ? (int32_t)qlab[slot] : 1;
+        head = (head + b) & (QCAP - 1);
+        cnt -= b;
+        const int tail = (head + cnt) & (QCAP - 1);
         const double4 gb = w.rec[2 * (int64_t)node];
         const double4 cb = w.rec[2 * (int64_t)node + 1];
-        const bool live = act && gb.w >= 0.0;   // popped and non-empty
+        const bool live = act && gb.w >= 0.0;   // taken and non-empty
         const bool isleaf = node >= nleaf;
-        const uint32_t gmask = live ? (uint32_t)(ent >> 32) & 0xffu : 0u;
-        const uint32_t nmask = PURE && live ? (uint32_t)(ent >> 40) & 0xffu : 0u;
+        const uint32_t gmask = live ? qm & 0xffu : 0u;
+        const uint32_t nmask = PURE && live ? (qm >> 8) & 0xffu : 0u;
         const double H2 = cb.w * cb.w;
         const int lvl = 31 - __builtin_clz((uint32_t)node);
         // per leaf (last to first, shifted in): accepted were it visited, and
@@ -307,19 +323,24 @@ __global__ __launch_bounds__(kBlock) void k_walk_wide(WalkArgs w, int32_t *queue
         const bool op = (ogm | onm) != 0u;
         const uint64_t b_open = ballot(op);
         const int no = __popcll(b_open);
-        if (sp + 2 * no > w.wcap) {
+        if (cnt + 2 * no > cap) {
             overflow = true;
             break;
         }
+        // the appended slots lie outside [head, head + cnt) (cnt + 2 no <=
+        // cap <= QCAP); some are the ones just taken, read above
         __builtin_amdgcn_wave_barrier();
         if (op) {
             const int r = rank_below(b_open);
-            const uint64_t masks = ((uint64_t)ogm << 32) | ((uint64_t)onm << 40);
-            stk[sp + 2 * r] = (uint64_t)(2 * node) | masks;
-            stk[sp + 2 * r + 1] = (uint64_t)(2 * node + 1) | masks;
+            const uint16_t masks = (uint16_t)(ogm | (onm << 8));
+            const int s0 = (tail + 2 * r) & (QCAP - 1), s1 = (tail + 2 * r + 1) & (QCAP - 1);
+            qlab[s0] = (uint32_t)(2 * node);
+            qlab[s1] = (uint32_t)(2 * node + 1);
+            qmsk[s0] = masks;
+            qmsk[s1] = masks;
         }
         __builtin_amdgcn_wave_barrier();
-        sp += 2 * no;
+        cnt += 2 * no;
         const bool hn = (nm | cm) != 0u;
         const uint64_t b_near = ballot(hn);
         if (hn) {
@@ -337,13 +358,12 @@ __global__ __launch_bounds__(kBlock) void k_walk_wide(WalkArgs w, int32_t *queue
         nf += __popcll(b_far);
     }
     if (overflow) {
-        if (lane == 0 && queue) queue[atomicAdd(&w.flag[6], 1)] = (int32_t)gi;
+        if (lane == 0 && queue) queue[atomicAdd(nqueue, 1)] = (int32_t)gi;
         return;
     }
     if (lane == 0) {
         w.near_cnt[gi] = nn;
         w.far_cnt[gi] = nf;
-        if (nn > kSortCap) atomicAdd(&w.flag[1], 1);
         if (nn > w.near_cap || nf > w.far_cap) atomicAdd(&w.flag[3], 1);
     }
 }
@@ -362,10 +382,11 @@ __global__ __launch_bounds__(kBlock) void k_slab_ends(int64_t ngroup, int64_t ne
     fend[g] = g * far_cap + fcnt[g];
 }
 
-// Sort each group's list by label (bitonic network in LDS, one wave per
-// group, CAP entries at most). Longer lists are queued for k_sort_long.
+// Sort the near lists of the groups walked by k_walk_group by label (bitonic
+// network in LDS, one wave per group, CAP entries at most): wave i takes group
+// only[i]. Longer lists are queued for k_sort_long.
 template <int CAP, int WAVES>
-__global__ __launch_bounds__(WAVES * kWave) void k_sort_lists(int64_t ngroup,
+__global__ __launch_bounds__(WAVES * kWave) void k_sort_lists(int64_t nonly, const int32_t *__restrict__ only,
                                                               const int64_t *__restrict__ beg,
                                                               const int64_t *__restrict__ end,
                                                               uint64_t *__restrict__ list,
@@ -373,8 +394,9 @@ __global__ __launch_bounds__(WAVES * kWave) void k_sort_lists(int64_t ngroup,
                                                               int32_t *__restrict__ long_q) {
     __shared__ uint64_t buf_all[WAVES][CAP];
     uint64_t *buf = buf_all[threadIdx.x / kWave];
-    const int64_t gi = wave_index();
-    if (gi >= ngroup) return;
+    const int64_t wi = wave_index();
+    if (wi >= nonly) return;
+    const int64_t gi = only[wi];
     const int lane = lane_id();
     const int64_t nbase = beg[gi];
     const int64_t nn = end[gi] - nbase;
@@ -508,42 +530,67 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     std::vector<void *> tmp;
     int64_t *ncnt = (int64_t *)dalloc(t, sizeof(int64_t) * NG, s, tmp);
     int64_t *fcnt = (int64_t *)dalloc(t, sizeof(int64_t) * NG, s, tmp);
-    int32_t *queue = (int32_t *)dalloc(t, sizeof(int32_t) * NG, s, tmp);   // groups for k_walk_group
+    int32_t *queue = (int32_t *)dalloc(t, sizeof(int32_t) * NG, s, tmp);    // groups for the 2nd tier
+    int32_t *queue2 = (int32_t *)dalloc(t, sizeof(int32_t) * NG, s, tmp);   // and for k_walk_group
     int64_t cn, cf;
     slab_caps(NG, cn, cf);
     std::vector<void *> slabs;
     uint64_t *nslab = (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cn, s, slabs);
     uint64_t *fslab = (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cf, s, slabs);
     for (void *p : slabs) tmp.push_back(p);   // freed at the end unless kept
-    if (!ncnt || !fcnt || !queue || !nslab || !fslab) return RCB_ENOMEM;
-    // RCB_WALK_WIDE_STACK (testing): a smaller wide-walk stack, so that more
-    // groups take the 8-wide walk
-    int wcap = kWStack;
+    if (!ncnt || !fcnt || !queue || !queue2 || !nslab || !fslab) return RCB_ENOMEM;
+    // RCB_WALK_WIDE_STACK (testing): smaller wide-walk rings, so that more
+    // groups take the later tiers
+    int cap1 = kWQueue, cap2 = kWQueue2;
     if (const char *e = getenv("RCB_WALK_WIDE_STACK")) {
         const int v = atoi(e);
-        if (v >= 2 && v < kWStack) wcap = v;
+        if (v >= 2) {
+            cap1 = std::min(cap1, v);
+            cap2 = std::min(cap2, v);
+        }
     }
     WalkArgs w{t->wrec, t->nhnode, t->k, t->gk, NG, t->p.theta * t->p.theta, ncnt, fcnt,
-               nullptr, nullptr, cn, cf, nslab, fslab, t->dflag, wcap};
+               nullptr, nullptr, cn, cf, nslab, fslab, t->dflag};
     const unsigned grid = (unsigned)((NG + kWaves - 1) / kWaves);
-    RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 4, s));
-    RCB_HIP(hipMemsetAsync(t->dflag + 6, 0, sizeof(int32_t), s));
     const bool pure = t->p.pure_mac != 0;
-    if (pure) k_walk_wide<true><<<grid, kBlock, 0, s>>>(w, queue);
-    else k_walk_wide<false><<<grid, kBlock, 0, s>>>(w, queue);
-    RCB_LAUNCH_CHECK("k_walk_wide<slab>");
-    int32_t flags[7] = {0, 0, 0, 0, 0, 0, 0};
-    RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 7, hipMemcpyDeviceToHost, s));
+    // the three tiers over all groups, then over the groups each one queued;
+    // q1/q2 null: the queues are known (second pass) and are not appended to
+    int64_t nq = 0, nq2 = 0;
+    auto walk_tiers = [&](bool count_queues) -> rcb_status {
+        int32_t *q1 = count_queues ? queue : nullptr, *q2 = count_queues ? queue2 : nullptr;
+        if (pure) k_walk_wide<true, kWQueue, kWaves><<<grid, kBlock, 0, s>>>(w, q1, t->dflag + 6, nullptr, 0, cap1);
+        else k_walk_wide<false, kWQueue, kWaves><<<grid, kBlock, 0, s>>>(w, q1, t->dflag + 6, nullptr, 0, cap1);
+        RCB_LAUNCH_CHECK("k_walk_wide");
+        if (count_queues) {
+            int32_t c = 0;
+            RCB_HIP(hipMemcpyAsync(&c, t->dflag + 6, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            RCB_HIP(hipStreamSynchronize(s));
+            nq = c;
+        }
+        if (nq == 0) return RCB_OK;
+        if (pure) k_walk_wide<true, kWQueue2, 1><<<(unsigned)nq, kWave, 0, s>>>(w, q2, t->dflag + 7, queue, nq, cap2);
+        else k_walk_wide<false, kWQueue2, 1><<<(unsigned)nq, kWave, 0, s>>>(w, q2, t->dflag + 7, queue, nq, cap2);
+        RCB_LAUNCH_CHECK("k_walk_wide<2nd tier>");
+        if (count_queues) {
+            int32_t c = 0;
+            RCB_HIP(hipMemcpyAsync(&c, t->dflag + 7, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            RCB_HIP(hipStreamSynchronize(s));
+            nq2 = c;
+        }
+        if (nq2 == 0) return RCB_OK;
+        const unsigned gridq = (unsigned)((nq2 + kWaves - 1) / kWaves);
+        if (pure) k_walk_group<true><<<gridq, kBlock, 0, s>>>(w, queue2, nq2);
+        else k_walk_group<false><<<gridq, kBlock, 0, s>>>(w, queue2, nq2);
+        RCB_LAUNCH_CHECK("k_walk_group");
+        return RCB_OK;
+    };
+    RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 4, s));
+    RCB_HIP(hipMemsetAsync(t->dflag + 6, 0, sizeof(int32_t) * 2, s));
+    rcb_status wst = walk_tiers(true);
+    if (wst != RCB_OK) return wst;
+    int32_t flags[4] = {0, 0, 0, 0};
+    RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
     RCB_HIP(hipStreamSynchronize(s));
-    const int64_t nq = flags[6];   // groups that outgrew the wide walk's stack
-    const unsigned gridq = (unsigned)((nq + kWaves - 1) / kWaves);
-    if (nq > 0) {
-        if (pure) k_walk_group<true><<<gridq, kBlock, 0, s>>>(w, queue, nq);
-        else k_walk_group<false><<<gridq, kBlock, 0, s>>>(w, queue, nq);
-        RCB_LAUNCH_CHECK("k_walk_group<slab>");
-        RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
-        RCB_HIP(hipStreamSynchronize(s));
-    }
     t->walk_requeued = nq;
     if (flags[0]) {
         set_error("walk: stack overflow (tree deeper than the walk stack supports)");
@@ -588,23 +635,19 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
         w.near_cap = w.far_cap = INT64_MAX;
         w.near_list = t->gnear;
         w.far_list = t->gfar;
-        if (pure) k_walk_wide<true><<<grid, kBlock, 0, s>>>(w, nullptr);
-        else k_walk_wide<false><<<grid, kBlock, 0, s>>>(w, nullptr);
-        RCB_LAUNCH_CHECK("k_walk_wide<exact>");
-        if (nq > 0) {
-            if (pure) k_walk_group<true><<<gridq, kBlock, 0, s>>>(w, queue, nq);
-            else k_walk_group<false><<<gridq, kBlock, 0, s>>>(w, queue, nq);
-            RCB_LAUNCH_CHECK("k_walk_group<exact>");
-        }
+        wst = walk_tiers(false);
+        if (wst != RCB_OK) return wst;
     }
     int32_t *long_q = nullptr;
     if (nlong > 0) {
         long_q = (int32_t *)dalloc(t, sizeof(int32_t) * nlong, s, tmp);
         if (!long_q) return RCB_ENOMEM;
     }
-    k_sort_lists<kSortCap, kWaves><<<grid, kBlock, 0, s>>>(NG, t->gnear_beg, t->gnear_end, t->gnear,
-                                                           t->dflag + 2, long_q);
-    RCB_LAUNCH_CHECK("k_sort_lists<near>");
+    if (nq2 > 0) {   // the wide walk's near lists are sorted already
+        k_sort_lists<kSortCap, kWaves><<<(unsigned)((nq2 + kWaves - 1) / kWaves), kBlock, 0, s>>>(
+            nq2, queue2, t->gnear_beg, t->gnear_end, t->gnear, t->dflag + 2, long_q);
+        RCB_LAUNCH_CHECK("k_sort_lists<near>");
+    }
     if (nlong > 0) {
         k_sort_long<<<nlong, 1024, 0, s>>>(long_q, t->gnear_beg, t->gnear_end, t->gnear);
         RCB_LAUNCH_CHECK("k_sort_long");

@@ -97,7 +97,7 @@ struct rcb_tree {
     // the neighbour slab, [5] median selection, [6] groups outgrowing the
     // wide walk's stack, [7] leaves queued for the neighbour re-search
     int32_t *dflag = nullptr;
-    int64_t walk_requeued = 0;         // groups of the last walk taken by k_walk_group
+    int64_t walk_requeued = 0;         // groups of the last walk that outgrew the first ring
     // per leaf: the 19 far-field coefficients of the current moments (written
     // by rcb_gravity, or by the VJP if no gravity call has) and 3 VJP scratch values
     double *farc = nullptr;

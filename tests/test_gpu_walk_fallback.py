@@ -1,9 +1,11 @@
-"""The wide group walk and the 8-wide walk that takes the groups whose stack
-would outgrow the wide one's make the same per-leaf decisions (Sec. 2.2-2.4.1).
-With the wide stack capped through RCB_WALK_WIDE_STACK, so that all, many or
-a few groups are walked a second time over what the first walk wrote, the
-lists, neighbours and accelerations still match the oracle, in both walk
-modes and through the exact second pass that long lists take."""
+"""The wide group walk (a FIFO of 1024 nodes, then 8192 for the groups that
+outgrow it) and the 8-wide walk that takes the groups outgrowing both make
+the same per-leaf decisions (Sec. 2.2-2.4.1). With the FIFOs capped through
+RCB_WALK_WIDE_STACK, so that all, many or a few groups are walked again over
+what the first walk wrote, and at the default sizes (where the clustered
+cases send groups to the 8192-node FIFO), the lists, neighbours and
+accelerations still match the oracle, in both walk modes and through the
+exact second pass that long lists take."""
 import os
 
 import numpy as np
@@ -58,5 +60,4 @@ def test_capped_wide_stack_gives_the_same_lists(n, nll, kind, hs, pure, wide_cap
         assert gate(np.stack([_np(ax), _np(ay), _np(az)], 1), ref) < TOL["fp64"]
         gt.destroy()
     wide_cap(None)
-    assert requeued[None] == 0
-    assert requeued[2] > 0 and requeued[2] >= requeued[24] >= requeued[96]
+    assert requeued[2] > 0 and requeued[2] >= requeued[24] >= requeued[96] >= requeued[None]
