@@ -35,6 +35,11 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kAdj = 10;    // M, R(3), Q(6)
 constexpr int kAdjCopies = 8;   // node-adjoint copies filled by k_vjp_far
+// Nodes of the levels above kMidLevel sit in the far lists of many groups at
+// once, and the atomics on their adjoints contend: they get kAdjMidCopies
+// copies (kAdjCopies / XCD), in their own array of kAdj * 2^kMidLevel per copy.
+constexpr int kMidLevel = 16;
+constexpr int kAdjMidCopies = 64;
 constexpr int kAcc = 30;    // G0(3), G1(9), G2(18) while accumulating
 constexpr int kMom = 23;    // S1(3), S2(6), S3(10), t1, sg(3): far_math.h SymMoments
 
@@ -58,6 +63,8 @@ struct VjpArgs {
     double *sink;   // 4 n, tree order: dx dy dz dm
     double *src;    // 4 n, tree order, atomics
     double *adj;    // kAdj per label, atomics; component q of label B at q * nlab + B
+    double *adjm;   // labels below nmid: kAdjMidCopies copies, q * nmid + B
+    int64_t nmid;
     int64_t n;
     int64_t nlab;
 };
@@ -219,11 +226,17 @@ __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
             }
         }
         if (emask) {
-            // each of the kAdjCopies copies takes the blocks of one residue
-            // mod kAdjCopies, i.e. of one XCD under round-robin dispatch
-            double *adj = a.adj + (int64_t)(blockIdx.x % kAdjCopies) * kAdj * a.nlab;
+            // each copy takes the blocks of one residue mod the number of
+            // copies, i.e. of one XCD under round-robin dispatch (8 | copies)
+            if (B < a.nmid) {
+                double *adj = a.adjm + (int64_t)(blockIdx.x % kAdjMidCopies) * kAdj * a.nmid;
 #pragma unroll
-            for (int q = 0; q < kAdj; ++q) atomicAdd(adj + q * a.nlab + B, ad[q]);
+                for (int q = 0; q < kAdj; ++q) atomicAdd(adj + q * a.nmid + B, ad[q]);
+            } else {
+                double *adj = a.adj + (int64_t)(blockIdx.x % kAdjCopies) * kAdj * a.nlab;
+#pragma unroll
+                for (int q = 0; q < kAdj; ++q) atomicAdd(adj + q * a.nlab + B, ad[q]);
+            }
         }
     }
     tile_sync();
@@ -337,8 +350,17 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
                         if (has_sink && j < nt) {
                             const T v[3] = {sx - sh.t.x[j], sy - sh.t.y[j], sz - sh.t.z[j]};
                             const T r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+                            const T hsum = ha + sh.t.h[j];
                             T F, dFr;
-                            soft_FdF<T>(r2, ha + sh.t.h[j], F, dFr);
+                            if (soft_outside<T>(r2, hsum)) {   // most pairs: r^-3 and -3 r^-5
+                                const T ri = rsq_t(r2);
+                                const T ri2 = ri * ri;
+                                const T r3 = ri2 * ri;
+                                F = r3;
+                                dFr = (T)-3 * (r3 * ri2);
+                            } else {
+                                soft_FdF<T>(r2, hsum, F, dFr);
+                            }
                             const T vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
                             const T mb = sh.t.m[j];
 #pragma unroll
@@ -468,12 +490,23 @@ __global__ __launch_bounds__(kBlock) void k_vjp_push(VjpArgs a, const double *__
     }
 }
 
-// node adjoints: the copies summed into the first (fixed order)
-__global__ void k_adj_reduce(double *__restrict__ adj, int64_t len) {
+// node adjoints: the copies summed in a fixed order into copy 0 of adj (labels
+// below nmid from the mid-level copies, the others from the kAdjCopies ones)
+__global__ void k_adj_reduce(double *__restrict__ adj, const double *__restrict__ adjm, int64_t nlab,
+                             int64_t nmid) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= len) return;
-    double v = adj[i];
-    for (int c = 1; c < kAdjCopies; ++c) v += adj[(int64_t)c * len + i];
+    if (i >= kAdj * nlab) return;
+    const int64_t q = i / nlab, B = i % nlab;
+    double v;
+    if (B < nmid) {
+        const int64_t len = kAdj * nmid, k = q * nmid + B;
+        v = adjm[k];
+        for (int c = 1; c < kAdjMidCopies; ++c) v += adjm[(int64_t)c * len + k];
+    } else {
+        const int64_t len = kAdj * nlab;
+        v = adj[i];
+        for (int c = 1; c < kAdjCopies; ++c) v += adj[(int64_t)c * len + i];
+    }
     adj[i] = v;
 }
 
@@ -488,6 +521,8 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     double *sink = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
     double *src = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
     double *adj = (double *)dalloc(t, sizeof(double) * kAdjCopies * kAdj * t->nlab, s, tmp);
+    const int64_t nmid = std::min<int64_t>(t->nlab, int64_t(1) << kMidLevel);
+    double *adjm = (double *)dalloc(t, sizeof(double) * kAdjMidCopies * kAdj * nmid, s, tmp);
     double *mom = (double *)dalloc(t, sizeof(double) * kMom * t->nleaf, s, tmp);
     if (!t->farc) {
         t->farc = (double *)dalloc(t, sizeof(double) * kLeafC * t->nleaf, s, t->list_allocs);
@@ -496,10 +531,12 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     double *leafc = t->farc;   // 19 far coefficients + the leaf's cotangent sum per leaf
     if (!sink || !src || !adj || !mom || !leafc) return RCB_ENOMEM;
     RCB_HIP(hipMemsetAsync(src, 0, sizeof(double) * 4 * n, s));
+    if (!adjm) return RCB_ENOMEM;
     RCB_HIP(hipMemsetAsync(adj, 0, sizeof(double) * kAdjCopies * kAdj * t->nlab, s));
+    RCB_HIP(hipMemsetAsync(adjm, 0, sizeof(double) * kAdjMidCopies * kAdj * nmid, s));
     VjpArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
               t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
-              t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, src, adj, n, t->nlab};
+              t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, src, adj, adjm, nmid, n, t->nlab};
     const unsigned gridg = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     const bool mixed = t->p.precision == RCB_MIXED;
     if (mixed) k_vjp_moments<true><<<gridg, kBlock, 0, s>>>(a);
@@ -514,7 +551,7 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     k_vjp_far<<<gridg, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_vjp_far");
     const int64_t alen = kAdj * t->nlab;
-    k_adj_reduce<<<(unsigned)((alen + 255) / 256), 256, 0, s>>>(adj, alen);
+    k_adj_reduce<<<(unsigned)((alen + 255) / 256), 256, 0, s>>>(adj, adjm, t->nlab, nmid);
     RCB_LAUNCH_CHECK("k_adj_reduce");
     if (mixed) k_vjp_near<true><<<gridg, kBlock, 0, s>>>(a);
     else k_vjp_near<false><<<gridg, kBlock, 0, s>>>(a);

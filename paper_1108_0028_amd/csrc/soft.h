@@ -33,8 +33,9 @@ __device__ __forceinline__ double rcp_t(double x) { return rcbfar::rcp64(x); }
 
 // True when the pair is certainly outside the kernel support whatever the
 // rounding of q: r^2 >= (h_a + h_b)^2 (1 + 2^-16) + r2_min. soft_F then
-// returns r^-3 (rinv * rinv * rinv), which the caller may compute directly;
-// the margin (far above the few-ulp errors of q) keeps the two identical.
+// returns r^-3 (rinv * rinv * rinv) and soft_FdF r^-3 and -3 r^-5, which the
+// caller may compute directly; the margin (far above the few-ulp errors of
+// q) keeps the two identical.
 template <typename T>
 __device__ __forceinline__ bool soft_outside(T r2, T hsum) {
     return r2 >= (hsum * (T)(1.0 + 1.0 / 65536.0)) * hsum + r2_min<T>();
