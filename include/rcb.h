@@ -160,8 +160,8 @@ rcb_status rcb_refresh(rcb_tree *t, const double *x, const double *y, const doub
  * lowest-level cell and keeps them in the tree. The neighbour and gravity
  * calls run it themselves when it has not run yet; calling it first only
  * moves the work. Synchronises `stream` (the list sizes are read back).
- * Errors: RCB_ECAPACITY if a walk stack overflows (a tree deeper than the
- * walk supports), RCB_ENOMEM.
+ * Errors: RCB_ECAPACITY if the last-resort walk's stack overflows (a tree
+ * deeper than 29 levels), RCB_ENOMEM.
  */
 rcb_status rcb_walk(rcb_tree *t, void *stream);
 

@@ -27,7 +27,6 @@ constexpr int kLeafC = 22;   // doubles per leaf in rcb_tree::farc
 
 constexpr int kWave = 64;
 constexpr int kChunk = 512;          // elements per wave item of the big-node passes
-constexpr int kStackCap = 2048;      // LIFO walk stack entries per wave (LDS)
 constexpr double kReachPad = 1.0 + 0x1p-32;
 
 struct BuildScratch {
@@ -92,10 +91,11 @@ struct rcb_tree {
     unsigned long long *nb_ovf_cnt = nullptr;   // triples claimed (may exceed the pool)
     int64_t nb_ovf_n = 0;              // triples claimed by the last count call
     bool nb_ovf_ok = true;             // all of them fitted in the pool
-    // device flags: [0] walk stack overflow, [1] long near lists, [2] their
+    // device flags: [0] 8-wide walk stack overflow, [1] long near lists, [2] their
     // queue, [3] groups outgrowing the list slabs, [4] particles outgrowing
     // the neighbour slab, [5] median selection, [6] groups outgrowing the
-    // wide walk's stack, [7] leaves queued for the neighbour re-search
+    // first wide-walk FIFO, [7] groups outgrowing the second FIFO (walk) and
+    // leaves queued for the neighbour re-search (neighbours)
     int32_t *dflag = nullptr;
     int64_t walk_requeued = 0;         // groups of the last walk that outgrew the first ring
     // per leaf: the 19 far-field coefficients of the current moments (written
