@@ -210,36 +210,58 @@ __device__ __forceinline__ void stage8(const double *__restrict__ a, int64_t bas
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
+// Staging of a wave's contiguous range [w0, wend) of at most kChunk elements
+// (the nodes of a packed wave): loaded coalesced, read back as this lane's
+// [p0, p0 + 8), zero at and past `end`.
+template <typename V>
+__device__ __forceinline__ void stage8w(const V *__restrict__ a, int64_t w0, int64_t wend, int64_t p0,
+                                        int64_t end, V *buf, V (&out)[8]) {
+    const int l = lane_id();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int e = 64 * t + l;
+        if (w0 + e < wend) buf[stage_slot(e)] = a[w0 + e];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int t = 0; t < 8; ++t) out[t] = p0 + t < end ? buf[stage_slot((int)(p0 + t - w0))] : (V)0;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+// The reverse: value t of this lane goes to position w0 + dl[t] (dl < 0: none),
+// then the range [w0, wend) is stored coalesced.
+template <typename V>
+__device__ __forceinline__ void scatter8w(V *__restrict__ a, int64_t w0, int64_t wend, const int (&dl)[8],
+                                          const V (&val)[8], V *buf) {
+    const int l = lane_id();
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+        if (dl[t] >= 0) buf[stage_slot(dl[t])] = val[t];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int e = 64 * t + l;
+        if (w0 + e < wend) a[w0 + e] = buf[stage_slot(e)];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 // `stage`: a wave-private buffer of kStage doubles (LANES == 64) or null
 // (direct loads of each lane's 8 consecutive elements).
+// The tree sums of one node from its elements [p0, p0 + 8) held by this lane
+// (zero past `end`), as loaded by chunk_sums or by a caller that staged them.
 template <int P, int LANES = kWave>
-__device__ __forceinline__ void chunk_sums(const PartIn &in, int64_t base, int64_t end,
-                                           const double g[3], const double c[3],
-                                           double (&sums)[Pay<P>::NS], double &mx,
-                                           double *stage = nullptr) {
+__device__ __forceinline__ void chunk_sums_regs(const double (&X)[8], const double (&Y)[8],
+                                                const double (&Z)[8], const double (&Mm)[8],
+                                                const double (&H)[8], int64_t p0, int64_t end,
+                                                const double g[3], const double c[3],
+                                                double (&sums)[Pay<P>::NS], double &mx) {
     constexpr int NS = Pay<P>::NS;
     double v[8][NS];
     double ml = -1.0;
-    const int64_t p0 = base + 8 * (int64_t)(lane_id() % LANES);
-    double X[8], Y[8], Z[8], Mm[8], H[8];
-    if (stage) {
-        stage8(in.x, base, end, stage, X);
-        stage8(in.y, base, end, stage, Y);
-        stage8(in.z, base, end, stage, Z);
-        stage8(in.m, base, end, stage, Mm);
-        if constexpr (P == 1) stage8(in.h, base, end, stage, H);
-    } else {
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int64_t i = p0 + t;
-            const bool ok = i < end;
-            X[t] = ok ? in.x[i] : 0.0;
-            Y[t] = ok ? in.y[i] : 0.0;
-            Z[t] = ok ? in.z[i] : 0.0;
-            Mm[t] = ok ? in.m[i] : 0.0;
-            if constexpr (P == 1) H[t] = ok ? in.h[i] : 0.0;
-        }
-    }
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int64_t i = p0 + t;
@@ -277,6 +299,34 @@ __device__ __forceinline__ void chunk_sums(const PartIn &in, int64_t base, int64
         sums[s] = group_sum<LANES>(a + b);
     }
     mx = group_max<LANES>(ml);
+}
+
+template <int P, int LANES = kWave>
+__device__ __forceinline__ void chunk_sums(const PartIn &in, int64_t base, int64_t end,
+                                           const double g[3], const double c[3],
+                                           double (&sums)[Pay<P>::NS], double &mx,
+                                           double *stage = nullptr) {
+    const int64_t p0 = base + 8 * (int64_t)(lane_id() % LANES);
+    double X[8], Y[8], Z[8], Mm[8], H[8];
+    if (stage) {
+        stage8(in.x, base, end, stage, X);
+        stage8(in.y, base, end, stage, Y);
+        stage8(in.z, base, end, stage, Z);
+        stage8(in.m, base, end, stage, Mm);
+        if constexpr (P == 1) stage8(in.h, base, end, stage, H);
+    } else {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int64_t i = p0 + t;
+            const bool ok = i < end;
+            X[t] = ok ? in.x[i] : 0.0;
+            Y[t] = ok ? in.y[i] : 0.0;
+            Z[t] = ok ? in.z[i] : 0.0;
+            Mm[t] = ok ? in.m[i] : 0.0;
+            if constexpr (P == 1) H[t] = ok ? in.h[i] : 0.0;
+        }
+    }
+    chunk_sums_regs<P, LANES>(X, Y, Z, Mm, H, p0, end, g, c, sums, mx);
 }
 
 struct NodeOut {
@@ -546,10 +596,11 @@ __global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int split, Par
                                                          PartOut out, NodeOut o, BigCtl bc,
                                                          int32_t *__restrict__ groups) {
     constexpr int kPack = kWave / GW;   // nodes per wave
+    __shared__ double stage_all[kBlock / kWave][kStage];
+    double *stage = stage_all[threadIdx.x / kWave];
     const int64_t w = wave_index();
     const int64_t nodes = (int64_t)1 << lvl;
     if (w * kPack >= nodes) return;
-    constexpr bool leaf = LEAF;
     const int lane = lane_id();
     const int gslot = lane / GW, gl = lane % GW;
     const int64_t j = w * kPack + gslot;
@@ -564,17 +615,17 @@ __global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int split, Par
         if (lane == 0) groups[atomicAdd(&bc.ctl[2], 1)] = (int32_t)w;
         return;
     }
-    if (!valid) return;   // whole 8-lane groups leave together
-    if (c == 0) {
-        finish_empty<GW>(o, lab, leaf, s, split != 0);
-        return;
-    }
-    double g[3];
-    box_centre(o, lab, g);
-    double sa[4], mx;
-    chunk_sums<0, GW>(in, s, (int64_t)s + c, g, g, sa, mx);
-    finish_a<GW>(o, lab, leaf, sa, mx, split != 0);
-    if (leaf) {
+    if constexpr (LEAF) {   // moments only: each lane loads its own 8 elements
+        if (!valid) return;   // whole groups leave together
+        if (c == 0) {
+            finish_empty<GW>(o, lab, true, s, split != 0);
+            return;
+        }
+        double g[3];
+        box_centre(o, lab, g);
+        double sa[4], mx;
+        chunk_sums<0, GW>(in, s, (int64_t)s + c, g, g, sa, mx);
+        finish_a<GW>(o, lab, true, sa, mx, split != 0);
         double com[3];
         const double M = sa[0] + 0.0;
 #pragma unroll
@@ -584,7 +635,28 @@ __global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int split, Par
         finish_b<GW>(o, lab, sb, hn);
         return;
     }
+    // the wave's nodes hold the contiguous range [w0, wend) (<= kChunk
+    // elements), staged through LDS coalesced; every lane takes part, those of
+    // absent or empty nodes with no elements
+    const int64_t jl = (w * kPack + kPack < nodes ? w * kPack + kPack : nodes) - 1;
+    const int64_t w0 = o.nfirst[nodes + w * kPack];
+    const int64_t wend = (int64_t)o.nfirst[nodes + jl] + o.ncount[nodes + jl];
+    const bool act = valid && c > 0;
+    if (valid && c == 0) finish_empty<GW>(o, lab, false, s, split != 0);
+    const int64_t e0 = (int64_t)s + 8 * gl, end = (int64_t)s + c;
+    double X[8], Y[8], Z[8], Mm[8], H[8];
+    stage8w(in.x, w0, wend, e0, end, stage, X);
+    stage8w(in.y, w0, wend, e0, end, stage, Y);
+    stage8w(in.z, w0, wend, e0, end, stage, Z);
+    stage8w(in.m, w0, wend, e0, end, stage, Mm);
+    double g[3];
+    box_centre(o, lab, g);
+    double sa[4], mx;
+    chunk_sums_regs<0, GW>(X, Y, Z, Mm, H, e0, end, g, g, sa, mx);
+    if (act) finish_a<GW>(o, lab, false, sa, mx, split != 0);
     if (!split) return;
+    int32_t I[8];
+    stage8w(id, w0, wend, e0, end, (int32_t *)stage, I);
     double lo[3], hi[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -600,12 +672,13 @@ __global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int split, Par
     if (hi[2] - lo[2] > best) ax = 2;
     const double plane = o.mplane ? o.mplane[lab] : (sa[1 + ax] + 0.0) / (sa[0] + 0.0);
     const int32_t tie = node_tie(o, lab);
-    const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
-    const int64_t e0 = (int64_t)s + 8 * gl, end = (int64_t)s + c;
     uint32_t lb = 0;
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
-        if (e0 + t < end && goes_left(xa[e0 + t], id, e0 + t, plane, tie)) lb |= 1u << t;
+    for (int t = 0; t < 8; ++t) {
+        const double xv = ax == 0 ? X[t] : (ax == 1 ? Y[t] : Z[t]);
+        if (act && e0 + t < end && (xv < plane || (tie != INT32_MIN && xv == plane && I[t] < tie)))
+            lb |= 1u << t;
+    }
     const int nl = __popc(lb);
     int incl = nl;   // inclusive scan of the left counts over the group
 #pragma unroll
@@ -615,21 +688,20 @@ __global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int split, Par
     }
     const int excl = incl - nl;
     const int nleft = __shfl(incl, gslot * GW + GW - 1, kWave);
+    int dl[8];   // destination relative to w0, -1: none
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-        const int64_t i = e0 + t;
-        if (i < end) {
-            const int lbefore = excl + __popc(lb & ((1u << t) - 1u));
-            const int e = 8 * gl + t;
-            const int64_t dst = (lb >> t) & 1u ? (int64_t)s + lbefore : (int64_t)s + nleft + (e - lbefore);
-            out.x[dst] = in.x[i];
-            out.y[dst] = in.y[i];
-            out.z[dst] = in.z[i];
-            out.m[dst] = in.m[i];
-            out.id[dst] = id[i];
-        }
+        const int lbefore = excl + __popc(lb & ((1u << t) - 1u));
+        const int e = 8 * gl + t;
+        const int64_t dst = (lb >> t) & 1u ? (int64_t)s + lbefore : (int64_t)s + nleft + (e - lbefore);
+        dl[t] = act && e0 + t < end ? (int)(dst - w0) : -1;
     }
-    if (gl == 0) {
+    scatter8w(out.x, w0, wend, dl, X, stage);
+    scatter8w(out.y, w0, wend, dl, Y, stage);
+    scatter8w(out.z, w0, wend, dl, Z, stage);
+    scatter8w(out.m, w0, wend, dl, Mm, stage);
+    scatter8w(out.id, w0, wend, dl, I, (int32_t *)stage);
+    if (act && gl == 0) {
         o.nfirst[2 * lab] = s;
         o.ncount[2 * lab] = nleft;
         o.nfirst[2 * lab + 1] = s + nleft;
