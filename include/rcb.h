@@ -162,6 +162,9 @@ rcb_status rcb_refresh(rcb_tree *t, const double *x, const double *y, const doub
  * moves the work. Synchronises `stream` (the list sizes are read back).
  * Errors: RCB_ECAPACITY if the last-resort walk's stack overflows (a tree
  * deeper than 29 levels), RCB_ENOMEM.
+ * Environment (testing): RCB_WALK_WIDE_STACK=n caps the breadth-first
+ * walk's node queues at n entries, so that more groups of cells are walked
+ * again by the later tiers; the lists do not change.
  */
 rcb_status rcb_walk(rcb_tree *t, void *stream);
 
