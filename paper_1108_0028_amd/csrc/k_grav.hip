@@ -319,11 +319,9 @@ rcb_status gravity(rcb_tree *t, void *ax, void *ay, void *az, hipStream_t s) {
     rcb_status st = ensure_walk(t, s);
     if (st != RCB_OK) return st;
     const bool rb = t->p.taylor_reading == RCB_READING_B;
-    // the far coefficients are kept for a VJP on the same moments
-    if (!rb && !t->farc) {
-        t->farc = (double *)dalloc(t, sizeof(double) * kLeafC * t->nleaf, s, t->list_allocs);
-        if (!t->farc) return RCB_ENOMEM;
-    }
+    // the far coefficients are kept for a VJP on the same moments (if the
+    // array cannot be had, gravity goes on without keeping them)
+    if (!rb && !t->farc) t->farc = (double *)dalloc(t, sizeof(double) * kLeafC * t->nleaf, s, t->list_allocs);
     double *farc = rb ? nullptr : t->farc;
     GravArgs g{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
                t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
