@@ -194,34 +194,23 @@ __device__ __forceinline__ double group_max(double v) {
 constexpr int kStage = kChunk + kChunk / 8;
 __device__ __forceinline__ int stage_slot(int e) { return e + (e >> 3); }
 
-__device__ __forceinline__ void stage8(const double *__restrict__ a, int64_t base, int64_t end,
-                                       double *buf, double (&out)[8]) {
-    const int l = lane_id();
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const int e = 64 * t + l;
-        buf[stage_slot(e)] = base + e < end ? a[base + e] : 0.0;
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#pragma unroll
-    for (int t = 0; t < 8; ++t) out[t] = buf[stage_slot(8 * l + t)];
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
-
 // Staging of a wave's contiguous range [w0, wend) of at most kChunk elements
-// (the nodes of a packed wave): loaded coalesced, read back as this lane's
-// [p0, p0 + 8), zero at and past `end`.
+// in two halves, so that a caller can issue the global loads of all its
+// fields before the first LDS round trip: load8c takes lane l's elements
+// w0 + 64 t + l (coalesced, zero past wend); transpose8 passes them through
+// LDS and returns this lane's [p0, p0 + 8), zero at and past `end`.
 template <typename V>
-__device__ __forceinline__ void stage8w(const V *__restrict__ a, int64_t w0, int64_t wend, int64_t p0,
-                                        int64_t end, V *buf, V (&out)[8]) {
+__device__ __forceinline__ void load8c(const V *__restrict__ a, int64_t w0, int64_t wend, V (&r)[8]) {
     const int l = lane_id();
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const int e = 64 * t + l;
-        if (w0 + e < wend) buf[stage_slot(e)] = a[w0 + e];
-    }
+    for (int t = 0; t < 8; ++t) r[t] = w0 + 64 * t + l < wend ? a[w0 + 64 * t + l] : (V)0;
+}
+template <typename V>
+__device__ __forceinline__ void transpose8(const V (&r)[8], int64_t w0, int64_t p0, int64_t end, V *buf,
+                                           V (&out)[8]) {
+    const int l = lane_id();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) buf[stage_slot(64 * t + l)] = r[t];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
@@ -308,12 +297,18 @@ __device__ __forceinline__ void chunk_sums(const PartIn &in, int64_t base, int64
                                            double *stage = nullptr) {
     const int64_t p0 = base + 8 * (int64_t)(lane_id() % LANES);
     double X[8], Y[8], Z[8], Mm[8], H[8];
-    if (stage) {
-        stage8(in.x, base, end, stage, X);
-        stage8(in.y, base, end, stage, Y);
-        stage8(in.z, base, end, stage, Z);
-        stage8(in.m, base, end, stage, Mm);
-        if constexpr (P == 1) stage8(in.h, base, end, stage, H);
+    if (stage) {   // all loads first, then the LDS passes
+        double rx[8], ry[8], rz[8], rm[8], rh[8];
+        load8c(in.x, base, end, rx);
+        load8c(in.y, base, end, ry);
+        load8c(in.z, base, end, rz);
+        load8c(in.m, base, end, rm);
+        if constexpr (P == 1) load8c(in.h, base, end, rh);
+        transpose8(rx, base, p0, end, stage, X);
+        transpose8(ry, base, p0, end, stage, Y);
+        transpose8(rz, base, p0, end, stage, Z);
+        transpose8(rm, base, p0, end, stage, Mm);
+        if constexpr (P == 1) transpose8(rh, base, p0, end, stage, H);
     } else {
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
@@ -645,10 +640,17 @@ __global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int split, Par
     if (valid && c == 0) finish_empty<GW>(o, lab, false, s, split != 0);
     const int64_t e0 = (int64_t)s + 8 * gl, end = (int64_t)s + c;
     double X[8], Y[8], Z[8], Mm[8], H[8];
-    stage8w(in.x, w0, wend, e0, end, stage, X);
-    stage8w(in.y, w0, wend, e0, end, stage, Y);
-    stage8w(in.z, w0, wend, e0, end, stage, Z);
-    stage8w(in.m, w0, wend, e0, end, stage, Mm);
+    {   // all loads first, then the LDS passes
+        double rx[8], ry[8], rz[8], rm[8];
+        load8c(in.x, w0, wend, rx);
+        load8c(in.y, w0, wend, ry);
+        load8c(in.z, w0, wend, rz);
+        load8c(in.m, w0, wend, rm);
+        transpose8(rx, w0, e0, end, stage, X);
+        transpose8(ry, w0, e0, end, stage, Y);
+        transpose8(rz, w0, e0, end, stage, Z);
+        transpose8(rm, w0, e0, end, stage, Mm);
+    }
     double g[3];
     box_centre(o, lab, g);
     double sa[4], mx;
@@ -656,7 +658,11 @@ __global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int split, Par
     if (act) finish_a<GW>(o, lab, false, sa, mx, split != 0);
     if (!split) return;
     int32_t I[8];
-    stage8w(id, w0, wend, e0, end, (int32_t *)stage, I);
+    {
+        int32_t ri[8];
+        load8c(id, w0, wend, ri);
+        transpose8(ri, w0, e0, end, (int32_t *)stage, I);
+    }
     double lo[3], hi[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
