@@ -62,9 +62,9 @@ struct VjpArgs {
     double *leafc;  // kLeafC per leaf
     double *sink;   // 4 n, tree order: dx dy dz dm
     double *src;    // 4 n, tree order, atomics
-    double *adj;    // kAdj per label, atomics; component q of label B at q * nlab + B
-    double *adjm;   // labels below nmid: kAdjMidCopies copies, q * nmid + B
-    int64_t nmid;
+    double *adj;    // kAdj per label (summed copies); component q of label B at q * nlab + B
+    double *adjm;   // unused
+    int64_t nmid;   // labels below nmid have kAdjMidCopies adjoint copies, q * nmid + B
     int64_t n;
     int64_t nlab;
 };
@@ -155,7 +155,10 @@ struct VjpFarShared {
     double com[8][3];          // and centres of mass
 };
 
-__global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
+// AT: the type of the node-adjoint copies (FP64; FP32 in the mixed form, whose
+// contract allows FP32 accumulation), summed in FP64 by k_adj_reduce
+template <typename AT>
+__global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a, AT *__restrict__ adjc, AT *__restrict__ adjmc) {
     __shared__ VjpFarShared sh_all[kWaves];
     VjpFarShared &sh = sh_all[threadIdx.x / kWave];
     double(*cotp)[3][kWave / 2] = sh.cot;
@@ -229,13 +232,15 @@ __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a) {
             // each copy takes the blocks of one residue mod the number of
             // copies, i.e. of one XCD under round-robin dispatch (8 | copies)
             if (B < a.nmid) {
-                double *adj = a.adjm + (int64_t)(blockIdx.x % kAdjMidCopies) * kAdj * a.nmid;
+                AT *adj = adjmc + (int64_t)(blockIdx.x % kAdjMidCopies) * kAdj * a.nmid;
 #pragma unroll
-                for (int q = 0; q < kAdj; ++q) atomicAdd(adj + q * a.nmid + B, ad[q]);
+                for (int q = 0; q < kAdj; ++q)
+                    __hip_atomic_fetch_add(adj + q * a.nmid + B, (AT)ad[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                double *adj = a.adj + (int64_t)(blockIdx.x % kAdjCopies) * kAdj * a.nlab;
+                AT *adj = adjc + (int64_t)(blockIdx.x % kAdjCopies) * kAdj * a.nlab;
 #pragma unroll
-                for (int q = 0; q < kAdj; ++q) atomicAdd(adj + q * a.nlab + B, ad[q]);
+                for (int q = 0; q < kAdj; ++q)
+                    __hip_atomic_fetch_add(adj + q * a.nlab + B, (AT)ad[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
@@ -490,9 +495,11 @@ __global__ __launch_bounds__(kBlock) void k_vjp_push(VjpArgs a, const double *__
     }
 }
 
-// node adjoints: the copies summed in a fixed order into copy 0 of adj (labels
-// below nmid from the mid-level copies, the others from the kAdjCopies ones)
-__global__ void k_adj_reduce(double *__restrict__ adj, const double *__restrict__ adjm, int64_t nlab,
+// node adjoints: the copies summed in FP64 in a fixed order into out (labels
+// below nmid from the mid-level copies, the others from the kAdjCopies ones);
+// out may be copy 0 of adjc (each thread reads its own element first)
+template <typename A>
+__global__ void k_adj_reduce(double *out, const A *adjc, const A *__restrict__ adjmc, int64_t nlab,
                              int64_t nmid) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= kAdj * nlab) return;
@@ -500,14 +507,14 @@ __global__ void k_adj_reduce(double *__restrict__ adj, const double *__restrict_
     double v;
     if (B < nmid) {
         const int64_t len = kAdj * nmid, k = q * nmid + B;
-        v = adjm[k];
-        for (int c = 1; c < kAdjMidCopies; ++c) v += adjm[(int64_t)c * len + k];
+        v = (double)adjmc[k];
+        for (int c = 1; c < kAdjMidCopies; ++c) v += (double)adjmc[(int64_t)c * len + k];
     } else {
         const int64_t len = kAdj * nlab;
-        v = adj[i];
-        for (int c = 1; c < kAdjCopies; ++c) v += adj[(int64_t)c * len + i];
+        v = (double)adjc[i];
+        for (int c = 1; c < kAdjCopies; ++c) v += (double)adjc[(int64_t)c * len + i];
     }
-    adj[i] = v;
+    out[i] = v;
 }
 
 }  // namespace
@@ -520,25 +527,28 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     const int64_t n = t->n;
     double *sink = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
     double *src = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
-    double *adj = (double *)dalloc(t, sizeof(double) * kAdjCopies * kAdj * t->nlab, s, tmp);
+    const bool mixed = t->p.precision == RCB_MIXED;
     const int64_t nmid = std::min<int64_t>(t->nlab, int64_t(1) << kMidLevel);
-    double *adjm = (double *)dalloc(t, sizeof(double) * kAdjMidCopies * kAdj * nmid, s, tmp);
+    // node-adjoint copies: FP64 (summed into copy 0 of adj) or, in the mixed
+    // form, FP32 (summed into adj)
+    const size_t adj_n = (size_t)kAdjCopies * kAdj * t->nlab, adjm_n = (size_t)kAdjMidCopies * kAdj * nmid;
+    double *adj = (double *)dalloc(t, sizeof(double) * (mixed ? (size_t)kAdj * t->nlab : adj_n), s, tmp);
+    void *adjc = mixed ? dalloc(t, sizeof(float) * adj_n, s, tmp) : (void *)adj;
+    void *adjmc = dalloc(t, (mixed ? sizeof(float) : sizeof(double)) * adjm_n, s, tmp);
     double *mom = (double *)dalloc(t, sizeof(double) * kMom * t->nleaf, s, tmp);
     if (!t->farc) {
         t->farc = (double *)dalloc(t, sizeof(double) * kLeafC * t->nleaf, s, t->list_allocs);
         t->farc_valid = false;
     }
     double *leafc = t->farc;   // 19 far coefficients + the leaf's cotangent sum per leaf
-    if (!sink || !src || !adj || !mom || !leafc) return RCB_ENOMEM;
+    if (!sink || !src || !adj || !adjc || !adjmc || !mom || !leafc) return RCB_ENOMEM;
     RCB_HIP(hipMemsetAsync(src, 0, sizeof(double) * 4 * n, s));
-    if (!adjm) return RCB_ENOMEM;
-    RCB_HIP(hipMemsetAsync(adj, 0, sizeof(double) * kAdjCopies * kAdj * t->nlab, s));
-    RCB_HIP(hipMemsetAsync(adjm, 0, sizeof(double) * kAdjMidCopies * kAdj * nmid, s));
+    RCB_HIP(hipMemsetAsync(adjc, 0, (mixed ? sizeof(float) : sizeof(double)) * adj_n, s));
+    RCB_HIP(hipMemsetAsync(adjmc, 0, (mixed ? sizeof(float) : sizeof(double)) * adjm_n, s));
     VjpArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
               t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
-              t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, src, adj, adjm, nmid, n, t->nlab};
+              t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, src, adj, nullptr, nmid, n, t->nlab};
     const unsigned gridg = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
-    const bool mixed = t->p.precision == RCB_MIXED;
     if (mixed) k_vjp_moments<true><<<gridg, kBlock, 0, s>>>(a);
     else k_vjp_moments<false><<<gridg, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_vjp_moments");
@@ -548,10 +558,18 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
         t->farc_valid = true;
     }
 
-    k_vjp_far<<<gridg, kBlock, 0, s>>>(a);
-    RCB_LAUNCH_CHECK("k_vjp_far");
     const int64_t alen = kAdj * t->nlab;
-    k_adj_reduce<<<(unsigned)((alen + 255) / 256), 256, 0, s>>>(adj, adjm, t->nlab, nmid);
+    const unsigned gridr = (unsigned)((alen + 255) / 256);
+    if (mixed) {
+        k_vjp_far<float><<<gridg, kBlock, 0, s>>>(a, (float *)adjc, (float *)adjmc);
+        RCB_LAUNCH_CHECK("k_vjp_far");
+        k_adj_reduce<float><<<gridr, 256, 0, s>>>(adj, (const float *)adjc, (const float *)adjmc, t->nlab, nmid);
+    } else {
+        k_vjp_far<double><<<gridg, kBlock, 0, s>>>(a, (double *)adjc, (double *)adjmc);
+        RCB_LAUNCH_CHECK("k_vjp_far");
+        k_adj_reduce<double><<<gridr, 256, 0, s>>>(adj, (const double *)adjc, (const double *)adjmc, t->nlab,
+                                                   nmid);
+    }
     RCB_LAUNCH_CHECK("k_adj_reduce");
     if (mixed) k_vjp_near<true><<<gridg, kBlock, 0, s>>>(a);
     else k_vjp_near<false><<<gridg, kBlock, 0, s>>>(a);
