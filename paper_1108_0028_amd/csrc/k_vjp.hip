@@ -61,7 +61,8 @@ struct VjpArgs {
     double *mom;    // kMom per leaf: symmetrised cotangent moments
     double *leafc;  // kLeafC per leaf
     double *sink;   // 4 n, tree order: dx dy dz dm
-    double *src;    // 4 n, tree order, atomics
+    double *src;    // 4 n, tree order, atomics (FP64 form)
+    float *srcf;    // the same in the mixed form (FP32 atomics, its contract's accumulation)
     double *adj;    // kAdj per label (summed copies); component q of label B at q * nlab + B
     double *adjm;   // unused
     int64_t nmid;   // labels below nmid have kAdjMidCopies adjoint copies, q * nmid + B
@@ -383,10 +384,20 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
                                      s2 = sh.t.acc[2][lane], s3 = sh.t.acc[3][lane];
                         if (s0 != 0.0 || s1 != 0.0 || s2 != 0.0 || s3 != 0.0) {
                             const int32_t pb = sh.t.pb[lane];
-                            atomicAdd(a.src + pb, s0);
-                            atomicAdd(a.src + a.n + pb, s1);
-                            atomicAdd(a.src + 2 * a.n + pb, s2);
-                            atomicAdd(a.src + 3 * a.n + pb, s3);
+                            if constexpr (MIXED) {
+                                __hip_atomic_fetch_add(a.srcf + pb, (float)s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                __hip_atomic_fetch_add(a.srcf + a.n + pb, (float)s1, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                                __hip_atomic_fetch_add(a.srcf + 2 * a.n + pb, (float)s2, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                                __hip_atomic_fetch_add(a.srcf + 3 * a.n + pb, (float)s3, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                            } else {
+                                atomicAdd(a.src + pb, s0);
+                                atomicAdd(a.src + a.n + pb, s1);
+                                atomicAdd(a.src + 2 * a.n + pb, s2);
+                                atomicAdd(a.src + 3 * a.n + pb, s3);
+                            }
                         }
                     }
                     tile_sync();
@@ -462,9 +473,11 @@ __global__ __launch_bounds__(kBlock) void k_vjp_push(VjpArgs a, const double *__
         const int64_t p = (int64_t)sG + si;
         const double r[3] = {a.px[p], a.py[p], a.pz[p]};
         const double mb = a.pm[p];
-        double dr[3] = {a.sink[p] + a.src[p], a.sink[a.n + p] + a.src[a.n + p],
-                        a.sink[2 * a.n + p] + a.src[2 * a.n + p]};
-        double dmb = a.sink[3 * a.n + p] + a.src[3 * a.n + p];
+        double sr[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sr[c] = MIXED ? (double)a.srcf[c * a.n + p] : a.src[c * a.n + p];
+        double dr[3] = {a.sink[p] + sr[0], a.sink[a.n + p] + sr[1], a.sink[2 * a.n + p] + sr[2]};
+        double dmb = a.sink[3 * a.n + p] + sr[3];
         const int64_t A = a.nleaf + gi * G + leaf_slot(lf, (int32_t)p);
         for (int64_t B = A; B > GL; B >>= 1) {
             double ad[kAdj];
@@ -526,8 +539,8 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     std::vector<void *> tmp;
     const int64_t n = t->n;
     double *sink = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
-    double *src = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
     const bool mixed = t->p.precision == RCB_MIXED;
+    void *srcv = dalloc(t, (mixed ? sizeof(float) : sizeof(double)) * 4 * n, s, tmp);
     const int64_t nmid = std::min<int64_t>(t->nlab, int64_t(1) << kMidLevel);
     // node-adjoint copies: FP64 (summed into copy 0 of adj) or, in the mixed
     // form, FP32 (summed into adj)
@@ -541,13 +554,14 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
         t->farc_valid = false;
     }
     double *leafc = t->farc;   // 19 far coefficients + the leaf's cotangent sum per leaf
-    if (!sink || !src || !adj || !adjc || !adjmc || !mom || !leafc) return RCB_ENOMEM;
-    RCB_HIP(hipMemsetAsync(src, 0, sizeof(double) * 4 * n, s));
+    if (!sink || !srcv || !adj || !adjc || !adjmc || !mom || !leafc) return RCB_ENOMEM;
+    RCB_HIP(hipMemsetAsync(srcv, 0, (mixed ? sizeof(float) : sizeof(double)) * 4 * n, s));
     RCB_HIP(hipMemsetAsync(adjc, 0, (mixed ? sizeof(float) : sizeof(double)) * adj_n, s));
     RCB_HIP(hipMemsetAsync(adjmc, 0, (mixed ? sizeof(float) : sizeof(double)) * adjm_n, s));
     VjpArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
               t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
-              t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, src, adj, nullptr, nmid, n, t->nlab};
+              t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, mixed ? nullptr : (double *)srcv,
+              mixed ? (float *)srcv : nullptr, adj, nullptr, nmid, n, t->nlab};
     const unsigned gridg = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     if (mixed) k_vjp_moments<true><<<gridg, kBlock, 0, s>>>(a);
     else k_vjp_moments<false><<<gridg, kBlock, 0, s>>>(a);
