@@ -204,18 +204,39 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
     }
 }
 
-// slab lists (tree order) -> the caller's CSR: 16 lanes per particle
-__global__ __launch_bounds__(kBlock) void k_nb_compact(int64_t n, const int32_t *__restrict__ pid,
+// caller index -> tree position
+__global__ __launch_bounds__(kBlock) void k_inv(int64_t n, const int32_t *__restrict__ pid,
+                                                int32_t *__restrict__ inv) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < n) inv[pid[p]] = (int32_t)p;
+}
+
+// slab lists -> the caller's CSR, walked in caller order so that the list
+// stores and offset loads are contiguous: 8 lanes per particle, each
+// loading up to 8 slab entries before its first store
+__global__ __launch_bounds__(kBlock) void k_nb_compact(int64_t n, const int32_t *__restrict__ inv,
                                                        const int64_t *__restrict__ offsets,
                                                        const int32_t *__restrict__ slab,
                                                        int32_t *__restrict__ ids) {
-    const int64_t p = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / 16;
-    const int j0 = threadIdx.x % 16;
-    if (p >= n) return;
-    const int32_t a = pid[p];
+    const int64_t a = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / 8;
+    const int j0 = threadIdx.x % 8;
+    if (a >= n) return;
     const int64_t o = offsets[a], c = offsets[a + 1] - o;
     if (c > kNbCap) return;   // searched again by its group
-    for (int64_t j = j0; j < c; j += 16) ids[o + j] = slab[p * kNbCap + j];
+    const int32_t *row = slab + (int64_t)inv[a] * kNbCap;
+    for (int b = 0; b < (int)c; b += 64) {
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = b + 8 * u + j0;
+            v[u] = j < c ? row[j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = b + 8 * u + j0;
+            if (j < c) ids[o + j] = v[u];
+        }
+    }
 }
 
 }  // namespace
@@ -232,7 +253,8 @@ rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipSt
     if (!t->nb_slab) {
         t->nb_slab = (int32_t *)dalloc(t, sizeof(int32_t) * t->n * kNbCap, s, t->list_allocs);
         t->nb_queue = (int32_t *)dalloc(t, sizeof(int32_t) * t->nleaf, s, t->list_allocs);
-        if (!t->nb_slab || !t->nb_queue) return RCB_ENOMEM;
+        t->nb_inv = (int32_t *)dalloc(t, sizeof(int32_t) * t->n, s, t->list_allocs);
+        if (!t->nb_slab || !t->nb_queue || !t->nb_inv) return RCB_ENOMEM;
     }
     RCB_HIP(hipMemsetAsync(t->dflag + 4, 0, sizeof(int32_t), s));
     RCB_HIP(hipMemsetAsync(t->dflag + 7, 0, sizeof(int32_t), s));
@@ -266,8 +288,9 @@ rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, in
                   std::to_string(t->nb_total));
         return RCB_ECAPACITY;
     }
-    const unsigned gridc = (unsigned)((t->n * 16 + kBlock - 1) / kBlock);
-    k_nb_compact<<<gridc, kBlock, 0, s>>>(t->n, t->pid, offsets, t->nb_slab, ids);
+    const unsigned gridc = (unsigned)((t->n * 8 + kBlock - 1) / kBlock);
+    k_inv<<<(unsigned)((t->n + kBlock - 1) / kBlock), kBlock, 0, s>>>(t->n, t->pid, t->nb_inv);
+    k_nb_compact<<<gridc, kBlock, 0, s>>>(t->n, t->nb_inv, offsets, t->nb_slab, ids);
     RCB_LAUNCH_CHECK("k_nb_compact");
     if (t->nb_nq > 0) {
         NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,

@@ -84,13 +84,10 @@ struct rcb_tree {
     int32_t *near_list = nullptr, *far_list = nullptr;
     int64_t nb_total = -1;             // neighbour total of the last count call
     int32_t *nb_slab = nullptr;        // neighbour ids of the count call, kNbCap per particle
+    int32_t *nb_inv = nullptr;         // caller index -> tree position (fill call)
     int32_t *nb_queue = nullptr;       // leaves with a particle of more than kNbCap neighbours
     int32_t nb_over = 0;               // particles with more than kNbCap neighbours
     int32_t nb_nq = 0;                 // entries of nb_queue
-    int32_t *nb_ovf = nullptr;         // their ids past kNbCap: (caller index, rank, id) triples
-    unsigned long long *nb_ovf_cnt = nullptr;   // triples claimed (may exceed the pool)
-    int64_t nb_ovf_n = 0;              // triples claimed by the last count call
-    bool nb_ovf_ok = true;             // all of them fitted in the pool
     // device flags: [0] 8-wide walk stack overflow, [1] long near lists, [2] their
     // queue, [3] groups outgrowing the list slabs, [4] particles outgrowing
     // the neighbour slab, [5] median selection, [6] groups outgrowing the
