@@ -341,6 +341,7 @@ struct NodeOut {
 __device__ __forceinline__ int32_t node_tie(const NodeOut &o, int64_t lab) {
     return o.mplane ? o.mtie[lab] : INT32_MIN;
 }
+
 __device__ __forceinline__ bool goes_left(double x, const int32_t *__restrict__ id, int64_t i,
                                           double plane, int32_t tie) {
     return x < plane || (tie != INT32_MIN && x == plane && id[i] < tie);
@@ -449,30 +450,46 @@ struct PartOut {
 // Stable partition of the elements [base, end): `lb` left and `rb` right
 // elements of the node precede base. Elements are taken 64 at a time in
 // order (lane l holds base + 64 t + l), ranks come from ballots, so the
-// stores of a side are contiguous across lanes.
+// stores of a side are contiguous across lanes. All of the wave's loads are
+// issued before its first store (the compiler cannot know that the output
+// arrays do not alias the inputs).
 __device__ __forceinline__ void scatter_chunk(const PartIn &in, const int32_t *__restrict__ id,
                                               const PartOut &out, int64_t base, int64_t end,
                                               int ax, double plane, int32_t tie, int64_t node_first,
                                               int64_t nleft_total, int64_t lb, int64_t rb) {
-    const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
     const int l = lane_id();
     int64_t rl = lb, rr = rb;
+    double vx[8], vy[8], vz[8], vm[8];
+    int32_t vid[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int64_t i = base + 64 * t + l;
         const bool valid = i < end;
-        const bool left = valid && goes_left(xa[i], id, i, plane, tie);
+        vx[t] = valid ? in.x[i] : 0.0;
+        vy[t] = valid ? in.y[i] : 0.0;
+        vz[t] = valid ? in.z[i] : 0.0;
+        vm[t] = valid ? in.m[i] : 0.0;
+        vid[t] = valid ? id[i] : 0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int64_t i = base + 64 * t + l;
+        const bool valid = i < end;
+        const double xv = ax == 0 ? vx[t] : (ax == 1 ? vy[t] : vz[t]);
+        // written out rather than through a helper: the helper form compiled
+        // to a partition pass a third slower on gfx950 (measured)
+        const bool left = valid && (xv < plane || (tie != INT32_MIN && xv == plane && vid[t] < tie));
         const uint64_t bl = ballot(left);
         const int nl = __popcll(bl);
         const int nv = (int)min<int64_t>(64, max<int64_t>(0, end - (base + 64 * t)));
         if (valid) {
             const int rk = rank_below(bl);
             const int64_t dst = left ? node_first + rl + rk : node_first + nleft_total + rr + (l - rk);
-            out.x[dst] = in.x[i];
-            out.y[dst] = in.y[i];
-            out.z[dst] = in.z[i];
-            out.m[dst] = in.m[i];
-            out.id[dst] = id[i];
+            out.x[dst] = vx[t];
+            out.y[dst] = vy[t];
+            out.z[dst] = vz[t];
+            out.m[dst] = vm[t];
+            out.id[dst] = vid[t];
         }
         rl += nl;
         rr += nv - nl;
