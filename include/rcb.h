@@ -138,28 +138,38 @@ rcb_status rcb_check_cells(rcb_tree *t, const double *x, const double *y, const 
                            int64_t n, int64_t *outside, void *stream);
 
 /*
- * Moments-only refresh with the tree held fixed (Sec. 2.1 "Updating the
- * tree": when no particle has left its lowest-level cell the tree is kept and
- * only its moments are recomputed). New positions, masses and smoothing
- * lengths replace the build's inputs, particle by particle in caller order;
- * topology (cell ranges, boxes, splits) and the interaction lists stay as
- * they are, and every node's mass, centre of mass, h_node_int, the leaves'
- * Eq. 1 quadrupole and h_node and the Eq. 2 quadrupoles above are recomputed
- * by the same canonical sums as rcb_build. Neighbour lists must be counted
- * again afterwards (rcb_neighbours_fill returns RCB_ESTATE until then).
+ * Tree update of Sec. 2.1 "Updating the tree": when no particle has left its
+ * lowest-level cell (rcb_check_cells() == 0) the tree is kept and only its
+ * moments are recomputed. New positions, masses and smoothing lengths replace
+ * the build's inputs, particle by particle in caller order; the topology
+ * (cell ranges, boxes, splits) stays, and every node's mass, centre of mass,
+ * h_node_int, the leaves' Eq. 1 quadrupole and h_node and the Eq. 2
+ * quadrupoles above are recomputed by the same canonical sums as rcb_build.
  *  x, y, z, m, h: n FP64 values each (device), n == the built n.
- * Errors: RCB_EINVAL (NULL pointer), RCB_ESTATE (n differs from the built n),
- * RCB_EINPUT (validate set and an input non-finite or m, h <= 0).
+ *  keep_lists: 0 -- the paper's step: the interaction lists (and neighbour
+ *              counts, kept far coefficients) are dropped, and the next call
+ *              that needs them walks the refreshed tree again, so neighbours
+ *              and the reachability override follow the new h and positions.
+ *              1 -- the tree held fixed for differentiation: rcb_gravity and
+ *              rcb_gravity_vjp keep using the old lists (the map whose
+ *              derivative rcb_gravity_vjp computes). Neighbour calls then
+ *              return RCB_ESTATE, since the old lists may miss neighbours of
+ *              the new inputs, until rcb_walk() has walked again.
+ * Errors: RCB_EINVAL (NULL pointer, keep_lists not 0 or 1), RCB_ESTATE (n
+ * differs from the built n), RCB_EINPUT (validate set and an input
+ * non-finite or m, h <= 0).
  */
 rcb_status rcb_refresh(rcb_tree *t, const double *x, const double *y, const double *z,
-                       const double *m, const double *h, int64_t n, void *stream);
+                       const double *m, const double *h, int64_t n, int32_t keep_lists,
+                       void *stream);
 
 /*
  * Tree walk (Sec. 2.2, with the reachability test of Sec. 2.3.1 and the MAC
  * of Sec. 2.4.1): makes the near and far interaction lists of every
  * lowest-level cell and keeps them in the tree. The neighbour and gravity
  * calls run it themselves when it has not run yet; calling it first only
- * moves the work. Synchronises `stream` (the list sizes are read back).
+ * moves the work; after rcb_refresh(keep_lists = 1) it walks the refreshed
+ * tree again. Synchronises `stream` (the list sizes are read back).
  * Errors: RCB_ECAPACITY if the last-resort walk's stack overflows (a tree
  * deeper than 29 levels), RCB_ENOMEM.
  * Environment (testing): RCB_WALK_WIDE_STACK=n caps the breadth-first
@@ -175,6 +185,7 @@ rcb_status rcb_walk(rcb_tree *t, void *stream);
  *  offsets: device int64[n + 1], receives the exclusive prefix sum of the
  *           counts (offsets[0] = 0, offsets[n] = total).
  *  total:   host int64, receives offsets[n]. This call synchronises `stream`.
+ * Errors: RCB_ESTATE after rcb_refresh(keep_lists = 1) until rcb_walk().
  */
 rcb_status rcb_neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, void *stream);
 
@@ -257,8 +268,17 @@ typedef enum {
  */
 rcb_status rcb_tree_export(rcb_tree *t, int32_t field, void *dst, size_t bytes, void *stream);
 
-/* Free the tree and its device memory (waits for its last stream). */
+/* Free the tree and its device memory (waits for its last stream). Blocks
+   of 1 GiB and more from the library's own allocator stay reserved for the
+   next tree on the same device (see rcb_release_cache). */
 void rcb_destroy(rcb_tree *t);
+
+/* Give back the device memory the library keeps for reuse: the freed blocks
+   of 1 GiB and more, and the unused part of each device's default
+   stream-ordered pool (its release threshold, raised by the library, is
+   restored). Call it when no tree is in use, e.g. before another framework
+   needs the memory. Waits for the blocks' last uses; never fails. */
+void rcb_release_cache(void);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *rcb_last_error(void);

@@ -234,6 +234,8 @@ static void split_node(otree *t, int64_t lab)
 static void compute_moments(otree *t)
 {
     int64_t leaf0 = (int64_t)1 << t->k;
+    /* every label on its own: no node reads another's result here */
+#pragma omp parallel for schedule(dynamic, 64)
     for (int64_t lab = 1; lab < t->nlab; ++lab) {
         int64_t s = t->first[lab], c = t->count[lab];
         double g[3];
@@ -380,8 +382,16 @@ otree *orc_build(int64_t n, const double *x, const double *y, const double *z,
     t->first[1] = 0;
     t->count[1] = n;
     t->axis[0] = -1;
-    for (int lvl = 0; lvl < t->k; ++lvl)
-        for (int64_t lab = (int64_t)1 << lvl; lab < ((int64_t)2 << lvl); ++lab) split_node(t, lab);
+    /* The nodes of one level are independent (each owns its particle range */
+    /* and its two children), so a level is split in parallel, as the paper  */
+    /* builds disjoint subtrees on separate processors (Sec. 2.1            */
+    /* "Parallelisation"). The median split's sort uses a global comparator */
+    /* key and stays serial.                                                 */
+    for (int lvl = 0; lvl < t->k; ++lvl) {
+        int64_t lab0 = (int64_t)1 << lvl, lab1 = (int64_t)2 << lvl;
+#pragma omp parallel for schedule(dynamic, 1) if (split != 2)
+        for (int64_t lab = lab0; lab < lab1; ++lab) split_node(t, lab);
+    }
     for (int64_t lab = (int64_t)1 << t->k; lab < t->nlab; ++lab) t->axis[lab] = -1;
     compute_moments(t);
     return t;

@@ -57,7 +57,7 @@ class RcbTreeInfo(C.Structure):
 
 EXPORTED = ["rcb_params_default", "rcb_build", "rcb_check_cells", "rcb_refresh", "rcb_walk", "rcb_neighbours_count", "rcb_neighbours_fill",
             "rcb_gravity", "rcb_gravity_vjp", "rcb_get_info", "rcb_tree_export", "rcb_destroy",
-            "rcb_last_error"]
+            "rcb_release_cache", "rcb_last_error"]
 
 _lib = None
 
@@ -82,7 +82,7 @@ def lib():
         L.rcb_build.restype = C.c_int
         L.rcb_check_cells.argtypes = [P, P, P, P, C.c_int64, C.POINTER(C.c_int64), P]
         L.rcb_check_cells.restype = C.c_int
-        L.rcb_refresh.argtypes = [P, P, P, P, P, P, C.c_int64, P]
+        L.rcb_refresh.argtypes = [P, P, P, P, P, P, C.c_int64, C.c_int32, P]
         L.rcb_refresh.restype = C.c_int
         L.rcb_walk.argtypes = [P, P]
         L.rcb_walk.restype = C.c_int
@@ -100,6 +100,8 @@ def lib():
         L.rcb_tree_export.restype = C.c_int
         L.rcb_destroy.argtypes = [P]
         L.rcb_destroy.restype = None
+        L.rcb_release_cache.argtypes = []
+        L.rcb_release_cache.restype = None
         L.rcb_last_error.argtypes = []
         L.rcb_last_error.restype = C.c_char_p
         _lib = L
@@ -192,11 +194,14 @@ class Tree:
                                      _stream()), "rcb_check_cells")
         return out.value
 
-    def refresh(self, x, y, z, m, h):
-        """New inputs on the same tree: moments recomputed, topology and lists kept."""
+    def refresh(self, x, y, z, m, h, keep_lists: bool = False):
+        """New inputs on the same tree: moments recomputed, topology kept.
+        keep_lists=False walks again on demand (the paper's tree update);
+        True keeps the interaction lists (the tree held fixed, as the VJP
+        assumes; neighbours then need walk() first)."""
         xs = [_dev(a, torch.float64, nm) for a, nm in zip((x, y, z, m, h), "xyzmh")]
-        _check(lib().rcb_refresh(self.handle, *[_ptr(a) for a in xs], self.n, _stream()),
-               "rcb_refresh")
+        _check(lib().rcb_refresh(self.handle, *[_ptr(a) for a in xs], self.n,
+                                 1 if keep_lists else 0, _stream()), "rcb_refresh")
         self._keep = xs   # inputs stay alive until the stream has used them
 
     def walk(self):
@@ -297,6 +302,11 @@ class RCBGravity(torch.autograd.Function):
         tree.destroy()
         ctx.tree = None
         return dx, dy, dz, dm, None, None, None, None, None
+
+
+def release_cache():
+    """Give back the device memory the library keeps for reuse (rcb_release_cache)."""
+    lib().rcb_release_cache()
 
 
 def gravity(x, y, z, m, h, n_ll: int = 12, theta: float = 0.7, precision: str = "fp64",

@@ -1305,7 +1305,7 @@ static rcb_status level_pass(rcb_tree *t, BuildScratch &b, const NodeOut &o, con
 rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const double *z,
                       const double *m, const double *h, hipStream_t s) {
     const int64_t n = t->n;
-    std::vector<void *> tmp;   // build scratch, freed at the end
+    Scratch tmp(t, s);   // build scratch, released when the call returns
     auto A = [&](size_t bytes, std::vector<void *> &owner) { return dalloc(t, bytes, s, owner); };
 
     // tree-owned arrays
@@ -1357,7 +1357,6 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         RCB_HIP(hipStreamSynchronize(s));
         if (flag) {
             set_error("rcb_build: input has a non-finite coordinate, m <= 0 or h <= 0");
-            for (void *p : tmp) dfree(t, p, s);
             return RCB_EINPUT;
         }
     }
@@ -1445,8 +1444,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     t->pid = t->lvl_id + (int64_t)t->k * n;
     for (void *p : {(void *)b.x[cur], (void *)b.y[cur], (void *)b.z[cur], (void *)b.m[cur]}) {
         t->allocs.push_back(p);
-        for (auto &q : tmp)
-            if (q == p) q = nullptr;
+        tmp.keep(p);
     }
     if (t->p.precision == RCB_MIXED) {
         t->fdx = (float *)A(sizeof(float) * n, t->allocs);
@@ -1460,14 +1458,12 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
             t->fdy, t->fdz, t->fm, t->fh);
         RCB_LAUNCH_CHECK("k_mixed_prep");
     }
-    for (void *p : tmp)
-        if (p) dfree(t, p, s);
     return RCB_OK;
 }
 
 rcb_status count_outside(rcb_tree *t, const double *x, const double *y, const double *z,
                          int64_t *outside, hipStream_t s) {
-    std::vector<void *> tmp;
+    Scratch tmp(t, s);
     unsigned long long *cnt = (unsigned long long *)dalloc(t, sizeof(unsigned long long), s, tmp);
     if (!cnt) return RCB_ENOMEM;
     RCB_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
@@ -1476,7 +1472,6 @@ rcb_status count_outside(rcb_tree *t, const double *x, const double *y, const do
     RCB_LAUNCH_CHECK("k_outside");
     unsigned long long h = 0;
     RCB_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
-    for (void *p : tmp) dfree(t, p, s);
     RCB_HIP(hipStreamSynchronize(s));
     *outside = (int64_t)h;
     return RCB_OK;
@@ -1485,12 +1480,13 @@ rcb_status count_outside(rcb_tree *t, const double *x, const double *y, const do
 // Moments-only refresh (the tree held fixed): new inputs in the built order,
 // then every node's M, centre of mass, h_node_int, leaf Eq. 1 quadrupole and
 // h_node by the same canonical sums as the build, Eq. 2 upwards, and the walk
-// records; boxes, splits, ranges and interaction lists stay.
+// records; boxes, splits and ranges stay. The caller decides what happens to
+// the interaction lists (rcb_refresh).
 rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const double *z,
                         const double *m, const double *h, hipStream_t s) {
     const int64_t n = t->n;
     t->farc_valid = false;   // the kept far coefficients belong to the old moments
-    std::vector<void *> tmp;
+    Scratch tmp(t, s);
     auto A = [&](size_t bytes) { return dalloc(t, bytes, s, tmp); };
     BuildScratch b{};
     b.max_big = std::min<int64_t>(t->nleaf, n / (kChunk + 1) + 1);
@@ -1515,7 +1511,6 @@ rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const dou
         RCB_HIP(hipStreamSynchronize(s));
         if (flag) {
             set_error("rcb_refresh: input has a non-finite coordinate, m <= 0 or h <= 0");
-            for (void *p : tmp) dfree(t, p, s);
             return RCB_EINPUT;
         }
     }
@@ -1551,7 +1546,6 @@ rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const dou
         RCB_LAUNCH_CHECK("k_mixed_prep");
     }
     t->nb_total = -1;   // neighbour counts belong to the old positions
-    for (void *p : tmp) dfree(t, p, s);
     return RCB_OK;
 }
 

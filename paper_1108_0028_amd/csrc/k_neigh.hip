@@ -245,9 +245,14 @@ __global__ __launch_bounds__(kBlock) void k_nb_compact(int64_t n, const int32_t 
 // kNbCap slots; fill then compacts the slab and searches again only the
 // groups holding a particle with more neighbours than that.
 rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipStream_t s) {
+    if (t->lists_kept) {
+        set_error("rcb_neighbours_count: the interaction lists were kept across rcb_refresh "
+                  "(keep_lists = 1) and may miss neighbours of the new inputs; call rcb_walk first");
+        return RCB_ESTATE;
+    }
     rcb_status st = ensure_walk(t, s);
     if (st != RCB_OK) return st;
-    std::vector<void *> tmp;
+    Scratch tmp(t, s);
     int64_t *counts = (int64_t *)dalloc(t, sizeof(int64_t) * t->n, s, tmp);
     if (!counts) return RCB_ENOMEM;
     if (!t->nb_slab) {
@@ -269,7 +274,6 @@ rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipSt
     int32_t over[4] = {0, 0, 0, 0};   // dflag[4..7]: particles past the slab, ..., leaves queued
     RCB_HIP(hipMemcpyAsync(total, offsets + t->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RCB_HIP(hipMemcpyAsync(over, t->dflag + 4, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
-    for (void *p : tmp) dfree(t, p, s);
     RCB_HIP(hipStreamSynchronize(s));
     t->nb_total = *total;
     t->nb_over = over[0];

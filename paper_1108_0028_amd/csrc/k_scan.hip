@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int64_t *__re
 
 rcb_status scan_i64(rcb_tree *t, const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
     const int64_t nb = n > 0 ? (n + kTile - 1) / kTile : 1;
-    std::vector<void *> tmp;
+    Scratch tmp(t, s);
     int64_t *bsum = (int64_t *)dalloc(t, sizeof(int64_t) * nb, s, tmp);
     if (!bsum) return RCB_ENOMEM;
     k_scan_reduce<<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, bsum);
@@ -93,7 +93,6 @@ rcb_status scan_i64(rcb_tree *t, const int64_t *in, int64_t *out, int64_t n, hip
     RCB_LAUNCH_CHECK("k_scan_top");
     k_scan_apply<<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, bsum, out);
     RCB_LAUNCH_CHECK("k_scan_apply");
-    dfree(t, bsum, s);
     return RCB_OK;
 }
 

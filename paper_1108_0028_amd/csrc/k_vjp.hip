@@ -536,7 +536,7 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
                        void *dy, void *dz, void *dm, hipStream_t s) {
     rcb_status st = ensure_walk(t, s);
     if (st != RCB_OK) return st;
-    std::vector<void *> tmp;
+    Scratch tmp(t, s);
     const int64_t n = t->n;
     double *sink = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
     const bool mixed = t->p.precision == RCB_MIXED;
@@ -591,7 +591,6 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     if (mixed) k_vjp_push<true><<<gridg, kBlock, 0, s>>>(a, adj, t->ncom, t->nM, dx, dy, dz, dm);
     else k_vjp_push<false><<<gridg, kBlock, 0, s>>>(a, adj, t->ncom, t->nM, dx, dy, dz, dm);
     RCB_LAUNCH_CHECK("k_vjp_push");
-    for (void *p : tmp) dfree(t, p, s);
     return RCB_OK;
 }
 

@@ -527,7 +527,7 @@ static void slab_caps(int64_t ngroup, int64_t &cn, int64_t &cf) {
 rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     if (t->walked) return RCB_OK;
     const int64_t NG = t->ngroup;
-    std::vector<void *> tmp;
+    Scratch tmp(t, s);
     int64_t *ncnt = (int64_t *)dalloc(t, sizeof(int64_t) * NG, s, tmp);
     int64_t *fcnt = (int64_t *)dalloc(t, sizeof(int64_t) * NG, s, tmp);
     int32_t *queue = (int32_t *)dalloc(t, sizeof(int32_t) * NG, s, tmp);    // groups for the 2nd tier
@@ -609,8 +609,10 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
         RCB_LAUNCH_CHECK("k_slab_ends");
         t->gnear = nslab;
         t->gfar = fslab;
-        tmp.resize(tmp.size() - slabs.size());
-        for (void *p : slabs) t->list_allocs.push_back(p);
+        for (void *p : slabs) {
+            tmp.keep(p);
+            t->list_allocs.push_back(p);
+        }
     } else {
         int64_t *noff = (int64_t *)dalloc(t, sizeof(int64_t) * (NG + 1), s, t->list_allocs);
         int64_t *foff = (int64_t *)dalloc(t, sizeof(int64_t) * (NG + 1), s, t->list_allocs);
@@ -652,8 +654,8 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
         k_sort_long<<<nlong, 1024, 0, s>>>(long_q, t->gnear_beg, t->gnear_end, t->gnear);
         RCB_LAUNCH_CHECK("k_sort_long");
     }
-    for (void *p : tmp) dfree(t, p, s);
     t->walked = true;
+    t->lists_kept = false;
     return RCB_OK;
 }
 
@@ -662,7 +664,7 @@ rcb_status ensure_leaf_lists(rcb_tree *t, hipStream_t s) {
     if (st != RCB_OK) return st;
     if (t->leaf_lists) return RCB_OK;
     const int64_t L = t->nleaf;
-    std::vector<void *> tmp;
+    Scratch tmp(t, s);
     int64_t *ncnt = (int64_t *)dalloc(t, sizeof(int64_t) * L, s, tmp);
     int64_t *fcnt = (int64_t *)dalloc(t, sizeof(int64_t) * L, s, tmp);
     t->near_off = (int64_t *)dalloc(t, sizeof(int64_t) * (L + 1), s, t->list_allocs);
@@ -689,11 +691,29 @@ rcb_status ensure_leaf_lists(rcb_tree *t, hipStream_t s) {
                                            nullptr, nullptr, t->near_off, t->far_off, t->near_list,
                                            t->far_list);
     RCB_LAUNCH_CHECK("k_expand<fill>");
-    for (void *p : tmp) dfree(t, p, s);
     t->near_total = tot[0];
     t->far_total = tot[1];
     t->leaf_lists = true;
     return RCB_OK;
+}
+
+void drop_lists(rcb_tree *t, hipStream_t s) {
+    for (void *p : t->list_allocs) dfree(t, p, s);
+    t->list_allocs.clear();
+    t->walked = false;
+    t->lists_kept = false;
+    t->gnear_beg = t->gnear_end = t->gfar_beg = t->gfar_end = nullptr;
+    t->gnear = t->gfar = nullptr;
+    t->leaf_lists = false;
+    t->near_total = t->far_total = -1;
+    t->near_off = t->far_off = nullptr;
+    t->near_list = t->far_list = nullptr;
+    t->nb_total = -1;
+    t->nb_slab = t->nb_inv = t->nb_queue = nullptr;
+    t->nb_over = t->nb_nq = 0;
+    t->walk_requeued = 0;
+    t->farc = nullptr;
+    t->farc_valid = false;
 }
 
 }  // namespace rcb

@@ -26,36 +26,57 @@ rcb_status hip_fail(hipError_t e, const char *what) {
 }
 
 // Stream-ordered allocation from the device's default pool, which keeps
-// freed memory for reuse (release threshold raised once per device). Blocks
-// of at least kCacheMin bytes are also kept by the library once freed and
-// handed out again for a request on the same device and stream that they fit
-// within a factor of two: allocating and freeing tens of GB through the pool
-// maps and unmaps memory on every tree at 10^8 particles. If an allocation
-// fails, the cached blocks are released and it is tried once more.
+// freed memory for reuse (release threshold raised once per device, restored
+// by rcb_release_cache). Blocks of at least kCacheMin bytes are also kept by
+// the library once freed and handed out again for a request on the same
+// device that they fit within a factor of two: allocating and freeing tens of
+// GB through the pool maps and unmaps memory on every tree at 10^8 particles.
+// A kept block carries an event recorded on the stream that freed it; the
+// stream that takes it over waits for that event first, so no stream handle
+// of the caller is held past the call. If an allocation fails, the kept
+// blocks are released and it is tried once more.
 namespace {
 constexpr size_t kCacheMin = (size_t)1 << 30;
+constexpr int kMaxDevices = 64;
 struct CachedBlock {
     void *p;
     size_t bytes;
     int device;
-    hipStream_t stream;
+    hipEvent_t done;   // recorded after the block's last use (null while in use)
 };
 std::mutex g_cache_mu;
 std::vector<CachedBlock> g_cached;                   // free, kept for reuse
 std::unordered_map<void *, CachedBlock> g_large;     // large blocks in use
+bool g_pool_set[kMaxDevices] = {false};
+uint64_t g_pool_thr[kMaxDevices] = {0};
 
-void release_cached(int device) {
-    std::vector<hipStream_t> streams;
+// Returns the kept blocks of `device` (all devices if < 0) to the pool and
+// trims the pool of every device concerned; g_cache_mu held.
+void release_cached_locked(int device) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    bool touched[kMaxDevices] = {false};
     for (auto it = g_cached.begin(); it != g_cached.end();) {
-        if (it->device == device) {
-            (void)hipFreeAsync(it->p, it->stream);
-            streams.push_back(it->stream);
-            it = g_cached.erase(it);
-        } else {
+        if (device >= 0 && it->device != device) {
             ++it;
+            continue;
         }
+        (void)hipSetDevice(it->device);
+        (void)hipEventSynchronize(it->done);   // the block's last use has finished
+        (void)hipEventDestroy(it->done);
+        (void)hipFreeAsync(it->p, nullptr);
+        if (it->device >= 0 && it->device < kMaxDevices) touched[it->device] = true;
+        it = g_cached.erase(it);
     }
-    for (hipStream_t st : streams) (void)hipStreamSynchronize(st);
+    for (int d = 0; d < kMaxDevices; ++d) {
+        if (!touched[d]) continue;
+        hipMemPool_t pool;
+        (void)hipSetDevice(d);
+        (void)hipStreamSynchronize(nullptr);
+        if (hipDeviceGetDefaultMemPool(&pool, d) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+    }
+    (void)hipSetDevice(cur);
+    (void)hipGetLastError();
 }
 }  // namespace
 
@@ -66,15 +87,17 @@ void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owne
         owner.push_back(q);
         return q;
     }
-    static bool pool_set[64] = {false};
     std::lock_guard<std::mutex> lock(g_cache_mu);
-    if (t->device >= 0 && t->device < 64 && !pool_set[t->device]) {
+    if (t->device >= 0 && t->device < kMaxDevices && !g_pool_set[t->device]) {
         hipMemPool_t pool;
-        if (hipDeviceGetDefaultMemPool(&pool, t->device) == hipSuccess) {
+        if (hipDeviceGetDefaultMemPool(&pool, t->device) == hipSuccess &&
+            hipMemPoolGetAttribute(pool, hipMemPoolAttrReleaseThreshold, &g_pool_thr[t->device]) ==
+                hipSuccess) {
             uint64_t thr = UINT64_MAX;
             hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+            g_pool_set[t->device] = true;
         }
-        pool_set[t->device] = true;
+        (void)hipGetLastError();
     }
     void *p = nullptr;
     if (bytes == 0) bytes = 16;
@@ -82,23 +105,24 @@ void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owne
         size_t best = SIZE_MAX;
         auto pick = g_cached.end();
         for (auto it = g_cached.begin(); it != g_cached.end(); ++it)
-            if (it->device == t->device && it->stream == s && it->bytes >= bytes && it->bytes <= 2 * bytes &&
-                it->bytes < best) {
+            if (it->device == t->device && it->bytes >= bytes && it->bytes <= 2 * bytes && it->bytes < best) {
                 best = it->bytes;
                 pick = it;
             }
-        if (pick != g_cached.end()) {
+        if (pick != g_cached.end() && hipStreamWaitEvent(s, pick->done, 0) == hipSuccess) {
             p = pick->p;
-            g_large[p] = *pick;
+            (void)hipEventDestroy(pick->done);
+            g_large[p] = CachedBlock{p, pick->bytes, t->device, nullptr};
             g_cached.erase(pick);
             owner.push_back(p);
             return p;
         }
+        (void)hipGetLastError();
     }
     hipError_t e = hipMallocAsync(&p, bytes, s);
     if (e != hipSuccess && !g_cached.empty()) {
         (void)hipGetLastError();
-        release_cached(t->device);
+        release_cached_locked(t->device);
         e = hipMallocAsync(&p, bytes, s);
     }
     if (e != hipSuccess) {
@@ -106,7 +130,7 @@ void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owne
         (void)hipGetLastError();
         p = nullptr;
     } else if (bytes >= kCacheMin) {
-        g_large[p] = CachedBlock{p, bytes, t->device, s};
+        g_large[p] = CachedBlock{p, bytes, t->device, nullptr};
     }
     owner.push_back(p);
     return p;
@@ -122,10 +146,15 @@ void dfree(rcb_tree *t, void *p, hipStream_t s) {
     auto it = g_large.find(p);
     if (it != g_large.end()) {
         CachedBlock b = it->second;
-        b.stream = s;   // later work on s is ordered after its last use
         g_large.erase(it);
-        g_cached.push_back(b);
-        return;
+        if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) == hipSuccess) {
+            if (hipEventRecord(b.done, s) == hipSuccess) {   // after the block's last use on s
+                g_cached.push_back(b);
+                return;
+            }
+            (void)hipEventDestroy(b.done);
+        }
+        (void)hipGetLastError();
     }
     (void)hipFreeAsync(p, s);
 }
@@ -226,7 +255,7 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
         // planes through the centre of number: build with unit weights (the
         // canonical sums then give sum(x) / count exactly), then recompute
         // every moment with the masses on the fixed tree
-        std::vector<void *> tmp;
+        Scratch tmp(t, t->stream);
         double *ones = (double *)dalloc(t, sizeof(double) * (size_t)n, t->stream, tmp);
         if (!ones) {
             st = RCB_ENOMEM;
@@ -235,7 +264,6 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
             st = hipGetLastError() == hipSuccess ? RCB_OK : RCB_EHIP;
             if (st == RCB_OK) st = build_tree(t, x, y, z, ones, h, t->stream);
             if (st == RCB_OK) st = refresh_tree(t, x, y, z, m, h, t->stream);
-            dfree(t, ones, t->stream);
         }
     } else {
         st = build_tree(t, x, y, z, m, h, t->stream);
@@ -268,7 +296,8 @@ rcb_status rcb_check_cells(rcb_tree *t, const double *x, const double *y, const 
 }
 
 rcb_status rcb_refresh(rcb_tree *t, const double *x, const double *y, const double *z,
-                       const double *m, const double *h, int64_t n, void *stream) {
+                       const double *m, const double *h, int64_t n, int32_t keep_lists,
+                       void *stream) {
     g_last_error.clear();
     if (!t || !x || !y || !z || !m || !h) {
         set_error("rcb_refresh: NULL argument");
@@ -279,8 +308,16 @@ rcb_status rcb_refresh(rcb_tree *t, const double *x, const double *y, const doub
                   std::to_string(t->n));
         return RCB_ESTATE;
     }
+    if (keep_lists != 0 && keep_lists != 1) {
+        set_error("rcb_refresh: keep_lists must be 0 or 1");
+        return RCB_EINVAL;
+    }
     t->stream = (hipStream_t)stream;
-    return refresh_tree(t, x, y, z, m, h, t->stream);
+    rcb_status st = refresh_tree(t, x, y, z, m, h, t->stream);
+    if (st != RCB_OK) return st;
+    if (!keep_lists) drop_lists(t, t->stream);   // walked again by the next call that needs lists
+    else if (t->walked) t->lists_kept = true;
+    return RCB_OK;
 }
 
 rcb_status rcb_walk(rcb_tree *t, void *stream) {
@@ -290,6 +327,7 @@ rcb_status rcb_walk(rcb_tree *t, void *stream) {
         return RCB_EINVAL;
     }
     t->stream = (hipStream_t)stream;
+    if (t->lists_kept) drop_lists(t, t->stream);   // lists of older inputs: walk again
     return ensure_walk(t, t->stream);
 }
 
@@ -406,6 +444,26 @@ void rcb_destroy(rcb_tree *t) {
     if (!t) return;
     free_all(t);
     delete t;
+}
+
+void rcb_release_cache(void) {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    release_cached_locked(-1);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (int d = 0; d < kMaxDevices; ++d) {
+        if (!g_pool_set[d]) continue;
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, d) == hipSuccess) {
+            (void)hipSetDevice(d);
+            (void)hipDeviceSynchronize();
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &g_pool_thr[d]);
+            (void)hipMemPoolTrimTo(pool, 0);
+        }
+        g_pool_set[d] = false;
+    }
+    (void)hipSetDevice(cur);
+    (void)hipGetLastError();
 }
 
 }  // extern "C"

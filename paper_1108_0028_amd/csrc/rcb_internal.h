@@ -74,6 +74,9 @@ struct rcb_tree {
     int gk = 0;
     int64_t ngroup = 0;
     bool walked = false;
+    // the lists were kept across a refresh (the tree held fixed): gravity and
+    // the VJP use them, the neighbour search needs a new walk
+    bool lists_kept = false;
     // group list of group g: gnear[gnear_beg[g] .. gnear_end[g]) (likewise far)
     int64_t *gnear_beg = nullptr, *gnear_end = nullptr, *gfar_beg = nullptr, *gfar_end = nullptr;
     uint64_t *gnear = nullptr, *gfar = nullptr;
@@ -112,13 +115,36 @@ void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owne
 // releases a dalloc block in stream order (large blocks stay cached for reuse)
 void dfree(rcb_tree *t, void *p, hipStream_t s);
 
+// Scratch blocks of one call: every block still listed when the scope ends
+// (on success and on every error return) is released in stream order. A
+// block handed over to the tree is taken out with keep().
+struct Scratch : std::vector<void *> {
+    rcb_tree *t;
+    hipStream_t s;
+    Scratch(rcb_tree *t_, hipStream_t s_) : t(t_), s(s_) {}
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
+    void keep(void *p) {
+        for (auto &q : *this)
+            if (q == p) q = nullptr;
+    }
+    ~Scratch() {
+        for (void *p : *this)
+            if (p) dfree(t, p, s);
+    }
+};
+
+// Forget the interaction lists and everything made from them (neighbour
+// slab, kept far coefficients); the next call that needs lists walks again.
+void drop_lists(rcb_tree *t, hipStream_t s);
+
 // build (k_build.hip)
 rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const double *z,
                       const double *m, const double *h, hipStream_t s);
 // particles whose new position lies outside their lowest-level cell (k_build.hip)
 rcb_status count_outside(rcb_tree *t, const double *x, const double *y, const double *z,
                          int64_t *outside, hipStream_t s);
-// moments-only refresh with new inputs, topology and lists held fixed (k_build.hip)
+// moments-only refresh with new inputs, topology held fixed (k_build.hip)
 rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const double *z,
                         const double *m, const double *h, hipStream_t s);
 // device exclusive scan of int64 counts in place-free form: out[0..n] (k_scan.hip)

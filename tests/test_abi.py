@@ -93,7 +93,7 @@ def test_null_tree_arguments():
     L = _lib()
     tot = C.c_int64()
     assert L.rcb_walk(None, None) == 1
-    assert L.rcb_refresh(None, *([C.c_void_p(8)] * 5), 1, None) == 1
+    assert L.rcb_refresh(None, *([C.c_void_p(8)] * 5), 1, 0, None) == 1
     assert L.rcb_check_cells(None, *([C.c_void_p(8)] * 3), 1, C.byref(tot), None) == 1
     assert L.rcb_neighbours_count(None, C.c_void_p(8), C.byref(tot), None) == 1
     assert L.rcb_neighbours_fill(None, C.c_void_p(8), C.c_void_p(8), 1, None) == 1

@@ -3,9 +3,16 @@ fixed-tree VJP, plus invariants and the autograd wrapper.
 
 Bar: per output array, max |d_gpu - d_oracle| <= tol * max |d_oracle| with
 tol = 1e-9 (FP64 form; only summation order and atomics ordering differ) and
-2e-3 (mixed form: the near-field pairs are FP32, whose kernel derivative
-terms scale as 1/r^4, so the backward pass loses about one more digit than
-the 2e-4 forward bar).
+1e-4 (mixed form). The mixed bar: every near pair is evaluated in FP32
+(unit roundoff u = 2^-24 = 6e-8) from offsets that carry one FP32 rounding
+of the cell-to-cell shift, and the kernel-derivative term dF/dr / r of a
+pair is about ten times more sensitive to a relative error in r than the
+force (it scales as r^-5 against r^-3 in the q >= 2 branch, and its spline
+branch is a difference of terms near q = 1); each output sums some 10^3 such
+terms, partly cancelling, plus FP32 atomic sums of node adjoints (summed in
+FP64 afterwards). Ten times u times 10^3 terms, relative to the largest
+output, is ~6e-4 in the worst case; the measured errors are 1e-6 to 1e-5,
+and 1e-4 keeps a factor of 10 or more above them.
 """
 import sys
 
@@ -18,7 +25,7 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-9, "mixed": 2e-3}
+TOL = {"fp64": 1e-9, "mixed": 1e-4}
 CASES = [(300, 4, "clustered"), (1001, 8, "plummer"), (5000, 12, "uniform")]
 
 
@@ -114,7 +121,7 @@ def test_refresh_matches_oracle_refresh(prec):
     moved = [c.x + 2e-3 * rng.normal(size=c.n), c.y + 2e-3 * rng.normal(size=c.n),
              c.z + 2e-3 * rng.normal(size=c.n), c.m * rng.uniform(0.9, 1.1, c.n),
              c.h * rng.uniform(0.9, 1.1, c.n)]
-    tree.refresh(*[_t(a) for a in moved])
+    tree.refresh(*[_t(a) for a in moved], keep_lists=True)
     ot.refresh(*moved)
     compare_trees(tree, ot)
     a = np.stack([_np(v) for v in tree.gravity()], 1)
@@ -135,7 +142,7 @@ def test_vjp_matches_finite_differences_on_refreshed_tree():
     dx, dy, dz, dm = [_np(o) for o in tree.vjp(*[_t(a) for a in g])]
 
     def L(vals):
-        tree.refresh(*[_t(a) for a in vals])
+        tree.refresh(*[_t(a) for a in vals], keep_lists=True)
         acc = [_np(v) for v in tree.gravity()]
         return float(sum(np.dot(gi, ai) for gi, ai in zip(g, acc)))
 

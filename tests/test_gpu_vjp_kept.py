@@ -47,7 +47,7 @@ def test_vjp_with_kept_and_computed_coefficients(prec):
     rng = np.random.default_rng(5)
     moved = [c.x + 2e-3 * rng.normal(size=c.n), c.y + 2e-3 * rng.normal(size=c.n),
              c.z + 2e-3 * rng.normal(size=c.n), c.m * rng.uniform(0.9, 1.1, c.n), c.h]
-    tree.refresh(*[_t(a) for a in moved])
+    tree.refresh(*[_t(a) for a in moved], keep_lists=True)   # the VJP's fixed tree
     ot.refresh(*moved)
     ref2 = ot.vjp(*g)
     stale = _rel(ref2, ref)

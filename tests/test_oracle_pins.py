@@ -458,6 +458,76 @@ def test_reading_a_is_the_more_accurate_at_the_working_angles():
         assert err["A"]["mean"] < err["B"]["mean"] and err["A"]["p99"] < err["B"]["p99"], th
 
 
+def _line16(y):
+    """16 equal masses on the x axis at x = 0, 1, ..., 15 (y given per
+    particle, z = 0), one particle per lowest-level cell (N_ll = 1, k = 4).
+    Every split is along x through a half-integer centre of mass, so the
+    cells are known by hand: particle i sits in leaf 16 + i; node 2 holds
+    particles 0..7 (box x in [0, 7.5]), node 3 particles 8..15 (box x in
+    [7.5, 15]), node 6 particles 8..11 (box x in [7.5, 11.5]), node 7
+    particles 12..15 (box x in [11.5, 15]). h is tiny, so no cell that does
+    not hold the sink's particle is reachable (Sec. 2.3.1)."""
+    n = 16
+    x = np.arange(n, dtype=np.float64)
+    z = np.zeros(n)
+    m = np.full(n, 1.0 / n)
+    h = np.full(n, 1e-4)
+    return O.OracleTree(x, np.asarray(y, np.float64), z, m, h, n_ll=1)
+
+
+def _far(t, leaf):
+    return set(int(v) for v in t.leaf_lists(leaf)[1])
+
+
+def test_mac_decisions_on_hand_built_cells():
+    """Eq. 4 (Sec. 2.4.1) decided by hand: cell B is accepted for sink cell A
+    iff H_B < theta R_AB, with H_B the longest side of B's box and R_AB the
+    distance of the two centres of mass.
+
+    y alternates -0.25, +0.25, so every box is 0.5 high and its centre of
+    mass has y = 0 (equal numbers of each sign) unless it holds one particle.
+    Sink leaf 16 (particle 0 at (0, -0.25, 0)) against node 3: H_3 = 7.5
+    (box 7.5 x 0.5 x 0), COM_3 = (11.5, 0, 0), R^2 = 11.5^2 + 0.25^2, so the
+    critical angle is theta* = 7.5 / sqrt(132.3125) = 0.65202... Just above it
+    node 3 is accepted; just below it node 3 is opened and its children 6
+    (H = 4, R ~ 9.5) and 7 (H = 3.5, R ~ 13.5) are accepted instead. The
+    readings that would move the decision: box centres instead of centres of
+    mass (R = 11 -> theta* = 0.68), the sink's own side (H_16 = 0.5 -> always
+    accepted), the box diagonal (sqrt(7.5^2 + 0.5^2) -> theta* = 0.6535) or
+    theta instead of theta^2 (accepted at theta*)."""
+    y = np.where(np.arange(16) % 2 == 0, -0.25, 0.25)
+    t = _line16(y)
+    assert t.k == 4
+    crit = 7.5 / math.sqrt(11.5 ** 2 + 0.25 ** 2)
+    t.walk(crit * (1 + 1e-9))
+    assert 3 in _far(t, 16)
+    t.walk(crit * (1 - 1e-9))
+    far = _far(t, 16)
+    assert 3 not in far and {6, 7} <= far
+    # the other way round: sink leaf 31 (particle 15, x = 15, box 14.5..15)
+    # against node 2: H_2 = 7.5, COM_2 = (3.5, 0, 0), same critical angle
+    t.walk(crit * (1 + 1e-9))
+    assert 2 in _far(t, 31)
+    t.walk(crit * (1 - 1e-9))
+    assert 2 not in _far(t, 31)
+    # between the geometric-centre angle and the diagonal's: accepted only
+    # by the centre-of-mass distance and the longest side
+    t.walk(0.6530)
+    assert 3 in _far(t, 16)
+
+
+def test_mac_is_strict_at_equality():
+    """All particles on the x axis: sink leaf 20 (particle 4 at x = 4)
+    against node 3 has H_3 = 7.5 and R = 11.5 - 4 = 7.5 exactly, so at
+    theta = 1 the ratio equals theta and Eq. 4's strict inequality rejects
+    the cell; one ulp above 1 it is accepted."""
+    t = _line16(np.zeros(16))
+    t.walk(1.0)
+    assert 3 not in _far(t, 20)
+    t.walk(float(np.nextafter(1.0, 2.0)))
+    assert 3 in _far(t, 20)
+
+
 def test_accuracy_on_uniform_sphere():
     # Sec. 3.1: error falls with theta; at theta = 0.5 on the homogeneous
     # sphere the mean relative error is well below 0.1%.
