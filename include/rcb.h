@@ -164,6 +164,30 @@ rcb_status rcb_refresh(rcb_tree *t, const double *x, const double *y, const doub
                        void *stream);
 
 /*
+ * rcb_refresh(t, x, y, z, m, h, n, keep_lists = 1, stream) for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight
+ * simulation or serving loops, harnesses that forbid hipMalloc. It allocates
+ * and frees nothing: its scratch (the gathered inputs of each level, 32 bytes
+ * per particle, and the level passes' bookkeeping, about 33 bytes per
+ * particle in all) lives in one static device array of 64 MiB that every GPU
+ * the library runs on holds until the process ends. The interaction lists
+ * are kept, as with keep_lists = 1 (rcb_walk() makes new ones, and
+ * allocates). Calls on one device share the array: calls that overlap in
+ * time on one device, on any streams, race and must be serialised by the
+ * caller. The tree itself must already exist (rcb_build allocates).
+ *  Arguments, results and the other errors as rcb_refresh.
+ * Errors: RCB_ECAPACITY if the tree needs more scratch than the array holds
+ * (rcb_refresh_noalloc_scratch(t) > rcb_refresh_noalloc_scratch(NULL):
+ * about 2 million particles).
+ */
+rcb_status rcb_refresh_noalloc(rcb_tree *t, const double *x, const double *y, const double *z,
+                               const double *m, const double *h, int64_t n, void *stream);
+
+/* Scratch bytes rcb_refresh_noalloc needs for tree t; with t == NULL the
+   size of the static array (the maximum). */
+size_t rcb_refresh_noalloc_scratch(const rcb_tree *t);
+
+/*
  * Tree walk (Sec. 2.2, with the reachability test of Sec. 2.3.1 and the MAC
  * of Sec. 2.4.1): makes the near and far interaction lists of every
  * lowest-level cell and keeps them in the tree. The neighbour and gravity

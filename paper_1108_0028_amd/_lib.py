@@ -57,7 +57,7 @@ class RcbTreeInfo(C.Structure):
 
 EXPORTED = ["rcb_params_default", "rcb_build", "rcb_check_cells", "rcb_refresh", "rcb_walk", "rcb_neighbours_count", "rcb_neighbours_fill",
             "rcb_gravity", "rcb_gravity_vjp", "rcb_get_info", "rcb_tree_export", "rcb_destroy",
-            "rcb_release_cache", "rcb_last_error"]
+            "rcb_release_cache", "rcb_refresh_noalloc", "rcb_refresh_noalloc_scratch", "rcb_last_error"]
 
 _lib = None
 
@@ -84,6 +84,10 @@ def lib():
         L.rcb_check_cells.restype = C.c_int
         L.rcb_refresh.argtypes = [P, P, P, P, P, P, C.c_int64, C.c_int32, P]
         L.rcb_refresh.restype = C.c_int
+        L.rcb_refresh_noalloc.argtypes = [P, P, P, P, P, P, C.c_int64, P]
+        L.rcb_refresh_noalloc.restype = C.c_int
+        L.rcb_refresh_noalloc_scratch.argtypes = [P]
+        L.rcb_refresh_noalloc_scratch.restype = C.c_size_t
         L.rcb_walk.argtypes = [P, P]
         L.rcb_walk.restype = C.c_int
         L.rcb_neighbours_count.argtypes = [P, P, C.POINTER(C.c_int64), P]

@@ -17,6 +17,8 @@
 // combines the chunk sums, and the partition runs as count / scan / scatter
 // over the same chunks. Kernels are HBM-bound: each level reads 32 B and
 // writes 36 B per particle.
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "rcb_internal.h"
@@ -1477,30 +1479,52 @@ rcb_status count_outside(rcb_tree *t, const double *x, const double *y, const do
     return RCB_OK;
 }
 
+// Scratch of a moments-only refresh, carved from one block: the gathered
+// inputs of a level (4 FP64 per particle) and the big-node machinery of the
+// level passes (no partition). Returns the bytes needed; with base != null
+// also sets the pointers (each sub-buffer 256-byte aligned).
+struct RefreshScratch {
+    double *rx, *ry, *rz, *rm;
+    BuildScratch b;
+};
+
+static size_t refresh_layout(const rcb_tree *t, char *base, RefreshScratch *r) {
+    const int64_t n = t->n;
+    const int64_t max_big = std::min<int64_t>(t->nleaf, n / (kChunk + 1) + 1);
+    const int64_t max_items = n / kChunk + max_big + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *p = base ? (void *)(base + off) : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    RefreshScratch z{};
+    z.rx = (double *)take(sizeof(double) * n);
+    z.ry = (double *)take(sizeof(double) * n);
+    z.rz = (double *)take(sizeof(double) * n);
+    z.rm = (double *)take(sizeof(double) * n);
+    z.b.max_big = max_big;
+    z.b.max_items = max_items;
+    z.b.ctl = (int32_t *)take(sizeof(int32_t) * 4);
+    z.b.big_node = (int32_t *)take(sizeof(int32_t) * max_big);
+    z.b.big_base = (int32_t *)take(sizeof(int32_t) * max_big);
+    z.b.item_big = (int32_t *)take(sizeof(int32_t) * max_items);
+    z.b.part = (double *)take(sizeof(double) * 8 * max_items);
+    z.b.pack_groups = (int32_t *)take(sizeof(int32_t) * (t->nleaf / 2 + 1));
+    if (r) *r = z;
+    return off;
+}
+
 // Moments-only refresh (the tree held fixed): new inputs in the built order,
 // then every node's M, centre of mass, h_node_int, leaf Eq. 1 quadrupole and
 // h_node by the same canonical sums as the build, Eq. 2 upwards, and the walk
 // records; boxes, splits and ranges stay. The caller decides what happens to
 // the interaction lists (rcb_refresh).
-rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const double *z,
-                        const double *m, const double *h, hipStream_t s) {
+static rcb_status refresh_core(rcb_tree *t, const double *x, const double *y, const double *z,
+                               const double *m, const double *h, RefreshScratch &r, hipStream_t s) {
     const int64_t n = t->n;
     t->farc_valid = false;   // the kept far coefficients belong to the old moments
-    Scratch tmp(t, s);
-    auto A = [&](size_t bytes) { return dalloc(t, bytes, s, tmp); };
-    BuildScratch b{};
-    b.max_big = std::min<int64_t>(t->nleaf, n / (kChunk + 1) + 1);
-    b.max_items = n / kChunk + b.max_big + 1;
-    b.ctl = (int32_t *)A(sizeof(int32_t) * 4);
-    b.big_node = (int32_t *)A(sizeof(int32_t) * b.max_big);
-    b.big_base = (int32_t *)A(sizeof(int32_t) * b.max_big);
-    b.item_big = (int32_t *)A(sizeof(int32_t) * b.max_items);
-    b.part = (double *)A(sizeof(double) * 8 * b.max_items);
-    b.pack_groups = (int32_t *)A(sizeof(int32_t) * (t->nleaf / 2 + 1));
-    double *rx = (double *)A(sizeof(double) * n), *ry = (double *)A(sizeof(double) * n);
-    double *rz = (double *)A(sizeof(double) * n), *rm = (double *)A(sizeof(double) * n);
-    for (void *p : tmp)
-        if (!p) return RCB_ENOMEM;
+    BuildScratch &b = r.b;
     if (t->p.validate) {
         const int nbp = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
         RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t), s));
@@ -1524,7 +1548,7 @@ rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const dou
     for (int lvl = 0; lvl <= t->k; ++lvl) {
         const int32_t *idl = t->lvl_id + (int64_t)lvl * n;
         const bool leaf = lvl == t->k;
-        PartIn in{rx, ry, rz, rm, nullptr};
+        PartIn in{r.rx, r.ry, r.rz, r.rm, nullptr};
         if (leaf) in = PartIn{t->px, t->py, t->pz, t->pm, t->ph};
         k_refresh_gather<<<gN, kBlock, 0, s>>>(x, y, z, m, h, idl, n, (double *)in.x, (double *)in.y,
                                                (double *)in.z, (double *)in.m, leaf ? t->ph : nullptr);
@@ -1547,6 +1571,70 @@ rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const dou
     }
     t->nb_total = -1;   // neighbour counts belong to the old positions
     return RCB_OK;
+}
+
+rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const double *z,
+                        const double *m, const double *h, hipStream_t s) {
+    Scratch tmp(t, s);
+    const size_t bytes = refresh_layout(t, nullptr, nullptr);
+    char *base = (char *)dalloc(t, bytes, s, tmp);
+    if (!base) return RCB_ENOMEM;
+    RefreshScratch r;
+    refresh_layout(t, base, &r);
+    return refresh_core(t, x, y, z, m, h, r, s);
+}
+
+// ---------------------------------------------------------------------------
+// Refresh without allocation: the scratch lives in one static device array
+// per GPU. Its name is only a host-side stand-in for the symbol; the device
+// address is looked up once per device and used everywhere host code needs
+// the memory. Calls on one device share the array, so calls that overlap
+// race; every buffer that must start at zero is cleared by the level passes.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {nullptr};
+}  // namespace
+
+size_t refresh_noalloc_bytes(const rcb_tree *t) { return refresh_layout(t, nullptr, nullptr); }
+
+size_t refresh_noalloc_capacity() { return kNoAllocScratchBytes; }
+
+rcb_status refresh_tree_noalloc(rcb_tree *t, const double *x, const double *y, const double *z,
+                                const double *m, const double *h, hipStream_t s) {
+    const size_t bytes = refresh_layout(t, nullptr, nullptr);
+    if (bytes > kNoAllocScratchBytes) {
+        set_error("rcb_refresh_noalloc: the tree needs " + std::to_string(bytes) +
+                  " bytes of scratch, more than the " + std::to_string(kNoAllocScratchBytes) +
+                  " of the static array (about " + std::to_string(kNoAllocScratchBytes / 33) +
+                  " particles); use rcb_refresh");
+        return RCB_ECAPACITY;
+    }
+    int dev = 0;
+    RCB_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) {
+        set_error("rcb_refresh_noalloc: device index out of range");
+        return RCB_EINVAL;
+    }
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void *p = nullptr;
+            hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) return hip_fail(e == hipSuccess ? hipErrorInvalidSymbol : e,
+                                                        "hipGetSymbolAddress(scratch)");
+            g_scratch_ptr[dev] = p;
+        }
+        ptr = g_scratch_ptr[dev];
+    }
+    RefreshScratch r;
+    refresh_layout(t, (char *)ptr, &r);
+    return refresh_core(t, x, y, z, m, h, r, s);
 }
 
 }  // namespace rcb

@@ -320,6 +320,29 @@ rcb_status rcb_refresh(rcb_tree *t, const double *x, const double *y, const doub
     return RCB_OK;
 }
 
+rcb_status rcb_refresh_noalloc(rcb_tree *t, const double *x, const double *y, const double *z,
+                               const double *m, const double *h, int64_t n, void *stream) {
+    g_last_error.clear();
+    if (!t || !x || !y || !z || !m || !h) {
+        set_error("rcb_refresh_noalloc: NULL argument");
+        return RCB_EINVAL;
+    }
+    if (n != t->n) {
+        set_error("rcb_refresh_noalloc: n = " + std::to_string(n) + " differs from the built n = " +
+                  std::to_string(t->n));
+        return RCB_ESTATE;
+    }
+    t->stream = (hipStream_t)stream;
+    rcb_status st = refresh_tree_noalloc(t, x, y, z, m, h, t->stream);
+    if (st != RCB_OK) return st;
+    if (t->walked) t->lists_kept = true;   // as rcb_refresh(keep_lists = 1): nothing is freed
+    return RCB_OK;
+}
+
+size_t rcb_refresh_noalloc_scratch(const rcb_tree *t) {
+    return t ? refresh_noalloc_bytes(t) : refresh_noalloc_capacity();
+}
+
 rcb_status rcb_walk(rcb_tree *t, void *stream) {
     g_last_error.clear();
     if (!t) {

@@ -147,6 +147,12 @@ rcb_status count_outside(rcb_tree *t, const double *x, const double *y, const do
 // moments-only refresh with new inputs, topology held fixed (k_build.hip)
 rcb_status refresh_tree(rcb_tree *t, const double *x, const double *y, const double *z,
                         const double *m, const double *h, hipStream_t s);
+// the same with its scratch in the library's static device array: no
+// allocation; RCB_ECAPACITY if the tree needs more than the array holds
+rcb_status refresh_tree_noalloc(rcb_tree *t, const double *x, const double *y, const double *z,
+                                const double *m, const double *h, hipStream_t s);
+size_t refresh_noalloc_bytes(const rcb_tree *t);
+size_t refresh_noalloc_capacity();
 // device exclusive scan of int64 counts in place-free form: out[0..n] (k_scan.hip)
 rcb_status scan_i64(rcb_tree *t, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
 // walk (k_walk.hip)

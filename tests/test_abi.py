@@ -94,6 +94,7 @@ def test_null_tree_arguments():
     tot = C.c_int64()
     assert L.rcb_walk(None, None) == 1
     assert L.rcb_refresh(None, *([C.c_void_p(8)] * 5), 1, 0, None) == 1
+    assert L.rcb_refresh_noalloc(None, *([C.c_void_p(8)] * 5), 1, None) == 1
     assert L.rcb_check_cells(None, *([C.c_void_p(8)] * 3), 1, C.byref(tot), None) == 1
     assert L.rcb_neighbours_count(None, C.c_void_p(8), C.byref(tot), None) == 1
     assert L.rcb_neighbours_fill(None, C.c_void_p(8), C.c_void_p(8), 1, None) == 1
@@ -101,3 +102,8 @@ def test_null_tree_arguments():
     assert L.rcb_gravity_vjp(None, *([C.c_void_p(8)] * 7), None) == 1
     assert L.rcb_tree_export(None, 0, C.c_void_p(8), 8, None) == 1
     L.rcb_destroy(None)
+
+
+def test_noalloc_refresh_capacity_is_stated():
+    L = _lib()
+    assert L.rcb_refresh_noalloc_scratch(None) == 64 << 20
