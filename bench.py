@@ -7,15 +7,18 @@ form and the FP64 CPU oracle.
 One step = rcb_build + rcb_walk + rcb_neighbours_count + rcb_neighbours_fill
 + rcb_gravity on inputs already resident in HBM, tree destroyed at the end.
 
-Prints ONE JSON line (rank 0). Extra fields: the FP64-form throughput, the
-mixed form's error against the FP64 form, per-phase times (HIP events on the
-library's stream inside the timed region), the roofline of the dominant
-kernel (k_gravity, one launch per step), the per-leaf HBM model of walk +
-gravity, and the oracle's CPU baseline.
+Prints ONE JSON line. Besides the contract fields: the FP64 form's
+throughput, the mixed form's error against the FP64 form, per-phase times
+(HIP events on the library's stream inside the timed region) with each
+phase's algorithmic work against its own bound, the roofline of the dominant
+kernel (k_gravity, one launch per step), the VJP's time against the
+forward's, the device memory a step holds, the force error against the
+direct sum on sampled particles, and the oracle's CPU baseline.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,19 +28,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X published peaks and the derived vector peak available to these kernels
-# (packed FP32 is disabled, so FP32 issues at the FP64 rate):
-# 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s.
+# MI355X published peaks
 PEAK_HBM_GBS = 8000.0
-PEAK_VALU_TFLOPS = 78.6
+PEAK_FP64_TFLOPS = 78.6        # vector FP64
+PEAK_FP32_TFLOPS = 157.3       # vector FP32
 
-# Algorithmic operation counts of one interaction, frozen from one count of
-# the straightforward formulas (an FMA counts as 2, a reciprocal or
-# reciprocal square root as 1); kernel rewrites that need fewer instructions
-# do not change them.
-FLOP_P2P = 38          # near pair: offset, r^2, rsqrt, rcp, q, both spline branches, m F v
-FLOP_M2L = 226         # far pair: D1..D5, Q x, x.Q.x, 3 f + 6 J + 10 H coefficients
-FLOP_L2P = 66          # per sink: f + J d + H[d, d]/2
+# Algorithmic operation weights per unit of work (fixed; kernel rewrites do
+# not change them): a near pair ~27 flop (FP32 in the mixed form), a far
+# (leaf, node) pair ~400 flop (FP64 M2L of reading A), a sink ~40 flop (L2P),
+# a (node, leaf) walk test ~20 flop (FP64: reachability and MAC), a candidate
+# pair of the neighbour cull ~8 flop (FP64 squared distance and compare).
+FLOP_P2P = 27
+FLOP_M2L = 400
+FLOP_L2P = 40
+FLOP_TEST = 20
+FLOP_CULL = 8
 
 
 def _args():
@@ -51,7 +56,11 @@ def _args():
     ap.add_argument("--pure-mac", action="store_true",
                     help="gravity lists from the geometric MAC alone (reachable cells may be accepted)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the steps only (for profiler runs): no counts, VJP, other form or errors")
     ap.add_argument("--cpu-leaves", type=int, default=2048)
+    ap.add_argument("--direct-leaves", type=int, default=160,
+                    help="lowest-level cells whose particles get the exact direct sum (cpu_baseline leg)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration for profiles)")
     return ap.parse_args()
@@ -60,7 +69,7 @@ def _args():
 def main():
     a = _args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: runs on one GPU only (no multi-GPU path); use --gpus 1",
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
@@ -76,7 +85,7 @@ def main():
     arrs = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in cloud.arrays()]
     torch.cuda.synchronize()
 
-    def step(prec, ev=None):
+    def step(prec, ev=None, keep=False):
         """One step: build, walk, neighbour search, gravity; events (if given)
         bracket each phase on the stream the library launches on."""
         rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
@@ -89,8 +98,10 @@ def main():
         rec(3)
         acc = t.gravity()
         rec(4)
+        if keep:
+            return t, acc, off
         t.destroy()
-        return acc, off
+        return None, acc, off
 
     def timed(prec, steps, warmup):
         for _ in range(warmup):
@@ -111,63 +122,24 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    # device memory one step holds (library pool + neighbour CSR), before any
+    # other tree has been made
+    mem = None
+    if not a.no_extras:
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        t_keep, _, off_keep = step(a.precision, keep=True)
+        torch.cuda.synchronize()
+        free1 = torch.cuda.mem_get_info()[0]
+        mem = {"bytes": int(free0 - free1), "bytes_per_particle": (free0 - free1) / n,
+               "basis": "device memory taken by one live step (tree, lists, neighbour slab and CSR, "
+                        "accelerations), from hipMemGetInfo"}
+        t_keep.destroy()
+        del off_keep
+
     sec, phases = timed(a.precision, a.steps, a.warmup)
     value = n / sec
-    grav_ms = phases["gravity"]   # one launch of k_gravity per step
-
-    # work counts of this tree for the roofline (outside the timed region)
-    t = Tree(*arrs, n_ll=a.n_ll, theta=a.theta, precision=a.precision, pure_mac=a.pure_mac)
-    cnt = t.export("count").to(torch.int64)
-    near = t.export("near").to(torch.int64)
-    in_field = (near & (1 << 30)) == 0     # entries of the gravity near field
-    near = near & 0x3FFFFFFF
-    noff = t.export("near_off")
-    foff = t.export("far_off")
-    inf = t.info()              # list totals are known once the lists exist
-    nleaf = 1 << inf["k"]
-    leaf = torch.arange(nleaf, device=dev)
-    L_A = noff[1:] - noff[:-1]
-    F_A = foff[1:] - foff[:-1]
-    n_A = cnt[nleaf:2 * nleaf]
-    P_A = torch.zeros(nleaf, dtype=torch.int64, device=dev).index_add_(
-        0, torch.repeat_interleave(leaf, L_A), cnt[near] * in_field)
-    pairs = int((P_A * n_A).sum())
-    t.destroy()
-    far_total = inf["far_total"]
-    near_total = inf["near_total"]
-
-    flops = FLOP_P2P * pairs + FLOP_M2L * far_total + FLOP_L2P * n
-    achieved_tf = flops / (grav_ms * 1e-3) / 1e12
-    traffic = _profiled_traffic("k_gravity_mixed") if a.precision == "mixed" else None
-    roofline = {"kernel": f"k_gravity<{a.precision}>", "bound": "alu", "achieved": achieved_tf,
-                "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tf / PEAK_VALU_TFLOPS,
-                "traffic": traffic, "kernel_ms": grav_ms, "pairs": pairs, "far_pairs": far_total,
-                "near_cells": near_total, "walk_requeued_groups": inf["walk_requeued"]}
-    # the per-leaf streaming model of the walk + gravity (bytes each lowest-level
-    # cell would read on its own): nodes tested V ~ 2 (F + L) in a binary walk
-    V_A = 2 * (F_A + L_A)
-    if a.precision == "mixed":
-        model_b = int((32 * V_A + 8 * L_A + 80 * F_A + 20 * P_A + 32 * n_A).sum())
-    else:
-        model_b = int((64 * V_A + 8 * L_A + 80 * F_A + 40 * P_A + 64 * n_A).sum())
-    wg_ms = phases["walk"] + phases["gravity"]
-    walk_model = {"bytes": model_b, "ms": wg_ms, "floor_ms": model_b / (PEAK_HBM_GBS * 1e9) * 1e3,
-                  "frac": model_b / (PEAK_HBM_GBS * 1e9) / (wg_ms * 1e-3)}
-
-    # the other form and the mixed-vs-FP64 error
-    other = "fp64" if a.precision == "mixed" else "mixed"
-    sec_o, _ = timed(other, max(2, a.steps // 3), 1)
-    acc_m, off = step("mixed")
-    acc_d, _ = step("fp64")
-    am = torch.stack([v.double() for v in acc_m], 1)
-    ad = torch.stack([v.double() for v in acc_d], 1)
-    da = (am - ad).norm(dim=1)
-    na = ad.norm(dim=1)
-    rms = float(na.pow(2).mean().sqrt())
-    rel = da / na.clamp_min(1e-300)
-    err = {"gate_max": float((da / na.clamp_min(1e-3 * rms)).max()),
-           "mean": float(rel.mean()), "p99": float(torch.quantile(rel.float(), 0.99))}
-
     out = {
         "metric": "particles/sec (build+neighbours+gravity), 4M Plummer: mixed FP32 vs FP64 at stated err",
         "value": value,
@@ -186,46 +158,201 @@ def main():
                    "n": n, "n_ll": a.n_ll, "theta": a.theta, "precision": a.precision,
                    "walk": "pure MAC" if a.pure_mac else "reachability overrides MAC (paper)"},
         "phases_ms": phases,
-        "other_form": {"precision": other, "value": n / sec_o, "ms_per_step": sec_o * 1e3},
-        "mixed_vs_fp64_error": err,
-        "neighbours_total": int(off[-1]),
-        "roofline": roofline,
-        "walk_gravity_hbm_model": walk_model,
     }
+    if a.no_extras:
+        print(json.dumps(out), flush=True)
+        return
+
+    # work counts of this tree (outside the timed region)
+    t, acc_m, off = step(a.precision, keep=True)
+    counts = _work_counts(t, off, n)
+    roof, phase_roof = _rooflines(counts, phases, a.precision, n, t.info()["k"])
+    out["roofline"] = roof
+    out["phases_roofline"] = phase_roof
+    out["neighbours_total"] = counts["neighbours"]
+    out["memory"] = mem
+    # VJP on the same tree after gravity (the far coefficients are kept)
+    out["vjp"] = _vjp_timing(t, n, phases, a.precision)
+    t.destroy()
+
+    # the other form and the mixed-vs-FP64 error
+    other = "fp64" if a.precision == "mixed" else "mixed"
+    sec_o, _ = timed(other, max(2, a.steps // 3), 1)
+    _, acc_o, _ = step(other)
+    acc = {a.precision: torch.stack([v.double() for v in acc_m], 1),
+           other: torch.stack([v.double() for v in acc_o], 1)}
+    da = (acc["mixed"] - acc["fp64"]).norm(dim=1)
+    na = acc["fp64"].norm(dim=1)
+    rms = float(na.pow(2).mean().sqrt())
+    rel = da / na.clamp_min(1e-300)
+    out["other_form"] = {"precision": other, "value": n / sec_o, "ms_per_step": sec_o * 1e3}
+    out["mixed_vs_fp64_error"] = {"gate_max": float((da / na.clamp_min(1e-3 * rms)).max()),
+                                  "mean": float(rel.mean()), "p99": float(torch.quantile(rel.float(), 0.99))}
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cloud, a)
+        base, direct = cpu_baseline(cloud, a)
+        out["cpu_baseline"] = base
+        out["force_error_vs_direct_sum"] = _direct_errors(direct, acc, a.theta)
     print(json.dumps(out), flush=True)
 
 
-def _profiled_traffic(name):
-    """HBM bytes per launch from the committed rocprofv3 counter summary
-    profiles/<name>_counters.md, if the kernel's sources are unchanged since
-    the counters were taken (else None)."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", f"{name}_counters.md")
-    if not os.path.exists(path):
-        return None
-    rec = {}
-    for line in open(path):
-        if line.startswith("- ") and ": " in line:
-            k, v = line[2:].split(": ", 1)
-            rec[k.strip()] = v.strip().strip("`")
-    try:
-        h = hashlib.sha256()
-        for f in rec["sources"].split(", "):
-            h.update(open(os.path.join(ROOT, f), "rb").read())
-        if h.hexdigest() != rec["sources_sha256"]:
-            return None
-        return int(rec["hbm_bytes_per_launch"])
-    except (KeyError, OSError, ValueError):
-        return None
+def _work_counts(t, off, n):
+    """Units of work of one step, counted from the tree's own lists."""
+    import torch
+    dev = off.device
+    cnt = t.export("count").to(torch.int64)
+    near = t.export("near").to(torch.int64)
+    noff = t.export("near_off")
+    inf = t.info()              # list totals are known once the per-cell lists exist
+    nleaf = 1 << inf["k"]
+    in_field = (near & (1 << 30)) == 0      # entries of the gravity near field
+    cand = (near & (1 << 31)) != 0          # entries holding neighbour candidates
+    lab = near & 0x3FFFFFFF
+    L_A = noff[1:] - noff[:-1]
+    n_A = cnt[nleaf:2 * nleaf]
+    leaf = torch.repeat_interleave(torch.arange(nleaf, device=dev), L_A)
+    P_A = torch.zeros(nleaf, dtype=torch.int64, device=dev).index_add_(0, leaf, cnt[lab] * in_field)
+    C_A = torch.zeros(nleaf, dtype=torch.int64, device=dev).index_add_(0, leaf, cnt[lab] * cand)
+    return {"pairs": int((P_A * n_A).sum()), "far_pairs": inf["far_total"], "near_cells": inf["near_total"],
+            "cand_particles": int(C_A.sum()), "cand_pairs": int((C_A * n_A).sum()),
+            "neighbours": int(off[-1]), "walk_nodes": inf["walk_nodes"], "walk_tests": inf["walk_tests"],
+            "walk_requeued_groups": inf["walk_requeued"], "n": n}
+
+
+def _profiled(kernel):
+    """FETCH_SIZE + WRITE_SIZE bytes per launch of `kernel` from a committed
+    rocprofv3 counter summary (profiles/*_counters.md), while the sources it
+    lists are unchanged (else None)."""
+    pdir = os.path.join(ROOT, "profiles")
+    for fn in sorted(os.listdir(pdir)):
+        if not fn.endswith("_counters.md"):
+            continue
+        rec, cur = {}, None
+        for line in open(os.path.join(pdir, fn)):
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                rec[k.strip()] = v.strip().strip("`")
+        try:
+            h = hashlib.sha256()
+            for f in rec["sources"].split(", "):
+                h.update(open(os.path.join(ROOT, f), "rb").read())
+            if h.hexdigest() != rec["sources_sha256"]:
+                continue
+            for item in rec["hbm_bytes_per_launch"].split("; "):
+                name, val = item.rsplit("=", 1)
+                if name.strip() == kernel:
+                    cur = int(val)
+        except (KeyError, OSError, ValueError):
+            continue
+        if cur is not None:
+            return cur
+    return None
+
+
+def _rooflines(c, phases, prec, n, k):
+    """The dominant kernel's roofline and each phase's algorithmic work against
+    its own bound (HBM bytes against 8 TB/s; flops against the vector peak of
+    their type; a mixed FP32/FP64 phase against the time both parts would need
+    at their peaks)."""
+    mixed = prec == "mixed"
+
+    def alu(f32, f64, ms):
+        floor_s = f32 / (PEAK_FP32_TFLOPS * 1e12) + f64 / (PEAK_FP64_TFLOPS * 1e12)
+        tot = f32 + f64
+        ach = tot / (ms * 1e-3) / 1e12
+        peak = tot / floor_s / 1e12 if floor_s > 0 else PEAK_FP64_TFLOPS
+        return {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "flops_fp32": f32, "flops_fp64": f64}
+
+    def hbm(nbytes, ms):
+        ach = nbytes / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "bytes": nbytes}
+
+    # gravity: near pairs (FP32 in the mixed form), far pairs (FP64 M2L), L2P per sink
+    near_f = FLOP_P2P * c["pairs"] + FLOP_L2P * n
+    far_f = FLOP_M2L * c["far_pairs"]
+    g = alu(near_f if mixed else 0, far_f + (0 if mixed else near_f), phases["gravity"])
+    kname = "k_gravity<true, false>" if mixed else "k_gravity<false, false>"
+    g.update({"kernel": kname, "kernel_ms": phases["gravity"], "traffic": _profiled(kname),
+              "basis": f"{FLOP_P2P} flop per near pair ({c['pairs']}), {FLOP_M2L} per far pair "
+                       f"({c['far_pairs']}), {FLOP_L2P} per sink ({n}); one launch per step, timed by "
+                       "HIP events on its stream"})
+    # build: compulsory HBM bytes N (48 k + 100) (each of the k levels reads
+    # and writes the node's particle data and order; the leaf level, bounds,
+    # gather and records the rest)
+    b = hbm(n * (48 * k + 100), phases["build"])
+    b["basis"] = f"N (48 k + 100) bytes, k = {k}"
+    # walk: FP64 tests of (node, visiting cell) pairs; also the node records it loads
+    w = alu(0, FLOP_TEST * c["walk_tests"], phases["walk"])
+    w["hbm_bytes"] = 64 * c["walk_nodes"]
+    w["hbm_frac"] = w["hbm_bytes"] / (phases["walk"] * 1e-3) / (PEAK_HBM_GBS * 1e9)
+    w["basis"] = (f"{FLOP_TEST} FP64 flop per (node, cell) test ({c['walk_tests']}); 64 B per node record "
+                  f"loaded per group of 8 cells ({c['walk_nodes']})")
+    w["traffic"] = _profiled("k_walk_wide<false, 1024, 4>")
+    # neighbours: FP64 distance test of every candidate pair; bytes: candidates
+    # (position + id), ids written and compacted, offsets
+    nb = alu(0, FLOP_CULL * c["cand_pairs"], phases["neighbours"])
+    nbytes = 28 * c["cand_particles"] + 12 * c["neighbours"] + 16 * n
+    nb["hbm_bytes"] = nbytes
+    nb["hbm_frac"] = nbytes / (phases["neighbours"] * 1e-3) / (PEAK_HBM_GBS * 1e9)
+    nb["basis"] = (f"{FLOP_CULL} FP64 flop per candidate pair ({c['cand_pairs']}); 28 B per candidate "
+                   f"particle of a cell ({c['cand_particles']}), 12 B per neighbour id, 16 B per particle")
+    nb["traffic"] = {k_: _profiled(k_) for k_ in ("k_neigh<true>", "k_nb_compact")}
+    g["counts"] = c
+    return g, {"build": b, "walk": w, "neighbours": nb, "gravity": {k_: v for k_, v in g.items()
+                                                                     if k_ != "counts"}}
+
+
+def _vjp_timing(t, n, phases, prec):
+    """rcb_gravity_vjp on the step's tree (after its gravity call), N(0,1)
+    cotangents; HIP events on the library's stream."""
+    import torch
+    import workloads as W
+    dt = torch.float32 if prec == "mixed" else torch.float64
+    g = [torch.from_numpy(v).to("cuda:0", dt) for v in W.cotangents(n)]
+    t.vjp(*g)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 3
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        t.vjp(*g)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    fwd = phases["build"] + phases["walk"] + phases["gravity"]
+    return {"ms": ms, "forward_ms": fwd, "vjp_over_forward": ms / fwd,
+            "basis": "forward = build + walk + gravity of the timed steps; the VJP reuses the tree, its "
+                     "lists and the far coefficients kept by the gravity call"}
+
+
+def _direct_errors(direct, acc, theta):
+    """Relative force errors (Sec. 3.1) of both forms at the bench's theta on
+    the sampled particles against the exact FP64 direct sum."""
+    import numpy as np
+    idx, ref = direct
+    out = {"theta": theta, "sinks": int(idx.size),
+           "reference": "oracle at theta = 0 (every cell near: the kernel-softened direct sum over all "
+                        "particles, FP64) on the particles of randomly sampled lowest-level cells"}
+    na = np.linalg.norm(ref, axis=1)
+    rms = float(np.sqrt(np.mean(na * na)))
+    for prec, a in acc.items():
+        got = a.cpu().numpy()[idx]
+        da = np.linalg.norm(got - ref, axis=1)
+        eps = da / np.maximum(na, 1e-300)
+        out[prec] = {"mean": float(eps.mean()), "p99": float(np.quantile(eps, 0.99)),
+                     "max": float(eps.max()), "frac_below_1pct": float((eps < 0.01).mean()),
+                     "gate_max": float((da / np.maximum(na, 1e-3 * rms)).max())}
+    return out
 
 
 def cpu_baseline(cloud, a):
-    """The FP64 oracle (unchanged) on the host: full tree build (serial), then
-    walk, neighbours and gravity for a random sample of leaves (OpenMP over
+    """The FP64 oracle (unchanged) on the host: full tree build, then walk,
+    neighbours and gravity for a random sample of leaves (OpenMP over
     leaves), with all threads and again with one; throughput scaled to
-    particles/s of build + neighbours + gravity."""
+    particles/s of build + neighbours + gravity. Afterwards, untimed, the
+    oracle at theta = 0 on another sample of leaves: the exact direct sum for
+    their particles."""
     import numpy as np
 
     from oracle import oracle as O
@@ -260,13 +387,22 @@ def cpu_baseline(cloud, a):
     O.set_threads(threads)
     build = t1 - t0
     rate = lambda p: 1.0 / (build / cloud.n + sum(p) / max(1, n_s))
-    return {"value": rate(ph), "unit": "particles/s", "cores": threads, "kind": "oracle",
+    base = {"value": rate(ph), "unit": "particles/s", "cores": threads, "kind": "oracle",
             "single_thread_value": rate(ph1), "cpu": model,
             "phases_s": {"build_all": build, "walk": ph[0], "neighbours": ph[1], "gravity": ph[2],
                          "walk_1thread": ph1[0], "neighbours_1thread": ph1[1], "gravity_1thread": ph1[2]},
-            "sample": f"oracle build of all {cloud.n} particles (serial, {build:.1f} s) + walk, "
-                      f"neighbours and gravity of {len(leaves)} random leaves ({n_s} particles, "
+            "sample": f"oracle build of all {cloud.n} particles ({build:.1f} s, levels split in parallel) + "
+                      f"walk, neighbours and gravity of {len(leaves)} random leaves ({n_s} particles, "
                       f"{sum(ph):.1f} s on {threads} OpenMP threads, {sum(ph1):.1f} s on 1)"}
+    # exact direct sums for the error report (not timed)
+    rng = np.random.default_rng(1)
+    dl = np.sort(rng.choice(ot.n_leaves, min(a.direct_leaves, ot.n_leaves), replace=False)) + ot.n_leaves
+    ot.walk(0.0, dl)
+    topo = ot.topology()
+    pos = np.concatenate([np.arange(topo["first"][l], topo["first"][l] + topo["count"][l]) for l in dl])
+    idx = topo["perm"][pos]
+    ref = np.stack(ot.gravity(), 1)[idx]
+    return base, (idx, ref)
 
 
 if __name__ == "__main__":

@@ -262,6 +262,11 @@ typedef struct {
     int64_t walk_requeued; /* groups of 8 lowest-level cells whose walk outgrew the first
                               FIFO (1024 nodes) and was redone with a larger one or, past
                               8192 nodes, by the 8-wide walk (same lists); -1 before the walk */
+    int64_t walk_nodes;    /* node records the breadth-first walk loaded: one per node per group
+                              of 8 sibling cells (groups walked again by a later tier count only
+                              their first attempt); -1 before the walk */
+    int64_t walk_tests;    /* (node, lowest-level cell) pairs among those whose cell's own walk
+                              reaches the node: the per-cell tests of Sec. 2.2; -1 before the walk */
 } rcb_tree_info;
 
 rcb_status rcb_get_info(const rcb_tree *t, rcb_tree_info *info /* host */);

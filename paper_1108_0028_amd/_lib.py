@@ -52,7 +52,8 @@ class RcbParams(C.Structure):
 class RcbTreeInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("k", C.c_int32), ("precision", C.c_int32),
                 ("n_labels", C.c_int64), ("near_total", C.c_int64), ("far_total", C.c_int64),
-                ("theta", C.c_double), ("walk_requeued", C.c_int64)]
+                ("theta", C.c_double), ("walk_requeued", C.c_int64), ("walk_nodes", C.c_int64),
+                ("walk_tests", C.c_int64)]
 
 
 EXPORTED = ["rcb_params_default", "rcb_build", "rcb_check_cells", "rcb_refresh", "rcb_walk", "rcb_neighbours_count", "rcb_neighbours_fill",
@@ -185,7 +186,7 @@ class Tree:
         _check(lib().rcb_get_info(self.handle, C.byref(i)), "rcb_get_info")
         return dict(n=i.n, k=i.k, precision=i.precision, n_labels=i.n_labels,
                     near_total=i.near_total, far_total=i.far_total, theta=i.theta,
-                    walk_requeued=i.walk_requeued)
+                    walk_requeued=i.walk_requeued, walk_nodes=i.walk_nodes, walk_tests=i.walk_tests)
 
     def out_dtype(self):
         return torch.float32 if self.precision == "mixed" else torch.float64

@@ -70,6 +70,7 @@ struct WalkArgs {
     int64_t near_cap, far_cap;
     uint64_t *near_list, *far_list;
     int32_t *flag;
+    unsigned long long *stats;   // if given: [0] node records tested, [1] (node, leaf) tests
 };
 
 // bit 8 s set iff byte s of x is non-zero (the lead lane of entry s)
@@ -274,6 +275,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_walk_wide(WalkArgs w, int32_t
     int head = 0, cnt = w.k == 0 ? 1 : 2;   // ring [head, head + cnt), indices mod kWQueue
     __builtin_amdgcn_wave_barrier();
     bool overflow = false;
+    uint32_t n_nodes = 0, n_tests = 0;      // this lane's share of the walk statistics
     while (cnt > 0) {
         const int b = cnt < kWave ? cnt : kWave;
         const bool act = lane < b;
@@ -289,6 +291,8 @@ __global__ __launch_bounds__(WAVES * kWave) void k_walk_wide(WalkArgs w, int32_t
         const bool isleaf = node >= nleaf;
         const uint32_t gmask = live ? qm & 0xffu : 0u;
         const uint32_t nmask = PURE && live ? (qm >> 8) & 0xffu : 0u;
+        n_nodes += act;
+        n_tests += __popc(gmask | nmask);
         const double H2 = cb.w * cb.w;
         const int lvl = 31 - __builtin_clz((uint32_t)node);
         // per leaf (last to first, shifted in): accepted were it visited, and
@@ -356,6 +360,13 @@ __global__ __launch_bounds__(WAVES * kWave) void k_walk_wide(WalkArgs w, int32_t
             if (i < w.far_cap) w.far_list[fbase + i] = (uint64_t)(uint32_t)node | ((uint64_t)far << 32);
         }
         nf += __popcll(b_far);
+    }
+    if (w.stats) {
+        const int sn = wave_sum_i((int)n_nodes), st = wave_sum_i((int)n_tests);
+        if (lane == 0) {
+            atomicAdd(&w.stats[0], (unsigned long long)sn);
+            atomicAdd(&w.stats[1], (unsigned long long)st);
+        }
     }
     if (overflow) {
         if (lane == 0 && queue) queue[atomicAdd(nqueue, 1)] = (int32_t)gi;
@@ -532,13 +543,14 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     int64_t *fcnt = (int64_t *)dalloc(t, sizeof(int64_t) * NG, s, tmp);
     int32_t *queue = (int32_t *)dalloc(t, sizeof(int32_t) * NG, s, tmp);    // groups for the 2nd tier
     int32_t *queue2 = (int32_t *)dalloc(t, sizeof(int32_t) * NG, s, tmp);   // and for k_walk_group
+    unsigned long long *stats = (unsigned long long *)dalloc(t, sizeof(unsigned long long) * 2, s, tmp);
     int64_t cn, cf;
     slab_caps(NG, cn, cf);
     std::vector<void *> slabs;
     uint64_t *nslab = (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cn, s, slabs);
     uint64_t *fslab = (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cf, s, slabs);
     for (void *p : slabs) tmp.push_back(p);   // freed at the end unless kept
-    if (!ncnt || !fcnt || !queue || !queue2 || !nslab || !fslab) return RCB_ENOMEM;
+    if (!ncnt || !fcnt || !queue || !queue2 || !stats || !nslab || !fslab) return RCB_ENOMEM;
     // RCB_WALK_WIDE_STACK (testing): smaller wide-walk rings, so that more
     // groups take the later tiers
     int cap1 = kWQueue, cap2 = kWQueue2;
@@ -550,7 +562,7 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
         }
     }
     WalkArgs w{t->wrec, t->nhnode, t->k, t->gk, NG, t->p.theta * t->p.theta, ncnt, fcnt,
-               nullptr, nullptr, cn, cf, nslab, fslab, t->dflag};
+               nullptr, nullptr, cn, cf, nslab, fslab, t->dflag, stats};
     const unsigned grid = (unsigned)((NG + kWaves - 1) / kWaves);
     const bool pure = t->p.pure_mac != 0;
     // the three tiers over all groups, then over the groups each one queued;
@@ -586,12 +598,18 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     };
     RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 4, s));
     RCB_HIP(hipMemsetAsync(t->dflag + 6, 0, sizeof(int32_t) * 2, s));
+    RCB_HIP(hipMemsetAsync(stats, 0, sizeof(unsigned long long) * 2, s));
     rcb_status wst = walk_tiers(true);
     if (wst != RCB_OK) return wst;
+    w.stats = nullptr;   // a second walk (exact lists) does not count again
     int32_t flags[4] = {0, 0, 0, 0};
+    unsigned long long hstats[2] = {0, 0};
     RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
+    RCB_HIP(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
     RCB_HIP(hipStreamSynchronize(s));
     t->walk_requeued = nq;
+    t->walk_nodes = (int64_t)hstats[0];
+    t->walk_tests = (int64_t)hstats[1];
     if (flags[0]) {
         set_error("walk: stack overflow (tree deeper than the walk stack supports)");
         return RCB_ECAPACITY;
@@ -712,6 +730,7 @@ void drop_lists(rcb_tree *t, hipStream_t s) {
     t->nb_slab = t->nb_inv = t->nb_queue = nullptr;
     t->nb_over = t->nb_nq = 0;
     t->walk_requeued = 0;
+    t->walk_nodes = t->walk_tests = -1;
     t->farc = nullptr;
     t->farc_valid = false;
 }

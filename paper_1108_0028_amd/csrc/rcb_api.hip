@@ -417,6 +417,8 @@ rcb_status rcb_get_info(const rcb_tree *t, rcb_tree_info *info) {
     info->far_total = t->leaf_lists ? t->far_total : -1;
     info->theta = t->p.theta;
     info->walk_requeued = t->walked ? t->walk_requeued : -1;
+    info->walk_nodes = t->walked ? t->walk_nodes : -1;
+    info->walk_tests = t->walked ? t->walk_tests : -1;
     return RCB_OK;
 }
 

@@ -98,6 +98,8 @@ struct rcb_tree {
     // leaves queued for the neighbour re-search (neighbours)
     int32_t *dflag = nullptr;
     int64_t walk_requeued = 0;         // groups of the last walk that outgrew the first ring
+    int64_t walk_nodes = -1;           // node records the first walk tier tested (per group)
+    int64_t walk_tests = -1;           // (node, visiting leaf) tests of the first tier
     // per leaf: the 19 far-field coefficients of the current moments (written
     // by rcb_gravity, or by the VJP if no gravity call has) and 3 VJP scratch values
     double *farc = nullptr;

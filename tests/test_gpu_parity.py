@@ -101,6 +101,11 @@ def test_tree_and_lists_bit_identical(n, nll, kind):
         gt.walk()          # explicit walk first; even sizes let the export run it
     ot.walk(0.6)
     compare_lists(gt, ot)
+    # the walk's count of (node, cell) tests equals the serial walks' visits
+    info = gt.info()
+    if info["walk_requeued"] == 0:
+        assert info["walk_tests"] == int(ot.list_sizes()[2][:, 0].sum())
+        assert info["walk_nodes"] > 0
 
 
 def test_degenerate_coincident_particles():
