@@ -22,7 +22,10 @@
  *    host values or size device lists synchronise the stream: rcb_walk()
  *    (and the first call that runs the walk on demand), rcb_check_cells(),
  *    rcb_neighbours_count(), rcb_destroy(), and rcb_build() / rcb_refresh()
- *    with validate = 1.
+ *    with validate = 1. rcb_build() (centre-of-mass and centre-of-number
+ *    splits) also waits, level by level, for each level's count of large
+ *    nodes while the device partitions the level before; it returns before
+ *    the build has finished on the device.
  *  - Inputs stay owned by the caller. rcb_build() copies what it needs, so
  *    the tree never aliases caller memory after the call returns.
  *  - Calls return rcb_status; nothing throws across the ABI. Argument errors

@@ -17,6 +17,7 @@
 // combines the chunk sums, and the partition runs as count / scan / scatter
 // over the same chunks. Kernels are HBM-bound: each level reads 32 B and
 // writes 36 B per particle.
+#include <chrono>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -739,8 +740,10 @@ __global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int split, Par
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_chunk_reduce(PartIn in, NodeOut o, BigCtl bc,
-                                                         double *__restrict__ part) {
+                                                         double *__restrict__ part,
+                                                         int32_t *__restrict__ clear_ctl = nullptr) {
     const int64_t w = wave_index();
+    if (clear_ctl && blockIdx.x == 0 && threadIdx.x < 4) clear_ctl[threadIdx.x] = 0;
     if (w >= bc.ctl[1]) return;
     const int bi = bc.item_big[w];
     const int64_t lab = bc.big_node[bi];
@@ -1054,6 +1057,626 @@ __global__ void k_outside(int64_t nleaf, const int32_t *__restrict__ nfirst,
     if (lane_id() == 0 && bad) atomicAdd(out, (unsigned long long)bad);
 }
 
+// ---------------------------------------------------------------------------
+// Subtrees. A node is "big" while it holds more than kSubMax particles or
+// lies more than kSubDepth levels above the lowest; big nodes go through the
+// device-wide chunk passes above, one level per launch. Every node that is
+// not big but whose parent is (or the root, if it is not big) is a subtree
+// root: one wave finishes its whole subtree down to level k with everything
+// in wave-private LDS -- the particles, and per node its range, box, mass,
+// centre of mass and quadrupole. Each level's canonical sums, split and
+// stable partition run there; node data, each level's particle order and
+// the final particle arrays are written to global memory and never read
+// back, and the quadrupoles are summed upwards (Eq. 2) from LDS. Roots come
+// from a queue filled by the level passes; a persistent grid takes them one
+// at a time, so every wave ends when the queue is empty.
+// ---------------------------------------------------------------------------
+constexpr int kSubMax = kChunk;                 // particles of a subtree root
+constexpr int kSubDepth = 6;                    // levels below a subtree root
+constexpr int kSubSlots = kSubMax + kSubMax / 8;
+constexpr int kSubNodes = (2 << kSubDepth) - 1; // nodes of a subtree: level d, index j at 2^d - 1 + j
+
+__device__ __forceinline__ bool is_big(int32_t c, int k, int lvl) {
+    return c > 0 && (c > kSubMax || k - lvl > kSubDepth);
+}
+
+// One lane per node of the level (a wave per 64 nodes): the children of the
+// previous level's big nodes are sorted into big nodes (registered for this
+// level's chunk passes, as level_node does) and subtree roots (queued).
+// Nodes below a subtree root are skipped: their parents' counts are still
+// zero from the clear at the start of the build.
+__global__ __launch_bounds__(kBlock) void k_level_classify(int lvl, int k, NodeOut o, BigCtl bc,
+                                                           int32_t *__restrict__ roots,
+                                                           int32_t *__restrict__ nroots, int max_big,
+                                                           int max_items, int32_t *__restrict__ flag) {
+    const int64_t w = wave_index();
+    const int64_t nodes = (int64_t)1 << lvl;
+    if (w * kWave >= nodes) return;
+    const int lane = lane_id();
+    const int64_t j = w * kWave + lane;
+    const bool valid = j < nodes;
+    const int64_t lab = nodes + (valid ? j : 0);
+    bool consider = valid && (lvl == 0 || is_big(o.ncount[lab >> 1], k, lvl - 1));
+    const int32_t c = consider ? o.ncount[lab] : 0;
+    const bool big = consider && is_big(c, k, lvl);
+    const bool root = consider && !big;
+    const uint64_t br = ballot(root);
+    int rbase = 0;
+    if (lane == 0 && br) rbase = atomicAdd(nroots, __popcll(br));
+    rbase = __shfl(rbase, 0, kWave);
+    if (root) roots[rbase + rank_below(br)] = (int32_t)lab;
+    int nch = 0, bi = 0, base = 0;
+    bool big_ok = big;
+    if (big) {
+        nch = (c + kChunk - 1) / kChunk;
+        bi = atomicAdd(&bc.ctl[0], 1);
+        base = atomicAdd(&bc.ctl[1], nch);
+        big_ok = bi < max_big && base + nch <= max_items;   // sized on the host; never exceeded
+        if (big_ok) {
+            bc.big_node[bi] = (int32_t)lab;
+            bc.big_base[bi] = base;
+        } else {
+            atomicOr(flag, 1);
+        }
+    }
+    // the chunk-to-node map of each big node, written by the whole wave
+    uint64_t bb = ballot(big_ok);
+    while (bb) {
+        const int src = __ffsll((long long)bb) - 1;
+        bb &= bb - 1;
+        const int nc = __shfl(nch, src, kWave), b0 = __shfl(base, src, kWave), id = __shfl(bi, src, kWave);
+        for (int q = lane; q < nc; q += kWave) bc.item_big[b0 + q] = id;
+    }
+}
+
+// The children of the big nodes of level lvl - 1 (one lane each, from that
+// level's list bp): sorted into big nodes of level lvl (registered in bn for
+// its chunk passes) and subtree roots (queued). The last block to finish
+// writes the level's totals (big nodes, chunks) to host memory `report`,
+// then the sequence number `seq` that the host waits for.
+__global__ __launch_bounds__(kBlock) void k_classify_children(int lvl, int k, NodeOut o, BigCtl bp, int nparent,
+                                                              BigCtl bn, int32_t *__restrict__ roots,
+                                                              int32_t *__restrict__ nroots, int max_big,
+                                                              int max_items, int32_t *__restrict__ flag,
+                                                              volatile int32_t *report, int32_t seq) {
+    const int64_t w = wave_index();
+    const int lane = lane_id();
+    const int64_t t = w * kWave + lane;
+    const bool valid = t < 2 * (int64_t)nparent;
+    const int64_t lab = valid ? 2 * (int64_t)bp.big_node[t >> 1] + (t & 1) : 0;
+    const int32_t c = valid ? o.ncount[lab] : 0;
+    const bool big = valid && is_big(c, k, lvl);
+    const bool root = valid && !big;
+    const uint64_t br = ballot(root);
+    int rbase = 0;
+    if (lane == 0 && br) rbase = atomicAdd(nroots, __popcll(br));
+    rbase = __shfl(rbase, 0, kWave);
+    if (root) roots[rbase + rank_below(br)] = (int32_t)lab;
+    int nch = 0, bi = 0, base = 0;
+    bool big_ok = big;
+    if (big) {
+        nch = (c + kChunk - 1) / kChunk;
+        bi = atomicAdd(&bn.ctl[0], 1);
+        base = atomicAdd(&bn.ctl[1], nch);
+        big_ok = bi < max_big && base + nch <= max_items;   // sized on the host; never exceeded
+        if (big_ok) {
+            bn.big_node[bi] = (int32_t)lab;
+            bn.big_base[bi] = base;
+        } else {
+            atomicOr(flag, 1);
+        }
+    }
+    uint64_t bb = ballot(big_ok);
+    while (bb) {
+        const int src = __ffsll((long long)bb) - 1;
+        bb &= bb - 1;
+        const int nc = __shfl(nch, src, kWave), b0 = __shfl(base, src, kWave), id = __shfl(bi, src, kWave);
+        for (int q = lane; q < nc; q += kWave) bn.item_big[b0 + q] = id;
+    }
+    // the last block reports the totals
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&bn.ctl[2], 1) == (int)gridDim.x - 1) {
+            __threadfence();
+            report[1] = atomicAdd(&bn.ctl[0], 0);
+            report[2] = atomicAdd(&bn.ctl[1], 0);
+            __threadfence_system();
+            report[0] = seq;
+            __threadfence_system();
+        }
+    }
+}
+
+struct SubArgs {
+    int k;
+    int64_t n;
+    const int32_t *roots;
+    const int32_t *qctl;     // [0] roots queued
+    int32_t *qhead;          // next root to take
+    double *bx[2], *by[2], *bz[2], *bm[2];   // particle buffers by level parity
+    int32_t *lvl_id;
+    const double *h;         // the caller's smoothing lengths (caller order)
+    double *ph;              // h in tree order, written for the subtree's particles
+    NodeOut o;
+};
+
+struct SubLds {
+    double x[kSubSlots], y[kSubSlots], z[kSubSlots], m[kSubSlots];
+    int32_t id[kSubSlots];
+    // per node of the subtree (slot 2^d - 1 + j for level l0 + d, label R0 2^d + j)
+    int32_t first[kSubNodes], count[kSubNodes];   // first: subtree-relative
+    double lo[kSubNodes][3], hi[kSubNodes][3];
+    double mass[kSubNodes], com[kSubNodes][3], q[kSubNodes][6];
+};
+
+// All descendants of the empty node E (level lvl, first particle `first`,
+// box lo/hi) down to level k: empty, with E's box; E's own range and box
+// were written by its parent. The whole wave takes part.
+__device__ __forceinline__ void fill_empty_subtree(const NodeOut o, int64_t E, int lvl, int k, int32_t first,
+                                                  const double (&lo)[3], const double (&hi)[3]) {
+    const int l = lane_id();
+    double g[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[d] = 0.5 * (lo[d] + hi[d]);
+    for (int j = 0; j <= k - lvl; ++j) {
+        const int64_t b = E << j, cnt = (int64_t)1 << j;
+        for (int64_t i = l; i < cnt; i += kWave) {
+            const int64_t L = b + i;
+            if (j > 0) {
+                o.nfirst[L] = first;
+                o.ncount[L] = 0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    o.nlo[3 * L + d] = lo[d];
+                    o.nhi[3 * L + d] = hi[d];
+                }
+            }
+            o.nM[L] = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) o.ncom[3 * L + d] = g[d];
+            o.nhint[L] = -1.0;
+            o.nhnode[L] = -1.0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) o.nQ[6 * L + q] = 0.0;
+        }
+    }
+}
+
+// One pass over up to 64 / GW nodes of subtree level d, GW lanes per node
+// (each lane holds 8 consecutive elements of its node, the canonical
+// pairwise tree padded to 8 GW): payload A and, for internal nodes, the
+// split and the stable partition of the node's elements in LDS (in place:
+// the pass's nodes are read completely before any element moves); the
+// children's ranges and boxes go to their LDS slots.
+// Sum and max over the GW lanes of this lane's group, GW a run-time power
+// of two (the same xor butterfly as group_sum / group_max)
+__device__ __forceinline__ double gsum(double v, int GW) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1)
+        if (o < GW) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ double gmax(double v, int GW) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1)
+        if (o < GW) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ void sub_pass(const NodeOut o, int k, const double *__restrict__ hin,
+                                         double *__restrict__ ph, SubLds &sh, int64_t R0, int d, int p,
+                                         int lvl, int64_t s0, float *fdx, float *fdy, float *fdz, float *fm,
+                                         float *fh, const int GW) {
+    const bool leaf = lvl == k;
+    const int lane = lane_id();
+    const int gslot = lane / GW, gl = lane % GW;
+    const int nd = 1 << d;
+    const int j = p + gslot;
+    const int slot = nd - 1 + (j < nd ? j : 0);
+    const int c = j < nd ? sh.count[slot] : 0;
+    const bool valid = c > 0;
+    const int f = sh.first[slot];
+    const int64_t lab = (R0 << d) + j;
+    double lo[3], hi[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        lo[q] = sh.lo[slot][q];
+        hi[q] = sh.hi[slot][q];
+    }
+    const double g[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
+    double X[8], Y[8], Z[8], Mm[8], H[8];
+    int32_t I[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int e = 8 * gl + t;
+        const bool ok = valid && e < c;
+        const int sl = stage_slot(ok ? f + e : 0);
+        X[t] = ok ? sh.x[sl] : 0.0;
+        Y[t] = ok ? sh.y[sl] : 0.0;
+        Z[t] = ok ? sh.z[sl] : 0.0;
+        Mm[t] = ok ? sh.m[sl] : 0.0;
+        I[t] = ok ? sh.id[sl] : 0;
+    }
+    // the leaves' smoothing lengths: gathered first, used after payload A
+    // (I is 0 past the node)
+    if (leaf) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) H[t] = hin[I[t]];
+    } else {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) H[t] = 0.0;
+    }
+    // payload A: m, m x, m y, m z summed by the canonical tree (8 in the
+    // lane, then across the group), and max |r - g|^2 (as chunk_sums_regs<0>)
+    double sa[4], mx;
+    {
+        double v[8][4];
+        double ml = -1.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (valid && 8 * gl + t < c) {
+                v[t][0] = Mm[t];
+                v[t][1] = Mm[t] * X[t];
+                v[t][2] = Mm[t] * Y[t];
+                v[t][3] = Mm[t] * Z[t];
+                ml = fmax(ml, dist2(X[t], Y[t], Z[t], g[0], g[1], g[2]));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[t][q] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double a0 = (v[0][q] + v[1][q]) + (v[2][q] + v[3][q]);
+            const double b0 = (v[4][q] + v[5][q]) + (v[6][q] + v[7][q]);
+            sa[q] = gsum(a0 + b0, GW);
+        }
+        mx = gmax(ml, GW);
+    }
+    const double M = sa[0] + 0.0;
+    double com[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) com[q] = (sa[1 + q] + 0.0) / M;
+    const bool lead = valid && gl == 0;
+    if (lead) {
+        o.nM[lab] = M;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) o.ncom[3 * lab + q] = com[q];
+        o.nhint[lab] = sqrt(mx);
+        o.nhnode[lab] = -1.0;
+        sh.mass[slot] = M;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) sh.com[slot][q] = com[q];
+    }
+    if (leaf) {
+        // Eq. 1 about the leaf's centre of mass (each component summed by the
+        // same tree as chunk_sums_regs<1>), and h_node
+        double ml = -1.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const bool ok = valid && 8 * gl + t < c;
+            if (ok) ml = fmax(ml, sqrt(dist2(X[t], Y[t], Z[t], g[0], g[1], g[2])) + 2.0 * H[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (valid && 8 * gl + t < c) ph[s0 + f + 8 * gl + t] = H[t];
+        const double hn = gmax(ml, GW);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            double v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (valid && 8 * gl + t < c) {
+                    const double d0 = X[t] - com[0], d1 = Y[t] - com[1], d2 = Z[t] - com[2];
+                    const double r2 = (d0 * d0 + d1 * d1) + d2 * d2;
+                    const double m3 = 3.0 * Mm[t];
+                    const double mr2 = Mm[t] * r2;
+                    v[t] = q == 0 ? (m3 * d0) * d0 - mr2 : q == 1 ? (m3 * d0) * d1 : q == 2 ? (m3 * d0) * d2
+                         : q == 3 ? (m3 * d1) * d1 - mr2 : q == 4 ? (m3 * d1) * d2 : (m3 * d2) * d2 - mr2;
+                } else {
+                    v[t] = 0.0;
+                }
+            }
+            const double sq = gsum(((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])), GW) + 0.0;
+            if (lead) {
+                o.nQ[6 * lab + q] = sq;
+                sh.q[slot][q] = sq;
+            }
+        }
+        if (lead) o.nhnode[lab] = hn;
+        if (fdx) {   // mixed form: FP32 offsets from the leaf's centre of mass
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int e = 8 * gl + t;
+                if (valid && e < c) {
+                    const int64_t i = s0 + f + e;
+                    fdx[i] = (float)(X[t] - com[0]);
+                    fdy[i] = (float)(Y[t] - com[1]);
+                    fdz[i] = (float)(Z[t] - com[2]);
+                    fm[i] = (float)Mm[t];
+                    fh[i] = (float)H[t];
+                }
+            }
+        }
+        return;
+    }
+    // split through the centre of mass along the longest side
+    int ax = 0;
+    double best = hi[0] - lo[0];
+    if (hi[1] - lo[1] > best) {
+        best = hi[1] - lo[1];
+        ax = 1;
+    }
+    if (hi[2] - lo[2] > best) ax = 2;
+    const double plane = ax == 0 ? com[0] : (ax == 1 ? com[1] : com[2]);
+    uint32_t lb = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const double xv = ax == 0 ? X[t] : (ax == 1 ? Y[t] : Z[t]);
+        if (valid && 8 * gl + t < c && xv < plane) lb |= 1u << t;
+    }
+    const int nl = __popc(lb);
+    int incl = nl;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        if (off < GW) {
+            const int y = __shfl_up(incl, off, kWave);
+            if (gl >= off) incl += y;
+        }
+    }
+    const int excl = incl - nl;
+    const int nleft = __shfl(incl, gslot * GW + GW - 1, kWave);
+    int dst[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int e = 8 * gl + t;
+        const int lbefore = excl + __popc(lb & ((1u << t) - 1u));
+        dst[t] = valid && e < c ? ((lb >> t) & 1u ? f + lbefore : f + nleft + (e - lbefore)) : -1;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        if (dst[t] >= 0) {
+            const int sl = stage_slot(dst[t]);
+            sh.x[sl] = X[t];
+            sh.y[sl] = Y[t];
+            sh.z[sl] = Z[t];
+            sh.m[sl] = Mm[t];
+            sh.id[sl] = I[t];
+        }
+    }
+    if (lead) {
+        const int64_t L = 2 * lab, R = 2 * lab + 1;
+        const int cs = 2 * nd - 1 + 2 * j;   // the children's slots
+        o.nfirst[L] = (int32_t)(s0 + f);
+        o.ncount[L] = nleft;
+        o.nfirst[R] = (int32_t)(s0 + f + nleft);
+        o.ncount[R] = c - nleft;
+        sh.first[cs] = f;
+        sh.count[cs] = nleft;
+        sh.first[cs + 1] = f + nleft;
+        sh.count[cs + 1] = c - nleft;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const double lh = q == ax ? plane : hi[q], rl = q == ax ? plane : lo[q];
+            o.nlo[3 * L + q] = lo[q];
+            o.nhi[3 * L + q] = lh;
+            o.nlo[3 * R + q] = rl;
+            o.nhi[3 * R + q] = hi[q];
+            sh.lo[cs][q] = lo[q];
+            sh.hi[cs][q] = lh;
+            sh.lo[cs + 1][q] = rl;
+            sh.hi[cs + 1][q] = hi[q];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+__global__ __launch_bounds__(kWave) void k_subtree(SubArgs a, float *fdx, float *fdy, float *fdz, float *fm,
+                                                      float *fh) {
+    __shared__ SubLds sh;
+    const int lane = lane_id();
+    const NodeOut o = a.o;
+    const int k = a.k;
+    const double *__restrict__ hin = a.h;
+    double *__restrict__ ph = a.ph;
+    const bool kp = k & 1;
+    double *ox = kp ? a.bx[1] : a.bx[0], *oy = kp ? a.by[1] : a.by[0];
+    double *oz = kp ? a.bz[1] : a.bz[0], *om = kp ? a.bm[1] : a.bm[0];
+    for (;;) {
+        int r = 0;
+        if (lane == 0) r = atomicAdd(a.qhead, 1);
+        r = __builtin_amdgcn_readfirstlane(__shfl(r, 0, kWave));
+        if (r >= a.qctl[0]) break;
+        const int64_t R0 = a.roots[r];
+        const int l0 = 63 - __clzll((unsigned long long)R0);
+        const int64_t s0 = o.nfirst[R0];
+        const int c0 = o.ncount[R0];
+        double rlo[3], rhi[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            rlo[q] = o.nlo[3 * R0 + q];
+            rhi[q] = o.nhi[3 * R0 + q];
+        }
+        if (c0 == 0) {   // an empty root (at any depth): its whole subtree
+            fill_empty_subtree(o, R0, l0, k, (int32_t)s0, rlo, rhi);
+            continue;
+        }
+        const bool par = l0 & 1;   // buffers chosen by select, not by a dynamic index
+        const double *ix = par ? a.bx[1] : a.bx[0], *iy = par ? a.by[1] : a.by[0];
+        const double *iz = par ? a.bz[1] : a.bz[0], *im = par ? a.bm[1] : a.bm[0];
+        {   // every load of the root's particles issued before the first LDS store
+            constexpr int kPer = kSubMax / kWave;
+            double vx[kPer], vy[kPer], vz[kPer], vm[kPer];
+            int32_t vi[kPer];
+            const int32_t *idl = a.lvl_id + (int64_t)l0 * a.n;
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int i = lane + kWave * q;
+                const int64_t src = s0 + (i < c0 ? i : 0);
+                vx[q] = ix[src];
+                vy[q] = iy[src];
+                vz[q] = iz[src];
+                vm[q] = im[src];
+                vi[q] = idl[src];
+            }
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int i = lane + kWave * q;
+                if (i < c0) {
+                    const int sl = stage_slot(i);
+                    sh.x[sl] = vx[q];
+                    sh.y[sl] = vy[q];
+                    sh.z[sl] = vz[q];
+                    sh.m[sl] = vm[q];
+                    sh.id[sl] = vi[q];
+                }
+            }
+        }
+        if (lane == 0) {
+            sh.first[0] = 0;
+            sh.count[0] = c0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                sh.lo[0][q] = rlo[q];
+                sh.hi[0][q] = rhi[q];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int D = k - l0;
+        for (int d = 0; d <= D; ++d) {
+            const int lvl = l0 + d, nd = 1 << d;
+            // empty nodes of this level (their parent sent every element to
+            // the other side): their subtrees are filled; nodes below them
+            // carry count -1 and are skipped from here on
+            const int cl = lane < nd ? sh.count[nd - 1 + lane] : 1;
+            uint64_t emp = ballot(d > 0 && cl == 0);
+            while (emp) {
+                const int j = __ffsll((long long)emp) - 1;
+                emp &= emp - 1;
+                const int sl = nd - 1 + j;
+                double clo[3], chi[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    clo[q] = sh.lo[sl][q];
+                    chi[q] = sh.hi[sl][q];
+                }
+                fill_empty_subtree(o, (R0 << d) + j, lvl, k, (int32_t)(s0 + sh.first[sl]), clo, chi);
+            }
+            int cm = 0;
+            for (int j = lane; j < nd; j += kWave) cm = max(cm, sh.count[nd - 1 + j]);
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) cm = max(cm, __shfl_xor(cm, off, kWave));
+            const int gw = cm <= 8 ? 1 : cm <= 16 ? 2 : cm <= 32 ? 4 : cm <= 64 ? 8 : cm <= 128 ? 16
+                         : cm <= 256 ? 32 : 64;
+            const int npg = kWave / gw;
+            float *f0 = lvl == k ? fdx : nullptr;
+            if (lvl < k) {   // the next level's slots: -1 unless a non-empty parent sets them
+                for (int i = lane; i < 2 * nd; i += kWave) sh.count[2 * nd - 1 + i] = -1;
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            }
+            for (int p = 0; p < nd; p += npg)
+                sub_pass(o, k, hin, ph, sh, R0, d, p, lvl, s0, f0, fdy, fdz, fm, fh, gw);
+            if (lvl == k) break;
+            // this level's partition is complete: the next level's order
+            for (int i = lane; i < c0; i += kWave)
+                a.lvl_id[(int64_t)(lvl + 1) * a.n + s0 + i] = sh.id[stage_slot(i)];
+        }
+        // final particle arrays (level k order)
+        for (int i = lane; i < c0; i += kWave) {
+            const int sl = stage_slot(i);
+            ox[s0 + i] = sh.x[sl];
+            oy[s0 + i] = sh.y[sl];
+            oz[s0 + i] = sh.z[sl];
+            om[s0 + i] = sh.m[sl];
+        }
+        // Eq. 2 upwards through the subtree's internal levels, from LDS
+        for (int d = D - 1; d >= 0; --d) {
+            const int nd = 1 << d;
+            for (int j = lane; j < nd; j += kWave) {
+                const int sl = nd - 1 + j;
+                if (sh.count[sl] <= 0) continue;   // Q = 0, written with the empty subtree
+                double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                const double pc[3] = {sh.com[sl][0], sh.com[sl][1], sh.com[sl][2]};
+                for (int ch = 0; ch < 2; ++ch) {
+                    const int cs = 2 * nd - 1 + 2 * j + ch;
+                    if (sh.count[cs] <= 0) continue;
+                    const double dx[3] = {sh.com[cs][0] - pc[0], sh.com[cs][1] - pc[1], sh.com[cs][2] - pc[2]};
+                    const double r2 = (dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2];
+                    const double MC = sh.mass[cs];
+                    const double m3 = 3.0 * MC;
+                    const double mr2 = MC * r2;
+                    acc[0] += (sh.q[cs][0] + (m3 * dx[0]) * dx[0]) - mr2;
+                    acc[1] += sh.q[cs][1] + (m3 * dx[0]) * dx[1];
+                    acc[2] += sh.q[cs][2] + (m3 * dx[0]) * dx[2];
+                    acc[3] += (sh.q[cs][3] + (m3 * dx[1]) * dx[1]) - mr2;
+                    acc[4] += sh.q[cs][4] + (m3 * dx[1]) * dx[2];
+                    acc[5] += (sh.q[cs][5] + (m3 * dx[2]) * dx[2]) - mr2;
+                }
+                const int64_t lab = (R0 << d) + j;
+#pragma unroll
+                for (int q6 = 0; q6 < 6; ++q6) {
+                    sh.q[sl][q6] = acc[q6];
+                    o.nQ[6 * lab + q6] = acc[q6];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+}
+
+// Eq. 2 for the big nodes of one level (the others are done by their subtree's wave)
+__global__ void k_upward_big(int lvl, int k, NodeOut o) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nodes = (int64_t)1 << lvl;
+    if (i >= nodes) return;
+    const int64_t lab = nodes + i;
+    if (!is_big(o.ncount[lab], k, lvl)) return;
+    const double pc[3] = {o.ncom[3 * lab], o.ncom[3 * lab + 1], o.ncom[3 * lab + 2]};
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int ch = 0; ch < 2; ++ch) {
+        const int64_t C = 2 * lab + ch;
+        if (o.ncount[C] == 0) continue;
+        const double dx[3] = {o.ncom[3 * C] - pc[0], o.ncom[3 * C + 1] - pc[1], o.ncom[3 * C + 2] - pc[2]};
+        const double r2 = (dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2];
+        const double MC = o.nM[C];
+        const double m3 = 3.0 * MC;
+        const double mr2 = MC * r2;
+        acc[0] += (o.nQ[6 * C + 0] + (m3 * dx[0]) * dx[0]) - mr2;
+        acc[1] += o.nQ[6 * C + 1] + (m3 * dx[0]) * dx[1];
+        acc[2] += o.nQ[6 * C + 2] + (m3 * dx[0]) * dx[2];
+        acc[3] += (o.nQ[6 * C + 3] + (m3 * dx[1]) * dx[1]) - mr2;
+        acc[4] += o.nQ[6 * C + 4] + (m3 * dx[1]) * dx[2];
+        acc[5] += (o.nQ[6 * C + 5] + (m3 * dx[2]) * dx[2]) - mr2;
+    }
+    for (int q = 0; q < 6; ++q) o.nQ[6 * lab + q] = acc[q];
+}
+
+// h in tree order for the big leaves (their order at level k is final);
+// the subtree waves write it for their own particles
+__global__ __launch_bounds__(kBlock) void k_gather_h_big(const double *__restrict__ h,
+                                                         const int32_t *__restrict__ id, NodeOut o, BigCtl bc,
+                                                         double *__restrict__ ph) {
+    const int64_t w = wave_index();
+    if (w >= bc.ctl[1]) return;
+    const int bi = bc.item_big[w];
+    const int64_t lab = bc.big_node[bi];
+    const int64_t j = w - bc.big_base[bi];
+    const int64_t s = o.nfirst[lab], c = o.ncount[lab];
+    const int64_t base = s + j * kChunk;
+    const int64_t end = min(base + kChunk, s + c);
+    for (int64_t i = base + lane_id(); i < end; i += kWave) ph[i] = h[id[i]];
+}
+
+
 inline unsigned blocks_for_waves(int64_t waves) {
     return (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
 }
@@ -1236,6 +1859,10 @@ __global__ __launch_bounds__(kBlock) void k_msel_pick(int lvl, int pass, MedSel 
 
 }  // namespace
 
+static rcb_status big_chain(rcb_tree *t, BuildScratch &b, const NodeOut &o, const BigCtl &bc, int lvl,
+                            bool split, const PartIn &in, const int32_t *id, const PartOut &out,
+                            hipStream_t s);
+
 // One level's node pass: payload A of every node (and B at the leaf level)
 // by small-node, packed and big-node kernels; with split, the partition of
 // the big nodes into `out` (the small ones partition themselves).
@@ -1244,8 +1871,6 @@ static rcb_status level_pass(rcb_tree *t, BuildScratch &b, const NodeOut &o, con
                              hipStream_t s) {
     const int64_t n = t->n;
     const bool leaf = lvl == t->k;
-    const int64_t item_waves = b.max_items;
-    const int64_t big_waves = b.max_big;
     RCB_HIP(hipMemsetAsync(b.ctl, 0, sizeof(int32_t) * 4, s));
     const int64_t nodes = (int64_t)1 << lvl;
     // group width: 8, 16 or 32 lanes per node while the average node
@@ -1282,7 +1907,19 @@ static rcb_status level_pass(rcb_tree *t, BuildScratch &b, const NodeOut &o, con
                                                                           nullptr, 1);
         RCB_LAUNCH_CHECK("k_level_small");
     }
-    const int64_t bw = std::min<int64_t>(big_waves, nodes);
+    return big_chain(t, b, o, bc, lvl, split, in, id, out, s);
+}
+
+// The big nodes' passes of one level: chunk sums, their canonical
+// combination (payload A, and B at the leaf level) and, when splitting, the
+// left counts, their scan and the stable scatter.
+static rcb_status big_chain(rcb_tree *t, BuildScratch &b, const NodeOut &o, const BigCtl &bc, int lvl,
+                            bool split, const PartIn &in, const int32_t *id, const PartOut &out,
+                            hipStream_t s) {
+    const bool leaf = lvl == t->k;
+    const int64_t item_waves = b.max_items;
+    const int64_t nodes = (int64_t)1 << lvl;
+    const int64_t bw = std::min<int64_t>(b.max_big, nodes);
     k_chunk_reduce<0><<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, o, bc, b.part);
     RCB_LAUNCH_CHECK("k_chunk_reduce<0>");
     k_big_finalize<0><<<(unsigned)bw, kFinWaves * kWave, 0, s>>>(leaf, split, o, bc, b.part);
@@ -1303,6 +1940,37 @@ static rcb_status level_pass(rcb_tree *t, BuildScratch &b, const NodeOut &o, con
     }
     return RCB_OK;
 }
+
+// Level counts written by k_classify_children into pinned host memory; the
+// host polls the sequence number. A report that does not arrive within a
+// few seconds, or a stream that has failed, ends the wait with an error.
+static thread_local int32_t g_level_seq = 0;
+
+static rcb_status wait_report(int32_t *hcnt, int32_t seq, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint64_t spin = 0;; ++spin) {
+        if (__atomic_load_n(&hcnt[0], __ATOMIC_ACQUIRE) == seq) return RCB_OK;
+        if ((spin & 1023) == 1023) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q != hipSuccess && q != hipErrorNotReady) return hip_fail(q, "build: level pass");
+            if (q == hipSuccess && __atomic_load_n(&hcnt[0], __ATOMIC_ACQUIRE) != seq) {
+                set_error("build: the level counts did not arrive");
+                return RCB_EHIP;
+            }
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(10)) {
+                set_error("build: timed out waiting for the level counts");
+                return RCB_EHIP;
+            }
+        }
+    }
+}
+
+static inline bool is_big_host(int64_t c, int k, int lvl) {
+    return c > 0 && (c > kSubMax || k - lvl > kSubDepth);
+}
+
+static rcb_status finish_build(rcb_tree *t, BuildScratch &b, const NodeOut &o, Scratch &tmp, int cur,
+                               hipStream_t s);
 
 rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const double *z,
                       const double *m, const double *h, hipStream_t s) {
@@ -1332,7 +2000,10 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         b.z[i] = (double *)A(sizeof(double) * n, tmp);
         b.m[i] = (double *)A(sizeof(double) * n, tmp);
     }
-    b.max_big = std::min<int64_t>(t->nleaf, n / (kChunk + 1) + 1);
+    // big nodes of one level: those of more than kChunk particles, and (fused
+    // build) every non-empty node more than kSubDepth levels above the lowest
+    const int64_t depth_big = t->k > kSubDepth ? (int64_t)1 << (t->k - kSubDepth - 1) : 0;
+    b.max_big = std::min<int64_t>(t->nleaf, std::max<int64_t>(n / (kChunk + 1) + 1, depth_big));
     b.max_items = n / kChunk + b.max_big + 1;
     b.ctl = (int32_t *)A(sizeof(int32_t) * 4, tmp);
     b.big_node = (int32_t *)A(sizeof(int32_t) * b.max_big, tmp);
@@ -1393,9 +2064,106 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     NodeOut o{t->nfirst, t->ncount, t->nlo, t->nhi, t->ncom, t->nM, t->nhint, t->nhnode, t->nQ,
               b.naxis, b.nplane, mplane, mtie};
     BigCtl bc{b.ctl, b.big_node, b.big_base, b.item_big};
+    // splits through a centre (mass or number): big nodes level by level,
+    // then every subtree of at most kSubMax particles by one wave
+    const bool fused = !median && getenv("RCB_BUILD_LEVELS") == nullptr;
+    if (fused) {
+        int32_t *roots = (int32_t *)A(sizeof(int32_t) * t->nleaf, tmp);
+        int32_t *qctl = (int32_t *)A(sizeof(int32_t) * 2, tmp);
+        // the control blocks and big-node lists alternate between levels: a
+        // level's lists are read by its passes while the next level's are made
+        int32_t *ctl2 = (int32_t *)A(sizeof(int32_t) * 4, tmp);
+        int32_t *bn2 = (int32_t *)A(sizeof(int32_t) * b.max_big, tmp);
+        int32_t *bb2 = (int32_t *)A(sizeof(int32_t) * b.max_big, tmp);
+        int32_t *ib2 = (int32_t *)A(sizeof(int32_t) * b.max_items, tmp);
+        if (!roots || !qctl || !ctl2 || !bn2 || !bb2 || !ib2) return RCB_ENOMEM;
+        const BigCtl bcs[2] = {bc, BigCtl{ctl2, bn2, bb2, ib2}};
+        RCB_HIP(hipMemsetAsync(qctl, 0, sizeof(int32_t) * 2, s));
+        RCB_HIP(hipMemsetAsync(b.ctl, 0, sizeof(int32_t) * 4, s));
+        RCB_HIP(hipMemsetAsync(ctl2, 0, sizeof(int32_t) * 4, s));
+        // the host learns each level's number of big nodes and chunks from a
+        // small copy made while that level's parent is still partitioning, so
+        // every pass is launched with its exact size and the loop stops at
+        // the first level without big nodes
+        // (coherent host memory, kept for the thread's later builds)
+        static thread_local int32_t *hcnt = nullptr;
+        if (!hcnt) {
+            if (hipHostMalloc((void **)&hcnt, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+                hcnt = nullptr;
+                return hip_fail(hipErrorOutOfMemory, "hipHostMalloc(level counts)");
+            }
+            hcnt[0] = 0;
+        }
+        int32_t *dcnt = nullptr;   // the same memory as seen by the device
+        RCB_HIP(hipHostGetDevicePointer((void **)&dcnt, hcnt, 0));
+        k_level_classify<<<1, kBlock, 0, s>>>(0, t->k, o, bcs[0], roots, qctl, (int)b.max_big, (int)b.max_items,
+                                              t->dflag + 5);
+        RCB_LAUNCH_CHECK("k_level_classify");
+        int64_t nbig = is_big_host((int64_t)n, t->k, 0) ? 1 : 0;
+        int64_t nitems = nbig ? (n + kChunk - 1) / kChunk : 0;
+        int cur = 0, last_big = -1;
+        for (int lvl = 0; lvl <= t->k && nbig > 0; ++lvl) {
+            const bool leaf = lvl == t->k;
+            const BigCtl &bl = bcs[lvl & 1], &bnx = bcs[(lvl + 1) & 1];
+            PartIn in{b.x[cur], b.y[cur], b.z[cur], b.m[cur], t->ph};
+            int32_t *id_next = leaf ? nullptr : t->lvl_id + (int64_t)(lvl + 1) * n;
+            PartOut out{b.x[cur ^ 1], b.y[cur ^ 1], b.z[cur ^ 1], b.m[cur ^ 1], id_next};
+            const int32_t *id_cur = t->lvl_id + (int64_t)lvl * n;
+            const unsigned gi = blocks_for_waves(nitems), gb = (unsigned)nbig;
+            last_big = lvl;
+            if (leaf) {   // the big leaves: their h, payloads A and B
+                k_gather_h_big<<<gi, kBlock, 0, s>>>(h, id_cur, o, bl, t->ph);
+                RCB_LAUNCH_CHECK("k_gather_h_big");
+            }
+            k_chunk_reduce<0><<<gi, kBlock, 0, s>>>(in, o, bl, b.part, leaf ? nullptr : bnx.ctl);
+            RCB_LAUNCH_CHECK("k_chunk_reduce<0>");
+            k_big_finalize<0><<<gb, kFinWaves * kWave, 0, s>>>(leaf, 1, o, bl, b.part);
+            RCB_LAUNCH_CHECK("k_big_finalize<0>");
+            if (leaf) {
+                k_chunk_reduce<1><<<gi, kBlock, 0, s>>>(in, o, bl, b.part);
+                RCB_LAUNCH_CHECK("k_chunk_reduce<1>");
+                k_big_finalize<1><<<gb, kFinWaves * kWave, 0, s>>>(leaf, 1, o, bl, b.part);
+                RCB_LAUNCH_CHECK("k_big_finalize<1>");
+                break;
+            }
+            k_part_count<<<gi, kBlock, 0, s>>>(in, id_cur, o, bl, b.part_left);
+            RCB_LAUNCH_CHECK("k_part_count");
+            k_part_scan<<<gb, kFinWaves * kWave, 0, s>>>(o, bl, b.part_left);
+            RCB_LAUNCH_CHECK("k_part_scan");
+            const int32_t seq = ++g_level_seq;
+            k_classify_children<<<blocks_for_waves((2 * nbig + kWave - 1) / kWave), kBlock, 0, s>>>(
+                lvl + 1, t->k, o, bl, (int)nbig, bnx, roots, qctl, (int)b.max_big, (int)b.max_items, t->dflag + 5,
+                dcnt, seq);
+            RCB_LAUNCH_CHECK("k_classify_children");
+            k_part_scatter<<<gi, kBlock, 0, s>>>(in, id_cur, out, o, bl, b.part_left);
+            RCB_LAUNCH_CHECK("k_part_scatter");
+            cur ^= 1;
+            // the scatter keeps the device busy while the host waits for the counts
+            rcb_status ws = wait_report(hcnt, seq, s);
+            if (ws != RCB_OK) return ws;
+            nbig = hcnt[1];
+            nitems = hcnt[2];
+            if (nbig > b.max_big || nitems > b.max_items) {
+                set_error("rcb_build: internal capacity of the big-node lists exceeded");
+                return RCB_EHIP;
+            }
+        }
+        // the particle buffers of level k: every subtree writes its final
+        // order there, as the last scatter of the big nodes did
+        cur = t->k & 1;
+        SubArgs sa{t->k, n, roots, qctl, qctl + 1, {b.x[0], b.x[1]}, {b.y[0], b.y[1]}, {b.z[0], b.z[1]},
+                   {b.m[0], b.m[1]}, t->lvl_id, h, t->ph, o};
+        const unsigned gsub = (unsigned)std::min<int64_t>(2048, t->nleaf);
+        k_subtree<<<gsub, kWave, 0, s>>>(sa, nullptr, nullptr, nullptr, nullptr, nullptr);
+        RCB_LAUNCH_CHECK("k_subtree");
+        for (int lvl = std::min(last_big, t->k - 1); lvl >= 0; --lvl) {
+            const int64_t nodes = (int64_t)1 << lvl;
+            k_upward_big<<<(unsigned)((nodes + 255) / 256), 256, 0, s>>>(lvl, t->k, o);
+            RCB_LAUNCH_CHECK("k_upward_big");
+        }
+        return finish_build(t, b, o, tmp, cur, s);
+    }
     int cur = 0;
-    const int64_t item_waves = b.max_items;
-    const int64_t big_waves = b.max_big;
     for (int lvl = 0; lvl <= t->k; ++lvl) {
         const bool leaf = lvl == t->k;
         if (leaf) {
@@ -1435,6 +2203,15 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         k_upward<<<(unsigned)((nodes + 255) / 256), 256, 0, s>>>(lvl, o);
         RCB_LAUNCH_CHECK("k_upward");
     }
+    return finish_build(t, b, o, tmp, cur, s);
+}
+
+// Walk records, the final particle buffers (the other half of the ping-pong
+// is released) and the mixed form's FP32 arrays.
+static rcb_status finish_build(rcb_tree *t, BuildScratch &b, const NodeOut &o, Scratch &tmp, int cur,
+                               hipStream_t s) {
+    const int64_t n = t->n;
+    auto A = [&](size_t bytes, std::vector<void *> &owner) { return dalloc(t, bytes, s, owner); };
     k_records<<<(unsigned)((t->nlab + 255) / 256), 256, 0, s>>>(t->nlab, o, t->wrec);
     RCB_LAUNCH_CHECK("k_records");
 

@@ -602,9 +602,9 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     rcb_status wst = walk_tiers(true);
     if (wst != RCB_OK) return wst;
     w.stats = nullptr;   // a second walk (exact lists) does not count again
-    int32_t flags[4] = {0, 0, 0, 0};
+    int32_t flags[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     unsigned long long hstats[2] = {0, 0};
-    RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
+    RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 8, hipMemcpyDeviceToHost, s));
     RCB_HIP(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
     RCB_HIP(hipStreamSynchronize(s));
     t->walk_requeued = nq;
@@ -613,6 +613,10 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     if (flags[0]) {
         set_error("walk: stack overflow (tree deeper than the walk stack supports)");
         return RCB_ECAPACITY;
+    }
+    if (flags[5]) {   // set by the build's node bookkeeping, which is sized never to overflow
+        set_error("walk: the build reported an internal capacity error (tree not valid)");
+        return RCB_EHIP;
     }
     const int32_t nlong = flags[1];
     if (flags[3] == 0) {
