@@ -219,10 +219,13 @@ rcb_status rcb_neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, v
 /*
  * Neighbour search, step 2: writes the neighbour ids (caller indices) of
  * particle a to ids[offsets[a] .. offsets[a+1]) -- the one-dimensional list
- * of Sec. 2.3.2. Within a list, neighbours appear in tree order (candidate
- * cells by ascending label, then the cell's particle order).
+ * of Sec. 2.3.2. Each list is ascending by caller index, so the output does
+ * not depend on the tree (split rule, N_ll) that found it.
  *  offsets:  the array filled by rcb_neighbours_count() for this tree.
  *  ids:      device int32[capacity]; capacity >= total, else RCB_ECAPACITY.
+ * The count call keeps up to 64 ids per particle in a scratch slab owned by
+ * the tree (256 bytes per particle, freed with the interaction lists); the
+ * cells holding a longer list are searched again here.
  */
 rcb_status rcb_neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids,
                                int64_t capacity, void *stream);

@@ -660,8 +660,10 @@ void orc_leaf_lists(const otree *t, int64_t A, int32_t *near, int32_t *far)
 
 /* ------------------------------------------------------------------------ */
 /* Neighbours (Sec. 2.3): cull the candidate leaves to |r_ab| < 2 h_a.       */
-/* Lists per particle, in original order; within a list, neighbours appear  */
-/* in tree order (candidate leaves by ascending label, leaf order inside).  */
+/* Lists per particle, in original order. The culled list comes out in     */
+/* tree order (candidate leaves by ascending label, leaf order inside); the */
+/* one-dimensional list of Sec. 2.3.2 then holds it ascending by original   */
+/* index, an order that does not depend on the tree.                        */
 /* Particles whose leaf was not walked get count -1.                        */
 /* ------------------------------------------------------------------------ */
 static int64_t cull_particle(const otree *t, const leaf_lists *L, int64_t a, int32_t *out)
@@ -682,6 +684,12 @@ static int64_t cull_particle(const otree *t, const leaf_lists *L, int64_t a, int
         }
     }
     return cnt;
+}
+
+static int cmp_i32(const void *pa, const void *pb)
+{
+    int32_t a = *(const int32_t *)pa, b = *(const int32_t *)pb;
+    return (a > b) - (a < b);
 }
 
 void orc_neighbours_count(const otree *t, int64_t *counts)
@@ -708,7 +716,8 @@ void orc_neighbours_fill(const otree *t, const int64_t *offsets, int32_t *ids)
         if (!L->walked) continue;
         for (int64_t p = t->first[A]; p < t->first[A] + t->count[A]; ++p) {
             int64_t a = t->perm[p];
-            cull_particle(t, L, a, ids + offsets[a]);
+            int64_t c = cull_particle(t, L, a, ids + offsets[a]);
+            qsort(ids + offsets[a], (size_t)c, sizeof(int32_t), cmp_i32);
         }
     }
 }

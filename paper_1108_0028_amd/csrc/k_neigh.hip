@@ -14,13 +14,17 @@
 // radius h_node(A) padded by 2^-32, Sec. 2.3.1): a neighbour b of a sink a
 // has |r_b - g_A| <= |r_b - r_a| + |r_a - g_A| < 2 h_a + |r_a - g_A|
 // <= h_node(A), so no neighbour is dropped, and the sources that stay are
-// compacted in order. Ranks
-// are taken by ballot within the sink's lane segment, so each list keeps tree
-// order. The count call writes the ids into a slab of kNbCap slots per
-// particle as well as the counts; the fill call then compacts the slab into
-// the caller's CSR; the lowest-level cells holding a particle with more
+// compacted in order. Ranks are taken by ballot within the sink's lane
+// segment.
+//
+// The count call writes each particle's count into the caller's offsets
+// array (scanned in place afterwards) and its first kNbCap ids into a slab
+// row indexed by caller id. The fill call streams the slab in caller order,
+// sorts each list ascending (a 64-input sorting network held by 8 lanes) and
+// stores it into the CSR. Lowest-level cells holding a particle with more
 // neighbours than the slab takes (queued by the count call) are searched
-// again, one wave each, writing at offsets[a] + rank.
+// again, one wave each, writing only those particles' lists at their
+// offsets; each such list is then sorted by one workgroup.
 #include "near_tile.h"
 #include "rcb_internal.h"
 
@@ -29,7 +33,11 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-constexpr int64_t kNbCap = 192;   // slab slots per particle (~50 neighbours expected)
+constexpr int kNbCap = 64;        // slab slots per particle (~50 neighbours expected)
+constexpr int kNbChunk = 192;     // slots of an overflow chunk: lists of up to 256 ids
+constexpr int kLongLds = 4096;    // lists searched again: sorted in LDS up to this length
+constexpr int kRingMask = 2 * kWave - 1;
+constexpr int kVmcnt0 = 0x0f70;   // s_waitcnt vmcnt(0), expcnt and lgkmcnt left free
 
 struct NeighArgs {
     int64_t nleaf;
@@ -44,12 +52,16 @@ struct NeighArgs {
     const int32_t *pid;
     int64_t *counts;          // slab mode: per-particle counts (caller order)
     const int64_t *offsets;   // fill mode: list starts (caller order)
-    int32_t *ids;             // fill mode: final lists; slab mode: kNbCap slots per particle
-    int32_t *flag;            // slab mode: particles with more than kNbCap neighbours
-    int32_t *queue;           // leaves (index from 0) holding such a particle: appended in slab
-                              // mode, searched again (wave i: queue[i]) otherwise
-    int32_t *nqueue;          // slab mode: entries appended
-    int64_t nq;               // fill mode: entries to search
+    int32_t *ids;             // fill mode: final lists; slab mode: kNbCap slots per caller index
+    int32_t *pool;            // slab mode: overflow chunks of kNbChunk slots
+    int64_t pool_cap;         // chunks in pool
+    int32_t *head;            // per caller index: its chunk, or -1 for a list searched again
+    int32_t *ctl;             // [0] lists searched again, [1] leaves queued, [2] chunks taken,
+                              // [3] lists in chunks (slab mode); [0] lists written (fill mode)
+    int32_t *queue;           // leaves (index from 0) holding a list searched again: appended in
+                              // slab mode, searched again (wave i: queue[i]) otherwise
+    int32_t *longq;           // caller indices: lists in chunks (slab mode), lists written (fill)
+    int64_t nq;               // fill mode: entries of queue
 };
 
 struct alignas(16) SrcN {
@@ -58,17 +70,24 @@ struct alignas(16) SrcN {
     int32_t id;   // caller index
 };
 
-// tile: kept sources accumulate until at least 64 wait (at most 127); the
-// last partial row is padded with sources that can never be neighbours
-// (pb = -1 at infinite distance)
+// tile: a ring of 128 sources; kept sources accumulate until at least 64 wait
+// (at most 127), whole rows are taken and the rest waits; the last partial
+// row is padded with sources that can never be neighbours (pb = -1 at
+// infinite distance). cnt / chunk: per sink slot of the pass, the
+// neighbours found so far (slots are handed out by LDS atomics, so a list is
+// stored in no particular order; the fill call sorts it) and its chunk.
 struct NeighShared {
     EntryChunk ec;
     SrcN tile[2 * kWave];
+    int32_t cnt[kWave];
+    int32_t chunk[kWave];
 };
 
-// SLAB: ids go to slot (tree position) * kNbCap + rank (ranks >= kNbCap are
-// only counted), counts are stored in caller order. Otherwise ids go to
-// offsets[pid] + rank.
+// SLAB: ids go to slab row (caller index) while it has room, then to a chunk
+// of the pool taken by the sink's 65th neighbour; lists longer than both, or
+// whose chunk could not be had, are only counted, and their leaf is queued.
+// Otherwise only the sinks queued that way are searched, their ids going to
+// offsets[pid] + slot.
 template <bool SLAB>
 __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
     __shared__ NeighShared sh_all[kWaves];
@@ -78,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
     int64_t gi;
     int li0, li1;   // the group's leaves to search
     if constexpr (SLAB) {
-        gi = wave_index();
+        gi = xcd_wave_index();
         if (gi >= a.ngroup) return;
         li0 = 0;
         li1 = G;
@@ -97,34 +116,72 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
         const int64_t A = a.nleaf + gi * G + li;
         const int32_t sA = a.nfirst[A], c = a.ncount[A];
         if (c == 0) continue;
-        bool leaf_over = false;   // slab mode: a sink of this leaf outgrew the slab
+        bool leaf_over = false;   // slab mode: a list of this leaf is searched again
         const LeafLanes L = leaf_lanes(c);
-        const uint64_t segmask = seg_mask(L);
         const double4 gA = a.rec[2 * A];
         const double rA = a.hnode[A] * kReachPad;
         const double rA2 = rA * rA;
         for (int g0 = 0; g0 < c; g0 += L.S) {
             const int si = g0 + L.sslot;
-            const bool has_sink = L.sslot < L.S && si < c;
+            bool has_sink = L.sslot < L.S && si < c;
             const int32_t pa = sA + (has_sink ? si : 0);
+            const int32_t oa = a.pid[pa];
+            int64_t obase = (int64_t)oa * kNbCap;
+            if constexpr (!SLAB) {   // the lists the count call could not keep
+                const int64_t o0 = has_sink ? a.offsets[oa] : 0;
+                has_sink = has_sink && a.offsets[oa + 1] - o0 > kNbCap && a.head[oa] < 0;
+                obase = o0;
+                if (ballot(has_sink) == 0ull) continue;
+            }
             const double xa = a.px[pa], ya = a.py[pa], za = a.pz[pa];
             const double two_h = 2.0 * a.ph[pa];
             const double lim = has_sink ? two_h * two_h : -1.0;
-            int cnt = 0;
-            const int32_t oa = a.pid[pa];
-            const int64_t obase = SLAB ? (int64_t)pa * kNbCap : (has_sink ? a.offsets[oa] : 0);
-            // rows [0, np) of the tile: slice j of a sink tests entries j, j + J, ...
-            auto rows = [&](int np) {
-                for (int u0 = 0; u0 < np; u0 += L.J) {
-                    const SrcN s = sh.tile[u0 + L.slice];
-                    const bool hit = s.pb != pa && dist2(xa, ya, za, s.x, s.y, s.z) < lim;
-                    const uint64_t bal = ballot(hit) & segmask;
-                    const int r = cnt + rank_below(bal);
-                    if (hit && (!SLAB || r < kNbCap)) a.ids[obase + r] = s.id;
-                    cnt += __popcll(bal);
+            if (L.slice == 0) {
+                sh.cnt[L.sslot] = 0;
+                sh.chunk[L.sslot] = -1;
+            }
+            tile_sync();
+            int head = 0;   // ring position of the first waiting source
+            // the hit's slot r of the sink's list: slab row, then its chunk
+            auto put = [&](bool hit, int r, int32_t id) {
+                if (hit && (!SLAB || r < kNbCap)) a.ids[obase + r] = id;
+                if constexpr (SLAB) {
+                    if (ballot(r >= kNbCap) != 0ull) {   // rare: a sink past its slab row
+                        if (r == kNbCap) {                // its first overflow takes a chunk
+                            const int32_t ch = atomicAdd(a.ctl + 2, 1);
+                            sh.chunk[L.sslot] = ch < a.pool_cap ? ch : -2;
+                        }
+                        tile_sync();
+                        if (r >= kNbCap && r < kNbCap + kNbChunk) {
+                            const int32_t ch = sh.chunk[L.sslot];
+                            if (ch >= 0) a.pool[(int64_t)ch * kNbChunk + (r - kNbCap)] = id;
+                        }
+                    }
                 }
             };
-            int fill = 0;   // kept sources waiting in tile[0, fill)
+            // rows [0, np) of the waiting sources: slice j of a sink tests j, j + J,
+            // ...; two rows per step, so that their LDS traffic overlaps
+            auto rows = [&](int np) {
+                int u0 = 0;
+                for (; u0 + L.J < np; u0 += 2 * L.J) {
+                    const SrcN s0 = sh.tile[(head + u0 + L.slice) & kRingMask];
+                    const SrcN s1 = sh.tile[(head + u0 + L.J + L.slice) & kRingMask];
+                    const bool h0 = (s0.pb != pa) & (dist2(xa, ya, za, s0.x, s0.y, s0.z) < lim);
+                    const bool h1 = (s1.pb != pa) & (dist2(xa, ya, za, s1.x, s1.y, s1.z) < lim);
+                    const int r0 = h0 ? atomicAdd(&sh.cnt[L.sslot], 1) : -1;
+                    const int r1 = h1 ? atomicAdd(&sh.cnt[L.sslot], 1) : -1;
+                    put(h0, r0, s0.id);
+                    put(h1, r1, s1.id);
+                }
+                if (u0 < np) {
+                    const SrcN s0 = sh.tile[(head + u0 + L.slice) & kRingMask];
+                    const bool h0 = (s0.pb != pa) & (dist2(xa, ya, za, s0.x, s0.y, s0.z) < lim);
+                    const int r0 = h0 ? atomicAdd(&sh.cnt[L.sslot], 1) : -1;
+                    put(h0, r0, s0.id);
+                }
+                head = (head + np) & kRingMask;
+            };
+            int fill = 0;   // kept sources waiting in the ring from head
             for (int64_t e0 = n0; e0 < n1; e0 += kWave) {
                 const int tot =
                     load_entry_chunk(a.gnear, a.nfirst, a.ncount, e0, n1, 1u << (8 + li), sh.ec);
@@ -144,13 +201,16 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
                     const bool keep = q < tot && dist2(gA.x, gA.y, gA.z, sx, sy, sz) < rA2;
                     const uint64_t kb = ballot(keep);
                     if (keep) {   // appended in order after the waiting ones
-                        SrcN &dst = sh.tile[fill + rank_below(kb)];
+                        SrcN &dst = sh.tile[(head + fill + rank_below(kb)) & kRingMask];
                         dst.x = sx;
                         dst.y = sy;
                         dst.z = sz;
                         dst.pb = spb;
                         dst.id = sid;
                     }
+                    // every gather has landed: otherwise the waits for them (which on
+                    // this chip also wait for all earlier stores) are left to the rows
+                    __builtin_amdgcn_s_waitcnt(kVmcnt0);
                     const int avail = fill + __popcll(kb);
                     tile_sync();
                     if (avail >= kWave) {   // whole rows only; the rest waits
@@ -158,33 +218,13 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
                         rows(np);
                         fill = avail - np;
                         tile_sync();
-                        double vx = 0.0, vy = 0.0, vz = 0.0;
-                        int32_t vpb = -1, vid = -1;
-                        if (lane < fill) {
-                            const SrcN &src = sh.tile[np + lane];
-                            vx = src.x;
-                            vy = src.y;
-                            vz = src.z;
-                            vpb = src.pb;
-                            vid = src.id;
-                        }
-                        tile_sync();
-                        if (lane < fill) {
-                            SrcN &dst = sh.tile[lane];
-                            dst.x = vx;
-                            dst.y = vy;
-                            dst.z = vz;
-                            dst.pb = vpb;
-                            dst.id = vid;
-                        }
-                        tile_sync();
                     } else {
                         fill = avail;
                     }
                 }
             }
             {   // pads the last partial row
-                SrcN &dst = sh.tile[fill + lane];
+                SrcN &dst = sh.tile[(head + fill + lane) & kRingMask];
                 dst.x = dst.y = dst.z = __builtin_inf();
                 dst.pb = -1;
                 dst.id = -1;
@@ -193,57 +233,230 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
             rows(fill);
             tile_sync();
             if (SLAB && has_sink && L.slice == 0) {
+                const int cnt = sh.cnt[L.sslot];
                 a.counts[oa] = cnt;
                 if (cnt > kNbCap) {
-                    atomicAdd(a.flag, 1);
-                    leaf_over = true;
+                    const int32_t ch = sh.chunk[L.sslot];
+                    if (ch >= 0 && cnt <= kNbCap + kNbChunk) {
+                        a.head[oa] = ch;
+                        a.longq[atomicAdd(a.ctl + 3, 1)] = oa;   // at most one per chunk
+                    } else {
+                        a.head[oa] = -1;
+                        atomicAdd(a.ctl, 1);
+                        leaf_over = true;
+                    }
                 }
             }
+            if (!SLAB && has_sink && L.slice == 0) a.longq[atomicAdd(a.ctl, 1)] = oa;
+            tile_sync();   // cnt / chunk are reset by the next pass
         }
-        if (SLAB && ballot(leaf_over) != 0ull && lane == 0) a.queue[atomicAdd(a.nqueue, 1)] = (int32_t)(A - a.nleaf);
+        if (SLAB && ballot(leaf_over) != 0ull && lane == 0) a.queue[atomicAdd(a.ctl + 1, 1)] = (int32_t)(A - a.nleaf);
     }
 }
 
-// caller index -> tree position
-__global__ __launch_bounds__(kBlock) void k_inv(int64_t n, const int32_t *__restrict__ pid,
-                                                int32_t *__restrict__ inv) {
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p < n) inv[pid[p]] = (int32_t)p;
+// Sorting network on 64 keys, all comparators ascending: for k = 2, 4, ..., 64
+// the first stage pairs i with i ^ (k - 1), the following ones i with i ^ d
+// (d = k/4, ..., 1); the smaller key goes to the lower index. Key i sits in
+// register i % 8 of lane i / 8 of an aligned group of 8 lanes, so strides
+// below 8 are exchanges between registers and the others between lanes.
+__device__ __forceinline__ void cex(uint32_t &lo, uint32_t &hi) {
+    const uint32_t a = lo, b = hi;
+    lo = a < b ? a : b;
+    hi = a < b ? b : a;
 }
 
-// slab lists -> the caller's CSR, walked in caller order so that the list
-// stores and offset loads are contiguous: 8 lanes per particle, each
-// loading up to 8 slab entries before its first store
-__global__ __launch_bounds__(kBlock) void k_nb_compact(int64_t n, const int32_t *__restrict__ inv,
-                                                       const int64_t *__restrict__ offsets,
+template <int K>
+__device__ __forceinline__ void net64_flip(uint32_t (&v)[8], int j0) {
+    if constexpr (K <= 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (u < (u ^ (K - 1))) cex(v[u], v[u ^ (K - 1)]);
+    } else {
+        const int m = (K >> 3) - 1;            // partner lane j0 ^ m, register 7 - u
+        const bool lower = (j0 & (K >> 4)) == 0;
+        uint32_t w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w[u] = (uint32_t)__shfl_xor((int)v[7 - u], m, kWave);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = lower ? (v[u] < w[u] ? v[u] : w[u]) : (v[u] < w[u] ? w[u] : v[u]);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void net64_stride(uint32_t (&v)[8], int j0) {
+    if constexpr (D < 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if ((u & D) == 0) cex(v[u], v[u | D]);
+    } else {
+        const int m = D >> 3;
+        const bool lower = (j0 & m) == 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t w = (uint32_t)__shfl_xor((int)v[u], m, kWave);
+            v[u] = lower ? (v[u] < w ? v[u] : w) : (v[u] < w ? w : v[u]);
+        }
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void net64_merge(uint32_t (&v)[8], int j0) {
+    net64_flip<K>(v, j0);
+    if constexpr (K >= 4) net64_stride<K / 4>(v, j0);
+    if constexpr (K >= 8) net64_stride<K / 8>(v, j0);
+    if constexpr (K >= 16) net64_stride<K / 16>(v, j0);
+    if constexpr (K >= 32) net64_stride<K / 32>(v, j0);
+    if constexpr (K >= 64) net64_stride<K / 64>(v, j0);
+}
+
+// slab rows -> the caller's CSR, in caller order: 8 lanes per particle, each
+// loading 8 consecutive slots of the row (keys past the count are 2^32 - 1,
+// i.e. last); the lists are sorted ascending, staged in LDS and stored one
+// particle at a time, each list by consecutive lanes. Lists longer than the
+// row are the long-list kernels'.
+__global__ __launch_bounds__(kBlock) void k_nb_compact(int64_t n, const int64_t *__restrict__ offsets,
                                                        const int32_t *__restrict__ slab,
                                                        int32_t *__restrict__ ids) {
+    __shared__ uint32_t stage[kWaves][8 * kNbCap];
+    uint32_t *st = stage[threadIdx.x / kWave];
+    const int lane = lane_id();
     const int64_t a = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / 8;
-    const int j0 = threadIdx.x % 8;
-    if (a >= n) return;
-    const int64_t o = offsets[a], c = offsets[a + 1] - o;
-    if (c > kNbCap) return;   // searched again by its group
-    const int32_t *row = slab + (int64_t)inv[a] * kNbCap;
-    for (int b = 0; b < (int)c; b += 64) {
-        int32_t v[8];
+    const int j0 = lane % 8, p = lane / 8;
+    int64_t o = 0, c = 0;
+    if (a < n) {
+        o = offsets[a];
+        c = offsets[a + 1] - o;
+        if (c > kNbCap) c = 0;
+    }
+    uint32_t v[8];
+    if (8 * j0 < c) {
+        const int4 *src = reinterpret_cast<const int4 *>(slab + a * kNbCap + 8 * j0);
+        const int4 x = src[0], y = src[1];
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int j = b + 8 * u + j0;
-            v[u] = j < c ? row[j] : 0;
+        for (int u = 0; u < 8; ++u)
+            if (8 * j0 + u >= c) v[u] = 0xffffffffu;
+    } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = 0xffffffffu;
+    }
+    if (ballot(c > 1) != 0ull) {   // wave-uniform: every lane takes part in the exchanges
+        net64_merge<2>(v, j0);
+        net64_merge<4>(v, j0);
+        net64_merge<8>(v, j0);
+        net64_merge<16>(v, j0);
+        net64_merge<32>(v, j0);
+        net64_merge<64>(v, j0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) st[p * kNbCap + 8 * j0 + u] = v[u];
+    tile_sync();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {   // particle q of the wave: its list by lanes 0 .. c - 1
+        const int64_t oq = __shfl(o, 8 * q, kWave);
+        const int cq = __shfl((int)c, 8 * q, kWave);
+        if (lane < cq) ids[oq + lane] = (int32_t)st[q * kNbCap + lane];
+    }
+}
+
+// Network of the same kind over P = 2^logP keys in LDS (P <= kLongLds),
+// comparators split over the nt threads of the caller (tid < nt); sync() is
+// called after each stage.
+template <typename Sync>
+__device__ __forceinline__ void lds_network(uint32_t *key, int logP, int tid, int nt, Sync sync) {
+    const int P = 1 << logP;
+    for (int lk = 1; lk <= logP; ++lk) {
+        for (int ld = lk - 1; ld >= 0; --ld) {
+            const int d = 1 << ld;
+            for (int t = tid; t < P / 2; t += nt) {
+                const int i = ((t >> ld) << (ld + 1)) | (t & (d - 1));   // bit d of i is clear
+                const int j = ld == lk - 1 ? (i ^ ((1 << lk) - 1)) : (i + d);
+                const uint32_t x = key[i], y = key[j];
+                if (y < x) {
+                    key[i] = y;
+                    key[j] = x;
+                }
+            }
+            sync();
         }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int j = b + 8 * u + j0;
-            if (j < c) ids[o + j] = v[u];
+    }
+}
+
+// Lists of kNbCap < c <= kNbCap + kNbChunk ids kept by the count call (row plus
+// one chunk): one wave per list, sorted in LDS over 128 or 256 keys.
+__global__ __launch_bounds__(kBlock) void k_nb_compact_long(int32_t nlong, const int32_t *__restrict__ longq,
+                                                            const int64_t *__restrict__ offsets,
+                                                            const int32_t *__restrict__ slab,
+                                                            const int32_t *__restrict__ head,
+                                                            const int32_t *__restrict__ pool,
+                                                            int32_t *__restrict__ ids) {
+    constexpr int P = kNbCap + kNbChunk;   // 256
+    __shared__ uint32_t keys[kWaves][P];
+    uint32_t *key = keys[threadIdx.x / kWave];
+    const int64_t w = wave_index();
+    if (w >= nlong) return;
+    const int lane = lane_id();
+    const int32_t a = longq[w];
+    const int64_t o = offsets[a];
+    const int c = (int)(offsets[a + 1] - o);
+    const int32_t *chunk = pool + (int64_t)head[a] * kNbChunk;
+    const int logP = c <= P / 2 ? 7 : 8;
+    for (int i = lane; i < (1 << logP); i += kWave)
+        key[i] = i >= c ? 0xffffffffu : (uint32_t)(i < kNbCap ? slab[(int64_t)a * kNbCap + i] : chunk[i - kNbCap]);
+    tile_sync();
+    lds_network(key, logP, lane, kWave, [] { tile_sync(); });
+    for (int i = lane; i < c; i += kWave) ids[o + i] = (int32_t)key[i];
+}
+
+// One workgroup per list searched again by the fill call: the same network
+// over the list's length rounded up to a power of two P, in LDS (padded with
+// 2^32 - 1) when P <= kLongLds, else in place in the CSR with the comparators
+// that reach past the end left out (with every comparator ascending, keys of
+// 2^32 - 1 past the end would never move).
+__global__ __launch_bounds__(kBlock) void k_nb_sort_long(const int32_t *__restrict__ longq,
+                                                         const int64_t *__restrict__ offsets,
+                                                         int32_t *__restrict__ ids) {
+    __shared__ uint32_t sm[kLongLds];
+    const int32_t a = longq[blockIdx.x];
+    const int64_t o = offsets[a], L = offsets[a + 1] - o;
+    int logP = 0;
+    while (((int64_t)1 << logP) < L) ++logP;
+    const int64_t P = (int64_t)1 << logP;
+    const int tid = threadIdx.x;
+    if (P <= kLongLds) {
+        for (int i = tid; i < P; i += kBlock) sm[i] = i < L ? (uint32_t)ids[o + i] : 0xffffffffu;
+        __syncthreads();
+        lds_network(sm, logP, tid, kBlock, [] { __syncthreads(); });
+        for (int i = tid; i < L; i += kBlock) ids[o + i] = (int32_t)sm[i];
+        return;
+    }
+    uint32_t *key = reinterpret_cast<uint32_t *>(ids + o);
+    for (int lk = 1; lk <= logP; ++lk) {
+        for (int ld = lk - 1; ld >= 0; --ld) {
+            const int64_t d = (int64_t)1 << ld;
+            for (int64_t t = tid; t < P / 2; t += kBlock) {
+                const int64_t i = ((t >> ld) << (ld + 1)) | (t & (d - 1));
+                const int64_t j = ld == lk - 1 ? (i ^ (((int64_t)1 << lk) - 1)) : (i + d);
+                if (j < L) {
+                    const uint32_t x = key[i], y = key[j];
+                    if (y < x) {
+                        key[i] = y;
+                        key[j] = x;
+                    }
+                }
+            }
+            __syncthreads();
         }
     }
 }
 
 }  // namespace
 
-// Count: one search that also writes every particle's ids into a slab of
-// kNbCap slots; fill then compacts the slab and searches again only the
-// groups holding a particle with more neighbours than that.
+// Count: one search that writes every particle's count into offsets (then
+// scanned in place) and its ids into the slab row (and a chunk of the pool
+// past the row); fill then compacts and sorts those, and searches again only
+// the cells holding a list that did not fit.
 rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipStream_t s) {
     if (t->lists_kept) {
         set_error("rcb_neighbours_count: the interaction lists were kept across rcb_refresh "
@@ -252,32 +465,36 @@ rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipSt
     }
     rcb_status st = ensure_walk(t, s);
     if (st != RCB_OK) return st;
-    Scratch tmp(t, s);
-    int64_t *counts = (int64_t *)dalloc(t, sizeof(int64_t) * t->n, s, tmp);
-    if (!counts) return RCB_ENOMEM;
     if (!t->nb_slab) {
+        // one chunk for every 32nd particle: lists past 64 ids are a few percent
+        // at ~50 neighbours; the rest is searched again by the fill call
+        t->nb_pool_cap = t->n / 32 + 1;
         t->nb_slab = (int32_t *)dalloc(t, sizeof(int32_t) * t->n * kNbCap, s, t->list_allocs);
+        t->nb_pool = (int32_t *)dalloc(t, sizeof(int32_t) * t->nb_pool_cap * kNbChunk, s, t->list_allocs);
+        t->nb_head = (int32_t *)dalloc(t, sizeof(int32_t) * t->n, s, t->list_allocs);
+        t->nb_longq = (int32_t *)dalloc(t, sizeof(int32_t) * t->nb_pool_cap, s, t->list_allocs);
         t->nb_queue = (int32_t *)dalloc(t, sizeof(int32_t) * t->nleaf, s, t->list_allocs);
-        t->nb_inv = (int32_t *)dalloc(t, sizeof(int32_t) * t->n, s, t->list_allocs);
-        if (!t->nb_slab || !t->nb_queue || !t->nb_inv) return RCB_ENOMEM;
+        t->nb_ctl = (int32_t *)dalloc(t, sizeof(int32_t) * 4, s, t->list_allocs);
+        if (!t->nb_slab || !t->nb_pool || !t->nb_head || !t->nb_longq || !t->nb_queue || !t->nb_ctl)
+            return RCB_ENOMEM;
     }
-    RCB_HIP(hipMemsetAsync(t->dflag + 4, 0, sizeof(int32_t), s));
-    RCB_HIP(hipMemsetAsync(t->dflag + 7, 0, sizeof(int32_t), s));
+    RCB_HIP(hipMemsetAsync(t->nb_ctl, 0, sizeof(int32_t) * 4, s));
     NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
-                t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, counts, nullptr, t->nb_slab,
-                t->dflag + 4, t->nb_queue, t->dflag + 7, 0};
+                t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, offsets, nullptr, t->nb_slab,
+                t->nb_pool, t->nb_pool_cap, t->nb_head, t->nb_ctl, t->nb_queue, t->nb_longq, 0};
     const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     k_neigh<true><<<grid, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_neigh<slab>");
-    st = scan_i64(t, counts, offsets, t->n, s);
+    st = scan_i64(t, offsets, offsets, t->n, s);   // in place
     if (st != RCB_OK) return st;
-    int32_t over[4] = {0, 0, 0, 0};   // dflag[4..7]: particles past the slab, ..., leaves queued
+    int32_t ctl[4] = {0, 0, 0, 0};
     RCB_HIP(hipMemcpyAsync(total, offsets + t->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RCB_HIP(hipMemcpyAsync(over, t->dflag + 4, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
+    RCB_HIP(hipMemcpyAsync(ctl, t->nb_ctl, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
     RCB_HIP(hipStreamSynchronize(s));
     t->nb_total = *total;
-    t->nb_over = over[0];
-    t->nb_nq = over[3];
+    t->nb_over = ctl[0];
+    t->nb_nq = ctl[1];
+    t->nb_long = ctl[3];
     return RCB_OK;
 }
 
@@ -293,16 +510,29 @@ rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, in
         return RCB_ECAPACITY;
     }
     const unsigned gridc = (unsigned)((t->n * 8 + kBlock - 1) / kBlock);
-    k_inv<<<(unsigned)((t->n + kBlock - 1) / kBlock), kBlock, 0, s>>>(t->n, t->pid, t->nb_inv);
-    k_nb_compact<<<gridc, kBlock, 0, s>>>(t->n, t->nb_inv, offsets, t->nb_slab, ids);
+    k_nb_compact<<<gridc, kBlock, 0, s>>>(t->n, offsets, t->nb_slab, ids);
     RCB_LAUNCH_CHECK("k_nb_compact");
+    if (t->nb_long > 0) {
+        const unsigned gl = (unsigned)((t->nb_long + kWaves - 1) / kWaves);
+        k_nb_compact_long<<<gl, kBlock, 0, s>>>(t->nb_long, t->nb_longq, offsets, t->nb_slab, t->nb_head,
+                                                t->nb_pool, ids);
+        RCB_LAUNCH_CHECK("k_nb_compact_long");
+    }
     if (t->nb_nq > 0) {
+        Scratch tmp(t, s);
+        int32_t *longq = (int32_t *)dalloc(t, sizeof(int32_t) * (size_t)t->nb_over, s, tmp);
+        int32_t *ctl = (int32_t *)dalloc(t, sizeof(int32_t), s, tmp);
+        if (!longq || !ctl) return RCB_ENOMEM;
+        RCB_HIP(hipMemsetAsync(ctl, 0, sizeof(int32_t), s));
         NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
-                    t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids, nullptr,
-                    t->nb_queue, nullptr, t->nb_nq};
+                    t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids,
+                    nullptr, 0, t->nb_head, ctl, t->nb_queue, longq, t->nb_nq};
         const unsigned grid = (unsigned)((t->nb_nq + kWaves - 1) / kWaves);
         k_neigh<false><<<grid, kBlock, 0, s>>>(a);
         RCB_LAUNCH_CHECK("k_neigh<fill>");
+        // exactly the nb_over lists the count call could not keep append themselves
+        k_nb_sort_long<<<(unsigned)t->nb_over, kBlock, 0, s>>>(longq, offsets, ids);
+        RCB_LAUNCH_CHECK("k_nb_sort_long");
     }
     return RCB_OK;
 }

@@ -1,5 +1,6 @@
 // k_scan.hip -- device exclusive prefix sum of int64 counts (neighbour
-// offsets, per-leaf list offsets): out[0] = 0, out[i + 1] = out[i] + in[i].
+// offsets, per-leaf list offsets): out[0] = 0, out[i + 1] = out[i] + in[i];
+// out may be in itself (in[n] is not read).
 // Three passes over blocks of 2048 values: block sums, a one-block scan of
 // the block sums, then the per-block scan with the block's carry.
 #include "rcb_internal.h"
@@ -60,9 +61,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t *__restrict__
     }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int64_t *__restrict__ in, int64_t n,
+// in may equal out: each thread reads its own values before writing them
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int64_t *in, int64_t n,
                                                              const int64_t *__restrict__ bsum,
-                                                             int64_t *__restrict__ out) {
+                                                             int64_t *out) {
     const int64_t base = blockIdx.x * (int64_t)kTile + threadIdx.x * (int64_t)kPer;
     int64_t v[kPer], s = 0;
 #pragma unroll

@@ -731,8 +731,9 @@ void drop_lists(rcb_tree *t, hipStream_t s) {
     t->near_off = t->far_off = nullptr;
     t->near_list = t->far_list = nullptr;
     t->nb_total = -1;
-    t->nb_slab = t->nb_inv = t->nb_queue = nullptr;
-    t->nb_over = t->nb_nq = 0;
+    t->nb_slab = t->nb_pool = t->nb_head = t->nb_longq = t->nb_queue = t->nb_ctl = nullptr;
+    t->nb_pool_cap = 0;
+    t->nb_over = t->nb_long = t->nb_nq = 0;
     t->walk_requeued = 0;
     t->walk_nodes = t->walk_tests = -1;
     t->farc = nullptr;

@@ -87,9 +87,14 @@ struct rcb_tree {
     int32_t *near_list = nullptr, *far_list = nullptr;
     int64_t nb_total = -1;             // neighbour total of the last count call
     int32_t *nb_slab = nullptr;        // neighbour ids of the count call, kNbCap per particle
-    int32_t *nb_inv = nullptr;         // caller index -> tree position (fill call)
-    int32_t *nb_queue = nullptr;       // leaves with a particle of more than kNbCap neighbours
-    int32_t nb_over = 0;               // particles with more than kNbCap neighbours
+    int32_t *nb_pool = nullptr;        // overflow chunks of the slab rows
+    int32_t *nb_head = nullptr;        // per particle: its chunk (lists past the row)
+    int32_t *nb_longq = nullptr;       // particles whose list sits in row + chunk
+    int32_t *nb_queue = nullptr;       // leaves holding a list that the fill call searches again
+    int32_t *nb_ctl = nullptr;         // device counters of the count call
+    int64_t nb_pool_cap = 0;           // chunks in nb_pool
+    int32_t nb_over = 0;               // lists the fill call searches again
+    int32_t nb_long = 0;               // lists kept in row + chunk
     int32_t nb_nq = 0;                 // entries of nb_queue
     // device flags: [0] 8-wide walk stack overflow, [1] long near lists, [2] their
     // queue, [3] groups outgrowing the list slabs, [4] particles outgrowing
@@ -182,6 +187,22 @@ __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 // (scalar registers and scalar loads).
 __device__ __forceinline__ int64_t wave_index() {
     const uint32_t w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    return (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)w);
+}
+
+// Workgroups are handed to the 8 XCDs in turn (workgroup b to XCD b mod 8),
+// and each XCD has its own L2. xcd_block() renumbers them so that XCD x takes
+// one contiguous range of logical workgroups: neighbouring groups of cells,
+// which share sources and tree nodes, then meet in the same L2. A bijection
+// on [0, gridDim.x) for any grid size.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_block() {
+    const uint32_t b = blockIdx.x, nb = gridDim.x;
+    const uint32_t q = nb / kXcds, r = nb % kXcds, x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+__device__ __forceinline__ int64_t xcd_wave_index() {
+    const uint32_t w = xcd_block() * (blockDim.x / kWave) + threadIdx.x / kWave;
     return (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)w);
 }
 
