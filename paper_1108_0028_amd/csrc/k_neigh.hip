@@ -33,11 +33,17 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
+// The search takes one wave per workgroup: the work of a group of cells
+// varies tenfold, and a wider workgroup would hold its LDS until its slowest
+// wave ends.
+constexpr int kSearchWaves = 1;
 constexpr int kNbCap = 64;        // slab slots per particle (~50 neighbours expected)
 constexpr int kNbChunk = 192;     // slots of an overflow chunk: lists of up to 256 ids
 constexpr int kLongLds = 4096;    // lists searched again: sorted in LDS up to this length
 constexpr int kRingMask = 2 * kWave - 1;
+constexpr int kRingBytes = 2 * kWave * 32;   // the ring of SrcN, in bytes
 constexpr int kVmcnt0 = 0x0f70;   // s_waitcnt vmcnt(0), expcnt and lgkmcnt left free
+constexpr int kIcmpUge = 35;      // unsigned >= for __builtin_amdgcn_uicmp
 
 struct NeighArgs {
     int64_t nleaf;
@@ -89,8 +95,8 @@ struct NeighShared {
 // Otherwise only the sinks queued that way are searched, their ids going to
 // offsets[pid] + slot.
 template <bool SLAB>
-__global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
-    __shared__ NeighShared sh_all[kWaves];
+__global__ __launch_bounds__(kSearchWaves * kWave) void k_neigh(NeighArgs a) {
+    __shared__ NeighShared sh_all[kSearchWaves];
     NeighShared &sh = sh_all[threadIdx.x / kWave];
     const int lane = lane_id();
     const int G = 1 << a.gk;
@@ -142,41 +148,56 @@ __global__ __launch_bounds__(kBlock) void k_neigh(NeighArgs a) {
             }
             tile_sync();
             int head = 0;   // ring position of the first waiting source
-            // the hit's slot r of the sink's list: slab row, then its chunk
-            auto put = [&](bool hit, int r, int32_t id) {
-                if (hit && (!SLAB || r < kNbCap)) a.ids[obase + r] = id;
+            int32_t *const row = a.ids + obase;
+            // hit h with slot r (0 for lanes without a hit): into the slab row, or
+            // (rare) the sink's chunk, which its first overflowing hit takes
+            auto put = [&](bool h, uint32_t r, int32_t id) {
+                const bool low = !SLAB || r < (uint32_t)kNbCap;
+                if (h & low) row[r] = id;
                 if constexpr (SLAB) {
-                    if (ballot(r >= kNbCap) != 0ull) {   // rare: a sink past its slab row
-                        if (r == kNbCap) {                // its first overflow takes a chunk
+                    // lanes with r >= kNbCap, as the comparison's own lane mask
+                    if (__builtin_amdgcn_uicmp(r, (uint32_t)kNbCap, kIcmpUge) != 0ull) {
+                        if (r == (uint32_t)kNbCap) {
                             const int32_t ch = atomicAdd(a.ctl + 2, 1);
                             sh.chunk[L.sslot] = ch < a.pool_cap ? ch : -2;
                         }
                         tile_sync();
-                        if (r >= kNbCap && r < kNbCap + kNbChunk) {
+                        if (!low && r < (uint32_t)(kNbCap + kNbChunk)) {
                             const int32_t ch = sh.chunk[L.sslot];
                             if (ch >= 0) a.pool[(int64_t)ch * kNbChunk + (r - kNbCap)] = id;
                         }
+                        tile_sync();
                     }
                 }
+            };
+            auto test = [&](const SrcN &src) {
+                return (src.pb != pa) & (dist2(xa, ya, za, src.x, src.y, src.z) < lim);
+            };
+            // the ring as byte offsets: (offset & kRingBytes - 1) wraps it
+            auto at = [&](int b) -> const SrcN & {
+                return *reinterpret_cast<const SrcN *>(reinterpret_cast<const char *>(sh.tile) +
+                                                       (b & (kRingBytes - 1)));
             };
             // rows [0, np) of the waiting sources: slice j of a sink tests j, j + J,
             // ...; two rows per step, so that their LDS traffic overlaps
             auto rows = [&](int np) {
+                const int b0 = (head + L.slice) * (int)sizeof(SrcN), bJ = L.J * (int)sizeof(SrcN);
                 int u0 = 0;
                 for (; u0 + L.J < np; u0 += 2 * L.J) {
-                    const SrcN s0 = sh.tile[(head + u0 + L.slice) & kRingMask];
-                    const SrcN s1 = sh.tile[(head + u0 + L.J + L.slice) & kRingMask];
-                    const bool h0 = (s0.pb != pa) & (dist2(xa, ya, za, s0.x, s0.y, s0.z) < lim);
-                    const bool h1 = (s1.pb != pa) & (dist2(xa, ya, za, s1.x, s1.y, s1.z) < lim);
-                    const int r0 = h0 ? atomicAdd(&sh.cnt[L.sslot], 1) : -1;
-                    const int r1 = h1 ? atomicAdd(&sh.cnt[L.sslot], 1) : -1;
+                    const int b = b0 + u0 * (int)sizeof(SrcN);
+                    const SrcN s0 = at(b), s1 = at(b + bJ);
+                    const bool h0 = test(s0), h1 = test(s1);
+                    uint32_t r0 = 0, r1 = 0;
+                    if (h0) r0 = atomicAdd((uint32_t *)&sh.cnt[L.sslot], 1u);
+                    if (h1) r1 = atomicAdd((uint32_t *)&sh.cnt[L.sslot], 1u);
                     put(h0, r0, s0.id);
                     put(h1, r1, s1.id);
                 }
                 if (u0 < np) {
-                    const SrcN s0 = sh.tile[(head + u0 + L.slice) & kRingMask];
-                    const bool h0 = (s0.pb != pa) & (dist2(xa, ya, za, s0.x, s0.y, s0.z) < lim);
-                    const int r0 = h0 ? atomicAdd(&sh.cnt[L.sslot], 1) : -1;
+                    const SrcN s0 = at(b0 + u0 * (int)sizeof(SrcN));
+                    const bool h0 = test(s0);
+                    uint32_t r0 = 0;
+                    if (h0) r0 = atomicAdd((uint32_t *)&sh.cnt[L.sslot], 1u);
                     put(h0, r0, s0.id);
                 }
                 head = (head + np) & kRingMask;
@@ -265,6 +286,24 @@ __device__ __forceinline__ void cex(uint32_t &lo, uint32_t &hi) {
     hi = a < b ? b : a;
 }
 
+// v of lane (lane ^ M) for M < 8, by DPP moves within rows (no LDS path):
+// quad permutations give xor 1, 2 and 3, the half-row mirror xor 7, and the
+// mirror followed by the quad reversal xor 4.
+template <int M>
+__device__ __forceinline__ uint32_t xor_lanes(uint32_t v) {
+    constexpr int kQuadXor1 = 0xb1, kQuadXor2 = 0x4e, kQuadXor3 = 0x1b, kHalfMirror = 0x141;
+    const int x = (int)v;
+    if constexpr (M == 1) return (uint32_t)__builtin_amdgcn_mov_dpp(x, kQuadXor1, 0xf, 0xf, true);
+    if constexpr (M == 2) return (uint32_t)__builtin_amdgcn_mov_dpp(x, kQuadXor2, 0xf, 0xf, true);
+    if constexpr (M == 3) return (uint32_t)__builtin_amdgcn_mov_dpp(x, kQuadXor3, 0xf, 0xf, true);
+    if constexpr (M == 7) return (uint32_t)__builtin_amdgcn_mov_dpp(x, kHalfMirror, 0xf, 0xf, true);
+    if constexpr (M == 4)
+        return (uint32_t)__builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, kHalfMirror, 0xf, 0xf, true),
+                                                  kQuadXor3, 0xf, 0xf, true);
+    static_assert(M == 1 || M == 2 || M == 3 || M == 4 || M == 7, "lane xor not provided");
+    return v;
+}
+
 template <int K>
 __device__ __forceinline__ void net64_flip(uint32_t (&v)[8], int j0) {
     if constexpr (K <= 8) {
@@ -272,11 +311,11 @@ __device__ __forceinline__ void net64_flip(uint32_t (&v)[8], int j0) {
         for (int u = 0; u < 8; ++u)
             if (u < (u ^ (K - 1))) cex(v[u], v[u ^ (K - 1)]);
     } else {
-        const int m = (K >> 3) - 1;            // partner lane j0 ^ m, register 7 - u
+        // partner: lane j0 ^ (K / 8 - 1), register 7 - u
         const bool lower = (j0 & (K >> 4)) == 0;
         uint32_t w[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) w[u] = (uint32_t)__shfl_xor((int)v[7 - u], m, kWave);
+        for (int u = 0; u < 8; ++u) w[u] = xor_lanes<(K >> 3) - 1>(v[7 - u]);
 #pragma unroll
         for (int u = 0; u < 8; ++u) v[u] = lower ? (v[u] < w[u] ? v[u] : w[u]) : (v[u] < w[u] ? w[u] : v[u]);
     }
@@ -289,11 +328,10 @@ __device__ __forceinline__ void net64_stride(uint32_t (&v)[8], int j0) {
         for (int u = 0; u < 8; ++u)
             if ((u & D) == 0) cex(v[u], v[u | D]);
     } else {
-        const int m = D >> 3;
-        const bool lower = (j0 & m) == 0;
+        const bool lower = (j0 & (D >> 3)) == 0;   // partner: lane j0 ^ (D / 8)
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const uint32_t w = (uint32_t)__shfl_xor((int)v[u], m, kWave);
+            const uint32_t w = xor_lanes<(D >> 3)>(v[u]);
             v[u] = lower ? (v[u] < w ? v[u] : w) : (v[u] < w ? w : v[u]);
         }
     }
@@ -354,8 +392,9 @@ __global__ __launch_bounds__(kBlock) void k_nb_compact(int64_t n, const int64_t 
     tile_sync();
 #pragma unroll
     for (int q = 0; q < 8; ++q) {   // particle q of the wave: its list by lanes 0 .. c - 1
-        const int64_t oq = __shfl(o, 8 * q, kWave);
-        const int cq = __shfl((int)c, 8 * q, kWave);
+        const int64_t oq = ((int64_t)__builtin_amdgcn_readlane((int)(o >> 32), 8 * q) << 32) |
+                           (uint32_t)__builtin_amdgcn_readlane((int)o, 8 * q);
+        const int cq = __builtin_amdgcn_readlane((int)c, 8 * q);
         if (lane < cq) ids[oq + lane] = (int32_t)st[q * kNbCap + lane];
     }
 }
@@ -482,8 +521,8 @@ rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipSt
     NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
                 t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, offsets, nullptr, t->nb_slab,
                 t->nb_pool, t->nb_pool_cap, t->nb_head, t->nb_ctl, t->nb_queue, t->nb_longq, 0};
-    const unsigned grid = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
-    k_neigh<true><<<grid, kBlock, 0, s>>>(a);
+    const unsigned grid = (unsigned)((t->ngroup + kSearchWaves - 1) / kSearchWaves);
+    k_neigh<true><<<grid, kSearchWaves * kWave, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_neigh<slab>");
     st = scan_i64(t, offsets, offsets, t->n, s);   // in place
     if (st != RCB_OK) return st;
@@ -527,8 +566,8 @@ rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, in
         NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
                     t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids,
                     nullptr, 0, t->nb_head, ctl, t->nb_queue, longq, t->nb_nq};
-        const unsigned grid = (unsigned)((t->nb_nq + kWaves - 1) / kWaves);
-        k_neigh<false><<<grid, kBlock, 0, s>>>(a);
+        const unsigned grid = (unsigned)((t->nb_nq + kSearchWaves - 1) / kSearchWaves);
+        k_neigh<false><<<grid, kSearchWaves * kWave, 0, s>>>(a);
         RCB_LAUNCH_CHECK("k_neigh<fill>");
         // exactly the nb_over lists the count call could not keep append themselves
         k_nb_sort_long<<<(unsigned)t->nb_over, kBlock, 0, s>>>(longq, offsets, ids);
