@@ -252,6 +252,10 @@ rcb_status rcb_gravity(rcb_tree *t, void *ax, void *ay, void *az, void *stream);
  * writes dL/dx, dL/dy, dL/dz and dL/dm. h gets no gradient. Near-field pairs
  * are recomputed, not stored. g*: n values, d*: n values, FP64 for RCB_FP64
  * and FP32 for RCB_MIXED. Valid after rcb_build() (gravity need not have run).
+ * Summation order: the source-side near-field terms and the node adjoints
+ * are added with atomics (FP64; FP32 in the mixed form), so two calls agree
+ * to rounding, not bit for bit. There is no atomic-free (deterministic)
+ * variant, and rcb_params has no switch asking for one.
  * Errors: RCB_EINVAL (NULL argument, or a tree built with RCB_READING_B).
  */
 rcb_status rcb_gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *gz,

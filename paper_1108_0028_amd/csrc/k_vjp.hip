@@ -33,7 +33,11 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kAdj = 10;    // M, R(3), Q(6)
+// M, R(3) and the traceless part of the Q adjoint, (xx, xy, xz, yy, yz) with
+// zz = -(xx + yy): Q is traceless, so the push (the only reader) sees the
+// adjoint's traceless part alone (6 aQ d - 2 tr(aQ) d = 6 (aQ - tr/3 I) d, and
+// likewise for dm), and one atomic per entry fewer goes out
+constexpr int kAdj = 9;
 constexpr int kAdjCopies = 8;   // node-adjoint copies filled by k_vjp_far
 // Nodes of the levels above kMidLevel sit in the far lists of many groups at
 // once, and the atomics on their adjoints contend: they get kAdjMidCopies
@@ -219,8 +223,12 @@ __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a, AT *__restrict__ 
                 ad[0] += aM;
 #pragma unroll
                 for (int u = 0; u < 3; ++u) ad[1 + u] -= rho[u];
-#pragma unroll
-                for (int q = 0; q < 6; ++q) ad[4 + q] += aQ[q];
+                const double tq = (aQ[0] + aQ[3] + aQ[5]) / 3.0;
+                ad[4] += aQ[0] - tq;
+                ad[5] += aQ[1];
+                ad[6] += aQ[2];
+                ad[7] += aQ[3] - tq;
+                ad[8] += aQ[4];
             }
             // lanes 2j and 2j + 1 add their terms, the even lane keeps the sum
 #pragma unroll
@@ -437,17 +445,15 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
 __device__ __forceinline__ void push_node(const double (&ad)[kAdj], double MB, const double (&cB)[3],
                                           const double (&r)[3], double mb, double (&dr)[3],
                                           double &dmb) {
-    const double Q[3][3] = {{ad[4], ad[5], ad[6]}, {ad[5], ad[7], ad[8]}, {ad[6], ad[8], ad[9]}};
+    const double Q[3][3] = {{ad[4], ad[5], ad[6]}, {ad[5], ad[7], ad[8]}, {ad[6], ad[8], -(ad[4] + ad[7])}};
     const double d[3] = {r[0] - cB[0], r[1] - cB[1], r[2] - cB[2]};
-    const double trQ = Q[0][0] + Q[1][1] + Q[2][2];
-    const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
     double Qd[3];
 #pragma unroll
     for (int l = 0; l < 3; ++l) Qd[l] = Q[l][0] * d[0] + Q[l][1] * d[1] + Q[l][2] * d[2];
 #pragma unroll
-    for (int l = 0; l < 3; ++l) dr[l] += ad[1 + l] * mb / MB + mb * (6.0 * Qd[l] - 2.0 * trQ * d[l]);
+    for (int l = 0; l < 3; ++l) dr[l] += ad[1 + l] * mb / MB + mb * (6.0 * Qd[l]);
     dmb += ad[0] + (ad[1] * d[0] + ad[2] * d[1] + ad[3] * d[2]) / MB +
-           3.0 * (d[0] * Qd[0] + d[1] * Qd[1] + d[2] * Qd[2]) - d2 * trQ;
+           3.0 * (d[0] * Qd[0] + d[1] * Qd[1] + d[2] * Qd[2]);
 }
 
 // node adjoints -> particles along each particle's ancestor chain; then the
