@@ -137,6 +137,29 @@ def main():
                         "accelerations), from hipMemGetInfo"}
         t_keep.destroy()
         del off_keep
+        # the neighbour search alone: its scratch (slab, overflow pool, queues)
+        # and the CSR it returns, on a walked tree, with the library's and
+        # torch's caches emptied first
+        from paper_1108_0028_amd import release_cache
+        torch.cuda.synchronize()
+        release_cache()
+        torch.cuda.empty_cache()
+        t_nb = Tree(*arrs, n_ll=a.n_ll, theta=a.theta, precision=a.precision, pure_mac=a.pure_mac)
+        t_nb.walk()
+        torch.cuda.synchronize()
+        f0 = torch.cuda.mem_get_info()[0]
+        off_nb, ids_nb = t_nb.neighbours()
+        torch.cuda.synchronize()
+        f1 = torch.cuda.mem_get_info()[0]
+        csr = off_nb.numel() * off_nb.element_size() + ids_nb.numel() * ids_nb.element_size()
+        mem["neighbours"] = {"bytes_per_particle": (f0 - f1) / n, "csr_bytes_per_particle": csr / n,
+                             "scratch_bytes_per_particle": (f0 - f1 - csr) / n,
+                             "basis": "hipMemGetInfo around the count + fill calls on a walked tree: the "
+                                      "library's scratch (64-slot slab, overflow chunks, queues) plus the "
+                                      "returned CSR (int64 offsets, int32 ids); allocations round up to "
+                                      "2 MiB"}
+        t_nb.destroy()
+        del off_nb, ids_nb
 
     sec, phases = timed(a.precision, a.steps, a.warmup)
     value = n / sec
@@ -282,6 +305,7 @@ def _rooflines(c, phases, prec, n, k):
     # gather and records the rest)
     b = hbm(n * (48 * k + 100), phases["build"])
     b["basis"] = f"N (48 k + 100) bytes, k = {k}"
+    b["traffic"] = {k_: _profiled(k_) for k_ in ("k_subtree", "k_part_scatter", "k_chunk_reduce<0>", "k_init")}
     # walk: FP64 tests of (node, visiting cell) pairs; also the node records it loads
     w = alu(0, FLOP_TEST * c["walk_tests"], phases["walk"])
     w["hbm_bytes"] = 64 * c["walk_nodes"]
@@ -297,7 +321,7 @@ def _rooflines(c, phases, prec, n, k):
     nb["hbm_frac"] = nbytes / (phases["neighbours"] * 1e-3) / (PEAK_HBM_GBS * 1e9)
     nb["basis"] = (f"{FLOP_CULL} FP64 flop per candidate pair ({c['cand_pairs']}); 28 B per candidate "
                    f"particle of a cell ({c['cand_particles']}), 12 B per neighbour id, 16 B per particle")
-    nb["traffic"] = {k_: _profiled(k_) for k_ in ("k_neigh<true>", "k_nb_compact")}
+    nb["traffic"] = {k_: _profiled(k_) for k_ in ("k_neigh<true>", "k_nb_compact", "k_nb_compact_long")}
     g["counts"] = c
     return g, {"build": b, "walk": w, "neighbours": nb, "gravity": {k_: v for k_, v in g.items()
                                                                      if k_ != "counts"}}
@@ -321,9 +345,12 @@ def _vjp_timing(t, n, phases, prec):
     torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[1]) / reps
     fwd = phases["build"] + phases["walk"] + phases["gravity"]
+    far = "k_vjp_far<float>" if prec == "mixed" else "k_vjp_far<double>"
+    near = "k_vjp_near<true>" if prec == "mixed" else "k_vjp_near<false>"
     return {"ms": ms, "forward_ms": fwd, "vjp_over_forward": ms / fwd,
             "basis": "forward = build + walk + gravity of the timed steps; the VJP reuses the tree, its "
-                     "lists and the far coefficients kept by the gravity call"}
+                     "lists and the far coefficients kept by the gravity call",
+            "traffic": {far: _profiled(far), near: _profiled(near)}}
 
 
 def _direct_errors(direct, acc, theta):
