@@ -34,6 +34,12 @@
  *    the calling thread.
  *  - A tree may be used by one stream at a time; calls on one tree must not
  *    overlap.
+ *  - Two environment variables select equivalent code paths, for tests:
+ *    RCB_BUILD_LEVELS (any value) makes rcb_build() run every level as one
+ *    device-wide pass instead of finishing small subtrees in one wave each
+ *    (same tree, bit for bit); RCB_WALK_WIDE_STACK=n caps the walk's
+ *    first-tier node queue at n entries, so that more groups go to the later
+ *    tiers (same lists).
  */
 #ifndef RCB_H
 #define RCB_H
