@@ -313,10 +313,12 @@ typedef enum {
  */
 rcb_status rcb_tree_export(rcb_tree *t, int32_t field, void *dst, size_t bytes, void *stream);
 
-/* Free the tree and its device memory (waits for its last stream). Blocks
-   of 1 GiB and more from the library's own allocator stay reserved for the
-   next tree on the same device (see rcb_release_cache). */
-void rcb_destroy(rcb_tree *t);
+/* Free the tree and its device memory, in stream order on `stream` (made to
+   wait for the tree's last stream first; NULL = the tree's last stream), and
+   wait for that stream. NULL t is a no-op. Blocks of 1 GiB and more from the
+   library's own allocator stay reserved for the next tree on the same device
+   (see rcb_release_cache). */
+void rcb_destroy(rcb_tree *t, void *stream);
 
 /* Give back the device memory the library keeps for reuse: the freed blocks
    of 1 GiB and more, and the unused part of each device's default

@@ -103,7 +103,7 @@ def lib():
         L.rcb_get_info.restype = C.c_int
         L.rcb_tree_export.argtypes = [P, C.c_int32, P, C.c_size_t, P]
         L.rcb_tree_export.restype = C.c_int
-        L.rcb_destroy.argtypes = [P]
+        L.rcb_destroy.argtypes = [P, P]
         L.rcb_destroy.restype = None
         L.rcb_release_cache.argtypes = []
         L.rcb_release_cache.restype = None
@@ -274,7 +274,11 @@ class Tree:
 
     def destroy(self):
         if self._h is not None:
-            lib().rcb_destroy(self._h)
+            try:
+                s = _stream()
+            except Exception:   # interpreter shutdown: the tree's own stream
+                s = None
+            lib().rcb_destroy(self._h, s)
             self._h = None
 
     def __del__(self):

@@ -159,12 +159,24 @@ void dfree(rcb_tree *t, void *p, hipStream_t s) {
     (void)hipFreeAsync(p, s);
 }
 
-static void free_all(rcb_tree *t) {
-    for (void *p : t->list_allocs) dfree(t, p, t->stream);
-    for (void *p : t->allocs) dfree(t, p, t->stream);
+// frees every block in stream order on s (after the tree's last work on its
+// own stream), then waits for s
+static void free_all(rcb_tree *t, hipStream_t s) {
+    if (s != t->stream) {
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+            (void)hipEventRecord(ev, t->stream);
+            (void)hipStreamWaitEvent(s, ev, 0);
+            (void)hipEventDestroy(ev);
+        } else {
+            (void)hipStreamSynchronize(t->stream);
+        }
+    }
+    for (void *p : t->list_allocs) dfree(t, p, s);
+    for (void *p : t->allocs) dfree(t, p, s);
     t->list_allocs.clear();
     t->allocs.clear();
-    (void)hipStreamSynchronize(t->stream);
+    (void)hipStreamSynchronize(s);
 }
 
 }  // namespace rcb
@@ -270,7 +282,7 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
     }
     if (st != RCB_OK) {
         std::string msg = g_last_error;
-        free_all(t);
+        free_all(t, t->stream);
         delete t;
         g_last_error = msg;
         return st;
@@ -465,9 +477,9 @@ rcb_status rcb_tree_export(rcb_tree *t, int32_t field, void *dst, size_t bytes, 
     return RCB_OK;
 }
 
-void rcb_destroy(rcb_tree *t) {
+void rcb_destroy(rcb_tree *t, void *stream) {
     if (!t) return;
-    free_all(t);
+    free_all(t, stream ? (hipStream_t)stream : t->stream);
     delete t;
 }
 

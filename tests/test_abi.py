@@ -101,7 +101,7 @@ def test_null_tree_arguments():
     assert L.rcb_gravity(None, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None) == 1
     assert L.rcb_gravity_vjp(None, *([C.c_void_p(8)] * 7), None) == 1
     assert L.rcb_tree_export(None, 0, C.c_void_p(8), 8, None) == 1
-    L.rcb_destroy(None)
+    L.rcb_destroy(None, None)
 
 
 def test_noalloc_refresh_capacity_is_stated():

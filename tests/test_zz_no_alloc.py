@@ -116,7 +116,7 @@ def test_noalloc_refresh_equals_refresh(prec):
         off = torch.empty(n + 1, dtype=torch.int64, device=dev)
         tot = C.c_int64()
         assert L.rcb_neighbours_count(h, _ptr(off), C.byref(tot), _stream()) == 5
-        L.rcb_destroy(h)
+        L.rcb_destroy(h, None)
         ref.destroy()
 
 
