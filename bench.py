@@ -408,16 +408,32 @@ def cpu_baseline(cloud, a):
         s3 = time.perf_counter()
         return int(valid.sum()), (s1 - s0, s2 - s1, s3 - s2)
 
+    def near_far():
+        """Table 1's NG and FG: the near and the far field alone, same leaves."""
+        s0 = time.perf_counter()
+        ot.gravity(parts=1)
+        s1 = time.perf_counter()
+        ot.gravity(parts=2)
+        s2 = time.perf_counter()
+        return s1 - s0, s2 - s1
+
     n_s, ph = sampled()
+    ng, fg = near_far()
     O.set_threads(1)
     _, ph1 = sampled()
     O.set_threads(threads)
     build = t1 - t0
     rate = lambda p: 1.0 / (build / cloud.n + sum(p) / max(1, n_s))
+    per = lambda sec: sec / max(1, n_s) * cloud.n   # seconds for all particles at the sampled rate
     base = {"value": rate(ph), "unit": "particles/s", "cores": threads, "kind": "oracle",
             "single_thread_value": rate(ph1), "cpu": model,
             "phases_s": {"build_all": build, "walk": ph[0], "neighbours": ph[1], "gravity": ph[2],
                          "walk_1thread": ph1[0], "neighbours_1thread": ph1[1], "gravity_1thread": ph1[2]},
+            "table1_s": {"TB": build, "N": per(ph[1]), "NG": per(ng), "FG": per(fg), "G": per(ph[2]),
+                         "walk": per(ph[0]),
+                         "basis": f"Table 1's columns for all {cloud.n} particles on {threads} threads: the "
+                                  "build as measured, the rest scaled from the sampled leaves (NG: near field "
+                                  "alone, FG: far field and its Taylor evaluation alone, G: both)"},
             "sample": f"oracle build of all {cloud.n} particles ({build:.1f} s, levels split in parallel) + "
                       f"walk, neighbours and gravity of {len(leaves)} random leaves ({n_s} particles, "
                       f"{sum(ph):.1f} s on {threads} OpenMP threads, {sum(ph1):.1f} s on 1)"}

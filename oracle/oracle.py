@@ -60,6 +60,7 @@ def lib():
         L.orc_deriv_tensor.argtypes = [C.c_int, dp, dp]
         L.orc_far_coeffs.argtypes = [C.c_double, dp, dp, dp, dp, dp, dp]
         L.orc_gravity.argtypes = [P, dp, dp, dp]
+        L.orc_gravity_parts.argtypes = [P, dp, dp, dp, C.c_int]
         L.orc_vjp.argtypes = [P, dp, dp, dp, dp, dp, dp, dp]
         L.orc_psum.argtypes = [dp, C.c_int64]
         L.orc_psum.restype = C.c_double
@@ -225,10 +226,17 @@ class OracleTree:
         self.reading = reading
         lib().orc_set_reading(self.ptr, {"A": 0, "B": 1}[reading])
 
-    def gravity(self):
+    def gravity(self, parts: int = 3):
+        """Accelerations of the walked leaves' particles (NaN elsewhere). parts:
+        1 = near field only, 2 = far field only, 3 = both (for timing the two
+        separately, as Table 1 does)."""
         ax = np.zeros(self.n); ay = np.zeros(self.n); az = np.zeros(self.n)
         dp = C.POINTER(C.c_double)
-        lib().orc_gravity(self.ptr, ax.ctypes.data_as(dp), ay.ctypes.data_as(dp), az.ctypes.data_as(dp))
+        if parts == 3:
+            lib().orc_gravity(self.ptr, ax.ctypes.data_as(dp), ay.ctypes.data_as(dp), az.ctypes.data_as(dp))
+        else:
+            lib().orc_gravity_parts(self.ptr, ax.ctypes.data_as(dp), ay.ctypes.data_as(dp),
+                                    az.ctypes.data_as(dp), parts)
         return ax, ay, az
 
     def vjp(self, gx, gy, gz):

@@ -929,7 +929,10 @@ static void leaf_far(const otree *t, int64_t A, const leaf_lists *L, double f[3]
 /*       + f_A + J_A d + (1/2) H_A[d, d],   d = r_a - COM_A  (Eq. 6).       */
 /* Output in original order; particles in leaves not walked get NaN.        */
 /* ------------------------------------------------------------------------ */
-void orc_gravity(const otree *t, double *ax, double *ay, double *az)
+/* parts: 1 = the near field only, 2 = the far field only (with its Taylor */
+/* evaluation, Eq. 6), 3 = both (orc_gravity). The parts exist to time the  */
+/* near and far field separately, as Table 1's NG and FG columns do.        */
+void orc_gravity_parts(const otree *t, double *ax, double *ay, double *az, int parts)
 {
     int64_t leaf0 = (int64_t)1 << t->k;
     for (int64_t i = 0; i < t->n; ++i) ax[i] = ay[i] = az[i] = NAN;
@@ -937,12 +940,12 @@ void orc_gravity(const otree *t, double *ax, double *ay, double *az)
     for (int64_t A = leaf0; A < t->nlab; ++A) {
         const leaf_lists *L = &t->lists[A - leaf0];
         if (!L->walked || t->count[A] == 0) continue;
-        double f[3], J[9], H[27];
-        leaf_far(t, A, L, f, J, H);
+        double f[3] = {0.0, 0.0, 0.0}, J[9] = {0.0}, H[27] = {0.0};
+        if (parts & 2) leaf_far(t, A, L, f, J, H);
         for (int64_t p = t->first[A]; p < t->first[A] + t->count[A]; ++p) {
             int64_t a = t->perm[p];
             double acc[3] = {0.0, 0.0, 0.0};
-            for (int64_t j = 0; j < L->nnear; ++j) {
+            for (int64_t j = 0; j < ((parts & 1) ? L->nnear : 0); ++j) {
                 if ((uint32_t)L->near[j] & NEAR_NBONLY) continue;   /* neighbour search only */
                 int64_t B = (int64_t)((uint32_t)L->near[j] & NEAR_LABEL);
                 for (int64_t q = t->first[B]; q < t->first[B] + t->count[B]; ++q) {
@@ -969,6 +972,11 @@ void orc_gravity(const otree *t, double *ax, double *ay, double *az)
             az[a] = out[2];
         }
     }
+}
+
+void orc_gravity(const otree *t, double *ax, double *ay, double *az)
+{
+    orc_gravity_parts(t, ax, ay, az, 3);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -419,6 +419,23 @@ def test_theta_zero_equals_brute_force(n, nll, kind):
     assert np.abs(tq).max() < 1e-13 * scale * np.abs(P).max()
 
 
+def test_gravity_parts_add_up():
+    """The near-only and far-only evaluations (used to time Table 1's NG and
+    FG columns) are the two terms of the full sum: at theta = 0 the far part
+    is zero and the near part is the whole; at theta = 0.7 they add up to the
+    full acceleration to rounding."""
+    c = W.small_random(2000, 77, "clustered")
+    t = O.OracleTree(*c.arrays(), n_ll=6)
+    t.walk(0.0)
+    assert np.all(np.stack(t.gravity(parts=2), 1) == 0.0)
+    np.testing.assert_array_equal(np.stack(t.gravity(parts=1), 1), np.stack(t.gravity(), 1))
+    t.walk(0.7)
+    full = np.stack(t.gravity(), 1)
+    near, far = np.stack(t.gravity(parts=1), 1), np.stack(t.gravity(parts=2), 1)
+    assert np.abs(far).max() > 1e-3 * np.abs(full).max()
+    assert np.abs(near + far - full).max() <= 1e-14 * np.abs(full).max()
+
+
 def test_reading_b_changes_only_the_sink_expansion():
     # Reading B keeps f and takes J, H from the monopole field: a particle alone
     # in its cell sits at the cell's centre of mass (d = 0 up to the rounding
