@@ -422,30 +422,72 @@ __device__ __forceinline__ void lds_network(uint32_t *key, int logP, int tid, in
     }
 }
 
+// The same all-ascending network over 64 U keys held U per lane (key i in
+// register i % U of lane i / U): strides below U are exchanges between
+// registers, the others between lanes (shuffles).
+template <int U>
+__device__ __forceinline__ void net_lanes(uint32_t (&v)[U], int lane) {
+    for (int k = 2; k <= kWave * U; k <<= 1) {
+        if (k <= U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (u < (u ^ (k - 1))) cex(v[u], v[u ^ (k - 1)]);
+        } else {   // partner: lane ^ (k / U - 1), register U - 1 - u
+            const bool lower = (lane & (k / (2 * U))) == 0;
+            uint32_t w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) w[u] = (uint32_t)__shfl_xor((int)v[U - 1 - u], k / U - 1, kWave);
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = lower ? (v[u] < w[u] ? v[u] : w[u]) : (v[u] < w[u] ? w[u] : v[u]);
+        }
+        for (int d = k / 4; d >= 1; d >>= 1) {
+            if (d < U) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if ((u & d) == 0) cex(v[u], v[u | d]);
+            } else {   // partner: lane ^ (d / U), same register
+                const bool lower = (lane & (d / U)) == 0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t w = (uint32_t)__shfl_xor((int)v[u], d / U, kWave);
+                    v[u] = lower ? (v[u] < w ? v[u] : w) : (v[u] < w ? w : v[u]);
+                }
+            }
+        }
+    }
+}
+
 // Lists of kNbCap < c <= kNbCap + kNbChunk ids kept by the count call (row plus
-// one chunk): one wave per list, sorted in LDS over 128 or 256 keys.
+// one chunk): one wave per list, 4 keys per lane (16-byte loads: lanes 0-15
+// read the row, the others the chunk), sorted in registers.
 __global__ __launch_bounds__(kBlock) void k_nb_compact_long(int32_t nlong, const int32_t *__restrict__ longq,
                                                             const int64_t *__restrict__ offsets,
                                                             const int32_t *__restrict__ slab,
                                                             const int32_t *__restrict__ head,
                                                             const int32_t *__restrict__ pool,
                                                             int32_t *__restrict__ ids) {
-    constexpr int P = kNbCap + kNbChunk;   // 256
-    __shared__ uint32_t keys[kWaves][P];
-    uint32_t *key = keys[threadIdx.x / kWave];
+    static_assert(kNbCap + kNbChunk == 4 * kWave, "row + chunk = 4 keys per lane");
     const int64_t w = wave_index();
     if (w >= nlong) return;
     const int lane = lane_id();
     const int32_t a = longq[w];
     const int64_t o = offsets[a];
     const int c = (int)(offsets[a + 1] - o);
-    const int32_t *chunk = pool + (int64_t)head[a] * kNbChunk;
-    const int logP = c <= P / 2 ? 7 : 8;
-    for (int i = lane; i < (1 << logP); i += kWave)
-        key[i] = i >= c ? 0xffffffffu : (uint32_t)(i < kNbCap ? slab[(int64_t)a * kNbCap + i] : chunk[i - kNbCap]);
-    tile_sync();
-    lds_network(key, logP, lane, kWave, [] { tile_sync(); });
-    for (int i = lane; i < c; i += kWave) ids[o + i] = (int32_t)key[i];
+    const int i0 = 4 * lane;
+    uint32_t v[4] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
+    if (i0 < c) {
+        const int4 q = i0 < kNbCap
+                           ? *reinterpret_cast<const int4 *>(slab + (int64_t)a * kNbCap + i0)
+                           : *reinterpret_cast<const int4 *>(pool + (int64_t)head[a] * kNbChunk + (i0 - kNbCap));
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + u >= c) v[u] = 0xffffffffu;
+    }
+    net_lanes<4>(v, lane);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (i0 + u < c) ids[o + i0 + u] = (int32_t)v[u];
 }
 
 // One workgroup per list searched again by the fill call: the same network
