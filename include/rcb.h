@@ -229,9 +229,11 @@ rcb_status rcb_neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, v
  * not depend on the tree (split rule, N_ll) that found it.
  *  offsets:  the array filled by rcb_neighbours_count() for this tree.
  *  ids:      device int32[capacity]; capacity >= total, else RCB_ECAPACITY.
- * The count call keeps up to 64 ids per particle in a scratch slab owned by
- * the tree (256 bytes per particle, freed with the interaction lists); the
- * cells holding a longer list are searched again here.
+ * The count call keeps each list in scratch owned by the tree (freed with
+ * the interaction lists): a 64-slot row per particle (256 bytes) and, for
+ * lists of up to 256, chunks of 64 slots from a pool of N/8 chunks (32 bytes
+ * per particle); the cells holding a list that fit neither are searched
+ * again here.
  */
 rcb_status rcb_neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids,
                                int64_t capacity, void *stream);

@@ -38,7 +38,8 @@ constexpr int kWaves = kBlock / kWave;
 // wave ends.
 constexpr int kSearchWaves = 1;
 constexpr int kNbCap = 64;        // slab slots per particle (~50 neighbours expected)
-constexpr int kNbChunk = 192;     // slots of an overflow chunk: lists of up to 256 ids
+constexpr int kNbChunk = 64;      // slots of an overflow chunk
+constexpr int kNbChunks = 3;      // chunks a list may take: lists of up to 256 ids
 constexpr int kLongLds = 4096;    // lists searched again: sorted in LDS up to this length
 constexpr int kRingMask = 2 * kWave - 1;
 constexpr int kRingBytes = 2 * kWave * 32;   // the ring of SrcN, in bytes
@@ -60,6 +61,7 @@ struct NeighArgs {
     const int64_t *offsets;   // fill mode: list starts (caller order)
     int32_t *ids;             // fill mode: final lists; slab mode: kNbCap slots per caller index
     int32_t *pool;            // slab mode: overflow chunks of kNbChunk slots
+    int32_t *longc;           // slab mode: the kNbChunks chunks of each entry of longq
     int64_t pool_cap;         // chunks in pool
     int32_t *head;            // per caller index: its chunk, or -1 for a list searched again
     int32_t *ctl;             // [0] lists searched again, [1] leaves queued, [2] chunks taken,
@@ -86,7 +88,7 @@ struct NeighShared {
     EntryChunk ec;
     SrcN tile[2 * kWave];
     int32_t cnt[kWave];
-    int32_t chunk[kWave];
+    int32_t chunk[kWave][kNbChunks];
 };
 
 // SLAB: ids go to slab row (caller index) while it has room, then to a chunk
@@ -144,27 +146,30 @@ __global__ __launch_bounds__(kSearchWaves * kWave) void k_neigh(NeighArgs a) {
             const double lim = has_sink ? two_h * two_h : -1.0;
             if (L.slice == 0) {
                 sh.cnt[L.sslot] = 0;
-                sh.chunk[L.sslot] = -1;
+#pragma unroll
+                for (int q = 0; q < kNbChunks; ++q) sh.chunk[L.sslot][q] = -1;
             }
             tile_sync();
             int head = 0;   // ring position of the first waiting source
             int32_t *const row = a.ids + obase;
             // hit h with slot r (0 for lanes without a hit): into the slab row, or
-            // (rare) the sink's chunk, which its first overflowing hit takes
+            // (rare) one of the sink's chunks, each taken by the hit of its first slot
             auto put = [&](bool h, uint32_t r, int32_t id) {
                 const bool low = !SLAB || r < (uint32_t)kNbCap;
                 if (h & low) row[r] = id;
                 if constexpr (SLAB) {
                     // lanes with r >= kNbCap, as the comparison's own lane mask
                     if (__builtin_amdgcn_uicmp(r, (uint32_t)kNbCap, kIcmpUge) != 0ull) {
-                        if (r == (uint32_t)kNbCap) {
+                        const uint32_t q = (r - kNbCap) / kNbChunk, o = (r - kNbCap) % kNbChunk;
+                        const bool kept = !low && q < (uint32_t)kNbChunks;
+                        if (kept && o == 0) {
                             const int32_t ch = atomicAdd(a.ctl + 2, 1);
-                            sh.chunk[L.sslot] = ch < a.pool_cap ? ch : -2;
+                            sh.chunk[L.sslot][q] = ch < a.pool_cap ? ch : -2;
                         }
                         tile_sync();
-                        if (!low && r < (uint32_t)(kNbCap + kNbChunk)) {
-                            const int32_t ch = sh.chunk[L.sslot];
-                            if (ch >= 0) a.pool[(int64_t)ch * kNbChunk + (r - kNbCap)] = id;
+                        if (kept) {
+                            const int32_t ch = sh.chunk[L.sslot][q];
+                            if (ch >= 0) a.pool[(int64_t)ch * kNbChunk + o] = id;
                         }
                         tile_sync();
                     }
@@ -257,10 +262,15 @@ __global__ __launch_bounds__(kSearchWaves * kWave) void k_neigh(NeighArgs a) {
                 const int cnt = sh.cnt[L.sslot];
                 a.counts[oa] = cnt;
                 if (cnt > kNbCap) {
-                    const int32_t ch = sh.chunk[L.sslot];
-                    if (ch >= 0 && cnt <= kNbCap + kNbChunk) {
-                        a.head[oa] = ch;
-                        a.longq[atomicAdd(a.ctl + 3, 1)] = oa;   // at most one per chunk
+                    const int need = (cnt - kNbCap + kNbChunk - 1) / kNbChunk;
+                    bool ok = need <= kNbChunks;
+                    for (int q = 0; ok && q < need; ++q) ok = sh.chunk[L.sslot][q] >= 0;
+                    if (ok) {   // at most one entry per chunk taken, so longq has room
+                        const int32_t e = atomicAdd(a.ctl + 3, 1);
+                        a.longq[e] = oa;
+#pragma unroll
+                        for (int q = 0; q < kNbChunks; ++q) a.longc[kNbChunks * e + q] = sh.chunk[L.sslot][q];
+                        a.head[oa] = e;
                     } else {
                         a.head[oa] = -1;
                         atomicAdd(a.ctl, 1);
@@ -457,16 +467,17 @@ __device__ __forceinline__ void net_lanes(uint32_t (&v)[U], int lane) {
     }
 }
 
-// Lists of kNbCap < c <= kNbCap + kNbChunk ids kept by the count call (row plus
-// one chunk): one wave per list, 4 keys per lane (16-byte loads: lanes 0-15
-// read the row, the others the chunk), sorted in registers.
+// Lists of kNbCap < c <= kNbCap + kNbChunks kNbChunk ids kept by the count
+// call (row plus chunks): one wave per list, 4 keys per lane (16-byte loads:
+// lanes 0-15 read the row, every further 16 lanes one chunk), sorted in
+// registers.
 __global__ __launch_bounds__(kBlock) void k_nb_compact_long(int32_t nlong, const int32_t *__restrict__ longq,
                                                             const int64_t *__restrict__ offsets,
                                                             const int32_t *__restrict__ slab,
-                                                            const int32_t *__restrict__ head,
+                                                            const int32_t *__restrict__ longc,
                                                             const int32_t *__restrict__ pool,
                                                             int32_t *__restrict__ ids) {
-    static_assert(kNbCap + kNbChunk == 4 * kWave, "row + chunk = 4 keys per lane");
+    static_assert(kNbCap + kNbChunks * kNbChunk == 4 * kWave, "row + chunks = 4 keys per lane");
     const int64_t w = wave_index();
     if (w >= nlong) return;
     const int lane = lane_id();
@@ -476,9 +487,11 @@ __global__ __launch_bounds__(kBlock) void k_nb_compact_long(int32_t nlong, const
     const int i0 = 4 * lane;
     uint32_t v[4] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
     if (i0 < c) {
-        const int4 q = i0 < kNbCap
-                           ? *reinterpret_cast<const int4 *>(slab + (int64_t)a * kNbCap + i0)
-                           : *reinterpret_cast<const int4 *>(pool + (int64_t)head[a] * kNbChunk + (i0 - kNbCap));
+        const int32_t *src = i0 < kNbCap
+                                 ? slab + (int64_t)a * kNbCap + i0
+                                 : pool + (int64_t)longc[kNbChunks * w + (i0 - kNbCap) / kNbChunk] * kNbChunk +
+                                       (i0 - kNbCap) % kNbChunk;
+        const int4 q = *reinterpret_cast<const int4 *>(src);
         v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -547,22 +560,25 @@ rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipSt
     rcb_status st = ensure_walk(t, s);
     if (st != RCB_OK) return st;
     if (!t->nb_slab) {
-        // one chunk for every 32nd particle: lists past 64 ids are a few percent
-        // at ~50 neighbours; the rest is searched again by the fill call
-        t->nb_pool_cap = t->n / 32 + 1;
+        // one 64-slot chunk for every 8th particle: lists past 64 ids are 3% (Plummer)
+        // to 8% (clumps) at ~50 neighbours on average; the rest is searched again by
+        // the fill call
+        t->nb_pool_cap = t->n / 8 + 1;
         t->nb_slab = (int32_t *)dalloc(t, sizeof(int32_t) * t->n * kNbCap, s, t->list_allocs);
         t->nb_pool = (int32_t *)dalloc(t, sizeof(int32_t) * t->nb_pool_cap * kNbChunk, s, t->list_allocs);
         t->nb_head = (int32_t *)dalloc(t, sizeof(int32_t) * t->n, s, t->list_allocs);
         t->nb_longq = (int32_t *)dalloc(t, sizeof(int32_t) * t->nb_pool_cap, s, t->list_allocs);
+        t->nb_longc = (int32_t *)dalloc(t, sizeof(int32_t) * kNbChunks * t->nb_pool_cap, s, t->list_allocs);
         t->nb_queue = (int32_t *)dalloc(t, sizeof(int32_t) * t->nleaf, s, t->list_allocs);
         t->nb_ctl = (int32_t *)dalloc(t, sizeof(int32_t) * 4, s, t->list_allocs);
-        if (!t->nb_slab || !t->nb_pool || !t->nb_head || !t->nb_longq || !t->nb_queue || !t->nb_ctl)
+        if (!t->nb_slab || !t->nb_pool || !t->nb_head || !t->nb_longq || !t->nb_longc || !t->nb_queue ||
+            !t->nb_ctl)
             return RCB_ENOMEM;
     }
     RCB_HIP(hipMemsetAsync(t->nb_ctl, 0, sizeof(int32_t) * 4, s));
     NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
                 t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, offsets, nullptr, t->nb_slab,
-                t->nb_pool, t->nb_pool_cap, t->nb_head, t->nb_ctl, t->nb_queue, t->nb_longq, 0};
+                t->nb_pool, t->nb_longc, t->nb_pool_cap, t->nb_head, t->nb_ctl, t->nb_queue, t->nb_longq, 0};
     const unsigned grid = (unsigned)((t->ngroup + kSearchWaves - 1) / kSearchWaves);
     k_neigh<true><<<grid, kSearchWaves * kWave, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_neigh<slab>");
@@ -595,7 +611,7 @@ rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, in
     RCB_LAUNCH_CHECK("k_nb_compact");
     if (t->nb_long > 0) {
         const unsigned gl = (unsigned)((t->nb_long + kWaves - 1) / kWaves);
-        k_nb_compact_long<<<gl, kBlock, 0, s>>>(t->nb_long, t->nb_longq, offsets, t->nb_slab, t->nb_head,
+        k_nb_compact_long<<<gl, kBlock, 0, s>>>(t->nb_long, t->nb_longq, offsets, t->nb_slab, t->nb_longc,
                                                 t->nb_pool, ids);
         RCB_LAUNCH_CHECK("k_nb_compact_long");
     }
@@ -607,7 +623,7 @@ rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, in
         RCB_HIP(hipMemsetAsync(ctl, 0, sizeof(int32_t), s));
         NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
                     t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids,
-                    nullptr, 0, t->nb_head, ctl, t->nb_queue, longq, t->nb_nq};
+                    nullptr, nullptr, 0, t->nb_head, ctl, t->nb_queue, longq, t->nb_nq};
         const unsigned grid = (unsigned)((t->nb_nq + kSearchWaves - 1) / kSearchWaves);
         k_neigh<false><<<grid, kSearchWaves * kWave, 0, s>>>(a);
         RCB_LAUNCH_CHECK("k_neigh<fill>");

@@ -731,7 +731,7 @@ void drop_lists(rcb_tree *t, hipStream_t s) {
     t->near_off = t->far_off = nullptr;
     t->near_list = t->far_list = nullptr;
     t->nb_total = -1;
-    t->nb_slab = t->nb_pool = t->nb_head = t->nb_longq = t->nb_queue = t->nb_ctl = nullptr;
+    t->nb_slab = t->nb_pool = t->nb_head = t->nb_longq = t->nb_longc = t->nb_queue = t->nb_ctl = nullptr;
     t->nb_pool_cap = 0;
     t->nb_over = t->nb_long = t->nb_nq = 0;
     t->walk_requeued = 0;

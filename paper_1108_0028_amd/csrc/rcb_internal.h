@@ -89,7 +89,8 @@ struct rcb_tree {
     int32_t *nb_slab = nullptr;        // neighbour ids of the count call, kNbCap per particle
     int32_t *nb_pool = nullptr;        // overflow chunks of the slab rows
     int32_t *nb_head = nullptr;        // per particle: its chunk (lists past the row)
-    int32_t *nb_longq = nullptr;       // particles whose list sits in row + chunk
+    int32_t *nb_longq = nullptr;       // particles whose list sits in row + chunks
+    int32_t *nb_longc = nullptr;       // the chunks of each nb_longq entry
     int32_t *nb_queue = nullptr;       // leaves holding a list that the fill call searches again
     int32_t *nb_ctl = nullptr;         // device counters of the count call
     int64_t nb_pool_cap = 0;           // chunks in nb_pool

@@ -217,7 +217,7 @@ def _direct(torch, P, m, h, sel, chunk=1 << 17):
 
 def scaling(a, np, torch, W, Tree, dev):
     print(f"| N | L | form | ms/step | build | walk | neighbours | gravity | particles/s | "
-          f"nb check | mean eps | max eps |\n|---:|---:|---|---:|---:|---:|---:|---:|---:|---|---:|---:|",
+          f"nb check | mean eps | max eps | B/particle |\n|---:|---:|---|---:|---:|---:|---:|---:|---:|---|---:|---:|---:|",
           flush=True)
     rng = np.random.default_rng(7)
     for n in [int(v) for v in a.sizes.split(",")]:
@@ -244,7 +244,14 @@ def scaling(a, np, torch, W, Tree, dev):
                 acc = t.gravity()
                 rec(4)
                 return t, off, ids, acc
+            from paper_1108_0028_amd import release_cache
+            torch.cuda.synchronize()
+            release_cache()
+            torch.cuda.empty_cache()
+            free0 = torch.cuda.mem_get_info()[0]
             t, off, ids, acc = step()            # warm-up; its outputs are checked
+            torch.cuda.synchronize()
+            mem = (free0 - torch.cuda.mem_get_info()[0]) / n   # device bytes per particle of a live step
             k = t.info()["k"]
             # neighbours of 32 sampled particles against an all-pairs search
             ok = True
@@ -254,7 +261,7 @@ def scaling(a, np, torch, W, Tree, dev):
                 lim = (2.0 * arrs[4][i]) ** 2
                 exact = torch.nonzero((d2 < lim) & (torch.arange(n, device=dev) != i)).flatten()
                 got = ids[off[i]:off[i + 1]].long()
-                ok &= bool(torch.equal(torch.sort(got).values, exact))
+                ok &= bool(torch.equal(got, exact))   # lists ascending by index
             am = torch.stack([v.double() for v in acc], 1)[sel]
             eps = ((am - ref).norm(dim=1) / ref.norm(dim=1)).cpu().numpy()
             t.destroy()
@@ -271,10 +278,11 @@ def scaling(a, np, torch, W, Tree, dev):
             med = np.median(np.array(rows), 0)
             row = {"n": n, "L": k, "form": prec, "ms_per_step": med[0] * 1e3, "build": med[1], "walk": med[2],
                    "neighbours": med[3], "gravity": med[4], "particles_per_s": n / med[0],
-                   "neighbours_match": ok, "mean_eps": float(eps.mean()), "max_eps": float(eps.max())}
+                   "neighbours_match": ok, "mean_eps": float(eps.mean()), "max_eps": float(eps.max()),
+                   "bytes_per_particle": mem}
             print(f"| {n} | {k} | {prec} | {row['ms_per_step']:.1f} | {med[1]:.1f} | {med[2]:.1f} | {med[3]:.1f} | "
                   f"{med[4]:.1f} | {row['particles_per_s']:.3g} | {'identical' if ok else 'DIFFER'} | "
-                  f"{row['mean_eps']:.2e} | {row['max_eps']:.2e} |", flush=True)
+                  f"{row['mean_eps']:.2e} | {row['max_eps']:.2e} | {mem:.0f} |", flush=True)
             print(json.dumps(row), flush=True)
         del arrs, P, ref
         torch.cuda.empty_cache()
