@@ -36,10 +36,12 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 __global__ __launch_bounds__(kBlock) void k_bounds_partial(const double *__restrict__ x,
                                                            const double *__restrict__ y,
                                                            const double *__restrict__ z, int64_t n,
-                                                           double *__restrict__ part) {
+                                                           double *__restrict__ part,
+                                                           int32_t *__restrict__ iota = nullptr) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
+        if (iota) iota[i] = (int32_t)i;   // the order of level 0
         double v[3] = {x[i], y[i], z[i]};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -71,10 +73,18 @@ __global__ __launch_bounds__(kBlock) void k_bounds_partial(const double *__restr
 
 // one block of 256 threads: per-thread minima / maxima over the partials,
 // then a tree over the block (min and max do not depend on the order)
+// Also sets the root's range and clears the nclr control words of clr.
 __global__ __launch_bounds__(256) void k_bounds_final(const double *__restrict__ part, int nb,
-                                                      double *__restrict__ nlo, double *__restrict__ nhi) {
+                                                      double *__restrict__ nlo, double *__restrict__ nhi,
+                                                      int32_t *__restrict__ nfirst, int32_t *__restrict__ ncount,
+                                                      int32_t n, int32_t *__restrict__ clr, int nclr) {
     __shared__ double red[6][256];
     const int t = threadIdx.x;
+    if (t == 0) {
+        nfirst[1] = 0;
+        ncount[1] = n;
+    }
+    for (int i = t; i < nclr; i += 256) clr[i] = 0;
     double r[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) r[d] = part[d];
@@ -120,11 +130,6 @@ __global__ void k_init(const double *__restrict__ x, const double *__restrict__ 
         om[i] = m[i];
         oid[i] = (int32_t)i;
     }
-}
-
-__global__ void k_set_root(int32_t *nfirst, int32_t *ncount, int32_t n) {
-    nfirst[1] = 0;
-    ncount[1] = n;
 }
 
 __global__ void k_gather_h(const double *__restrict__ h, const int32_t *__restrict__ id, int64_t n,
@@ -943,6 +948,8 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(PartIn in, const int32_
     scatter_chunk(in, id, out, base, end, o.naxis[lab], o.nplane[lab], node_tie(o, lab), s, nleft, lb, rb);
 }
 
+constexpr int64_t kUpwardOne = 256;   // levels of at most this many nodes: Eq. 2 in one workgroup
+
 // Eq. 2: parent quadrupole from the non-empty children, shifted by the
 // offset between the centres of mass.
 __global__ void k_upward(int lvl, NodeOut o) {
@@ -1195,6 +1202,7 @@ struct SubArgs {
     const int32_t *qctl;     // [0] roots queued
     int32_t *qhead;          // next root to take
     double *bx[2], *by[2], *bz[2], *bm[2];   // particle buffers by level parity
+    const double *x0, *y0, *z0, *m0;         // level 0: the caller's arrays
     int32_t *lvl_id;
     const double *h;         // the caller's smoothing lengths (caller order)
     double *ph;              // h in tree order, written for the subtree's particles
@@ -1475,6 +1483,61 @@ __device__ __forceinline__ void sub_pass(const NodeOut o, int k, const double *_
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
+// The next subtree root of a wave, fetched in four stages while the wave
+// builds the current one, so that each stage's memory latency hides under a
+// level of the current build: 0 takes a queue slot, 1 reads its label, 2 the
+// root's range and box, 3 issues the loads of its particles (lane l holds
+// elements l + 64 q), which the wave puts into LDS when it starts the root.
+constexpr int kSubPer = kSubMax / kWave;
+struct SubNext {
+    int rv;          // lane 0: the queue slot from the atomic
+    int r;           // the queue slot (uniform)
+    int64_t R0, s0;
+    int c0;
+    double lo[3], hi[3];
+    double vx[kSubPer], vy[kSubPer], vz[kSubPer], vm[kSubPer];
+    int32_t vi[kSubPer];
+};
+
+__device__ __forceinline__ void next_root_stage(const SubArgs &a, int nq, int stage, SubNext &nx) {
+    const int lane = lane_id();
+    if (stage == 0) {
+        nx.rv = 0;
+        if (lane == 0) nx.rv = atomicAdd(a.qhead, 1);
+    } else if (stage == 1) {
+        nx.r = __builtin_amdgcn_readlane(nx.rv, 0);
+        nx.R0 = nx.r < nq ? a.roots[nx.r] : 1;
+    } else if (stage == 2) {
+        if (nx.r >= nq) return;
+        const int64_t R0 = nx.R0;
+        nx.s0 = a.o.nfirst[R0];
+        nx.c0 = a.o.ncount[R0];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            nx.lo[q] = a.o.nlo[3 * R0 + q];
+            nx.hi[q] = a.o.nhi[3 * R0 + q];
+        }
+    } else {
+        if (nx.r >= nq || nx.c0 == 0) return;
+        const int l0 = 63 - __clzll((unsigned long long)nx.R0);
+        const bool par = l0 & 1;   // buffers chosen by select, not by a dynamic index
+        const bool top = l0 == 0;
+        const double *ix = top ? a.x0 : (par ? a.bx[1] : a.bx[0]), *iy = top ? a.y0 : (par ? a.by[1] : a.by[0]);
+        const double *iz = top ? a.z0 : (par ? a.bz[1] : a.bz[0]), *im = top ? a.m0 : (par ? a.bm[1] : a.bm[0]);
+        const int32_t *idl = a.lvl_id + (int64_t)l0 * a.n;
+#pragma unroll
+        for (int q = 0; q < kSubPer; ++q) {
+            const int i = lane + kWave * q;
+            const int64_t src = nx.s0 + (i < nx.c0 ? i : 0);
+            nx.vx[q] = ix[src];
+            nx.vy[q] = iy[src];
+            nx.vz[q] = iz[src];
+            nx.vm[q] = im[src];
+            nx.vi[q] = idl[src];
+        }
+    }
+}
+
 __global__ __launch_bounds__(kWave) void k_subtree(SubArgs a, float *fdx, float *fdy, float *fdz, float *fm,
                                                       float *fh) {
     __shared__ SubLds sh;
@@ -1486,56 +1549,40 @@ __global__ __launch_bounds__(kWave) void k_subtree(SubArgs a, float *fdx, float 
     const bool kp = k & 1;
     double *ox = kp ? a.bx[1] : a.bx[0], *oy = kp ? a.by[1] : a.by[0];
     double *oz = kp ? a.bz[1] : a.bz[0], *om = kp ? a.bm[1] : a.bm[0];
+    const int nq = a.qctl[0];
+    SubNext nx;
+    for (int st = 0; st < 4; ++st) next_root_stage(a, nq, st, nx);   // the first root
     for (;;) {
-        int r = 0;
-        if (lane == 0) r = atomicAdd(a.qhead, 1);
-        r = __builtin_amdgcn_readfirstlane(__shfl(r, 0, kWave));
-        if (r >= a.qctl[0]) break;
-        const int64_t R0 = a.roots[r];
+        if (nx.r >= nq) break;
+        const int64_t R0 = nx.R0;
         const int l0 = 63 - __clzll((unsigned long long)R0);
-        const int64_t s0 = o.nfirst[R0];
-        const int c0 = o.ncount[R0];
+        const int64_t s0 = nx.s0;
+        const int c0 = nx.c0;
         double rlo[3], rhi[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            rlo[q] = o.nlo[3 * R0 + q];
-            rhi[q] = o.nhi[3 * R0 + q];
+            rlo[q] = nx.lo[q];
+            rhi[q] = nx.hi[q];
         }
         if (c0 == 0) {   // an empty root (at any depth): its whole subtree
             fill_empty_subtree(o, R0, l0, k, (int32_t)s0, rlo, rhi);
+            for (int st = 0; st < 4; ++st) next_root_stage(a, nq, st, nx);
             continue;
         }
-        const bool par = l0 & 1;   // buffers chosen by select, not by a dynamic index
-        const double *ix = par ? a.bx[1] : a.bx[0], *iy = par ? a.by[1] : a.by[0];
-        const double *iz = par ? a.bz[1] : a.bz[0], *im = par ? a.bm[1] : a.bm[0];
-        {   // every load of the root's particles issued before the first LDS store
-            constexpr int kPer = kSubMax / kWave;
-            double vx[kPer], vy[kPer], vz[kPer], vm[kPer];
-            int32_t vi[kPer];
-            const int32_t *idl = a.lvl_id + (int64_t)l0 * a.n;
 #pragma unroll
-            for (int q = 0; q < kPer; ++q) {
-                const int i = lane + kWave * q;
-                const int64_t src = s0 + (i < c0 ? i : 0);
-                vx[q] = ix[src];
-                vy[q] = iy[src];
-                vz[q] = iz[src];
-                vm[q] = im[src];
-                vi[q] = idl[src];
-            }
-#pragma unroll
-            for (int q = 0; q < kPer; ++q) {
-                const int i = lane + kWave * q;
-                if (i < c0) {
-                    const int sl = stage_slot(i);
-                    sh.x[sl] = vx[q];
-                    sh.y[sl] = vy[q];
-                    sh.z[sl] = vz[q];
-                    sh.m[sl] = vm[q];
-                    sh.id[sl] = vi[q];
-                }
+        for (int q = 0; q < kSubPer; ++q) {   // the root's particles, loaded while the last root was built
+            const int i = lane + kWave * q;
+            if (i < c0) {
+                const int sl = stage_slot(i);
+                sh.x[sl] = nx.vx[q];
+                sh.y[sl] = nx.vy[q];
+                sh.z[sl] = nx.vz[q];
+                sh.m[sl] = nx.vm[q];
+                sh.id[sl] = nx.vi[q];
             }
         }
+        int nst = 0;   // the next root's fetch: one stage now, one after each level's passes
+        next_root_stage(a, nq, nst++, nx);
         if (lane == 0) {
             sh.first[0] = 0;
             sh.count[0] = c0;
@@ -1582,11 +1629,13 @@ __global__ __launch_bounds__(kWave) void k_subtree(SubArgs a, float *fdx, float 
             }
             for (int p = 0; p < nd; p += npg)
                 sub_pass(o, k, hin, ph, sh, R0, d, p, lvl, s0, f0, fdy, fdz, fm, fh, gw);
+            if (nst < 4) next_root_stage(a, nq, nst++, nx);
             if (lvl == k) break;
             // this level's partition is complete: the next level's order
             for (int i = lane; i < c0; i += kWave)
                 a.lvl_id[(int64_t)(lvl + 1) * a.n + s0 + i] = sh.id[stage_slot(i)];
         }
+        while (nst < 4) next_root_stage(a, nq, nst++, nx);
         // final particle arrays (level k order)
         for (int i = lane; i < c0; i += kWave) {
             const int sl = stage_slot(i);
@@ -1660,6 +1709,38 @@ __global__ void k_upward_big(int lvl, int k, NodeOut o) {
     for (int q = 0; q < 6; ++q) o.nQ[6 * lab + q] = acc[q];
 }
 
+// k_upward_big for the levels top .. 0 in one launch: one workgroup, the
+// levels in turn (a level reads only the one below it, written before the
+// barrier by this workgroup)
+__global__ __launch_bounds__(1024) void k_upward_levels(int top, int k, NodeOut o) {
+    for (int lvl = top; lvl >= 0; --lvl) {
+        const int64_t nodes = (int64_t)1 << lvl;
+        for (int64_t i = threadIdx.x; i < nodes; i += blockDim.x) {
+            const int64_t lab = nodes + i;
+            if (!is_big(o.ncount[lab], k, lvl)) continue;
+            const double pc[3] = {o.ncom[3 * lab], o.ncom[3 * lab + 1], o.ncom[3 * lab + 2]};
+            double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int ch = 0; ch < 2; ++ch) {
+                const int64_t C = 2 * lab + ch;
+                if (o.ncount[C] == 0) continue;
+                const double dx[3] = {o.ncom[3 * C] - pc[0], o.ncom[3 * C + 1] - pc[1], o.ncom[3 * C + 2] - pc[2]};
+                const double r2 = (dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2];
+                const double MC = o.nM[C];
+                const double m3 = 3.0 * MC;
+                const double mr2 = MC * r2;
+                acc[0] += (o.nQ[6 * C + 0] + (m3 * dx[0]) * dx[0]) - mr2;
+                acc[1] += o.nQ[6 * C + 1] + (m3 * dx[0]) * dx[1];
+                acc[2] += o.nQ[6 * C + 2] + (m3 * dx[0]) * dx[2];
+                acc[3] += (o.nQ[6 * C + 3] + (m3 * dx[1]) * dx[1]) - mr2;
+                acc[4] += o.nQ[6 * C + 4] + (m3 * dx[1]) * dx[2];
+                acc[5] += (o.nQ[6 * C + 5] + (m3 * dx[2]) * dx[2]) - mr2;
+            }
+            for (int q = 0; q < 6; ++q) o.nQ[6 * lab + q] = acc[q];
+        }
+        __syncthreads();
+    }
+}
+
 // h in tree order for the big leaves (their order at level k is final);
 // the subtree waves write it for their own particles
 __global__ __launch_bounds__(kBlock) void k_gather_h_big(const double *__restrict__ h,
@@ -1674,6 +1755,32 @@ __global__ __launch_bounds__(kBlock) void k_gather_h_big(const double *__restric
     const int64_t base = s + j * kChunk;
     const int64_t end = min(base + kChunk, s + c);
     for (int64_t i = base + lane_id(); i < end; i += kWave) ph[i] = h[id[i]];
+}
+
+// k_mixed_prep for the big leaves only (the subtree waves write the FP32
+// arrays of their own leaves), one wave per chunk of a big leaf
+__global__ __launch_bounds__(kBlock) void k_mixed_big(NodeOut o, BigCtl bc, const double *__restrict__ px,
+                                                      const double *__restrict__ py, const double *__restrict__ pz,
+                                                      const double *__restrict__ pm, const double *__restrict__ ph,
+                                                      float *__restrict__ fdx, float *__restrict__ fdy,
+                                                      float *__restrict__ fdz, float *__restrict__ fm,
+                                                      float *__restrict__ fh) {
+    const int64_t w = wave_index();
+    if (w >= bc.ctl[1]) return;
+    const int bi = bc.item_big[w];
+    const int64_t lab = bc.big_node[bi];
+    const int64_t j = w - bc.big_base[bi];
+    const int64_t s = o.nfirst[lab], c = o.ncount[lab];
+    const int64_t base = s + j * kChunk;
+    const int64_t end = min(base + kChunk, s + c);
+    const double cx = o.ncom[3 * lab], cy = o.ncom[3 * lab + 1], cz = o.ncom[3 * lab + 2];
+    for (int64_t i = base + lane_id(); i < end; i += kWave) {
+        fdx[i] = (float)(px[i] - cx);
+        fdy[i] = (float)(py[i] - cy);
+        fdz[i] = (float)(pz[i] - cz);
+        fm[i] = (float)pm[i];
+        fh[i] = (float)ph[i];
+    }
 }
 
 
@@ -1972,6 +2079,18 @@ static inline bool is_big_host(int64_t c, int k, int lvl) {
 static rcb_status finish_build(rcb_tree *t, BuildScratch &b, const NodeOut &o, Scratch &tmp, int cur,
                                hipStream_t s);
 
+// The mixed form's FP32 particle arrays (tree-owned)
+static rcb_status alloc_mixed(rcb_tree *t, hipStream_t s) {
+    const size_t bytes = sizeof(float) * t->n;
+    t->fdx = (float *)dalloc(t, bytes, s, t->allocs);
+    t->fdy = (float *)dalloc(t, bytes, s, t->allocs);
+    t->fdz = (float *)dalloc(t, bytes, s, t->allocs);
+    t->fm = (float *)dalloc(t, bytes, s, t->allocs);
+    t->fh = (float *)dalloc(t, bytes, s, t->allocs);
+    if (!t->fdx || !t->fdy || !t->fdz || !t->fm || !t->fh) return RCB_ENOMEM;
+    return RCB_OK;
+}
+
 rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const double *z,
                       const double *m, const double *h, hipStream_t s) {
     const int64_t n = t->n;
@@ -2034,17 +2153,52 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         }
     }
     const unsigned gN = (unsigned)std::min<int64_t>(4096, (n + kBlock - 1) / kBlock);
-    k_init<<<gN, kBlock, 0, s>>>(x, y, z, m, n, b.x[0], b.y[0], b.z[0], b.m[0], t->lvl_id);
-    RCB_LAUNCH_CHECK("k_init");
-    k_bounds_partial<<<nbp, kBlock, 0, s>>>(x, y, z, n, b.bounds);
-    RCB_LAUNCH_CHECK("k_bounds_partial");
-    k_bounds_final<<<1, 256, 0, s>>>(b.bounds, nbp, t->nlo, t->nhi);
-    RCB_LAUNCH_CHECK("k_bounds_final");
-    k_set_root<<<1, 1, 0, s>>>(t->nfirst, t->ncount, (int32_t)n);
-    RCB_LAUNCH_CHECK("k_set_root");
     // median split: planes and ties per label, radix-select state for the
     // levels whose nodes exceed kSelSmall (at most n / kSelSmall nodes)
     const bool median = t->p.split == RCB_SPLIT_MEDIAN;
+    // splits through a centre (mass or number): big nodes level by level,
+    // then every subtree of at most kSubMax particles by one wave; level 0
+    // reads the caller's arrays, whose order is the identity
+    const bool fused = !median && getenv("RCB_BUILD_LEVELS") == nullptr;
+    // control words cleared by k_bounds_final: the roots queue (2), and the
+    // big-node control blocks of even and odd levels (4 each)
+    int32_t *clr = (int32_t *)A(sizeof(int32_t) * 16, tmp);
+    if (!clr) return RCB_ENOMEM;
+    int32_t *qctl = clr;   // [0] roots queued, [1] next root to take
+    int32_t *roots = nullptr, *bn2 = nullptr, *bb2 = nullptr, *ib2 = nullptr, *dcnt = nullptr;
+    // the host learns each level's number of big nodes and chunks from a
+    // small copy made while that level's parent is still partitioning, so
+    // every pass is launched with its exact size and the loop stops at the
+    // first level without big nodes (coherent host memory, kept for the
+    // thread's later builds)
+    static thread_local int32_t *hcnt = nullptr;
+    if (fused) {   // (everything allocated before the first launch)
+        roots = (int32_t *)A(sizeof(int32_t) * t->nleaf, tmp);
+        bn2 = (int32_t *)A(sizeof(int32_t) * b.max_big, tmp);
+        bb2 = (int32_t *)A(sizeof(int32_t) * b.max_big, tmp);
+        ib2 = (int32_t *)A(sizeof(int32_t) * b.max_items, tmp);
+        if (!roots || !bn2 || !bb2 || !ib2) return RCB_ENOMEM;
+        if (t->p.precision == RCB_MIXED) {   // written by the subtree waves
+            rcb_status st = alloc_mixed(t, s);
+            if (st != RCB_OK) return st;
+        }
+        if (!hcnt) {
+            if (hipHostMalloc((void **)&hcnt, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+                hcnt = nullptr;
+                return hip_fail(hipErrorOutOfMemory, "hipHostMalloc(level counts)");
+            }
+            hcnt[0] = 0;
+        }
+        RCB_HIP(hipHostGetDevicePointer((void **)&dcnt, hcnt, 0));   // as seen by the device
+    }
+    if (!fused) {
+        k_init<<<gN, kBlock, 0, s>>>(x, y, z, m, n, b.x[0], b.y[0], b.z[0], b.m[0], t->lvl_id);
+        RCB_LAUNCH_CHECK("k_init");
+    }
+    k_bounds_partial<<<nbp, kBlock, 0, s>>>(x, y, z, n, b.bounds, fused ? t->lvl_id : nullptr);
+    RCB_LAUNCH_CHECK("k_bounds_partial");
+    k_bounds_final<<<1, 256, 0, s>>>(b.bounds, nbp, t->nlo, t->nhi, t->nfirst, t->ncount, (int32_t)n, clr, 16);
+    RCB_LAUNCH_CHECK("k_bounds_final");
     double *mplane = nullptr;
     int32_t *mtie = nullptr;
     MedSel ms{};
@@ -2064,38 +2218,10 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     NodeOut o{t->nfirst, t->ncount, t->nlo, t->nhi, t->ncom, t->nM, t->nhint, t->nhnode, t->nQ,
               b.naxis, b.nplane, mplane, mtie};
     BigCtl bc{b.ctl, b.big_node, b.big_base, b.item_big};
-    // splits through a centre (mass or number): big nodes level by level,
-    // then every subtree of at most kSubMax particles by one wave
-    const bool fused = !median && getenv("RCB_BUILD_LEVELS") == nullptr;
     if (fused) {
-        int32_t *roots = (int32_t *)A(sizeof(int32_t) * t->nleaf, tmp);
-        int32_t *qctl = (int32_t *)A(sizeof(int32_t) * 2, tmp);
         // the control blocks and big-node lists alternate between levels: a
         // level's lists are read by its passes while the next level's are made
-        int32_t *ctl2 = (int32_t *)A(sizeof(int32_t) * 4, tmp);
-        int32_t *bn2 = (int32_t *)A(sizeof(int32_t) * b.max_big, tmp);
-        int32_t *bb2 = (int32_t *)A(sizeof(int32_t) * b.max_big, tmp);
-        int32_t *ib2 = (int32_t *)A(sizeof(int32_t) * b.max_items, tmp);
-        if (!roots || !qctl || !ctl2 || !bn2 || !bb2 || !ib2) return RCB_ENOMEM;
-        const BigCtl bcs[2] = {bc, BigCtl{ctl2, bn2, bb2, ib2}};
-        RCB_HIP(hipMemsetAsync(qctl, 0, sizeof(int32_t) * 2, s));
-        RCB_HIP(hipMemsetAsync(b.ctl, 0, sizeof(int32_t) * 4, s));
-        RCB_HIP(hipMemsetAsync(ctl2, 0, sizeof(int32_t) * 4, s));
-        // the host learns each level's number of big nodes and chunks from a
-        // small copy made while that level's parent is still partitioning, so
-        // every pass is launched with its exact size and the loop stops at
-        // the first level without big nodes
-        // (coherent host memory, kept for the thread's later builds)
-        static thread_local int32_t *hcnt = nullptr;
-        if (!hcnt) {
-            if (hipHostMalloc((void **)&hcnt, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
-                hcnt = nullptr;
-                return hip_fail(hipErrorOutOfMemory, "hipHostMalloc(level counts)");
-            }
-            hcnt[0] = 0;
-        }
-        int32_t *dcnt = nullptr;   // the same memory as seen by the device
-        RCB_HIP(hipHostGetDevicePointer((void **)&dcnt, hcnt, 0));
+        const BigCtl bcs[2] = {BigCtl{clr + 2, b.big_node, b.big_base, b.item_big}, BigCtl{clr + 6, bn2, bb2, ib2}};
         k_level_classify<<<1, kBlock, 0, s>>>(0, t->k, o, bcs[0], roots, qctl, (int)b.max_big, (int)b.max_items,
                                               t->dflag + 5);
         RCB_LAUNCH_CHECK("k_level_classify");
@@ -2105,7 +2231,8 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         for (int lvl = 0; lvl <= t->k && nbig > 0; ++lvl) {
             const bool leaf = lvl == t->k;
             const BigCtl &bl = bcs[lvl & 1], &bnx = bcs[(lvl + 1) & 1];
-            PartIn in{b.x[cur], b.y[cur], b.z[cur], b.m[cur], t->ph};
+            // level 0 reads the caller's arrays (its order is the identity)
+            const PartIn in = lvl == 0 ? PartIn{x, y, z, m, t->ph} : PartIn{b.x[cur], b.y[cur], b.z[cur], b.m[cur], t->ph};
             int32_t *id_next = leaf ? nullptr : t->lvl_id + (int64_t)(lvl + 1) * n;
             PartOut out{b.x[cur ^ 1], b.y[cur ^ 1], b.z[cur ^ 1], b.m[cur ^ 1], id_next};
             const int32_t *id_cur = t->lvl_id + (int64_t)lvl * n;
@@ -2152,14 +2279,33 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         // order there, as the last scatter of the big nodes did
         cur = t->k & 1;
         SubArgs sa{t->k, n, roots, qctl, qctl + 1, {b.x[0], b.x[1]}, {b.y[0], b.y[1]}, {b.z[0], b.z[1]},
-                   {b.m[0], b.m[1]}, t->lvl_id, h, t->ph, o};
+                   {b.m[0], b.m[1]}, x, y, z, m, t->lvl_id, h, t->ph, o};
+        // mixed form: the subtree waves write the FP32 leaf-frame arrays of
+        // their leaves as they finish them, k_mixed_big those of big leaves
+        const bool mixed = t->p.precision == RCB_MIXED;
+        if (mixed) {
+            if (last_big == t->k) {
+                const BigCtl &bl = bcs[t->k & 1];
+                k_mixed_big<<<blocks_for_waves(nitems), kBlock, 0, s>>>(o, bl, b.x[cur], b.y[cur], b.z[cur],
+                                                                      b.m[cur], t->ph, t->fdx, t->fdy, t->fdz,
+                                                                      t->fm, t->fh);
+                RCB_LAUNCH_CHECK("k_mixed_big");
+            }
+        }
         const unsigned gsub = (unsigned)std::min<int64_t>(2048, t->nleaf);
-        k_subtree<<<gsub, kWave, 0, s>>>(sa, nullptr, nullptr, nullptr, nullptr, nullptr);
+        k_subtree<<<gsub, kWave, 0, s>>>(sa, t->fdx, t->fdy, t->fdz, t->fm, t->fh);
         RCB_LAUNCH_CHECK("k_subtree");
-        for (int lvl = std::min(last_big, t->k - 1); lvl >= 0; --lvl) {
+        // Eq. 2 for the big nodes: the wide levels one launch each, the
+        // levels of at most kUpwardOne nodes in one workgroup
+        int lvl = std::min(last_big, t->k - 1);
+        for (; lvl >= 0 && ((int64_t)1 << lvl) > kUpwardOne; --lvl) {
             const int64_t nodes = (int64_t)1 << lvl;
             k_upward_big<<<(unsigned)((nodes + 255) / 256), 256, 0, s>>>(lvl, t->k, o);
             RCB_LAUNCH_CHECK("k_upward_big");
+        }
+        if (lvl >= 0) {
+            k_upward_levels<<<1, 1024, 0, s>>>(lvl, t->k, o);
+            RCB_LAUNCH_CHECK("k_upward_levels");
         }
         return finish_build(t, b, o, tmp, cur, s);
     }
@@ -2225,13 +2371,9 @@ static rcb_status finish_build(rcb_tree *t, BuildScratch &b, const NodeOut &o, S
         t->allocs.push_back(p);
         tmp.keep(p);
     }
-    if (t->p.precision == RCB_MIXED) {
-        t->fdx = (float *)A(sizeof(float) * n, t->allocs);
-        t->fdy = (float *)A(sizeof(float) * n, t->allocs);
-        t->fdz = (float *)A(sizeof(float) * n, t->allocs);
-        t->fm = (float *)A(sizeof(float) * n, t->allocs);
-        t->fh = (float *)A(sizeof(float) * n, t->allocs);
-        if (!t->fdx || !t->fdy || !t->fdz || !t->fm || !t->fh) return RCB_ENOMEM;
+    if (t->p.precision == RCB_MIXED && !t->fdx) {   // (the fused build wrote them already)
+        rcb_status st = alloc_mixed(t, s);
+        if (st != RCB_OK) return st;
         k_mixed_prep<<<blocks_for_waves((t->nleaf + 7) / 8), kBlock, 0, s>>>(
             t->nleaf, t->nfirst, t->ncount, t->ncom, t->px, t->py, t->pz, t->pm, t->ph, t->fdx,
             t->fdy, t->fdz, t->fm, t->fh);
