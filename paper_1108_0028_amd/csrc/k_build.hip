@@ -785,14 +785,18 @@ __global__ __launch_bounds__(kBlock) void k_chunk_reduce(PartIn in, NodeOut o, B
 // right); the wave results are then merged pairwise. Every step combines
 // aligned neighbours, so the result is the canonical pairwise sum.
 constexpr int kFinWaves = 16;
+constexpr int kFinOneMax = 4 * kWave;
+constexpr int kReportSlots = 64;   // level reports, one per level (more than any depth)
 
-template <int P>
-__global__ __launch_bounds__(kFinWaves * kWave) void k_big_finalize(int leaf_level, int split, NodeOut o,
-                                                                    BigCtl bc,
-                                                                    const double *__restrict__ part) {
+// FW = kFinWaves, or 1 (one wave per node) on the levels whose big nodes are
+// many and of at most a few groups.
+template <int P, int FW = kFinWaves>
+__global__ __launch_bounds__(FW * kWave) void k_big_finalize(int leaf_level, int split, NodeOut o,
+                                                             BigCtl bc,
+                                                             const double *__restrict__ part) {
     constexpr int NS = Pay<P>::NS;
-    __shared__ double stk[kFinWaves][32][NS];
-    __shared__ double res[kFinWaves][NS + 1];
+    __shared__ double stk[FW][32][NS];
+    __shared__ double res[FW][NS + 1];
     const int wv = threadIdx.x / kWave;
     const int64_t bi = blockIdx.x;
     if (bi >= bc.ctl[0]) return;
@@ -803,8 +807,8 @@ __global__ __launch_bounds__(kFinWaves * kWave) void k_big_finalize(int leaf_lev
     const int64_t ngroups = (nch + kWave - 1) / kWave;
     int64_t gp = 1;
     while (gp < ngroups) gp <<= 1;
-    const int64_t per = gp >= kFinWaves ? gp / kFinWaves : 1;   // groups per wave
-    const int active = gp >= kFinWaves ? kFinWaves : (int)gp;
+    const int64_t per = gp >= FW ? gp / FW : 1;   // groups per wave
+    const int active = gp >= FW ? FW : (int)gp;
     if (wv < active) {
         double mx = -1.0;
         for (int64_t k = 0; k < per; ++k) {
@@ -893,9 +897,10 @@ __global__ __launch_bounds__(kBlock) void k_part_count(PartIn in, const int32_t 
 // exclusive offsets of a big node's chunk left-counts, one block of
 // kFinWaves waves per big node: each wave scans a contiguous run of chunks
 // after an exclusive scan of the waves' totals
-__global__ __launch_bounds__(kFinWaves * kWave) void k_part_scan(NodeOut o, BigCtl bc,
-                                                                 int32_t *__restrict__ part_left) {
-    __shared__ int64_t tot[kFinWaves];
+template <int FW = kFinWaves>
+__global__ __launch_bounds__(FW * kWave) void k_part_scan(NodeOut o, BigCtl bc,
+                                                          int32_t *__restrict__ part_left) {
+    __shared__ int64_t tot[FW];
     const int wv = threadIdx.x / kWave;
     const int64_t bi = blockIdx.x;
     if (bi >= bc.ctl[0]) return;
@@ -903,7 +908,7 @@ __global__ __launch_bounds__(kFinWaves * kWave) void k_part_scan(NodeOut o, BigC
     const int64_t base = bc.big_base[bi];
     const int64_t s = o.nfirst[lab], c = o.ncount[lab];
     const int64_t nch = (c + kChunk - 1) / kChunk;
-    const int64_t seg = (nch + kFinWaves - 1) / kFinWaves;
+    const int64_t seg = (nch + FW - 1) / FW;
     const int64_t c0 = wv * seg, c1 = min(nch, c0 + seg);
     int64_t mine = 0;
     for (int64_t g0 = c0; g0 < c1; g0 += kWave) {
@@ -921,9 +926,9 @@ __global__ __launch_bounds__(kFinWaves * kWave) void k_part_scan(NodeOut o, BigC
         if (j < c1) part_left[base + j] = (int32_t)(run + e);
         run += wave_sum_i(v);
     }
-    if (wv == kFinWaves - 1 && lane_id() == 0) {
+    if (wv == FW - 1 && lane_id() == 0) {
         int64_t all = 0;
-        for (int w = 0; w < kFinWaves; ++w) all += tot[w];
+        for (int w = 0; w < FW; ++w) all += tot[w];
         o.nfirst[2 * lab] = (int32_t)s;
         o.ncount[2 * lab] = (int32_t)all;
         o.nfirst[2 * lab + 1] = (int32_t)(s + all);
@@ -1149,22 +1154,38 @@ __global__ __launch_bounds__(kBlock) void k_classify_children(int lvl, int k, No
     const int64_t w = wave_index();
     const int lane = lane_id();
     const int64_t t = w * kWave + lane;
-    const bool valid = t < 2 * (int64_t)nparent;
+    // nparent bounds the parents (the grid may be sized before their count is known)
+    const int np = min(nparent, bp.ctl[0]);
+    const bool valid = t < 2 * (int64_t)np;
     const int64_t lab = valid ? 2 * (int64_t)bp.big_node[t >> 1] + (t & 1) : 0;
     const int32_t c = valid ? o.ncount[lab] : 0;
     const bool big = valid && is_big(c, k, lvl);
     const bool root = valid && !big;
     const uint64_t br = ballot(root);
-    int rbase = 0;
-    if (lane == 0 && br) rbase = atomicAdd(nroots, __popcll(br));
+    // one atomic per wave and counter: the roots, the big nodes and their
+    // chunks (ranks and offsets inside the wave from its ballot and scan)
+    const uint64_t bg = ballot(big);
+    const int nch = big ? (c + kChunk - 1) / kChunk : 0;
+    const int cex = wave_excl_scan(nch);
+    const int ctot = __shfl(cex + nch, kWave - 1, kWave);
+    int mc = nch;   // the level's largest big node, in chunks
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) mc = max(mc, __shfl_xor(mc, off, kWave));
+    int rbase = 0, bbase = 0, ibase = 0;
+    if (lane == 0) {
+        if (br) rbase = atomicAdd(nroots, __popcll(br));
+        if (bg) {
+            bbase = atomicAdd(&bn.ctl[0], __popcll(bg));
+            ibase = atomicAdd(&bn.ctl[1], ctot);
+            atomicMax(&bn.ctl[3], mc);
+        }
+    }
     rbase = __shfl(rbase, 0, kWave);
     if (root) roots[rbase + rank_below(br)] = (int32_t)lab;
-    int nch = 0, bi = 0, base = 0;
+    const int bi = __shfl(bbase, 0, kWave) + rank_below(bg);
+    const int base = __shfl(ibase, 0, kWave) + cex;
     bool big_ok = big;
     if (big) {
-        nch = (c + kChunk - 1) / kChunk;
-        bi = atomicAdd(&bn.ctl[0], 1);
-        base = atomicAdd(&bn.ctl[1], nch);
         big_ok = bi < max_big && base + nch <= max_items;   // sized on the host; never exceeded
         if (big_ok) {
             bn.big_node[bi] = (int32_t)lab;
@@ -1188,6 +1209,7 @@ __global__ __launch_bounds__(kBlock) void k_classify_children(int lvl, int k, No
             __threadfence();
             report[1] = atomicAdd(&bn.ctl[0], 0);
             report[2] = atomicAdd(&bn.ctl[1], 0);
+            report[3] = atomicAdd(&bn.ctl[3], 0);
             __threadfence_system();
             report[0] = seq;
             __threadfence_system();
@@ -2039,7 +2061,7 @@ static rcb_status big_chain(rcb_tree *t, BuildScratch &b, const NodeOut &o, cons
     } else if (split) {
         k_part_count<<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, id, o, bc, b.part_left);
         RCB_LAUNCH_CHECK("k_part_count");
-        k_part_scan<<<(unsigned)bw, kFinWaves * kWave, 0, s>>>(o, bc, b.part_left);
+        k_part_scan<><<<(unsigned)bw, kFinWaves * kWave, 0, s>>>(o, bc, b.part_left);
         RCB_LAUNCH_CHECK("k_part_scan");
         k_part_scatter<<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, id, out, o, bc,
                                                                        b.part_left);
@@ -2057,7 +2079,9 @@ static rcb_status wait_report(int32_t *hcnt, int32_t seq, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     for (uint64_t spin = 0;; ++spin) {
         if (__atomic_load_n(&hcnt[0], __ATOMIC_ACQUIRE) == seq) return RCB_OK;
-        if ((spin & 1023) == 1023) {
+        // the stream is queried only once the wait is long (a query puts a
+        // marker into the queue, which stalls the device between kernels)
+        if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
             const hipError_t q = hipStreamQuery(s);
             if (q != hipSuccess && q != hipErrorNotReady) return hip_fail(q, "build: level pass");
             if (q == hipSuccess && __atomic_load_n(&hcnt[0], __ATOMIC_ACQUIRE) != seq) {
@@ -2166,11 +2190,11 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     if (!clr) return RCB_ENOMEM;
     int32_t *qctl = clr;   // [0] roots queued, [1] next root to take
     int32_t *roots = nullptr, *bn2 = nullptr, *bb2 = nullptr, *ib2 = nullptr, *dcnt = nullptr;
-    // the host learns each level's number of big nodes and chunks from a
-    // small copy made while that level's parent is still partitioning, so
-    // every pass is launched with its exact size and the loop stops at the
-    // first level without big nodes (coherent host memory, kept for the
-    // thread's later builds)
+    // the host learns each level's number of big nodes, chunks and largest
+    // node from a report its parent's classification writes into the level's
+    // slot of coherent host memory (kept for the thread's later builds); a
+    // level goes into the queue before its report arrives, with grids sized
+    // by bounds, and the loop stops at the first level without big nodes
     static thread_local int32_t *hcnt = nullptr;
     if (fused) {   // (everything allocated before the first launch)
         roots = (int32_t *)A(sizeof(int32_t) * t->nleaf, tmp);
@@ -2183,11 +2207,12 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
             if (st != RCB_OK) return st;
         }
         if (!hcnt) {
-            if (hipHostMalloc((void **)&hcnt, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+            if (hipHostMalloc((void **)&hcnt, sizeof(int32_t) * 4 * kReportSlots,
+                              hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
                 hcnt = nullptr;
                 return hip_fail(hipErrorOutOfMemory, "hipHostMalloc(level counts)");
             }
-            hcnt[0] = 0;
+            for (int i = 0; i < 4 * kReportSlots; ++i) hcnt[i] = 0;
         }
         RCB_HIP(hipHostGetDevicePointer((void **)&dcnt, hcnt, 0));   // as seen by the device
     }
@@ -2227,49 +2252,86 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         RCB_LAUNCH_CHECK("k_level_classify");
         int64_t nbig = is_big_host((int64_t)n, t->k, 0) ? 1 : 0;
         int64_t nitems = nbig ? (n + kChunk - 1) / kChunk : 0;
+        int64_t maxnch = nitems;   // chunks of the level's largest big node
         int cur = 0, last_big = -1;
-        for (int lvl = 0; lvl <= t->k && nbig > 0; ++lvl) {
-            const bool leaf = lvl == t->k;
+        // one level's passes (not the lowest), with grids sized from the
+        // counts or bounds given; its children's classification reports into
+        // slot lvl + 1
+        auto level = [&](int lvl, int c, int64_t nb, int64_t ni, int64_t mc, int32_t seq) -> rcb_status {
             const BigCtl &bl = bcs[lvl & 1], &bnx = bcs[(lvl + 1) & 1];
             // level 0 reads the caller's arrays (its order is the identity)
-            const PartIn in = lvl == 0 ? PartIn{x, y, z, m, t->ph} : PartIn{b.x[cur], b.y[cur], b.z[cur], b.m[cur], t->ph};
-            int32_t *id_next = leaf ? nullptr : t->lvl_id + (int64_t)(lvl + 1) * n;
-            PartOut out{b.x[cur ^ 1], b.y[cur ^ 1], b.z[cur ^ 1], b.m[cur ^ 1], id_next};
+            const PartIn in = lvl == 0 ? PartIn{x, y, z, m, t->ph} : PartIn{b.x[c], b.y[c], b.z[c], b.m[c], t->ph};
+            PartOut out{b.x[c ^ 1], b.y[c ^ 1], b.z[c ^ 1], b.m[c ^ 1], t->lvl_id + (int64_t)(lvl + 1) * n};
             const int32_t *id_cur = t->lvl_id + (int64_t)lvl * n;
-            const unsigned gi = blocks_for_waves(nitems), gb = (unsigned)nbig;
-            last_big = lvl;
-            if (leaf) {   // the big leaves: their h, payloads A and B
-                k_gather_h_big<<<gi, kBlock, 0, s>>>(h, id_cur, o, bl, t->ph);
-                RCB_LAUNCH_CHECK("k_gather_h_big");
-            }
-            k_chunk_reduce<0><<<gi, kBlock, 0, s>>>(in, o, bl, b.part, leaf ? nullptr : bnx.ctl);
+            const unsigned gi = blocks_for_waves(ni), gb = (unsigned)nb;
+            // one wave per node for the combination and the scan once no big
+            // node has more than kFinOneMax chunks (else kFinWaves per node)
+            const bool one = mc <= kFinOneMax;
+            k_chunk_reduce<0><<<gi, kBlock, 0, s>>>(in, o, bl, b.part, bnx.ctl);
             RCB_LAUNCH_CHECK("k_chunk_reduce<0>");
-            k_big_finalize<0><<<gb, kFinWaves * kWave, 0, s>>>(leaf, 1, o, bl, b.part);
+            if (one) k_big_finalize<0, 1><<<gb, kWave, 0, s>>>(0, 1, o, bl, b.part);
+            else k_big_finalize<0><<<gb, kFinWaves * kWave, 0, s>>>(0, 1, o, bl, b.part);
             RCB_LAUNCH_CHECK("k_big_finalize<0>");
-            if (leaf) {
-                k_chunk_reduce<1><<<gi, kBlock, 0, s>>>(in, o, bl, b.part);
-                RCB_LAUNCH_CHECK("k_chunk_reduce<1>");
-                k_big_finalize<1><<<gb, kFinWaves * kWave, 0, s>>>(leaf, 1, o, bl, b.part);
-                RCB_LAUNCH_CHECK("k_big_finalize<1>");
-                break;
-            }
             k_part_count<<<gi, kBlock, 0, s>>>(in, id_cur, o, bl, b.part_left);
             RCB_LAUNCH_CHECK("k_part_count");
-            k_part_scan<<<gb, kFinWaves * kWave, 0, s>>>(o, bl, b.part_left);
+            if (one) k_part_scan<1><<<gb, kWave, 0, s>>>(o, bl, b.part_left);
+            else k_part_scan<><<<gb, kFinWaves * kWave, 0, s>>>(o, bl, b.part_left);
             RCB_LAUNCH_CHECK("k_part_scan");
-            const int32_t seq = ++g_level_seq;
-            k_classify_children<<<blocks_for_waves((2 * nbig + kWave - 1) / kWave), kBlock, 0, s>>>(
-                lvl + 1, t->k, o, bl, (int)nbig, bnx, roots, qctl, (int)b.max_big, (int)b.max_items, t->dflag + 5,
-                dcnt, seq);
+            k_classify_children<<<blocks_for_waves((2 * nb + kWave - 1) / kWave), kBlock, 0, s>>>(
+                lvl + 1, t->k, o, bl, (int)nb, bnx, roots, qctl, (int)b.max_big, (int)b.max_items, t->dflag + 5,
+                dcnt + 4 * (lvl + 1), seq);
             RCB_LAUNCH_CHECK("k_classify_children");
             k_part_scatter<<<gi, kBlock, 0, s>>>(in, id_cur, out, o, bl, b.part_left);
             RCB_LAUNCH_CHECK("k_part_scatter");
+            return RCB_OK;
+        };
+        bool queued = false;   // the level is already in the queue (sized by bounds)
+        int32_t qseq = 0;
+        int qlvl = -1;
+        for (int lvl = 0; lvl <= t->k && nbig > 0; ++lvl) {
+            last_big = lvl;
+            if (lvl == t->k) {   // the big leaves: their h, payloads A and B
+                const BigCtl &bl = bcs[lvl & 1];
+                const PartIn in{b.x[cur], b.y[cur], b.z[cur], b.m[cur], t->ph};
+                const int32_t *id_cur = t->lvl_id + (int64_t)lvl * n;
+                const unsigned gi = blocks_for_waves(nitems), gb = (unsigned)nbig;
+                k_gather_h_big<<<gi, kBlock, 0, s>>>(h, id_cur, o, bl, t->ph);
+                RCB_LAUNCH_CHECK("k_gather_h_big");
+                k_chunk_reduce<0><<<gi, kBlock, 0, s>>>(in, o, bl, b.part);
+                RCB_LAUNCH_CHECK("k_chunk_reduce<0>");
+                k_big_finalize<0><<<gb, kFinWaves * kWave, 0, s>>>(1, 1, o, bl, b.part);
+                RCB_LAUNCH_CHECK("k_big_finalize<0>");
+                k_chunk_reduce<1><<<gi, kBlock, 0, s>>>(in, o, bl, b.part);
+                RCB_LAUNCH_CHECK("k_chunk_reduce<1>");
+                k_big_finalize<1><<<gb, kFinWaves * kWave, 0, s>>>(1, 1, o, bl, b.part);
+                RCB_LAUNCH_CHECK("k_big_finalize<1>");
+                break;
+            }
+            int32_t seq = qseq;
+            if (!queued) {
+                seq = ++g_level_seq;
+                rcb_status st = level(lvl, cur, nbig, nitems, maxnch, seq);
+                if (st != RCB_OK) return st;
+            }
+            queued = false;
             cur ^= 1;
-            // the scatter keeps the device busy while the host waits for the counts
-            rcb_status ws = wait_report(hcnt, seq, s);
+            if (lvl + 1 < t->k) {
+                // the next level goes into the queue before this one's counts
+                // arrive, so the device does not wait for the host: its grids
+                // are sized by bounds (at most two children per big node, one
+                // more chunk per big node, no node larger than its parent)
+                qseq = ++g_level_seq;
+                qlvl = lvl + 1;
+                rcb_status st = level(lvl + 1, cur, 2 * nbig, nitems + nbig, maxnch, qseq);
+                if (st != RCB_OK) return st;
+                queued = true;
+            }
+            int32_t *rep = hcnt + 4 * (lvl + 1);
+            rcb_status ws = wait_report(rep, seq, s);
             if (ws != RCB_OK) return ws;
-            nbig = hcnt[1];
-            nitems = hcnt[2];
+            nbig = rep[1];
+            nitems = rep[2];
+            maxnch = rep[3];
             if (nbig > b.max_big || nitems > b.max_items) {
                 set_error("rcb_build: internal capacity of the big-node lists exceeded");
                 return RCB_EHIP;
@@ -2307,7 +2369,13 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
             k_upward_levels<<<1, 1024, 0, s>>>(lvl, t->k, o);
             RCB_LAUNCH_CHECK("k_upward_levels");
         }
-        return finish_build(t, b, o, tmp, cur, s);
+        rcb_status st = finish_build(t, b, o, tmp, cur, s);
+        if (queued && st == RCB_OK) {
+            // the level queued last found no big nodes; its report still
+            // arrives, and is awaited so that it cannot land in a later build
+            st = wait_report(hcnt + 4 * (qlvl + 1), qseq, s);
+        }
+        return st;
     }
     int cur = 0;
     for (int lvl = 0; lvl <= t->k; ++lvl) {
