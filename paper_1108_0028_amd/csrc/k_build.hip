@@ -743,12 +743,30 @@ __global__ __launch_bounds__(kBlock) void k_level_packed(int lvl, int split, Par
 // ---------------------------------------------------------------------------
 // big nodes
 // ---------------------------------------------------------------------------
+// Level counts for the host: big nodes, chunks and the largest node's chunks
+// of control block ctl into report[1..3], then the sequence number into
+// report[0] (coherent host memory; the host polls it).
+__device__ __forceinline__ void write_report(const int32_t *ctl, volatile int32_t *report, int32_t seq) {
+    report[1] = ctl[0];
+    report[2] = ctl[1];
+    report[3] = ctl[3];
+    __threadfence_system();
+    report[0] = seq;
+}
+
+__global__ void k_report(const int32_t *ctl, volatile int32_t *report, int32_t seq) {
+    write_report(ctl, report, seq);
+}
+
+// report (if given): the counts of bc, which the previous kernel completed
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_chunk_reduce(PartIn in, NodeOut o, BigCtl bc,
                                                          double *__restrict__ part,
-                                                         int32_t *__restrict__ clear_ctl = nullptr) {
+                                                         int32_t *__restrict__ clear_ctl = nullptr,
+                                                         volatile int32_t *report = nullptr, int32_t seq = 0) {
     const int64_t w = wave_index();
     if (clear_ctl && blockIdx.x == 0 && threadIdx.x < 4) clear_ctl[threadIdx.x] = 0;
+    if (report && blockIdx.x == 0 && threadIdx.x == 0) write_report(bc.ctl, report, seq);
     if (w >= bc.ctl[1]) return;
     const int bi = bc.item_big[w];
     const int64_t lab = bc.big_node[bi];
@@ -936,10 +954,9 @@ __global__ __launch_bounds__(FW * kWave) void k_part_scan(NodeOut o, BigCtl bc,
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_part_scatter(PartIn in, const int32_t *__restrict__ id,
-                                                         PartOut out, NodeOut o, BigCtl bc,
-                                                         const int32_t *__restrict__ part_left) {
-    const int64_t w = wave_index();
+__device__ __forceinline__ void part_scatter(int64_t w, const PartIn &in, const int32_t *__restrict__ id,
+                                             const PartOut &out, const NodeOut &o, const BigCtl &bc,
+                                             const int32_t *__restrict__ part_left) {
     if (w >= bc.ctl[1]) return;
     const int bi = bc.item_big[w];
     const int64_t lab = bc.big_node[bi];
@@ -951,6 +968,12 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(PartIn in, const int32_
     const int64_t rb = j * kChunk - lb;
     const int64_t nleft = o.ncount[2 * lab];
     scatter_chunk(in, id, out, base, end, o.naxis[lab], o.nplane[lab], node_tie(o, lab), s, nleft, lb, rb);
+}
+
+__global__ __launch_bounds__(kBlock) void k_part_scatter(PartIn in, const int32_t *__restrict__ id,
+                                                         PartOut out, NodeOut o, BigCtl bc,
+                                                         const int32_t *__restrict__ part_left) {
+    part_scatter(wave_index(), in, id, out, o, bc, part_left);
 }
 
 constexpr int64_t kUpwardOne = 256;   // levels of at most this many nodes: Eq. 2 in one workgroup
@@ -1146,13 +1169,24 @@ __global__ __launch_bounds__(kBlock) void k_level_classify(int lvl, int k, NodeO
 // its chunk passes) and subtree roots (queued). The last block to finish
 // writes the level's totals (big nodes, chunks) to host memory `report`,
 // then the sequence number `seq` that the host waits for.
-__global__ __launch_bounds__(kBlock) void k_classify_children(int lvl, int k, NodeOut o, BigCtl bp, int nparent,
-                                                              BigCtl bn, int32_t *__restrict__ roots,
-                                                              int32_t *__restrict__ nroots, int max_big,
-                                                              int max_items, int32_t *__restrict__ flag,
-                                                              volatile int32_t *report, int32_t seq) {
-    const int64_t w = wave_index();
+struct ClassifyArgs {
+    int lvl, k;
+    BigCtl bp;
+    int nparent;
+    BigCtl bn;
+    int32_t *roots, *nroots;
+    int max_big, max_items;
+    int32_t *flag;
+};
+
+// w: the wave's index among the nblocks workgroups that classify
+__device__ __forceinline__ void classify_children(const ClassifyArgs &ca, const NodeOut &o, int64_t w) {
     const int lane = lane_id();
+    const int lvl = ca.lvl, k = ca.k, nparent = ca.nparent, max_big = ca.max_big, max_items = ca.max_items;
+    const BigCtl &bp = ca.bp, &bn = ca.bn;
+    int32_t *__restrict__ roots = ca.roots;
+    int32_t *nroots = ca.nroots;
+    int32_t *flag = ca.flag;
     const int64_t t = w * kWave + lane;
     // nparent bounds the parents (the grid may be sized before their count is known)
     const int np = min(nparent, bp.ctl[0]);
@@ -1201,19 +1235,24 @@ __global__ __launch_bounds__(kBlock) void k_classify_children(int lvl, int k, No
         const int nc = __shfl(nch, src, kWave), b0 = __shfl(base, src, kWave), id = __shfl(bi, src, kWave);
         for (int q = lane; q < nc; q += kWave) bn.item_big[b0 + q] = id;
     }
-    // the last block reports the totals
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(&bn.ctl[2], 1) == (int)gridDim.x - 1) {
-            __threadfence();
-            report[1] = atomicAdd(&bn.ctl[0], 0);
-            report[2] = atomicAdd(&bn.ctl[1], 0);
-            report[3] = atomicAdd(&bn.ctl[3], 0);
-            __threadfence_system();
-            report[0] = seq;
-            __threadfence_system();
-        }
+}
+
+// The children's classification and the partition of one level in one
+// launch (both need only the scan): workgroups [0, ncls) classify, the
+// others scatter, so the classification's atomics run under the scatter's
+// memory traffic instead of between two launches. The level's counts reach
+// the host from the next kernel in the stream (k_chunk_reduce of the next
+// level, or k_report), which sees them complete.
+__global__ __launch_bounds__(kBlock) void k_scatter_classify(PartIn in, const int32_t *__restrict__ id, PartOut out,
+                                                             NodeOut o, BigCtl bc,
+                                                             const int32_t *__restrict__ part_left, int ncls,
+                                                             ClassifyArgs ca) {
+    if ((int)blockIdx.x < ncls) {
+        const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+        classify_children(ca, o, (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)w));
+    } else {
+        const int64_t w = (int64_t)(blockIdx.x - ncls) * kWavesPerBlock + threadIdx.x / kWave;
+        part_scatter((int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)w), in, id, out, o, bc, part_left);
     }
 }
 
@@ -2070,9 +2109,10 @@ static rcb_status big_chain(rcb_tree *t, BuildScratch &b, const NodeOut &o, cons
     return RCB_OK;
 }
 
-// Level counts written by k_classify_children into pinned host memory; the
-// host polls the sequence number. A report that does not arrive within a
-// few seconds, or a stream that has failed, ends the wait with an error.
+// Level counts written into pinned host memory by the first kernel after the
+// classification of the level's nodes; the host polls the sequence number. A
+// report that does not arrive within a few seconds, or a stream that has
+// failed, ends the wait with an error.
 static thread_local int32_t g_level_seq = 0;
 
 static rcb_status wait_report(int32_t *hcnt, int32_t seq, hipStream_t s) {
@@ -2191,10 +2231,11 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     int32_t *qctl = clr;   // [0] roots queued, [1] next root to take
     int32_t *roots = nullptr, *bn2 = nullptr, *bb2 = nullptr, *ib2 = nullptr, *dcnt = nullptr;
     // the host learns each level's number of big nodes, chunks and largest
-    // node from a report its parent's classification writes into the level's
-    // slot of coherent host memory (kept for the thread's later builds); a
-    // level goes into the queue before its report arrives, with grids sized
-    // by bounds, and the loop stops at the first level without big nodes
+    // node from a report in the level's slot of coherent host memory (kept
+    // for the thread's later builds), written by the first kernel after its
+    // parent's classification; a level goes into the queue before its
+    // report arrives, with grids sized by bounds, and the loop stops at the
+    // first level without big nodes
     static thread_local int32_t *hcnt = nullptr;
     if (fused) {   // (everything allocated before the first launch)
         roots = (int32_t *)A(sizeof(int32_t) * t->nleaf, tmp);
@@ -2255,9 +2296,9 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         int64_t maxnch = nitems;   // chunks of the level's largest big node
         int cur = 0, last_big = -1;
         // one level's passes (not the lowest), with grids sized from the
-        // counts or bounds given; its children's classification reports into
-        // slot lvl + 1
-        auto level = [&](int lvl, int c, int64_t nb, int64_t ni, int64_t mc, int32_t seq) -> rcb_status {
+        // counts or bounds given; with rseq, its first kernel reports the
+        // level's counts into slot lvl (the previous launch completed them)
+        auto level = [&](int lvl, int c, int64_t nb, int64_t ni, int64_t mc, int32_t rseq) -> rcb_status {
             const BigCtl &bl = bcs[lvl & 1], &bnx = bcs[(lvl + 1) & 1];
             // level 0 reads the caller's arrays (its order is the identity)
             const PartIn in = lvl == 0 ? PartIn{x, y, z, m, t->ph} : PartIn{b.x[c], b.y[c], b.z[c], b.m[c], t->ph};
@@ -2267,7 +2308,8 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
             // one wave per node for the combination and the scan once no big
             // node has more than kFinOneMax chunks (else kFinWaves per node)
             const bool one = mc <= kFinOneMax;
-            k_chunk_reduce<0><<<gi, kBlock, 0, s>>>(in, o, bl, b.part, bnx.ctl);
+            k_chunk_reduce<0><<<gi, kBlock, 0, s>>>(in, o, bl, b.part, bnx.ctl, rseq ? dcnt + 4 * lvl : nullptr,
+                                                    rseq);
             RCB_LAUNCH_CHECK("k_chunk_reduce<0>");
             if (one) k_big_finalize<0, 1><<<gb, kWave, 0, s>>>(0, 1, o, bl, b.part);
             else k_big_finalize<0><<<gb, kFinWaves * kWave, 0, s>>>(0, 1, o, bl, b.part);
@@ -2277,17 +2319,14 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
             if (one) k_part_scan<1><<<gb, kWave, 0, s>>>(o, bl, b.part_left);
             else k_part_scan<><<<gb, kFinWaves * kWave, 0, s>>>(o, bl, b.part_left);
             RCB_LAUNCH_CHECK("k_part_scan");
-            k_classify_children<<<blocks_for_waves((2 * nb + kWave - 1) / kWave), kBlock, 0, s>>>(
-                lvl + 1, t->k, o, bl, (int)nb, bnx, roots, qctl, (int)b.max_big, (int)b.max_items, t->dflag + 5,
-                dcnt + 4 * (lvl + 1), seq);
-            RCB_LAUNCH_CHECK("k_classify_children");
-            k_part_scatter<<<gi, kBlock, 0, s>>>(in, id_cur, out, o, bl, b.part_left);
-            RCB_LAUNCH_CHECK("k_part_scatter");
+            const int ncls = (int)blocks_for_waves((2 * nb + kWave - 1) / kWave);
+            const ClassifyArgs ca{lvl + 1, t->k, bl, (int)nb, bnx, roots, qctl, (int)b.max_big, (int)b.max_items,
+                                  t->dflag + 5};
+            k_scatter_classify<<<ncls + gi, kBlock, 0, s>>>(in, id_cur, out, o, bl, b.part_left, ncls, ca);
+            RCB_LAUNCH_CHECK("k_scatter_classify");
             return RCB_OK;
         };
         bool queued = false;   // the level is already in the queue (sized by bounds)
-        int32_t qseq = 0;
-        int qlvl = -1;
         for (int lvl = 0; lvl <= t->k && nbig > 0; ++lvl) {
             last_big = lvl;
             if (lvl == t->k) {   // the big leaves: their h, payloads A and B
@@ -2307,24 +2346,25 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
                 RCB_LAUNCH_CHECK("k_big_finalize<1>");
                 break;
             }
-            int32_t seq = qseq;
             if (!queued) {
-                seq = ++g_level_seq;
-                rcb_status st = level(lvl, cur, nbig, nitems, maxnch, seq);
+                rcb_status st = level(lvl, cur, nbig, nitems, maxnch, 0);
                 if (st != RCB_OK) return st;
             }
             queued = false;
             cur ^= 1;
+            const int32_t seq = ++g_level_seq;
             if (lvl + 1 < t->k) {
                 // the next level goes into the queue before this one's counts
                 // arrive, so the device does not wait for the host: its grids
                 // are sized by bounds (at most two children per big node, one
-                // more chunk per big node, no node larger than its parent)
-                qseq = ++g_level_seq;
-                qlvl = lvl + 1;
-                rcb_status st = level(lvl + 1, cur, 2 * nbig, nitems + nbig, maxnch, qseq);
+                // more chunk per big node, no node larger than its parent),
+                // and its first kernel reports its counts
+                rcb_status st = level(lvl + 1, cur, 2 * nbig, nitems + nbig, maxnch, seq);
                 if (st != RCB_OK) return st;
                 queued = true;
+            } else {
+                k_report<<<1, 1, 0, s>>>(bcs[(lvl + 1) & 1].ctl, dcnt + 4 * (lvl + 1), seq);
+                RCB_LAUNCH_CHECK("k_report");
             }
             int32_t *rep = hcnt + 4 * (lvl + 1);
             rcb_status ws = wait_report(rep, seq, s);
@@ -2369,13 +2409,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
             k_upward_levels<<<1, 1024, 0, s>>>(lvl, t->k, o);
             RCB_LAUNCH_CHECK("k_upward_levels");
         }
-        rcb_status st = finish_build(t, b, o, tmp, cur, s);
-        if (queued && st == RCB_OK) {
-            // the level queued last found no big nodes; its report still
-            // arrives, and is awaited so that it cannot land in a later build
-            st = wait_report(hcnt + 4 * (qlvl + 1), qseq, s);
-        }
-        return st;
+        return finish_build(t, b, o, tmp, cur, s);
     }
     int cur = 0;
     for (int lvl = 0; lvl <= t->k; ++lvl) {
