@@ -887,9 +887,16 @@ __global__ __launch_bounds__(FW * kWave) void k_big_finalize(int leaf_level, int
     }
 }
 
+// FIN (levels whose big nodes have at most 64 chunks): each wave first
+// combines its node's chunk sums itself, as k_big_finalize<0, 1> does for a
+// single group (one chunk per lane, the butterfly), and takes the split from
+// them; the node's first chunk writes payload A. Otherwise the split comes
+// from k_big_finalize.
+template <bool FIN>
 __global__ __launch_bounds__(kBlock) void k_part_count(PartIn in, const int32_t *__restrict__ id,
                                                        NodeOut o, BigCtl bc,
-                                                       int32_t *__restrict__ part_left) {
+                                                       int32_t *__restrict__ part_left,
+                                                       const double *__restrict__ part = nullptr) {
     const int64_t w = wave_index();
     if (w >= bc.ctl[1]) return;
     const int bi = bc.item_big[w];
@@ -898,8 +905,38 @@ __global__ __launch_bounds__(kBlock) void k_part_count(PartIn in, const int32_t 
     const int64_t s = o.nfirst[lab], c = o.ncount[lab];
     const int64_t base = s + j * kChunk;
     const int64_t end = min(base + kChunk, s + c);
-    const int ax = o.naxis[lab];
-    const double plane = o.nplane[lab];
+    int ax;
+    double plane;
+    if constexpr (FIN) {
+        const int64_t nch = (c + kChunk - 1) / kChunk;   // <= kWave
+        const int64_t p0 = bc.big_base[bi];
+        const int l = lane_id();
+        const bool ok = l < nch;
+        double sv[4], mx = ok ? part[8 * (p0 + l) + 7] : -1.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sv[q] = wave_sum(ok ? part[8 * (p0 + l) + q] : 0.0);
+        mx = wave_max(mx);
+        if (j == 0) finish_a(o, lab, false, sv, mx, true);
+        double lo[3], hi[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = o.nlo[3 * lab + d];
+            hi[d] = o.nhi[3 * lab + d];
+        }
+        ax = 0;
+        double best = hi[0] - lo[0];
+        if (hi[1] - lo[1] > best) {
+            best = hi[1] - lo[1];
+            ax = 1;
+        }
+        if (hi[2] - lo[2] > best) ax = 2;
+        const double M = sv[0] + 0.0;
+        const double sa = ax == 0 ? sv[1] : (ax == 1 ? sv[2] : sv[3]);
+        plane = o.mplane ? o.mplane[lab] : (sa + 0.0) / M;   // as finish_a
+    } else {
+        ax = o.naxis[lab];
+        plane = o.nplane[lab];
+    }
     const int32_t tie = node_tie(o, lab);
     const double *xa = ax == 0 ? in.x : (ax == 1 ? in.y : in.z);
     int nl = 0;
@@ -2098,7 +2135,7 @@ static rcb_status big_chain(rcb_tree *t, BuildScratch &b, const NodeOut &o, cons
         k_big_finalize<1><<<(unsigned)bw, kFinWaves * kWave, 0, s>>>(leaf, split, o, bc, b.part);
         RCB_LAUNCH_CHECK("k_big_finalize<1>");
     } else if (split) {
-        k_part_count<<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, id, o, bc, b.part_left);
+        k_part_count<false><<<blocks_for_waves(item_waves), kBlock, 0, s>>>(in, id, o, bc, b.part_left);
         RCB_LAUNCH_CHECK("k_part_count");
         k_part_scan<><<<(unsigned)bw, kFinWaves * kWave, 0, s>>>(o, bc, b.part_left);
         RCB_LAUNCH_CHECK("k_part_scan");
@@ -2308,13 +2345,19 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
             // one wave per node for the combination and the scan once no big
             // node has more than kFinOneMax chunks (else kFinWaves per node)
             const bool one = mc <= kFinOneMax;
+            // the combination inside the count pass once no big node has more
+            // than one group of chunks
+            const bool fin = mc <= kWave;
             k_chunk_reduce<0><<<gi, kBlock, 0, s>>>(in, o, bl, b.part, bnx.ctl, rseq ? dcnt + 4 * lvl : nullptr,
                                                     rseq);
             RCB_LAUNCH_CHECK("k_chunk_reduce<0>");
-            if (one) k_big_finalize<0, 1><<<gb, kWave, 0, s>>>(0, 1, o, bl, b.part);
-            else k_big_finalize<0><<<gb, kFinWaves * kWave, 0, s>>>(0, 1, o, bl, b.part);
-            RCB_LAUNCH_CHECK("k_big_finalize<0>");
-            k_part_count<<<gi, kBlock, 0, s>>>(in, id_cur, o, bl, b.part_left);
+            if (!fin) {
+                if (one) k_big_finalize<0, 1><<<gb, kWave, 0, s>>>(0, 1, o, bl, b.part);
+                else k_big_finalize<0><<<gb, kFinWaves * kWave, 0, s>>>(0, 1, o, bl, b.part);
+                RCB_LAUNCH_CHECK("k_big_finalize<0>");
+            }
+            if (fin) k_part_count<true><<<gi, kBlock, 0, s>>>(in, id_cur, o, bl, b.part_left, b.part);
+            else k_part_count<false><<<gi, kBlock, 0, s>>>(in, id_cur, o, bl, b.part_left);
             RCB_LAUNCH_CHECK("k_part_count");
             if (one) k_part_scan<1><<<gb, kWave, 0, s>>>(o, bl, b.part_left);
             else k_part_scan<><<<gb, kFinWaves * kWave, 0, s>>>(o, bl, b.part_left);
