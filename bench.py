@@ -305,7 +305,8 @@ def _rooflines(c, phases, prec, n, k):
     # gather and records the rest)
     b = hbm(n * (48 * k + 100), phases["build"])
     b["basis"] = f"N (48 k + 100) bytes, k = {k}"
-    b["traffic"] = {k_: _profiled(k_) for k_ in ("k_subtree", "k_part_scatter", "k_chunk_reduce<0>", "k_init")}
+    b["traffic"] = {k_: _profiled(k_) for k_ in ("k_subtree", "k_scatter_classify", "k_chunk_reduce<0>",
+                                                 "k_part_count<false>", "k_part_count<true>")}
     # walk: FP64 tests of (node, visiting cell) pairs; also the node records it loads
     w = alu(0, FLOP_TEST * c["walk_tests"], phases["walk"])
     w["hbm_bytes"] = 64 * c["walk_nodes"]
