@@ -19,13 +19,15 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    All work is enqueued on it; inputs must stay valid and outputs must not
  *    be read until the stream has passed the call. The calls that return
- *    host values or size device lists synchronise the stream: rcb_walk()
- *    (and the first call that runs the walk on demand), rcb_check_cells(),
- *    rcb_neighbours_count(), rcb_destroy(), and rcb_build() / rcb_refresh()
- *    with validate = 1. rcb_build() (centre-of-mass and centre-of-number
- *    splits) also waits, level by level, for each level's count of large
- *    nodes while the device partitions the level before; it returns before
- *    the build has finished on the device.
+ *    host values or size device lists wait until the stream has passed the
+ *    values they need: rcb_walk() (and the first call that runs the walk on
+ *    demand) and rcb_neighbours_count() (by polling values the device writes
+ *    into pinned host memory after the work before them), rcb_check_cells(),
+ *    and rcb_build() / rcb_refresh() with validate = 1 (by synchronising the
+ *    stream). rcb_build() (centre-of-mass and centre-of-number splits) also
+ *    waits, level by level, for each level's count of large nodes while the
+ *    device partitions the levels before it; it returns before the build has
+ *    finished on the device. rcb_destroy() does not wait.
  *  - Inputs stay owned by the caller. rcb_build() copies what it needs, so
  *    the tree never aliases caller memory after the call returns.
  *  - Calls return rcb_status; nothing throws across the ABI. Argument errors
@@ -100,8 +102,8 @@ typedef struct {
     int32_t split;      /* rcb_split: where a cell is cut; moments always use the masses */
     int32_t taylor_reading;   /* rcb_taylor_reading of the far-field sink coefficients */
     /* Optional workspace allocator, both or neither (NULL: the library
-       allocates from the device's stream-ordered pool and keeps blocks of
-       1 GiB and more for reuse). alloc(bytes, stream, ctx) returns device
+       allocates from the device's stream-ordered pool and keeps freed blocks
+       for reuse on the stream that freed them). alloc(bytes, stream, ctx) returns device
        memory usable in stream order on `stream`, or NULL (the call then fails
        with RCB_ENOMEM); free(ptr, stream, ctx) releases it in stream order.
        Every block is freed by the call that allocated it or by
@@ -202,7 +204,8 @@ size_t rcb_refresh_noalloc_scratch(const rcb_tree *t);
  * lowest-level cell and keeps them in the tree. The neighbour and gravity
  * calls run it themselves when it has not run yet; calling it first only
  * moves the work; after rcb_refresh(keep_lists = 1) it walks the refreshed
- * tree again. Synchronises `stream` (the list sizes are read back).
+ * tree again. Waits until `stream` has passed the walk (the list sizes and
+ * flags are read back through pinned host memory).
  * Errors: RCB_ECAPACITY if the last-resort walk's stack overflows (a tree
  * deeper than 29 levels), RCB_ENOMEM.
  * Environment (testing): RCB_WALK_WIDE_STACK=n caps the breadth-first
@@ -217,7 +220,9 @@ rcb_status rcb_walk(rcb_tree *t, void *stream);
  * reachability test of Sec. 2.3.1 keeps.
  *  offsets: device int64[n + 1], receives the exclusive prefix sum of the
  *           counts (offsets[0] = 0, offsets[n] = total).
- *  total:   host int64, receives offsets[n]. This call synchronises `stream`.
+ *  total:   host int64, receives offsets[n]. This call waits until `stream`
+ *           has passed the count (the total is read back through pinned host
+ *           memory).
  * Errors: RCB_ESTATE after rcb_refresh(keep_lists = 1) until rcb_walk().
  */
 rcb_status rcb_neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, void *stream);
@@ -317,16 +322,18 @@ rcb_status rcb_tree_export(rcb_tree *t, int32_t field, void *dst, size_t bytes, 
 
 /* Free the tree and its device memory, in stream order on `stream` (made to
    wait for the tree's last stream first; NULL = the tree's last stream), and
-   wait for that stream. NULL t is a no-op. Blocks of 1 GiB and more from the
-   library's own allocator stay reserved for the next tree on the same device
-   (see rcb_release_cache). */
+   return without waiting: the memory is reused only by work queued on that
+   stream after the call (or, from the caller's allocator, as its free()
+   allows). NULL t is a no-op. Blocks from the library's own allocator stay
+   reserved for later requests on the same device and stream (up to a quarter
+   of the device's memory; see rcb_release_cache). */
 void rcb_destroy(rcb_tree *t, void *stream);
 
-/* Give back the device memory the library keeps for reuse: the freed blocks
-   of 1 GiB and more, and the unused part of each device's default
-   stream-ordered pool (its release threshold, raised by the library, is
-   restored). Call it when no tree is in use, e.g. before another framework
-   needs the memory. Waits for the blocks' last uses; never fails. */
+/* Give back the device memory the library keeps for reuse: its freed blocks,
+   and the unused part of each device's default stream-ordered pool (its
+   release threshold, raised by the library, is restored). Call it when no
+   tree is in use, e.g. before another framework needs the memory. Waits for
+   the devices concerned to finish their work; never fails. */
 void rcb_release_cache(void);
 
 /* Message of the last failed call on this thread ("" if none). */

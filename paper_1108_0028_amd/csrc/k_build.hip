@@ -2076,7 +2076,7 @@ static rcb_status level_pass(rcb_tree *t, BuildScratch &b, const NodeOut &o, con
                              hipStream_t s) {
     const int64_t n = t->n;
     const bool leaf = lvl == t->k;
-    RCB_HIP(hipMemsetAsync(b.ctl, 0, sizeof(int32_t) * 4, s));
+    RCB_ZERO(b.ctl, sizeof(int32_t) * 4, s);
     const int64_t nodes = (int64_t)1 << lvl;
     // group width: 8, 16 or 32 lanes per node while the average node
     // holds at most 4 GW particles (capacity 8 GW)
@@ -2152,26 +2152,6 @@ static rcb_status big_chain(rcb_tree *t, BuildScratch &b, const NodeOut &o, cons
 // failed, ends the wait with an error.
 static thread_local int32_t g_level_seq = 0;
 
-static rcb_status wait_report(int32_t *hcnt, int32_t seq, hipStream_t s) {
-    const auto t0 = std::chrono::steady_clock::now();
-    for (uint64_t spin = 0;; ++spin) {
-        if (__atomic_load_n(&hcnt[0], __ATOMIC_ACQUIRE) == seq) return RCB_OK;
-        // the stream is queried only once the wait is long (a query puts a
-        // marker into the queue, which stalls the device between kernels)
-        if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
-            const hipError_t q = hipStreamQuery(s);
-            if (q != hipSuccess && q != hipErrorNotReady) return hip_fail(q, "build: level pass");
-            if (q == hipSuccess && __atomic_load_n(&hcnt[0], __ATOMIC_ACQUIRE) != seq) {
-                set_error("build: the level counts did not arrive");
-                return RCB_EHIP;
-            }
-            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(10)) {
-                set_error("build: timed out waiting for the level counts");
-                return RCB_EHIP;
-            }
-        }
-    }
-}
 
 static inline bool is_big_host(int64_t c, int k, int lvl) {
     return c > 0 && (c > kSubMax || k - lvl > kSubDepth);
@@ -2241,7 +2221,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
     for (void *p : tmp)
         if (!p) return RCB_ENOMEM;
 
-    RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 8, s));
+    RCB_ZERO(t->dflag, sizeof(int32_t) * 8, s);
     if (t->p.validate) {
         k_validate<<<nbp, kBlock, 0, s>>>(x, y, z, m, h, n, t->dflag);
         RCB_LAUNCH_CHECK("k_validate");
@@ -2316,7 +2296,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
         for (void *p : {(void *)mplane, (void *)mtie, (void *)ms.khi, (void *)ms.klo, (void *)ms.rank,
                         (void *)ms.hist})
             if (!p) return RCB_ENOMEM;
-        RCB_HIP(hipMemsetAsync(ms.hist, 0, sizeof(uint32_t) * 256 * max_sel, s));
+        RCB_ZERO(ms.hist, sizeof(uint32_t) * 256 * max_sel, s);
     }
     NodeOut o{t->nfirst, t->ncount, t->nlo, t->nhi, t->ncom, t->nM, t->nhint, t->nhnode, t->nQ,
               b.naxis, b.nplane, mplane, mtie};
@@ -2410,7 +2390,7 @@ rcb_status build_tree(rcb_tree *t, const double *x, const double *y, const doubl
                 RCB_LAUNCH_CHECK("k_report");
             }
             int32_t *rep = hcnt + 4 * (lvl + 1);
-            rcb_status ws = wait_report(rep, seq, s);
+            rcb_status ws = wait_host_word(rep, seq, s, "build: level pass");
             if (ws != RCB_OK) return ws;
             nbig = rep[1];
             nitems = rep[2];
@@ -2532,7 +2512,7 @@ rcb_status count_outside(rcb_tree *t, const double *x, const double *y, const do
     Scratch tmp(t, s);
     unsigned long long *cnt = (unsigned long long *)dalloc(t, sizeof(unsigned long long), s, tmp);
     if (!cnt) return RCB_ENOMEM;
-    RCB_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
+    RCB_ZERO(cnt, sizeof(unsigned long long), s);
     k_outside<<<blocks_for_waves(t->nleaf), kBlock, 0, s>>>(t->nleaf, t->nfirst, t->ncount, t->nlo,
                                                             t->nhi, t->pid, x, y, z, cnt);
     RCB_LAUNCH_CHECK("k_outside");
@@ -2591,7 +2571,7 @@ static rcb_status refresh_core(rcb_tree *t, const double *x, const double *y, co
     BuildScratch &b = r.b;
     if (t->p.validate) {
         const int nbp = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
-        RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t), s));
+        RCB_ZERO(t->dflag, sizeof(int32_t), s);
         k_validate<<<nbp, kBlock, 0, s>>>(x, y, z, m, h, n, t->dflag);
         RCB_LAUNCH_CHECK("k_validate");
         int32_t flag = 0;

@@ -595,7 +595,7 @@ rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipSt
             !t->nb_ctl)
             return RCB_ENOMEM;
     }
-    RCB_HIP(hipMemsetAsync(t->nb_ctl, 0, sizeof(int32_t) * 4, s));
+    RCB_ZERO(t->nb_ctl, sizeof(int32_t) * 4, s);
     NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
                 t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, offsets, nullptr, t->nb_slab,
                 t->nb_pool, t->nb_longc, t->nb_pool_cap, t->nb_head, t->nb_ctl, t->nb_queue, t->nb_longq, 0,
@@ -606,9 +606,9 @@ rcb_status neighbours_count(rcb_tree *t, int64_t *offsets, int64_t *total, hipSt
     st = scan_i64(t, offsets, offsets, t->n, s);   // in place
     if (st != RCB_OK) return st;
     int32_t ctl[4] = {0, 0, 0, 0};
-    RCB_HIP(hipMemcpyAsync(total, offsets + t->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RCB_HIP(hipMemcpyAsync(ctl, t->nb_ctl, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
-    RCB_HIP(hipStreamSynchronize(s));
+    const HostRead r[2] = {{offsets + t->n, total, (int)sizeof(int64_t)}, {t->nb_ctl, ctl, (int)sizeof(ctl)}};
+    st = read_small(s, r, 2, "rcb_neighbours_count");
+    if (st != RCB_OK) return st;
     t->nb_total = *total;
     t->nb_over = ctl[0];
     t->nb_nq = ctl[1];
@@ -648,7 +648,7 @@ rcb_status neighbours_fill(rcb_tree *t, const int64_t *offsets, int32_t *ids, in
         int32_t *longq = (int32_t *)dalloc(t, sizeof(int32_t) * (size_t)t->nb_over, s, tmp);
         int32_t *ctl = (int32_t *)dalloc(t, sizeof(int32_t), s, tmp);
         if (!longq || !ctl) return RCB_ENOMEM;
-        RCB_HIP(hipMemsetAsync(ctl, 0, sizeof(int32_t), s));
+        RCB_ZERO(ctl, sizeof(int32_t), s);
         NeighArgs a{t->nleaf, t->gk, t->ngroup, t->wrec, t->nhnode, t->nfirst, t->ncount, t->gnear_beg,
                     t->gnear_end, t->gnear, t->px, t->py, t->pz, t->ph, t->pid, nullptr, offsets, ids,
                     nullptr, nullptr, 0, t->nb_head, ctl, t->nb_queue, longq, t->nb_nq, false};

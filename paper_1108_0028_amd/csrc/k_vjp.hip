@@ -561,9 +561,9 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     }
     double *leafc = t->farc;   // 19 far coefficients + the leaf's cotangent sum per leaf
     if (!sink || !srcv || !adj || !adjc || !adjmc || !mom || !leafc) return RCB_ENOMEM;
-    RCB_HIP(hipMemsetAsync(srcv, 0, (mixed ? sizeof(float) : sizeof(double)) * 4 * n, s));
-    RCB_HIP(hipMemsetAsync(adjc, 0, (mixed ? sizeof(float) : sizeof(double)) * adj_n, s));
-    RCB_HIP(hipMemsetAsync(adjmc, 0, (mixed ? sizeof(float) : sizeof(double)) * adjm_n, s));
+    RCB_ZERO(srcv, (mixed ? sizeof(float) : sizeof(double)) * 4 * n, s);
+    RCB_ZERO(adjc, (mixed ? sizeof(float) : sizeof(double)) * adj_n, s);
+    RCB_ZERO(adjmc, (mixed ? sizeof(float) : sizeof(double)) * adjm_n, s);
     VjpArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
               t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
               t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, mixed ? nullptr : (double *)srcv,

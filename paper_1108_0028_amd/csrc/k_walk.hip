@@ -539,18 +539,26 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     if (t->walked) return RCB_OK;
     const int64_t NG = t->ngroup;
     Scratch tmp(t, s);
-    int64_t *ncnt = (int64_t *)dalloc(t, sizeof(int64_t) * NG, s, tmp);
-    int64_t *fcnt = (int64_t *)dalloc(t, sizeof(int64_t) * NG, s, tmp);
-    int32_t *queue = (int32_t *)dalloc(t, sizeof(int32_t) * NG, s, tmp);    // groups for the 2nd tier
-    int32_t *queue2 = (int32_t *)dalloc(t, sizeof(int32_t) * NG, s, tmp);   // and for k_walk_group
-    unsigned long long *stats = (unsigned long long *)dalloc(t, sizeof(unsigned long long) * 2, s, tmp);
+    // per-group counts, the later tiers' queues and the statistics: one block
+    // kept by the tree for its later walks (no frees between the walk's
+    // kernels and the next call's)
+    const size_t ws_bytes = sizeof(int64_t) * 2 * NG + sizeof(int32_t) * 2 * NG + 2 * sizeof(unsigned long long) + 64;
+    if (!t->walk_ws) {
+        t->walk_ws = dalloc(t, ws_bytes, s, t->allocs);
+        if (!t->walk_ws) return RCB_ENOMEM;
+    }
+    int64_t *ncnt = (int64_t *)t->walk_ws;
+    int64_t *fcnt = ncnt + NG;
+    unsigned long long *stats = (unsigned long long *)(fcnt + NG);
+    int32_t *queue = (int32_t *)(stats + 2);    // groups for the 2nd tier
+    int32_t *queue2 = queue + NG;               // and for k_walk_group
     int64_t cn, cf;
     slab_caps(NG, cn, cf);
     std::vector<void *> slabs;
     uint64_t *nslab = (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cn, s, slabs);
     uint64_t *fslab = (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cf, s, slabs);
     for (void *p : slabs) tmp.push_back(p);   // freed at the end unless kept
-    if (!ncnt || !fcnt || !queue || !queue2 || !stats || !nslab || !fslab) return RCB_ENOMEM;
+    if (!nslab || !fslab) return RCB_ENOMEM;
     // RCB_WALK_WIDE_STACK (testing): smaller wide-walk rings, so that more
     // groups take the later tiers
     int cap1 = kWQueue, cap2 = kWQueue2;
@@ -568,45 +576,47 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     // the three tiers over all groups, then over the groups each one queued;
     // q1/q2 null: the queues are known (second pass) and are not appended to
     int64_t nq = 0, nq2 = 0;
+    // the flags (errors, list counts, the tiers' queue lengths) and the
+    // statistics, read once after each tier that runs
+    int32_t flags[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long hstats[2] = {0, 0};
+    auto read_flags = [&]() -> rcb_status {
+        const HostRead r[2] = {{t->dflag, flags, (int)sizeof(flags)}, {stats, hstats, (int)sizeof(hstats)}};
+        return read_small(s, r, 2, "rcb_walk");
+    };
     auto walk_tiers = [&](bool count_queues) -> rcb_status {
         int32_t *q1 = count_queues ? queue : nullptr, *q2 = count_queues ? queue2 : nullptr;
         if (pure) k_walk_wide<true, kWQueue, kWaves><<<grid, kBlock, 0, s>>>(w, q1, t->dflag + 6, nullptr, 0, cap1);
         else k_walk_wide<false, kWQueue, kWaves><<<grid, kBlock, 0, s>>>(w, q1, t->dflag + 6, nullptr, 0, cap1);
         RCB_LAUNCH_CHECK("k_walk_wide");
         if (count_queues) {
-            int32_t c = 0;
-            RCB_HIP(hipMemcpyAsync(&c, t->dflag + 6, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            RCB_HIP(hipStreamSynchronize(s));
-            nq = c;
+            rcb_status st = read_flags();
+            if (st != RCB_OK) return st;
+            nq = flags[6];
         }
         if (nq == 0) return RCB_OK;
         if (pure) k_walk_wide<true, kWQueue2, 1><<<(unsigned)nq, kWave, 0, s>>>(w, q2, t->dflag + 7, queue, nq, cap2);
         else k_walk_wide<false, kWQueue2, 1><<<(unsigned)nq, kWave, 0, s>>>(w, q2, t->dflag + 7, queue, nq, cap2);
         RCB_LAUNCH_CHECK("k_walk_wide<2nd tier>");
         if (count_queues) {
-            int32_t c = 0;
-            RCB_HIP(hipMemcpyAsync(&c, t->dflag + 7, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            RCB_HIP(hipStreamSynchronize(s));
-            nq2 = c;
+            rcb_status st = read_flags();
+            if (st != RCB_OK) return st;
+            nq2 = flags[7];
         }
         if (nq2 == 0) return RCB_OK;
         const unsigned gridq = (unsigned)((nq2 + kWaves - 1) / kWaves);
         if (pure) k_walk_group<true><<<gridq, kBlock, 0, s>>>(w, queue2, nq2);
         else k_walk_group<false><<<gridq, kBlock, 0, s>>>(w, queue2, nq2);
         RCB_LAUNCH_CHECK("k_walk_group");
+        if (count_queues) return read_flags();
         return RCB_OK;
     };
-    RCB_HIP(hipMemsetAsync(t->dflag, 0, sizeof(int32_t) * 4, s));
-    RCB_HIP(hipMemsetAsync(t->dflag + 6, 0, sizeof(int32_t) * 2, s));
-    RCB_HIP(hipMemsetAsync(stats, 0, sizeof(unsigned long long) * 2, s));
+    RCB_ZERO(t->dflag, sizeof(int32_t) * 4, s);
+    RCB_ZERO(t->dflag + 6, sizeof(int32_t) * 2, s);
+    RCB_ZERO(stats, sizeof(unsigned long long) * 2, s);
     rcb_status wst = walk_tiers(true);
     if (wst != RCB_OK) return wst;
     w.stats = nullptr;   // a second walk (exact lists) does not count again
-    int32_t flags[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    unsigned long long hstats[2] = {0, 0};
-    RCB_HIP(hipMemcpyAsync(flags, t->dflag, sizeof(int32_t) * 8, hipMemcpyDeviceToHost, s));
-    RCB_HIP(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
-    RCB_HIP(hipStreamSynchronize(s));
     t->walk_requeued = nq;
     t->walk_nodes = (int64_t)hstats[0];
     t->walk_tests = (int64_t)hstats[1];
@@ -644,9 +654,9 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
         st = scan_i64(t, fcnt, foff, NG, s);
         if (st != RCB_OK) return st;
         int64_t tot[2] = {0, 0};
-        RCB_HIP(hipMemcpyAsync(&tot[0], noff + NG, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        RCB_HIP(hipMemcpyAsync(&tot[1], foff + NG, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        RCB_HIP(hipStreamSynchronize(s));
+        const HostRead r[2] = {{noff + NG, &tot[0], (int)sizeof(int64_t)}, {foff + NG, &tot[1], (int)sizeof(int64_t)}};
+        st = read_small(s, r, 2, "rcb_walk");
+        if (st != RCB_OK) return st;
         t->gnear = (uint64_t *)dalloc(t, sizeof(uint64_t) * std::max<int64_t>(1, tot[0]), s, t->list_allocs);
         t->gfar = (uint64_t *)dalloc(t, sizeof(uint64_t) * std::max<int64_t>(1, tot[1]), s, t->list_allocs);
         if (!t->gnear || !t->gfar) return RCB_ENOMEM;

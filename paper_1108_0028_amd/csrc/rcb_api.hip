@@ -1,5 +1,7 @@
 // rcb_api.hip -- the C ABI declared in include/rcb.h: argument checks on the
 // host, tree lifetime, stream-ordered device memory.
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -25,54 +27,178 @@ rcb_status hip_fail(hipError_t e, const char *what) {
     return e == hipErrorOutOfMemory ? RCB_ENOMEM : RCB_EHIP;
 }
 
-// Stream-ordered allocation from the device's default pool, which keeps
-// freed memory for reuse (release threshold raised once per device, restored
-// by rcb_release_cache). Blocks of at least kCacheMin bytes are also kept by
-// the library once freed and handed out again for a request on the same
-// device that they fit within a factor of two: allocating and freeing tens of
-// GB through the pool maps and unmaps memory on every tree at 10^8 particles.
-// A kept block carries an event recorded on the stream that freed it; the
-// stream that takes it over waits for that event first, so no stream handle
-// of the caller is held past the call. If an allocation fails, the kept
-// blocks are released and it is tried once more.
+rcb_status wait_host_word(volatile int32_t *w, int32_t seq, hipStream_t s, const char *what) {
+    const auto t0 = std::chrono::steady_clock::now();
+    auto next_query = t0 + std::chrono::milliseconds(200);
+    for (uint64_t spin = 0;; ++spin) {
+        if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return RCB_OK;
+        // the stream is queried (for a failed stream) only once the wait is
+        // long, and then rarely: each query put a marker between the queued
+        // kernels, which left the device idle for microseconds each time
+        if ((spin & 1023) != 1023) continue;
+        const auto now = std::chrono::steady_clock::now();
+        if (now >= next_query) {
+            next_query = now + std::chrono::milliseconds(50);
+            const hipError_t q = hipStreamQuery(s);
+            if (q != hipSuccess && q != hipErrorNotReady) return hip_fail(q, what);
+            if (q == hipSuccess && __atomic_load_n(w, __ATOMIC_ACQUIRE) != seq) {
+                set_error(std::string(what) + ": the device's report did not arrive");
+                return RCB_EHIP;
+            }
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(10)) {
+                set_error(std::string(what) + ": timed out waiting for the device's report");
+                return RCB_EHIP;
+            }
+        }
+    }
+}
+
 namespace {
-constexpr size_t kCacheMin = (size_t)1 << 30;
+__global__ void k_zero(uint32_t *p, int64_t words) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+}  // namespace
+
+rcb_status zero_async(void *p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return RCB_OK;
+    if (bytes % 4 != 0 || ((uintptr_t)p & 3) != 0) {
+        set_error("zero_async: unaligned block");
+        return RCB_EINVAL;
+    }
+    const int64_t words = (int64_t)(bytes / 4);
+    const unsigned grid = (unsigned)std::min<int64_t>(2048, (words + 255) / 256);
+    k_zero<<<grid, 256, 0, s>>>((uint32_t *)p, words);
+    RCB_LAUNCH_CHECK("k_zero");
+    return RCB_OK;
+}
+
+namespace {
+struct ReadArgs {
+    const int32_t *src[kReadItems];
+    int words[kReadItems];
+    int n;
+    volatile int32_t *box;   // [0] sequence number, data from [4]
+    int32_t seq;
+};
+
+__global__ void k_read_small(ReadArgs r) {
+    int o = 4;
+    for (int i = 0; i < r.n; ++i)
+        for (int w = 0; w < r.words[i]; ++w) r.box[o++] = r.src[i][w];
+    __threadfence_system();
+    r.box[0] = r.seq;
+}
+}  // namespace
+
+rcb_status read_small(hipStream_t s, const HostRead *items, int n, const char *what) {
+    static thread_local int32_t *box = nullptr, *dbox = nullptr;
+    static thread_local int32_t seq = 0;
+    if (n < 0 || n > kReadItems) {
+        set_error(std::string(what) + ": too many values for one read");
+        return RCB_EINVAL;
+    }
+    if (!box) {
+        if (hipHostMalloc((void **)&box, sizeof(int32_t) * (4 + kReadBytes / 4),
+                          hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+            box = nullptr;
+            return hip_fail(hipErrorOutOfMemory, "hipHostMalloc(read buffer)");
+        }
+        box[0] = 0;
+        if (hipHostGetDevicePointer((void **)&dbox, box, 0) != hipSuccess) {
+            (void)hipHostFree(box);
+            box = nullptr;
+            return hip_fail(hipErrorInvalidValue, "hipHostGetDevicePointer(read buffer)");
+        }
+    }
+    ReadArgs r{};
+    int total = 0;
+    for (int i = 0; i < n; ++i) {
+        if (items[i].bytes % 4 != 0 || ((uintptr_t)items[i].src & 3) != 0) {
+            set_error(std::string(what) + ": unaligned value");
+            return RCB_EINVAL;
+        }
+        r.src[i] = (const int32_t *)items[i].src;
+        r.words[i] = items[i].bytes / 4;
+        total += items[i].bytes;
+    }
+    if (total > kReadBytes) {
+        set_error(std::string(what) + ": values too large for one read");
+        return RCB_EINVAL;
+    }
+    r.n = n;
+    r.box = dbox;
+    r.seq = ++seq;
+    k_read_small<<<1, 1, 0, s>>>(r);
+    RCB_LAUNCH_CHECK("k_read_small");
+    rcb_status st = wait_host_word(box, r.seq, s, what);
+    if (st != RCB_OK) return st;
+    int o = 4;
+    for (int i = 0; i < n; ++i) {
+        memcpy(items[i].dst, box + o, items[i].bytes);
+        o += items[i].bytes / 4;
+    }
+    return RCB_OK;
+}
+
+// Device memory of the library's own allocator. Blocks come from the
+// device's default stream-ordered pool (its release threshold raised once per
+// device, restored by rcb_release_cache) and, once freed, are kept by the
+// library: a later request on the same device and the same stream that a
+// kept block fits within a factor of two takes it back with no HIP call at
+// all. Reuse on the stream that freed the block is safe in stream order with
+// no event; a free therefore costs no HIP call either (each stream-ordered
+// free put a marker into the stream that held the device for several
+// microseconds between the kernels around it). A device keeps at most a
+// quarter of its memory this way (past that, frees go to the pool). Kept
+// blocks go back to the pool when an allocation fails and in
+// rcb_release_cache, after the device has finished its work (the freeing
+// streams are never used again, so they may have been destroyed by then).
+namespace {
 constexpr int kMaxDevices = 64;
-struct CachedBlock {
+struct KeptBlock {
     void *p;
     size_t bytes;
     int device;
-    hipEvent_t done;   // recorded after the block's last use (null while in use)
+    hipStream_t stream;   // freed on; compared, never used
 };
 std::mutex g_cache_mu;
-std::vector<CachedBlock> g_cached;                   // free, kept for reuse
-std::unordered_map<void *, CachedBlock> g_large;     // large blocks in use
+std::vector<KeptBlock> g_kept;                         // free, kept for reuse
+std::unordered_map<void *, size_t> g_live;             // the library's blocks in use: their size
 bool g_pool_set[kMaxDevices] = {false};
 uint64_t g_pool_thr[kMaxDevices] = {0};
+size_t g_kept_bytes[kMaxDevices] = {0};
+size_t g_kept_cap[kMaxDevices] = {0};
 
-// Returns the kept blocks of `device` (all devices if < 0) to the pool and
-// trims the pool of every device concerned; g_cache_mu held.
-void release_cached_locked(int device) {
+// Returns the kept blocks of `device` (all devices if < 0) to the pool once
+// the device is idle, and trims the pool of every device concerned;
+// g_cache_mu held.
+void release_kept_locked(int device) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     bool touched[kMaxDevices] = {false};
-    for (auto it = g_cached.begin(); it != g_cached.end();) {
+    for (const KeptBlock &b : g_kept)
+        if ((device < 0 || b.device == device) && b.device >= 0 && b.device < kMaxDevices) touched[b.device] = true;
+    for (int d = 0; d < kMaxDevices; ++d) {
+        if (!touched[d]) continue;
+        (void)hipSetDevice(d);
+        (void)hipDeviceSynchronize();   // every kept block's last use has finished
+    }
+    for (auto it = g_kept.begin(); it != g_kept.end();) {
         if (device >= 0 && it->device != device) {
             ++it;
             continue;
         }
         (void)hipSetDevice(it->device);
-        (void)hipEventSynchronize(it->done);   // the block's last use has finished
-        (void)hipEventDestroy(it->done);
         (void)hipFreeAsync(it->p, nullptr);
-        if (it->device >= 0 && it->device < kMaxDevices) touched[it->device] = true;
-        it = g_cached.erase(it);
+        if (it->device >= 0 && it->device < kMaxDevices) g_kept_bytes[it->device] -= it->bytes;
+        it = g_kept.erase(it);
     }
     for (int d = 0; d < kMaxDevices; ++d) {
         if (!touched[d]) continue;
         hipMemPool_t pool;
         (void)hipSetDevice(d);
-        (void)hipStreamSynchronize(nullptr);
+        (void)hipDeviceSynchronize();
         if (hipDeviceGetDefaultMemPool(&pool, d) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
     }
     (void)hipSetDevice(cur);
@@ -96,41 +222,38 @@ void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owne
             uint64_t thr = UINT64_MAX;
             hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
             g_pool_set[t->device] = true;
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) == hipSuccess) g_kept_cap[t->device] = tot / 4;
         }
         (void)hipGetLastError();
     }
+    bytes = (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255;
+    auto pick = g_kept.end();
+    for (auto it = g_kept.begin(); it != g_kept.end(); ++it)
+        if (it->device == t->device && it->stream == s && it->bytes >= bytes && it->bytes <= 2 * bytes &&
+            (pick == g_kept.end() || it->bytes < pick->bytes))
+            pick = it;
     void *p = nullptr;
-    if (bytes == 0) bytes = 16;
-    if (bytes >= kCacheMin) {
-        size_t best = SIZE_MAX;
-        auto pick = g_cached.end();
-        for (auto it = g_cached.begin(); it != g_cached.end(); ++it)
-            if (it->device == t->device && it->bytes >= bytes && it->bytes <= 2 * bytes && it->bytes < best) {
-                best = it->bytes;
-                pick = it;
-            }
-        if (pick != g_cached.end() && hipStreamWaitEvent(s, pick->done, 0) == hipSuccess) {
-            p = pick->p;
-            (void)hipEventDestroy(pick->done);
-            g_large[p] = CachedBlock{p, pick->bytes, t->device, nullptr};
-            g_cached.erase(pick);
-            owner.push_back(p);
-            return p;
-        }
-        (void)hipGetLastError();
+    if (pick != g_kept.end()) {
+        p = pick->p;
+        g_live[p] = pick->bytes;
+        g_kept_bytes[pick->device] -= pick->bytes;
+        g_kept.erase(pick);
+        owner.push_back(p);
+        return p;
     }
     hipError_t e = hipMallocAsync(&p, bytes, s);
-    if (e != hipSuccess && !g_cached.empty()) {
+    if (e != hipSuccess && !g_kept.empty()) {
         (void)hipGetLastError();
-        release_cached_locked(t->device);
+        release_kept_locked(t->device);
         e = hipMallocAsync(&p, bytes, s);
     }
     if (e != hipSuccess) {
         set_error(std::string("hipMallocAsync(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
         (void)hipGetLastError();
         p = nullptr;
-    } else if (bytes >= kCacheMin) {
-        g_large[p] = CachedBlock{p, bytes, t->device, nullptr};
+    } else {
+        g_live[p] = bytes;
     }
     owner.push_back(p);
     return p;
@@ -143,24 +266,26 @@ void dfree(rcb_tree *t, void *p, hipStream_t s) {
         return;
     }
     std::lock_guard<std::mutex> lock(g_cache_mu);
-    auto it = g_large.find(p);
-    if (it != g_large.end()) {
-        CachedBlock b = it->second;
-        g_large.erase(it);
-        if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) == hipSuccess) {
-            if (hipEventRecord(b.done, s) == hipSuccess) {   // after the block's last use on s
-                g_cached.push_back(b);
-                return;
-            }
-            (void)hipEventDestroy(b.done);
-        }
+    auto it = g_live.find(p);
+    if (it == g_live.end()) {   // not the library's (never: every block is registered)
+        (void)hipFreeAsync(p, s);
         (void)hipGetLastError();
+        return;
     }
-    (void)hipFreeAsync(p, s);
+    const size_t bytes = it->second;
+    g_live.erase(it);
+    const int d = t->device;
+    if (d < 0 || d >= kMaxDevices || g_kept_bytes[d] + bytes > g_kept_cap[d]) {
+        (void)hipFreeAsync(p, s);   // past the cap: back to the pool
+        (void)hipGetLastError();
+        return;
+    }
+    g_kept.push_back(KeptBlock{p, bytes, d, s});
+    g_kept_bytes[d] += bytes;
 }
 
 // frees every block in stream order on s (after the tree's last work on its
-// own stream), then waits for s
+// own stream); the memory is reused only by work queued after the frees
 static void free_all(rcb_tree *t, hipStream_t s) {
     if (s != t->stream) {
         hipEvent_t ev;
@@ -176,7 +301,6 @@ static void free_all(rcb_tree *t, hipStream_t s) {
     for (void *p : t->allocs) dfree(t, p, s);
     t->list_allocs.clear();
     t->allocs.clear();
-    (void)hipStreamSynchronize(s);
 }
 
 }  // namespace rcb
@@ -485,7 +609,7 @@ void rcb_destroy(rcb_tree *t, void *stream) {
 
 void rcb_release_cache(void) {
     std::lock_guard<std::mutex> lock(g_cache_mu);
-    release_cached_locked(-1);
+    release_kept_locked(-1);
     int cur = 0;
     (void)hipGetDevice(&cur);
     for (int d = 0; d < kMaxDevices; ++d) {

@@ -84,6 +84,7 @@ struct rcb_tree {
     bool leaf_lists = false;
     int64_t near_total = -1, far_total = -1;
     int64_t *near_off = nullptr, *far_off = nullptr;
+    void *walk_ws = nullptr;   // the walk's per-group counts, queues and statistics (kept for later walks)
     int32_t *near_list = nullptr, *far_list = nullptr;
     int64_t nb_total = -1;             // neighbour total of the last count call
     int32_t *nb_slab = nullptr;        // neighbour ids of the count call, kNbCap per particle
@@ -120,6 +121,26 @@ namespace rcb {
 void set_error(const std::string &msg);
 rcb_status hip_fail(hipError_t e, const char *what);
 void *dalloc(rcb_tree *t, size_t bytes, hipStream_t s, std::vector<void *> &owner);
+// Small device values read by the host once the work queued on s before them
+// has run, without synchronising the stream: a one-thread kernel copies them
+// into coherent pinned memory (one buffer per host thread) and writes a
+// sequence number after them, which the host polls. Each item is a multiple
+// of 4 bytes, 4-byte aligned; at most kReadItems items of kReadBytes in all.
+constexpr int kReadItems = 8;
+constexpr int kReadBytes = 128;
+struct HostRead {
+    const void *src;   // device
+    void *dst;         // host
+    int bytes;
+};
+rcb_status read_small(hipStream_t s, const HostRead *items, int n, const char *what);
+// Zeroes `bytes` (a multiple of 4, 4-byte aligned) at p in stream order with a
+// kernel of the library (hipMemsetAsync's fill left the device idle for tens
+// of microseconds before it, and cannot go into a captured graph).
+rcb_status zero_async(void *p, size_t bytes, hipStream_t s);
+// Polls host word w until it equals seq (the stream is queried only once the
+// wait is long, for errors); a report that does not come ends with an error.
+rcb_status wait_host_word(volatile int32_t *w, int32_t seq, hipStream_t s, const char *what);
 // releases a dalloc block in stream order (large blocks stay cached for reuse)
 void dfree(rcb_tree *t, void *p, hipStream_t s);
 
@@ -292,6 +313,11 @@ __device__ __forceinline__ double dist2(double ax, double ay, double az, double 
         if (_e != hipSuccess) return rcb::hip_fail(_e, #expr); \
     } while (0)
 
+#define RCB_ZERO(p, bytes, stream)                                     \
+    do {                                                               \
+        rcb_status _z = rcb::zero_async((p), (bytes), (stream));       \
+        if (_z != RCB_OK) return _z;                                   \
+    } while (0)
 #define RCB_LAUNCH_CHECK(name)                                   \
     do {                                                         \
         hipError_t _e = hipGetLastError();                       \
