@@ -584,13 +584,26 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
         const HostRead r[2] = {{t->dflag, flags, (int)sizeof(flags)}, {stats, hstats, (int)sizeof(hstats)}};
         return read_small(s, r, 2, "rcb_walk");
     };
+    // the slab lists' ends per group (in the common case, that no list
+    // outgrew its slab); launched before the flags are read, again if the
+    // later tiers rewrote some counts
+    int64_t *ends = (int64_t *)dalloc(t, sizeof(int64_t) * 4 * NG, s, t->list_allocs);
+    if (!ends) return RCB_ENOMEM;
+    auto slab_ends = [&]() -> rcb_status {
+        k_slab_ends<<<(unsigned)((NG + kBlock - 1) / kBlock), kBlock, 0, s>>>(NG, cn, cf, ncnt, fcnt, ends, ends + NG,
+                                                                              ends + 2 * NG, ends + 3 * NG);
+        RCB_LAUNCH_CHECK("k_slab_ends");
+        return RCB_OK;
+    };
     auto walk_tiers = [&](bool count_queues) -> rcb_status {
         int32_t *q1 = count_queues ? queue : nullptr, *q2 = count_queues ? queue2 : nullptr;
         if (pure) k_walk_wide<true, kWQueue, kWaves><<<grid, kBlock, 0, s>>>(w, q1, t->dflag + 6, nullptr, 0, cap1);
         else k_walk_wide<false, kWQueue, kWaves><<<grid, kBlock, 0, s>>>(w, q1, t->dflag + 6, nullptr, 0, cap1);
         RCB_LAUNCH_CHECK("k_walk_wide");
         if (count_queues) {
-            rcb_status st = read_flags();
+            rcb_status st = slab_ends();
+            if (st != RCB_OK) return st;
+            st = read_flags();
             if (st != RCB_OK) return st;
             nq = flags[6];
         }
@@ -630,15 +643,14 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     }
     const int32_t nlong = flags[1];
     if (flags[3] == 0) {
-        int64_t *ends = (int64_t *)dalloc(t, sizeof(int64_t) * 4 * NG, s, t->list_allocs);
-        if (!ends) return RCB_ENOMEM;
+        if (nq > 0) {   // the later tiers rewrote the counts of their groups
+            rcb_status st = slab_ends();
+            if (st != RCB_OK) return st;
+        }
         t->gnear_beg = ends;
         t->gnear_end = ends + NG;
         t->gfar_beg = ends + 2 * NG;
         t->gfar_end = ends + 3 * NG;
-        k_slab_ends<<<(unsigned)((NG + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-            NG, cn, cf, ncnt, fcnt, t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end);
-        RCB_LAUNCH_CHECK("k_slab_ends");
         t->gnear = nslab;
         t->gfar = fslab;
         for (void *p : slabs) {
