@@ -99,6 +99,7 @@ def main():
         acc = t.gravity()
         rec(4)
         if keep:
+            t.kept_ids = ids   # the CSR stays alive with the tree
             return t, acc, off
         t.destroy()
         return None, acc, off
@@ -127,20 +128,28 @@ def main():
     # other tree has been made
     mem = None
     if not a.no_extras:
+        from paper_1108_0028_amd import release_cache
         torch.cuda.synchronize()
         free0 = torch.cuda.mem_get_info()[0]
-        t_keep, _, off_keep = step(a.precision, keep=True)
+        t_keep, acc_keep, off_keep = step(a.precision, keep=True)
         torch.cuda.synchronize()
         free1 = torch.cuda.mem_get_info()[0]
+        # the same with the caches emptied: what the live tree, its lists and
+        # the step's outputs hold (the library's scratch of the step went back)
+        release_cache()
+        torch.cuda.empty_cache()
+        free2 = torch.cuda.mem_get_info()[0]
         mem = {"bytes": int(free0 - free1), "bytes_per_particle": (free0 - free1) / n,
-               "basis": "device memory taken by one live step (tree, lists, neighbour slab and CSR, "
-                        "accelerations), from hipMemGetInfo"}
+               "live_bytes_per_particle": (free0 - free2) / n,
+               "basis": "device memory taken by one step, from hipMemGetInfo: bytes = held after the step "
+                        "(the live tree with its lists and neighbour search state, the accelerations and "
+                        "offsets, and the scratch the library and torch keep for the next step); "
+                        "live_bytes_per_particle = the same once their kept scratch is released"}
         t_keep.destroy()
-        del off_keep
+        del off_keep, acc_keep
         # the neighbour search alone: its scratch (slab, overflow pool, queues)
         # and the CSR it returns, on a walked tree, with the library's and
         # torch's caches emptied first
-        from paper_1108_0028_amd import release_cache
         torch.cuda.synchronize()
         release_cache()
         torch.cuda.empty_cache()
