@@ -243,13 +243,10 @@ __global__ __launch_bounds__(kBlock) void k_gravity(GravArgs g) {
                         const T vx = xa - s.x, vy = ya - s.y, vz = za - s.z;
                         const T r2 = (vx * vx + vy * vy) + vz * vz;
                         const T hsum = ha + s.h;
-                        T F;
-                        if (soft_outside<T>(r2, hsum)) {   // most pairs: the rest of soft_F is skipped
-                            const T ri = rsq_t(r2);
-                            F = ri * ri * ri;
-                        } else {
-                            F = soft_F<T>(r2, hsum);
-                        }
+                        const T ri = rsq_t(r2);
+                        const T r3 = ri * ri * ri;
+                        T F = r3;
+                        if (!soft_outside<T>(r2, hsum)) F = soft_F<T>(r2, ri, r3, hsum);
                         F *= s.m;
                         ax -= F * vx;
                         ay -= F * vy;

@@ -356,25 +356,21 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
                     tile_sync();
                     const int nt = tot - t < kWave ? tot - t : kWave;
                     const int rows = (nt + L.J - 1) / L.J;
-                    const int r0 = L.sslot % rows;
-                    for (int st = 0; st < rows; ++st) {
-                        int r = r0 + st;
-                        if (r >= rows) r -= rows;
-                        const int j = r * L.J + L.slice;
+                    // sink slot s starts at row s mod rows, so that the lanes of
+                    // one step add into different sources
+                    const int span = rows * L.J;
+                    int j = (L.sslot % rows) * L.J + L.slice;
+                    for (int st = 0; st < rows; ++st, j = j + L.J < span ? j + L.J : j + L.J - span) {
                         if (has_sink && j < nt) {
                             const T v[3] = {sx - sh.t.x[j], sy - sh.t.y[j], sz - sh.t.z[j]};
                             const T r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
                             const T hsum = ha + sh.t.h[j];
-                            T F, dFr;
-                            if (soft_outside<T>(r2, hsum)) {   // most pairs: r^-3 and -3 r^-5
-                                const T ri = rsq_t(r2);
-                                const T ri2 = ri * ri;
-                                const T r3 = ri2 * ri;
-                                F = r3;
-                                dFr = (T)-3 * (r3 * ri2);
-                            } else {
-                                soft_FdF<T>(r2, hsum, F, dFr);
-                            }
+                            const T ri = rsq_t(r2);
+                            const T ri2 = ri * ri;
+                            const T r3 = ri2 * ri;
+                            const T r5 = r3 * ri2;
+                            T F = r3, dFr = (T)-3 * r5;
+                            if (!soft_outside<T>(r2, hsum)) soft_FdF<T>(r2, ri, r3, r5, hsum, F, dFr);
                             const T vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
                             const T mb = sh.t.m[j];
 #pragma unroll

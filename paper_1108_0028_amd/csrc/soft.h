@@ -8,9 +8,9 @@
 //   h^-5 (-12/5 + 3/2 q)                                   q < 1
 //   h^-5 (12/5 - 1/2 q) - 3 h^-4 / r + r^-5 / 5            1 <= q < 2
 //   -3 r^-5                                                q >= 2
-// Branch-free: the two inner pieces share one polynomial whose coefficients
-// are selected by q < 1. Arguments are r^2 and h_a + h_b; r^2 below the
-// smallest normal number is taken as 0 (the pair then adds nothing).
+// The two inner pieces share one polynomial whose coefficients are selected
+// by q < 1 (no branch). Arguments are r^2, h_a + h_b and the caller's powers
+// of 1/r.
 #pragma once
 
 #include "far_math.h"
@@ -32,22 +32,24 @@ __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x
 __device__ __forceinline__ double rcp_t(double x) { return rcbfar::rcp64(x); }
 
 // True when the pair is certainly outside the kernel support whatever the
-// rounding of q: r^2 >= (h_a + h_b)^2 (1 + 2^-16) + r2_min. soft_F then
-// returns r^-3 (rinv * rinv * rinv) and soft_FdF r^-3 and -3 r^-5, which the
-// caller may compute directly; the margin (far above the few-ulp errors of
-// q) keeps the two identical.
+// rounding of q: r^2 >= (h_a + h_b)^2 (1 + 2^-16) + r2_min. F is then r^-3
+// and dF/dr / r is -3 r^-5, as soft_F and soft_FdF would return them; the
+// margin (far above the few-ulp errors of q) keeps the two identical.
 template <typename T>
 __device__ __forceinline__ bool soft_outside(T r2, T hsum) {
     return r2 >= (hsum * (T)(1.0 + 1.0 / 65536.0)) * hsum + r2_min<T>();
 }
 
+// The callers compute rinv = rsq_t(r2), r3 = rinv^3 (and r5 = r3 rinv^2) for
+// every pair and call these only for pairs not certainly outside, which reuse
+// them. r^2 below r2_min is taken as 0 here (rinv is inf there): q = 0, and
+// the pair, whose offset is then zero or below 1e-19, adds nothing.
 template <typename T>
-__device__ __forceinline__ T soft_F(T r2, T hsum) {
-    const T rinv = r2 >= r2_min<T>() ? rsq_t(r2) : (T)0;
+__device__ __forceinline__ T soft_F(T r2, T rinv, T r3, T hsum) {
+    const T ri = r2 >= r2_min<T>() ? rinv : (T)0;
     const T hinv = (T)2 * rcp_t(hsum);
-    const T q = r2 * rinv * hinv;
+    const T q = r2 * ri * hinv;
     const T h3 = hinv * hinv * hinv;
-    const T r3 = rinv * rinv * rinv;
     const bool in = q < (T)1;
     const T k0 = in ? (T)(4.0 / 3.0) : (T)(8.0 / 3.0);
     const T k1 = in ? (T)0 : (T)-3;
@@ -59,17 +61,14 @@ __device__ __forceinline__ T soft_F(T r2, T hsum) {
 }
 
 template <typename T>
-__device__ __forceinline__ void soft_FdF(T r2, T hsum, T &F, T &dFr) {
-    const T rinv = r2 >= r2_min<T>() ? rsq_t(r2) : (T)0;
+__device__ __forceinline__ void soft_FdF(T r2, T rinv, T r3, T r5, T hsum, T &F, T &dFr) {
+    const T ri = r2 >= r2_min<T>() ? rinv : (T)0;
     const T hinv = (T)2 * rcp_t(hsum);
-    const T q = r2 * rinv * hinv;
+    const T q = r2 * ri * hinv;
     const T h2 = hinv * hinv;
     const T h3 = h2 * hinv;
     const T h4 = h2 * h2;
     const T h5 = h4 * hinv;
-    const T ri2 = rinv * rinv;
-    const T r3 = ri2 * rinv;
-    const T r5 = r3 * ri2;
     const bool in = q < (T)1, near = q < (T)2;
     const T k0 = in ? (T)(4.0 / 3.0) : (T)(8.0 / 3.0);
     const T k1 = in ? (T)0 : (T)-3;
@@ -79,7 +78,7 @@ __device__ __forceinline__ void soft_FdF(T r2, T hsum, T &F, T &dFr) {
     const T d1 = in ? (T)1.5 : (T)-0.5;
     const T poly = k0 + q * (k1 + q * (k2 + q * k3));
     const T tail = in ? (T)0 : r3 * (T)(1.0 / 15.0);
-    const T dtail = in ? (T)0 : (T)0.2 * r5 - (T)3 * h4 * rinv;
+    const T dtail = in ? (T)0 : (T)0.2 * r5 - (T)3 * h4 * ri;
     F = near ? h3 * poly - tail : r3;
     dFr = near ? h5 * (d0 + d1 * q) + dtail : (T)-3 * r5;
 }
