@@ -524,10 +524,14 @@ __global__ __launch_bounds__(kBlock) void k_expand(int64_t nleaf, int gk,
 }  // namespace
 
 // Slab capacities: 1024 near and up to 16384 far entries per group, within
-// a budget of about 8 GB for both slabs (at 4M particles and theta = 0.7 the
-// group lists average ~170 near and ~2150 far entries).
-static void slab_caps(int64_t ngroup, int64_t &cn, int64_t &cf) {
-    const int64_t budget = (int64_t)8 << 30;
+// a budget for both slabs of 8 GB or 480 bytes per particle, whichever is
+// larger. At 4M particles and theta = 0.7 the group lists average ~170 near
+// and ~2150 far entries; at depth 23 (67M-1e8 particles, 2^20 groups) the
+// per-particle budget leaves 2816-4672 far entries per group, enough for the
+// clustered test cloud's lists, so that the walk runs once. n = 0 gives the
+// 8 GB budget alone (the fallback when the larger slabs cannot be had).
+static void slab_caps(int64_t ngroup, int64_t n, int64_t &cn, int64_t &cf) {
+    const int64_t budget = std::max<int64_t>((int64_t)8 << 30, 480 * n);
     cn = 1024;
     cf = budget / (8 * ngroup) - cn;
     cf = std::min<int64_t>(16384, std::max<int64_t>(1024, cf & ~(int64_t)63));
@@ -552,11 +556,16 @@ rcb_status ensure_walk(rcb_tree *t, hipStream_t s) {
     unsigned long long *stats = (unsigned long long *)(fcnt + NG);
     int32_t *queue = (int32_t *)(stats + 2);    // groups for the 2nd tier
     int32_t *queue2 = queue + NG;               // and for k_walk_group
-    int64_t cn, cf;
-    slab_caps(NG, cn, cf);
+    int64_t cn = 0, cf = 0;
     std::vector<void *> slabs;
-    uint64_t *nslab = (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cn, s, slabs);
-    uint64_t *fslab = (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cf, s, slabs);
+    uint64_t *nslab = nullptr, *fslab = nullptr;
+    for (int attempt = 0; attempt < 2 && !(nslab && fslab); ++attempt) {
+        for (void *p : slabs) dfree(t, p, s);
+        slabs.clear();
+        slab_caps(NG, attempt == 0 ? t->n : 0, cn, cf);
+        nslab = (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cn, s, slabs);
+        fslab = nslab ? (uint64_t *)dalloc(t, sizeof(uint64_t) * NG * cf, s, slabs) : nullptr;
+    }
     for (void *p : slabs) tmp.push_back(p);   // freed at the end unless kept
     if (!nslab || !fslab) return RCB_ENOMEM;
     // RCB_WALK_WIDE_STACK (testing): smaller wide-walk rings, so that more
