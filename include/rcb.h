@@ -101,6 +101,13 @@ typedef struct {
                            through reachable cells only */
     int32_t split;      /* rcb_split: where a cell is cut; moments always use the masses */
     int32_t taylor_reading;   /* rcb_taylor_reading of the far-field sink coefficients */
+    int32_t deterministic;    /* 0: rcb_gravity_vjp adds source-side near-field terms and node
+                                 adjoints with atomics (fastest; reproducible to rounding);
+                                 1: no atomics -- per-node and per-cell lists of the groups
+                                 that hold each node or cell are made by a stable sort, and
+                                 every sum runs in a fixed order, so repeated calls give the
+                                 same bits (more time and 16 B of device memory per entry
+                                 of the per-group lists) */
     /* Optional workspace allocator, both or neither (NULL: the library
        allocates from the device's stream-ordered pool and keeps freed blocks
        for reuse on the stream that freed them). alloc(bytes, stream, ctx) returns device
@@ -114,7 +121,7 @@ typedef struct {
 } rcb_params;
 
 /* Paper defaults: n_ll = 12, theta = 0.7, FP64, validate = 0, pure_mac = 0,
-   split = RCB_SPLIT_MASS, taylor_reading = RCB_READING_A. */
+   split = RCB_SPLIT_MASS, taylor_reading = RCB_READING_A, deterministic = 0. */
 void rcb_params_default(rcb_params *p);
 
 /*
@@ -265,10 +272,15 @@ rcb_status rcb_gravity(rcb_tree *t, void *ax, void *ay, void *az, void *stream);
  * writes dL/dx, dL/dy, dL/dz and dL/dm. h gets no gradient. Near-field pairs
  * are recomputed, not stored. g*: n values, d*: n values, FP64 for RCB_FP64
  * and FP32 for RCB_MIXED. Valid after rcb_build() (gravity need not have run).
- * Summation order: the source-side near-field terms and the node adjoints
- * are added with atomics (FP64; FP32 in the mixed form), so two calls agree
- * to rounding, not bit for bit. There is no atomic-free (deterministic)
- * variant, and rcb_params has no switch asking for one.
+ * Summation order: with deterministic = 0 the source-side near-field terms
+ * and the node adjoints are added with atomics (FP64; FP32 in the mixed
+ * form), so two calls agree to rounding, not bit for bit. With
+ * deterministic = 1 nothing is added atomically: each node's adjoint is
+ * summed over the groups that accepted it (ascending group, fixed chunks of
+ * 512 entries, then the chunks in order) and each source particle's terms
+ * over the sink cells whose near list holds its cell, in FP64 in both forms;
+ * two calls on the same tree and inputs give identical outputs. The lists
+ * of groups per node and per cell are made on each call (stable label sort).
  * Errors: RCB_EINVAL (NULL argument, or a tree built with RCB_READING_B).
  */
 rcb_status rcb_gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *gz,

@@ -45,7 +45,7 @@ _TORCH_FREE = _FREE_FN(_torch_free)
 class RcbParams(C.Structure):
     _fields_ = [("n_ll", C.c_int32), ("precision", C.c_int32), ("theta", C.c_double),
                 ("validate", C.c_int32), ("pure_mac", C.c_int32),
-                ("split", C.c_int32), ("taylor_reading", C.c_int32),
+                ("split", C.c_int32), ("taylor_reading", C.c_int32), ("deterministic", C.c_int32),
                 ("alloc", _ALLOC_FN), ("free", _FREE_FN), ("alloc_ctx", C.c_void_p)]
 
 
@@ -139,13 +139,15 @@ class Tree:
 
     def __init__(self, x, y, z, m, h, n_ll: int = 12, theta: float = 0.7, precision: str = "fp64",
                  validate: bool = False, pure_mac: bool = False, split: str = "mass",
-                 taylor_reading: str = "A", allocator: str = "library"):
+                 taylor_reading: str = "A", allocator: str = "library",
+                 deterministic: bool = False):
         """split: "mass" (planes through the centre of mass, the paper's),
         "number" (through the centre of number) or "median" (median position
         split: equal halves). taylor_reading: "A" (J, H of the full field) or
         "B" (J, H of the monopole field; no VJP). allocator: "library" (the
         library's stream-ordered pool) or "torch" (workspace from PyTorch's
-        caching allocator through rcb_params.alloc / free)."""
+        caching allocator through rcb_params.alloc / free). deterministic:
+        the VJP adds nothing atomically and repeats bit for bit."""
         L = lib()
         arrs = [_dev(a, torch.float64, nm) for a, nm in zip((x, y, z, m, h), "xyzmh")]
         n = arrs[0].numel()
@@ -161,6 +163,7 @@ class Tree:
         p.pure_mac = 1 if pure_mac else 0
         p.split = {"mass": 0, "number": 1, "median": 2}[split]
         p.taylor_reading = {"A": 0, "B": 1}[taylor_reading]
+        p.deterministic = 1 if deterministic else 0
         if allocator == "torch":
             p.alloc = _TORCH_ALLOC
             p.free = _TORCH_FREE

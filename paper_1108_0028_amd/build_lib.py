@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "librcb.so")
 ARCH = os.environ.get("RCB_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["rcb_api.hip", "k_build.hip", "k_scan.hip", "k_walk.hip", "k_neigh.hip", "k_grav.hip",
-           "k_vjp.hip"]
+           "k_vjp.hip", "k_sort.hip"]
 CONTRACT = {"k_grav.hip": "-ffp-contract=fast", "k_vjp.hip": "-ffp-contract=fast"}
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result",

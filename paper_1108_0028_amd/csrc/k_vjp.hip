@@ -162,7 +162,9 @@ struct VjpFarShared {
 
 // AT: the type of the node-adjoint copies (FP64; FP32 in the mixed form, whose
 // contract allows FP32 accumulation), summed in FP64 by k_adj_reduce
-template <typename AT>
+// NODES = false (the deterministic form): only the sink-centre sums; the node
+// adjoints are summed per node by k_vjp_far_node instead.
+template <typename AT, bool NODES>
 __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a, AT *__restrict__ adjc, AT *__restrict__ adjmc) {
     __shared__ VjpFarShared sh_all[kWaves];
     VjpFarShared &sh = sh_all[threadIdx.x / kWave];
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a, AT *__restrict__ 
                 if (!(lane & 1)) cotp[i][u][lane >> 1] += t;
             }
         }
-        if (emask) {
+        if (NODES && emask) {
             // each copy takes the blocks of one residue mod the number of
             // copies, i.e. of one XCD under round-robin dispatch (8 | copies)
             if (B < a.nmid) {
@@ -282,7 +284,9 @@ struct VjpShared {
     VjpTile<T> t;
 };
 
-template <bool MIXED>
+// SRC = false (the deterministic form): sink-side terms only; the source-side
+// terms are summed per source cell by k_vjp_near_src instead.
+template <bool MIXED, bool SRC>
 __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
     using T = typename std::conditional<MIXED, float, double>::type;
     __shared__ VjpShared<T> sh_all[kWaves];
@@ -377,13 +381,13 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
                             for (int cc = 0; cc < 3; ++cc) {
                                 const T Kg = mb * (F * ga[cc] + dFr * v[cc] * vg);
                                 acc[cc] -= (double)Kg;
-                                atomicAdd(&sh.t.acc[cc][j], (double)Kg);
+                                if (SRC) atomicAdd(&sh.t.acc[cc][j], (double)Kg);
                             }
-                            atomicAdd(&sh.t.acc[3][j], (double)(-F * vg));
+                            if (SRC) atomicAdd(&sh.t.acc[3][j], (double)(-F * vg));
                         }
                     }
                     tile_sync();
-                    if (lane < nt) {
+                    if (SRC && lane < nt) {
                         const double s0 = sh.t.acc[0][lane], s1 = sh.t.acc[1][lane],
                                      s2 = sh.t.acc[2][lane], s3 = sh.t.acc[3][lane];
                         if (s0 != 0.0 || s1 != 0.0 || s2 != 0.0 || s3 != 0.0) {
@@ -532,6 +536,391 @@ __global__ void k_adj_reduce(double *out, const A *adjc, const A *__restrict__ a
     out[i] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Deterministic form: no atomics. The per-group lists are turned into lists
+// of the groups that hold each node (far) or each lowest-level cell (near),
+// ascending by group (k_sort.hip), and every sum runs in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kDetChunk = 512;   // far entries per wave of k_vjp_far_node
+
+// cotangent moments without atomics: the group's leaves in turn, 64 particles
+// at a time, each of the 30 sums a canonical wave sum (wave_sum)
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_vjp_moments_det(VjpArgs a) {
+    const int64_t gi = wave_index();
+    if (gi >= a.ngroup) return;
+    const int lane = lane_id();
+    const int G = 1 << a.gk;
+    for (int li = 0; li < G; ++li) {
+        const int64_t A = a.nleaf + gi * G + li;
+        const int32_t sA = a.nfirst[A], c = a.ncount[A];
+        double m[kAcc];
+#pragma unroll
+        for (int q = 0; q < kAcc; ++q) m[q] = 0.0;
+        for (int s0 = 0; s0 < c; s0 += kWave) {
+            const int si = s0 + lane;
+            double g[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0};
+            if (si < c) {
+                const int32_t p = sA + si;
+                const int32_t o = a.pid[p];
+                g[0] = load_g<MIXED>(a.gx, o);
+                g[1] = load_g<MIXED>(a.gy, o);
+                g[2] = load_g<MIXED>(a.gz, o);
+                d[0] = a.px[p] - a.ncom[3 * A];
+                d[1] = a.py[p] - a.ncom[3 * A + 1];
+                d[2] = a.pz[p] - a.ncom[3 * A + 2];
+            }
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                m[u] += wave_sum(g[u]);
+#pragma unroll
+                for (int l = 0; l < 3; ++l) m[3 + 3 * u + l] += wave_sum(g[u] * d[l]);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    const int l = k < 3 ? 0 : (k < 5 ? 1 : 2);
+                    const int mm = k < 3 ? k : (k < 5 ? k - 2 : 2);
+                    m[12 + 6 * u + k] += wave_sum(g[u] * d[l] * d[mm]);
+                }
+            }
+        }
+        if (lane == 0) {
+            rcbfar::SymMoments S;
+            rcbfar::sym_moments(m, m + 3, m + 12, S);
+            double *o = a.mom + (gi * G + li) * kMom;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) o[q] = S.S1[q];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) o[3 + q] = S.S2[q];
+#pragma unroll
+            for (int q = 0; q < 10; ++q) o[9 + q] = S.S3[q];
+            o[19] = S.t1;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) o[20 + q] = S.sg[q];
+        }
+    }
+}
+
+// entries per group
+__global__ void k_det_count(const int64_t *__restrict__ beg, const int64_t *__restrict__ end,
+                            int64_t ngroup, int64_t *__restrict__ cnt) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g < ngroup) cnt[g] = end[g] - beg[g];
+}
+
+// item = label << 32 | group << 8 | mask (bits 32-39 of the list entry: the far
+// mask, or the near mask), written in group order at the group's offset
+__global__ __launch_bounds__(kBlock) void k_det_items(const int64_t *__restrict__ beg,
+                                                      const int64_t *__restrict__ end,
+                                                      const uint64_t *__restrict__ list, int64_t ngroup,
+                                                      const int64_t *__restrict__ base,
+                                                      uint64_t *__restrict__ items) {
+    const int64_t gi = wave_index();
+    if (gi >= ngroup) return;
+    const int64_t e0 = beg[gi], ne = end[gi] - e0, o = base[gi];
+    for (int64_t j = lane_id(); j < ne; j += kWave) {
+        const uint64_t ent = list[e0 + j];
+        const uint64_t lab = (uint32_t)ent & 0x7fffffffu;
+        const uint64_t mask = (ent >> 32) & 0xffu;
+        items[o + j] = (lab << 32) | ((uint64_t)gi << 8) | mask;
+    }
+}
+
+// each label's range [lb, le) in the sorted items (lb = le = 0 if absent)
+__global__ void k_det_bounds(const uint64_t *__restrict__ it, int64_t n, int64_t *__restrict__ lb,
+                             int64_t *__restrict__ le) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t B = (uint32_t)(it[i] >> 32);
+    if (i == 0 || (uint32_t)(it[i - 1] >> 32) != B) lb[B] = i;
+    if (i == n - 1 || (uint32_t)(it[i + 1] >> 32) != B) le[B] = i + 1;
+}
+
+// chunks of kDetChunk entries per label
+__global__ void k_det_nchunk(const int64_t *__restrict__ lb, const int64_t *__restrict__ le,
+                             int64_t nlab, int64_t *__restrict__ nc) {
+    const int64_t B = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (B < nlab) nc[B] = (le[B] - lb[B] + kDetChunk - 1) / kDetChunk;
+}
+
+__global__ void k_det_owner(const int64_t *__restrict__ cb, int64_t nlab, int32_t *__restrict__ owner) {
+    const int64_t B = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (B >= nlab) return;
+    for (int64_t c = cb[B]; c < cb[B + 1]; ++c) owner[c] = (int32_t)B;
+}
+
+// node adjoints, one wave per chunk of one node's entries: lanes over the
+// entries (group, far mask), each summing the node's adjoint over the leaves
+// of its mask in order; the chunk's sum is a canonical wave sum
+__global__ __launch_bounds__(kBlock) void k_vjp_far_node(VjpArgs a, const uint64_t *__restrict__ items,
+                                                         const int64_t *__restrict__ lb,
+                                                         const int64_t *__restrict__ le,
+                                                         const int64_t *__restrict__ cb,
+                                                         const int32_t *__restrict__ owner, int64_t nchunk,
+                                                         double *__restrict__ part) {
+    const int64_t c = wave_index();
+    if (c >= nchunk) return;
+    const int lane = lane_id();
+    const int G = 1 << a.gk;
+    const int64_t B = __builtin_amdgcn_readfirstlane(owner[c]);
+    const int64_t e_beg = lb[B] + (c - cb[B]) * kDetChunk;
+    const int64_t e_end = e_beg + kDetChunk < le[B] ? e_beg + kDetChunk : le[B];
+    double qq[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) qq[q] = a.nQ[6 * B + q];
+    const double cB[3] = {a.ncom[3 * B], a.ncom[3 * B + 1], a.ncom[3 * B + 2]};
+    const double MB = a.nM[B];
+    double ad[kAdj];
+#pragma unroll
+    for (int q = 0; q < kAdj; ++q) ad[q] = 0.0;
+    for (int64_t e0 = e_beg; e0 < e_end; e0 += kWave) {
+        const int64_t e = e0 + lane;
+        if (e >= e_end) continue;
+        const uint64_t it = items[e];
+        const int64_t gi = (uint32_t)it >> 8;
+        const uint32_t mask = (uint32_t)it & 0xffu;
+        for (int i = 0; i < G; ++i) {
+            if (!((mask >> i) & 1u)) continue;
+            const int64_t leaf = gi * G + i;
+            const int64_t A = a.nleaf + leaf;
+            const double *mo = a.mom + leaf * kMom;
+            rcbfar::SymMoments Sm;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) Sm.S1[q] = mo[q];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) Sm.S2[q] = mo[3 + q];
+#pragma unroll
+            for (int q = 0; q < 10; ++q) Sm.S3[q] = mo[9 + q];
+            Sm.t1 = mo[19];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) Sm.sg[q] = mo[20 + q];
+            double rho[3], ct[3] = {0.0, 0.0, 0.0}, aM, aQ[6];
+            rcbfar::far_pair_adjoint_sym(a.ncom[3 * A] - cB[0], a.ncom[3 * A + 1] - cB[1],
+                                         a.ncom[3 * A + 2] - cB[2], MB, qq, Sm, rho, ct, aM, aQ);
+            ad[0] += aM;
+#pragma unroll
+            for (int u = 0; u < 3; ++u) ad[1 + u] -= rho[u];
+            const double tq = (aQ[0] + aQ[3] + aQ[5]) / 3.0;
+            ad[4] += aQ[0] - tq;
+            ad[5] += aQ[1];
+            ad[6] += aQ[2];
+            ad[7] += aQ[3] - tq;
+            ad[8] += aQ[4];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kAdj; ++q) {
+        const double v = wave_sum(ad[q]);
+        if (lane == 0) part[c * kAdj + q] = v;
+    }
+}
+
+// adj[q * nlab + B] = sum of the node's chunk sums in chunk order (0 if none)
+__global__ void k_det_adj_sum(const double *__restrict__ part, const int64_t *__restrict__ cb, int64_t nlab,
+                              double *__restrict__ adj) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= kAdj * nlab) return;
+    const int64_t q = i / nlab, B = i % nlab;
+    double v = 0.0;
+    for (int64_t c = cb[B]; c < cb[B + 1]; ++c) v += part[c * kAdj + q];
+    adj[i] = v;
+}
+
+// source-side near terms, one wave per lowest-level cell B: lanes (source
+// slot, slice) over B's particles as in leaf_lanes; the sink cells A whose
+// near list holds B (the groups ascending, then the cells of the near mask)
+// are staged 64 particles at a time in LDS, and each slice takes every J-th
+// sink. The pair arithmetic is that of k_vjp_near; the slices' sums are
+// combined by seg_sum and written (no atomics: B owns its particles).
+template <typename T>
+struct SinkTile {
+    T x[kWave], y[kWave], z[kWave], h[kWave], g[3][kWave];
+};
+
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_vjp_near_src(VjpArgs a, const uint64_t *__restrict__ items,
+                                                         const int64_t *__restrict__ lb,
+                                                         const int64_t *__restrict__ le) {
+    using T = typename std::conditional<MIXED, float, double>::type;
+    __shared__ SinkTile<T> sh_all[kWaves];
+    SinkTile<T> &sh = sh_all[threadIdx.x / kWave];
+    const int64_t bl = wave_index();
+    if (bl >= a.nleaf) return;
+    const int lane = lane_id();
+    const int G = 1 << a.gk;
+    const int64_t B = a.nleaf + bl;
+    const int32_t sB = a.nfirst[B], c = a.ncount[B];
+    if (c == 0) return;
+    const LeafLanes L = leaf_lanes(c);
+    const int64_t e_beg = lb[B], e_end = le[B];
+    const double cB[3] = {a.ncom[3 * B], a.ncom[3 * B + 1], a.ncom[3 * B + 2]};
+    for (int g0 = 0; g0 < c; g0 += L.S) {
+        const int si = g0 + L.sslot;
+        const bool has_src = L.sslot < L.S && si < c;
+        const int32_t pb = sB + (has_src ? si : 0);
+        T mb, hb;
+        if constexpr (MIXED) {
+            mb = a.fm[pb];
+            hb = a.fh[pb];
+        } else {
+            mb = a.pm[pb];
+            hb = a.ph[pb];
+        }
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t e = e_beg; e < e_end; ++e) {
+            const uint64_t it = items[e];
+            const int64_t gi = (uint32_t)it >> 8;
+            const uint32_t mask = (uint32_t)it & 0xffu;
+            for (int li = 0; li < G; ++li) {
+                if (!((mask >> li) & 1u)) continue;
+                const int64_t A = a.nleaf + gi * G + li;
+                const int32_t sA = a.nfirst[A], cA = a.ncount[A];
+                T bx, by, bz;   // the source in the frame of the sink cell's particles
+                if constexpr (MIXED) {
+                    bx = (float)(cB[0] - a.ncom[3 * A]) + a.fdx[pb];
+                    by = (float)(cB[1] - a.ncom[3 * A + 1]) + a.fdy[pb];
+                    bz = (float)(cB[2] - a.ncom[3 * A + 2]) + a.fdz[pb];
+                } else {
+                    bx = a.px[pb];
+                    by = a.py[pb];
+                    bz = a.pz[pb];
+                }
+                for (int t0 = 0; t0 < cA; t0 += kWave) {
+                    const int q = t0 + lane;
+                    if (q < cA) {
+                        const int32_t pa = sA + q;
+                        const int32_t oa = a.pid[pa];
+                        if constexpr (MIXED) {
+                            sh.x[lane] = a.fdx[pa];
+                            sh.y[lane] = a.fdy[pa];
+                            sh.z[lane] = a.fdz[pa];
+                            sh.h[lane] = a.fh[pa];
+                        } else {
+                            sh.x[lane] = a.px[pa];
+                            sh.y[lane] = a.py[pa];
+                            sh.z[lane] = a.pz[pa];
+                            sh.h[lane] = a.ph[pa];
+                        }
+                        sh.g[0][lane] = (T)load_g<MIXED>(a.gx, oa);
+                        sh.g[1][lane] = (T)load_g<MIXED>(a.gy, oa);
+                        sh.g[2][lane] = (T)load_g<MIXED>(a.gz, oa);
+                    }
+                    tile_sync();
+                    const int nt = cA - t0 < kWave ? cA - t0 : kWave;
+                    if (has_src) {
+                        for (int j = L.slice; j < nt; j += L.J) {
+                            const T v[3] = {sh.x[j] - bx, sh.y[j] - by, sh.z[j] - bz};
+                            const T r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+                            const T hsum = sh.h[j] + hb;
+                            const T ri = rsq_t(r2);
+                            const T ri2 = ri * ri;
+                            const T r3 = ri2 * ri;
+                            const T r5 = r3 * ri2;
+                            T F = r3, dFr = (T)-3 * r5;
+                            if (!soft_outside<T>(r2, hsum)) soft_FdF<T>(r2, ri, r3, r5, hsum, F, dFr);
+                            const T ga[3] = {sh.g[0][j], sh.g[1][j], sh.g[2][j]};
+                            const T vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
+#pragma unroll
+                            for (int cc = 0; cc < 3; ++cc) acc[cc] += (double)(mb * (F * ga[cc] + dFr * v[cc] * vg));
+                            acc[3] += (double)(-F * vg);
+                        }
+                    }
+                    tile_sync();
+                }
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) acc[cc] = seg_sum(acc[cc], L.slice, L.J);
+        if (has_src && L.slice == 0) {
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                if constexpr (MIXED) a.srcf[cc * a.n + pb] = (float)acc[cc];
+                else a.src[cc * a.n + pb] = acc[cc];
+            }
+        }
+    }
+}
+
+// per-node lists of one list kind: the items sorted by label and each
+// label's range in them
+struct DetLists {
+    uint64_t *items = nullptr;
+    int64_t *lb = nullptr, *le = nullptr;
+    int64_t total = 0;
+};
+
+rcb_status det_lists(rcb_tree *t, const int64_t *beg, const int64_t *end, const uint64_t *list, Scratch &tmp,
+                     hipStream_t s, DetLists &out) {
+    const int64_t NG = t->ngroup;
+    int64_t *cnt = (int64_t *)dalloc(t, sizeof(int64_t) * (NG + 1), s, tmp);
+    if (!cnt) return RCB_ENOMEM;
+    k_det_count<<<(unsigned)((NG + 255) / 256), 256, 0, s>>>(beg, end, NG, cnt);
+    RCB_LAUNCH_CHECK("k_det_count");
+    rcb_status st = scan_i64(t, cnt, cnt, NG, s);
+    if (st != RCB_OK) return st;
+    int64_t total = 0;
+    HostRead rd{cnt + NG, &total, (int)sizeof(int64_t)};
+    st = read_small(s, &rd, 1, "deterministic VJP: list size");
+    if (st != RCB_OK) return st;
+    const int64_t cap = total > 0 ? total : 1;
+    uint64_t *ia = (uint64_t *)dalloc(t, sizeof(uint64_t) * cap, s, tmp);
+    uint64_t *ib = (uint64_t *)dalloc(t, sizeof(uint64_t) * cap, s, tmp);
+    int64_t *lbe = (int64_t *)dalloc(t, sizeof(int64_t) * 2 * t->nlab, s, tmp);
+    if (!ia || !ib || !lbe) return RCB_ENOMEM;
+    k_det_items<<<(unsigned)((NG + kWaves - 1) / kWaves), kBlock, 0, s>>>(beg, end, list, NG, cnt, ia);
+    RCB_LAUNCH_CHECK("k_det_items");
+    st = sort_by_label(t, ia, ib, total, t->k + 1, s, &out.items);
+    if (st != RCB_OK) return st;
+    RCB_ZERO(lbe, sizeof(int64_t) * 2 * t->nlab, s);
+    out.lb = lbe;
+    out.le = lbe + t->nlab;
+    out.total = total;
+    if (total > 0) {
+        k_det_bounds<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(out.items, total, out.lb, out.le);
+        RCB_LAUNCH_CHECK("k_det_bounds");
+    }
+    return RCB_OK;
+}
+
+// node adjoints (FP64, q * nlab + B) and source-side near terms of the
+// deterministic form
+rcb_status vjp_det(rcb_tree *t, const VjpArgs &a, double *adj, bool mixed, Scratch &tmp, hipStream_t s) {
+    const int64_t nlab = t->nlab;
+    DetLists far, near;
+    rcb_status st = det_lists(t, t->gfar_beg, t->gfar_end, t->gfar, tmp, s, far);
+    if (st != RCB_OK) return st;
+    int64_t *cb = (int64_t *)dalloc(t, sizeof(int64_t) * (nlab + 1), s, tmp);
+    if (!cb) return RCB_ENOMEM;
+    const unsigned gl = (unsigned)((nlab + 255) / 256);
+    k_det_nchunk<<<gl, 256, 0, s>>>(far.lb, far.le, nlab, cb);
+    RCB_LAUNCH_CHECK("k_det_nchunk");
+    st = scan_i64(t, cb, cb, nlab, s);
+    if (st != RCB_OK) return st;
+    int64_t nchunk = 0;
+    HostRead rd{cb + nlab, &nchunk, (int)sizeof(int64_t)};
+    st = read_small(s, &rd, 1, "deterministic VJP: chunk count");
+    if (st != RCB_OK) return st;
+    const int64_t ncap = nchunk > 0 ? nchunk : 1;
+    int32_t *owner = (int32_t *)dalloc(t, sizeof(int32_t) * ncap, s, tmp);
+    double *part = (double *)dalloc(t, sizeof(double) * kAdj * ncap, s, tmp);
+    if (!owner || !part) return RCB_ENOMEM;
+    if (nchunk > 0) {
+        k_det_owner<<<gl, 256, 0, s>>>(cb, nlab, owner);
+        RCB_LAUNCH_CHECK("k_det_owner");
+        k_vjp_far_node<<<(unsigned)((nchunk + kWaves - 1) / kWaves), kBlock, 0, s>>>(a, far.items, far.lb, far.le,
+                                                                                    cb, owner, nchunk, part);
+        RCB_LAUNCH_CHECK("k_vjp_far_node");
+    }
+    k_det_adj_sum<<<(unsigned)((kAdj * nlab + 255) / 256), 256, 0, s>>>(part, cb, nlab, adj);
+    RCB_LAUNCH_CHECK("k_det_adj_sum");
+    st = det_lists(t, t->gnear_beg, t->gnear_end, t->gnear, tmp, s, near);
+    if (st != RCB_OK) return st;
+    const unsigned gn = (unsigned)((t->nleaf + kWaves - 1) / kWaves);
+    if (mixed) k_vjp_near_src<true><<<gn, kBlock, 0, s>>>(a, near.items, near.lb, near.le);
+    else k_vjp_near_src<false><<<gn, kBlock, 0, s>>>(a, near.items, near.lb, near.le);
+    RCB_LAUNCH_CHECK("k_vjp_near_src");
+    return RCB_OK;
+}
+
 }  // namespace
 
 rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *gz, void *dx,
@@ -543,13 +932,19 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     double *sink = (double *)dalloc(t, sizeof(double) * 4 * n, s, tmp);
     const bool mixed = t->p.precision == RCB_MIXED;
     void *srcv = dalloc(t, (mixed ? sizeof(float) : sizeof(double)) * 4 * n, s, tmp);
+    const bool det = t->p.deterministic != 0;
+    if (det && t->ngroup > (int64_t(1) << 24)) {
+        set_error("rcb_gravity_vjp: the deterministic form takes at most 2^24 groups of cells (k <= 26)");
+        return RCB_ECAPACITY;
+    }
     const int64_t nmid = std::min<int64_t>(t->nlab, int64_t(1) << kMidLevel);
     // node-adjoint copies: FP64 (summed into copy 0 of adj) or, in the mixed
-    // form, FP32 (summed into adj)
-    const size_t adj_n = (size_t)kAdjCopies * kAdj * t->nlab, adjm_n = (size_t)kAdjMidCopies * kAdj * nmid;
-    double *adj = (double *)dalloc(t, sizeof(double) * (mixed ? (size_t)kAdj * t->nlab : adj_n), s, tmp);
-    void *adjc = mixed ? dalloc(t, sizeof(float) * adj_n, s, tmp) : (void *)adj;
-    void *adjmc = dalloc(t, (mixed ? sizeof(float) : sizeof(double)) * adjm_n, s, tmp);
+    // form, FP32 (summed into adj); the deterministic form writes adj alone
+    const size_t adj_n = det ? 0 : (size_t)kAdjCopies * kAdj * t->nlab;
+    const size_t adjm_n = det ? 0 : (size_t)kAdjMidCopies * kAdj * nmid;
+    double *adj = (double *)dalloc(t, sizeof(double) * (mixed || det ? (size_t)kAdj * t->nlab : adj_n), s, tmp);
+    void *adjc = det ? (void *)adj : mixed ? dalloc(t, sizeof(float) * adj_n, s, tmp) : (void *)adj;
+    void *adjmc = det ? (void *)adj : dalloc(t, (mixed ? sizeof(float) : sizeof(double)) * adjm_n, s, tmp);
     double *mom = (double *)dalloc(t, sizeof(double) * kMom * t->nleaf, s, tmp);
     if (!t->farc) {
         t->farc = (double *)dalloc(t, sizeof(double) * kLeafC * t->nleaf, s, t->list_allocs);
@@ -558,14 +953,18 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     double *leafc = t->farc;   // 19 far coefficients + the leaf's cotangent sum per leaf
     if (!sink || !srcv || !adj || !adjc || !adjmc || !mom || !leafc) return RCB_ENOMEM;
     RCB_ZERO(srcv, (mixed ? sizeof(float) : sizeof(double)) * 4 * n, s);
-    RCB_ZERO(adjc, (mixed ? sizeof(float) : sizeof(double)) * adj_n, s);
-    RCB_ZERO(adjmc, (mixed ? sizeof(float) : sizeof(double)) * adjm_n, s);
+    if (!det) {
+        RCB_ZERO(adjc, (mixed ? sizeof(float) : sizeof(double)) * adj_n, s);
+        RCB_ZERO(adjmc, (mixed ? sizeof(float) : sizeof(double)) * adjm_n, s);
+    }
     VjpArgs a{t->nleaf, t->gk, t->ngroup, t->nfirst, t->ncount, t->ncom, t->nM, t->nQ,
               t->gnear_beg, t->gnear_end, t->gfar_beg, t->gfar_end, t->gnear, t->gfar, t->px, t->py, t->pz, t->pm, t->ph,
               t->fdx, t->fdy, t->fdz, t->fm, t->fh, t->pid, gx, gy, gz, mom, leafc, sink, mixed ? nullptr : (double *)srcv,
               mixed ? (float *)srcv : nullptr, adj, nullptr, nmid, n, t->nlab};
     const unsigned gridg = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
-    if (mixed) k_vjp_moments<true><<<gridg, kBlock, 0, s>>>(a);
+    if (det && mixed) k_vjp_moments_det<true><<<gridg, kBlock, 0, s>>>(a);
+    else if (det) k_vjp_moments_det<false><<<gridg, kBlock, 0, s>>>(a);
+    else if (mixed) k_vjp_moments<true><<<gridg, kBlock, 0, s>>>(a);
     else k_vjp_moments<false><<<gridg, kBlock, 0, s>>>(a);
     RCB_LAUNCH_CHECK("k_vjp_moments");
     if (!t->farc_valid) {   // else kept by the last rcb_gravity on these moments
@@ -576,20 +975,33 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
 
     const int64_t alen = kAdj * t->nlab;
     const unsigned gridr = (unsigned)((alen + 255) / 256);
-    if (mixed) {
-        k_vjp_far<float><<<gridg, kBlock, 0, s>>>(a, (float *)adjc, (float *)adjmc);
+    if (det) {
+        // sink-centre sums per leaf, then node adjoints and source-side terms
+        // from the per-node lists
+        k_vjp_far<double, false><<<gridg, kBlock, 0, s>>>(a, nullptr, nullptr);
         RCB_LAUNCH_CHECK("k_vjp_far");
-        k_adj_reduce<float><<<gridr, 256, 0, s>>>(adj, (const float *)adjc, (const float *)adjmc, t->nlab, nmid);
+        st = vjp_det(t, a, adj, mixed, tmp, s);
+        if (st != RCB_OK) return st;
+        if (mixed) k_vjp_near<true, false><<<gridg, kBlock, 0, s>>>(a);
+        else k_vjp_near<false, false><<<gridg, kBlock, 0, s>>>(a);
+        RCB_LAUNCH_CHECK("k_vjp_near");
     } else {
-        k_vjp_far<double><<<gridg, kBlock, 0, s>>>(a, (double *)adjc, (double *)adjmc);
-        RCB_LAUNCH_CHECK("k_vjp_far");
-        k_adj_reduce<double><<<gridr, 256, 0, s>>>(adj, (const double *)adjc, (const double *)adjmc, t->nlab,
-                                                   nmid);
+        if (mixed) {
+            k_vjp_far<float, true><<<gridg, kBlock, 0, s>>>(a, (float *)adjc, (float *)adjmc);
+            RCB_LAUNCH_CHECK("k_vjp_far");
+            k_adj_reduce<float><<<gridr, 256, 0, s>>>(adj, (const float *)adjc, (const float *)adjmc, t->nlab,
+                                                      nmid);
+        } else {
+            k_vjp_far<double, true><<<gridg, kBlock, 0, s>>>(a, (double *)adjc, (double *)adjmc);
+            RCB_LAUNCH_CHECK("k_vjp_far");
+            k_adj_reduce<double><<<gridr, 256, 0, s>>>(adj, (const double *)adjc, (const double *)adjmc, t->nlab,
+                                                       nmid);
+        }
+        RCB_LAUNCH_CHECK("k_adj_reduce");
+        if (mixed) k_vjp_near<true, true><<<gridg, kBlock, 0, s>>>(a);
+        else k_vjp_near<false, true><<<gridg, kBlock, 0, s>>>(a);
+        RCB_LAUNCH_CHECK("k_vjp_near");
     }
-    RCB_LAUNCH_CHECK("k_adj_reduce");
-    if (mixed) k_vjp_near<true><<<gridg, kBlock, 0, s>>>(a);
-    else k_vjp_near<false><<<gridg, kBlock, 0, s>>>(a);
-    RCB_LAUNCH_CHECK("k_vjp_near");
     if (mixed) k_vjp_push<true><<<gridg, kBlock, 0, s>>>(a, adj, t->ncom, t->nM, dx, dy, dz, dm);
     else k_vjp_push<false><<<gridg, kBlock, 0, s>>>(a, adj, t->ncom, t->nM, dx, dy, dz, dm);
     RCB_LAUNCH_CHECK("k_vjp_push");

@@ -318,6 +318,7 @@ void rcb_params_default(rcb_params *p) {
     p->pure_mac = 0;
     p->split = RCB_SPLIT_MASS;
     p->taylor_reading = RCB_READING_A;
+    p->deterministic = 0;
     p->alloc = nullptr;
     p->free = nullptr;
     p->alloc_ctx = nullptr;
@@ -364,6 +365,10 @@ rcb_status rcb_build(const double *x, const double *y, const double *z, const do
     }
     if (p->taylor_reading != RCB_READING_A && p->taylor_reading != RCB_READING_B) {
         set_error("rcb_build: taylor_reading must be RCB_READING_A or RCB_READING_B");
+        return RCB_EINVAL;
+    }
+    if (p->deterministic != 0 && p->deterministic != 1) {
+        set_error("rcb_build: deterministic must be 0 or 1");
         return RCB_EINVAL;
     }
     if (p->split != RCB_SPLIT_MASS && p->split != RCB_SPLIT_NUMBER && p->split != RCB_SPLIT_MEDIAN) {

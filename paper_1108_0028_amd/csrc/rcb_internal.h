@@ -184,6 +184,10 @@ size_t refresh_noalloc_bytes(const rcb_tree *t);
 size_t refresh_noalloc_capacity();
 // device exclusive scan of int64 counts in place-free form: out[0..n] (k_scan.hip)
 rcb_status scan_i64(rcb_tree *t, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+// stable sort of items by bits 32 .. 32 + bits - 1 (k_sort.hip); a and b hold n
+// items each, the input in a; *result is a or b, whichever holds the output
+rcb_status sort_by_label(rcb_tree *t, uint64_t *a, uint64_t *b, int64_t n, int bits,
+                         hipStream_t s, uint64_t **result);
 // walk (k_walk.hip)
 rcb_status ensure_walk(rcb_tree *t, hipStream_t s);
 rcb_status ensure_leaf_lists(rcb_tree *t, hipStream_t s);

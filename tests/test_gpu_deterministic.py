@@ -1,0 +1,123 @@
+"""The VJP's deterministic form (rcb_params.deterministic = 1): nothing is
+added atomically and every sum runs in a fixed order, so two calls on one
+tree, and calls on two trees built from the same inputs, give identical
+bits. Its outputs must meet the same VJP bars against the oracle as the
+atomic form (only the summation order differs: per node over the groups
+that accepted it, per source over the sink cells that hold its cell), and
+agree with the atomic form on the same inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+import workloads as W
+
+from test_gpu_vjp import TOL
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(300, 4, "clustered", 0.5), (1001, 8, "plummer", 0.8), (5000, 12, "uniform", 0.0),
+         (5000, 12, "uniform", 0.5), (20000, 128, "clustered", 0.7)]
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _tree(c, nll, theta, prec, det, pure_mac=False):
+    import torch
+    from paper_1108_0028_amd import Tree
+    return Tree(*[torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0") for a in c.arrays()], n_ll=nll,
+                theta=theta, precision=prec, deterministic=det, pure_mac=pure_mac)
+
+
+def _vjp(tree, g, prec):
+    import torch
+    dt = torch.float32 if prec == "mixed" else torch.float64
+    return tree.vjp(*[torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", dt) for a in g])
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _same_bits(a, b):
+    import torch
+    for x, y in zip(a, b):
+        assert torch.equal(x, y), float((x.double() - y.double()).abs().max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,nll,kind,theta", CASES)
+def test_deterministic_vjp_repeats_and_matches_oracle(n, nll, kind, theta, prec):
+    c = W.small_random(n, 500 + n, kind, h_scale=0.5 if nll > 64 else 1.0)
+    g = W.cotangents(n, seed=n)
+    ot = O.OracleTree(*c.arrays(), n_ll=nll)
+    ot.walk(theta)
+    ref = ot.vjp(*g)
+    _say("deterministic vjp", prec, n, nll, kind, theta)
+    t1 = _tree(c, nll, theta, prec, True)
+    a = _vjp(t1, g, prec)              # computes and keeps the far coefficients
+    b = _vjp(t1, g, prec)              # reuses them
+    _same_bits(a, b)
+    t2 = _tree(c, nll, theta, prec, True)
+    _same_bits(a, _vjp(t2, g, prec))
+    for name, x, r in zip(("dx", "dy", "dz", "dm"), a, ref):
+        e = _rel(_np(x), r)
+        print(f"   {name} rel err {e:.2e}", flush=True)
+        assert e <= TOL[prec], (name, e)
+    t3 = _tree(c, nll, theta, prec, False)
+    for name, x, y in zip(("dx", "dy", "dz", "dm"), a, _vjp(t3, g, prec)):
+        assert _rel(_np(x), _np(y)) <= TOL[prec], name
+    for t in (t1, t2, t3):
+        t.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_deterministic_vjp_pure_mac(prec):
+    c = W.small_random(3000, 91, "plummer")
+    g = W.cotangents(c.n, seed=92)
+    ot = O.OracleTree(*c.arrays(), n_ll=8)
+    ot.walk(0.7, pure_mac=True)
+    ref = ot.vjp(*g)
+    _say("deterministic vjp, pure MAC", prec)
+    t1 = _tree(c, 8, 0.7, prec, True, pure_mac=True)
+    a = _vjp(t1, g, prec)
+    _same_bits(a, _vjp(t1, g, prec))
+    for name, x, r in zip(("dx", "dy", "dz", "dm"), a, ref):
+        e = _rel(_np(x), r)
+        print(f"   {name} rel err {e:.2e}", flush=True)
+        assert e <= TOL[prec], (name, e)
+    t1.destroy()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_deterministic_vjp_1m(prec):
+    """1M Plummer: two calls identical; against the atomic form (whose FP64
+    VJP equals the oracle's on sampled cells at this size) within the bar."""
+    import torch
+    c = W.plummer()
+    g = W.cotangents(c.n)
+    _say("deterministic vjp 1M", prec)
+    t1 = _tree(c, 12, 0.7, prec, True)
+    t1.gravity()
+    a = _vjp(t1, g, prec)
+    b = _vjp(t1, g, prec)
+    torch.cuda.synchronize()
+    _same_bits(a, b)
+    t1.destroy()
+    t2 = _tree(c, 12, 0.7, prec, False)
+    t2.gravity()
+    ref = _vjp(t2, g, prec)
+    for name, x, y in zip(("dx", "dy", "dz", "dm"), a, ref):
+        e = _rel(_np(x), _np(y))
+        print(f"   deterministic vs atomic {name} rel err {e:.2e}", flush=True)
+        assert e <= TOL[prec], (name, e)
+    t2.destroy()
