@@ -206,6 +206,16 @@ def main():
     # VJP on the same tree after gravity (the far coefficients are kept)
     out["vjp"] = _vjp_timing(t, n, phases, a.precision)
     t.destroy()
+    # the deterministic form (no atomics) on a tree of the same inputs
+    td = Tree(*arrs, n_ll=a.n_ll, theta=a.theta, precision=a.precision, pure_mac=a.pure_mac,
+              deterministic=True)
+    td.gravity()
+    vd = _vjp_timing(td, n, phases, a.precision)
+    out["vjp_deterministic"] = {"ms": vd["ms"], "vjp_over_forward": vd["vjp_over_forward"],
+                                "basis": "rcb_params.deterministic = 1: node adjoints and source-side "
+                                         "near terms summed per node / per cell in a fixed order "
+                                         "(label sort of the group lists on each call)"}
+    td.destroy()
 
     # the other form and the mixed-vs-FP64 error
     other = "fp64" if a.precision == "mixed" else "mixed"

@@ -41,7 +41,10 @@
  *    device-wide pass instead of finishing small subtrees in one wave each
  *    (same tree, bit for bit); RCB_WALK_WIDE_STACK=n caps the walk's
  *    first-tier node queue at n entries, so that more groups go to the later
- *    tiers (same lists).
+ *    tiers (same lists); RCB_VJP_DET_RECOMPUTE (any value) makes the
+ *    deterministic rcb_gravity_vjp() recompute each node's adjoint per node
+ *    instead of storing each far entry's (the path it takes when that array
+ *    cannot be allocated; equal to rounding, each path repeats bit for bit).
  */
 #ifndef RCB_H
 #define RCB_H
@@ -106,8 +109,8 @@ typedef struct {
                                  1: no atomics -- per-node and per-cell lists of the groups
                                  that hold each node or cell are made by a stable sort, and
                                  every sum runs in a fixed order, so repeated calls give the
-                                 same bits (more time and 16 B of device memory per entry
-                                 of the per-group lists) */
+                                 same bits (more time; device memory of 16 B per entry
+                                 of the per-group lists and 72 B per far entry) */
     /* Optional workspace allocator, both or neither (NULL: the library
        allocates from the device's stream-ordered pool and keeps freed blocks
        for reuse on the stream that freed them). alloc(bytes, stream, ctx) returns device
@@ -277,7 +280,8 @@ rcb_status rcb_gravity(rcb_tree *t, void *ax, void *ay, void *az, void *stream);
  * form), so two calls agree to rounding, not bit for bit. With
  * deterministic = 1 nothing is added atomically: each node's adjoint is
  * summed over the groups that accepted it (ascending group, fixed chunks of
- * 512 entries, then the chunks in order) and each source particle's terms
+ * 512 entries, then the chunks in order; each group's part over its cells in
+ * order) and each source particle's terms
  * over the sink cells whose near list holds its cell, in FP64 in both forms;
  * two calls on the same tree and inputs give identical outputs. The lists
  * of groups per node and per cell are made on each call (stable label sort).

@@ -297,9 +297,10 @@ class RCBGravity(torch.autograd.Function):
     lists held fixed). h receives no gradient."""
 
     @staticmethod
-    def forward(ctx, x, y, z, m, h, n_ll=12, theta=0.7, precision="fp64", pure_mac=False):
+    def forward(ctx, x, y, z, m, h, n_ll=12, theta=0.7, precision="fp64", pure_mac=False,
+                deterministic=False):
         tree = Tree(x.detach(), y.detach(), z.detach(), m.detach(), h.detach(), n_ll=n_ll,
-                    theta=theta, precision=precision, pure_mac=pure_mac)
+                    theta=theta, precision=precision, pure_mac=pure_mac, deterministic=deterministic)
         ax, ay, az = tree.gravity()
         ctx.tree = tree
         return ax, ay, az
@@ -313,7 +314,7 @@ class RCBGravity(torch.autograd.Function):
         dx, dy, dz, dm = tree.vjp(*g)
         tree.destroy()
         ctx.tree = None
-        return dx, dy, dz, dm, None, None, None, None, None
+        return dx, dy, dz, dm, None, None, None, None, None, None
 
 
 def release_cache():
@@ -322,6 +323,7 @@ def release_cache():
 
 
 def gravity(x, y, z, m, h, n_ll: int = 12, theta: float = 0.7, precision: str = "fp64",
-            pure_mac: bool = False):
-    """Differentiable accelerations (see RCBGravity)."""
-    return RCBGravity.apply(x, y, z, m, h, n_ll, theta, precision, pure_mac)
+            pure_mac: bool = False, deterministic: bool = False):
+    """Differentiable accelerations (see RCBGravity); deterministic: a
+    backward that repeats bit for bit (no atomics)."""
+    return RCBGravity.apply(x, y, z, m, h, n_ll, theta, precision, pure_mac, deterministic)

@@ -23,6 +23,8 @@
 // (dQ/dCOM = 0 because sum m d = 0).
 // Kernels: moments (per group) -> far (per group) -> near (per group, leaf by
 // leaf) -> push.
+#include <cstdlib>
+
 #include "far_math.h"
 #include "near_tile.h"
 #include "rcb_internal.h"
@@ -72,6 +74,10 @@ struct VjpArgs {
     int64_t nmid;   // labels below nmid have kAdjMidCopies adjoint copies, q * nmid + B
     int64_t n;
     int64_t nlab;
+    // deterministic form: each far entry's node adjoint (kAdj FP64) at row
+    // cbase[group] + (entry - the group's first entry)
+    double *contrib;
+    const int64_t *cbase;
 };
 
 template <bool MIXED>
@@ -162,9 +168,13 @@ struct VjpFarShared {
 
 // AT: the type of the node-adjoint copies (FP64; FP32 in the mixed form, whose
 // contract allows FP32 accumulation), summed in FP64 by k_adj_reduce
-// NODES = false (the deterministic form): only the sink-centre sums; the node
-// adjoints are summed per node by k_vjp_far_node instead.
-template <typename AT, bool NODES>
+// MODE kFarAtomic: node adjoints added atomically to the copies. The
+// deterministic form: kFarStore writes each entry's node adjoint (its sum over
+// the group's leaves, in leaf order) to a.contrib, summed per node later;
+// kFarCot computes the sink-centre sums only (k_vjp_far_node then computes
+// the node adjoints itself).
+constexpr int kFarAtomic = 0, kFarCot = 1, kFarStore = 2;
+template <typename AT, int MODE>
 __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a, AT *__restrict__ adjc, AT *__restrict__ adjmc) {
     __shared__ VjpFarShared sh_all[kWaves];
     VjpFarShared &sh = sh_all[threadIdx.x / kWave];
@@ -239,7 +249,12 @@ __global__ __launch_bounds__(kBlock) void k_vjp_far(VjpArgs a, AT *__restrict__ 
                 if (!(lane & 1)) cotp[i][u][lane >> 1] += t;
             }
         }
-        if (NODES && emask) {
+        if (MODE == kFarStore && emask) {
+            double *row = a.contrib + (a.cbase[gi] + (e - f0)) * kAdj;
+#pragma unroll
+            for (int q = 0; q < kAdj; ++q) row[q] = ad[q];
+        }
+        if (MODE == kFarAtomic && emask) {
             // each copy takes the blocks of one residue mod the number of
             // copies, i.e. of one XCD under round-robin dispatch (8 | copies)
             if (B < a.nmid) {
@@ -608,11 +623,12 @@ __global__ void k_det_count(const int64_t *__restrict__ beg, const int64_t *__re
 }
 
 // item = label << 32 | group << 8 | mask (bits 32-39 of the list entry: the far
-// mask, or the near mask), written in group order at the group's offset
+// mask, or the near mask), or with compact = true label << 32 | the item's own
+// index; written in group order at the group's offset
 __global__ __launch_bounds__(kBlock) void k_det_items(const int64_t *__restrict__ beg,
                                                       const int64_t *__restrict__ end,
                                                       const uint64_t *__restrict__ list, int64_t ngroup,
-                                                      const int64_t *__restrict__ base,
+                                                      const int64_t *__restrict__ base, bool compact,
                                                       uint64_t *__restrict__ items) {
     const int64_t gi = wave_index();
     if (gi >= ngroup) return;
@@ -621,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_det_items(const int64_t *__restrict_
         const uint64_t ent = list[e0 + j];
         const uint64_t lab = (uint32_t)ent & 0x7fffffffu;
         const uint64_t mask = (ent >> 32) & 0xffu;
-        items[o + j] = (lab << 32) | ((uint64_t)gi << 8) | mask;
+        items[o + j] = (lab << 32) | (compact ? (uint64_t)(o + j) : (((uint64_t)gi << 8) | mask));
     }
 }
 
@@ -649,8 +665,10 @@ __global__ void k_det_owner(const int64_t *__restrict__ cb, int64_t nlab, int32_
 }
 
 // node adjoints, one wave per chunk of one node's entries: lanes over the
-// entries (group, far mask), each summing the node's adjoint over the leaves
-// of its mask in order; the chunk's sum is a canonical wave sum
+// entries, each taking the entry's adjoint stored by k_vjp_far (STORED) or
+// summing it over the leaves of the entry's far mask in order; the chunk's
+// sum is a canonical wave sum
+template <bool STORED>
 __global__ __launch_bounds__(kBlock) void k_vjp_far_node(VjpArgs a, const uint64_t *__restrict__ items,
                                                          const int64_t *__restrict__ lb,
                                                          const int64_t *__restrict__ le,
@@ -676,6 +694,12 @@ __global__ __launch_bounds__(kBlock) void k_vjp_far_node(VjpArgs a, const uint64
         const int64_t e = e0 + lane;
         if (e >= e_end) continue;
         const uint64_t it = items[e];
+        if constexpr (STORED) {
+            const double *row = a.contrib + (int64_t)(uint32_t)it * kAdj;
+#pragma unroll
+            for (int q = 0; q < kAdj; ++q) ad[q] += row[q];
+            continue;
+        }
         const int64_t gi = (uint32_t)it >> 8;
         const uint32_t mask = (uint32_t)it & 0xffu;
         for (int i = 0; i < G; ++i) {
@@ -726,14 +750,24 @@ __global__ void k_det_adj_sum(const double *__restrict__ part, const int64_t *__
 }
 
 // source-side near terms, one wave per lowest-level cell B: lanes (source
-// slot, slice) over B's particles as in leaf_lanes; the sink cells A whose
-// near list holds B (the groups ascending, then the cells of the near mask)
-// are staged 64 particles at a time in LDS, and each slice takes every J-th
-// sink. The pair arithmetic is that of k_vjp_near; the slices' sums are
-// combined by seg_sum and written (no atomics: B owns its particles).
+// slot, slice) over B's particles as in leaf_lanes. The sink cells A whose
+// near list holds B (the groups ascending, then the cells of each group's
+// near mask) are taken 8 groups (64 cells) at a time; an exclusive scan of
+// their sizes gives each cell's first sink, and the sinks are staged 64 at a
+// time in LDS (near_tile.h's chunk layout), each slice taking every J-th.
+// In the mixed form a staged sink carries the FP32 shift from its cell's
+// centre of mass to B's, so the pair arithmetic is exactly that of
+// k_vjp_near. The slices' sums are combined by seg_sum and written (no
+// atomics: B owns its particles).
 template <typename T>
 struct SinkTile {
     T x[kWave], y[kWave], z[kWave], h[kWave], g[3][kWave];
+    float sx[kWave], sy[kWave], sz[kWave];   // mixed form: (float)(com_B - com_A)
+};
+template <typename T>
+struct SrcShared {
+    EntryChunk ec;
+    SinkTile<T> t;
 };
 
 template <bool MIXED>
@@ -741,8 +775,8 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near_src(VjpArgs a, const uint64
                                                          const int64_t *__restrict__ lb,
                                                          const int64_t *__restrict__ le) {
     using T = typename std::conditional<MIXED, float, double>::type;
-    __shared__ SinkTile<T> sh_all[kWaves];
-    SinkTile<T> &sh = sh_all[threadIdx.x / kWave];
+    __shared__ SrcShared<T> sh_all[kWaves];
+    SrcShared<T> &sh = sh_all[threadIdx.x / kWave];
     const int64_t bl = wave_index();
     if (bl >= a.nleaf) return;
     const int lane = lane_id();
@@ -757,75 +791,96 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near_src(VjpArgs a, const uint64
         const int si = g0 + L.sslot;
         const bool has_src = L.sslot < L.S && si < c;
         const int32_t pb = sB + (has_src ? si : 0);
-        T mb, hb;
+        T mb, hb, bx, by, bz;   // bx..: FP64 position, or the FP32 offset from com_B
         if constexpr (MIXED) {
             mb = a.fm[pb];
             hb = a.fh[pb];
+            bx = a.fdx[pb];
+            by = a.fdy[pb];
+            bz = a.fdz[pb];
         } else {
             mb = a.pm[pb];
             hb = a.ph[pb];
+            bx = a.px[pb];
+            by = a.py[pb];
+            bz = a.pz[pb];
         }
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t e = e_beg; e < e_end; ++e) {
-            const uint64_t it = items[e];
-            const int64_t gi = (uint32_t)it >> 8;
-            const uint32_t mask = (uint32_t)it & 0xffu;
-            for (int li = 0; li < G; ++li) {
-                if (!((mask >> li) & 1u)) continue;
-                const int64_t A = a.nleaf + gi * G + li;
-                const int32_t sA = a.nfirst[A], cA = a.ncount[A];
-                T bx, by, bz;   // the source in the frame of the sink cell's particles
-                if constexpr (MIXED) {
-                    bx = (float)(cB[0] - a.ncom[3 * A]) + a.fdx[pb];
-                    by = (float)(cB[1] - a.ncom[3 * A + 1]) + a.fdy[pb];
-                    bz = (float)(cB[2] - a.ncom[3 * A + 2]) + a.fdz[pb];
-                } else {
-                    bx = a.px[pb];
-                    by = a.py[pb];
-                    bz = a.pz[pb];
+        for (int64_t e0 = e_beg; e0 < e_end; e0 += kWave / 8) {
+            // lane = (group entry e0 + lane / 8, cell lane % 8 of its mask)
+            const int64_t e = e0 + (lane >> 3);
+            const int li = lane & 7;
+            int32_t fA = 0, cA = 0, A = 0;
+            if (e < e_end && li < G) {
+                const uint64_t it = items[e];
+                if (((uint32_t)it >> li) & 1u) {
+                    A = (int32_t)(a.nleaf + (int64_t)((uint32_t)it >> 8) * G + li);
+                    fA = a.nfirst[A];
+                    cA = a.ncount[A];
                 }
-                for (int t0 = 0; t0 < cA; t0 += kWave) {
-                    const int q = t0 + lane;
-                    if (q < cA) {
-                        const int32_t pa = sA + q;
-                        const int32_t oa = a.pid[pa];
-                        if constexpr (MIXED) {
-                            sh.x[lane] = a.fdx[pa];
-                            sh.y[lane] = a.fdy[pa];
-                            sh.z[lane] = a.fdz[pa];
-                            sh.h[lane] = a.fh[pa];
+            }
+            const int p = wave_excl_scan(cA);
+            sh.ec.fB[lane] = fA;
+            sh.ec.pos[lane] = p;
+            sh.ec.label[lane] = A;
+            if (lane == kWave - 1) sh.ec.pos[kWave] = p + cA;
+            tile_sync();
+            const int tot = __builtin_amdgcn_readfirstlane(sh.ec.pos[kWave]);
+            for (int t = 0; t < tot; t += kWave) {
+                const int q = t + lane;
+                if (q < tot) {
+                    const int k = entry_of(sh.ec, q);
+                    const int32_t pa = sh.ec.fB[k] + (q - sh.ec.pos[k]);
+                    const int32_t oa = a.pid[pa];
+                    if constexpr (MIXED) {
+                        const int64_t Ak = sh.ec.label[k];
+                        sh.t.x[lane] = a.fdx[pa];
+                        sh.t.y[lane] = a.fdy[pa];
+                        sh.t.z[lane] = a.fdz[pa];
+                        sh.t.h[lane] = a.fh[pa];
+                        sh.t.sx[lane] = (float)(cB[0] - a.ncom[3 * Ak]);
+                        sh.t.sy[lane] = (float)(cB[1] - a.ncom[3 * Ak + 1]);
+                        sh.t.sz[lane] = (float)(cB[2] - a.ncom[3 * Ak + 2]);
+                    } else {
+                        sh.t.x[lane] = a.px[pa];
+                        sh.t.y[lane] = a.py[pa];
+                        sh.t.z[lane] = a.pz[pa];
+                        sh.t.h[lane] = a.ph[pa];
+                    }
+                    sh.t.g[0][lane] = (T)load_g<MIXED>(a.gx, oa);
+                    sh.t.g[1][lane] = (T)load_g<MIXED>(a.gy, oa);
+                    sh.t.g[2][lane] = (T)load_g<MIXED>(a.gz, oa);
+                }
+                tile_sync();
+                const int nt = tot - t < kWave ? tot - t : kWave;
+                if (has_src) {
+                    for (int j = L.slice; j < nt; j += L.J) {
+                        T v[3];
+                        if constexpr (MIXED) {   // the source in the sink cell's frame, as in k_vjp_near
+                            v[0] = sh.t.x[j] - (sh.t.sx[j] + bx);
+                            v[1] = sh.t.y[j] - (sh.t.sy[j] + by);
+                            v[2] = sh.t.z[j] - (sh.t.sz[j] + bz);
                         } else {
-                            sh.x[lane] = a.px[pa];
-                            sh.y[lane] = a.py[pa];
-                            sh.z[lane] = a.pz[pa];
-                            sh.h[lane] = a.ph[pa];
+                            v[0] = sh.t.x[j] - bx;
+                            v[1] = sh.t.y[j] - by;
+                            v[2] = sh.t.z[j] - bz;
                         }
-                        sh.g[0][lane] = (T)load_g<MIXED>(a.gx, oa);
-                        sh.g[1][lane] = (T)load_g<MIXED>(a.gy, oa);
-                        sh.g[2][lane] = (T)load_g<MIXED>(a.gz, oa);
-                    }
-                    tile_sync();
-                    const int nt = cA - t0 < kWave ? cA - t0 : kWave;
-                    if (has_src) {
-                        for (int j = L.slice; j < nt; j += L.J) {
-                            const T v[3] = {sh.x[j] - bx, sh.y[j] - by, sh.z[j] - bz};
-                            const T r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
-                            const T hsum = sh.h[j] + hb;
-                            const T ri = rsq_t(r2);
-                            const T ri2 = ri * ri;
-                            const T r3 = ri2 * ri;
-                            const T r5 = r3 * ri2;
-                            T F = r3, dFr = (T)-3 * r5;
-                            if (!soft_outside<T>(r2, hsum)) soft_FdF<T>(r2, ri, r3, r5, hsum, F, dFr);
-                            const T ga[3] = {sh.g[0][j], sh.g[1][j], sh.g[2][j]};
-                            const T vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
+                        const T r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+                        const T hsum = sh.t.h[j] + hb;
+                        const T ri = rsq_t(r2);
+                        const T ri2 = ri * ri;
+                        const T r3 = ri2 * ri;
+                        const T r5 = r3 * ri2;
+                        T F = r3, dFr = (T)-3 * r5;
+                        if (!soft_outside<T>(r2, hsum)) soft_FdF<T>(r2, ri, r3, r5, hsum, F, dFr);
+                        const T ga[3] = {sh.t.g[0][j], sh.t.g[1][j], sh.t.g[2][j]};
+                        const T vg = v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2];
 #pragma unroll
-                            for (int cc = 0; cc < 3; ++cc) acc[cc] += (double)(mb * (F * ga[cc] + dFr * v[cc] * vg));
-                            acc[3] += (double)(-F * vg);
-                        }
+                        for (int cc = 0; cc < 3; ++cc) acc[cc] += (double)(mb * (F * ga[cc] + dFr * v[cc] * vg));
+                        acc[3] += (double)(-F * vg);
                     }
-                    tile_sync();
                 }
+                tile_sync();
             }
         }
 #pragma unroll
@@ -843,13 +898,14 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near_src(VjpArgs a, const uint64
 // per-node lists of one list kind: the items sorted by label and each
 // label's range in them
 struct DetLists {
+    int64_t *base = nullptr;   // each group's first item (exclusive scan of the list sizes)
+    int64_t total = 0;
     uint64_t *items = nullptr;
     int64_t *lb = nullptr, *le = nullptr;
-    int64_t total = 0;
 };
 
-rcb_status det_lists(rcb_tree *t, const int64_t *beg, const int64_t *end, const uint64_t *list, Scratch &tmp,
-                     hipStream_t s, DetLists &out) {
+rcb_status det_count(rcb_tree *t, const int64_t *beg, const int64_t *end, Scratch &tmp, hipStream_t s,
+                     DetLists &out) {
     const int64_t NG = t->ngroup;
     int64_t *cnt = (int64_t *)dalloc(t, sizeof(int64_t) * (NG + 1), s, tmp);
     if (!cnt) return RCB_ENOMEM;
@@ -857,23 +913,29 @@ rcb_status det_lists(rcb_tree *t, const int64_t *beg, const int64_t *end, const 
     RCB_LAUNCH_CHECK("k_det_count");
     rcb_status st = scan_i64(t, cnt, cnt, NG, s);
     if (st != RCB_OK) return st;
-    int64_t total = 0;
-    HostRead rd{cnt + NG, &total, (int)sizeof(int64_t)};
+    HostRead rd{cnt + NG, &out.total, (int)sizeof(int64_t)};
     st = read_small(s, &rd, 1, "deterministic VJP: list size");
     if (st != RCB_OK) return st;
+    out.base = cnt;
+    return RCB_OK;
+}
+
+rcb_status det_sort(rcb_tree *t, const int64_t *beg, const int64_t *end, const uint64_t *list, bool compact,
+                    Scratch &tmp, hipStream_t s, DetLists &out) {
+    const int64_t NG = t->ngroup, total = out.total;
     const int64_t cap = total > 0 ? total : 1;
     uint64_t *ia = (uint64_t *)dalloc(t, sizeof(uint64_t) * cap, s, tmp);
     uint64_t *ib = (uint64_t *)dalloc(t, sizeof(uint64_t) * cap, s, tmp);
     int64_t *lbe = (int64_t *)dalloc(t, sizeof(int64_t) * 2 * t->nlab, s, tmp);
     if (!ia || !ib || !lbe) return RCB_ENOMEM;
-    k_det_items<<<(unsigned)((NG + kWaves - 1) / kWaves), kBlock, 0, s>>>(beg, end, list, NG, cnt, ia);
+    k_det_items<<<(unsigned)((NG + kWaves - 1) / kWaves), kBlock, 0, s>>>(beg, end, list, NG, out.base, compact,
+                                                                          ia);
     RCB_LAUNCH_CHECK("k_det_items");
-    st = sort_by_label(t, ia, ib, total, t->k + 1, s, &out.items);
+    rcb_status st = sort_by_label(t, ia, ib, total, t->k + 1, s, &out.items);
     if (st != RCB_OK) return st;
     RCB_ZERO(lbe, sizeof(int64_t) * 2 * t->nlab, s);
     out.lb = lbe;
     out.le = lbe + t->nlab;
-    out.total = total;
     if (total > 0) {
         k_det_bounds<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(out.items, total, out.lb, out.le);
         RCB_LAUNCH_CHECK("k_det_bounds");
@@ -881,12 +943,26 @@ rcb_status det_lists(rcb_tree *t, const int64_t *beg, const int64_t *end, const 
     return RCB_OK;
 }
 
-// node adjoints (FP64, q * nlab + B) and source-side near terms of the
-// deterministic form
-rcb_status vjp_det(rcb_tree *t, const VjpArgs &a, double *adj, bool mixed, Scratch &tmp, hipStream_t s) {
+// The deterministic form after the cotangent moments and far coefficients:
+// sink-centre sums and node adjoints (FP64, q * nlab + B) of the far field,
+// and the source-side near terms. Each far entry's node adjoint is stored by
+// k_vjp_far and summed per node (72 B per entry); if that array cannot be had
+// (or RCB_VJP_DET_RECOMPUTE is set) k_vjp_far_node recomputes it per node.
+rcb_status vjp_det(rcb_tree *t, VjpArgs a, double *adj, bool mixed, Scratch &tmp, hipStream_t s) {
     const int64_t nlab = t->nlab;
+    const unsigned gridg = (unsigned)((t->ngroup + kWaves - 1) / kWaves);
     DetLists far, near;
-    rcb_status st = det_lists(t, t->gfar_beg, t->gfar_end, t->gfar, tmp, s, far);
+    rcb_status st = det_count(t, t->gfar_beg, t->gfar_end, tmp, s, far);
+    if (st != RCB_OK) return st;
+    double *contrib = nullptr;
+    if (far.total > 0 && far.total < (int64_t(1) << 32) && getenv("RCB_VJP_DET_RECOMPUTE") == nullptr)
+        contrib = (double *)dalloc(t, sizeof(double) * kAdj * far.total, s, tmp);
+    a.contrib = contrib;
+    a.cbase = far.base;
+    if (contrib) k_vjp_far<double, kFarStore><<<gridg, kBlock, 0, s>>>(a, nullptr, nullptr);
+    else k_vjp_far<double, kFarCot><<<gridg, kBlock, 0, s>>>(a, nullptr, nullptr);
+    RCB_LAUNCH_CHECK("k_vjp_far");
+    st = det_sort(t, t->gfar_beg, t->gfar_end, t->gfar, contrib != nullptr, tmp, s, far);
     if (st != RCB_OK) return st;
     int64_t *cb = (int64_t *)dalloc(t, sizeof(int64_t) * (nlab + 1), s, tmp);
     if (!cb) return RCB_ENOMEM;
@@ -906,13 +982,16 @@ rcb_status vjp_det(rcb_tree *t, const VjpArgs &a, double *adj, bool mixed, Scrat
     if (nchunk > 0) {
         k_det_owner<<<gl, 256, 0, s>>>(cb, nlab, owner);
         RCB_LAUNCH_CHECK("k_det_owner");
-        k_vjp_far_node<<<(unsigned)((nchunk + kWaves - 1) / kWaves), kBlock, 0, s>>>(a, far.items, far.lb, far.le,
-                                                                                    cb, owner, nchunk, part);
+        const unsigned gc = (unsigned)((nchunk + kWaves - 1) / kWaves);
+        if (contrib) k_vjp_far_node<true><<<gc, kBlock, 0, s>>>(a, far.items, far.lb, far.le, cb, owner, nchunk, part);
+        else k_vjp_far_node<false><<<gc, kBlock, 0, s>>>(a, far.items, far.lb, far.le, cb, owner, nchunk, part);
         RCB_LAUNCH_CHECK("k_vjp_far_node");
     }
     k_det_adj_sum<<<(unsigned)((kAdj * nlab + 255) / 256), 256, 0, s>>>(part, cb, nlab, adj);
     RCB_LAUNCH_CHECK("k_det_adj_sum");
-    st = det_lists(t, t->gnear_beg, t->gnear_end, t->gnear, tmp, s, near);
+    st = det_count(t, t->gnear_beg, t->gnear_end, tmp, s, near);
+    if (st != RCB_OK) return st;
+    st = det_sort(t, t->gnear_beg, t->gnear_end, t->gnear, false, tmp, s, near);
     if (st != RCB_OK) return st;
     const unsigned gn = (unsigned)((t->nleaf + kWaves - 1) / kWaves);
     if (mixed) k_vjp_near_src<true><<<gn, kBlock, 0, s>>>(a, near.items, near.lb, near.le);
@@ -976,10 +1055,8 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     const int64_t alen = kAdj * t->nlab;
     const unsigned gridr = (unsigned)((alen + 255) / 256);
     if (det) {
-        // sink-centre sums per leaf, then node adjoints and source-side terms
-        // from the per-node lists
-        k_vjp_far<double, false><<<gridg, kBlock, 0, s>>>(a, nullptr, nullptr);
-        RCB_LAUNCH_CHECK("k_vjp_far");
+        // far field, then node adjoints and source-side terms from the
+        // per-node lists
         st = vjp_det(t, a, adj, mixed, tmp, s);
         if (st != RCB_OK) return st;
         if (mixed) k_vjp_near<true, false><<<gridg, kBlock, 0, s>>>(a);
@@ -987,12 +1064,12 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
         RCB_LAUNCH_CHECK("k_vjp_near");
     } else {
         if (mixed) {
-            k_vjp_far<float, true><<<gridg, kBlock, 0, s>>>(a, (float *)adjc, (float *)adjmc);
+            k_vjp_far<float, kFarAtomic><<<gridg, kBlock, 0, s>>>(a, (float *)adjc, (float *)adjmc);
             RCB_LAUNCH_CHECK("k_vjp_far");
             k_adj_reduce<float><<<gridr, 256, 0, s>>>(adj, (const float *)adjc, (const float *)adjmc, t->nlab,
                                                       nmid);
         } else {
-            k_vjp_far<double, true><<<gridg, kBlock, 0, s>>>(a, (double *)adjc, (double *)adjmc);
+            k_vjp_far<double, kFarAtomic><<<gridg, kBlock, 0, s>>>(a, (double *)adjc, (double *)adjmc);
             RCB_LAUNCH_CHECK("k_vjp_far");
             k_adj_reduce<double><<<gridr, 256, 0, s>>>(adj, (const double *)adjc, (const double *)adjmc, t->nlab,
                                                        nmid);

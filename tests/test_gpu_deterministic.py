@@ -121,3 +121,47 @@ def test_deterministic_vjp_1m(prec):
         print(f"   deterministic vs atomic {name} rel err {e:.2e}", flush=True)
         assert e <= TOL[prec], (name, e)
     t2.destroy()
+
+
+def test_autograd_backward_deterministic():
+    """gravity(..., deterministic=True): two backward passes give the same
+    bits, equal to the deterministic rcb_gravity_vjp on a tree of the inputs."""
+    import torch
+    from paper_1108_0028_amd import gravity
+    c = W.small_random(2000, 17, "clustered")
+    g = W.cotangents(c.n, seed=18)
+    grads = []
+    for _ in range(2):
+        x, y, z, m = [torch.from_numpy(a).to("cuda:0").requires_grad_(True) for a in (c.x, c.y, c.z, c.m)]
+        h = torch.from_numpy(c.h).to("cuda:0")
+        ax, ay, az = gravity(x, y, z, m, h, 8, 0.6, "fp64", deterministic=True)
+        L = sum((v * torch.from_numpy(w).to("cuda:0")).sum() for v, w in zip((ax, ay, az), g))
+        L.backward()
+        grads.append([v.grad for v in (x, y, z, m)])
+    _same_bits(grads[0], grads[1])
+    t = _tree(c, 8, 0.6, "fp64", True)
+    t.gravity()
+    _same_bits(grads[0], _vjp(t, g, "fp64"))
+    t.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_deterministic_vjp_recomputed_node_adjoints(prec, monkeypatch):
+    """RCB_VJP_DET_RECOMPUTE: the node adjoints are recomputed per node
+    (the path taken when the per-entry array cannot be allocated); it too
+    repeats bit for bit and meets the oracle bar."""
+    c = W.small_random(5000, 5500, "plummer")
+    g = W.cotangents(c.n, seed=5501)
+    ot = O.OracleTree(*c.arrays(), n_ll=12)
+    ot.walk(0.6)
+    ref = ot.vjp(*g)
+    monkeypatch.setenv("RCB_VJP_DET_RECOMPUTE", "1")
+    _say("deterministic vjp, node adjoints recomputed", prec)
+    t1 = _tree(c, 12, 0.6, prec, True)
+    a = _vjp(t1, g, prec)
+    _same_bits(a, _vjp(t1, g, prec))
+    for name, x, r in zip(("dx", "dy", "dz", "dm"), a, ref):
+        e = _rel(_np(x), r)
+        print(f"   {name} rel err {e:.2e}", flush=True)
+        assert e <= TOL[prec], (name, e)
+    t1.destroy()
