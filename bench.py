@@ -365,8 +365,8 @@ def _vjp_timing(t, n, phases, prec):
     torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[1]) / reps
     fwd = phases["build"] + phases["walk"] + phases["gravity"]
-    far = "k_vjp_far<float>" if prec == "mixed" else "k_vjp_far<double>"
-    near = "k_vjp_near<true>" if prec == "mixed" else "k_vjp_near<false>"
+    far = "k_vjp_far<float, 0>" if prec == "mixed" else "k_vjp_far<double, 0>"
+    near = "k_vjp_near<true, true>" if prec == "mixed" else "k_vjp_near<false, true>"
     return {"ms": ms, "forward_ms": fwd, "vjp_over_forward": ms / fwd,
             "basis": "forward = build + walk + gravity of the timed steps; the VJP reuses the tree, its "
                      "lists and the far coefficients kept by the gravity call",

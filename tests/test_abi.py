@@ -44,11 +44,12 @@ def test_params_default_is_the_paper_default():
     p = RcbParams()
     L.rcb_params_default(C.byref(p))
     assert p.n_ll == 12 and p.theta == 0.7 and p.precision == 0 and p.validate == 0
-    assert p.pure_mac == 0 and p.split == 0 and p.taylor_reading == 0
+    assert p.pure_mac == 0 and p.split == 0 and p.taylor_reading == 0 and p.deterministic == 0
 
 
 @pytest.mark.parametrize("case", ["null_out", "null_x", "n_zero", "n_neg", "n_huge", "nll_zero",
-                                  "theta_neg", "theta_nan", "precision", "pure_mac", "split", "reading"])
+                                  "theta_neg", "theta_nan", "precision", "pure_mac", "split", "reading",
+                                  "deterministic"])
 def test_build_rejects_bad_arguments_on_host(case):
     from paper_1108_0028_amd._lib import RcbParams
     L = _lib()
@@ -83,6 +84,8 @@ def test_build_rejects_bad_arguments_on_host(case):
         p.split = 3
     elif case == "reading":
         p.taylor_reading = 2
+    elif case == "deterministic":
+        p.deterministic = 2
     st = L.rcb_build(*ptrs, n, C.byref(p), None, outp)
     assert st == 1   # RCB_EINVAL
     assert L.rcb_last_error().decode().startswith("rcb_build")
