@@ -78,6 +78,9 @@ struct VjpArgs {
     // cbase[group] + (entry - the group's first entry)
     double *contrib;
     const int64_t *cbase;
+    // deterministic form: the cotangents in tree order, 3 n values of the
+    // output type (component c of tree position p at c * n + p)
+    void *gtree;
 };
 
 template <bool MIXED>
@@ -615,6 +618,19 @@ __global__ __launch_bounds__(kBlock) void k_vjp_moments_det(VjpArgs a) {
     }
 }
 
+// the cotangents in tree order (contiguous per cell for the source-side pass)
+template <bool MIXED>
+__global__ void k_det_gather_g(VjpArgs a) {
+    using T = typename std::conditional<MIXED, float, double>::type;
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const int32_t o = a.pid[p];
+    T *gt = (T *)a.gtree;
+    gt[p] = (T)load_g<MIXED>(a.gx, o);
+    gt[a.n + p] = (T)load_g<MIXED>(a.gy, o);
+    gt[2 * a.n + p] = (T)load_g<MIXED>(a.gz, o);
+}
+
 // entries per group
 __global__ void k_det_count(const int64_t *__restrict__ beg, const int64_t *__restrict__ end,
                             int64_t ngroup, int64_t *__restrict__ cnt) {
@@ -831,7 +847,6 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near_src(VjpArgs a, const uint64
                 if (q < tot) {
                     const int k = entry_of(sh.ec, q);
                     const int32_t pa = sh.ec.fB[k] + (q - sh.ec.pos[k]);
-                    const int32_t oa = a.pid[pa];
                     if constexpr (MIXED) {
                         const int64_t Ak = sh.ec.label[k];
                         sh.t.x[lane] = a.fdx[pa];
@@ -847,9 +862,10 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near_src(VjpArgs a, const uint64
                         sh.t.z[lane] = a.pz[pa];
                         sh.t.h[lane] = a.ph[pa];
                     }
-                    sh.t.g[0][lane] = (T)load_g<MIXED>(a.gx, oa);
-                    sh.t.g[1][lane] = (T)load_g<MIXED>(a.gy, oa);
-                    sh.t.g[2][lane] = (T)load_g<MIXED>(a.gz, oa);
+                    const T *gt = (const T *)a.gtree;
+                    sh.t.g[0][lane] = gt[pa];
+                    sh.t.g[1][lane] = gt[a.n + pa];
+                    sh.t.g[2][lane] = gt[2 * a.n + pa];
                 }
                 tile_sync();
                 const int nt = tot - t < kWave ? tot - t : kWave;
@@ -993,6 +1009,12 @@ rcb_status vjp_det(rcb_tree *t, VjpArgs a, double *adj, bool mixed, Scratch &tmp
     if (st != RCB_OK) return st;
     st = det_sort(t, t->gnear_beg, t->gnear_end, t->gnear, false, tmp, s, near);
     if (st != RCB_OK) return st;
+    a.gtree = dalloc(t, (mixed ? sizeof(float) : sizeof(double)) * 3 * t->n, s, tmp);
+    if (!a.gtree) return RCB_ENOMEM;
+    const unsigned gp = (unsigned)((t->n + 255) / 256);
+    if (mixed) k_det_gather_g<true><<<gp, 256, 0, s>>>(a);
+    else k_det_gather_g<false><<<gp, 256, 0, s>>>(a);
+    RCB_LAUNCH_CHECK("k_det_gather_g");
     const unsigned gn = (unsigned)((t->nleaf + kWaves - 1) / kWaves);
     if (mixed) k_vjp_near_src<true><<<gn, kBlock, 0, s>>>(a, near.items, near.lb, near.le);
     else k_vjp_near_src<false><<<gn, kBlock, 0, s>>>(a, near.items, near.lb, near.le);
