@@ -383,7 +383,10 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near(VjpArgs a) {
                     const int span = rows * L.J;
                     int j = (L.sslot % rows) * L.J + L.slice;
                     for (int st = 0; st < rows; ++st, j = j + L.J < span ? j + L.J : j + L.J - span) {
-                        if (has_sink && j < nt) {
+                        // the deterministic form leaves out the self pair, whose sink and
+                        // source terms cancel exactly (v = 0) but would be computed in two
+                        // kernels there
+                        if (has_sink && j < nt && (SRC || sh.t.pb[j] != pa)) {
                             const T v[3] = {sx - sh.t.x[j], sy - sh.t.y[j], sz - sh.t.z[j]};
                             const T r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
                             const T hsum = ha + sh.t.h[j];
@@ -779,6 +782,7 @@ template <typename T>
 struct SinkTile {
     T x[kWave], y[kWave], z[kWave], h[kWave], g[3][kWave];
     float sx[kWave], sy[kWave], sz[kWave];   // mixed form: (float)(com_B - com_A)
+    int32_t pa[kWave];                       // tree position (the self pair is left out)
 };
 template <typename T>
 struct SrcShared {
@@ -847,6 +851,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near_src(VjpArgs a, const uint64
                 if (q < tot) {
                     const int k = entry_of(sh.ec, q);
                     const int32_t pa = sh.ec.fB[k] + (q - sh.ec.pos[k]);
+                    sh.t.pa[lane] = pa;
                     if constexpr (MIXED) {
                         const int64_t Ak = sh.ec.label[k];
                         sh.t.x[lane] = a.fdx[pa];
@@ -871,6 +876,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp_near_src(VjpArgs a, const uint64
                 const int nt = tot - t < kWave ? tot - t : kWave;
                 if (has_src) {
                     for (int j = L.slice; j < nt; j += L.J) {
+                        if (sh.t.pa[j] == pb) continue;   // the self pair: v = 0, no term
                         T v[3];
                         if constexpr (MIXED) {   // the source in the sink cell's frame, as in k_vjp_near
                             v[0] = sh.t.x[j] - (sh.t.sx[j] + bx);

@@ -165,3 +165,25 @@ def test_deterministic_vjp_recomputed_node_adjoints(prec, monkeypatch):
         print(f"   {name} rel err {e:.2e}", flush=True)
         assert e <= TOL[prec], (name, e)
     t1.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,nll", [(1, 12), (2, 1), (5, 2), (13, 12), (37, 3)])
+def test_deterministic_vjp_tiny_trees(n, nll, prec):
+    """Trees of depth 0 to 4 (fewer than 8 cells per group, empty far lists):
+    the deterministic form against the oracle, twice."""
+    c = W.small_random(n, 900 + n, "uniform")
+    g = W.cotangents(n, seed=n + 1)
+    ot = O.OracleTree(*c.arrays(), n_ll=nll)
+    ot.walk(0.5)
+    ref = ot.vjp(*g)
+    _say("deterministic vjp, tiny tree", prec, n, nll)
+    t1 = _tree(c, nll, 0.5, prec, True)
+    a = _vjp(t1, g, prec)
+    _same_bits(a, _vjp(t1, g, prec))
+    for name, x, r in zip(("dx", "dy", "dz", "dm"), a, ref):
+        scale = np.abs(r).max()
+        e = float(np.abs(_np(x) - r).max() / scale) if scale > 0 else float(np.abs(_np(x)).max())
+        print(f"   {name} err {e:.2e}", flush=True)
+        assert e <= TOL[prec], (name, e)
+    t1.destroy()
