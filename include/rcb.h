@@ -281,11 +281,14 @@ rcb_status rcb_gravity(rcb_tree *t, void *ax, void *ay, void *az, void *stream);
  * deterministic = 1 nothing is added atomically: each node's adjoint is
  * summed over the groups that accepted it (ascending group, fixed chunks of
  * 512 entries, then the chunks in order; each group's part over its cells in
- * order) and each source particle's terms
- * over the sink cells whose near list holds its cell, in FP64 in both forms;
- * two calls on the same tree and inputs give identical outputs. The lists
- * of groups per node and per cell are made on each call (stable label sort).
- * Errors: RCB_EINVAL (NULL argument, or a tree built with RCB_READING_B).
+ * order) and each source particle's terms over the sink cells whose near
+ * list holds its cell (sums in FP64 in both forms; a particle's pair with
+ * itself, whose terms cancel, is left out); two calls on the same tree and
+ * inputs give identical outputs. The lists of groups per node and per cell
+ * are made on each call (stable label sort).
+ * Errors: RCB_EINVAL (NULL argument, or a tree built with RCB_READING_B);
+ * with deterministic = 1 also RCB_ENOMEM (the lists' sort buffers) and
+ * RCB_ECAPACITY (more than 2^24 groups of 8 cells, k > 26).
  */
 rcb_status rcb_gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *gz,
                            void *dx, void *dy, void *dz, void *dm, void *stream);
