@@ -288,7 +288,7 @@ rcb_status rcb_gravity(rcb_tree *t, void *ax, void *ay, void *az, void *stream);
  * are made on each call (stable label sort).
  * Errors: RCB_EINVAL (NULL argument, or a tree built with RCB_READING_B);
  * with deterministic = 1 also RCB_ENOMEM (the lists' sort buffers) and
- * RCB_ECAPACITY (more than 2^24 groups of 8 cells, k > 26).
+ * RCB_ECAPACITY (more than 2^24 groups of 8 cells, k > 27).
  */
 rcb_status rcb_gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *gz,
                            void *dx, void *dy, void *dz, void *dm, void *stream);

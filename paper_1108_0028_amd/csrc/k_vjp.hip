@@ -1041,7 +1041,7 @@ rcb_status gravity_vjp(rcb_tree *t, const void *gx, const void *gy, const void *
     void *srcv = dalloc(t, (mixed ? sizeof(float) : sizeof(double)) * 4 * n, s, tmp);
     const bool det = t->p.deterministic != 0;
     if (det && t->ngroup > (int64_t(1) << 24)) {
-        set_error("rcb_gravity_vjp: the deterministic form takes at most 2^24 groups of cells (k <= 26)");
+        set_error("rcb_gravity_vjp: the deterministic form takes at most 2^24 groups of 8 cells (k <= 27)");
         return RCB_ECAPACITY;
     }
     const int64_t nmid = std::min<int64_t>(t->nlab, int64_t(1) << kMidLevel);
